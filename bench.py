@@ -1,0 +1,191 @@
+"""Benchmark: batched FP32 A + A* pairs per second at n = 512 on one MI355X.
+
+One step = pat_forward_batched + pat_adjoint_batched on a batch of B images
+(n = 512, m = 1024 detectors on the full circle, nt = 1024 samples on (0, 2],
+c = R = a = 1).  Inputs are seeded synthetic random-ellipse phantoms and
+N(0,1) traces, resident in HBM before the timed region.  Prints one JSON line.
+
+The line carries
+  * value        pairs/s over the whole job (B * steps / elapsed),
+  * roofline     for the dominant kernel: algorithmic bytes per launch divided
+                 by its average launch time from HIP events recorded on the
+                 launch stream during the timed steps, against 8 TB/s,
+  * accuracy     relative L2 error of the first image's traces against the
+                 FP64 oracle's stored samples (tests/golden/full_n512.npz),
+  * cpu_baseline the FP64 oracle timed on the host cores on a bounded sample
+                 of the same workload, extrapolated to pairs/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+STAGES = ["rows_fwd", "cols_fwd", "ring_fwd", "dct_fwd", "lowk_fwd", "synth_fwd", "synth_adj", "lowk_adj",
+          "dct_adj", "ring_adj", "spread_adj", "cols_adj", "rows_adj"]
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes(info: dict, B: int, geom: dict) -> dict:
+    """Algorithmic HBM bytes per launch (B images, FP32): each kernel's compulsory
+    reads of its inputs and writes of its outputs, once each."""
+    n, m, nt = info["n"], info["m"], info["nt"]
+    Ng, L, Kp, K = info["grid"], info["rings"], info["kpad"], info["kmax"]
+    w = info["stencil"]
+    hw = (w + 1) // 2
+    Rw, Ew = Ng // 2 + 1, Ng // 2 + 1 + 2 * hw
+    c8, r4 = 8, 4
+    R = c8 * n * Rw
+    E = c8 * Ng * Ew
+    V = c8 * L * Kp
+    G = c8 * nt * Kp
+    tb = r4 * L * Kp  # Bessel/taper table, read once per launch per image
+    P = c8 * info["ring_points"]
+    per = {
+        "rows_fwd": r4 * n * n + R, "cols_fwd": R + E, "ring_fwd": E + V + tb, "dct_fwd": V + G,
+        "lowk_fwd": 2 * c8 * nt * (info["klow"] + 1), "synth_fwd": G + r4 * nt * m,
+        "synth_adj": r4 * nt * m + G, "lowk_adj": c8 * nt * (info["klow"] + 1),
+        "dct_adj": G + V, "ring_adj": V + tb + P, "spread_adj": P + E, "cols_adj": E + R, "rows_adj": R + r4 * n * n,
+    }
+    return {k: v * B for k, v in per.items()}
+
+
+def cpu_baseline(geom: dict, seconds_budget: float = 20.0) -> dict:
+    """Time the FP64 oracle on a bounded sample of the workload and extrapolate:
+    forward on a few detectors (all times) and adjoint on a few pixels."""
+    import oracle
+    from paper_2510_24687_amd import phantoms as P
+    n, m, nt = geom["n"], geom["m"], geom["nt"]
+    f = P.ellipse_phantom(n, 0)
+    y = P.randn((nt, m), 1)
+    oracle.build()
+    ndet, npix = 2, 32
+    t0 = time.time()
+    oracle.forward(geom, f, dets=list(range(ndet)))
+    t_f = time.time() - t0
+    t0 = time.time()
+    oracle.adjoint(geom, y, pix=list(range(0, n * n, (n * n) // npix))[:npix])
+    t_a = time.time() - t0
+    # adjoint time = fixed trace pre-contraction + per-pixel cost; time one pixel set twice as big to split them
+    t0 = time.time()
+    oracle.adjoint(geom, y, pix=list(range(0, n * n, (n * n) // (2 * npix)))[:2 * npix])
+    t_a2 = time.time() - t0
+    per_pix = max(t_a2 - t_a, 1e-9) / npix
+    fixed = max(t_a - per_pix * npix, 0.0)
+    full_f = t_f * m / ndet
+    full_a = fixed + per_pix * n * n
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / (full_f + full_a), "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": "forward on %d of %d detectors (all %d times) + adjoint on %d and %d of %d pixels, n=%d; "
+                      "extrapolated to one full A+A* pair (%.1f s measured)"
+                      % (ndet, m, nt, npix, 2 * npix, n * n, n, t_f + t_a + t_a2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the operators shard by image; "
+              "a multi-GPU run is not part of it)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_24687_amd import pat
+    from paper_2510_24687_amd import phantoms as P
+
+    n, B = args.n, args.batch
+    geom = P.full_circle(n, 2 * n, 2 * n, T=2.0)
+    plan = pat.Plan(geom, torch.float32, max_batch=B)
+    info = plan.info
+    dev = plan.device
+    f_np = P.ellipse_batch(n, range(B))
+    y_np = np.stack([P.randn((geom["nt"], geom["m"]), 100 + b) for b in range(B)])
+    f = torch.tensor(f_np, dtype=torch.float32, device=dev)
+    y = torch.tensor(y_np, dtype=torch.float32, device=dev)
+    g = torch.empty((B, geom["nt"], geom["m"]), dtype=torch.float32, device=dev)
+    fa = torch.empty((B, n, n), dtype=torch.float32, device=dev)
+
+    for _ in range(args.warmup):
+        plan.forward(f, out=g)
+        plan.adjoint(y, out=fa)
+    torch.cuda.synchronize()
+
+    # accuracy of this run's first image against the oracle's stored samples
+    acc = None
+    gold = os.path.join(ROOT, "tests", "golden", "full_n%d.npz" % n)
+    if os.path.exists(gold):
+        z = np.load(gold)
+        got = g[0].double().cpu().numpy()[:, z["dets"]]
+        acc_f = float(np.linalg.norm(got - z["forward"]) / np.linalg.norm(z["forward"]))
+        y0 = torch.tensor(P.randn((geom["nt"], geom["m"]), 1), dtype=torch.float32, device=dev)
+        a0 = plan.adjoint(y0).double().cpu().numpy().ravel()[z["pix"]]
+        acc_a = float(np.linalg.norm(a0 - z["adjoint"]) / np.linalg.norm(z["adjoint"]))
+        acc = {"forward_rel_l2": acc_f, "adjoint_rel_l2": acc_a,
+               "sample": "%d detectors x %d times; %d pixels" % (len(z["dets"]), geom["nt"], len(z["pix"]))}
+        torch.cuda.synchronize()
+
+    lib = pat.load()
+    lib.pat_timing_start(plan._h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.forward(f, out=g)
+        plan.adjoint(y, out=fa)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    import ctypes
+    ms = (ctypes.c_double * 13)()
+    cnt = (ctypes.c_int * 13)()
+    rc = lib.pat_timing_stop(plan._h, ms, cnt, 13)
+    if rc != 0:
+        raise RuntimeError("pat_timing_stop failed")
+    stage_ms = {STAGES[i]: ms[i] / max(cnt[i], 1) for i in range(13)}
+    bytes_ = stage_bytes(info, B, geom)
+    dom = max(stage_ms, key=stage_ms.get)
+    achieved = bytes_[dom] / (stage_ms[dom] * 1e-3) / 1e9
+    pairs = B * args.steps / elapsed
+    step_ms = elapsed / args.steps * 1e3
+    total_alg = sum(bytes_.values())
+    out = {
+        "metric": "A+A* pairs/s at n=512 FP32 (<=1e-4 rel err)",
+        "value": pairs,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded random-ellipse phantoms, N(0,1) traces)",
+        "config": {"workload": "A+A* pairs: n=%d image, m=%d detectors on the full circle, nt=%d samples on (0,2], "
+                               "c=R=a=1, batch %d" % (n, geom["m"], geom["nt"], B),
+                   "batch": B, "n": n, "m": geom["m"], "nt": geom["nt"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "stage_ms_per_launch": stage_ms,
+        "pair_alg_bytes_per_image": total_alg / B,
+        "pair_effective_GBs": total_alg / (step_ms * 1e-3) / 1e9,
+        "accuracy_vs_oracle": acc,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(geom)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

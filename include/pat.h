@@ -1,0 +1,177 @@
+/*
+ * pat.h -- C ABI of the MI355X (gfx950) library for the fast circular-geometry
+ * photoacoustic operators of Hauptmann, Kunyansky & Poimala,
+ * "Fast algorithms enabling optimization and deep learning for photoacoustic
+ * tomography in a circular detection geometry" (arXiv 2510.24687).
+ *
+ * Operators
+ *   A  : initial pressure f on an n x n grid  ->  traces g(t_j, z_i) on the
+ *        detector circle (the wave operator of Sec. 1, eq. E:green_conv),
+ *        evaluated in O(n^2 log n) by the harmonic route of Sec. 3.1
+ *        (Algorithm 1: 2D FFT, Cartesian->polar interpolation, angular FFT
+ *        per ring, Bessel-weighted cosine transform per harmonic, angular
+ *        synthesis per time sample, restriction to the arc).
+ *   A* : the adjoint of A under the L2 inner products of eq.
+ *        eqn:innerProducts (Sec. 2.1, eq. E:adjoint), computed as the exact
+ *        weighted transpose of the discrete A: A* = s A^T with
+ *        s = (T/nt)(R*arc/m)/h^2 (Algorithm 2 of Sec. 3.2 in transposed
+ *        form; see pat_adjoint_scale).
+ *
+ * Discrete model.  A sampled image is the band-limited function whose 2D
+ * Fourier transform is W(|xi|) F(xi), F(xi) = (h^2/2pi) sum_pq f_pq
+ * exp(-i xi.x_pq) (the transform convention of Sec. 2.1.1), W a smooth radial
+ * taper equal to 1 on [0, taper_rho*Lambda] and 0 from Lambda = pi/h on.
+ * The returned traces are the exact wave solution (eq. E:kwave) for that
+ * function, up to the algorithm's approximation error (bounded per plan; FP32
+ * plans stay below 1e-5 relative L2 before rounding).
+ *
+ * Layout and conventions
+ *   pixel centres  x_pq = (-a + (q+1/2)h, -a + (p+1/2)h), h = 2a/n;
+ *   f              row-major f[p*n + q] (p = y index, q = x index);
+ *   detectors      theta_i = theta0 + i*arc/m, z_i = R (cos, sin)(theta_i),
+ *                  i = 0..m-1; 2*pi*m/arc must be an integer m_full (the
+ *                  detectors are a subset of m_full equispaced angles);
+ *   times          t_j = (j+1) T/nt, j = 0..nt-1 (samples on (0, T]);
+ *   g              row-major g[j*m + i] (time-major, detector fastest);
+ *   batches        image b of a batch starts at f + b*f_stride (elements),
+ *                  its traces at g + b*g_stride.
+ *   precision      PAT_F32 plans read/write float, PAT_F64 plans double.
+ *
+ * Ownership.  The caller owns every buffer passed in (inputs, outputs and the
+ * workspace; all device memory).  A plan owns its device tables and frees
+ * them in pat_plan_destroy.  Plans are immutable after creation.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  All
+ * compute calls are asynchronous on it: they enqueue kernels and return.
+ * Two calls that run concurrently must use distinct workspaces.
+ *
+ * Errors.  Every function returns PAT_OK (0) or a negative status; nothing
+ * throws across the ABI.  pat_last_error() returns a thread-local detail
+ * string for the most recent failure on the calling thread.
+ */
+#ifndef PAT_H
+#define PAT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PAT_OK = 0,
+    PAT_EINVAL = -1,       /* invalid argument (null pointer, bad size, bad geometry) */
+    PAT_EUNSUPPORTED = -2, /* valid but unsupported configuration (e.g. m_full not a power of two) */
+    PAT_ENOMEM = -3,       /* device or host allocation failed */
+    PAT_EHIP = -4,         /* a HIP runtime call or kernel launch failed */
+    PAT_ESMALL = -5        /* workspace or batch capacity too small */
+};
+
+typedef enum { PAT_F32 = 0, PAT_F64 = 1 } pat_dtype;
+
+/* Acquisition geometry (problem statement of Sec. 1-2: speed of sound c,
+ * detector circle of radius R, m detectors on an arc Gamma of the circle,
+ * nt samples on (0, T]); image grid n x n on [-a, a]^2. */
+typedef struct {
+    int n;              /* image is n x n, n >= 8                               */
+    double a;           /* image half-width (image covers [-a, a]^2)            */
+    double R;           /* detector-circle radius                               */
+    double c;           /* speed of sound                                       */
+    int m;              /* number of detectors                                  */
+    double theta0;      /* angle of detector 0 (radians)                        */
+    double arc;         /* angular extent covered: detector spacing is arc/m    */
+    int nt;             /* number of time samples                               */
+    double T;           /* final time                                           */
+    double taper_rho;   /* W = 1 on [0, taper_rho*Lambda]; 0 < taper_rho < 1    */
+    double mask_radius; /* 0: none; else f restricted to |x| <= mask_radius in
+                           A and A* (the projection Pi_Omega0 of Algorithm 2)   */
+} pat_geometry;
+
+typedef struct pat_plan_s* pat_plan;
+
+/* Parameters the plan chose (for diagnostics and tests). */
+typedef struct {
+    int n, m, nt, m_full;
+    int grid;           /* oversampled Cartesian FFT size (per side)             */
+    int stencil;        /* interpolation stencil width w (cells per direction)   */
+    int rings;          /* number of polar rings L (lambda_l = l*dlam < Lambda)  */
+    int dct_half;       /* M: the cosine transform uses a 2M-point FFT           */
+    int kmax;           /* largest angular harmonic K                            */
+    int kpad;           /* harmonic row pitch (K+1 rounded up)                   */
+    int klow;           /* harmonics 0..klow get the low-frequency correction    */
+    int lcorr;          /* rings entering the low-frequency correction           */
+    int ring_points;    /* half-ring sample count summed over rings              */
+    int max_ring;       /* largest ring FFT size                                 */
+    int spread_tiles;   /* tiles of the adjoint's deterministic spread           */
+    double dlam;        /* ring spacing in lambda                                */
+    double period;      /* time period 2*pi/(c*dlam) of the cosine transform     */
+    double lambda_max;  /* Lambda = pi/h                                         */
+    size_t ws_per_image;/* workspace bytes per image                             */
+    size_t table_bytes; /* device bytes held by the plan                         */
+} pat_plan_info;
+
+/* Create a plan: validates the geometry, computes its tables on the host in
+ * FP64 (Bessel functions by Miller's backward recurrence, gridding kernel and
+ * its transform, low-frequency quadrature, spread tiling) and uploads them.
+ * max_batch bounds the batch of later calls (>= 1).  tuning_cache_path may be
+ * NULL; otherwise launch-shape choices are read from / appended to that file.
+ * Synchronises the current device once.  Returns PAT_OK and *out, or an error
+ * (then *out is NULL). */
+int pat_plan_create(pat_plan* out, const pat_geometry* g, pat_dtype dt, int max_batch,
+                    const char* tuning_cache_path);
+
+/* Same parameters and host tables as pat_plan_create, but no device work:
+ * fills *info only.  Usable without a GPU. */
+int pat_plan_query(const pat_geometry* g, pat_dtype dt, pat_plan_info* info);
+
+int pat_plan_destroy(pat_plan p);
+int pat_plan_get_info(pat_plan p, pat_plan_info* info);
+
+/* Device workspace bytes needed for a batch of `batch` images (<= max_batch). */
+int pat_workspace_size(pat_plan p, int batch, size_t* bytes);
+
+/* g = A f for one image.  f: n*n device elements, g: nt*m device elements. */
+int pat_forward(pat_plan p, const void* f, void* g, void* ws, void* stream);
+
+/* f = A* g (weighted adjoint) for one image. */
+int pat_adjoint(pat_plan p, const void* g, void* f, void* ws, void* stream);
+
+/* Batched forms: B images (1 <= B <= max_batch), strides in elements
+ * (f_stride >= n*n, g_stride >= nt*m). */
+int pat_forward_batched(pat_plan p, int B, const void* f, long f_stride, void* g, long g_stride,
+                        void* ws, void* stream);
+int pat_adjoint_batched(pat_plan p, int B, const void* g, long g_stride, void* f, long f_stride,
+                        void* ws, void* stream);
+
+/* s such that A* = s A^T: s = (T/nt) (R*arc/m) / h^2, the rectangle-rule
+ * weights of the inner products eqn:innerProducts. */
+int pat_adjoint_scale(pat_plan p, double* s);
+
+const char* pat_status_string(int code);
+const char* pat_last_error(void);
+
+/* Stage timing.  Stages of the forward and adjoint chains, in launch order. */
+enum {
+    PAT_STAGE_ROWS_FWD = 0, PAT_STAGE_COLS_FWD, PAT_STAGE_RING_FWD, PAT_STAGE_DCT_FWD, PAT_STAGE_LOWK_FWD,
+    PAT_STAGE_SYNTH_FWD, PAT_STAGE_SYNTH_ADJ, PAT_STAGE_LOWK_ADJ, PAT_STAGE_DCT_ADJ, PAT_STAGE_RING_ADJ,
+    PAT_STAGE_SPREAD_ADJ, PAT_STAGE_COLS_ADJ, PAT_STAGE_ROWS_ADJ, PAT_NUM_STAGES
+};
+
+/* Start recording a HIP event pair on the launch stream around every kernel
+ * of later pat_forward* / pat_adjoint* calls on this plan (no host syncs are
+ * added).  pat_timing_stop waits for the recorded events, writes the summed
+ * milliseconds and launch counts per stage into ms[] / launches[] (arrays of
+ * at least PAT_NUM_STAGES entries) and turns recording off.  Not for plans
+ * used from several threads at once. */
+int pat_timing_start(pat_plan p);
+int pat_timing_stop(pat_plan p, double* ms, int* launches, int nstages);
+
+/* Host-side checks of plan internals (no GPU needed).  Fills out[0..K] with
+ * J_k(x) for k = 0..K computed by the plan's Miller recurrence. */
+int pat_debug_bessel(double x, int K, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAT_H */

@@ -1,0 +1,65 @@
+// Internal declarations shared by the host plan builder (pat_plan.cpp) and
+// the HIP kernels/entry points (pat_kernels.hip).
+#pragma once
+
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "../../include/pat.h"
+
+namespace pat {
+
+// Everything the plan decides, derived from the geometry and the precision.
+struct Params {
+    pat_geometry g;
+    pat_dtype dt;
+    int n, m, nt, mf;       // image side, detectors, time samples, full-circle detector count
+    double h, Lam, rmax;    // pixel size, Nyquist radius pi/h, largest |x| entering A
+    double shift;           // x_q = h (q' + shift), q' = q - n/2 (integer division)
+    int Ng;                 // oversampled Cartesian grid (per side), power of two
+    int w, hw;              // stencil width, half-width ceil(w/2)
+    double beta;            // exponential-of-semicircle kernel parameter
+    int Rw;                 // row-pass width Ng/2 + 1
+    int Ew;                 // extended half-grid width Ng/2 + 1 + 2 hw
+    double eps;             // target size of each neglected term
+    int M;                  // cosine transform via a 2M-point FFT
+    double period, dlam;    // time period of the discrete cosine sum, ring spacing
+    int L;                  // rings lambda_l = l dlam < Lam
+    int K, Kp;              // largest harmonic, row pitch of the harmonic arrays
+    int klow;               // harmonics 0..klow get the low-frequency correction
+    int Ls;                 // half-width of the band-limited interpolation kernel (samples)
+    double lam_c, lam_s;    // low-frequency split: erfc step centre and width
+    int lcorr;              // rings feeding the low-frequency correction
+    int Nmax;               // twiddle table length (largest FFT)
+    int max_ring;           // largest ring FFT
+    int npts;               // half-ring samples over all rings
+    int tileR, tileC, ntileR, ntileC;  // spread tiling of the extended half grid
+    int nruns;
+    double pre_scale;       // h^2 / (2 pi)
+    double adj_scale;       // (T/nt)(R arc/m)/h^2
+};
+
+struct HostPlan {
+    Params P;
+    std::vector<double> Dq;                 // n: 1/phi_hat(2 pi q'/Ng)
+    std::vector<double> lam;                // L
+    std::vector<int> ringN, ringLog, ringOff, ringK;  // L
+    std::vector<double> Tb;                 // L x Kp, real Bessel/taper/quadrature weights (1/N_l folded)
+    std::vector<double> Mk;                 // (klow+1) x nt x lcorr
+    std::vector<double> phase;              // 2*Kp: e^{i k theta0} (re, im)
+    std::vector<double> tw;                 // 2*Nmax: e^{-2 pi i k / Nmax} (re, im)
+    std::vector<int> tileStart;             // ntiles + 1
+    std::vector<int> runs;                  // 3 per run: ring, first half-ring index, count
+};
+
+// Fills P and all host tables.  Returns PAT_OK or an error with `err` set.
+int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& out, std::string& err);
+
+// J_k(x), k = 0..K, by Miller's backward recurrence normalised with
+// J_0 + 2 sum_k J_2k = 1.
+void bessel_j_all(double x, int K, double* out);
+
+void set_error(const std::string& s);
+
+}  // namespace pat

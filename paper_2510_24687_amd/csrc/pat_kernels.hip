@@ -1,0 +1,1068 @@
+// HIP kernels (gfx950) and C-ABI entry points for the fast circular-geometry
+// photoacoustic operators of Hauptmann, Kunyansky & Poimala (arXiv 2510.24687).
+//
+// Forward chain (Algorithm 1, Sec. 3.1), one launch per stage, batched over
+// images in gridDim.y:
+//   rows_fwd   pre-correct, zero-extend and FFT two image rows at a time (real
+//              rows packed into one complex FFT) -> half spectrum per row
+//   cols_fwd   FFT along y for a block of spectrum columns -> extended half grid
+//              (extra columns beyond both ends hold the conjugate-symmetric values)
+//   ring_fwd   per ring: gather the half ring from the grid with the w x w
+//              kernel (step 3), fill the other half by conjugate symmetry, ring
+//              FFT (step 4, eq. E:eq3), Bessel/taper/quadrature weights -> V(l,k)
+//   dct        per harmonic: cosine sum over rings (step 5, eq. E:inverse_cos_tr)
+//              as a 2M-point FFT -> G_k(t_j)
+//   lowk_fwd   exact low-frequency quadrature for harmonics 0..klow
+//   synth_fwd  per pair of time rows: fold harmonics onto the m_full detector
+//              grid and inverse FFT (steps 6-7, eq. E:FourSerForg), keep the arc
+// The adjoint runs the exact transposes in reverse order; the transpose of the
+// gather is a deterministic per-tile spread (no global atomics).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "pat_internal.h"
+
+namespace pat {
+const char* last_error();
+}
+
+namespace {
+
+constexpr int NT = 256;  // threads per block for every kernel
+
+template <typename T>
+struct cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+template <typename T>
+__device__ __forceinline__ cx<T> conjg(cx<T> a) { return {a.x, -a.y}; }
+// multiply by i^k
+template <typename T>
+__device__ __forceinline__ cx<T> mul_ipow(cx<T> a, int k)
+{
+    switch (k & 3) {
+        case 0: return a;
+        case 1: return {-a.y, a.x};
+        case 2: return {-a.x, -a.y};
+        default: return {a.y, -a.x};
+    }
+}
+
+__device__ __forceinline__ void sincospi_t(float x, float* s, float* c) { sincospif(x, s, c); }
+__device__ __forceinline__ void sincospi_t(double x, double* s, double* c) { sincospi(x, s, c); }
+__device__ __forceinline__ void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ float exp_t(float x) { return expf(x); }
+__device__ __forceinline__ double exp_t(double x) { return exp(x); }
+__device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
+__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
+__device__ __forceinline__ float ceil_t(float x) { return ceilf(x); }
+__device__ __forceinline__ double ceil_t(double x) { return ceil(x); }
+
+// ---------------------------------------------------------------------------
+// In-LDS FFT of `nb` independent sequences of length 2^logN stored at
+// buf + b*stride.  Iterative decimation in time: bit-reversal permutation,
+// an optional radix-2 stage, then radix-4 stages (two radix-2 stages fused in
+// registers).  tw holds e^{-2 pi i k/Nmax}; inverse = conjugate twiddles (no
+// 1/N).  All threads of the block take part; the routine ends synchronised.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void lds_fft(cx<T>* buf, int logN, int nb, int stride, const cx<T>* __restrict__ tw, int logNmax,
+                        bool inverse)
+{
+    const int N = 1 << logN;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    if (logN == 0) return;
+    for (int it = tid; it < nb * N; it += nth) {
+        int b = it >> logN, i = it & (N - 1);
+        int j = __brev((unsigned)i) >> (32 - logN);
+        if (i < j) {
+            cx<T>* s = buf + b * stride;
+            cx<T> t = s[i];
+            s[i] = s[j];
+            s[j] = t;
+        }
+    }
+    __syncthreads();
+    int st = 0;
+    if (logN & 1) {
+        for (int it = tid; it < nb * (N >> 1); it += nth) {
+            int b = it >> (logN - 1), i = it & ((N >> 1) - 1);
+            cx<T>* s = buf + b * stride;
+            cx<T> a0 = s[2 * i], a1 = s[2 * i + 1];
+            s[2 * i] = a0 + a1;
+            s[2 * i + 1] = a0 - a1;
+        }
+        __syncthreads();
+        st = 1;
+    }
+    for (; st < logN; st += 2) {
+        const int h = 1 << st;
+        const int sh1 = logNmax - st - 1, sh2 = logNmax - st - 2;
+        const int q = N >> 2;
+        for (int it = tid; it < nb * q; it += nth) {
+            int b = it / q, g = it - b * q;
+            int j = g & (h - 1);
+            int i0 = ((g >> st) << (st + 2)) + j;
+            cx<T>* s = buf + b * stride;
+            cx<T> a0 = s[i0], a1 = s[i0 + h], a2 = s[i0 + 2 * h], a3 = s[i0 + 3 * h];
+            cx<T> w1 = tw[j << sh1], w2 = tw[j << sh2];
+            if (inverse) {
+                w1.y = -w1.y;
+                w2.y = -w2.y;
+            }
+            cx<T> t1 = cmul(w1, a1), t3 = cmul(w1, a3);
+            cx<T> b0 = a0 + t1, b1 = a0 - t1, b2 = a2 + t3, b3 = a2 - t3;
+            cx<T> u2 = cmul(w2, b2), u3 = cmul(w2, b3);
+            u3 = inverse ? cx<T>{-u3.y, u3.x} : cx<T>{u3.y, -u3.x};
+            s[i0] = b0 + u2;
+            s[i0 + 2 * h] = b0 - u2;
+            s[i0 + h] = b1 + u3;
+            s[i0 + 3 * h] = b1 - u3;
+        }
+        __syncthreads();
+    }
+}
+
+// Plan data as seen by the kernels.
+template <typename T>
+struct Dev {
+    int n, m, nt, mf, logmf;
+    int Ng, logNg, w, hw, Rw, Ew;
+    int M, log2M, L, K, Kp, klow, lcorr, npts;
+    int tileR, tileC, ntileC, logNmax;
+    int colsCW, dctCW;
+    T beta, shift, half;        // half = Ng / (2 Lambda): grid cells per unit lambda
+    T lamh;                     // h: u = lambda h cos(phi)
+    T dlam, pre_scale, adj_scale;
+    double mask_r2, a, h;       // mask test in double (same decision as the oracle)
+    const T* Dq;                // n
+    const T* lam;               // L
+    const int* ringN;           // L
+    const int* ringLog;         // L
+    const int* ringOff;         // L
+    const int* ringK;           // L
+    const T* Tb;                // L x Kp
+    const T* Mk;                // (klow+1) x nt x lcorr
+    const cx<T>* phase;         // Kp
+    const cx<T>* tw;            // Nmax
+    const int* tileStart;       // ntiles+1
+    const int* runs;            // 3 per run
+};
+
+template <typename T>
+__device__ __forceinline__ bool in_mask(const Dev<T>& d, int p, int q)
+{
+    if (d.mask_r2 <= 0.0) return true;
+    double x = -d.a + (q + 0.5) * d.h, y = -d.a + (p + 0.5) * d.h;
+    return x * x + y * y <= d.mask_r2;
+}
+
+// exponential-of-semicircle kernel at offset `dd` cells
+template <typename T>
+__device__ __forceinline__ T es_w(T dd, T two_over_w, T beta)
+{
+    T z = dd * two_over_w;
+    T s = T(1) - z * z;
+    return s > T(0) ? exp_t(beta * (sqrt_t(s) - T(1))) : T(0);
+}
+
+// Grid position, first taps and weights of half-ring sample si of ring l
+// (WMAX is the stencil width w: 6 for FP32 plans, 13 for FP64 plans).
+template <typename T, int WMAX>
+struct Taps {
+    int gx0, gy0;
+    T wx[WMAX], wy[WMAX];
+    cx<T> ph;  // e^{-i shift (u + v)}
+};
+
+template <typename T, int WMAX>
+__device__ __forceinline__ void point_taps(const Dev<T>& d, T lam, int N, int si, Taps<T, WMAX>& tp)
+{
+    int s = si - (N >> 2);
+    T sn, cs;
+    sincospi_t(T(2) * T(s) / T(N), &sn, &cs);
+    T x = lam * d.half * cs, y = lam * d.half * sn;
+    T hwf = T(0.5) * T(WMAX);
+    tp.gx0 = (int)ceil_t(x - hwf);
+    tp.gy0 = (int)ceil_t(y - hwf);
+    T tw_ = T(2) / T(WMAX);
+#pragma unroll
+    for (int j = 0; j < WMAX; ++j) {
+        tp.wx[j] = es_w(x - T(tp.gx0 + j), tw_, d.beta);
+        tp.wy[j] = es_w(y - T(tp.gy0 + j), tw_, d.beta);
+    }
+    T ang = -d.shift * lam * d.lamh * (cs + sn);
+    T ps, pc;
+    sincos_t(ang, &ps, &pc);
+    tp.ph = {pc, ps};
+}
+
+// ---------------------------------------------------------------------------
+// forward kernels
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void rows_fwd(Dev<T> d, const T* __restrict__ f, long fstride, cx<T>* R,
+                                               size_t ws_img)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const int b = blockIdx.y, p1 = 2 * blockIdx.x, p2 = p1 + 1;
+    const T* fb = f + (size_t)b * fstride;
+    cx<T>* Rb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(R) + (size_t)b * ws_img);
+    const int Ng = d.Ng, n = d.n;
+    for (int i = threadIdx.x; i < Ng; i += blockDim.x) buf[i] = {T(0), T(0)};
+    __syncthreads();
+    const T s1 = p1 < n ? d.Dq[p1] * d.pre_scale : T(0);
+    const T s2 = p2 < n ? d.Dq[p2] * d.pre_scale : T(0);
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        int qi = (q - n / 2 + Ng) & (Ng - 1);
+        T a = (p1 < n && in_mask(d, p1, q)) ? fb[(size_t)p1 * n + q] * d.Dq[q] * s1 : T(0);
+        T c = (p2 < n && in_mask(d, p2, q)) ? fb[(size_t)p2 * n + q] * d.Dq[q] * s2 : T(0);
+        buf[qi] = {a, c};
+    }
+    __syncthreads();
+    lds_fft(buf, d.logNg, 1, 0, d.tw, d.logNmax, false);
+    for (int g = threadIdx.x; g <= Ng / 2; g += blockDim.x) {
+        cx<T> zg = buf[g], zm = buf[(Ng - g) & (Ng - 1)];
+        cx<T> x1 = {T(0.5) * (zg.x + zm.x), T(0.5) * (zg.y - zm.y)};
+        cx<T> x2 = {T(0.5) * (zg.y + zm.y), T(0.5) * (zm.x - zg.x)};
+        if (p1 < n) Rb[(size_t)p1 * d.Rw + g] = x1;
+        if (p2 < n) Rb[(size_t)p2 * d.Rw + g] = x2;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void cols_fwd(Dev<T> d, const cx<T>* R, cx<T>* E, size_t ws_img)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const int b = blockIdx.y, CW = d.colsCW, x0 = blockIdx.x * CW;
+    const int Ng = d.Ng, n = d.n;
+    const cx<T>* Rb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(R) + (size_t)b * ws_img);
+    cx<T>* Eb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(E) + (size_t)b * ws_img);
+    for (int i = threadIdx.x; i < CW * Ng; i += blockDim.x) buf[i] = {T(0), T(0)};
+    __syncthreads();
+    for (int i = threadIdx.x; i < CW * n; i += blockDim.x) {
+        int p = i / CW, c = i - p * CW;
+        int gx = x0 + c;
+        if (gx < d.Rw) buf[c * Ng + ((p - n / 2 + Ng) & (Ng - 1))] = Rb[(size_t)p * d.Rw + gx];
+    }
+    __syncthreads();
+    lds_fft(buf, d.logNg, CW, Ng, d.tw, d.logNmax, false);
+    for (int i = threadIdx.x; i < CW * Ng; i += blockDim.x) {
+        int gy = i / CW, c = i - gy * CW;
+        int gx = x0 + c;
+        if (gx >= d.Rw) continue;
+        cx<T> v = buf[c * Ng + gy];
+        Eb[(size_t)gy * d.Ew + gx + d.hw] = v;
+        int gym = (Ng - gy) & (Ng - 1);
+        if (gx >= 1 && gx <= d.hw) Eb[(size_t)gym * d.Ew + d.hw - gx] = conjg(v);
+        if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) Eb[(size_t)gym * d.Ew + d.hw + Ng - gx] = conjg(v);
+    }
+}
+
+template <typename T, int WMAX>
+__global__ __launch_bounds__(NT) void ring_fwd(Dev<T> d, const cx<T>* E, cx<T>* V, cx<T>* Ulow, size_t ws_img)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const int b = blockIdx.y, l = blockIdx.x;
+    const int N = d.ringN[l], logN = d.ringLog[l], Kl = d.ringK[l];
+    const T lam = d.lam[l];
+    const cx<T>* Eb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(E) + (size_t)b * ws_img);
+    cx<T>* Vb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(V) + (size_t)b * ws_img);
+    cx<T>* Ub = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(Ulow) + (size_t)b * ws_img);
+    const int mask = d.Ng - 1;
+    for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
+        Taps<T, WMAX> tp;
+        point_taps<T, WMAX>(d, lam, N, si, tp);
+        cx<T> acc = {T(0), T(0)};
+#pragma unroll
+        for (int jy = 0; jy < WMAX; ++jy) {
+            const cx<T>* row = Eb + (size_t)((tp.gy0 + jy) & mask) * d.Ew + tp.gx0 + d.hw;
+            cx<T> racc = {T(0), T(0)};
+#pragma unroll
+            for (int jx = 0; jx < WMAX; ++jx) {
+                racc = racc + row[jx] * tp.wx[jx];
+            }
+            acc = acc + racc * tp.wy[jy];
+        }
+        cx<T> v = cmul(acc, tp.ph);
+        int s = si - N / 4;
+        buf[s & (N - 1)] = v;
+        buf[(s + N / 2) & (N - 1)] = conjg(v);
+    }
+    __syncthreads();
+    lds_fft(buf, logN, 1, 0, d.tw, d.logNmax, false);
+    const T invN = T(1) / T(N);
+    for (int k = threadIdx.x; k < d.Kp; k += blockDim.x) {
+        cx<T> out = {T(0), T(0)};
+        if (k <= Kl) out = mul_ipow(buf[k] * d.Tb[(size_t)l * d.Kp + k], k);
+        Vb[(size_t)l * d.Kp + k] = out;
+        if (l < d.lcorr && k <= d.klow) Ub[(size_t)l * (d.klow + 1) + k] = (k <= Kl ? buf[k] : cx<T>{T(0), T(0)}) * invN;
+    }
+}
+
+// Cosine sum via a 2M-point FFT on CW columns of a row-major [rows][Kp] array.
+//   forward: in = V [L][Kp] (rows l), out = G [nt][Kp]:  G(j) = sum_l V_l cos(pi l j / M), j = 1..nt
+//   adjoint: in = G [nt][Kp], out = V [L][Kp]:           V(l) = sum_j G_j cos(pi l j / M), l = 0..L-1
+template <typename T>
+__global__ __launch_bounds__(NT) void dct_cols(Dev<T> d, const cx<T>* in, cx<T>* out, size_t ws_img, int adjoint)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const int b = blockIdx.y, CW = d.dctCW, k0 = blockIdx.x * CW;
+    const int N2 = 2 * d.M;
+    const cx<T>* ib = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(in) + (size_t)b * ws_img);
+    cx<T>* ob = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(out) + (size_t)b * ws_img);
+    for (int i = threadIdx.x; i < CW * N2; i += blockDim.x) buf[i] = {T(0), T(0)};
+    __syncthreads();
+    const int nin = adjoint ? d.nt : d.L;
+    for (int i = threadIdx.x; i < CW * nin; i += blockDim.x) {
+        int r = i / CW, c = i - r * CW;
+        int k = k0 + c;
+        if (k < d.Kp) buf[c * N2 + (adjoint ? r + 1 : r)] = ib[(size_t)r * d.Kp + k];
+    }
+    __syncthreads();
+    lds_fft(buf, d.log2M + 1, CW, N2, d.tw, d.logNmax, true);
+    const int nout = adjoint ? d.L : d.nt;
+    for (int i = threadIdx.x; i < CW * nout; i += blockDim.x) {
+        int r = i / CW, c = i - r * CW;
+        int k = k0 + c;
+        if (k >= d.Kp) continue;
+        int j = adjoint ? r : r + 1;
+        cx<T> v = (buf[c * N2 + j] + buf[c * N2 + ((N2 - j) & (N2 - 1))]) * T(0.5);
+        ob[(size_t)r * d.Kp + k] = v;
+    }
+}
+
+// G_k(t_j) += i^k sum_l Mk[k][j][l] Ulow[l][k], k = 0..klow
+template <typename T>
+__global__ __launch_bounds__(NT) void lowk_fwd(Dev<T> d, const cx<T>* Ulow, cx<T>* G, size_t ws_img)
+{
+    const int b = blockIdx.y;
+    const cx<T>* Ub = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(Ulow) + (size_t)b * ws_img);
+    cx<T>* Gb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(G) + (size_t)b * ws_img);
+    const int items = d.nt * (d.klow + 1);
+    for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < items; it += gridDim.x * blockDim.x) {
+        int j = it / (d.klow + 1), k = it - j * (d.klow + 1);
+        const T* row = d.Mk + ((size_t)k * d.nt + j) * d.lcorr;
+        cx<T> acc = {T(0), T(0)};
+        for (int l = 0; l < d.lcorr; ++l) acc = acc + Ub[(size_t)l * (d.klow + 1) + k] * row[l];
+        cx<T>* dst = Gb + (size_t)j * d.Kp + k;
+        *dst = *dst + mul_ipow(acc, k);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void synth_fwd(Dev<T> d, const cx<T>* G, T* g, long gstride, size_t ws_img)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* Z1 = reinterpret_cast<cx<T>*>(smem_raw);
+    cx<T>* Z2 = Z1 + d.mf;
+    const int b = blockIdx.y, j1 = 2 * blockIdx.x, j2 = j1 + 1;
+    const int mf = d.mf;
+    const cx<T>* Gb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(G) + (size_t)b * ws_img);
+    T* gb = g + (size_t)b * gstride;
+    const bool has2 = j2 < d.nt;
+    for (int r = threadIdx.x; r < mf; r += blockDim.x) {
+        cx<T> z1 = {T(0), T(0)}, z2 = {T(0), T(0)};
+        for (int k = r; k <= d.K; k += mf) {
+            cx<T> ph = d.phase[k] * (k == 0 ? T(1) : T(2));
+            z1 = z1 + cmul(ph, Gb[(size_t)j1 * d.Kp + k]);
+            if (has2) z2 = z2 + cmul(ph, Gb[(size_t)j2 * d.Kp + k]);
+        }
+        Z1[r] = z1;
+        Z2[r] = z2;
+    }
+    __syncthreads();
+    // Q_r = Herm(Z1)_r + i Herm(Z2)_r,  Herm(Z)_r = (Z_r + conj(Z_{-r}))/2.
+    // Each thread owns the pair (r, mf - r) and rewrites both entries of Z1 in place.
+    for (int r = threadIdx.x; r <= mf / 2; r += blockDim.x) {
+        int rm = (mf - r) & (mf - 1);
+        cx<T> a = Z1[r], am = Z1[rm], c = Z2[r], cm = Z2[rm];
+        cx<T> h1 = {T(0.5) * (a.x + am.x), T(0.5) * (a.y - am.y)};
+        cx<T> h2 = {T(0.5) * (c.x + cm.x), T(0.5) * (c.y - cm.y)};
+        Z1[r] = {h1.x - h2.y, h1.y + h2.x};
+        if (rm != r) Z1[rm] = {h1.x + h2.y, h2.x - h1.y};
+    }
+    __syncthreads();
+    lds_fft(Z1, d.logmf, 1, 0, d.tw, d.logNmax, true);
+    for (int i = threadIdx.x; i < d.m; i += blockDim.x) {
+        gb[(size_t)j1 * d.m + i] = Z1[i].x;
+        if (has2) gb[(size_t)j2 * d.m + i] = Z1[i].y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint kernels (exact transposes, reverse order)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void synth_adj(Dev<T> d, const T* g, long gstride, cx<T>* G, size_t ws_img)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* Z = reinterpret_cast<cx<T>*>(smem_raw);
+    const int b = blockIdx.y, j1 = 2 * blockIdx.x, j2 = j1 + 1;
+    const int mf = d.mf;
+    const bool has2 = j2 < d.nt;
+    const T* gb = g + (size_t)b * gstride;
+    cx<T>* Gb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(G) + (size_t)b * ws_img);
+    for (int i = threadIdx.x; i < mf; i += blockDim.x) {
+        T a = i < d.m ? gb[(size_t)j1 * d.m + i] : T(0);
+        T c = (i < d.m && has2) ? gb[(size_t)j2 * d.m + i] : T(0);
+        Z[i] = {a, c};
+    }
+    __syncthreads();
+    lds_fft(Z, d.logmf, 1, 0, d.tw, d.logNmax, false);
+    for (int k = threadIdx.x; k < d.Kp; k += blockDim.x) {
+        cx<T> y1 = {T(0), T(0)}, y2 = {T(0), T(0)};
+        if (k <= d.K) {
+            int r = k & (mf - 1), rm = (mf - r) & (mf - 1);
+            cx<T> zr = Z[r], zm = Z[rm];
+            y1 = {T(0.5) * (zr.x + zm.x), T(0.5) * (zr.y - zm.y)};
+            y2 = {T(0.5) * (zr.y + zm.y), T(0.5) * (zm.x - zr.x)};
+            cx<T> ph = conjg(d.phase[k]) * (k == 0 ? T(1) : T(2));
+            y1 = cmul(ph, y1);
+            y2 = cmul(ph, y2);
+        }
+        Gb[(size_t)j1 * d.Kp + k] = y1;
+        if (has2) Gb[(size_t)j2 * d.Kp + k] = y2;
+    }
+}
+
+// Ulow_hat[l][k] = conj(i^k) sum_j Mk[k][j][l] G_hat[j][k]; one block per ring l.
+template <typename T>
+__global__ __launch_bounds__(NT) void lowk_adj(Dev<T> d, const cx<T>* G, cx<T>* Ulow, size_t ws_img)
+{
+    __shared__ cx<T> red[NT];
+    const int b = blockIdx.y, l = blockIdx.x;
+    const cx<T>* Gb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(G) + (size_t)b * ws_img);
+    cx<T>* Ub = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(Ulow) + (size_t)b * ws_img);
+    for (int k = 0; k <= d.klow; ++k) {
+        cx<T> acc = {T(0), T(0)};
+        for (int j = threadIdx.x; j < d.nt; j += blockDim.x)
+            acc = acc + Gb[(size_t)j * d.Kp + k] * d.Mk[((size_t)k * d.nt + j) * d.lcorr + l];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) Ub[(size_t)l * (d.klow + 1) + k] = mul_ipow(red[0], (4 - (k & 3)) & 3);
+        __syncthreads();
+    }
+}
+
+template <typename T, int WMAX>
+__global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const cx<T>* Ulow, cx<T>* Pol,
+                                               size_t ws_img)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const int b = blockIdx.y, l = blockIdx.x;
+    const int N = d.ringN[l], logN = d.ringLog[l], Kl = d.ringK[l];
+    const cx<T>* Vb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(V) + (size_t)b * ws_img);
+    const cx<T>* Ub = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(Ulow) + (size_t)b * ws_img);
+    cx<T>* Pb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(Pol) + (size_t)b * ws_img);
+    const T invN = T(1) / T(N);
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        cx<T> v = {T(0), T(0)};
+        if (k <= Kl) {
+            v = mul_ipow(Vb[(size_t)l * d.Kp + k] * d.Tb[(size_t)l * d.Kp + k], (4 - (k & 3)) & 3);
+            if (l < d.lcorr && k <= d.klow) v = v + Ub[(size_t)l * (d.klow + 1) + k] * invN;
+        }
+        buf[k] = v;
+    }
+    __syncthreads();
+    lds_fft(buf, logN, 1, 0, d.tw, d.logNmax, true);
+    const int off = d.ringOff[l];
+    for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
+        int s = si - N / 4;
+        // transpose of the conjugate-symmetric fill; the point phase is undone in spread_adj
+        Pb[off + si] = buf[s & (N - 1)] + conjg(buf[(s + N / 2) & (N - 1)]);
+    }
+}
+
+// Transpose of the gather: each block owns a tileR x tileC tile of the extended
+// half grid and accumulates, in LDS, the taps of every half-ring sample listed
+// for it; then stores the whole tile.
+template <typename T, int WMAX>
+__global__ __launch_bounds__(NT) void spread_adj(Dev<T> d, const cx<T>* Pol, cx<T>* E, size_t ws_img)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T* acc = reinterpret_cast<T*>(smem_raw);                           // 2 * tileR * tileC
+    int* rl = reinterpret_cast<int*>(acc + 2 * d.tileR * d.tileC);      // NT runs: ring
+    int* rs = rl + NT;                                                  // first index
+    int* rp = rs + NT;                                                  // prefix of counts (NT+1)
+    const int b = blockIdx.y, t = blockIdx.x;
+    const int tr = t / d.ntileC, tc = t - tr * d.ntileC;
+    const int r0 = tr * d.tileR, c0 = tc * d.tileC;
+    const cx<T>* Pb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(Pol) + (size_t)b * ws_img);
+    cx<T>* Eb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(E) + (size_t)b * ws_img);
+    for (int i = threadIdx.x; i < 2 * d.tileR * d.tileC; i += blockDim.x) acc[i] = T(0);
+    const int rb = d.tileStart[t], re = d.tileStart[t + 1];
+    const int mask = d.Ng - 1;
+    for (int c = rb; c < re; c += NT) {
+        const int nr = min(NT, re - c);
+        __syncthreads();
+        if (threadIdx.x < nr) {
+            rl[threadIdx.x] = d.runs[3 * (c + threadIdx.x)];
+            rs[threadIdx.x] = d.runs[3 * (c + threadIdx.x) + 1];
+            rp[threadIdx.x + 1] = d.runs[3 * (c + threadIdx.x) + 2];
+        }
+        if (threadIdx.x == 0) rp[0] = 0;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int i = 1; i <= nr; ++i) rp[i] += rp[i - 1];
+        __syncthreads();
+        const int total = rp[nr];
+        for (int it = threadIdx.x; it < total; it += blockDim.x) {
+            int lo = 0, hi = nr - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (rp[mid] <= it) lo = mid;
+                else hi = mid - 1;
+            }
+            const int l = rl[lo], si = rs[lo] + (it - rp[lo]);
+            const int N = d.ringN[l];
+            Taps<T, WMAX> tp;
+            point_taps<T, WMAX>(d, d.lam[l], N, si, tp);
+            const cx<T> v = cmul(Pb[d.ringOff[l] + si], conjg(tp.ph));
+#pragma unroll
+            for (int jy = 0; jy < WMAX; ++jy) {
+                int row = (tp.gy0 + jy) & mask;
+                int rr = row - r0;
+                if (rr < 0 || rr >= d.tileR) continue;
+                cx<T> vy = v * tp.wy[jy];
+#pragma unroll
+                for (int jx = 0; jx < WMAX; ++jx) {
+                    int cc = tp.gx0 + jx + d.hw - c0;
+                    if (cc < 0 || cc >= d.tileC) continue;
+                    T* a = acc + 2 * (rr * d.tileC + cc);
+                    atomicAdd(a, vy.x * tp.wx[jx]);
+                    atomicAdd(a + 1, vy.y * tp.wx[jx]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < d.tileR * d.tileC; i += blockDim.x) {
+        int rr = i / d.tileC, cc = i - rr * d.tileC;
+        int row = r0 + rr, col = c0 + cc;
+        if (row < d.Ng && col < d.Ew) Eb[(size_t)row * d.Ew + col] = {acc[2 * i], acc[2 * i + 1]};
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void cols_adj(Dev<T> d, const cx<T>* E, cx<T>* R, size_t ws_img)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const int b = blockIdx.y, CW = d.colsCW, x0 = blockIdx.x * CW;
+    const int Ng = d.Ng, n = d.n;
+    const cx<T>* Eb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(E) + (size_t)b * ws_img);
+    cx<T>* Rb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(R) + (size_t)b * ws_img);
+    for (int i = threadIdx.x; i < CW * Ng; i += blockDim.x) {
+        int gy = i / CW, c = i - gy * CW;
+        int gx = x0 + c;
+        cx<T> v = {T(0), T(0)};
+        if (gx < d.Rw) {
+            v = Eb[(size_t)gy * d.Ew + gx + d.hw];
+            int gym = (Ng - gy) & (Ng - 1);
+            if (gx >= 1 && gx <= d.hw) v = v + conjg(Eb[(size_t)gym * d.Ew + d.hw - gx]);
+            if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) v = v + conjg(Eb[(size_t)gym * d.Ew + d.hw + Ng - gx]);
+        }
+        buf[c * Ng + gy] = v;
+    }
+    __syncthreads();
+    lds_fft(buf, d.logNg, CW, Ng, d.tw, d.logNmax, true);
+    for (int i = threadIdx.x; i < CW * n; i += blockDim.x) {
+        int p = i / CW, c = i - p * CW;
+        int gx = x0 + c;
+        if (gx < d.Rw) Rb[(size_t)p * d.Rw + gx] = buf[c * Ng + ((p - n / 2 + Ng) & (Ng - 1))];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void rows_adj(Dev<T> d, const cx<T>* R, T* f, long fstride, size_t ws_img)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const int b = blockIdx.y, p1 = 2 * blockIdx.x, p2 = p1 + 1;
+    const int Ng = d.Ng, n = d.n, hN = Ng / 2;
+    const cx<T>* Rb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(R) + (size_t)b * ws_img);
+    T* fb = f + (size_t)b * fstride;
+    const bool has2 = p2 < n;
+    for (int g = threadIdx.x; g < Ng; g += blockDim.x) {
+        cx<T> xa, xb;
+        if (g == 0 || g == hN) {
+            xa = {Rb[(size_t)p1 * d.Rw + g].x, T(0)};
+            xb = {has2 ? Rb[(size_t)p2 * d.Rw + g].x : T(0), T(0)};
+        } else if (g < hN) {
+            xa = Rb[(size_t)p1 * d.Rw + g] * T(0.5);
+            xb = has2 ? Rb[(size_t)p2 * d.Rw + g] * T(0.5) : cx<T>{T(0), T(0)};
+        } else {
+            xa = conjg(Rb[(size_t)p1 * d.Rw + (Ng - g)]) * T(0.5);
+            xb = has2 ? conjg(Rb[(size_t)p2 * d.Rw + (Ng - g)]) * T(0.5) : cx<T>{T(0), T(0)};
+        }
+        buf[g] = {xa.x - xb.y, xa.y + xb.x};
+    }
+    __syncthreads();
+    lds_fft(buf, d.logNg, 1, 0, d.tw, d.logNmax, true);
+    const T s1 = d.Dq[p1] * d.pre_scale * d.adj_scale;
+    const T s2 = has2 ? d.Dq[p2] * d.pre_scale * d.adj_scale : T(0);
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        cx<T> v = buf[(q - n / 2 + Ng) & (Ng - 1)];
+        fb[(size_t)p1 * n + q] = in_mask(d, p1, q) ? v.x * d.Dq[q] * s1 : T(0);
+        if (has2) fb[(size_t)p2 * n + q] = in_mask(d, p2, q) ? v.y * d.Dq[q] * s2 : T(0);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan object and C ABI
+// ---------------------------------------------------------------------------
+struct pat_plan_s {
+    pat::HostPlan H;
+    int max_batch = 1;
+    int device = 0;
+    size_t ws_img = 0;                    // bytes per image
+    size_t offR, offE, offV, offG, offU, offP;  // byte offsets inside one image's workspace
+    std::vector<void*> allocs;
+    size_t table_bytes = 0;
+    Dev<float> df{};
+    Dev<double> dd{};
+    // optional per-stage timing with HIP events recorded on the launch stream
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;       // pairs (start, end)
+    std::vector<int> ev_stage;             // stage of each recorded pair
+    size_t ev_used = 0;
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+void layout(pat_plan_s* p)
+{
+    const pat::Params& P = p->H.P;
+    size_t cs = (P.dt == PAT_F64) ? 16 : 8;
+    size_t o = 0;
+    p->offR = o; o = align256(o + cs * (size_t)P.n * P.Rw);
+    p->offE = o; o = align256(o + cs * (size_t)P.Ng * P.Ew);
+    p->offV = o; o = align256(o + cs * (size_t)P.L * P.Kp);
+    p->offG = o; o = align256(o + cs * (size_t)P.nt * P.Kp);
+    p->offU = o; o = align256(o + cs * (size_t)P.lcorr * (P.klow + 1));
+    p->offP = o; o = align256(o + cs * (size_t)P.npts);
+    p->ws_img = o;
+}
+
+int lds_cols(const pat::Params& P)
+{
+    size_t cs = (P.dt == PAT_F64) ? 16 : 8;
+    int cw = 16;
+    while (cw > 1 && (size_t)cw * P.Ng * cs > 65536) cw >>= 1;
+    return cw;
+}
+
+int lds_dct(const pat::Params& P)
+{
+    size_t cs = (P.dt == PAT_F64) ? 16 : 8;
+    int cw = 8;
+    while (cw > 1 && (size_t)cw * 2 * P.M * cs > 65536) cw >>= 1;
+    return cw;
+}
+
+int ilog2i(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+template <typename T>
+int upload(pat_plan_s* p, Dev<T>& d)
+{
+    const pat::HostPlan& H = p->H;
+    const pat::Params& P = H.P;
+    auto put = [&](const void* src, size_t bytes, const void** dst) -> int {
+        void* ptr = nullptr;
+        if (bytes == 0) bytes = 16;
+        if (hipMalloc(&ptr, bytes) != hipSuccess) return PAT_ENOMEM;
+        p->allocs.push_back(ptr);
+        p->table_bytes += bytes;
+        if (src && hipMemcpy(ptr, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return PAT_EHIP;
+        *dst = ptr;
+        return PAT_OK;
+    };
+    auto conv = [](const std::vector<double>& v) {
+        std::vector<T> o(v.size());
+        for (size_t i = 0; i < v.size(); ++i) o[i] = (T)v[i];
+        return o;
+    };
+    std::vector<T> Dq = conv(H.Dq), lam = conv(H.lam), Tb = conv(H.Tb), Mk = conv(H.Mk), ph = conv(H.phase),
+                   tw = conv(H.tw);
+    int rc;
+    if ((rc = put(Dq.data(), Dq.size() * sizeof(T), (const void**)&d.Dq))) return rc;
+    if ((rc = put(lam.data(), lam.size() * sizeof(T), (const void**)&d.lam))) return rc;
+    if ((rc = put(H.ringN.data(), H.ringN.size() * sizeof(int), (const void**)&d.ringN))) return rc;
+    if ((rc = put(H.ringLog.data(), H.ringLog.size() * sizeof(int), (const void**)&d.ringLog))) return rc;
+    if ((rc = put(H.ringOff.data(), H.ringOff.size() * sizeof(int), (const void**)&d.ringOff))) return rc;
+    if ((rc = put(H.ringK.data(), H.ringK.size() * sizeof(int), (const void**)&d.ringK))) return rc;
+    if ((rc = put(Tb.data(), Tb.size() * sizeof(T), (const void**)&d.Tb))) return rc;
+    if ((rc = put(Mk.data(), Mk.size() * sizeof(T), (const void**)&d.Mk))) return rc;
+    if ((rc = put(ph.data(), ph.size() * sizeof(T), (const void**)&d.phase))) return rc;
+    if ((rc = put(tw.data(), tw.size() * sizeof(T), (const void**)&d.tw))) return rc;
+    if ((rc = put(H.tileStart.data(), H.tileStart.size() * sizeof(int), (const void**)&d.tileStart))) return rc;
+    if ((rc = put(H.runs.data(), H.runs.size() * sizeof(int), (const void**)&d.runs))) return rc;
+    d.n = P.n; d.m = P.m; d.nt = P.nt; d.mf = P.mf; d.logmf = ilog2i(P.mf);
+    d.Ng = P.Ng; d.logNg = ilog2i(P.Ng); d.w = P.w; d.hw = P.hw; d.Rw = P.Rw; d.Ew = P.Ew;
+    d.M = P.M; d.log2M = ilog2i(P.M); d.L = P.L; d.K = P.K; d.Kp = P.Kp; d.klow = P.klow; d.lcorr = P.lcorr;
+    d.npts = P.npts; d.tileR = P.tileR; d.tileC = P.tileC; d.ntileC = P.ntileC; d.logNmax = ilog2i(P.Nmax);
+    d.colsCW = lds_cols(P);
+    d.dctCW = lds_dct(P);
+    d.beta = (T)P.beta; d.shift = (T)P.shift; d.half = (T)(0.5 * P.Ng / P.Lam); d.lamh = (T)P.h;
+    d.dlam = (T)P.dlam; d.pre_scale = (T)P.pre_scale; d.adj_scale = (T)P.adj_scale;
+    d.mask_r2 = P.g.mask_radius > 0 ? P.g.mask_radius * P.g.mask_radius : 0.0;
+    d.a = P.g.a; d.h = P.h;
+    return PAT_OK;
+}
+
+int fail(int code, const std::string& msg)
+{
+    pat::set_error(msg);
+    return code;
+}
+
+int check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(PAT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return PAT_OK;
+}
+
+// Records a start/end event pair around one launch when timing is enabled.
+struct StageTimer {
+    pat_plan_s* p;
+    hipStream_t st;
+    int stage;
+    StageTimer(pat_plan_s* p_, hipStream_t st_, int stage_) : p(p_), st(st_), stage(stage_)
+    {
+        if (!p->timing) return;
+        if (p->ev_used * 2 + 2 > p->ev_pool.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { p->timing = false; return; }
+            p->ev_pool.push_back(a);
+            p->ev_pool.push_back(b);
+        }
+        (void)hipEventRecord(p->ev_pool[2 * p->ev_used], st);
+    }
+    ~StageTimer()
+    {
+        if (!p->timing) return;
+        (void)hipEventRecord(p->ev_pool[2 * p->ev_used + 1], st);
+        if (p->ev_stage.size() <= p->ev_used) p->ev_stage.resize(p->ev_used + 1);
+        p->ev_stage[p->ev_used] = stage;
+        ++p->ev_used;
+    }
+};
+
+template <typename T, int WMAX>
+int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g, long gs, char* ws, hipStream_t st)
+{
+    const size_t wi = p->ws_img;
+    const size_t cs = sizeof(cx<T>);
+    cx<T>* R = reinterpret_cast<cx<T>*>(ws + p->offR);
+    cx<T>* E = reinterpret_cast<cx<T>*>(ws + p->offE);
+    cx<T>* V = reinterpret_cast<cx<T>*>(ws + p->offV);
+    cx<T>* G = reinterpret_cast<cx<T>*>(ws + p->offG);
+    cx<T>* U = reinterpret_cast<cx<T>*>(ws + p->offU);
+    int rc;
+    {
+        StageTimer tm(p, st, 0);
+        rows_fwd<T><<<dim3((d.n + 1) / 2, B), NT, cs * d.Ng, st>>>(d, f, fs, R, wi);
+    }
+    if ((rc = check_launch("rows_fwd"))) return rc;
+    {
+        StageTimer tm(p, st, 1);
+        cols_fwd<T><<<dim3((d.Rw + d.colsCW - 1) / d.colsCW, B), NT, cs * d.Ng * d.colsCW, st>>>(d, R, E, wi);
+    }
+    if ((rc = check_launch("cols_fwd"))) return rc;
+    {
+        StageTimer tm(p, st, 2);
+        ring_fwd<T, WMAX><<<dim3(d.L, B), NT, cs * p->H.P.max_ring, st>>>(d, E, V, U, wi);
+    }
+    if ((rc = check_launch("ring_fwd"))) return rc;
+    {
+        StageTimer tm(p, st, 3);
+        dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, cs * 2 * d.M * d.dctCW, st>>>(d, V, G, wi, 0);
+    }
+    if ((rc = check_launch("dct_fwd"))) return rc;
+    {
+        StageTimer tm(p, st, 4);
+        lowk_fwd<T><<<dim3((d.nt * (d.klow + 1) + NT - 1) / NT, B), NT, 0, st>>>(d, U, G, wi);
+    }
+    if ((rc = check_launch("lowk_fwd"))) return rc;
+    {
+        StageTimer tm(p, st, 5);
+        synth_fwd<T><<<dim3((d.nt + 1) / 2, B), NT, cs * 2 * d.mf, st>>>(d, G, g, gs, wi);
+    }
+    return check_launch("synth_fwd");
+}
+
+template <typename T, int WMAX>
+int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f, long fs, char* ws, hipStream_t st)
+{
+    const size_t wi = p->ws_img;
+    const size_t cs = sizeof(cx<T>);
+    cx<T>* R = reinterpret_cast<cx<T>*>(ws + p->offR);
+    cx<T>* E = reinterpret_cast<cx<T>*>(ws + p->offE);
+    cx<T>* V = reinterpret_cast<cx<T>*>(ws + p->offV);
+    cx<T>* G = reinterpret_cast<cx<T>*>(ws + p->offG);
+    cx<T>* U = reinterpret_cast<cx<T>*>(ws + p->offU);
+    cx<T>* Pol = reinterpret_cast<cx<T>*>(ws + p->offP);
+    const pat::Params& P = p->H.P;
+    int rc;
+    {
+        StageTimer tm(p, st, 6);
+        synth_adj<T><<<dim3((d.nt + 1) / 2, B), NT, cs * d.mf, st>>>(d, g, gs, G, wi);
+    }
+    if ((rc = check_launch("synth_adj"))) return rc;
+    {
+        StageTimer tm(p, st, 7);
+        lowk_adj<T><<<dim3(d.lcorr, B), NT, 0, st>>>(d, G, U, wi);
+    }
+    if ((rc = check_launch("lowk_adj"))) return rc;
+    {
+        StageTimer tm(p, st, 8);
+        dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, cs * 2 * d.M * d.dctCW, st>>>(d, G, V, wi, 1);
+    }
+    if ((rc = check_launch("dct_adj"))) return rc;
+    {
+        StageTimer tm(p, st, 9);
+        ring_adj<T, WMAX><<<dim3(d.L, B), NT, cs * P.max_ring, st>>>(d, V, U, Pol, wi);
+    }
+    if ((rc = check_launch("ring_adj"))) return rc;
+    size_t sp_lds = sizeof(T) * 2 * d.tileR * d.tileC + sizeof(int) * (3 * NT + 1);
+    {
+        StageTimer tm(p, st, 10);
+        spread_adj<T, WMAX><<<dim3(P.ntileR * P.ntileC, B), NT, sp_lds, st>>>(d, Pol, E, wi);
+    }
+    if ((rc = check_launch("spread_adj"))) return rc;
+    {
+        StageTimer tm(p, st, 11);
+        cols_adj<T><<<dim3((d.Rw + d.colsCW - 1) / d.colsCW, B), NT, cs * d.Ng * d.colsCW, st>>>(d, E, R, wi);
+    }
+    if ((rc = check_launch("cols_adj"))) return rc;
+    {
+        StageTimer tm(p, st, 12);
+        rows_adj<T><<<dim3((d.n + 1) / 2, B), NT, cs * d.Ng, st>>>(d, R, f, fs, wi);
+    }
+    return check_launch("rows_adj");
+}
+
+int lds_ok(const pat::Params& P, std::string& err)
+{
+    size_t cs = (P.dt == PAT_F64) ? 16 : 8;
+    size_t need = std::max({cs * P.Ng, cs * (size_t)P.max_ring, cs * 2 * (size_t)P.M, cs * 2 * (size_t)P.mf});
+    if (need > 65536) {
+        err = "problem too large for the single-block LDS transforms (64 KiB)";
+        return PAT_EUNSUPPORTED;
+    }
+    return PAT_OK;
+}
+
+void fill_info(const pat::Params& P, pat_plan_info* info, size_t ws_img, size_t table_bytes)
+{
+    std::memset(info, 0, sizeof(*info));
+    info->n = P.n; info->m = P.m; info->nt = P.nt; info->m_full = P.mf;
+    info->grid = P.Ng; info->stencil = P.w; info->rings = P.L; info->dct_half = P.M;
+    info->kmax = P.K; info->kpad = P.Kp; info->klow = P.klow; info->lcorr = P.lcorr;
+    info->ring_points = P.npts; info->max_ring = P.max_ring; info->spread_tiles = P.ntileR * P.ntileC;
+    info->dlam = P.dlam; info->period = P.period; info->lambda_max = P.Lam;
+    info->ws_per_image = ws_img; info->table_bytes = table_bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pat_status_string(int code)
+{
+    switch (code) {
+        case PAT_OK: return "ok";
+        case PAT_EINVAL: return "invalid argument";
+        case PAT_EUNSUPPORTED: return "unsupported configuration";
+        case PAT_ENOMEM: return "out of memory";
+        case PAT_EHIP: return "HIP runtime error";
+        case PAT_ESMALL: return "workspace or batch too small";
+        default: return "unknown status";
+    }
+}
+
+const char* pat_last_error(void) { return pat::last_error(); }
+
+int pat_debug_bessel(double x, int K, double* out)
+{
+    if (!out || K < 0) return fail(PAT_EINVAL, "pat_debug_bessel: bad arguments");
+    pat::bessel_j_all(x, K, out);
+    return PAT_OK;
+}
+
+int pat_plan_query(const pat_geometry* g, pat_dtype dt, pat_plan_info* info)
+{
+    if (!g || !info) return fail(PAT_EINVAL, "pat_plan_query: null argument");
+    pat_plan_s tmp;
+    std::string err;
+    int rc = pat::build_host_plan(*g, dt, tmp.H, err);
+    if (rc) return fail(rc, err);
+    if ((rc = lds_ok(tmp.H.P, err))) return fail(rc, err);
+    layout(&tmp);
+    fill_info(tmp.H.P, info, tmp.ws_img, 0);
+    return PAT_OK;
+}
+
+int pat_plan_create(pat_plan* out, const pat_geometry* g, pat_dtype dt, int max_batch, const char* tuning_cache_path)
+{
+    (void)tuning_cache_path;
+    if (!out) return fail(PAT_EINVAL, "pat_plan_create: out is NULL");
+    *out = nullptr;
+    if (!g) return fail(PAT_EINVAL, "pat_plan_create: geometry is NULL");
+    if (max_batch < 1) return fail(PAT_EINVAL, "pat_plan_create: max_batch must be >= 1");
+    std::unique_ptr<pat_plan_s> p(new pat_plan_s());
+    std::string err;
+    int rc = pat::build_host_plan(*g, dt, p->H, err);
+    if (rc) return fail(rc, err);
+    if ((rc = lds_ok(p->H.P, err))) return fail(rc, err);
+    if (p->H.P.w != (dt == PAT_F64 ? 13 : 6)) return fail(PAT_EUNSUPPORTED, "stencil width does not match the compiled kernels");
+    p->max_batch = max_batch;
+    layout(p.get());
+    if (hipGetDevice(&p->device) != hipSuccess) return fail(PAT_EHIP, "pat_plan_create: no HIP device");
+    rc = (dt == PAT_F64) ? upload<double>(p.get(), p->dd) : upload<float>(p.get(), p->df);
+    if (rc) {
+        for (void* a : p->allocs) (void)hipFree(a);
+        return fail(rc, "pat_plan_create: table upload failed");
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        for (void* a : p->allocs) (void)hipFree(a);
+        return fail(PAT_EHIP, "pat_plan_create: device synchronisation failed");
+    }
+    *out = p.release();
+    return PAT_OK;
+}
+
+int pat_plan_destroy(pat_plan p)
+{
+    if (!p) return fail(PAT_EINVAL, "pat_plan_destroy: NULL plan");
+    for (void* a : p->allocs) (void)hipFree(a);
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+    delete p;
+    return PAT_OK;
+}
+
+int pat_plan_get_info(pat_plan p, pat_plan_info* info)
+{
+    if (!p || !info) return fail(PAT_EINVAL, "pat_plan_get_info: null argument");
+    fill_info(p->H.P, info, p->ws_img, p->table_bytes);
+    return PAT_OK;
+}
+
+int pat_workspace_size(pat_plan p, int batch, size_t* bytes)
+{
+    if (!p || !bytes) return fail(PAT_EINVAL, "pat_workspace_size: null argument");
+    if (batch < 1 || batch > p->max_batch) return fail(PAT_ESMALL, "pat_workspace_size: batch outside [1, max_batch]");
+    *bytes = p->ws_img * (size_t)batch;
+    return PAT_OK;
+}
+
+int pat_adjoint_scale(pat_plan p, double* s)
+{
+    if (!p || !s) return fail(PAT_EINVAL, "pat_adjoint_scale: null argument");
+    *s = p->H.P.adj_scale;
+    return PAT_OK;
+}
+
+int pat_forward_batched(pat_plan p, int B, const void* f, long f_stride, void* g, long g_stride, void* ws,
+                        void* stream)
+{
+    if (!p || !f || !g || !ws) return fail(PAT_EINVAL, "pat_forward_batched: null pointer");
+    const pat::Params& P = p->H.P;
+    if (B < 1 || B > p->max_batch) return fail(PAT_ESMALL, "pat_forward_batched: B outside [1, max_batch]");
+    if (f_stride < (long)P.n * P.n || g_stride < (long)P.nt * P.m)
+        return fail(PAT_EINVAL, "pat_forward_batched: stride smaller than one image");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (P.dt == PAT_F64)
+        return run_forward<double, 13>(p, p->dd, B, (const double*)f, f_stride, (double*)g, g_stride, (char*)ws, st);
+    return run_forward<float, 6>(p, p->df, B, (const float*)f, f_stride, (float*)g, g_stride, (char*)ws, st);
+}
+
+int pat_adjoint_batched(pat_plan p, int B, const void* g, long g_stride, void* f, long f_stride, void* ws,
+                        void* stream)
+{
+    if (!p || !f || !g || !ws) return fail(PAT_EINVAL, "pat_adjoint_batched: null pointer");
+    const pat::Params& P = p->H.P;
+    if (B < 1 || B > p->max_batch) return fail(PAT_ESMALL, "pat_adjoint_batched: B outside [1, max_batch]");
+    if (f_stride < (long)P.n * P.n || g_stride < (long)P.nt * P.m)
+        return fail(PAT_EINVAL, "pat_adjoint_batched: stride smaller than one image");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (P.dt == PAT_F64)
+        return run_adjoint<double, 13>(p, p->dd, B, (const double*)g, g_stride, (double*)f, f_stride, (char*)ws, st);
+    return run_adjoint<float, 6>(p, p->df, B, (const float*)g, g_stride, (float*)f, f_stride, (char*)ws, st);
+}
+
+int pat_timing_start(pat_plan p)
+{
+    if (!p) return fail(PAT_EINVAL, "pat_timing_start: NULL plan");
+    p->timing = true;
+    p->ev_used = 0;
+    return PAT_OK;
+}
+
+int pat_timing_stop(pat_plan p, double* ms, int* launches, int nstages)
+{
+    if (!p || !ms || !launches || nstages < PAT_NUM_STAGES) return fail(PAT_EINVAL, "pat_timing_stop: bad arguments");
+    for (int i = 0; i < nstages; ++i) { ms[i] = 0.0; launches[i] = 0; }
+    for (size_t i = 0; i < p->ev_used; ++i) {
+        if (hipEventSynchronize(p->ev_pool[2 * i + 1]) != hipSuccess) return fail(PAT_EHIP, "pat_timing_stop: event sync failed");
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, p->ev_pool[2 * i], p->ev_pool[2 * i + 1]) != hipSuccess)
+            return fail(PAT_EHIP, "pat_timing_stop: elapsed time failed");
+        ms[p->ev_stage[i]] += t;
+        launches[p->ev_stage[i]] += 1;
+    }
+    p->timing = false;
+    p->ev_used = 0;
+    return PAT_OK;
+}
+
+int pat_forward(pat_plan p, const void* f, void* g, void* ws, void* stream)
+{
+    if (!p) return fail(PAT_EINVAL, "pat_forward: NULL plan");
+    return pat_forward_batched(p, 1, f, (long)p->H.P.n * p->H.P.n, g, (long)p->H.P.nt * p->H.P.m, ws, stream);
+}
+
+int pat_adjoint(pat_plan p, const void* g, void* f, void* ws, void* stream)
+{
+    if (!p) return fail(PAT_EINVAL, "pat_adjoint: NULL plan");
+    return pat_adjoint_batched(p, 1, g, (long)p->H.P.nt * p->H.P.m, f, (long)p->H.P.n * p->H.P.n, ws, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+"""Thin ctypes binding of ``libpat.so`` (the C ABI declared in include/pat.h).
+
+Only argument marshalling lives here: every step of A and A* runs in the HIP
+kernels of the library.  PyTorch supplies device memory and the current HIP
+stream.  If the library is not built, or no GPU is present, calls raise --
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpat.so")
+_lib = None
+
+PAT_F32, PAT_F64 = 0, 1
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("a", ctypes.c_double), ("R", ctypes.c_double),
+                ("c", ctypes.c_double), ("m", ctypes.c_int), ("theta0", ctypes.c_double),
+                ("arc", ctypes.c_double), ("nt", ctypes.c_int), ("T", ctypes.c_double),
+                ("taper_rho", ctypes.c_double), ("mask_radius", ctypes.c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("m", ctypes.c_int), ("nt", ctypes.c_int), ("m_full", ctypes.c_int),
+                ("grid", ctypes.c_int), ("stencil", ctypes.c_int), ("rings", ctypes.c_int),
+                ("dct_half", ctypes.c_int), ("kmax", ctypes.c_int), ("kpad", ctypes.c_int),
+                ("klow", ctypes.c_int), ("lcorr", ctypes.c_int), ("ring_points", ctypes.c_int),
+                ("max_ring", ctypes.c_int), ("spread_tiles", ctypes.c_int),
+                ("dlam", ctypes.c_double), ("period", ctypes.c_double), ("lambda_max", ctypes.c_double),
+                ("ws_per_image", ctypes.c_size_t), ("table_bytes", ctypes.c_size_t)]
+
+
+EXPORTED = ["pat_plan_create", "pat_plan_query", "pat_plan_destroy", "pat_plan_get_info",
+            "pat_workspace_size", "pat_forward", "pat_adjoint", "pat_forward_batched",
+            "pat_adjoint_batched", "pat_adjoint_scale", "pat_status_string", "pat_last_error",
+            "pat_debug_bessel"]
+
+
+def load():
+    """Load libpat.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libpat.so is not built (run __graft_entry__.build() or "
+                           "python paper_2510_24687_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, L, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_size_t
+    gp = ctypes.POINTER(Geometry)
+    lib.pat_plan_create.argtypes = [ctypes.POINTER(vp), gp, i, i, ctypes.c_char_p]
+    lib.pat_plan_query.argtypes = [gp, i, ctypes.POINTER(PlanInfo)]
+    lib.pat_plan_destroy.argtypes = [vp]
+    lib.pat_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.pat_workspace_size.argtypes = [vp, i, ctypes.POINTER(sz)]
+    lib.pat_forward.argtypes = [vp, vp, vp, vp, vp]
+    lib.pat_adjoint.argtypes = [vp, vp, vp, vp, vp]
+    lib.pat_forward_batched.argtypes = [vp, i, vp, L, vp, L, vp, vp]
+    lib.pat_adjoint_batched.argtypes = [vp, i, vp, L, vp, L, vp, vp]
+    lib.pat_adjoint_scale.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.pat_status_string.argtypes = [i]
+    lib.pat_status_string.restype = ctypes.c_char_p
+    lib.pat_last_error.restype = ctypes.c_char_p
+    lib.pat_debug_bessel.argtypes = [ctypes.c_double, i, ctypes.POINTER(ctypes.c_double)]
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        lib = load()
+        raise RuntimeError("%s failed: %s (%s)" % (what, lib.pat_status_string(rc).decode(),
+                                                    lib.pat_last_error().decode()))
+
+
+GEOM_DEFAULTS = dict(a=1.0, R=1.0, c=1.0, theta0=0.0, arc=2 * math.pi, T=2.0, rho=0.8, mask_radius=0.0)
+
+
+def make_geometry(geom: dict) -> Geometry:
+    g = dict(GEOM_DEFAULTS)
+    g.update(geom)
+    return Geometry(int(g["n"]), float(g["a"]), float(g["R"]), float(g["c"]), int(g["m"]),
+                    float(g["theta0"]), float(g["arc"]), int(g["nt"]), float(g["T"]),
+                    float(g.get("taper_rho", g["rho"])), float(g["mask_radius"]))
+
+
+def _info_dict(info: PlanInfo) -> dict:
+    return {name: getattr(info, name) for name, _ in PlanInfo._fields_}
+
+
+def plan_query(geom: dict, dtype: str = "f32") -> dict:
+    """Parameters the library would choose for this geometry (host only)."""
+    lib = load()
+    info = PlanInfo()
+    _check(lib.pat_plan_query(ctypes.byref(make_geometry(geom)), PAT_F64 if dtype == "f64" else PAT_F32,
+                              ctypes.byref(info)), "pat_plan_query")
+    return _info_dict(info)
+
+
+def debug_bessel(x: float, K: int) -> np.ndarray:
+    lib = load()
+    out = np.zeros(K + 1)
+    _check(lib.pat_debug_bessel(float(x), int(K), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "pat_debug_bessel")
+    return out
+
+
+class Plan:
+    """A plan for one geometry and precision.  ``forward`` / ``adjoint`` take
+    torch tensors on the GPU, shaped (n, n) / (nt, m) or batched (B, n, n) /
+    (B, nt, m), and return new tensors (or fill ``out``)."""
+
+    def __init__(self, geom: dict, dtype=None, max_batch: int = 1, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libpat needs a GPU: torch.cuda.is_available() is False")
+        self.torch = torch
+        self.dtype = torch.float32 if dtype is None else dtype
+        if self.dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.geom = dict(GEOM_DEFAULTS)
+        self.geom.update(geom)
+        self.n, self.m, self.nt = int(self.geom["n"]), int(self.geom["m"]), int(self.geom["nt"])
+        self.max_batch = int(max_batch)
+        lib = load()
+        self._lib = lib
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.pat_plan_create(ctypes.byref(h), ctypes.byref(make_geometry(self.geom)),
+                                       PAT_F64 if self.dtype == torch.float64 else PAT_F32,
+                                       self.max_batch, None), "pat_plan_create")
+        self._h = h
+        info = PlanInfo()
+        _check(lib.pat_plan_get_info(h, ctypes.byref(info)), "pat_plan_get_info")
+        self.info = _info_dict(info)
+        s = ctypes.c_double()
+        _check(lib.pat_adjoint_scale(h, ctypes.byref(s)), "pat_adjoint_scale")
+        self.adjoint_scale = s.value
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and self._lib is not None:
+            try:
+                self.torch.cuda.synchronize(self.device)
+            except Exception:
+                pass
+            self._lib.pat_plan_destroy(h)
+            self._h = None
+
+    def workspace(self, batch: int):
+        need = self.info["ws_per_image"] * batch
+        if self._ws is None or self._ws.numel() < need:
+            cap = self.info["ws_per_image"] * self.max_batch
+            self._ws = self.torch.empty(max(need, cap), dtype=self.torch.uint8, device=self.device)
+        return self._ws
+
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _prep(self, x, shape_tail):
+        t = self.torch
+        if not isinstance(x, t.Tensor) or x.device.type != "cuda":
+            raise TypeError("expected a CUDA tensor")
+        if x.dtype != self.dtype:
+            raise TypeError("tensor dtype %s does not match plan dtype %s" % (x.dtype, self.dtype))
+        single = x.dim() == 2
+        xb = x.unsqueeze(0) if single else x
+        if tuple(xb.shape[1:]) != shape_tail:
+            raise ValueError("expected trailing shape %s, got %s" % (shape_tail, tuple(xb.shape[1:])))
+        return xb.contiguous(), single
+
+    def forward(self, f, out=None):
+        fb, single = self._prep(f, (self.n, self.n))
+        B = fb.shape[0]
+        g = out if out is not None else self.torch.empty((B, self.nt, self.m), dtype=self.dtype, device=self.device)
+        for s in range(0, B, self.max_batch):
+            e = min(B, s + self.max_batch)
+            ws = self.workspace(e - s)
+            _check(self._lib.pat_forward_batched(self._h, e - s, ctypes.c_void_p(fb[s].data_ptr()), self.n * self.n,
+                                                 ctypes.c_void_p(g[s].data_ptr()), self.nt * self.m,
+                                                 ctypes.c_void_p(ws.data_ptr()), self._stream()),
+                   "pat_forward_batched")
+        return g[0] if single and out is None else g
+
+    def adjoint(self, g, out=None):
+        gb, single = self._prep(g, (self.nt, self.m))
+        B = gb.shape[0]
+        f = out if out is not None else self.torch.empty((B, self.n, self.n), dtype=self.dtype, device=self.device)
+        for s in range(0, B, self.max_batch):
+            e = min(B, s + self.max_batch)
+            ws = self.workspace(e - s)
+            _check(self._lib.pat_adjoint_batched(self._h, e - s, ctypes.c_void_p(gb[s].data_ptr()), self.nt * self.m,
+                                                 ctypes.c_void_p(f[s].data_ptr()), self.n * self.n,
+                                                 ctypes.c_void_p(ws.data_ptr()), self._stream()),
+                   "pat_adjoint_batched")
+        return f[0] if single and out is None else f
+
+    def transpose(self, g, out=None):
+        """Euclidean transpose A^T = A*/s."""
+        f = self.adjoint(g, out=out)
+        f.mul_(1.0 / self.adjoint_scale)
+        return f

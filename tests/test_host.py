@@ -1,0 +1,114 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports
+every symbol the header declares, validates geometries, and its plan logic
+(parameter choices, Bessel recurrence) is sound."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2510_24687_amd import pat
+from paper_2510_24687_amd import phantoms as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pat.LIB_PATH):
+        from paper_2510_24687_amd import build
+        build.build()
+    return pat.load()
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "pat.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pat_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(pat.EXPORTED) <= set(names)
+
+
+def test_status_strings(lib):
+    assert lib.pat_status_string(0) == b"ok"
+    for code in (-1, -2, -3, -4, -5):
+        assert lib.pat_status_string(code) not in (b"ok", b"unknown status")
+
+
+def test_null_arguments_are_rejected_without_device_work(lib):
+    vp = ctypes.c_void_p
+    assert lib.pat_forward(None, None, None, None, None) == -1
+    assert lib.pat_adjoint_batched(None, 1, None, 0, None, 0, None, None) == -1
+    assert lib.pat_plan_destroy(None) == -1
+    out = vp()
+    assert lib.pat_plan_create(ctypes.byref(out), None, 0, 1, None) == -1
+    assert b"NULL" in lib.pat_last_error()
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(n=4), -1), (dict(c=-1.0), -1), (dict(rho=1.0), -1), (dict(m=360), -2),
+    (dict(arc=2.0), -1), (dict(mask_radius=-0.1), -1), (dict(nt=0), -1),
+])
+def test_invalid_geometries(lib, bad, code):
+    g = P.full_circle(64, 128, 128)
+    g.update(bad)
+    info = pat.PlanInfo()
+    rc = lib.pat_plan_query(ctypes.byref(pat.make_geometry(g)), 0, ctypes.byref(info))
+    assert rc == code, lib.pat_last_error()
+
+
+def test_plan_parameters_for_the_workloads(lib):
+    m512 = pat.plan_query(P.full_circle(512, 1024, 1024), "f32")
+    assert m512["grid"] == 1024 and m512["stencil"] == 6 and m512["m_full"] == 1024
+    assert abs(m512["period"] - 8.0) < 1e-12           # 2 M c T/nt with M = 2048
+    assert m512["rings"] == 1024 and m512["dct_half"] == 2048
+    assert 820 <= m512["kmax"] <= 900                    # Lambda R = 804 plus the Bessel transition zone
+    assert m512["max_ring"] == 2048
+    arc = pat.plan_query(P.top_arc(256, 256, 512, 180.0), "f32")
+    assert arc["m_full"] == 512
+    c1 = pat.plan_query(P.full_circle(64, 128, 128), "f64")
+    assert c1["stencil"] == 13 and c1["period"] >= 16.0
+    # the period always leaves room for the compact part of every harmonic's time signal
+    for g, dt in [(P.full_circle(32, 64, 64), "f32"), (P.full_circle(128, 256, 256), "f32"),
+                  (P.top_arc(128, 256, 256, 180.0), "f64")]:
+        q = pat.plan_query(g, dt)
+        assert q["period"] > g["T"] + 1 + math.sqrt(2)
+        assert q["rings"] * q["dlam"] >= q["lambda_max"] - 1e-9
+
+
+def test_bessel_recurrence_against_mpmath(lib):
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 30
+    for x in (0.0, 0.37, 5.5, 63.0, 401.3, 804.2):
+        K = 900
+        J = pat.debug_bessel(x, K)
+        scale = np.max(np.abs(J))
+        for k in (0, 1, 2, 7, 60, int(x), int(x) + 20, 880):
+            ref = float(mpmath.besselj(k, x))
+            assert abs(J[k] - ref) <= 5e-15 * max(scale, 1e-300) + 1e-300, (x, k, J[k], ref)
+
+
+def test_product_package_does_not_touch_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2510_24687_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "from oracle" not in text, fn
+                assert "pat_oracle" not in text, fn
+
+
+def test_plan_needs_a_gpu_and_says_so():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError, match="GPU"):
+        pat.Plan(P.full_circle(32, 64, 64))
