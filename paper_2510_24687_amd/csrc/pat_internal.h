@@ -34,8 +34,6 @@ struct Params {
     int Nmax;               // twiddle table length (largest FFT)
     int max_ring;           // largest ring FFT
     int npts;               // half-ring samples over all rings
-    int tileR, tileC, ntileR, ntileC;  // spread tiling of the extended half grid
-    int nruns;
     double pre_scale;       // h^2 / (2 pi)
     double adj_scale;       // (T/nt)(R arc/m)/h^2
 };
@@ -49,8 +47,7 @@ struct HostPlan {
     std::vector<double> Mk;                 // (klow+1) x nt x lcorr
     std::vector<double> phase;              // 2*Kp: e^{i k theta0} (re, im)
     std::vector<double> tw;                 // 2*Nmax: e^{-2 pi i k / Nmax} (re, im)
-    std::vector<int> tileStart;             // ntiles + 1
-    std::vector<int> runs;                  // 3 per run: ring, first half-ring index, count
+    std::vector<double> pos;                // 2*npts: grid position (x, y) of each half-ring sample
 };
 
 // Fills P and all host tables.  Returns PAT_OK or an error with `err` set.

@@ -36,6 +36,8 @@ const char* last_error();
 namespace {
 
 constexpr int NT = 256;  // threads per block for every kernel
+constexpr int FFT_REGS = 16;                 // complex values per thread and pass in lds_fft
+constexpr int FFT_BLOCK_POINTS = FFT_REGS * NT;  // nb * N limit of one lds_fft call
 
 template <typename T>
 struct cx {
@@ -64,8 +66,6 @@ __device__ __forceinline__ cx<T> mul_ipow(cx<T> a, int k)
     }
 }
 
-__device__ __forceinline__ void sincospi_t(float x, float* s, float* c) { sincospif(x, s, c); }
-__device__ __forceinline__ void sincospi_t(double x, double* s, double* c) { sincospi(x, s, c); }
 __device__ __forceinline__ void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ float exp_t(float x) { return expf(x); }
@@ -76,67 +76,159 @@ __device__ __forceinline__ float ceil_t(float x) { return ceilf(x); }
 __device__ __forceinline__ double ceil_t(double x) { return ceil(x); }
 
 // ---------------------------------------------------------------------------
-// In-LDS FFT of `nb` independent sequences of length 2^logN stored at
-// buf + b*stride.  Iterative decimation in time: bit-reversal permutation,
-// an optional radix-2 stage, then radix-4 stages (two radix-2 stages fused in
-// registers).  tw holds e^{-2 pi i k/Nmax}; inverse = conjugate twiddles (no
-// 1/N).  All threads of the block take part; the routine ends synchronised.
+// FFT of `nb` independent sequences of length N = 2^logN held in LDS at
+// buf + b*stride: Stockham autosort (natural order in and out, no bit
+// reversal) with radix-16/8/4/2 butterflies computed in registers, so an
+// N = 4096 transform takes three LDS round trips.  A pass with radix R and
+// sub-transform length Ns reads x[t + r N/R], multiplies by W_{Ns R}^{r k}
+// (k = t mod Ns), does a length-R DFT and writes to (t/Ns) Ns R + k + r Ns.
+// tw holds e^{-2 pi i k/Nmax}; `inv` selects e^{+...} (no 1/N).  Requires
+// blockDim.x == NT and nb*N <= FFT_BLOCK_POINTS (each thread keeps at most
+// FFT_REGS complex values of one pass in registers).  Ends synchronised.
 // ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void dft4(cx<T>& a, cx<T>& b, cx<T>& c, cx<T>& e, bool inv)
+{
+    cx<T> s0 = a + c, d0 = a - c, s1 = b + e, d1 = b - e;
+    cx<T> jd1 = inv ? cx<T>{-d1.y, d1.x} : cx<T>{d1.y, -d1.x};  // -i d1 (forward) / +i d1 (inverse)
+    a = s0 + s1;
+    c = s0 - s1;
+    b = d0 + jd1;
+    e = d0 - jd1;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_reg(cx<T>* v, bool inv);
+
+template <>
+__device__ __forceinline__ void dft_reg<float, 2>(cx<float>* v, bool) { cx<float> t = v[0]; v[0] = t + v[1]; v[1] = t - v[1]; }
+template <>
+__device__ __forceinline__ void dft_reg<double, 2>(cx<double>* v, bool) { cx<double> t = v[0]; v[0] = t + v[1]; v[1] = t - v[1]; }
+
+template <typename T>
+__device__ __forceinline__ void dft4_arr(cx<T>* v, bool inv) { dft4(v[0], v[1], v[2], v[3], inv); }
+template <>
+__device__ __forceinline__ void dft_reg<float, 4>(cx<float>* v, bool inv) { dft4_arr(v, inv); }
+template <>
+__device__ __forceinline__ void dft_reg<double, 4>(cx<double>* v, bool inv) { dft4_arr(v, inv); }
+
+// e^{-2 pi i m/16}, m = 0..15
+__constant__ const double W16C[16] = {1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977, 0.0,
+                                      -0.38268343236508977, -0.70710678118654752, -0.92387953251128674, -1.0,
+                                      -0.92387953251128674, -0.70710678118654752, -0.38268343236508977, 0.0,
+                                      0.38268343236508977, 0.70710678118654752, 0.92387953251128674};
+
+template <typename T>
+__device__ __forceinline__ cx<T> w16(int m, bool inv)
+{
+    // cos(2 pi m/16), -sin(2 pi m/16) (forward)
+    const T c = (T)W16C[m & 15];
+    const T s = (T)W16C[(m + 12) & 15];  // cos(2 pi (m-4)/16) = sin(2 pi m/16)
+    return inv ? cx<T>{c, s} : cx<T>{c, -s};
+}
+
+// size N1*N2 DFT from N2 DFTs of size N1 (stride N2), twiddles W_N^{n2 k1}, N1 DFTs of size N2
+template <typename T, int R>
+__device__ __forceinline__ void dft_split(cx<T>* v, bool inv)
+{
+    constexpr int N1 = 4, N2 = R / 4;
+    cx<T> a[N2][N1];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) a[n2][n1] = v[N2 * n1 + n2];
+        dft4(a[n2][0], a[n2][1], a[n2][2], a[n2][3], inv);
+#pragma unroll
+        for (int k1 = 1; k1 < N1; ++k1)
+            if (n2 > 0) a[n2][k1] = cmul(a[n2][k1], w16<T>((16 / R) * n2 * k1, inv));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+        if (N2 == 2) {
+            cx<T> t = a[0][k1];
+            v[k1] = t + a[1][k1];
+            v[k1 + 4] = t - a[1][k1];
+        } else {
+            cx<T> b0 = a[0][k1], b1 = a[1][k1], b2 = a[2][k1], b3 = a[3][k1];
+            dft4(b0, b1, b2, b3, inv);
+            v[k1] = b0;
+            v[k1 + 4] = b1;
+            v[k1 + 8] = b2;
+            v[k1 + 12] = b3;
+        }
+    }
+}
+template <>
+__device__ __forceinline__ void dft_reg<float, 8>(cx<float>* v, bool inv) { dft_split<float, 8>(v, inv); }
+template <>
+__device__ __forceinline__ void dft_reg<double, 8>(cx<double>* v, bool inv) { dft_split<double, 8>(v, inv); }
+template <>
+__device__ __forceinline__ void dft_reg<float, 16>(cx<float>* v, bool inv) { dft_split<float, 16>(v, inv); }
+template <>
+__device__ __forceinline__ void dft_reg<double, 16>(cx<double>* v, bool inv) { dft_split<double, 16>(v, inv); }
+
+template <typename T, int R>
+__device__ __noinline__ void stockham_pass(cx<T>* buf, int logN, int logNs, int nb, int stride,
+                                              const cx<T>* __restrict__ tw, int logNmax, bool inv)
+{
+    constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+    constexpr int BPT = FFT_REGS / R;
+    const int lnbf = logN - LR;
+    const int nbf = 1 << lnbf;
+    const int total = nb << lnbf;
+    cx<T> v[BPT][R];
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int it = threadIdx.x + u * NT;
+        if (it < total) {
+            const int b = it >> lnbf, t = it & (nbf - 1);
+            const cx<T>* s = buf + b * stride;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[u][r] = s[t + (r << lnbf)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int it = threadIdx.x + u * NT;
+        if (it < total) {
+            const int b = it >> lnbf, t = it & (nbf - 1);
+            const int k = t & ((1 << logNs) - 1);
+            if (logNs > 0) {
+                const int sh = logNmax - logNs - LR;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cx<T> w = tw[(r * k) << sh];
+                    if (inv) w.y = -w.y;
+                    v[u][r] = cmul(v[u][r], w);
+                }
+            }
+            dft_reg<T, R>(v[u], inv);
+            cx<T>* s = buf + b * stride;
+            const int base = ((t >> logNs) << (logNs + LR)) + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) s[base + (r << logNs)] = v[u][r];
+        }
+    }
+    __syncthreads();
+}
+
 template <typename T>
 __device__ void lds_fft(cx<T>* buf, int logN, int nb, int stride, const cx<T>* __restrict__ tw, int logNmax,
                         bool inverse)
 {
-    const int N = 1 << logN;
-    const int tid = threadIdx.x, nth = blockDim.x;
     if (logN == 0) return;
-    for (int it = tid; it < nb * N; it += nth) {
-        int b = it >> logN, i = it & (N - 1);
-        int j = __brev((unsigned)i) >> (32 - logN);
-        if (i < j) {
-            cx<T>* s = buf + b * stride;
-            cx<T> t = s[i];
-            s[i] = s[j];
-            s[j] = t;
+    const int P = (logN + 3) / 4;  // passes; radices as equal as possible, at most 16
+    int logNs = 0;
+    for (int p = 0; p < P; ++p) {
+        const int lr = logN / P + (p < logN % P ? 1 : 0);
+        switch (lr) {
+            case 1: stockham_pass<T, 2>(buf, logN, logNs, nb, stride, tw, logNmax, inverse); break;
+            case 2: stockham_pass<T, 4>(buf, logN, logNs, nb, stride, tw, logNmax, inverse); break;
+            case 3: stockham_pass<T, 8>(buf, logN, logNs, nb, stride, tw, logNmax, inverse); break;
+            default: stockham_pass<T, 16>(buf, logN, logNs, nb, stride, tw, logNmax, inverse); break;
         }
-    }
-    __syncthreads();
-    int st = 0;
-    if (logN & 1) {
-        for (int it = tid; it < nb * (N >> 1); it += nth) {
-            int b = it >> (logN - 1), i = it & ((N >> 1) - 1);
-            cx<T>* s = buf + b * stride;
-            cx<T> a0 = s[2 * i], a1 = s[2 * i + 1];
-            s[2 * i] = a0 + a1;
-            s[2 * i + 1] = a0 - a1;
-        }
-        __syncthreads();
-        st = 1;
-    }
-    for (; st < logN; st += 2) {
-        const int h = 1 << st;
-        const int sh1 = logNmax - st - 1, sh2 = logNmax - st - 2;
-        const int q = N >> 2;
-        for (int it = tid; it < nb * q; it += nth) {
-            int b = it / q, g = it - b * q;
-            int j = g & (h - 1);
-            int i0 = ((g >> st) << (st + 2)) + j;
-            cx<T>* s = buf + b * stride;
-            cx<T> a0 = s[i0], a1 = s[i0 + h], a2 = s[i0 + 2 * h], a3 = s[i0 + 3 * h];
-            cx<T> w1 = tw[j << sh1], w2 = tw[j << sh2];
-            if (inverse) {
-                w1.y = -w1.y;
-                w2.y = -w2.y;
-            }
-            cx<T> t1 = cmul(w1, a1), t3 = cmul(w1, a3);
-            cx<T> b0 = a0 + t1, b1 = a0 - t1, b2 = a2 + t3, b3 = a2 - t3;
-            cx<T> u2 = cmul(w2, b2), u3 = cmul(w2, b3);
-            u3 = inverse ? cx<T>{-u3.y, u3.x} : cx<T>{u3.y, -u3.x};
-            s[i0] = b0 + u2;
-            s[i0 + 2 * h] = b0 - u2;
-            s[i0 + h] = b1 + u3;
-            s[i0 + 3 * h] = b1 - u3;
-        }
-        __syncthreads();
+        logNs += lr;
     }
 }
 
@@ -146,7 +238,7 @@ struct Dev {
     int n, m, nt, mf, logmf;
     int Ng, logNg, w, hw, Rw, Ew;
     int M, log2M, L, K, Kp, klow, lcorr, npts;
-    int tileR, tileC, ntileC, logNmax;
+    int logNmax;
     int colsCW, dctCW;
     T beta, shift, half;        // half = Ng / (2 Lambda): grid cells per unit lambda
     T lamh;                     // h: u = lambda h cos(phi)
@@ -162,8 +254,7 @@ struct Dev {
     const T* Mk;                // (klow+1) x nt x lcorr
     const cx<T>* phase;         // Kp
     const cx<T>* tw;            // Nmax
-    const int* tileStart;       // ntiles+1
-    const int* runs;            // 3 per run
+    const cx<T>* pos;           // npts: grid position (x, y) of each half-ring sample
 };
 
 template <typename T>
@@ -192,13 +283,31 @@ struct Taps {
     cx<T> ph;  // e^{-i shift (u + v)}
 };
 
-template <typename T, int WMAX>
-__device__ __forceinline__ void point_taps(const Dev<T>& d, T lam, int N, int si, Taps<T, WMAX>& tp)
+// Grid position (cells) of half-ring sample si of a ring with N samples at
+// radius lam: x = lam * Ng/(2 Lambda) * cos(2 pi s/N), s = si - N/4.  The
+// gather and the spread both call this, so they select identical taps.
+template <typename T>
+__device__ __forceinline__ void point_xy(const Dev<T>& d, int p, T& x, T& y)
 {
-    int s = si - (N >> 2);
-    T sn, cs;
-    sincospi_t(T(2) * T(s) / T(N), &sn, &cs);
-    T x = lam * d.half * cs, y = lam * d.half * sn;
+    const cx<T> q = d.pos[p];
+    x = q.x;
+    y = q.y;
+}
+
+// e^{-i shift (u + v)} of a sample at grid position (x, y): u + v = h lam (cos + sin) = h (x + y)/half
+template <typename T>
+__device__ __forceinline__ cx<T> point_phase(const Dev<T>& d, T x, T y)
+{
+    T ps, pc;
+    sincos_t(-d.shift * d.lamh * (x + y) / d.half, &ps, &pc);
+    return {pc, ps};
+}
+
+template <typename T, int WMAX>
+__device__ __forceinline__ void point_taps(const Dev<T>& d, int p, Taps<T, WMAX>& tp)
+{
+    T x, y;
+    point_xy(d, p, x, y);
     T hwf = T(0.5) * T(WMAX);
     tp.gx0 = (int)ceil_t(x - hwf);
     tp.gy0 = (int)ceil_t(y - hwf);
@@ -208,10 +317,7 @@ __device__ __forceinline__ void point_taps(const Dev<T>& d, T lam, int N, int si
         tp.wx[j] = es_w(x - T(tp.gx0 + j), tw_, d.beta);
         tp.wy[j] = es_w(y - T(tp.gy0 + j), tw_, d.beta);
     }
-    T ang = -d.shift * lam * d.lamh * (cs + sn);
-    T ps, pc;
-    sincos_t(ang, &ps, &pc);
-    tp.ph = {pc, ps};
+    tp.ph = point_phase(d, x, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -285,14 +391,13 @@ __global__ __launch_bounds__(NT) void ring_fwd(Dev<T> d, const cx<T>* E, cx<T>* 
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     const int b = blockIdx.y, l = blockIdx.x;
     const int N = d.ringN[l], logN = d.ringLog[l], Kl = d.ringK[l];
-    const T lam = d.lam[l];
     const cx<T>* Eb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(E) + (size_t)b * ws_img);
     cx<T>* Vb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(V) + (size_t)b * ws_img);
     cx<T>* Ub = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(Ulow) + (size_t)b * ws_img);
     const int mask = d.Ng - 1;
     for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
         Taps<T, WMAX> tp;
-        point_taps<T, WMAX>(d, lam, N, si, tp);
+        point_taps<T, WMAX>(d, d.ringOff[l] + si, tp);
         cx<T> acc = {T(0), T(0)};
 #pragma unroll
         for (int jy = 0; jy < WMAX; ++jy) {
@@ -320,36 +425,53 @@ __global__ __launch_bounds__(NT) void ring_fwd(Dev<T> d, const cx<T>* E, cx<T>* 
     }
 }
 
-// Cosine sum via a 2M-point FFT on CW columns of a row-major [rows][Kp] array.
-//   forward: in = V [L][Kp] (rows l), out = G [nt][Kp]:  G(j) = sum_l V_l cos(pi l j / M), j = 1..nt
-//   adjoint: in = G [nt][Kp], out = V [L][Kp]:           V(l) = sum_j G_j cos(pi l j / M), l = 0..L-1
+// Cosine sum on CW columns of a row-major [rows][Kp] array:
+//   forward: in = V [L][Kp] (x = l),       out = G [nt][Kp] (y = j = 1..nt)
+//   adjoint: in = G [nt][Kp] (x = j),      out = V [L][Kp] (y = l = 0..L-1)
+//   out(y) = sum_x in(x) cos(pi x y / M) = (X(y) + X(-y))/2, X(y) = sum_x in(x) e^{i pi x y/M}.
+// Outputs are split by parity, y = 2y' + r: X(2y'+r) is the M-point inverse DFT of
+// in(x) e^{i pi x r/M} (folded mod M) at y', and X(-y) = that DFT at (-y'-r) mod M.
+// Two M-point FFTs replace one 2M-point FFT of a zero-padded column.
 template <typename T>
 __global__ __launch_bounds__(NT) void dct_cols(Dev<T> d, const cx<T>* in, cx<T>* out, size_t ws_img, int adjoint)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     const int b = blockIdx.y, CW = d.dctCW, k0 = blockIdx.x * CW;
-    const int N2 = 2 * d.M;
+    const int M = d.M, logM = d.log2M;
     const cx<T>* ib = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(in) + (size_t)b * ws_img);
     cx<T>* ob = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(out) + (size_t)b * ws_img);
-    for (int i = threadIdx.x; i < CW * N2; i += blockDim.x) buf[i] = {T(0), T(0)};
-    __syncthreads();
-    const int nin = adjoint ? d.nt : d.L;
-    for (int i = threadIdx.x; i < CW * nin; i += blockDim.x) {
-        int r = i / CW, c = i - r * CW;
-        int k = k0 + c;
-        if (k < d.Kp) buf[c * N2 + (adjoint ? r + 1 : r)] = ib[(size_t)r * d.Kp + k];
-    }
-    __syncthreads();
-    lds_fft(buf, d.log2M + 1, CW, N2, d.tw, d.logNmax, true);
+    // valid input indices x in [x_lo, x_hi), stored at row x - x_lo
+    const int x_lo = adjoint ? 1 : 0, x_hi = adjoint ? d.nt + 1 : d.L;
     const int nout = adjoint ? d.L : d.nt;
-    for (int i = threadIdx.x; i < CW * nout; i += blockDim.x) {
-        int r = i / CW, c = i - r * CW;
-        int k = k0 + c;
-        if (k >= d.Kp) continue;
-        int j = adjoint ? r : r + 1;
-        cx<T> v = (buf[c * N2 + j] + buf[c * N2 + ((N2 - j) & (N2 - 1))]) * T(0.5);
-        ob[(size_t)r * d.Kp + k] = v;
+    const int sh = d.logNmax - logM - 1;  // e^{i pi x/M} = conj(tw[x << sh])
+    for (int r = 0; r < 2; ++r) {
+        for (int i = threadIdx.x; i < CW * M; i += blockDim.x) {
+            const int xs = i / CW, c = i - xs * CW;  // slot xs = x mod M
+            const int k = k0 + c;
+            cx<T> acc = {T(0), T(0)};
+            if (k < d.Kp) {
+                for (int x = xs; x < x_hi; x += M) {
+                    if (x < x_lo) continue;
+                    cx<T> v = ib[(size_t)(x - x_lo) * d.Kp + k];
+                    if (r) v = cmul(v, conjg(d.tw[x << sh]));
+                    acc = acc + v;
+                }
+            }
+            buf[c * M + xs] = acc;
+        }
+        __syncthreads();
+        lds_fft(buf, logM, CW, M, d.tw, d.logNmax, true);
+        for (int i = threadIdx.x; i < CW * nout; i += blockDim.x) {
+            const int orow = i / CW, c = i - orow * CW;
+            const int k = k0 + c;
+            const int y = adjoint ? orow : orow + 1;
+            if (k >= d.Kp || (y & 1) != r) continue;
+            const int yp = (y - r) >> 1;
+            const int ypp = (M - yp - r) & (M - 1);
+            ob[(size_t)orow * d.Kp + k] = (buf[c * M + yp] + buf[c * M + ypp]) * T(0.5);
+        }
+        __syncthreads();
     }
 }
 
@@ -470,17 +592,18 @@ __global__ __launch_bounds__(NT) void lowk_adj(Dev<T> d, const cx<T>* G, cx<T>* 
     }
 }
 
+// Samples are written image-minor, Pol[(ringOff[l] + si) * B + b], already
+// multiplied by the conjugate point phase, for the batched spread below.
 template <typename T, int WMAX>
-__global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const cx<T>* Ulow, cx<T>* Pol,
+__global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const cx<T>* Ulow, cx<T>* Pol, int B,
                                                size_t ws_img)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const int b = blockIdx.y, l = blockIdx.x;
+    const int b = blockIdx.x, l = blockIdx.y;
     const int N = d.ringN[l], logN = d.ringLog[l], Kl = d.ringK[l];
     const cx<T>* Vb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(V) + (size_t)b * ws_img);
     const cx<T>* Ub = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(Ulow) + (size_t)b * ws_img);
-    cx<T>* Pb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(Pol) + (size_t)b * ws_img);
     const T invN = T(1) / T(N);
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         cx<T> v = {T(0), T(0)};
@@ -494,79 +617,130 @@ __global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const c
     lds_fft(buf, logN, 1, 0, d.tw, d.logNmax, true);
     const int off = d.ringOff[l];
     for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
-        int s = si - N / 4;
-        // transpose of the conjugate-symmetric fill; the point phase is undone in spread_adj
-        Pb[off + si] = buf[s & (N - 1)] + conjg(buf[(s + N / 2) & (N - 1)]);
+        const int s = si - N / 4;
+        // transpose of the conjugate-symmetric fill, then of the point phase
+        const cx<T> uf = buf[s & (N - 1)] + conjg(buf[(s + N / 2) & (N - 1)]);
+        T x, y;
+        point_xy(d, off + si, x, y);
+        Pol[(size_t)(off + si) * B + b] = cmul(uf, conjg(point_phase(d, x, y)));
     }
 }
 
-// Transpose of the gather: each block owns a tileR x tileC tile of the extended
-// half grid and accumulates, in LDS, the taps of every half-ring sample listed
-// for it; then stores the whole tile.
-template <typename T, int WMAX>
-__global__ __launch_bounds__(NT) void spread_adj(Dev<T> d, const cx<T>* Pol, cx<T>* E, size_t ws_img)
+// Transpose of the gather.  Each wave owns an 8 x 8 tile of cells of the
+// extended half grid (one cell per lane) and BC images.  A sample at grid
+// position (x, y) feeds cell (gx, gy) exactly when gx - ceil(x - w/2) lies in
+// [0, w) and (gy - ceil(y - w/2)) mod Ng lies in [0, w) -- the gather's own tap
+// rule -- so every sample that can feed the tile lies in the tile's box
+// widened by w/2 (plus half a cell).  The lanes first compute, one ring per
+// lane, the interval of sample angles where the ring crosses that box (asin of
+// the box's y-band intersected with acos of its x-band); then the whole wave
+// walks those samples in lockstep: position and the BC image values of the
+// current sample are the same for every lane (scalar loads, one cache line),
+// each lane tests the tap rule for its own cell and accumulates weight *
+// value.  No atomics; a fixed summation order per cell.
+template <typename T, int W, int BC>
+__global__ __launch_bounds__(NT) void spread_tiles(Dev<T> d, const cx<T>* Pol, int B, cx<T>* E, size_t ws_img)
 {
-    extern __shared__ unsigned char smem_raw[];
-    T* acc = reinterpret_cast<T*>(smem_raw);                           // 2 * tileR * tileC
-    int* rl = reinterpret_cast<int*>(acc + 2 * d.tileR * d.tileC);      // NT runs: ring
-    int* rs = rl + NT;                                                  // first index
-    int* rp = rs + NT;                                                  // prefix of counts (NT+1)
-    const int b = blockIdx.y, t = blockIdx.x;
-    const int tr = t / d.ntileC, tc = t - tr * d.ntileC;
-    const int r0 = tr * d.tileR, c0 = tc * d.tileC;
-    const cx<T>* Pb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(Pol) + (size_t)b * ws_img);
-    cx<T>* Eb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(E) + (size_t)b * ws_img);
-    for (int i = threadIdx.x; i < 2 * d.tileR * d.tileC; i += blockDim.x) acc[i] = T(0);
-    const int rb = d.tileStart[t], re = d.tileStart[t + 1];
-    const int mask = d.Ng - 1;
-    for (int c = rb; c < re; c += NT) {
-        const int nr = min(NT, re - c);
-        __syncthreads();
-        if (threadIdx.x < nr) {
-            rl[threadIdx.x] = d.runs[3 * (c + threadIdx.x)];
-            rs[threadIdx.x] = d.runs[3 * (c + threadIdx.x) + 1];
-            rp[threadIdx.x + 1] = d.runs[3 * (c + threadIdx.x) + 2];
-        }
-        if (threadIdx.x == 0) rp[0] = 0;
-        __syncthreads();
-        if (threadIdx.x == 0)
-            for (int i = 1; i <= nr; ++i) rp[i] += rp[i - 1];
-        __syncthreads();
-        const int total = rp[nr];
-        for (int it = threadIdx.x; it < total; it += blockDim.x) {
-            int lo = 0, hi = nr - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (rp[mid] <= it) lo = mid;
-                else hi = mid - 1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tx0 = blockIdx.x * 16 + (wave & 1) * 8;   // first column of the wave's tile
+    const int ty0 = blockIdx.y * 16 + (wave >> 1) * 8;  // first row
+    const int e = tx0 + (lane & 7), gy = ty0 + (lane >> 3);
+    const int b0 = blockIdx.z * BC;
+    const int nb = min(BC, B - b0);
+    const int Ng = d.Ng, mask = Ng - 1;
+    const bool valid = e < d.Ew && gy < Ng;
+    const int gx = e - d.hw;
+    const T hwf = T(0.5) * T(W), tw_ = T(2) / T(W);
+    const T rstep = d.half * d.dlam;  // ring spacing in cells
+    const T TWO_PI = T(6.283185307179586);
+    cx<T> acc[BC];
+#pragma unroll
+    for (int k = 0; k < BC; ++k) acc[k] = {T(0), T(0)};
+    if (ty0 < Ng && tx0 < d.Ew) {
+        const int gys0 = ty0 < Ng / 2 ? ty0 : ty0 - Ng;  // signed first row (tiles never straddle Ng/2)
+        const int gxf = tx0 - d.hw;
+        for (int wrap = 0; wrap < 2; ++wrap) {
+            int ys = gys0;
+            if (wrap) {
+                if (gys0 > -Ng / 2 + W + 2 && gys0 + 8 < Ng / 2 - W - 2) break;
+                ys = gys0 > 0 ? gys0 - Ng : gys0 + Ng;
             }
-            const int l = rl[lo], si = rs[lo] + (it - rp[lo]);
-            const int N = d.ringN[l];
-            Taps<T, WMAX> tp;
-            point_taps<T, WMAX>(d, d.lam[l], N, si, tp);
-            const cx<T> v = cmul(Pb[d.ringOff[l] + si], conjg(tp.ph));
+            const T xa = max(T(gxf) - hwf - T(0.5), T(0)), xb = T(gxf + 7) + hwf + T(0.5);
+            const T ya = T(ys) - hwf - T(0.5), yb = T(ys + 7) + hwf + T(0.5);
+            if (xb <= T(0)) continue;
+            const T dy = ya > T(0) ? ya : (yb < T(0) ? -yb : T(0));
+            const T rmin = sqrt_t(xa * xa + dy * dy);
+            const T rmax = sqrt_t(xb * xb + max(ya * ya, yb * yb));
+            const int l0 = max(0, (int)(rmin / rstep) - 1);
+            const int l1 = min(d.L - 1, (int)(rmax / rstep) + 1);
+            for (int rb = l0; rb <= l1; rb += 64) {
+                // this lane's ring: sample-index intervals [u_lo, u_hi] and [v_lo, v_hi]
+                const int l = rb + lane;
+                int u_lo = 1, u_hi = 0, v_lo = 1, v_hi = 0;
+                if (l <= l1) {
+                    const int N = d.ringN[l], q4 = N >> 2, off = d.ringOff[l] + q4;
+                    const T rho = d.lam[l] * d.half;
+                    if (rho <= T(0)) {
+                        u_lo = off - q4;
+                        u_hi = off + q4 - 1;
+                    } else if (rho >= rmin - T(1) && rho <= rmax + T(1)) {
+                        const T f = T(N) / TWO_PI;
+                        const T pya = asin(max(T(-1), min(T(1), ya / rho)));
+                        const T pyb = asin(max(T(-1), min(T(1), yb / rho)));
+                        const T pxl = acos(max(T(-1), min(T(1), xb / rho)));
+                        const T pxh = acos(max(T(-1), min(T(1), xa / rho)));
+                        const T a0 = max(pya, pxl), a1 = min(pyb, pxh);      // upper branch of the x-band
+                        const T c0 = max(pya, -pxh), c1 = min(pyb, -pxl);    // lower branch
+                        int s0 = 1, s1 = 0, t0 = 1, t1 = 0;
+                        if (a0 <= a1) {
+                            s0 = max(-q4, (int)ceil_t(a0 * f - T(0.05)));
+                            s1 = min(q4 - 1, (int)floor(a1 * f + T(0.05)));
+                        }
+                        if (c0 <= c1) {
+                            t0 = max(-q4, (int)ceil_t(c0 * f - T(0.05)));
+                            t1 = min(q4 - 1, (int)floor(c1 * f + T(0.05)));
+                        }
+                        if (s0 <= s1 && t0 <= t1 && t1 >= s0 - 1 && t0 <= s1 + 1) {  // touching: merge
+                            s0 = min(s0, t0);
+                            s1 = max(s1, t1);
+                            t0 = 1;
+                            t1 = 0;
+                        }
+                        u_lo = off + s0; u_hi = off + s1;
+                        v_lo = off + t0; v_hi = off + t1;
+                    }
+                }
+                const int nr = min(64, l1 - rb + 1);
+                for (int r = 0; r < nr; ++r) {
+                    for (int part = 0; part < 2; ++part) {
+                        const int plo = __builtin_amdgcn_readlane(part ? v_lo : u_lo, r);
+                        const int phi = __builtin_amdgcn_readlane(part ? v_hi : u_hi, r);
+                        for (int p = plo; p <= phi; ++p) {
+                            const cx<T> q = d.pos[p];
+                            const int gx0 = (int)ceil_t(q.x - hwf);
+                            const int gy0 = (int)ceil_t(q.y - hwf);
+                            const int jx = gx - gx0;
+                            const int jy = (gy - gy0) & mask;
+                            if (valid && (unsigned)jx < (unsigned)W && jy < W) {
+                                const T wgt = es_w(q.x - T(gx0 + jx), tw_, d.beta) * es_w(q.y - T(gy0 + jy), tw_, d.beta);
+                                const cx<T>* src = Pol + (size_t)p * B + b0;
 #pragma unroll
-            for (int jy = 0; jy < WMAX; ++jy) {
-                int row = (tp.gy0 + jy) & mask;
-                int rr = row - r0;
-                if (rr < 0 || rr >= d.tileR) continue;
-                cx<T> vy = v * tp.wy[jy];
-#pragma unroll
-                for (int jx = 0; jx < WMAX; ++jx) {
-                    int cc = tp.gx0 + jx + d.hw - c0;
-                    if (cc < 0 || cc >= d.tileC) continue;
-                    T* a = acc + 2 * (rr * d.tileC + cc);
-                    atomicAdd(a, vy.x * tp.wx[jx]);
-                    atomicAdd(a + 1, vy.y * tp.wx[jx]);
+                                for (int k = 0; k < BC; ++k)
+                                    if (k < nb) acc[k] = acc[k] + src[k] * wgt;
+                            }
+                        }
+                    }
                 }
             }
         }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < d.tileR * d.tileC; i += blockDim.x) {
-        int rr = i / d.tileC, cc = i - rr * d.tileC;
-        int row = r0 + rr, col = c0 + cc;
-        if (row < d.Ng && col < d.Ew) Eb[(size_t)row * d.Ew + col] = {acc[2 * i], acc[2 * i + 1]};
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < BC; ++k)
+            if (k < nb) {
+                cx<T>* Eb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(E) + (size_t)(b0 + k) * ws_img);
+                Eb[(size_t)gy * d.Ew + e] = acc[k];
+            }
     }
 }
 
@@ -644,7 +818,8 @@ struct pat_plan_s {
     pat::HostPlan H;
     int max_batch = 1;
     int device = 0;
-    size_t ws_img = 0;                    // bytes per image
+    size_t ws_img = 0;                    // workspace bytes per image (pat_workspace_size / batch)
+    size_t ws_stride = 0;                 // bytes between per-image slices; the batch's sample array follows them
     size_t offR, offE, offV, offG, offU, offP;  // byte offsets inside one image's workspace
     std::vector<void*> allocs;
     size_t table_bytes = 0;
@@ -671,23 +846,25 @@ void layout(pat_plan_s* p)
     p->offV = o; o = align256(o + cs * (size_t)P.L * P.Kp);
     p->offG = o; o = align256(o + cs * (size_t)P.nt * P.Kp);
     p->offU = o; o = align256(o + cs * (size_t)P.lcorr * (P.klow + 1));
-    p->offP = o; o = align256(o + cs * (size_t)P.npts);
-    p->ws_img = o;
+    p->ws_stride = o;
+    // the adjoint's half-ring samples, image-minor: B * npts values after the B slices
+    p->offP = 0;
+    p->ws_img = o + align256(cs * (size_t)P.npts);
 }
 
 int lds_cols(const pat::Params& P)
 {
     size_t cs = (P.dt == PAT_F64) ? 16 : 8;
     int cw = 16;
-    while (cw > 1 && (size_t)cw * P.Ng * cs > 65536) cw >>= 1;
+    while (cw > 1 && ((size_t)cw * P.Ng * cs > 65536 || (size_t)cw * P.Ng > FFT_BLOCK_POINTS)) cw >>= 1;
     return cw;
 }
 
 int lds_dct(const pat::Params& P)
 {
     size_t cs = (P.dt == PAT_F64) ? 16 : 8;
-    int cw = 8;
-    while (cw > 1 && (size_t)cw * 2 * P.M * cs > 65536) cw >>= 1;
+    int cw = 16;
+    while (cw > 1 && ((size_t)cw * P.M * cs > 65536 || (size_t)cw * P.M > FFT_BLOCK_POINTS)) cw >>= 1;
     return cw;
 }
 
@@ -731,12 +908,12 @@ int upload(pat_plan_s* p, Dev<T>& d)
     if ((rc = put(Mk.data(), Mk.size() * sizeof(T), (const void**)&d.Mk))) return rc;
     if ((rc = put(ph.data(), ph.size() * sizeof(T), (const void**)&d.phase))) return rc;
     if ((rc = put(tw.data(), tw.size() * sizeof(T), (const void**)&d.tw))) return rc;
-    if ((rc = put(H.tileStart.data(), H.tileStart.size() * sizeof(int), (const void**)&d.tileStart))) return rc;
-    if ((rc = put(H.runs.data(), H.runs.size() * sizeof(int), (const void**)&d.runs))) return rc;
+    std::vector<T> pos = conv(H.pos);
+    if ((rc = put(pos.data(), pos.size() * sizeof(T), (const void**)&d.pos))) return rc;
     d.n = P.n; d.m = P.m; d.nt = P.nt; d.mf = P.mf; d.logmf = ilog2i(P.mf);
     d.Ng = P.Ng; d.logNg = ilog2i(P.Ng); d.w = P.w; d.hw = P.hw; d.Rw = P.Rw; d.Ew = P.Ew;
     d.M = P.M; d.log2M = ilog2i(P.M); d.L = P.L; d.K = P.K; d.Kp = P.Kp; d.klow = P.klow; d.lcorr = P.lcorr;
-    d.npts = P.npts; d.tileR = P.tileR; d.tileC = P.tileC; d.ntileC = P.ntileC; d.logNmax = ilog2i(P.Nmax);
+    d.npts = P.npts; d.logNmax = ilog2i(P.Nmax);
     d.colsCW = lds_cols(P);
     d.dctCW = lds_dct(P);
     d.beta = (T)P.beta; d.shift = (T)P.shift; d.half = (T)(0.5 * P.Ng / P.Lam); d.lamh = (T)P.h;
@@ -788,7 +965,7 @@ struct StageTimer {
 template <typename T, int WMAX>
 int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g, long gs, char* ws, hipStream_t st)
 {
-    const size_t wi = p->ws_img;
+    const size_t wi = p->ws_stride;
     const size_t cs = sizeof(cx<T>);
     cx<T>* R = reinterpret_cast<cx<T>*>(ws + p->offR);
     cx<T>* E = reinterpret_cast<cx<T>*>(ws + p->offE);
@@ -813,7 +990,7 @@ int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g
     if ((rc = check_launch("ring_fwd"))) return rc;
     {
         StageTimer tm(p, st, 3);
-        dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, cs * 2 * d.M * d.dctCW, st>>>(d, V, G, wi, 0);
+        dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, cs * d.M * d.dctCW, st>>>(d, V, G, wi, 0);
     }
     if ((rc = check_launch("dct_fwd"))) return rc;
     {
@@ -831,14 +1008,14 @@ int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g
 template <typename T, int WMAX>
 int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f, long fs, char* ws, hipStream_t st)
 {
-    const size_t wi = p->ws_img;
+    const size_t wi = p->ws_stride;
     const size_t cs = sizeof(cx<T>);
     cx<T>* R = reinterpret_cast<cx<T>*>(ws + p->offR);
     cx<T>* E = reinterpret_cast<cx<T>*>(ws + p->offE);
     cx<T>* V = reinterpret_cast<cx<T>*>(ws + p->offV);
     cx<T>* G = reinterpret_cast<cx<T>*>(ws + p->offG);
     cx<T>* U = reinterpret_cast<cx<T>*>(ws + p->offU);
-    cx<T>* Pol = reinterpret_cast<cx<T>*>(ws + p->offP);
+    cx<T>* Pol = reinterpret_cast<cx<T>*>(ws + (size_t)B * p->ws_stride);
     const pat::Params& P = p->H.P;
     int rc;
     {
@@ -853,18 +1030,18 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
     if ((rc = check_launch("lowk_adj"))) return rc;
     {
         StageTimer tm(p, st, 8);
-        dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, cs * 2 * d.M * d.dctCW, st>>>(d, G, V, wi, 1);
+        dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, cs * d.M * d.dctCW, st>>>(d, G, V, wi, 1);
     }
     if ((rc = check_launch("dct_adj"))) return rc;
     {
         StageTimer tm(p, st, 9);
-        ring_adj<T, WMAX><<<dim3(d.L, B), NT, cs * P.max_ring, st>>>(d, V, U, Pol, wi);
+        ring_adj<T, WMAX><<<dim3(B, d.L), NT, cs * P.max_ring, st>>>(d, V, U, Pol, B, wi);
     }
     if ((rc = check_launch("ring_adj"))) return rc;
-    size_t sp_lds = sizeof(T) * 2 * d.tileR * d.tileC + sizeof(int) * (3 * NT + 1);
     {
         StageTimer tm(p, st, 10);
-        spread_adj<T, WMAX><<<dim3(P.ntileR * P.ntileC, B), NT, sp_lds, st>>>(d, Pol, E, wi);
+        constexpr int BC = sizeof(T) == 4 ? 16 : 8;
+        spread_tiles<T, WMAX, BC><<<dim3((d.Ew + 15) / 16, (d.Ng + 15) / 16, (B + BC - 1) / BC), NT, 0, st>>>(d, Pol, B, E, wi);
     }
     if ((rc = check_launch("spread_adj"))) return rc;
     {
@@ -882,9 +1059,10 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
 int lds_ok(const pat::Params& P, std::string& err)
 {
     size_t cs = (P.dt == PAT_F64) ? 16 : 8;
-    size_t need = std::max({cs * P.Ng, cs * (size_t)P.max_ring, cs * 2 * (size_t)P.M, cs * 2 * (size_t)P.mf});
-    if (need > 65536) {
-        err = "problem too large for the single-block LDS transforms (64 KiB)";
+    size_t need = std::max({cs * P.Ng, cs * (size_t)P.max_ring, cs * (size_t)P.M, cs * 2 * (size_t)P.mf});
+    int longest = std::max({P.Ng, P.max_ring, P.M, P.mf});
+    if (need > 65536 || longest > FFT_BLOCK_POINTS) {
+        err = "problem too large for the single-block LDS transforms (64 KiB, 4096 points)";
         return PAT_EUNSUPPORTED;
     }
     return PAT_OK;
@@ -896,7 +1074,7 @@ void fill_info(const pat::Params& P, pat_plan_info* info, size_t ws_img, size_t 
     info->n = P.n; info->m = P.m; info->nt = P.nt; info->m_full = P.mf;
     info->grid = P.Ng; info->stencil = P.w; info->rings = P.L; info->dct_half = P.M;
     info->kmax = P.K; info->kpad = P.Kp; info->klow = P.klow; info->lcorr = P.lcorr;
-    info->ring_points = P.npts; info->max_ring = P.max_ring; info->spread_tiles = P.ntileR * P.ntileC;
+    info->ring_points = P.npts; info->max_ring = P.max_ring; info->spread_tiles = ((P.Ew + 15) / 16) * ((P.Ng + 15) / 16);
     info->dlam = P.dlam; info->period = P.period; info->lambda_max = P.Lam;
     info->ws_per_image = ws_img; info->table_bytes = table_bytes;
 }

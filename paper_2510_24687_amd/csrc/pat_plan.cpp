@@ -326,58 +326,22 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
         H.tw[2 * k + 1] = std::sin(a);
     }
 
-    // spread tiling of the extended half grid: every half-ring sample is listed
-    // under each tile its (w+2)-wide footprint touches; consecutive samples of a
-    // ring under one tile form a run.
-    P.tileR = 32;
-    P.tileC = 32;
-    P.ntileR = (P.Ng + P.tileR - 1) / P.tileR;
-    P.ntileC = (P.Ew + P.tileC - 1) / P.tileC;
+    // grid positions (cells) of every half-ring sample, shared by the gather
+    // and its transpose so both select identical taps
+    H.pos.resize(2 * (size_t)P.npts);
     {
-        int ntiles = P.ntileR * P.ntileC;
-        std::vector<std::vector<int>> lists(ntiles);  // packed (l, s) pairs as runs later
-        std::vector<int> touched;
-        const double half = 0.5 * P.Ng / P.Lam;  // grid cells per unit lambda... x = lam*cos*Ng/(2 Lam)
+        const double half = 0.5 * P.Ng / P.Lam;
         for (int l = 0; l < P.L; ++l) {
             int N = H.ringN[l];
             for (int si = 0; si < N / 2; ++si) {
                 int s = si - N / 4;
                 double ph = 2.0 * M_PI * s / N;
-                double x = H.lam[l] * half * std::cos(ph);
-                double y = H.lam[l] * half * std::sin(ph);
-                int gx0 = (int)std::ceil(x - 0.5 * P.w) - 1;
-                int gy0 = (int)std::ceil(y - 0.5 * P.w) - 1;
-                int e0 = std::max(0, gx0 + P.hw), e1 = std::min(P.Ew - 1, gx0 + P.hw + P.w + 1);
-                touched.clear();
-                for (int jy = 0; jy < P.w + 2; ++jy) {
-                    int row = ((gy0 + jy) % P.Ng + P.Ng) % P.Ng;
-                    int tr = row / P.tileR;
-                    for (int tc = e0 / P.tileC; tc <= e1 / P.tileC; ++tc) touched.push_back(tr * P.ntileC + tc);
-                }
-                std::sort(touched.begin(), touched.end());
-                touched.erase(std::unique(touched.begin(), touched.end()), touched.end());
-                for (int t : touched) {
-                    std::vector<int>& L = lists[t];
-                    size_t nr = L.size() / 3;
-                    if (nr && L[3 * (nr - 1)] == l && L[3 * (nr - 1) + 1] + L[3 * (nr - 1) + 2] == si)
-                        L[3 * (nr - 1) + 2] += 1;
-                    else {
-                        L.push_back(l);
-                        L.push_back(si);
-                        L.push_back(1);
-                    }
-                }
+                H.pos[2 * ((size_t)H.ringOff[l] + si)] = H.lam[l] * half * std::cos(ph);
+                H.pos[2 * ((size_t)H.ringOff[l] + si) + 1] = H.lam[l] * half * std::sin(ph);
             }
         }
-        H.tileStart.assign(ntiles + 1, 0);
-        H.runs.clear();
-        for (int t = 0; t < ntiles; ++t) {
-            H.tileStart[t] = (int)(H.runs.size() / 3);
-            H.runs.insert(H.runs.end(), lists[t].begin(), lists[t].end());
-        }
-        H.tileStart[ntiles] = (int)(H.runs.size() / 3);
-        P.nruns = H.tileStart[ntiles];
     }
+    if (H.ringN.back() > 4096) { err = "internal: ring FFT larger than 4096"; return PAT_EUNSUPPORTED; }
     return PAT_OK;
 }
 
