@@ -57,6 +57,84 @@ def stage_bytes(info: dict, B: int, geom: dict) -> dict:
     return {k: v * B for k, v in per.items()}
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ("paper_2510_24687_amd/csrc/pat_kernels.hip", "paper_2510_24687_amd/csrc/pat_plan.cpp"):
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, B: int):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (profiles/traffic_n512.json), scaled by the copy-kernel
+    calibration recorded there; None if the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_n512.json")
+    if not os.path.exists(path):
+        return None
+    z = json.load(open(path))
+    if z.get("source_hash") != kernel_source_hash() or kernel not in z.get("kernels", {}) or z.get("batch") != B:
+        return None
+    k = z["kernels"][kernel]
+    return (k["fetch_kib"] * z["fetch_scale"] + k["write_kib"] * z["write_scale"]) * 1024.0
+
+
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
+    """A plain device-to-device copy of known size, for scaling the counters."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def solver_bench(iters: int = 200, count: int = 64, lam: float = 1e-3, noise: float = 0.05):
+    """Batched, graph-captured NNLS and Chambolle-Pock TV-LS: `count` seeded
+    random-ellipse phantoms with n drawn from {128, 256, 512}, m = 2n detectors
+    on the top 180-degree arc, nt = 2n, data A f + 5% noise; `iters` replays of
+    one captured iteration covering every instance."""
+    import torch
+    from paper_2510_24687_amd import pat, solvers
+    from paper_2510_24687_amd import phantoms as P
+    rng = np.random.default_rng(2024)
+    sizes = rng.choice([128, 256, 512], size=count)
+    groups, truths = [], []
+    for n in (128, 256, 512):
+        seeds = [s for s in range(count) if sizes[s] == n]
+        if not seeds:
+            continue
+        plan = pat.Plan(P.top_arc(int(n), 2 * int(n), 2 * int(n), 180.0), torch.float32, max_batch=len(seeds))
+        f = torch.tensor(P.ellipse_batch(int(n), seeds), dtype=torch.float32, device=plan.device)
+        g = plan.forward(f).double().cpu().numpy()
+        g = np.stack([P.add_noise(gi, noise, 5000 + s) for gi, s in zip(g, seeds)])
+        groups.append((plan, torch.tensor(g, dtype=torch.float32, device=plan.device), None))
+        truths.append(f)
+    out = {"instances": int(count), "sizes": {str(k): int(np.sum(sizes == k)) for k in (128, 256, 512)},
+           "iterations": iters}
+    norms = [solvers.opnorm(p) for p, _, _ in groups]
+    for method in ("nnls", "tv"):
+        sol = solvers.BatchedSolver(groups, method=method, lam=lam, opnorms=norms)
+        sol.capture()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sol.replay(iters)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        errs = []
+        for G, f in zip(sol.groups, truths):
+            d = (G.f - f).double()
+            errs += list((torch.linalg.vector_norm(d.flatten(1), dim=1) /
+                          torch.linalg.vector_norm(f.double().flatten(1), dim=1)).cpu().numpy())
+        out[method] = {"total_ms": ms, "ms_per_iteration": ms / iters,
+                       "mean_rel_l2_error": float(np.mean(errs)),
+                       "graph": "one captured iteration (all instances), replayed"}
+    return out
+
+
 def cpu_baseline(geom: dict, seconds_budget: float = 20.0) -> dict:
     """Time the FP64 oracle on a bounded sample of the workload and extrapolate:
     forward on a few detectors (all times) and adjoint on a few pixels."""
@@ -96,7 +174,17 @@ def main():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--solvers", action="store_true",
+                    help="batched graph-captured NNLS / TV-LS on 64 mixed-size instances instead of the pair benchmark")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (for rocprofv3 counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.solvers:
+        print(json.dumps({"solvers": solver_bench()}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the operators shard by image; "
               "a multi-GPU run is not part of it)", file=sys.stderr)
@@ -176,7 +264,8 @@ def main():
                                "c=R=a=1, batch %d" % (n, geom["m"], geom["nt"], B),
                    "batch": B, "n": n, "m": geom["m"], "nt": geom["nt"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, B),
+                     "alg_bytes_per_launch": bytes_[dom]},
         "stage_ms_per_launch": stage_ms,
         "pair_alg_bytes_per_image": total_alg / B,
         "pair_effective_GBs": total_alg / (step_ms * 1e-3) / 1e9,

@@ -166,6 +166,34 @@ enum {
 int pat_timing_start(pat_plan p);
 int pat_timing_stop(pat_plan p, double* ms, int* launches, int nstages);
 
+/* ---- Fused update steps of the iterative reconstructions (Sec. 4.2) ------
+ * All operate on device arrays of the plan's precision, asynchronously on
+ * `stream`; images are laid out as in pat_forward_batched (contiguous,
+ * stride n*n for images, nt*m for traces).  `support` (may be NULL) is a
+ * B x n x n array multiplied into the result (the projection Pi_Omega0). */
+
+/* r = a x + b y over `count` elements (y may be NULL: r = a x). */
+int pat_axpby(pat_plan p, long count, double a, const void* x, double b, const void* y, void* r, void* stream);
+
+/* Projected gradient step of NNLS (eq:NNLS-projstep, eqn:projectionHalfCircle):
+ * f = support * max(0, f - tau * grad) for B images. */
+int pat_nnls_update(pat_plan p, int B, void* f, const void* grad, double tau, const void* support, void* stream);
+
+/* Chambolle-Pock dual step for the data term 1/2 ||A f - g||^2 (eqn:PDHG-dual):
+ * q = (q + sigma (Afbar - g)) / (1 + sigma), B trace arrays. */
+int pat_cp_dual_data(pat_plan p, int B, void* q, const void* Afbar, const void* g, double sigma, void* stream);
+
+/* Dual step for lam * TV: p = proj_{|p| <= lam}(p + sigma grad_h fbar); p holds
+ * two n x n planes (x- then y-differences) per image; grad_h = forward
+ * differences / h with a zero last difference. */
+int pat_cp_dual_tv(pat_plan p, int B, void* pgrad, const void* fbar, double sigma, double lam, void* stream);
+
+/* Primal step and extrapolation (eqn:PDHG-primal, eqn:PDHG-relaxation in the
+ * usual Chambolle-Pock form): f_new = support * max(0, f - tau (Astar_q - div_h p)),
+ * fbar = f_new + theta (f_new - f), f = f_new. */
+int pat_cp_primal(pat_plan p, int B, void* f, void* fbar, const void* Astar_q, const void* pgrad, double tau,
+                  double theta, const void* support, void* stream);
+
 /* Host-side checks of plan internals (no GPU needed).  Fills out[0..K] with
  * J_k(x) for k = 0..K computed by the plan's Miller recurrence. */
 int pat_debug_bessel(double x, int K, double* out);

@@ -232,6 +232,23 @@ __device__ void lds_fft(cx<T>* buf, int logN, int nb, int stride, const cx<T>* _
     }
 }
 
+// MI355X dispatches consecutive workgroups of a grid round-robin over its 8
+// XCDs, each with its own L2.  Kernels whose neighbouring work items share
+// cache lines (adjacent columns, adjacent rings, neighbouring tiles) renumber
+// their workgroups so that each XCD receives one contiguous range of the
+// logical (x, y) grid: logical = xcd * (count on earlier XCDs) + arrival index.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ void xcd_block(int& bx, int& by)
+{
+    const int nx = gridDim.x, total = gridDim.x * gridDim.y;
+    const int lin = blockIdx.x + nx * blockIdx.y;
+    const int xcd = lin % NUM_XCD, local = lin / NUM_XCD;
+    const int per = total / NUM_XCD, rem = total % NUM_XCD;
+    const int logical = (xcd < rem) ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+    bx = logical % nx;
+    by = logical / nx;
+}
+
 // Plan data as seen by the kernels.
 template <typename T>
 struct Dev {
@@ -329,7 +346,9 @@ __global__ __launch_bounds__(NT) void rows_fwd(Dev<T> d, const T* __restrict__ f
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const int b = blockIdx.y, p1 = 2 * blockIdx.x, p2 = p1 + 1;
+    int bx_, b;
+    xcd_block(bx_, b);
+    const int p1 = 2 * bx_, p2 = p1 + 1;
     const T* fb = f + (size_t)b * fstride;
     cx<T>* Rb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(R) + (size_t)b * ws_img);
     const int Ng = d.Ng, n = d.n;
@@ -359,7 +378,9 @@ __global__ __launch_bounds__(NT) void cols_fwd(Dev<T> d, const cx<T>* R, cx<T>* 
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const int b = blockIdx.y, CW = d.colsCW, x0 = blockIdx.x * CW;
+    int bx_, b;
+    xcd_block(bx_, b);
+    const int CW = d.colsCW, x0 = bx_ * CW;
     const int Ng = d.Ng, n = d.n;
     const cx<T>* Rb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(R) + (size_t)b * ws_img);
     cx<T>* Eb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(E) + (size_t)b * ws_img);
@@ -389,7 +410,8 @@ __global__ __launch_bounds__(NT) void ring_fwd(Dev<T> d, const cx<T>* E, cx<T>* 
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const int b = blockIdx.y, l = blockIdx.x;
+    int l, b;
+    xcd_block(l, b);
     const int N = d.ringN[l], logN = d.ringLog[l], Kl = d.ringK[l];
     const cx<T>* Eb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(E) + (size_t)b * ws_img);
     cx<T>* Vb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(V) + (size_t)b * ws_img);
@@ -437,7 +459,9 @@ __global__ __launch_bounds__(NT) void dct_cols(Dev<T> d, const cx<T>* in, cx<T>*
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const int b = blockIdx.y, CW = d.dctCW, k0 = blockIdx.x * CW;
+    int bx_, b;
+    xcd_block(bx_, b);
+    const int CW = d.dctCW, k0 = bx_ * CW;
     const int M = d.M, logM = d.log2M;
     const cx<T>* ib = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(in) + (size_t)b * ws_img);
     cx<T>* ob = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(out) + (size_t)b * ws_img);
@@ -499,7 +523,9 @@ __global__ __launch_bounds__(NT) void synth_fwd(Dev<T> d, const cx<T>* G, T* g, 
     extern __shared__ unsigned char smem_raw[];
     cx<T>* Z1 = reinterpret_cast<cx<T>*>(smem_raw);
     cx<T>* Z2 = Z1 + d.mf;
-    const int b = blockIdx.y, j1 = 2 * blockIdx.x, j2 = j1 + 1;
+    int bx_, b;
+    xcd_block(bx_, b);
+    const int j1 = 2 * bx_, j2 = j1 + 1;
     const int mf = d.mf;
     const cx<T>* Gb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(G) + (size_t)b * ws_img);
     T* gb = g + (size_t)b * gstride;
@@ -541,7 +567,9 @@ __global__ __launch_bounds__(NT) void synth_adj(Dev<T> d, const T* g, long gstri
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* Z = reinterpret_cast<cx<T>*>(smem_raw);
-    const int b = blockIdx.y, j1 = 2 * blockIdx.x, j2 = j1 + 1;
+    int bx_, b;
+    xcd_block(bx_, b);
+    const int j1 = 2 * bx_, j2 = j1 + 1;
     const int mf = d.mf;
     const bool has2 = j2 < d.nt;
     const T* gb = g + (size_t)b * gstride;
@@ -600,6 +628,7 @@ __global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const c
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    // no XCD renumbering here: contiguous ranges of rings would unbalance the XCDs
     const int b = blockIdx.x, l = blockIdx.y;
     const int N = d.ringN[l], logN = d.ringLog[l], Kl = d.ringK[l];
     const cx<T>* Vb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(V) + (size_t)b * ws_img);
@@ -642,8 +671,10 @@ template <typename T, int W, int BC>
 __global__ __launch_bounds__(NT) void spread_tiles(Dev<T> d, const cx<T>* Pol, int B, cx<T>* E, size_t ws_img)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tx0 = blockIdx.x * 16 + (wave & 1) * 8;   // first column of the wave's tile
-    const int ty0 = blockIdx.y * 16 + (wave >> 1) * 8;  // first row
+    int bxt, byt;
+    xcd_block(bxt, byt);  // gridDim.z (image groups) is handled by blockIdx.z below
+    const int tx0 = bxt * 16 + (wave & 1) * 8;   // first column of the wave's tile
+    const int ty0 = byt * 16 + (wave >> 1) * 8;  // first row
     const int e = tx0 + (lane & 7), gy = ty0 + (lane >> 3);
     const int b0 = blockIdx.z * BC;
     const int nb = min(BC, B - b0);
@@ -749,7 +780,9 @@ __global__ __launch_bounds__(NT) void cols_adj(Dev<T> d, const cx<T>* E, cx<T>* 
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const int b = blockIdx.y, CW = d.colsCW, x0 = blockIdx.x * CW;
+    int bx_, b;
+    xcd_block(bx_, b);
+    const int CW = d.colsCW, x0 = bx_ * CW;
     const int Ng = d.Ng, n = d.n;
     const cx<T>* Eb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(E) + (size_t)b * ws_img);
     cx<T>* Rb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(R) + (size_t)b * ws_img);
@@ -779,7 +812,9 @@ __global__ __launch_bounds__(NT) void rows_adj(Dev<T> d, const cx<T>* R, T* f, l
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    const int b = blockIdx.y, p1 = 2 * blockIdx.x, p2 = p1 + 1;
+    int bx_, b;
+    xcd_block(bx_, b);
+    const int p1 = 2 * bx_, p2 = p1 + 1;
     const int Ng = d.Ng, n = d.n, hN = Ng / 2;
     const cx<T>* Rb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(R) + (size_t)b * ws_img);
     T* fb = f + (size_t)b * fstride;
@@ -1080,6 +1115,19 @@ void fill_info(const pat::Params& P, pat_plan_info* info, size_t ws_img, size_t 
 }
 
 }  // namespace
+
+namespace pat {
+int plan_image_size(pat_plan p, int* n, int* nt, int* m, double* h, int* is_f64)
+{
+    if (!p) return PAT_EINVAL;
+    *n = p->H.P.n;
+    *nt = p->H.P.nt;
+    *m = p->H.P.m;
+    *h = p->H.P.h;
+    *is_f64 = p->H.P.dt == PAT_F64;
+    return PAT_OK;
+}
+}  // namespace pat
 
 extern "C" {
 

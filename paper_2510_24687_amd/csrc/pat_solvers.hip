@@ -1,0 +1,195 @@
+// Fused update kernels of the iterative reconstructions of Sec. 4.2 of
+// Hauptmann, Kunyansky & Poimala (arXiv 2510.24687), run between the
+// library's A / A* launches:
+//   projected-gradient NNLS (eq. eqn:NNLS, eq:NNLS-projstep, eqn:projectionHalfCircle)
+//   Chambolle-Pock / PDHG for TV-regularised least squares (eqs. eqn:PDHG-dual,
+//   eqn:PDHG-primal, eqn:PDHG-relaxation) with K = [A; grad_h], the data term
+//   1/2 ||A f - g||^2_Y, the regulariser lam * sum h^2 |grad_h f| and f >= 0.
+// grad_h uses forward differences divided by h with a zero last difference
+// (Neumann); div_h is minus its adjoint, so <grad_h f, p> = -<f, div_h p>.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "pat_internal.h"
+
+namespace pat {
+int plan_image_size(pat_plan p, int* n, int* nt, int* m, double* h, int* is_f64);
+}
+
+namespace {
+
+constexpr int NT = 256;
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_axpby(long count, T a, const T* x, T b, const T* y, T* r)
+{
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < count; i += (long)gridDim.x * NT)
+        r[i] = a * x[i] + (y ? b * y[i] : T(0));
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_nnls(long count, T* f, const T* grad, T tau, const T* support)
+{
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < count; i += (long)gridDim.x * NT) {
+        T v = f[i] - tau * grad[i];
+        v = v > T(0) ? v : T(0);
+        f[i] = support ? v * support[i] : v;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_dual_data(long count, T* q, const T* Af, const T* g, T sigma)
+{
+    const T inv = T(1) / (T(1) + sigma);
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < count; i += (long)gridDim.x * NT)
+        q[i] = (q[i] + sigma * (Af[i] - g[i])) * inv;
+}
+
+// p = (px, py) stored as two n x n planes per image: p[b][0] = x-differences, p[b][1] = y-differences
+template <typename T>
+__global__ __launch_bounds__(NT) void k_dual_tv(int B, int n, T* p, const T* fbar, T sigma, T lam, T inv_h)
+{
+    const long per = (long)n * n;
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < B * per; i += (long)gridDim.x * NT) {
+        const long b = i / per, k = i - b * per;
+        const int r = (int)(k / n), c = (int)(k - (long)r * n);
+        const T* fb = fbar + b * per;
+        const T gx = c < n - 1 ? (fb[k + 1] - fb[k]) * inv_h : T(0);
+        const T gy = r < n - 1 ? (fb[k + n] - fb[k]) * inv_h : T(0);
+        T* px = p + b * 2 * per;
+        T* py = px + per;
+        T ax = px[k] + sigma * gx, ay = py[k] + sigma * gy;
+        const T mag = sqrt(ax * ax + ay * ay);
+        const T s = mag > lam ? lam / mag : T(1);
+        px[k] = ax * s;
+        py[k] = ay * s;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_primal(int B, int n, T* f, T* fbar, const T* Aq, const T* p, T tau, T theta,
+                                               T inv_h, const T* support)
+{
+    const long per = (long)n * n;
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < B * per; i += (long)gridDim.x * NT) {
+        const long b = i / per, k = i - b * per;
+        const int r = (int)(k / n), c = (int)(k - (long)r * n);
+        const T* px = p + b * 2 * per;
+        const T* py = px + per;
+        // div_h p = (px[c] - px[c-1])/h + (py[r] - py[r-1])/h, with the last difference excluded
+        T dx = (c < n - 1 ? px[k] : T(0)) - (c > 0 ? px[k - 1] : T(0));
+        T dy = (r < n - 1 ? py[k] : T(0)) - (r > 0 ? py[k - n] : T(0));
+        const T div = (dx + dy) * inv_h;
+        const T f_old = f[i];
+        T v = f_old - tau * (Aq[i] - div);
+        v = v > T(0) ? v : T(0);
+        if (support) v *= support[i];
+        f[i] = v;
+        fbar[i] = v + theta * (v - f_old);
+    }
+}
+
+int grid_for(long count)
+{
+    long g = (count + NT - 1) / NT;
+    if (g > 65536) g = 65536;
+    return (int)(g < 1 ? 1 : g);
+}
+
+int launch_status(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        pat::set_error(std::string(what) + ": " + hipGetErrorString(e));
+        return PAT_EHIP;
+    }
+    return PAT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pat_axpby(pat_plan p, long count, double a, const void* x, double b, const void* y, void* r, void* stream)
+{
+    int n, nt, m, f64;
+    double h;
+    if (!p || !x || !r || count < 0) { pat::set_error("pat_axpby: bad arguments"); return PAT_EINVAL; }
+    if (pat::plan_image_size(p, &n, &nt, &m, &h, &f64)) return PAT_EINVAL;
+    if (count == 0) return PAT_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (f64)
+        k_axpby<double><<<grid_for(count), NT, 0, st>>>(count, a, (const double*)x, b, (const double*)y, (double*)r);
+    else
+        k_axpby<float><<<grid_for(count), NT, 0, st>>>(count, (float)a, (const float*)x, (float)b, (const float*)y, (float*)r);
+    return launch_status("pat_axpby");
+}
+
+int pat_nnls_update(pat_plan p, int B, void* f, const void* grad, double tau, const void* support, void* stream)
+{
+    int n, nt, m, f64;
+    double h;
+    if (!p || !f || !grad || B < 1) { pat::set_error("pat_nnls_update: bad arguments"); return PAT_EINVAL; }
+    if (pat::plan_image_size(p, &n, &nt, &m, &h, &f64)) return PAT_EINVAL;
+    const long count = (long)B * n * n;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (f64)
+        k_nnls<double><<<grid_for(count), NT, 0, st>>>(count, (double*)f, (const double*)grad, tau, (const double*)support);
+    else
+        k_nnls<float><<<grid_for(count), NT, 0, st>>>(count, (float*)f, (const float*)grad, (float)tau, (const float*)support);
+    return launch_status("pat_nnls_update");
+}
+
+int pat_cp_dual_data(pat_plan p, int B, void* q, const void* Afbar, const void* g, double sigma, void* stream)
+{
+    int n, nt, m, f64;
+    double h;
+    if (!p || !q || !Afbar || !g || B < 1) { pat::set_error("pat_cp_dual_data: bad arguments"); return PAT_EINVAL; }
+    if (pat::plan_image_size(p, &n, &nt, &m, &h, &f64)) return PAT_EINVAL;
+    const long count = (long)B * nt * m;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (f64)
+        k_dual_data<double><<<grid_for(count), NT, 0, st>>>(count, (double*)q, (const double*)Afbar, (const double*)g, sigma);
+    else
+        k_dual_data<float><<<grid_for(count), NT, 0, st>>>(count, (float*)q, (const float*)Afbar, (const float*)g, (float)sigma);
+    return launch_status("pat_cp_dual_data");
+}
+
+int pat_cp_dual_tv(pat_plan p, int B, void* pgrad, const void* fbar, double sigma, double lam, void* stream)
+{
+    int n, nt, m, f64;
+    double h;
+    if (!p || !pgrad || !fbar || B < 1 || !(lam >= 0)) { pat::set_error("pat_cp_dual_tv: bad arguments"); return PAT_EINVAL; }
+    if (pat::plan_image_size(p, &n, &nt, &m, &h, &f64)) return PAT_EINVAL;
+    const long count = (long)B * n * n;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (f64)
+        k_dual_tv<double><<<grid_for(count), NT, 0, st>>>(B, n, (double*)pgrad, (const double*)fbar, sigma, lam, 1.0 / h);
+    else
+        k_dual_tv<float><<<grid_for(count), NT, 0, st>>>(B, n, (float*)pgrad, (const float*)fbar, (float)sigma, (float)lam,
+                                                          (float)(1.0 / h));
+    return launch_status("pat_cp_dual_tv");
+}
+
+int pat_cp_primal(pat_plan p, int B, void* f, void* fbar, const void* Astar_q, const void* pgrad, double tau,
+                  double theta, const void* support, void* stream)
+{
+    int n, nt, m, f64;
+    double h;
+    if (!p || !f || !fbar || !Astar_q || !pgrad || B < 1) { pat::set_error("pat_cp_primal: bad arguments"); return PAT_EINVAL; }
+    if (pat::plan_image_size(p, &n, &nt, &m, &h, &f64)) return PAT_EINVAL;
+    const long count = (long)B * n * n;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (f64)
+        k_primal<double><<<grid_for(count), NT, 0, st>>>(B, n, (double*)f, (double*)fbar, (const double*)Astar_q,
+                                                          (const double*)pgrad, tau, theta, 1.0 / h, (const double*)support);
+    else
+        k_primal<float><<<grid_for(count), NT, 0, st>>>(B, n, (float*)f, (float*)fbar, (const float*)Astar_q,
+                                                         (const float*)pgrad, (float)tau, (float)theta, (float)(1.0 / h),
+                                                         (const float*)support);
+    return launch_status("pat_cp_primal");
+}
+
+}  // extern "C"
