@@ -135,6 +135,109 @@ def solver_bench(iters: int = 200, count: int = 64, lam: float = 1e-3, noise: fl
     return out
 
 
+def lpd_bench(steps: int = 3000, n_train: int = 10000, n_test: int = 64, batch: int = 8, iters: int = 10,
+              noise: float = 0.02, lam: float = 1e-3, tv_iters: int = 200, lr: float = 1e-3, save: str = ""):
+    """Learned primal-dual vs TV-LS time-to-PSNR: n = 256 images, m = 256
+    detectors on the top 180-degree arc, nt = 512, 2% noise.  Trains the
+    10-iteration LPD (batch 8) on seeded random-ellipse phantoms whose data the
+    GPU forward operator generates, then reconstructs 64 held-out phantoms
+    with the trained network and with 200 graph-captured CP-TV iterations."""
+    import torch
+    from paper_2510_24687_amd import lpd as L
+    from paper_2510_24687_amd import pat, solvers
+    from paper_2510_24687_amd import phantoms as P
+    t_start = time.time()
+
+    def log(what, **kw):
+        d = {"lpd_progress": what, "t_s": round(time.time() - t_start, 1)}
+        d.update(kw)
+        print(json.dumps(d), flush=True)
+
+    geom = P.top_arc(256, 256, 512, 180.0)
+    plan = pat.Plan(geom, torch.float32, max_batch=max(batch, n_test))
+    test = L.make_dataset(plan, range(10 ** 6, 10 ** 6 + n_test), noise, noise_seed=2)
+    train = L.make_dataset(plan, range(n_train), noise, noise_seed=1)
+    torch.cuda.synchronize()
+    log("data", train=n_train, test=n_test)
+    s_A, s_U = L.input_scales(plan, train)
+    net = L.LPD(plan, batch, iters, s_A=s_A, s_U=s_U, seed=0)
+    untrained = L.evaluate(net, test)
+    t0 = time.time()
+    hist = L.train(net, train, steps, lr=lr, log_every=100, log=lambda it, loss: log("train", step=it, loss=loss))
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    params = net.params.cpu().numpy()
+    if save:
+        np.savez(save, params=params, s_A=s_A, s_U=s_U, geometry=json.dumps(geom), steps=steps)
+    del net
+    torch.cuda.empty_cache()
+    inf = L.LPD(plan, batch, iters, params=params, train=False, s_A=s_A, s_U=s_U)
+    inf.capture_forward()
+    nb = n_test // batch
+    for _ in range(2):
+        vals = L.evaluate(inf, test, per_image=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ys = [test["y"][b * batch:(b + 1) * batch] for b in range(nb)]
+    torch.cuda.synchronize()
+    e0.record()
+    for b in range(nb):
+        inf.y.copy_(ys[b])
+        inf.graph_fwd.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    t_lpd = e0.elapsed_time(e1) / 1e3
+    psnr_lpd = float(np.mean(vals))
+    log("lpd_eval", psnr=psnr_lpd, seconds=t_lpd)
+
+    def solve(method, lam_):
+        sol = solvers.BatchedSolver([(plan, test["y"], None)], method=method, lam=lam_, opnorms=[norm])
+        sol.capture()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        sol.replay(tv_iters)
+        b.record()
+        torch.cuda.synchronize()
+        per_it = a.elapsed_time(b) / 1e3 / tv_iters
+        sol.reset()
+        traj = []
+        for _ in range(tv_iters):
+            sol.replay(1)
+            traj.append(float(L.psnr(sol.groups[0].f, test["f"]).mean()))
+        return per_it, traj
+
+    norm = solvers.opnorm(plan)
+    out_tv = {}
+    for lam_ in sorted({lam, 1e-4, 3e-4, 3e-3, 1e-2}):
+        per_it, traj = solve("tv", lam_)
+        final = traj[-1]
+        first = next(i for i, v in enumerate(traj) if v >= final)
+        lpd_time_its = int(t_lpd / per_it)
+        out_tv["%g" % lam_] = {"psnr_200": final, "best_psnr": max(traj), "seconds_per_iteration": per_it,
+                              "time_to_own_200_psnr_s": (first + 1) * per_it,
+                              "psnr_at_lpd_time": traj[min(max(lpd_time_its, 1), tv_iters) - 1]}
+        log("tv", lam=lam_, psnr=final)
+    per_it, traj = solve("nnls", 0.0)
+    tv = out_tv["%g" % lam]
+    res = {
+        "workload": "n=256, m=256 on the top 180-degree arc, nt=512, 2%% noise; %d test phantoms (seeds 1e6..), "
+                    "LPD batch %d, K=%d" % (n_test, batch, iters),
+        "psnr_lpd": psnr_lpd, "psnr_tv200": tv["psnr_200"], "t_lpd_s": t_lpd,
+        "t_tv_s": tv["time_to_own_200_psnr_s"],
+        "pass": bool(psnr_lpd >= tv["psnr_200"] and t_lpd < tv["time_to_own_200_psnr_s"]),
+        "tv": out_tv, "tv_lambda": lam,
+        "nnls": {"psnr_200": traj[-1], "seconds_per_iteration": per_it},
+        "ablation": {"untrained_lpd_psnr": untrained, "trained_lpd_psnr": psnr_lpd,
+                     "backprojection_psnr": L.backprojection_psnr(plan, test, s_U)},
+        "training": {"steps": steps, "batch": batch, "phantoms": n_train, "seconds": train_s,
+                     "steps_per_s": steps / train_s, "images_per_s": steps * batch / train_s,
+                     "operator_evaluations_per_step": 4 * iters, "loss_history": hist[-10:], "lr": lr},
+        "inference_images_per_s": n_test / t_lpd,
+        "scales": {"s_A": s_A, "s_U": s_U},
+    }
+    return res
+
+
 def cpu_baseline(geom: dict, seconds_budget: float = 20.0) -> dict:
     """Time the FP64 oracle on a bounded sample of the workload and extrapolate:
     forward on a few detectors (all times) and adjoint on a few pixels."""
@@ -176,6 +279,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solvers", action="store_true",
                     help="batched graph-captured NNLS / TV-LS on 64 mixed-size instances instead of the pair benchmark")
+    ap.add_argument("--lpd", action="store_true",
+                    help="learned primal-dual training + time-to-PSNR against TV-LS (n=256, 180-degree arc)")
+    ap.add_argument("--lpd-steps", type=int, default=3000)
+    ap.add_argument("--lpd-train", type=int, default=10000)
+    ap.add_argument("--lpd-lr", type=float, default=1e-3)
+    ap.add_argument("--lpd-save", default="", help="write the trained weights (npz) here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for rocprofv3 counter calibration)")
     args = ap.parse_args()
@@ -184,6 +293,10 @@ def main():
         return
     if args.solvers:
         print(json.dumps({"solvers": solver_bench()}), flush=True)
+        return
+    if args.lpd:
+        print(json.dumps({"lpd": lpd_bench(steps=args.lpd_steps, n_train=args.lpd_train, lr=args.lpd_lr,
+                                           save=args.lpd_save)}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the operators shard by image; "

@@ -194,6 +194,84 @@ int pat_cp_dual_tv(pat_plan p, int B, void* pgrad, const void* fbar, double sigm
 int pat_cp_primal(pat_plan p, int B, void* f, void* fbar, const void* Astar_q, const void* pgrad, double tau,
                   double theta, const void* support, void* stream);
 
+/* ---- Learned primal-dual reconstructor (Sec. 4.2.1, eqs. eq:LPD_dual,
+ * eq:LPD_primal, loss eq:emp_loss) -----------------------------------------
+ * The dual and primal networks are stacks of 3x3 convolutions (stride 1,
+ * zero padding 1, cross-correlation) between FP32 tensors of two layouts:
+ *   planar: up to 4 separate B x H x W planes (batch stride H*W), e.g. the
+ *           LPD inputs q, A f, y or f, A* q, and the 1-channel outputs;
+ *   NHWC:   B x H x W x 32 hidden feature maps (channel fastest).
+ * Operands are rounded to bfloat16 (nearest-even) and multiplied on the
+ * matrix cores with FP32 accumulation.  Weights are FP32 masters
+ * w[cout][cin][3][3] packed by pat_conv_pack_weights.  All calls are
+ * asynchronous on `stream`; pointers are device pointers owned by the caller.
+ * Errors: PAT_EINVAL for null or inconsistent arguments, PAT_EUNSUPPORTED for
+ * channel counts other than 1..4 (planar) / 32 (NHWC), PAT_EHIP on a launch
+ * failure. */
+typedef struct {
+    int B, H, W;
+    int cin, cout;        /* planar: 1..4; NHWC: 32                                */
+    int in_planar;        /* input layout                                          */
+    int out_planar;       /* output layout                                         */
+    const void* in[4];    /* planar: in[0..cin-1]; NHWC: in[0]                      */
+    void* out[4];         /* planar: out[c] (NULL = channel not written); NHWC: out[0] */
+    const void* residual[4]; /* planar outputs: added after scaling (NULL = none)   */
+    float scale[4];       /* planar input: plane c is multiplied by scale[c];
+                             planar output: out[c] = residual[c] + scale[c] * (conv + bias) */
+    const void* weight;   /* packed bf16 weights (pat_conv_pack_weights)            */
+    const void* bias;     /* FP32 [cout] or NULL                                    */
+    const void* alpha;    /* FP32 [cout] PReLU slopes or NULL (NHWC outputs only)   */
+    void* pre;            /* NHWC outputs: copy of the pre-activation, or NULL      */
+} pat_conv_desc;
+
+/* Elements (bf16) of a packed weight array for an effective convolution with
+ * cout_e outputs and cin_e inputs of the given layout; -1 if unsupported. */
+long pat_conv_packed_size(int cout_e, int cin_e, int in_planar);
+
+/* Pack w[cout][cin][3][3] (FP32, device) to bf16.  transpose = 0: the
+ * forward convolution.  transpose = 1: the input-gradient convolution
+ * (cin_e = cout, cout_e = cin, kernel flipped), so that the gradient with
+ * respect to the layer input is pat_conv3x3 of the output gradient.
+ * in_planar is the layout of the effective convolution's input. */
+int pat_conv_pack_weights(const void* w, int cout, int cin, int transpose, int in_planar, void* dst, void* stream);
+
+/* out = act(conv3x3(in) + bias) (NHWC out; act = PReLU if alpha, pre gets the
+ * value before it) or out[c] = residual[c] + scale[c] (conv3x3(in) + bias)[c]
+ * (planar out). */
+int pat_conv3x3(const pat_conv_desc* d, void* stream);
+
+/* Floats of FP32 scratch pat_conv3x3_wgrad needs for this layer and chunking. */
+long pat_conv_wgrad_partials(const pat_conv_desc* d, int rows_per_chunk);
+
+/* Weight gradient of the layer d (d->in as in the forward, d->cout outputs):
+ * grad_w[co][ci][ky][kx] (+)= sum_{b,y,x} grad_out[b,y,x,co] * in[b, y+ky-1,
+ * x+kx-1, ci] (scaled planar inputs as in the forward), with operands rounded
+ * to bf16 and the sum taken per chunk of rows_per_chunk image rows on the
+ * matrix cores, then over chunks in FP64 in a fixed order (deterministic).
+ * grad_out has d's output layout; a planar grad_out needs cout == 1.
+ * accumulate = 0 overwrites grad_w, 1 adds to it. */
+int pat_conv3x3_wgrad(const pat_conv_desc* d, const void* grad_out, int rows_per_chunk, void* partials,
+                      void* grad_w, int accumulate, void* stream);
+
+/* PReLU backward over npix NHWC 32-channel pixels: grad_pre = grad_act *
+ * (pre > 0 ? 1 : alpha); grad_bias_alpha[0..31] (+)= sum grad_pre (the bias
+ * gradient of the producing convolution), grad_bias_alpha[32..63] (+)= sum
+ * grad_act * pre * [pre <= 0] (the slope gradient).  partials: 64 * nblocks
+ * floats of scratch. */
+int pat_prelu_backward(long npix, const void* grad_act, const void* pre, const void* alpha, void* grad_pre,
+                       void* partials, int nblocks, void* grad_bias_alpha, int accumulate, void* stream);
+
+/* out[0] (+)= sum of count FP32 values (the bias gradient of a 1-channel
+ * planar layer); partials: nblocks floats of scratch. */
+int pat_plane_sum(long count, const void* g, void* partials, int nblocks, void* out, int accumulate, void* stream);
+
+/* One Adam step (bias-corrected first and second moments) over count FP32
+ * parameters with step size lr_t = lr_min + (lr - lr_min) (1 + cos(pi s)) / 2,
+ * s = min(1, (t-1) / (total_steps-1)), t = *step + 1 read from the device;
+ * *step is then incremented on the device, so a captured step replays as is. */
+int pat_adam(long count, void* param, const void* grad, void* m, void* v, void* step, double lr, double lr_min,
+             int total_steps, double beta1, double beta2, double eps, void* stream);
+
 /* Host-side checks of plan internals (no GPU needed).  Fills out[0..K] with
  * J_k(x) for k = 0..K computed by the plan's Miller recurrence. */
 int pat_debug_bessel(double x, int K, double* out);

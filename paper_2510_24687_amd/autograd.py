@@ -46,7 +46,7 @@ class _Adjoint(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_f):
         out = ctx.plan.forward(grad_f.contiguous())
-        return out.mul_(ctx.plan.adjoint_scale), None
+        return ctx.plan.scale_(out, ctx.plan.adjoint_scale), None
 
 
 def forward(f: torch.Tensor, plan: Plan) -> torch.Tensor:

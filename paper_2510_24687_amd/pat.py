@@ -41,7 +41,17 @@ class PlanInfo(ctypes.Structure):
 EXPORTED = ["pat_plan_create", "pat_plan_query", "pat_plan_destroy", "pat_plan_get_info",
             "pat_workspace_size", "pat_forward", "pat_adjoint", "pat_forward_batched",
             "pat_adjoint_batched", "pat_adjoint_scale", "pat_status_string", "pat_last_error",
-            "pat_debug_bessel"]
+            "pat_debug_bessel", "pat_axpby", "pat_conv_packed_size", "pat_conv_pack_weights", "pat_conv3x3",
+            "pat_conv_wgrad_partials", "pat_conv3x3_wgrad", "pat_prelu_backward", "pat_plane_sum", "pat_adam"]
+
+
+class ConvDesc(ctypes.Structure):
+    """pat_conv_desc: one 3x3 convolution between planar / NHWC FP32 tensors."""
+    _fields_ = [("B", ctypes.c_int), ("H", ctypes.c_int), ("W", ctypes.c_int), ("cin", ctypes.c_int),
+                ("cout", ctypes.c_int), ("in_planar", ctypes.c_int), ("out_planar", ctypes.c_int),
+                ("inp", ctypes.c_void_p * 4), ("out", ctypes.c_void_p * 4), ("residual", ctypes.c_void_p * 4),
+                ("scale", ctypes.c_float * 4), ("weight", ctypes.c_void_p), ("bias", ctypes.c_void_p),
+                ("alpha", ctypes.c_void_p), ("pre", ctypes.c_void_p)]
 
 
 def load():
@@ -69,6 +79,19 @@ def load():
     lib.pat_status_string.restype = ctypes.c_char_p
     lib.pat_last_error.restype = ctypes.c_char_p
     lib.pat_debug_bessel.argtypes = [ctypes.c_double, i, ctypes.POINTER(ctypes.c_double)]
+    D = ctypes.c_double
+    lib.pat_axpby.argtypes = [vp, L, D, vp, D, vp, vp, vp]
+    cd = ctypes.POINTER(ConvDesc)
+    lib.pat_conv_packed_size.argtypes = [i, i, i]
+    lib.pat_conv_packed_size.restype = L
+    lib.pat_conv_pack_weights.argtypes = [vp, i, i, i, i, vp, vp]
+    lib.pat_conv3x3.argtypes = [cd, vp]
+    lib.pat_conv_wgrad_partials.argtypes = [cd, i]
+    lib.pat_conv_wgrad_partials.restype = L
+    lib.pat_conv3x3_wgrad.argtypes = [cd, vp, i, vp, vp, i, vp]
+    lib.pat_prelu_backward.argtypes = [L, vp, vp, vp, vp, vp, i, vp, i, vp]
+    lib.pat_plane_sum.argtypes = [L, vp, vp, i, vp, i, vp]
+    lib.pat_adam.argtypes = [L, vp, vp, vp, vp, vp, D, D, i, D, D, D, vp]
     _lib = lib
     return lib
 
@@ -204,8 +227,14 @@ class Plan:
                    "pat_adjoint_batched")
         return f[0] if single and out is None else f
 
+    def scale_(self, x, a: float):
+        """x *= a in place (library kernel; x contiguous, plan dtype)."""
+        if not x.is_contiguous() or x.dtype != self.dtype:
+            raise TypeError("expected a contiguous tensor of the plan's dtype")
+        _check(self._lib.pat_axpby(self._h, x.numel(), float(a), ctypes.c_void_p(x.data_ptr()), 0.0, None,
+                                   ctypes.c_void_p(x.data_ptr()), self._stream()), "pat_axpby")
+        return x
+
     def transpose(self, g, out=None):
         """Euclidean transpose A^T = A*/s."""
-        f = self.adjoint(g, out=out)
-        f.mul_(1.0 / self.adjoint_scale)
-        return f
+        return self.scale_(self.adjoint(g, out=out), 1.0 / self.adjoint_scale)

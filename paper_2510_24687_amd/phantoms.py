@@ -47,17 +47,14 @@ def sample_blobs(blobs: np.ndarray, n: int, a: float = 1.0) -> np.ndarray:
     return f
 
 
-def ellipse_phantom(n: int, seed: int, count: int = 10, support: float = 0.9,
-                    axes=(0.05, 0.4), a: float = 1.0) -> np.ndarray:
-    """Random-ellipse phantom: per ellipse, semi-axes uniform in ``axes``,
-    rotation uniform in [0, pi), intensity uniform in [0, 1]; the centre is
-    rejection-sampled until |c| + max(semi-axes) <= support.  Ellipses are
-    summed (pixel-centre inclusion) and the result clipped to [0, 1]."""
+def ellipse_params(seed: int, count: int = 10, support: float = 0.9, axes=(0.05, 0.4)) -> np.ndarray:
+    """Random-ellipse parameters, rows (cx, cy, semi-axis 1, semi-axis 2,
+    rotation, intensity): per ellipse, semi-axes uniform in ``axes``, rotation
+    uniform in [0, pi), intensity uniform in [0, 1]; the centre is
+    rejection-sampled until |c| + max(semi-axes) <= support."""
     rng = np.random.default_rng(seed)
-    xs = pixel_centres(n, a)
-    X, Y = np.meshgrid(xs, xs)
-    f = np.zeros((n, n))
-    for _ in range(count):
+    out = np.zeros((count, 6))
+    for e in range(count):
         ax1, ax2 = rng.uniform(*axes), rng.uniform(*axes)
         rot = rng.uniform(0.0, np.pi)
         val = rng.uniform(0.0, 1.0)
@@ -66,11 +63,43 @@ def ellipse_phantom(n: int, seed: int, count: int = 10, support: float = 0.9,
             c = rng.uniform(-lim, lim, size=2)
             if np.hypot(*c) <= lim:
                 break
+        out[e] = (c[0], c[1], ax1, ax2, rot, val)
+    return out
+
+
+def ellipse_phantom(n: int, seed: int, count: int = 10, support: float = 0.9,
+                    axes=(0.05, 0.4), a: float = 1.0) -> np.ndarray:
+    """Random-ellipse phantom from ellipse_params: the ellipses are summed
+    (pixel-centre inclusion) and the result clipped to [0, 1]."""
+    xs = pixel_centres(n, a)
+    X, Y = np.meshgrid(xs, xs)
+    f = np.zeros((n, n))
+    for cx, cy, ax1, ax2, rot, val in ellipse_params(seed, count, support, axes):
         cr, sr = np.cos(rot), np.sin(rot)
-        u = (X - c[0]) * cr + (Y - c[1]) * sr
-        v = -(X - c[0]) * sr + (Y - c[1]) * cr
+        u = (X - cx) * cr + (Y - cy) * sr
+        v = -(X - cx) * sr + (Y - cy) * cr
         f += val * ((u / ax1) ** 2 + (v / ax2) ** 2 <= 1.0)
     return np.clip(f, 0.0, 1.0)
+
+
+def ellipse_images(params: np.ndarray, n: int, a: float = 1.0, device="cuda"):
+    """The same rasterisation as ellipse_phantom for a stack of parameter sets
+    (N, count, 6), done with torch on ``device`` in float64 and returned as
+    float32 (N, n, n).  Used to generate large training sets in device memory;
+    pixels on an ellipse boundary may differ from the numpy version by the
+    last-bit differences of the two sine/cosine implementations."""
+    import torch
+    xs = torch.tensor(pixel_centres(n, a), dtype=torch.float64, device=device)
+    Y, X = torch.meshgrid(xs, xs, indexing="ij")
+    prm = torch.tensor(np.asarray(params, dtype=np.float64), device=device)
+    f = torch.zeros((prm.shape[0], n, n), dtype=torch.float64, device=device)
+    for e in range(prm.shape[1]):
+        cx, cy, ax1, ax2, rot, val = [prm[:, e, i].view(-1, 1, 1) for i in range(6)]
+        cr, sr = torch.cos(rot), torch.sin(rot)
+        u = (X - cx) * cr + (Y - cy) * sr
+        v = -(X - cx) * sr + (Y - cy) * cr
+        f += val * (((u / ax1) ** 2 + (v / ax2) ** 2) <= 1.0)
+    return torch.clamp(f, 0.0, 1.0).to(torch.float32)
 
 
 def ellipse_batch(n: int, seeds, **kw) -> np.ndarray:

@@ -1,0 +1,340 @@
+"""Learned primal-dual kernels on the GPU against the CPU oracle (oracle/lpd.py):
+BF16-MFMA convolutions (forward, input gradient, weight gradient), PReLU
+backward, bias sums, Adam, the whole unrolled network's loss gradient, graph
+replay, and what training gains over the untrained network."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from oracle import lpd as OL  # noqa: E402
+from paper_2510_24687_amd import lpd as L  # noqa: E402
+from paper_2510_24687_amd import pat  # noqa: E402
+from paper_2510_24687_amd import phantoms as P  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+# FP32 accumulation of <= 288 bf16 x bf16 products (exact in FP32) against an
+# FP64 sum of the same products: |error| <~ 288 * 2^-24 * sum |terms|.
+TOL_CONV = 2e-5
+
+
+def rel(a, b):
+    a, b = np.ravel(np.asarray(a, dtype=np.float64)), np.ravel(np.asarray(b, dtype=np.float64))
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def st():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def cuda32(x):
+    return torch.tensor(np.asarray(x, dtype=np.float32), device="cuda")
+
+
+def planes_to_nchw(planes):
+    return np.stack([p for p in planes], axis=1)
+
+
+def nhwc_to_nchw(x):
+    return np.transpose(x, (0, 3, 1, 2))
+
+
+def pack(lib, w, cout, cin, transpose, in_planar):
+    coe, cie = (cin, cout) if transpose else (cout, cin)
+    n = lib.pat_conv_packed_size(coe, cie, int(in_planar))
+    dst = torch.empty(n, dtype=torch.int16, device="cuda")
+    pat._check(lib.pat_conv_pack_weights(w.data_ptr(), cout, cin, transpose, int(in_planar), dst.data_ptr(), st()),
+               "pack")
+    return dst
+
+
+def f32(x):
+    """values representable in FP32 (inputs of both sides)"""
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 19, 300), (1, 7, 33)])
+def test_conv_forward_variants_vs_oracle(B, H, W):
+    lib = pat.load()
+    rng = np.random.default_rng(B * 100 + W)
+    # planar 3 -> NHWC 32 with input scales, bias, PReLU and pre-activation copy
+    x = f32(rng.standard_normal((B, 3, H, W)))
+    w1 = f32(0.3 * rng.standard_normal((32, 3, 3, 3)))
+    b1 = f32(0.1 * rng.standard_normal(32))
+    a1 = f32(0.2 + 0.1 * rng.random(32))
+    scales = [1.0, 0.5, 2.0]
+    xs = [cuda32(x[:, c]) for c in range(3)]  # kept alive: descriptors hold raw pointers
+    w1g, b1g, a1g = cuda32(w1), cuda32(b1), cuda32(a1)
+    out = torch.zeros((B, H, W, 32), device="cuda")
+    pre = torch.zeros((B, H, W, 32), device="cuda")
+    wf = pack(lib, w1g, 32, 3, 0, True)
+    d = L._desc(B, H, W, 3, 32, True, False, xs, [out], wf, b1g, a1g, pre, scale=scales)
+    pat._check(lib.pat_conv3x3(ctypes.byref(d), st()), "conv")
+    xsc = x * np.array(scales).reshape(1, 3, 1, 1)
+    ref_pre = OL.conv3x3(torch.tensor(xsc), torch.tensor(w1), torch.tensor(b1)).numpy()
+    ref = OL.prelu(torch.tensor(ref_pre), torch.tensor(a1)).numpy()
+    assert rel(nhwc_to_nchw(pre.cpu().numpy()), ref_pre) < TOL_CONV
+    assert rel(nhwc_to_nchw(out.cpu().numpy()), ref) < TOL_CONV
+    # NHWC 32 -> NHWC 32, no bias, no activation
+    h = f32(rng.standard_normal((B, H, W, 32)))
+    w2 = f32(0.1 * rng.standard_normal((32, 32, 3, 3)))
+    out2 = torch.zeros((B, H, W, 32), device="cuda")
+    w2g = cuda32(w2)
+    hg = cuda32(h)
+    d = L._desc(B, H, W, 32, 32, False, False, [hg], [out2], pack(lib, w2g, 32, 32, 0, False))
+    pat._check(lib.pat_conv3x3(ctypes.byref(d), st()), "conv")
+    ref2 = OL.conv3x3(torch.tensor(nhwc_to_nchw(h)), torch.tensor(w2)).numpy()
+    assert rel(nhwc_to_nchw(out2.cpu().numpy()), ref2) < TOL_CONV
+    # NHWC 32 -> planar 1 with bias and residual
+    w3 = f32(0.1 * rng.standard_normal((1, 32, 3, 3)))
+    b3 = f32([0.37])
+    res = f32(rng.standard_normal((B, H, W)))
+    out3 = torch.zeros((B, H, W), device="cuda")
+    w3g, b3g, resg = cuda32(w3), cuda32(b3), cuda32(res)
+    d = L._desc(B, H, W, 32, 1, False, True, [hg], [out3], pack(lib, w3g, 1, 32, 0, False), b3g, residual=[resg])
+    pat._check(lib.pat_conv3x3(ctypes.byref(d), st()), "conv")
+    ref3 = res + OL.conv3x3(torch.tensor(nhwc_to_nchw(h)), torch.tensor(w3), torch.tensor(b3)).numpy()[:, 0]
+    assert rel(out3.cpu().numpy(), ref3) < TOL_CONV
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 19, 300)])
+def test_input_gradient_convolutions_vs_oracle(B, H, W):
+    """pat_conv3x3 with transposed packing = conv_transpose2d of the oracle."""
+    lib = pat.load()
+    rng = np.random.default_rng(7)
+    # layer 3 type: planar 1 -> NHWC 32 (gradient of a 32 -> 1 layer)
+    w3 = f32(0.2 * rng.standard_normal((1, 32, 3, 3)))
+    gy = f32(rng.standard_normal((B, H, W)))
+    gx = torch.zeros((B, H, W, 32), device="cuda")
+    gyg, w3g = cuda32(gy), cuda32(w3)
+    d = L._desc(B, H, W, 1, 32, True, False, [gyg], [gx], pack(lib, w3g, 1, 32, 1, True))
+    pat._check(lib.pat_conv3x3(ctypes.byref(d), st()), "conv")
+    ref = torch.nn.functional.conv_transpose2d(OL.bf16(torch.tensor(gy[:, None])), OL.bf16(torch.tensor(w3)),
+                                               padding=1).numpy()
+    assert rel(nhwc_to_nchw(gx.cpu().numpy()), ref) < TOL_CONV
+    # layer 2 type: NHWC -> NHWC
+    w2 = f32(0.1 * rng.standard_normal((32, 32, 3, 3)))
+    g2 = f32(rng.standard_normal((B, H, W, 32)))
+    gx2 = torch.zeros((B, H, W, 32), device="cuda")
+    g2g, w2g = cuda32(g2), cuda32(w2)
+    d = L._desc(B, H, W, 32, 32, False, False, [g2g], [gx2], pack(lib, w2g, 32, 32, 1, False))
+    pat._check(lib.pat_conv3x3(ctypes.byref(d), st()), "conv")
+    ref = torch.nn.functional.conv_transpose2d(OL.bf16(torch.tensor(nhwc_to_nchw(g2))), OL.bf16(torch.tensor(w2)),
+                                               padding=1).numpy()
+    assert rel(nhwc_to_nchw(gx2.cpu().numpy()), ref) < TOL_CONV
+    # layer 1 type: NHWC -> planar 3 with output scales, residual on plane 0, plane 2 skipped
+    w1 = f32(0.3 * rng.standard_normal((32, 3, 3, 3)))
+    res = f32(rng.standard_normal((B, H, W)))
+    o0 = torch.zeros((B, H, W), device="cuda")
+    o1 = torch.zeros((B, H, W), device="cuda")
+    w1g, resg = cuda32(w1), cuda32(res)
+    d = L._desc(B, H, W, 32, 3, False, True, [g2g], [o0, o1, None], pack(lib, w1g, 32, 3, 1, False),
+                residual=[resg, None, None], scale=[1.0, 0.5, 2.0])
+    pat._check(lib.pat_conv3x3(ctypes.byref(d), st()), "conv")
+    ref = torch.nn.functional.conv_transpose2d(OL.bf16(torch.tensor(nhwc_to_nchw(g2))), OL.bf16(torch.tensor(w1)),
+                                               padding=1).numpy()
+    assert rel(o0.cpu().numpy(), res + ref[:, 0]) < TOL_CONV
+    assert rel(o1.cpu().numpy(), 0.5 * ref[:, 1]) < TOL_CONV
+
+
+def test_weight_gradients_vs_oracle():
+    lib = pat.load()
+    rng = np.random.default_rng(11)
+    B, H, W, rows = 2, 19, 300, 5      # ragged chunks of rows and a ragged row tail
+    part = torch.zeros(4 << 20, device="cuda")
+    # planar 3 (scaled) -> 32
+    x = f32(rng.standard_normal((B, 3, H, W)))
+    g = f32(rng.standard_normal((B, H, W, 32)))
+    gw = torch.zeros(32 * 3 * 9, device="cuda")
+    scales = [1.0, 0.5, 2.0]
+    xg = [cuda32(x[:, c]) for c in range(3)]
+    gg = cuda32(g)
+    d = L._desc(B, H, W, 3, 32, True, False, xg, [], None, scale=scales)
+    d.weight = 1  # not read by the weight gradient; must be non-null for validation
+    assert lib.pat_conv_wgrad_partials(ctypes.byref(d), rows) <= part.numel()
+    pat._check(lib.pat_conv3x3_wgrad(ctypes.byref(d), gg.data_ptr(), rows, part.data_ptr(), gw.data_ptr(), 0,
+                                     st()), "wgrad")
+    xsc = x * np.array(scales).reshape(1, 3, 1, 1)
+    ref = torch.nn.grad.conv2d_weight(OL.bf16(torch.tensor(xsc)), (32, 3, 3, 3), OL.bf16(torch.tensor(nhwc_to_nchw(g))),
+                                      padding=1).numpy()
+    assert rel(gw.cpu().numpy(), ref) < TOL_CONV
+    # accumulate: a second call adds
+    pat._check(lib.pat_conv3x3_wgrad(ctypes.byref(d), gg.data_ptr(), rows, part.data_ptr(), gw.data_ptr(), 1,
+                                     st()), "wgrad")
+    assert rel(gw.cpu().numpy(), 2 * ref) < TOL_CONV
+    # NHWC 32 -> 32
+    h = f32(rng.standard_normal((B, H, W, 32)))
+    gw2 = torch.zeros(32 * 32 * 9, device="cuda")
+    hg = cuda32(h)
+    d = L._desc(B, H, W, 32, 32, False, False, [hg], [], None)
+    d.weight = 1
+    pat._check(lib.pat_conv3x3_wgrad(ctypes.byref(d), gg.data_ptr(), rows, part.data_ptr(), gw2.data_ptr(), 0,
+                                     st()), "wgrad")
+    ref2 = torch.nn.grad.conv2d_weight(OL.bf16(torch.tensor(nhwc_to_nchw(h))), (32, 32, 3, 3),
+                                       OL.bf16(torch.tensor(nhwc_to_nchw(g))), padding=1).numpy()
+    assert rel(gw2.cpu().numpy(), ref2) < TOL_CONV
+    # NHWC 32 -> planar 1
+    g1 = f32(rng.standard_normal((B, H, W)))
+    gw3 = torch.zeros(32 * 9, device="cuda")
+    g1g = cuda32(g1)
+    d = L._desc(B, H, W, 32, 1, False, True, [hg], [], None)
+    d.weight = 1
+    pat._check(lib.pat_conv3x3_wgrad(ctypes.byref(d), g1g.data_ptr(), rows, part.data_ptr(), gw3.data_ptr(), 0,
+                                     st()), "wgrad")
+    ref3 = torch.nn.grad.conv2d_weight(OL.bf16(torch.tensor(nhwc_to_nchw(h))), (1, 32, 3, 3),
+                                       OL.bf16(torch.tensor(g1[:, None])), padding=1).numpy()
+    assert rel(gw3.cpu().numpy(), ref3) < TOL_CONV
+
+
+def test_prelu_backward_and_bias_sums():
+    lib = pat.load()
+    rng = np.random.default_rng(3)
+    npix = 3 * 17 * 29
+    ga = f32(rng.standard_normal((npix, 32)))
+    x = f32(rng.standard_normal((npix, 32)))
+    al = f32(0.1 + 0.3 * rng.random(32))
+    gx = torch.zeros((npix, 32), device="cuda")
+    part = torch.zeros(64 * 37, device="cuda")
+    gba = torch.zeros(64, device="cuda")
+    gag, xg, alg = cuda32(ga), cuda32(x), cuda32(al)  # kept alive while the kernel may run
+    pat._check(lib.pat_prelu_backward(npix, gag.data_ptr(), xg.data_ptr(), alg.data_ptr(),
+                                      gx.data_ptr(), part.data_ptr(), 37, gba.data_ptr(), 0, st()), "prelu")
+    want = np.where(x > 0, ga, al * ga)
+    assert np.array_equal(gx.cpu().numpy(), want.astype(np.float32))
+    assert rel(gba[:32].cpu().numpy(), want.sum(0)) < 1e-5
+    assert rel(gba[32:].cpu().numpy(), np.where(x > 0, 0.0, ga * x).sum(0)) < 1e-5
+    s = torch.zeros(1, device="cuda")
+    v = f32(rng.standard_normal(12345))
+    vg = cuda32(v)
+    pat._check(lib.pat_plane_sum(v.size, vg.data_ptr(), part.data_ptr(), 37, s.data_ptr(), 0, st()), "sum")
+    pat._check(lib.pat_plane_sum(v.size, vg.data_ptr(), part.data_ptr(), 37, s.data_ptr(), 1, st()), "sum")
+    assert abs(float(s) - 2 * v.sum()) < 1e-4 * np.abs(v).sum()
+
+
+def test_adam_matches_reference():
+    lib = pat.load()
+    rng = np.random.default_rng(4)
+    n = 5000
+    p = f32(rng.standard_normal(n))
+    pg, mg, vg = cuda32(p), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    m, v, q = np.zeros(n), np.zeros(n), p.copy()
+    for t in range(1, 6):
+        g = f32(rng.standard_normal(n))
+        gg = cuda32(g)
+        pat._check(lib.pat_adam(n, pg.data_ptr(), gg.data_ptr(), mg.data_ptr(), vg.data_ptr(), step.data_ptr(),
+                                1e-2, 1e-4, 8, 0.9, 0.999, 1e-8, st()), "adam")
+        q, m, v = OL.adam_reference(q, g, m, v, t, 1e-2, 1e-4, 8)
+    assert int(step) == 5
+    assert np.max(np.abs(pg.cpu().numpy() - q)) < 1e-6
+
+
+def _tiny_setup(K=3):
+    geom = P.top_arc(16, 16, 32, 180.0)
+    plan = pat.Plan(geom, torch.float32, max_batch=2)
+    f_true = P.ellipse_batch(16, [21, 22])
+    y = np.stack([P.add_noise(O.forward(geom, fi), 0.02, 30 + i) for i, fi in enumerate(f_true)])
+    params = L.init_params(9)
+    # a larger last layer so that every layer carries a visible gradient
+    Pd = L.unpack(params)
+    Pd["dual.w3"][...] *= 10
+    Pd["primal.w3"][...] *= 10
+    params = np.concatenate([Pd[k].ravel() for k, _ in L.param_layout()]).astype(np.float32)
+    return geom, plan, f32(f_true), f32(y), params, K
+
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_lpd_loss_gradient_vs_oracle(K):
+    """Loss, f_K and every parameter gradient of K unrolled iterations at
+    n = 16 (m = 16 on a 180-degree arc, nt = 32, batch 2) against the oracle
+    network run on the oracle's A / A* with the same bf16 rounding.
+
+    Tolerances.  Both sides round the convolution operands to bf16 from FP32
+    values, but those FP32 values differ by the operators' FP32 error (~1e-6
+    relative here) and by FP32 accumulation, so a small fraction of the
+    roundings land on the other side of a rounding midpoint, each moving one
+    operand by up to 2^-8 relative.  With one iteration that fraction is
+    ~1e-4 and the results agree to ~2e-5; every further iteration feeds the
+    flipped values forward through a network of gain > 1, so at K = 3 the
+    agreement is bounded by the size of the bf16 effect itself, which the
+    test measures as the distance to the unrounded FP64 network and requires
+    the GPU to be several times closer to the rounded oracle than that."""
+    geom, plan, f_true, y, params, _ = _tiny_setup()
+    s_A, s_U = 0.9, 1.7
+    net = L.LPD(plan, 2, iters=K, params=params, s_A=s_A, s_U=s_U)
+    yg, fg = cuda32(y), cuda32(f_true)
+    net.set_batch(yg, fg)
+    net.forward_pass()
+    net.backward_pass()
+    torch.cuda.synchronize()
+    Pd = {k: v.astype(np.float64) for k, v in L.unpack(params).items()}
+    loss_o, fK_o, g_o = OL.loss_and_grads(geom, Pd, y, f_true, K, s_A, s_U, rounding=True)
+    loss_x, fK_x, g_x = OL.loss_and_grads(geom, Pd, y, f_true, K, s_A, s_U, rounding=False)
+    grads = L.unpack(net.grads.cpu().numpy())
+    fK = net.f[K].cpu().numpy()
+    e_f, e_fx = rel(fK, fK_o), rel(fK_x, fK_o)
+    e_g = {k: rel(grads[k], g_o[k]) for k in g_o}
+    e_gx = {k: rel(g_x[k], g_o[k]) for k in g_o}
+    print("K=%d f_K: gpu %.2e, bf16 effect %.2e" % (K, e_f, e_fx))
+    for k in g_o:
+        print("  %-10s gpu %.2e  bf16 effect %.2e" % (k, e_g[k], e_gx[k]))
+    if K == 1:
+        assert e_f < 1e-4
+        assert abs(net.loss() - loss_o) < 1e-4 * loss_o
+        for k in g_o:
+            assert e_g[k] < 1e-4, k
+    else:
+        assert e_f < 0.25 * e_fx
+        assert abs(net.loss() - loss_o) < 1e-2 * loss_o
+        for k in g_o:
+            assert e_g[k] < 0.5 * e_gx[k] or e_g[k] < 2e-3, k
+
+
+def test_lpd_graph_replay_equals_eager_training():
+    geom, plan, f_true, y, params, K = _tiny_setup(K=2)
+    a = L.LPD(plan, 2, iters=K, params=params)
+    b = L.LPD(plan, 2, iters=K, params=params)
+    for net in (a, b):
+        net.opt.update(lr=1e-3, total=10)
+        net.set_batch(cuda32(y), cuda32(f_true))
+    for _ in range(3):
+        a.train_step()
+    b.capture_train()
+    for _ in range(3):
+        b.graph_train.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(a.params, b.params)
+    assert int(b.step_count) == 3
+
+
+def test_training_gains_over_untrained_network():
+    """800 steps on 256 phantoms (n = 32, 180-degree arc) raise the held-out
+    PSNR well above the untrained network and above the method without the
+    learned part: the same number (K = 5) of projected-gradient (NNLS)
+    iterations with the same operators."""
+    from paper_2510_24687_amd import solvers as S
+    geom = P.top_arc(32, 32, 64, 180.0)
+    plan = pat.Plan(geom, torch.float32, max_batch=16)
+    ds = L.make_dataset(plan, range(256), noise=0.02, noise_seed=5)
+    test = L.make_dataset(plan, range(10 ** 6, 10 ** 6 + 16), noise=0.02, noise_seed=6)
+    s_A, s_U = L.input_scales(plan, ds)
+    K = 5
+    net = L.LPD(plan, 8, iters=K, s_A=s_A, s_U=s_U, seed=1)
+    base = L.evaluate(net, test)
+    log = L.train(net, ds, steps=800, lr=3e-3)
+    after = L.evaluate(net, test)
+    sol = S.BatchedSolver([(plan, test["y"], None)], method="nnls")
+    for _ in range(K):
+        sol.step()
+    nnls = float(L.psnr(sol.groups[0].f, test["f"]).mean())
+    bp = L.backprojection_psnr(plan, test, s_U)
+    print("untrained %.2f dB, trained %.2f dB, NNLS(%d) %.2f dB, back-projection %.2f dB, loss %s"
+          % (base, after, K, nnls, bp, log[-3:]))
+    assert after > base + 8.0
+    assert after > nnls + 3.0
+    assert after > bp
