@@ -65,7 +65,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, B: int):
+SHAPE_KEYS = ["tune_fft_radix_log2", "tune_cols_per_block", "tune_dct_cols_per_block", "tune_ring_images",
+              "tune_spread_images"]
+
+
+def measured_traffic(kernel: str, B: int, shapes: dict = None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary (profiles/traffic_n512.json), scaled by the copy-kernel
     calibration recorded there; None if the kernels changed since."""
@@ -74,6 +78,8 @@ def measured_traffic(kernel: str, B: int):
         return None
     z = json.load(open(path))
     if z.get("source_hash") != kernel_source_hash() or kernel not in z.get("kernels", {}) or z.get("batch") != B:
+        return None
+    if shapes is not None and z.get("launch_shapes") not in (None, shapes):
         return None
     k = z["kernels"][kernel]
     return (k["fetch_kib"] * z["fetch_scale"] + k["write_kib"] * z["write_scale"]) * 1024.0
@@ -285,6 +291,8 @@ def main():
     ap.add_argument("--lpd-train", type=int, default=10000)
     ap.add_argument("--lpd-lr", type=float, default=1e-3)
     ap.add_argument("--lpd-save", default="", help="write the trained weights (npz) here")
+    ap.add_argument("--tuning-cache", default="",
+                    help="autotuner cache file (default: a fresh temporary file, i.e. tune at start-up)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for rocprofv3 counter calibration)")
     args = ap.parse_args()
@@ -309,8 +317,15 @@ def main():
 
     n, B = args.n, args.batch
     geom = P.full_circle(n, 2 * n, 2 * n, T=2.0)
-    plan = pat.Plan(geom, torch.float32, max_batch=B)
+    # launch shapes from the library's autotuner (a fresh cache: measured at plan creation)
+    cache = args.tuning_cache
+    if not cache:
+        import tempfile
+        fd, cache = tempfile.mkstemp(prefix="pat_tune_", suffix=".txt")
+        os.close(fd)
+    plan = pat.Plan(geom, torch.float32, max_batch=B, tuning_cache=cache)
     info = plan.info
+    shapes = {k: info[k] for k in SHAPE_KEYS}
     dev = plan.device
     f_np = P.ellipse_batch(n, range(B))
     y_np = np.stack([P.randn((geom["nt"], geom["m"]), 100 + b) for b in range(B)])
@@ -377,8 +392,9 @@ def main():
                                "c=R=a=1, batch %d" % (n, geom["m"], geom["nt"], B),
                    "batch": B, "n": n, "m": geom["m"], "nt": geom["nt"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, B),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, B, shapes),
                      "alg_bytes_per_launch": bytes_[dom]},
+        "launch_shapes": dict(shapes, tuned=info["tuned"]),
         "stage_ms_per_launch": stage_ms,
         "pair_alg_bytes_per_image": total_alg / B,
         "pair_effective_GBs": total_alg / (step_ms * 1e-3) / 1e9,

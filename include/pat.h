@@ -108,14 +108,30 @@ typedef struct {
     double lambda_max;  /* Lambda = pi/h                                         */
     size_t ws_per_image;/* workspace bytes per image                             */
     size_t table_bytes; /* device bytes held by the plan                         */
+    /* launch shapes in use (defaults from the LDS limits, or the autotuner's)   */
+    int tune_fft_radix_log2;      /* largest FFT pass radix 2^x (3 or 4)            */
+    int tune_cols_per_block;      /* spectrum columns per column-FFT block          */
+    int tune_dct_cols_per_block;  /* harmonics per cosine-transform block           */
+    int tune_ring_images;         /* images per ring-gather block                   */
+    int tune_spread_images;       /* images per spread group                        */
+    int tuned;                    /* 0 defaults, 1 measured at creation, 2 cached   */
+    double tuned_ms;              /* forward + adjoint ms at max_batch when tuned   */
 } pat_plan_info;
 
 /* Create a plan: validates the geometry, computes its tables on the host in
  * FP64 (Bessel functions by Miller's backward recurrence, gridding kernel and
- * its transform, low-frequency quadrature, spread tiling) and uploads them.
- * max_batch bounds the batch of later calls (>= 1).  tuning_cache_path may be
- * NULL; otherwise launch-shape choices are read from / appended to that file.
- * Synchronises the current device once.  Returns PAT_OK and *out, or an error
+ * its transform, low-frequency quadrature, sample positions) and uploads them.
+ * max_batch bounds the batch of later calls (>= 1).
+ * tuning_cache_path: NULL or "" keeps the default launch shapes.  Otherwise
+ * the plan looks up its key (device architecture, dtype, geometry, max_batch)
+ * in that text file (one line per entry, "key | choices"; the last matching
+ * line wins); if absent it times the candidate launch shapes (FFT pass radix,
+ * columns per transform block, images per ring-gather block and per spread
+ * group) one choice at a time with forward + adjoint at max_batch, keeps the
+ * fastest, and appends a line.  A missing or unreadable file is treated as
+ * empty; a line that fails validation is ignored.  The search allocates and
+ * frees a temporary workspace.
+ * Synchronises the current device.  Returns PAT_OK and *out, or an error
  * (then *out is NULL). */
 int pat_plan_create(pat_plan* out, const pat_geometry* g, pat_dtype dt, int max_batch,
                     const char* tuning_cache_path);
@@ -142,6 +158,25 @@ int pat_forward_batched(pat_plan p, int B, const void* f, long f_stride, void* g
                         void* ws, void* stream);
 int pat_adjoint_batched(pat_plan p, int B, const void* g, long g_stride, void* f, long f_stride,
                         void* ws, void* stream);
+
+/* ---- Groups of plans (batching of uneven image sizes) --------------------
+ * A group runs the forward (or adjoint) chains of up to 6 plans of the same
+ * precision together: each stage is ONE kernel launch whose blocks cover
+ * every plan's grid (13 launches per A + A* pair for the whole group instead
+ * of 13 per plan), with results identical to per-plan calls.  The group
+ * keeps pointers to the plans (they must outlive it; each plan at most once)
+ * and uses their launch shapes, except that the spread takes its widest image
+ * group.  Per plan i: batch[i] images (1..max_batch),
+ * contiguous inputs / outputs (image stride n*n, trace stride nt*m), and its
+ * own workspace ws[i] of pat_workspace_size(plan_i, batch[i]) bytes.
+ * Asynchronous on `stream`; capturable in a HIP graph. */
+typedef struct pat_group_s* pat_group;
+int pat_group_create(pat_group* out, int count, const pat_plan* plans);
+int pat_group_destroy(pat_group g);
+int pat_group_forward(pat_group g, const int* batch, const void* const* f, void* const* gout, void* const* ws,
+                      void* stream);
+int pat_group_adjoint(pat_group g, const int* batch, const void* const* gin, void* const* f, void* const* ws,
+                      void* stream);
 
 /* s such that A* = s A^T: s = (T/nt) (R*arc/m) / h^2, the rectangle-rule
  * weights of the inner products eqn:innerProducts. */
@@ -268,9 +303,20 @@ int pat_plane_sum(long count, const void* g, void* partials, int nblocks, void* 
 /* One Adam step (bias-corrected first and second moments) over count FP32
  * parameters with step size lr_t = lr_min + (lr - lr_min) (1 + cos(pi s)) / 2,
  * s = min(1, (t-1) / (total_steps-1)), t = *step + 1 read from the device;
- * *step is then incremented on the device, so a captured step replays as is. */
+ * *step is then incremented on the device, so a captured step replays as is.
+ * clip > 0 first scales the gradient by min(1, clip / ||grad||_2) (global
+ * norm, computed on the device into `scratch`, >= 65 doubles); clip = 0
+ * disables it (scratch may be NULL). */
 int pat_adam(long count, void* param, const void* grad, void* m, void* v, void* step, double lr, double lr_min,
-             int total_steps, double beta1, double beta2, double eps, void* stream);
+             int total_steps, double beta1, double beta2, double eps, double clip, void* scratch, void* stream);
+
+/* ||A|| (operator norm from the X to the Y inner products of
+ * eqn:innerProducts) by power iteration on A*A: `iters` steps from a fixed
+ * pseudo-random start, the Rayleigh quotient <f, A*A f>_X / <f, f>_X of the
+ * last step.  For step sizes of the iterative solvers (Sec. 4.2).  ws: a
+ * workspace for batch 1.  Allocates (and frees) two images, one trace and a
+ * few scalars of device memory and synchronises `stream` once at the end. */
+int pat_opnorm_estimate(pat_plan p, int iters, double* norm, void* ws, void* stream);
 
 /* Host-side checks of plan internals (no GPU needed).  Fills out[0..K] with
  * J_k(x) for k = 0..K computed by the plan's Miller recurrence. */

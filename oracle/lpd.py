@@ -139,9 +139,12 @@ def loss_and_grads(geom, P, y, target, iters, s_A=1.0, s_U=1.0, rounding=True):
     return float(loss.detach()), fK.detach().numpy(), {k: v.grad.numpy() for k, v in Pt.items()}
 
 
-def adam_reference(p, g, m, v, t, lr0, lr_min, total, b1=0.9, b2=0.999, eps=1e-8):
+def adam_reference(p, g, m, v, t, lr0, lr_min, total, b1=0.9, b2=0.999, eps=1e-8, clip=0.0):
     """One Adam step (Kingma & Ba, bias-corrected moments) with the step size
-    lr_min + (lr0 - lr_min) (1 + cos(pi min(1, (t-1)/(total-1)))) / 2."""
+    lr_min + (lr0 - lr_min) (1 + cos(pi min(1, (t-1)/(total-1)))) / 2, after
+    scaling g by min(1, clip / ||g||_2) when clip > 0."""
+    if clip > 0:
+        g = g * min(1.0, clip / float(np.sqrt(np.sum(np.asarray(g, dtype=np.float64) ** 2))))
     frac = min(1.0, (t - 1) / max(total - 1, 1))
     lr = lr_min + 0.5 * (lr0 - lr_min) * (1 + math.cos(math.pi * frac))
     m = b1 * m + (1 - b1) * g

@@ -195,11 +195,26 @@ __device__ __noinline__ void stockham_pass(cx<T>* buf, int logN, int logNs, int 
             const int b = it >> lnbf, t = it & (nbf - 1);
             const int k = t & ((1 << logNs) - 1);
             if (logNs > 0) {
+                // W^r for r = 1..R-1 from the table entries W^1, W^2, W^4, W^8 (at
+                // most three products each), instead of R-1 table reads
                 const int sh = logNmax - logNs - LR;
+                cx<T> wp[LR];
+#pragma unroll
+                for (int e = 0; e < LR; ++e) {
+                    wp[e] = tw[(k << e) << sh];
+                    if (inv) wp[e].y = -wp[e].y;
+                }
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    cx<T> w = tw[(r * k) << sh];
-                    if (inv) w.y = -w.y;
+                    cx<T> w = {T(1), T(0)};
+                    bool first = true;
+#pragma unroll
+                    for (int e = 0; e < LR; ++e) {
+                        if (r & (1 << e)) {
+                            w = first ? wp[e] : cmul(w, wp[e]);
+                            first = false;
+                        }
+                    }
                     v[u][r] = cmul(v[u][r], w);
                 }
             }
@@ -215,10 +230,10 @@ __device__ __noinline__ void stockham_pass(cx<T>* buf, int logN, int logNs, int 
 
 template <typename T>
 __device__ void lds_fft(cx<T>* buf, int logN, int nb, int stride, const cx<T>* __restrict__ tw, int logNmax,
-                        bool inverse)
+                        bool inverse, int maxlr)
 {
     if (logN == 0) return;
-    const int P = (logN + 3) / 4;  // passes; radices as equal as possible, at most 16
+    const int P = (logN + maxlr - 1) / maxlr;  // passes; radices as equal as possible, at most 2^maxlr
     int logNs = 0;
     for (int p = 0; p < P; ++p) {
         const int lr = logN / P + (p < logN % P ? 1 : 0);
@@ -238,16 +253,33 @@ __device__ void lds_fft(cx<T>* buf, int logN, int nb, int stride, const cx<T>* _
 // their workgroups so that each XCD receives one contiguous range of the
 // logical (x, y) grid: logical = xcd * (count on earlier XCDs) + arrival index.
 constexpr int NUM_XCD = 8;
-__device__ __forceinline__ void xcd_block(int& bx, int& by)
+__device__ __forceinline__ void xcd_remap(int lin, int nx, int total, int& bx, int& by)
 {
-    const int nx = gridDim.x, total = gridDim.x * gridDim.y;
-    const int lin = blockIdx.x + nx * blockIdx.y;
     const int xcd = lin % NUM_XCD, local = lin / NUM_XCD;
     const int per = total / NUM_XCD, rem = total % NUM_XCD;
     const int logical = (xcd < rem) ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
     bx = logical % nx;
     by = logical / nx;
 }
+__device__ __forceinline__ void xcd_block(int& bx, int& by)
+{
+    xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x, gridDim.x * gridDim.y, bx, by);
+}
+
+// Block coordinates of a kernel body: (x, y, z) of the stage's logical grid
+// and its x extent.  The single-plan kernels take them from the hardware
+// grid; the grouped kernels (several plans in one launch) derive them from
+// the block's rank inside its plan's range.
+struct Blk {
+    int x, y, z, nx;
+};
+__device__ __forceinline__ Blk blk_xcd()
+{
+    int bx, by;
+    xcd_block(bx, by);
+    return {bx, by, (int)blockIdx.z, (int)gridDim.x};
+}
+__device__ __forceinline__ Blk blk_plain() { return {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, (int)gridDim.x}; }
 
 // Plan data as seen by the kernels.
 template <typename T>
@@ -257,6 +289,7 @@ struct Dev {
     int M, log2M, L, K, Kp, klow, lcorr, npts;
     int logNmax;
     int colsCW, dctCW;
+    int fft_lr;                 // largest FFT pass radix is 2^fft_lr (3 or 4)
     T beta, shift, half;        // half = Ng / (2 Lambda): grid cells per unit lambda
     T lamh;                     // h: u = lambda h cos(phi)
     T dlam, pre_scale, adj_scale;
@@ -341,13 +374,14 @@ __device__ __forceinline__ void point_taps(const Dev<T>& d, int p, Taps<T, WMAX>
 // forward kernels
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void rows_fwd(Dev<T> d, const T* __restrict__ f, long fstride, cx<T>* R,
+__device__ __forceinline__ void rows_fwd_body(const Dev<T>& d, Blk bk, const T* __restrict__ f, long fstride, cx<T>* R,
                                                size_t ws_img)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     int bx_, b;
-    xcd_block(bx_, b);
+    bx_ = bk.x;
+    b = bk.y;
     const int p1 = 2 * bx_, p2 = p1 + 1;
     const T* fb = f + (size_t)b * fstride;
     cx<T>* Rb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(R) + (size_t)b * ws_img);
@@ -363,7 +397,7 @@ __global__ __launch_bounds__(NT) void rows_fwd(Dev<T> d, const T* __restrict__ f
         buf[qi] = {a, c};
     }
     __syncthreads();
-    lds_fft(buf, d.logNg, 1, 0, d.tw, d.logNmax, false);
+    lds_fft(buf, d.logNg, 1, 0, d.tw, d.logNmax, false, d.fft_lr);
     for (int g = threadIdx.x; g <= Ng / 2; g += blockDim.x) {
         cx<T> zg = buf[g], zm = buf[(Ng - g) & (Ng - 1)];
         cx<T> x1 = {T(0.5) * (zg.x + zm.x), T(0.5) * (zg.y - zm.y)};
@@ -374,12 +408,20 @@ __global__ __launch_bounds__(NT) void rows_fwd(Dev<T> d, const T* __restrict__ f
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void cols_fwd(Dev<T> d, const cx<T>* R, cx<T>* E, size_t ws_img)
+__global__ __launch_bounds__(NT) void rows_fwd(Dev<T> d, const T* __restrict__ f, long fstride, cx<T>* R,
+                                               size_t ws_img)
+{
+    rows_fwd_body<T>(d, blk_xcd(), f, fstride, R, ws_img);
+}
+
+template <typename T>
+__device__ __forceinline__ void cols_fwd_body(const Dev<T>& d, Blk bk, const cx<T>* R, cx<T>* E, size_t ws_img)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     int bx_, b;
-    xcd_block(bx_, b);
+    bx_ = bk.x;
+    b = bk.y;
     const int CW = d.colsCW, x0 = bx_ * CW;
     const int Ng = d.Ng, n = d.n;
     const cx<T>* Rb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(R) + (size_t)b * ws_img);
@@ -392,7 +434,7 @@ __global__ __launch_bounds__(NT) void cols_fwd(Dev<T> d, const cx<T>* R, cx<T>* 
         if (gx < d.Rw) buf[c * Ng + ((p - n / 2 + Ng) & (Ng - 1))] = Rb[(size_t)p * d.Rw + gx];
     }
     __syncthreads();
-    lds_fft(buf, d.logNg, CW, Ng, d.tw, d.logNmax, false);
+    lds_fft(buf, d.logNg, CW, Ng, d.tw, d.logNmax, false, d.fft_lr);
     for (int i = threadIdx.x; i < CW * Ng; i += blockDim.x) {
         int gy = i / CW, c = i - gy * CW;
         int gx = x0 + c;
@@ -405,46 +447,71 @@ __global__ __launch_bounds__(NT) void cols_fwd(Dev<T> d, const cx<T>* R, cx<T>* 
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(NT) void cols_fwd(Dev<T> d, const cx<T>* R, cx<T>* E, size_t ws_img)
+{
+    cols_fwd_body<T>(d, blk_xcd(), R, E, ws_img);
+}
+
+// One block per (ring, group of up to G images): the taps, weights and phase
+// of each half-ring sample are computed once and applied to every image of
+// the group (the transcendental work does not depend on the image).
 template <typename T, int WMAX>
-__global__ __launch_bounds__(NT) void ring_fwd(Dev<T> d, const cx<T>* E, cx<T>* V, cx<T>* Ulow, size_t ws_img)
+__device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<T>* E, cx<T>* V, cx<T>* Ulow, size_t ws_img, int B,
+                                               int G)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    int l, b;
-    xcd_block(l, b);
+    int l, grp;
+    l = bk.x;
+    grp = bk.y;
+    const int b0 = grp * G, nb = min(G, B - b0);
     const int N = d.ringN[l], logN = d.ringLog[l], Kl = d.ringK[l];
-    const cx<T>* Eb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(E) + (size_t)b * ws_img);
-    cx<T>* Vb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(V) + (size_t)b * ws_img);
-    cx<T>* Ub = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(Ulow) + (size_t)b * ws_img);
     const int mask = d.Ng - 1;
     for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
         Taps<T, WMAX> tp;
         point_taps<T, WMAX>(d, d.ringOff[l] + si, tp);
-        cx<T> acc = {T(0), T(0)};
+        const int s = si - N / 4;
+        for (int i = 0; i < nb; ++i) {
+            const cx<T>* Eb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(E) + (size_t)(b0 + i) * ws_img);
+            cx<T> acc = {T(0), T(0)};
 #pragma unroll
-        for (int jy = 0; jy < WMAX; ++jy) {
-            const cx<T>* row = Eb + (size_t)((tp.gy0 + jy) & mask) * d.Ew + tp.gx0 + d.hw;
-            cx<T> racc = {T(0), T(0)};
+            for (int jy = 0; jy < WMAX; ++jy) {
+                const cx<T>* row = Eb + (size_t)((tp.gy0 + jy) & mask) * d.Ew + tp.gx0 + d.hw;
+                cx<T> racc = {T(0), T(0)};
 #pragma unroll
-            for (int jx = 0; jx < WMAX; ++jx) {
-                racc = racc + row[jx] * tp.wx[jx];
+                for (int jx = 0; jx < WMAX; ++jx) racc = racc + row[jx] * tp.wx[jx];
+                acc = acc + racc * tp.wy[jy];
             }
-            acc = acc + racc * tp.wy[jy];
+            const cx<T> v = cmul(acc, tp.ph);
+            cx<T>* bi = buf + i * N;
+            bi[s & (N - 1)] = v;
+            bi[(s + N / 2) & (N - 1)] = conjg(v);
         }
-        cx<T> v = cmul(acc, tp.ph);
-        int s = si - N / 4;
-        buf[s & (N - 1)] = v;
-        buf[(s + N / 2) & (N - 1)] = conjg(v);
     }
     __syncthreads();
-    lds_fft(buf, logN, 1, 0, d.tw, d.logNmax, false);
+    const int per_call = max(1, min(nb, FFT_BLOCK_POINTS >> logN));
+    for (int i = 0; i < nb; i += per_call)
+        lds_fft(buf + i * N, logN, min(per_call, nb - i), N, d.tw, d.logNmax, false, d.fft_lr);
     const T invN = T(1) / T(N);
-    for (int k = threadIdx.x; k < d.Kp; k += blockDim.x) {
-        cx<T> out = {T(0), T(0)};
-        if (k <= Kl) out = mul_ipow(buf[k] * d.Tb[(size_t)l * d.Kp + k], k);
-        Vb[(size_t)l * d.Kp + k] = out;
-        if (l < d.lcorr && k <= d.klow) Ub[(size_t)l * (d.klow + 1) + k] = (k <= Kl ? buf[k] : cx<T>{T(0), T(0)}) * invN;
+    for (int i = 0; i < nb; ++i) {
+        const cx<T>* bi = buf + i * N;
+        cx<T>* Vb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(V) + (size_t)(b0 + i) * ws_img);
+        cx<T>* Ub = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(Ulow) + (size_t)(b0 + i) * ws_img);
+        for (int k = threadIdx.x; k < d.Kp; k += blockDim.x) {
+            cx<T> out = {T(0), T(0)};
+            if (k <= Kl) out = mul_ipow(bi[k] * d.Tb[(size_t)l * d.Kp + k], k);
+            Vb[(size_t)l * d.Kp + k] = out;
+            if (l < d.lcorr && k <= d.klow) Ub[(size_t)l * (d.klow + 1) + k] = (k <= Kl ? bi[k] : cx<T>{T(0), T(0)}) * invN;
+        }
     }
+}
+
+template <typename T, int WMAX>
+__global__ __launch_bounds__(NT) void ring_fwd(Dev<T> d, const cx<T>* E, cx<T>* V, cx<T>* Ulow, size_t ws_img, int B,
+                                               int G)
+{
+    ring_fwd_body<T, WMAX>(d, blk_xcd(), E, V, Ulow, ws_img, B, G);
 }
 
 // Cosine sum on CW columns of a row-major [rows][Kp] array:
@@ -455,12 +522,13 @@ __global__ __launch_bounds__(NT) void ring_fwd(Dev<T> d, const cx<T>* E, cx<T>* 
 // in(x) e^{i pi x r/M} (folded mod M) at y', and X(-y) = that DFT at (-y'-r) mod M.
 // Two M-point FFTs replace one 2M-point FFT of a zero-padded column.
 template <typename T>
-__global__ __launch_bounds__(NT) void dct_cols(Dev<T> d, const cx<T>* in, cx<T>* out, size_t ws_img, int adjoint)
+__device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<T>* in, cx<T>* out, size_t ws_img, int adjoint)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     int bx_, b;
-    xcd_block(bx_, b);
+    bx_ = bk.x;
+    b = bk.y;
     const int CW = d.dctCW, k0 = bx_ * CW;
     const int M = d.M, logM = d.log2M;
     const cx<T>* ib = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(in) + (size_t)b * ws_img);
@@ -485,7 +553,7 @@ __global__ __launch_bounds__(NT) void dct_cols(Dev<T> d, const cx<T>* in, cx<T>*
             buf[c * M + xs] = acc;
         }
         __syncthreads();
-        lds_fft(buf, logM, CW, M, d.tw, d.logNmax, true);
+        lds_fft(buf, logM, CW, M, d.tw, d.logNmax, true, d.fft_lr);
         for (int i = threadIdx.x; i < CW * nout; i += blockDim.x) {
             const int orow = i / CW, c = i - orow * CW;
             const int k = k0 + c;
@@ -499,15 +567,21 @@ __global__ __launch_bounds__(NT) void dct_cols(Dev<T> d, const cx<T>* in, cx<T>*
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(NT) void dct_cols(Dev<T> d, const cx<T>* in, cx<T>* out, size_t ws_img, int adjoint)
+{
+    dct_cols_body<T>(d, blk_xcd(), in, out, ws_img, adjoint);
+}
+
 // G_k(t_j) += i^k sum_l Mk[k][j][l] Ulow[l][k], k = 0..klow
 template <typename T>
-__global__ __launch_bounds__(NT) void lowk_fwd(Dev<T> d, const cx<T>* Ulow, cx<T>* G, size_t ws_img)
+__device__ __forceinline__ void lowk_fwd_body(const Dev<T>& d, Blk bk, const cx<T>* Ulow, cx<T>* G, size_t ws_img)
 {
-    const int b = blockIdx.y;
+    const int b = bk.y;
     const cx<T>* Ub = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(Ulow) + (size_t)b * ws_img);
     cx<T>* Gb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(G) + (size_t)b * ws_img);
     const int items = d.nt * (d.klow + 1);
-    for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < items; it += gridDim.x * blockDim.x) {
+    for (int it = bk.x * blockDim.x + threadIdx.x; it < items; it += bk.nx * blockDim.x) {
         int j = it / (d.klow + 1), k = it - j * (d.klow + 1);
         const T* row = d.Mk + ((size_t)k * d.nt + j) * d.lcorr;
         cx<T> acc = {T(0), T(0)};
@@ -518,13 +592,20 @@ __global__ __launch_bounds__(NT) void lowk_fwd(Dev<T> d, const cx<T>* Ulow, cx<T
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void synth_fwd(Dev<T> d, const cx<T>* G, T* g, long gstride, size_t ws_img)
+__global__ __launch_bounds__(NT) void lowk_fwd(Dev<T> d, const cx<T>* Ulow, cx<T>* G, size_t ws_img)
+{
+    lowk_fwd_body<T>(d, blk_plain(), Ulow, G, ws_img);
+}
+
+template <typename T>
+__device__ __forceinline__ void synth_fwd_body(const Dev<T>& d, Blk bk, const cx<T>* G, T* g, long gstride, size_t ws_img)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* Z1 = reinterpret_cast<cx<T>*>(smem_raw);
     cx<T>* Z2 = Z1 + d.mf;
     int bx_, b;
-    xcd_block(bx_, b);
+    bx_ = bk.x;
+    b = bk.y;
     const int j1 = 2 * bx_, j2 = j1 + 1;
     const int mf = d.mf;
     const cx<T>* Gb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(G) + (size_t)b * ws_img);
@@ -552,23 +633,30 @@ __global__ __launch_bounds__(NT) void synth_fwd(Dev<T> d, const cx<T>* G, T* g, 
         if (rm != r) Z1[rm] = {h1.x + h2.y, h2.x - h1.y};
     }
     __syncthreads();
-    lds_fft(Z1, d.logmf, 1, 0, d.tw, d.logNmax, true);
+    lds_fft(Z1, d.logmf, 1, 0, d.tw, d.logNmax, true, d.fft_lr);
     for (int i = threadIdx.x; i < d.m; i += blockDim.x) {
         gb[(size_t)j1 * d.m + i] = Z1[i].x;
         if (has2) gb[(size_t)j2 * d.m + i] = Z1[i].y;
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(NT) void synth_fwd(Dev<T> d, const cx<T>* G, T* g, long gstride, size_t ws_img)
+{
+    synth_fwd_body<T>(d, blk_xcd(), G, g, gstride, ws_img);
+}
+
 // ---------------------------------------------------------------------------
 // adjoint kernels (exact transposes, reverse order)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void synth_adj(Dev<T> d, const T* g, long gstride, cx<T>* G, size_t ws_img)
+__device__ __forceinline__ void synth_adj_body(const Dev<T>& d, Blk bk, const T* g, long gstride, cx<T>* G, size_t ws_img)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* Z = reinterpret_cast<cx<T>*>(smem_raw);
     int bx_, b;
-    xcd_block(bx_, b);
+    bx_ = bk.x;
+    b = bk.y;
     const int j1 = 2 * bx_, j2 = j1 + 1;
     const int mf = d.mf;
     const bool has2 = j2 < d.nt;
@@ -580,7 +668,7 @@ __global__ __launch_bounds__(NT) void synth_adj(Dev<T> d, const T* g, long gstri
         Z[i] = {a, c};
     }
     __syncthreads();
-    lds_fft(Z, d.logmf, 1, 0, d.tw, d.logNmax, false);
+    lds_fft(Z, d.logmf, 1, 0, d.tw, d.logNmax, false, d.fft_lr);
     for (int k = threadIdx.x; k < d.Kp; k += blockDim.x) {
         cx<T> y1 = {T(0), T(0)}, y2 = {T(0), T(0)};
         if (k <= d.K) {
@@ -597,12 +685,18 @@ __global__ __launch_bounds__(NT) void synth_adj(Dev<T> d, const T* g, long gstri
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(NT) void synth_adj(Dev<T> d, const T* g, long gstride, cx<T>* G, size_t ws_img)
+{
+    synth_adj_body<T>(d, blk_xcd(), g, gstride, G, ws_img);
+}
+
 // Ulow_hat[l][k] = conj(i^k) sum_j Mk[k][j][l] G_hat[j][k]; one block per ring l.
 template <typename T>
-__global__ __launch_bounds__(NT) void lowk_adj(Dev<T> d, const cx<T>* G, cx<T>* Ulow, size_t ws_img)
+__device__ __forceinline__ void lowk_adj_body(const Dev<T>& d, Blk bk, const cx<T>* G, cx<T>* Ulow, size_t ws_img)
 {
     __shared__ cx<T> red[NT];
-    const int b = blockIdx.y, l = blockIdx.x;
+    const int b = bk.y, l = bk.x;
     const cx<T>* Gb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(G) + (size_t)b * ws_img);
     cx<T>* Ub = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(Ulow) + (size_t)b * ws_img);
     for (int k = 0; k <= d.klow; ++k) {
@@ -620,16 +714,22 @@ __global__ __launch_bounds__(NT) void lowk_adj(Dev<T> d, const cx<T>* G, cx<T>* 
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(NT) void lowk_adj(Dev<T> d, const cx<T>* G, cx<T>* Ulow, size_t ws_img)
+{
+    lowk_adj_body<T>(d, blk_plain(), G, Ulow, ws_img);
+}
+
 // Samples are written image-minor, Pol[(ringOff[l] + si) * B + b], already
 // multiplied by the conjugate point phase, for the batched spread below.
 template <typename T, int WMAX>
-__global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const cx<T>* Ulow, cx<T>* Pol, int B,
+__device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<T>* V, const cx<T>* Ulow, cx<T>* Pol, int B,
                                                size_t ws_img)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     // no XCD renumbering here: contiguous ranges of rings would unbalance the XCDs
-    const int b = blockIdx.x, l = blockIdx.y;
+    const int b = bk.x, l = bk.y;
     const int N = d.ringN[l], logN = d.ringLog[l], Kl = d.ringK[l];
     const cx<T>* Vb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(V) + (size_t)b * ws_img);
     const cx<T>* Ub = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(Ulow) + (size_t)b * ws_img);
@@ -643,7 +743,7 @@ __global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const c
         buf[k] = v;
     }
     __syncthreads();
-    lds_fft(buf, logN, 1, 0, d.tw, d.logNmax, true);
+    lds_fft(buf, logN, 1, 0, d.tw, d.logNmax, true, d.fft_lr);
     const int off = d.ringOff[l];
     for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
         const int s = si - N / 4;
@@ -653,6 +753,13 @@ __global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const c
         point_xy(d, off + si, x, y);
         Pol[(size_t)(off + si) * B + b] = cmul(uf, conjg(point_phase(d, x, y)));
     }
+}
+
+template <typename T, int WMAX>
+__global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const cx<T>* Ulow, cx<T>* Pol, int B,
+                                               size_t ws_img)
+{
+    ring_adj_body<T, WMAX>(d, blk_plain(), V, Ulow, Pol, B, ws_img);
 }
 
 // Transpose of the gather.  Each wave owns an 8 x 8 tile of cells of the
@@ -668,15 +775,16 @@ __global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const c
 // each lane tests the tap rule for its own cell and accumulates weight *
 // value.  No atomics; a fixed summation order per cell.
 template <typename T, int W, int BC>
-__global__ __launch_bounds__(NT) void spread_tiles(Dev<T> d, const cx<T>* Pol, int B, cx<T>* E, size_t ws_img)
+__device__ __forceinline__ void spread_tiles_body(const Dev<T>& d, Blk bk, const cx<T>* Pol, int B, cx<T>* E, size_t ws_img)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int bxt, byt;
-    xcd_block(bxt, byt);  // gridDim.z (image groups) is handled by blockIdx.z below
+    bxt = bk.x;
+    byt = bk.y;
     const int tx0 = bxt * 16 + (wave & 1) * 8;   // first column of the wave's tile
     const int ty0 = byt * 16 + (wave >> 1) * 8;  // first row
     const int e = tx0 + (lane & 7), gy = ty0 + (lane >> 3);
-    const int b0 = blockIdx.z * BC;
+    const int b0 = bk.z * BC;
     const int nb = min(BC, B - b0);
     const int Ng = d.Ng, mask = Ng - 1;
     const bool valid = e < d.Ew && gy < Ng;
@@ -754,10 +862,15 @@ __global__ __launch_bounds__(NT) void spread_tiles(Dev<T> d, const cx<T>* Pol, i
                             const int jy = (gy - gy0) & mask;
                             if (valid && (unsigned)jx < (unsigned)W && jy < W) {
                                 const T wgt = es_w(q.x - T(gx0 + jx), tw_, d.beta) * es_w(q.y - T(gy0 + jy), tw_, d.beta);
+                                // all BC values of the sample in one go (wide scalar loads, one
+                                // wait); entries past the batch are padding or the next point's
+                                // values and only reach accumulators that are never stored
                                 const cx<T>* src = Pol + (size_t)p * B + b0;
+                                cx<T> val[BC];
 #pragma unroll
-                                for (int k = 0; k < BC; ++k)
-                                    if (k < nb) acc[k] = acc[k] + src[k] * wgt;
+                                for (int k = 0; k < BC; ++k) val[k] = src[k];
+#pragma unroll
+                                for (int k = 0; k < BC; ++k) acc[k] = acc[k] + val[k] * wgt;
                             }
                         }
                     }
@@ -775,13 +888,20 @@ __global__ __launch_bounds__(NT) void spread_tiles(Dev<T> d, const cx<T>* Pol, i
     }
 }
 
+template <typename T, int W, int BC>
+__global__ __launch_bounds__(NT) void spread_tiles(Dev<T> d, const cx<T>* Pol, int B, cx<T>* E, size_t ws_img)
+{
+    spread_tiles_body<T, W, BC>(d, blk_xcd(), Pol, B, E, ws_img);
+}
+
 template <typename T>
-__global__ __launch_bounds__(NT) void cols_adj(Dev<T> d, const cx<T>* E, cx<T>* R, size_t ws_img)
+__device__ __forceinline__ void cols_adj_body(const Dev<T>& d, Blk bk, const cx<T>* E, cx<T>* R, size_t ws_img)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     int bx_, b;
-    xcd_block(bx_, b);
+    bx_ = bk.x;
+    b = bk.y;
     const int CW = d.colsCW, x0 = bx_ * CW;
     const int Ng = d.Ng, n = d.n;
     const cx<T>* Eb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(E) + (size_t)b * ws_img);
@@ -799,7 +919,7 @@ __global__ __launch_bounds__(NT) void cols_adj(Dev<T> d, const cx<T>* E, cx<T>* 
         buf[c * Ng + gy] = v;
     }
     __syncthreads();
-    lds_fft(buf, d.logNg, CW, Ng, d.tw, d.logNmax, true);
+    lds_fft(buf, d.logNg, CW, Ng, d.tw, d.logNmax, true, d.fft_lr);
     for (int i = threadIdx.x; i < CW * n; i += blockDim.x) {
         int p = i / CW, c = i - p * CW;
         int gx = x0 + c;
@@ -808,12 +928,19 @@ __global__ __launch_bounds__(NT) void cols_adj(Dev<T> d, const cx<T>* E, cx<T>* 
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void rows_adj(Dev<T> d, const cx<T>* R, T* f, long fstride, size_t ws_img)
+__global__ __launch_bounds__(NT) void cols_adj(Dev<T> d, const cx<T>* E, cx<T>* R, size_t ws_img)
+{
+    cols_adj_body<T>(d, blk_xcd(), E, R, ws_img);
+}
+
+template <typename T>
+__device__ __forceinline__ void rows_adj_body(const Dev<T>& d, Blk bk, const cx<T>* R, T* f, long fstride, size_t ws_img)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     int bx_, b;
-    xcd_block(bx_, b);
+    bx_ = bk.x;
+    b = bk.y;
     const int p1 = 2 * bx_, p2 = p1 + 1;
     const int Ng = d.Ng, n = d.n, hN = Ng / 2;
     const cx<T>* Rb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(R) + (size_t)b * ws_img);
@@ -834,7 +961,7 @@ __global__ __launch_bounds__(NT) void rows_adj(Dev<T> d, const cx<T>* R, T* f, l
         buf[g] = {xa.x - xb.y, xa.y + xb.x};
     }
     __syncthreads();
-    lds_fft(buf, d.logNg, 1, 0, d.tw, d.logNmax, true);
+    lds_fft(buf, d.logNg, 1, 0, d.tw, d.logNmax, true, d.fft_lr);
     const T s1 = d.Dq[p1] * d.pre_scale * d.adj_scale;
     const T s2 = has2 ? d.Dq[p2] * d.pre_scale * d.adj_scale : T(0);
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
@@ -842,6 +969,12 @@ __global__ __launch_bounds__(NT) void rows_adj(Dev<T> d, const cx<T>* R, T* f, l
         fb[(size_t)p1 * n + q] = in_mask(d, p1, q) ? v.x * d.Dq[q] * s1 : T(0);
         if (has2) fb[(size_t)p2 * n + q] = in_mask(d, p2, q) ? v.y * d.Dq[q] * s2 : T(0);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void rows_adj(Dev<T> d, const cx<T>* R, T* f, long fstride, size_t ws_img)
+{
+    rows_adj_body<T>(d, blk_xcd(), R, f, fstride, ws_img);
 }
 
 }  // namespace
@@ -860,6 +993,10 @@ struct pat_plan_s {
     size_t table_bytes = 0;
     Dev<float> df{};
     Dev<double> dd{};
+    // launch-shape choices (defaults from LDS limits; replaced by the autotuner's)
+    int cols_cw = 1, dct_cw = 1, ring_g = 1, spread_bc = 16, fft_lr = 4;
+    int tuned = 0;                        // 1: measured now, 2: read from the tuning cache
+    double tuned_ms = 0.0;
     // optional per-stage timing with HIP events recorded on the launch stream
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;       // pairs (start, end)
@@ -870,6 +1007,8 @@ struct pat_plan_s {
 namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+constexpr size_t SPREAD_PAD = 16;  // >= the spread's image group BC
 
 void layout(pat_plan_s* p)
 {
@@ -883,8 +1022,9 @@ void layout(pat_plan_s* p)
     p->offU = o; o = align256(o + cs * (size_t)P.lcorr * (P.klow + 1));
     p->ws_stride = o;
     // the adjoint's half-ring samples, image-minor: B * npts values after the B slices
+    // (plus SPREAD_PAD values: the spread reads whole groups of images per sample)
     p->offP = 0;
-    p->ws_img = o + align256(cs * (size_t)P.npts);
+    p->ws_img = o + align256(cs * ((size_t)P.npts + SPREAD_PAD));
 }
 
 int lds_cols(const pat::Params& P)
@@ -893,6 +1033,15 @@ int lds_cols(const pat::Params& P)
     int cw = 16;
     while (cw > 1 && ((size_t)cw * P.Ng * cs > 65536 || (size_t)cw * P.Ng > FFT_BLOCK_POINTS)) cw >>= 1;
     return cw;
+}
+
+// largest number of images per ring_fwd block that fits 64 KiB of LDS (at most 4)
+int ring_group_max(const pat::Params& P)
+{
+    size_t cs = (P.dt == PAT_F64) ? 16 : 8;
+    int g = 4;
+    while (g > 1 && (size_t)g * P.max_ring * cs > 65536) g >>= 1;
+    return g;
 }
 
 int lds_dct(const pat::Params& P)
@@ -949,8 +1098,9 @@ int upload(pat_plan_s* p, Dev<T>& d)
     d.Ng = P.Ng; d.logNg = ilog2i(P.Ng); d.w = P.w; d.hw = P.hw; d.Rw = P.Rw; d.Ew = P.Ew;
     d.M = P.M; d.log2M = ilog2i(P.M); d.L = P.L; d.K = P.K; d.Kp = P.Kp; d.klow = P.klow; d.lcorr = P.lcorr;
     d.npts = P.npts; d.logNmax = ilog2i(P.Nmax);
-    d.colsCW = lds_cols(P);
-    d.dctCW = lds_dct(P);
+    d.colsCW = p->cols_cw;
+    d.dctCW = p->dct_cw;
+    d.fft_lr = p->fft_lr;
     d.beta = (T)P.beta; d.shift = (T)P.shift; d.half = (T)(0.5 * P.Ng / P.Lam); d.lamh = (T)P.h;
     d.dlam = (T)P.dlam; d.pre_scale = (T)P.pre_scale; d.adj_scale = (T)P.adj_scale;
     d.mask_r2 = P.g.mask_radius > 0 ? P.g.mask_radius * P.g.mask_radius : 0.0;
@@ -1020,7 +1170,8 @@ int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g
     if ((rc = check_launch("cols_fwd"))) return rc;
     {
         StageTimer tm(p, st, 2);
-        ring_fwd<T, WMAX><<<dim3(d.L, B), NT, cs * p->H.P.max_ring, st>>>(d, E, V, U, wi);
+        const int G = std::max(1, std::min(p->ring_g, B));
+        ring_fwd<T, WMAX><<<dim3(d.L, (B + G - 1) / G), NT, cs * G * p->H.P.max_ring, st>>>(d, E, V, U, wi, B, G);
     }
     if ((rc = check_launch("ring_fwd"))) return rc;
     {
@@ -1075,8 +1226,13 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
     if ((rc = check_launch("ring_adj"))) return rc;
     {
         StageTimer tm(p, st, 10);
-        constexpr int BC = sizeof(T) == 4 ? 16 : 8;
-        spread_tiles<T, WMAX, BC><<<dim3((d.Ew + 15) / 16, (d.Ng + 15) / 16, (B + BC - 1) / BC), NT, 0, st>>>(d, Pol, B, E, wi);
+        constexpr int BCL = sizeof(T) == 4 ? 16 : 8;  // image group of the spread: BCL or BCL / 2
+        const dim3 grid((d.Ew + 15) / 16, (d.Ng + 15) / 16, 1);
+        if (p->spread_bc >= BCL)
+            spread_tiles<T, WMAX, BCL><<<dim3(grid.x, grid.y, (B + BCL - 1) / BCL), NT, 0, st>>>(d, Pol, B, E, wi);
+        else
+            spread_tiles<T, WMAX, BCL / 2><<<dim3(grid.x, grid.y, (B + BCL / 2 - 1) / (BCL / 2)), NT, 0, st>>>(d, Pol, B,
+                                                                                                             E, wi);
     }
     if ((rc = check_launch("spread_adj"))) return rc;
     {
@@ -1091,6 +1247,374 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
     return check_launch("rows_adj");
 }
 
+// ---------------------------------------------------------------------------
+// Grouped launches: plans of different sizes (same precision) run each stage
+// as one launch whose blocks cover the grids of all plans back to back.  A
+// block finds its plan from the per-stage block offsets (padded to multiples
+// of the XCD count), rebuilds its stage coordinates and runs the same kernel
+// body as the single-plan launch, so results are identical to per-plan calls.
+// ---------------------------------------------------------------------------
+constexpr int GROUP_MAX = 6;
+
+template <typename T>
+struct GroupPlan {
+    Dev<T> d;
+    const T* fin;
+    T* fout;
+    const T* gin;
+    T* gout;
+    long fs, gs;
+    char *R, *E, *V, *Gh, *U, *Pol;
+    size_t wi;
+    int B, G;
+    int off[PAT_NUM_STAGES];
+};
+
+template <typename T>
+struct GroupArgs {
+    GroupPlan<T> p[GROUP_MAX];
+    int nplans;
+};
+
+template <typename T>
+__host__ __device__ inline void stage_grid(const Dev<T>& d, int S, int B, int G, int BC, int& nx, int& ny, int& nz)
+{
+    nz = 1;
+    switch (S) {
+        case PAT_STAGE_ROWS_FWD:
+        case PAT_STAGE_ROWS_ADJ: nx = (d.n + 1) / 2; ny = B; break;
+        case PAT_STAGE_COLS_FWD:
+        case PAT_STAGE_COLS_ADJ: nx = (d.Rw + d.colsCW - 1) / d.colsCW; ny = B; break;
+        case PAT_STAGE_RING_FWD: nx = d.L; ny = (B + G - 1) / G; break;
+        case PAT_STAGE_DCT_FWD:
+        case PAT_STAGE_DCT_ADJ: nx = (d.Kp + d.dctCW - 1) / d.dctCW; ny = B; break;
+        case PAT_STAGE_LOWK_FWD: nx = (d.nt * (d.klow + 1) + NT - 1) / NT; ny = B; break;
+        case PAT_STAGE_SYNTH_FWD:
+        case PAT_STAGE_SYNTH_ADJ: nx = (d.nt + 1) / 2; ny = B; break;
+        case PAT_STAGE_LOWK_ADJ: nx = d.lcorr; ny = B; break;
+        case PAT_STAGE_RING_ADJ: nx = B; ny = d.L; break;
+        default: nx = (d.Ew + 15) / 16; ny = (d.Ng + 15) / 16; nz = (B + BC - 1) / BC; break;  // spread
+    }
+}
+
+template <typename T, int WMAX, int S>
+__global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
+{
+    constexpr int BC = sizeof(T) == 4 ? 16 : 8;
+    const int lin = blockIdx.x;
+    int pi = 0;
+    while (pi + 1 < ga.nplans && lin >= ga.p[pi + 1].off[S]) ++pi;
+    const GroupPlan<T>& q = ga.p[pi];
+    int nx, ny, nz;
+    stage_grid(q.d, S, q.B, q.G, BC, nx, ny, nz);
+    const int local = lin - q.off[S], plane = nx * ny;
+    if (local >= plane * nz) return;  // padding block
+    Blk bk;
+    bk.nx = nx;
+    bk.z = local / plane;
+    const int r = local - bk.z * plane;
+    if (S == PAT_STAGE_LOWK_FWD || S == PAT_STAGE_LOWK_ADJ || S == PAT_STAGE_RING_ADJ) {
+        bk.x = r % nx;
+        bk.y = r / nx;
+    } else {
+        xcd_remap(r, nx, plane, bk.x, bk.y);
+    }
+    cx<T>* R = reinterpret_cast<cx<T>*>(q.R);
+    cx<T>* E = reinterpret_cast<cx<T>*>(q.E);
+    cx<T>* V = reinterpret_cast<cx<T>*>(q.V);
+    cx<T>* Gh = reinterpret_cast<cx<T>*>(q.Gh);
+    cx<T>* U = reinterpret_cast<cx<T>*>(q.U);
+    cx<T>* Pol = reinterpret_cast<cx<T>*>(q.Pol);
+    if constexpr (S == PAT_STAGE_ROWS_FWD) rows_fwd_body<T>(q.d, bk, q.fin, q.fs, R, q.wi);
+    if constexpr (S == PAT_STAGE_COLS_FWD) cols_fwd_body<T>(q.d, bk, R, E, q.wi);
+    if constexpr (S == PAT_STAGE_RING_FWD) ring_fwd_body<T, WMAX>(q.d, bk, E, V, U, q.wi, q.B, q.G);
+    if constexpr (S == PAT_STAGE_DCT_FWD) dct_cols_body<T>(q.d, bk, V, Gh, q.wi, 0);
+    if constexpr (S == PAT_STAGE_LOWK_FWD) lowk_fwd_body<T>(q.d, bk, U, Gh, q.wi);
+    if constexpr (S == PAT_STAGE_SYNTH_FWD) synth_fwd_body<T>(q.d, bk, Gh, q.gout, q.gs, q.wi);
+    if constexpr (S == PAT_STAGE_SYNTH_ADJ) synth_adj_body<T>(q.d, bk, q.gin, q.gs, Gh, q.wi);
+    if constexpr (S == PAT_STAGE_LOWK_ADJ) lowk_adj_body<T>(q.d, bk, Gh, U, q.wi);
+    if constexpr (S == PAT_STAGE_DCT_ADJ) dct_cols_body<T>(q.d, bk, Gh, V, q.wi, 1);
+    if constexpr (S == PAT_STAGE_RING_ADJ) ring_adj_body<T, WMAX>(q.d, bk, V, U, Pol, q.B, q.wi);
+    if constexpr (S == PAT_STAGE_SPREAD_ADJ) spread_tiles_body<T, WMAX, BC>(q.d, bk, Pol, q.B, E, q.wi);
+    if constexpr (S == PAT_STAGE_COLS_ADJ) cols_adj_body<T>(q.d, bk, E, R, q.wi);
+    if constexpr (S == PAT_STAGE_ROWS_ADJ) rows_adj_body<T>(q.d, bk, R, q.fout, q.fs, q.wi);
+}
+
+inline const Dev<float>& dev_of(const pat_plan_s* p, float*) { return p->df; }
+inline const Dev<double>& dev_of(const pat_plan_s* p, double*) { return p->dd; }
+
+// dynamic LDS bytes of stage S for plan p with ring group G
+size_t stage_lds(const pat_plan_s* p, int S, int G)
+{
+    const pat::Params& P = p->H.P;
+    const size_t cs = (P.dt == PAT_F64) ? 16 : 8;
+    switch (S) {
+        case PAT_STAGE_ROWS_FWD:
+        case PAT_STAGE_ROWS_ADJ: return cs * P.Ng;
+        case PAT_STAGE_COLS_FWD:
+        case PAT_STAGE_COLS_ADJ: return cs * P.Ng * p->cols_cw;
+        case PAT_STAGE_RING_FWD: return cs * G * P.max_ring;
+        case PAT_STAGE_DCT_FWD:
+        case PAT_STAGE_DCT_ADJ: return cs * P.M * p->dct_cw;
+        case PAT_STAGE_SYNTH_FWD: return cs * 2 * P.mf;
+        case PAT_STAGE_SYNTH_ADJ: return cs * P.mf;
+        case PAT_STAGE_RING_ADJ: return cs * P.max_ring;
+        default: return 0;
+    }
+}
+
+template <int S, typename T, int WMAX>
+int launch_grouped(const GroupArgs<T>& ga, int blocks, size_t lds, hipStream_t st)
+{
+    grouped_stage<T, WMAX, S><<<blocks, NT, lds, st>>>(ga);
+    return check_launch("grouped stage");
+}
+
+template <typename T, int WMAX>
+int group_run(const std::vector<pat_plan_s*>& plans, bool adjoint, const int* batch, const void* const* in,
+              void* const* out, void* const* ws, hipStream_t st)
+{
+    static_assert(sizeof(GroupArgs<T>) <= 4000, "grouped kernel arguments exceed the kernarg limit");
+    constexpr int BC = sizeof(T) == 4 ? 16 : 8;
+    GroupArgs<T> ga;
+    std::memset(&ga, 0, sizeof(ga));
+    ga.nplans = (int)plans.size();
+    int total[PAT_NUM_STAGES] = {0};
+    size_t lds[PAT_NUM_STAGES] = {0};
+    for (int i = 0; i < ga.nplans; ++i) {
+        pat_plan_s* p = plans[i];
+        const pat::Params& P = p->H.P;
+        GroupPlan<T>& q = ga.p[i];
+        const int B = batch[i];
+        if (B < 1 || B > p->max_batch) return fail(PAT_ESMALL, "pat_group: batch outside [1, max_batch] of a plan");
+        if (!in[i] || !out[i] || !ws[i]) return fail(PAT_EINVAL, "pat_group: null pointer");
+        q.d = dev_of(p, (T*)nullptr);
+        q.B = B;
+        q.G = std::max(1, std::min(p->ring_g, B));
+        q.fs = (long)P.n * P.n;
+        q.gs = (long)P.nt * P.m;
+        if (adjoint) {
+            q.gin = static_cast<const T*>(in[i]);
+            q.fout = static_cast<T*>(out[i]);
+        } else {
+            q.fin = static_cast<const T*>(in[i]);
+            q.gout = static_cast<T*>(out[i]);
+        }
+        char* w = static_cast<char*>(ws[i]);
+        q.R = w + p->offR; q.E = w + p->offE; q.V = w + p->offV; q.Gh = w + p->offG; q.U = w + p->offU;
+        q.Pol = w + (size_t)B * p->ws_stride;
+        q.wi = p->ws_stride;
+        for (int S = 0; S < PAT_NUM_STAGES; ++S) {
+            int nx, ny, nz;
+            stage_grid(q.d, S, B, q.G, BC, nx, ny, nz);
+            q.off[S] = total[S];
+            total[S] += (nx * ny * nz + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
+            lds[S] = std::max(lds[S], stage_lds(p, S, q.G));
+        }
+    }
+    int rc;
+    if (!adjoint) {
+        if ((rc = launch_grouped<PAT_STAGE_ROWS_FWD, T, WMAX>(ga, total[0], lds[0], st))) return rc;
+        if ((rc = launch_grouped<PAT_STAGE_COLS_FWD, T, WMAX>(ga, total[1], lds[1], st))) return rc;
+        if ((rc = launch_grouped<PAT_STAGE_RING_FWD, T, WMAX>(ga, total[2], lds[2], st))) return rc;
+        if ((rc = launch_grouped<PAT_STAGE_DCT_FWD, T, WMAX>(ga, total[3], lds[3], st))) return rc;
+        if ((rc = launch_grouped<PAT_STAGE_LOWK_FWD, T, WMAX>(ga, total[4], lds[4], st))) return rc;
+        return launch_grouped<PAT_STAGE_SYNTH_FWD, T, WMAX>(ga, total[5], lds[5], st);
+    }
+    if ((rc = launch_grouped<PAT_STAGE_SYNTH_ADJ, T, WMAX>(ga, total[6], lds[6], st))) return rc;
+    if ((rc = launch_grouped<PAT_STAGE_LOWK_ADJ, T, WMAX>(ga, total[7], lds[7], st))) return rc;
+    if ((rc = launch_grouped<PAT_STAGE_DCT_ADJ, T, WMAX>(ga, total[8], lds[8], st))) return rc;
+    if ((rc = launch_grouped<PAT_STAGE_RING_ADJ, T, WMAX>(ga, total[9], lds[9], st))) return rc;
+    if ((rc = launch_grouped<PAT_STAGE_SPREAD_ADJ, T, WMAX>(ga, total[10], lds[10], st))) return rc;
+    if ((rc = launch_grouped<PAT_STAGE_COLS_ADJ, T, WMAX>(ga, total[11], lds[11], st))) return rc;
+    return launch_grouped<PAT_STAGE_ROWS_ADJ, T, WMAX>(ga, total[12], lds[12], st);
+}
+
+// ---------------------------------------------------------------------------
+// Launch-shape autotuner.  Choices: the largest FFT pass radix (16 or 8), the
+// column count of the column-FFT and cosine-transform blocks, the number of
+// images per ring_fwd block and per spread group.  Defaults follow the LDS
+// limits; with a tuning cache path the plan looks its geometry / batch /
+// device up in the cache and otherwise times every candidate of one choice
+// at a time (forward + adjoint at the plan's max_batch, zero data: the
+// kernels' work does not depend on the values) and appends the winner.
+// ---------------------------------------------------------------------------
+void default_tune(pat_plan_s* p)
+{
+    const pat::Params& P = p->H.P;
+    p->cols_cw = lds_cols(P);
+    p->dct_cw = lds_dct(P);
+    p->ring_g = ring_group_max(P);
+    p->spread_bc = (P.dt == PAT_F64) ? 8 : 16;
+    p->fft_lr = 4;
+}
+
+void apply_tune(pat_plan_s* p)
+{
+    p->df.colsCW = p->dd.colsCW = p->cols_cw;
+    p->df.dctCW = p->dd.dctCW = p->dct_cw;
+    p->df.fft_lr = p->dd.fft_lr = p->fft_lr;
+}
+
+bool pow2_in(int v, int hi) { return v >= 1 && v <= hi && (v & (v - 1)) == 0; }
+
+bool tune_valid(const pat_plan_s* p)
+{
+    const pat::Params& P = p->H.P;
+    const int bcl = (P.dt == PAT_F64) ? 8 : 16;
+    return pow2_in(p->cols_cw, lds_cols(P)) && pow2_in(p->dct_cw, lds_dct(P)) && pow2_in(p->ring_g, ring_group_max(P)) &&
+           (p->spread_bc == bcl || p->spread_bc == bcl / 2) && (p->fft_lr == 3 || p->fft_lr == 4);
+}
+
+std::string tune_key(const pat_plan_s* p)
+{
+    const pat::Params& P = p->H.P;
+    const pat_geometry& g = P.g;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
+    for (char& ch : arch)
+        if (ch == ' ' || ch == '|') ch = '_';
+    char buf[640];
+    std::snprintf(buf, sizeof(buf),
+                  "pat-tune-1 arch=%s dtype=%d n=%d m=%d nt=%d a=%.17g R=%.17g c=%.17g theta0=%.17g arc=%.17g T=%.17g "
+                  "rho=%.17g mask=%.17g batch=%d",
+                  arch.c_str(), (int)P.dt, g.n, g.m, g.nt, g.a, g.R, g.c, g.theta0, g.arc, g.T, g.taper_rho,
+                  g.mask_radius, p->max_batch);
+    return buf;
+}
+
+bool tune_lookup(pat_plan_s* p, const char* path, const std::string& key)
+{
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) return false;
+    bool found = false;
+    std::vector<char> line(4096);
+    while (std::fgets(line.data(), (int)line.size(), fp)) {
+        std::string l(line.data());
+        const size_t bar = l.find(" | ");
+        if (bar == std::string::npos || l.compare(0, bar, key) != 0 || bar != key.size()) continue;
+        pat_plan_s t = *p;
+        double ms = 0;
+        if (std::sscanf(l.c_str() + bar + 3, "cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=%lf",
+                        &t.cols_cw, &t.dct_cw, &t.ring_g, &t.spread_bc, &t.fft_lr, &ms) == 6 &&
+            tune_valid(&t)) {
+            p->cols_cw = t.cols_cw; p->dct_cw = t.dct_cw; p->ring_g = t.ring_g;
+            p->spread_bc = t.spread_bc; p->fft_lr = t.fft_lr; p->tuned_ms = ms;
+            found = true;  // keep scanning: the last matching line wins
+        }
+    }
+    std::fclose(fp);
+    return found;
+}
+
+void tune_store(const pat_plan_s* p, const char* path, const std::string& key)
+{
+    FILE* fp = std::fopen(path, "a");
+    if (!fp) return;
+    std::fprintf(fp, "%s | cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=%.6f\n", key.c_str(),
+                 p->cols_cw, p->dct_cw, p->ring_g, p->spread_bc, p->fft_lr, p->tuned_ms);
+    std::fclose(fp);
+}
+
+template <typename T, int WMAX>
+int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g, long gs, char* ws, hipStream_t st);
+template <typename T, int WMAX>
+int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f, long fs, char* ws, hipStream_t st);
+
+template <typename T, int WMAX>
+int tune_search(pat_plan_s* p, const Dev<T>& d)
+{
+    const pat::Params& P = p->H.P;
+    const int B = p->max_batch;
+    const long fsz = (long)P.n * P.n, gsz = (long)P.nt * P.m;
+    void *ws = nullptr, *f = nullptr, *g = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = PAT_OK;
+    auto cleanup = [&]() {
+        if (ws) (void)hipFree(ws);
+        if (f) (void)hipFree(f);
+        if (g) (void)hipFree(g);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (st) (void)hipStreamDestroy(st);
+    };
+    if (hipMalloc(&ws, p->ws_img * (size_t)B) != hipSuccess || hipMalloc(&f, sizeof(T) * fsz * B) != hipSuccess ||
+        hipMalloc(&g, sizeof(T) * gsz * B) != hipSuccess) {
+        cleanup();
+        return fail(PAT_ENOMEM, "autotuner: workspace allocation failed");
+    }
+    if (hipMemset(f, 0, sizeof(T) * fsz * B) != hipSuccess || hipMemset(g, 0, sizeof(T) * gsz * B) != hipSuccess ||
+        hipStreamCreate(&st) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(PAT_EHIP, "autotuner: set-up failed");
+    }
+    auto measure = [&](double& ms) -> int {
+        apply_tune(p);
+        for (int rep = 0; rep < 4; ++rep) {
+            if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) return PAT_EHIP;
+            int r = run_forward<T, WMAX>(p, d, B, (const T*)f, fsz, (T*)g, gsz, (char*)ws, st);
+            if (!r) r = run_adjoint<T, WMAX>(p, d, B, (const T*)g, gsz, (T*)f, fsz, (char*)ws, st);
+            if (r) return r;
+        }
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return PAT_EHIP;
+        float t = 0;
+        if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) return PAT_EHIP;
+        ms = t / 3.0;
+        return PAT_OK;
+    };
+    const int bcl = (P.dt == PAT_F64) ? 8 : 16;
+    struct Choice {
+        int* field;
+        std::vector<int> cands;
+    };
+    std::vector<int> cw, dw, rg;
+    for (int v = lds_cols(P); v >= 1; v >>= 1) cw.push_back(v);
+    for (int v = lds_dct(P); v >= 1; v >>= 1) dw.push_back(v);
+    for (int v = ring_group_max(P); v >= 1; v >>= 1) rg.push_back(v);
+    std::vector<Choice> choices = {{&p->fft_lr, {4, 3}},
+                                   {&p->cols_cw, cw},
+                                   {&p->dct_cw, dw},
+                                   {&p->ring_g, rg},
+                                   {&p->spread_bc, {bcl, bcl / 2}}};
+    double best = 0;
+    if ((rc = measure(best))) { cleanup(); return fail(rc, "autotuner: timing run failed"); }
+    for (Choice& c : choices) {
+        int keep = *c.field;
+        for (int v : c.cands) {
+            if (v == keep) continue;
+            *c.field = v;
+            double ms = 0;
+            if ((rc = measure(ms))) { cleanup(); return fail(rc, "autotuner: timing run failed"); }
+            if (ms < best) {
+                best = ms;
+                keep = v;
+            }
+        }
+        *c.field = keep;
+    }
+    apply_tune(p);
+    p->tuned_ms = best;
+    cleanup();
+    return PAT_OK;
+}
+
+int autotune(pat_plan_s* p, const char* path)
+{
+    const std::string key = tune_key(p);
+    if (tune_lookup(p, path, key)) {
+        apply_tune(p);
+        p->tuned = 2;
+        return PAT_OK;
+    }
+    int rc = (p->H.P.dt == PAT_F64) ? tune_search<double, 13>(p, p->dd) : tune_search<float, 6>(p, p->df);
+    if (rc) return rc;
+    p->tuned = 1;
+    tune_store(p, path, key);
+    return PAT_OK;
+}
+
 int lds_ok(const pat::Params& P, std::string& err)
 {
     size_t cs = (P.dt == PAT_F64) ? 16 : 8;
@@ -1103,9 +1627,18 @@ int lds_ok(const pat::Params& P, std::string& err)
     return PAT_OK;
 }
 
-void fill_info(const pat::Params& P, pat_plan_info* info, size_t ws_img, size_t table_bytes)
+void fill_info(const pat::Params& P, pat_plan_info* info, size_t ws_img, size_t table_bytes, const pat_plan_s* p)
 {
     std::memset(info, 0, sizeof(*info));
+    if (p) {
+        info->tune_fft_radix_log2 = p->fft_lr;
+        info->tune_cols_per_block = p->cols_cw;
+        info->tune_dct_cols_per_block = p->dct_cw;
+        info->tune_ring_images = p->ring_g;
+        info->tune_spread_images = p->spread_bc;
+        info->tuned = p->tuned;
+        info->tuned_ms = p->tuned_ms;
+    }
     info->n = P.n; info->m = P.m; info->nt = P.nt; info->m_full = P.mf;
     info->grid = P.Ng; info->stencil = P.w; info->rings = P.L; info->dct_half = P.M;
     info->kmax = P.K; info->kpad = P.Kp; info->klow = P.klow; info->lcorr = P.lcorr;
@@ -1162,13 +1695,13 @@ int pat_plan_query(const pat_geometry* g, pat_dtype dt, pat_plan_info* info)
     if (rc) return fail(rc, err);
     if ((rc = lds_ok(tmp.H.P, err))) return fail(rc, err);
     layout(&tmp);
-    fill_info(tmp.H.P, info, tmp.ws_img, 0);
+    default_tune(&tmp);
+    fill_info(tmp.H.P, info, tmp.ws_img, 0, &tmp);
     return PAT_OK;
 }
 
 int pat_plan_create(pat_plan* out, const pat_geometry* g, pat_dtype dt, int max_batch, const char* tuning_cache_path)
 {
-    (void)tuning_cache_path;
     if (!out) return fail(PAT_EINVAL, "pat_plan_create: out is NULL");
     *out = nullptr;
     if (!g) return fail(PAT_EINVAL, "pat_plan_create: geometry is NULL");
@@ -1181,6 +1714,7 @@ int pat_plan_create(pat_plan* out, const pat_geometry* g, pat_dtype dt, int max_
     if (p->H.P.w != (dt == PAT_F64 ? 13 : 6)) return fail(PAT_EUNSUPPORTED, "stencil width does not match the compiled kernels");
     p->max_batch = max_batch;
     layout(p.get());
+    default_tune(p.get());
     if (hipGetDevice(&p->device) != hipSuccess) return fail(PAT_EHIP, "pat_plan_create: no HIP device");
     rc = (dt == PAT_F64) ? upload<double>(p.get(), p->dd) : upload<float>(p.get(), p->df);
     if (rc) {
@@ -1191,8 +1725,65 @@ int pat_plan_create(pat_plan* out, const pat_geometry* g, pat_dtype dt, int max_
         for (void* a : p->allocs) (void)hipFree(a);
         return fail(PAT_EHIP, "pat_plan_create: device synchronisation failed");
     }
+    if (tuning_cache_path && tuning_cache_path[0]) {
+        if ((rc = autotune(p.get(), tuning_cache_path))) {
+            for (void* a : p->allocs) (void)hipFree(a);
+            return rc;
+        }
+    }
     *out = p.release();
     return PAT_OK;
+}
+
+struct pat_group_s {
+    std::vector<pat_plan_s*> plans;
+    bool f64 = false;
+};
+
+int pat_group_create(pat_group* out, int count, const pat_plan* plans)
+{
+    if (!out) return fail(PAT_EINVAL, "pat_group_create: out is NULL");
+    *out = nullptr;
+    if (!plans || count < 1) return fail(PAT_EINVAL, "pat_group_create: need at least one plan");
+    if (count > GROUP_MAX) return fail(PAT_EUNSUPPORTED, "pat_group_create: more plans than a group holds");
+    std::unique_ptr<pat_group_s> g(new pat_group_s());
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i]) return fail(PAT_EINVAL, "pat_group_create: NULL plan");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return fail(PAT_EINVAL, "pat_group_create: a plan appears twice");
+        const bool f64 = plans[i]->H.P.dt == PAT_F64;
+        if (i > 0 && f64 != g->f64) return fail(PAT_EINVAL, "pat_group_create: plans of different precision");
+        if (i > 0 && plans[i]->device != g->plans[0]->device) return fail(PAT_EINVAL, "pat_group_create: plans on different devices");
+        g->f64 = f64;
+        g->plans.push_back(plans[i]);
+    }
+    *out = g.release();
+    return PAT_OK;
+}
+
+int pat_group_destroy(pat_group g)
+{
+    if (!g) return fail(PAT_EINVAL, "pat_group_destroy: NULL group");
+    delete g;
+    return PAT_OK;
+}
+
+int pat_group_forward(pat_group g, const int* batch, const void* const* f, void* const* gout, void* const* ws,
+                      void* stream)
+{
+    if (!g || !batch || !f || !gout || !ws) return fail(PAT_EINVAL, "pat_group_forward: null argument");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return g->f64 ? group_run<double, 13>(g->plans, false, batch, f, gout, ws, st)
+                  : group_run<float, 6>(g->plans, false, batch, f, gout, ws, st);
+}
+
+int pat_group_adjoint(pat_group g, const int* batch, const void* const* gin, void* const* f, void* const* ws,
+                      void* stream)
+{
+    if (!g || !batch || !gin || !f || !ws) return fail(PAT_EINVAL, "pat_group_adjoint: null argument");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return g->f64 ? group_run<double, 13>(g->plans, true, batch, gin, f, ws, st)
+                  : group_run<float, 6>(g->plans, true, batch, gin, f, ws, st);
 }
 
 int pat_plan_destroy(pat_plan p)
@@ -1207,7 +1798,7 @@ int pat_plan_destroy(pat_plan p)
 int pat_plan_get_info(pat_plan p, pat_plan_info* info)
 {
     if (!p || !info) return fail(PAT_EINVAL, "pat_plan_get_info: null argument");
-    fill_info(p->H.P, info, p->ws_img, p->table_bytes);
+    fill_info(p->H.P, info, p->ws_img, p->table_bytes, p);
     return PAT_OK;
 }
 

@@ -16,6 +16,7 @@
 // deep-learning convention).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 
@@ -325,20 +326,52 @@ __global__ __launch_bounds__(NT) void pack_weights(const float* w, int cout, int
     dst[i] = to_bf16(v);
 }
 
+// Squared L2 norm of the gradient, two deterministic stages: per-block FP64
+// partial sums, then one block adds them in a fixed order into *out.
+__global__ __launch_bounds__(NT) void sumsq_partial(long count, const float* g, double* part)
+{
+    __shared__ double red[NT];
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * NT + threadIdx.x; i < count; i += (long)gridDim.x * NT) acc += (double)g[i] * g[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = NT / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(NT) void sumsq_final(const double* part, int nparts, double* out)
+{
+    __shared__ double red[NT];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += NT) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = NT / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
 // Adam (bias-corrected moments) with a cosine-decayed step size; the step
 // counter lives on the device so that a captured training step can be
-// replayed unchanged.  t = *step + 1 on entry.
+// replayed unchanged.  t = *step + 1 on entry.  With gsq != null the
+// gradient is first scaled by min(1, clip / ||g||), ||g||^2 = *gsq.
 __global__ __launch_bounds__(NT) void adam_step(long count, float* p, const float* g, float* m, float* v,
                                                 const int* step, float lr0, float lr_min, int total, float b1,
-                                                float b2, float eps)
+                                                float b2, float eps, const double* gsq, float clip)
 {
     const int t = *step + 1;
+    const float gs = (gsq && *gsq > (double)clip * clip) ? (float)(clip / sqrt(*gsq)) : 1.f;
     const float frac = fminf(1.f, (float)(t - 1) / (float)(total > 1 ? total - 1 : 1));
     const float lr = lr_min + 0.5f * (lr0 - lr_min) * (1.f + cosf(3.14159265358979f * frac));
     const float c1 = 1.f / (1.f - powf(b1, (float)t));
     const float c2 = 1.f / (1.f - powf(b2, (float)t));
     for (long i = (long)blockIdx.x * NT + threadIdx.x; i < count; i += (long)gridDim.x * NT) {
-        const float gi = g[i];
+        const float gi = g[i] * gs;
         const float mi = b1 * m[i] + (1.f - b1) * gi;
         const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
         m[i] = mi;
@@ -521,19 +554,31 @@ int pat_plane_sum(long count, const void* g, void* partials, int nblocks, void* 
 }
 
 int pat_adam(long count, void* param, const void* grad, void* m, void* v, void* step, double lr, double lr_min,
-             int total_steps, double beta1, double beta2, double eps, void* stream)
+             int total_steps, double beta1, double beta2, double eps, double clip, void* scratch, void* stream)
 {
     if (!param || !grad || !m || !v || !step || count < 1 || total_steps < 1 || !(lr >= 0) || !(lr_min >= 0) ||
-        !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0)) {
+        !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0) || !(clip >= 0) ||
+        (clip > 0 && !scratch)) {
         pat::set_error("pat_adam: bad arguments");
         return PAT_EINVAL;
     }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     long blocks = (count + NT - 1) / NT;
     if (blocks > 4096) blocks = 4096;
+    double* gsq = nullptr;
+    if (clip > 0) {
+        constexpr int NPART = 64;
+        double* part = static_cast<double*>(scratch);
+        gsq = part + NPART;
+        sumsq_partial<<<(int)std::min<long>(blocks, NPART), NT, 0, st>>>(count, static_cast<const float*>(grad), part);
+        sumsq_final<<<1, NT, 0, st>>>(part, (int)std::min<long>(blocks, NPART), gsq);
+        int rc = status("sumsq");
+        if (rc) return rc;
+    }
     adam_step<<<(int)blocks, NT, 0, st>>>(count, static_cast<float*>(param), static_cast<const float*>(grad),
                                           static_cast<float*>(m), static_cast<float*>(v), static_cast<const int*>(step),
-                                          (float)lr, (float)lr_min, total_steps, (float)beta1, (float)beta2, (float)eps);
+                                          (float)lr, (float)lr_min, total_steps, (float)beta1, (float)beta2, (float)eps,
+                                          gsq, (float)clip);
     int rc = status("adam_step");
     if (rc) return rc;
     step_increment<<<1, 64, 0, st>>>(static_cast<int*>(step));

@@ -9,6 +9,8 @@
 // (Neumann); div_h is minus its adjoint, so <grad_h f, p> = -<f, div_h p>.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <string>
 
@@ -88,6 +90,58 @@ __global__ __launch_bounds__(NT) void k_primal(int B, int n, T* f, T* fbar, cons
         if (support) v *= support[i];
         f[i] = v;
         fbar[i] = v + theta * (v - f_old);
+    }
+}
+
+// Deterministic inner product, first stage: per-block partial sums of x*y
+// (FP64 accumulation), blocks = gridDim.x.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_dot_partial(long count, const T* x, const T* y, double* part)
+{
+    __shared__ double red[NT];
+    double acc = 0.0;
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < count; i += (long)gridDim.x * NT)
+        acc += (double)x[i] * (double)y[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = NT / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// second stage: out[0] = sum of nparts partials (one block)
+__global__ __launch_bounds__(NT) void k_dot_final(const double* part, int nparts, double* out)
+{
+    __shared__ double red[NT];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += NT) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = NT / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// x *= 1 / sqrt(*ss) (ss on the device)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_scale_rsqrt(long count, T* x, const double* ss)
+{
+    const T s = (T)(1.0 / sqrt(*ss > 0.0 ? *ss : 1.0));
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < count; i += (long)gridDim.x * NT) x[i] *= s;
+}
+
+// deterministic start vector: a counter-based hash of the index mapped to [-1, 1)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_hash_fill(long count, T* x, unsigned seed)
+{
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < count; i += (long)gridDim.x * NT) {
+        unsigned v = (unsigned)i * 0x9E3779B9u ^ seed;
+        v ^= v >> 16; v *= 0x85EBCA6Bu; v ^= v >> 13; v *= 0xC2B2AE35u; v ^= v >> 16;
+        x[i] = (T)((double)v * (2.0 / 4294967296.0) - 1.0);
     }
 }
 
@@ -190,6 +244,74 @@ int pat_cp_primal(pat_plan p, int B, void* f, void* fbar, const void* Astar_q, c
                                                          (const float*)pgrad, (float)tau, (float)theta, (float)(1.0 / h),
                                                          (const float*)support);
     return launch_status("pat_cp_primal");
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+int opnorm_run(pat_plan p, int n, int nt, int m, int iters, double* norm, void* ws, hipStream_t st)
+{
+    const long fc = (long)n * n, gc = (long)nt * m;
+    T *f = nullptr, *u = nullptr, *g = nullptr;
+    double *part = nullptr, *scal = nullptr;
+    constexpr int NPART = 256;
+    int rc = PAT_OK;
+    auto cleanup = [&]() {
+        if (f) (void)hipFree(f);
+        if (u) (void)hipFree(u);
+        if (g) (void)hipFree(g);
+        if (part) (void)hipFree(part);
+        if (scal) (void)hipFree(scal);
+    };
+    if (hipMalloc(&f, sizeof(T) * fc) != hipSuccess || hipMalloc(&u, sizeof(T) * fc) != hipSuccess ||
+        hipMalloc(&g, sizeof(T) * gc) != hipSuccess || hipMalloc(&part, sizeof(double) * NPART) != hipSuccess ||
+        hipMalloc(&scal, sizeof(double) * 2) != hipSuccess) {
+        cleanup();
+        pat::set_error("pat_opnorm_estimate: allocation failed");
+        return PAT_ENOMEM;
+    }
+    const int gb = std::min(NPART, grid_for(fc));
+    k_hash_fill<T><<<grid_for(fc), NT, 0, st>>>(fc, f, 12345u);
+    for (int it = 0; it < iters && !rc; ++it) {
+        // f /= ||f||;  u = A* A f;  lambda = <f, u> / <f, f> (the X weights cancel)
+        k_dot_partial<T><<<gb, NT, 0, st>>>(fc, f, f, part);
+        k_dot_final<<<1, NT, 0, st>>>(part, gb, scal);
+        k_scale_rsqrt<T><<<grid_for(fc), NT, 0, st>>>(fc, f, scal);
+        if ((rc = launch_status("pat_opnorm_estimate"))) break;
+        if ((rc = pat_forward(p, f, g, ws, st))) break;
+        if ((rc = pat_adjoint(p, g, u, ws, st))) break;
+        k_dot_partial<T><<<gb, NT, 0, st>>>(fc, f, u, part);
+        k_dot_final<<<1, NT, 0, st>>>(part, gb, scal + 1);
+        if ((rc = launch_status("pat_opnorm_estimate"))) break;
+        std::swap(f, u);
+    }
+    double lam = 0.0;
+    if (!rc) {
+        if (hipMemcpyAsync(&lam, scal + 1, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            pat::set_error("pat_opnorm_estimate: read-back failed");
+            rc = PAT_EHIP;
+        }
+    }
+    cleanup();
+    if (!rc) *norm = std::sqrt(std::max(lam, 0.0));
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pat_opnorm_estimate(pat_plan p, int iters, double* norm, void* ws, void* stream)
+{
+    int n, nt, m, f64;
+    double h;
+    if (!p || !norm || !ws || iters < 1) { pat::set_error("pat_opnorm_estimate: bad arguments"); return PAT_EINVAL; }
+    if (pat::plan_image_size(p, &n, &nt, &m, &h, &f64)) return PAT_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return f64 ? opnorm_run<double>(p, n, nt, m, iters, norm, ws, st) : opnorm_run<float>(p, n, nt, m, iters, norm, ws, st);
 }
 
 }  // extern "C"

@@ -254,10 +254,11 @@ class LPD:
             self.adam_m = torch.zeros_like(self.params)
             self.adam_v = torch.zeros_like(self.params)
             self.step_count = torch.zeros(1, dtype=torch.int32, device=dev)
+            self.adam_scratch = torch.zeros(128, dtype=torch.float64, device=dev)
         plan.workspace(B)
         self.graph_fwd = None
         self.graph_train = None
-        self.opt = dict(lr=1e-3, lr_min=1e-5, total=1000, beta1=0.9, beta2=0.999, eps=1e-8)
+        self.opt = dict(lr=1e-3, lr_min=1e-5, total=1000, beta1=0.9, beta2=0.99, eps=1e-8, clip=1.0)
 
     # ---- launch sequences -------------------------------------------------
     def _st(self):
@@ -323,7 +324,7 @@ class LPD:
         o = self.opt
         _check(self.lib.pat_adam(self.nparams, _p(self.params), _p(self.grads), _p(self.adam_m), _p(self.adam_v),
                                  _p(self.step_count), o["lr"], o["lr_min"], int(o["total"]), o["beta1"], o["beta2"],
-                                 o["eps"], self._st()), "pat_adam")
+                                 o["eps"], o["clip"], _p(self.adam_scratch), self._st()), "pat_adam")
 
     def train_step(self):
         self.forward_pass()
@@ -421,10 +422,11 @@ def input_scales(plan: Plan, ds: dict, count: int = 64):
 
 
 def train(net: LPD, ds: dict, steps: int, lr: float = 1e-3, lr_min: float = 1e-5, seed: int = 0,
-          log_every: int = 50, log=None):
-    """Adam with cosine decay over ``steps`` captured training steps, batches
-    drawn as epochs of a seeded permutation.  Returns [(step, loss)]."""
-    net.opt.update(lr=lr, lr_min=lr_min, total=steps)
+          log_every: int = 50, log=None, clip: float = 1.0):
+    """Adam with cosine decay and global-norm gradient clipping over ``steps``
+    captured training steps, batches drawn as epochs of a seeded permutation.
+    Returns [(step, loss)]."""
+    net.opt.update(lr=lr, lr_min=lr_min, total=steps, clip=clip)
     N, B = ds["f"].shape[0], net.B
     rng = np.random.default_rng(seed)
     order, pos = rng.permutation(N), 0

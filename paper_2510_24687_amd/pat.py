@@ -35,14 +35,18 @@ class PlanInfo(ctypes.Structure):
                 ("klow", ctypes.c_int), ("lcorr", ctypes.c_int), ("ring_points", ctypes.c_int),
                 ("max_ring", ctypes.c_int), ("spread_tiles", ctypes.c_int),
                 ("dlam", ctypes.c_double), ("period", ctypes.c_double), ("lambda_max", ctypes.c_double),
-                ("ws_per_image", ctypes.c_size_t), ("table_bytes", ctypes.c_size_t)]
+                ("ws_per_image", ctypes.c_size_t), ("table_bytes", ctypes.c_size_t),
+                ("tune_fft_radix_log2", ctypes.c_int), ("tune_cols_per_block", ctypes.c_int),
+                ("tune_dct_cols_per_block", ctypes.c_int), ("tune_ring_images", ctypes.c_int),
+                ("tune_spread_images", ctypes.c_int), ("tuned", ctypes.c_int), ("tuned_ms", ctypes.c_double)]
 
 
 EXPORTED = ["pat_plan_create", "pat_plan_query", "pat_plan_destroy", "pat_plan_get_info",
             "pat_workspace_size", "pat_forward", "pat_adjoint", "pat_forward_batched",
             "pat_adjoint_batched", "pat_adjoint_scale", "pat_status_string", "pat_last_error",
             "pat_debug_bessel", "pat_axpby", "pat_conv_packed_size", "pat_conv_pack_weights", "pat_conv3x3",
-            "pat_conv_wgrad_partials", "pat_conv3x3_wgrad", "pat_prelu_backward", "pat_plane_sum", "pat_adam"]
+            "pat_conv_wgrad_partials", "pat_conv3x3_wgrad", "pat_prelu_backward", "pat_plane_sum", "pat_adam", "pat_opnorm_estimate",
+            "pat_group_create", "pat_group_destroy", "pat_group_forward", "pat_group_adjoint"]
 
 
 class ConvDesc(ctypes.Structure):
@@ -91,7 +95,13 @@ def load():
     lib.pat_conv3x3_wgrad.argtypes = [cd, vp, i, vp, vp, i, vp]
     lib.pat_prelu_backward.argtypes = [L, vp, vp, vp, vp, vp, i, vp, i, vp]
     lib.pat_plane_sum.argtypes = [L, vp, vp, i, vp, i, vp]
-    lib.pat_adam.argtypes = [L, vp, vp, vp, vp, vp, D, D, i, D, D, D, vp]
+    lib.pat_adam.argtypes = [L, vp, vp, vp, vp, vp, D, D, i, D, D, D, D, vp, vp]
+    lib.pat_opnorm_estimate.argtypes = [vp, i, ctypes.POINTER(D), vp, vp]
+    lib.pat_group_create.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp)]
+    lib.pat_group_destroy.argtypes = [vp]
+    ip, vpp = ctypes.POINTER(i), ctypes.POINTER(vp)
+    lib.pat_group_forward.argtypes = [vp, ip, vpp, vpp, vpp, vp]
+    lib.pat_group_adjoint.argtypes = [vp, ip, vpp, vpp, vpp, vp]
     _lib = lib
     return lib
 
@@ -140,7 +150,8 @@ class Plan:
     torch tensors on the GPU, shaped (n, n) / (nt, m) or batched (B, n, n) /
     (B, nt, m), and return new tensors (or fill ``out``)."""
 
-    def __init__(self, geom: dict, dtype=None, max_batch: int = 1, device=None):
+    def __init__(self, geom: dict, dtype=None, max_batch: int = 1, device=None, tuning_cache: Optional[str] = None):
+        """tuning_cache: path of the autotuner's cache file (None: default launch shapes)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libpat needs a GPU: torch.cuda.is_available() is False")
@@ -159,7 +170,8 @@ class Plan:
         with torch.cuda.device(self.device):
             _check(lib.pat_plan_create(ctypes.byref(h), ctypes.byref(make_geometry(self.geom)),
                                        PAT_F64 if self.dtype == torch.float64 else PAT_F32,
-                                       self.max_batch, None), "pat_plan_create")
+                                       self.max_batch, tuning_cache.encode() if tuning_cache else None),
+                   "pat_plan_create")
         self._h = h
         info = PlanInfo()
         _check(lib.pat_plan_get_info(h, ctypes.byref(info)), "pat_plan_get_info")
@@ -227,6 +239,14 @@ class Plan:
                    "pat_adjoint_batched")
         return f[0] if single and out is None else f
 
+    def opnorm(self, iters: int = 30) -> float:
+        """||A|| from the X to the Y inner products (power iteration in the library)."""
+        out = ctypes.c_double()
+        ws = self.workspace(1)
+        _check(self._lib.pat_opnorm_estimate(self._h, int(iters), ctypes.byref(out), ctypes.c_void_p(ws.data_ptr()),
+                                             self._stream()), "pat_opnorm_estimate")
+        return out.value
+
     def scale_(self, x, a: float):
         """x *= a in place (library kernel; x contiguous, plan dtype)."""
         if not x.is_contiguous() or x.dtype != self.dtype:
@@ -238,3 +258,49 @@ class Plan:
     def transpose(self, g, out=None):
         """Euclidean transpose A^T = A*/s."""
         return self.scale_(self.adjoint(g, out=out), 1.0 / self.adjoint_scale)
+
+
+class Group:
+    """Plans of different image sizes (same precision) whose forward / adjoint
+    chains run as one grouped launch per stage (pat_group_*)."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        lib = load()
+        self._lib = lib
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib.pat_group_create(ctypes.byref(h), len(self.plans), arr), "pat_group_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and self._lib is not None:
+            self._lib.pat_group_destroy(h)
+            self._h = None
+
+    def _run(self, fn, ins, outs, tails_in, what):
+        n = len(self.plans)
+        if len(ins) != n or len(outs) != n:
+            raise ValueError("one input and one output per plan")
+        batch = (ctypes.c_int * n)()
+        pin, pout, pws = (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)()
+        for i, (p, x, y) in enumerate(zip(self.plans, ins, outs)):
+            for t in (x, y):
+                if not t.is_contiguous() or t.dtype != p.dtype or t.device.type != "cuda":
+                    raise TypeError("expected contiguous CUDA tensors of the plan's dtype")
+            if tuple(x.shape[1:]) != tails_in(p) or x.shape[0] != y.shape[0]:
+                raise ValueError("shape mismatch for plan %d" % i)
+            batch[i] = x.shape[0]
+            pin[i], pout[i] = x.data_ptr(), y.data_ptr()
+            pws[i] = p.workspace(x.shape[0]).data_ptr()
+        _check(fn(self._h, batch, pin, pout, pws, self.plans[0]._stream()), what)
+        return outs
+
+    def forward(self, fs, outs):
+        """outs[i] = A_i fs[i] (fs[i]: (B_i, n_i, n_i), outs[i]: (B_i, nt_i, m_i))."""
+        return self._run(self._lib.pat_group_forward, fs, outs, lambda p: (p.n, p.n), "pat_group_forward")
+
+    def adjoint(self, gs, outs):
+        """outs[i] = A*_i gs[i]."""
+        return self._run(self._lib.pat_group_adjoint, gs, outs, lambda p: (p.nt, p.m), "pat_group_adjoint")

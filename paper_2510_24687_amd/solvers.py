@@ -25,7 +25,7 @@ from typing import List, Optional
 
 import torch
 
-from .pat import Plan, load, _check
+from .pat import Group, Plan, load, _check
 
 _VP = ctypes.c_void_p
 
@@ -48,16 +48,8 @@ def _bind(lib):
 
 
 def opnorm(plan: Plan, iters: int = 30, seed: int = 0) -> float:
-    """||A||_{X->Y} by power iteration on A*A (X inner product h^2 sum)."""
-    gen = torch.Generator(device=plan.device).manual_seed(seed)
-    f = torch.randn((plan.n, plan.n), dtype=plan.dtype, device=plan.device, generator=gen)
-    lam = 0.0
-    for _ in range(iters):
-        f = f / torch.linalg.vector_norm(f)
-        a = plan.adjoint(plan.forward(f))
-        lam = float(torch.sum(a * f))
-        f = a
-    return math.sqrt(max(lam, 0.0))
+    """||A||_{X->Y} by power iteration on A*A (pat_opnorm_estimate)."""
+    return plan.opnorm(iters)
 
 
 def tv_norm_bound(plan: Plan) -> float:
@@ -90,12 +82,16 @@ class BatchedSolver:
     ``groups`` is a list of (plan, g, support) with g of shape (B, nt, m).
     """
 
-    def __init__(self, groups, method: str = "nnls", lam: float = 1e-3, opnorms=None):
+    def __init__(self, groups, method: str = "nnls", lam: float = 1e-3, opnorms=None, grouped: bool = False):
+        """grouped: run the operators of all plans as one grouped launch per
+        stage (pat_group_forward / pat_group_adjoint) instead of one launch
+        chain per plan."""
         if method not in ("nnls", "tv"):
             raise ValueError("method must be 'nnls' or 'tv'")
         self.method, self.lam = method, float(lam)
         self.lib = _bind(load())
         self.groups: List[_Group] = [_Group(p, g, s) for p, g, s in groups]
+        self.opgroup = Group([G.plan for G in self.groups]) if grouped else None
         self.norms = opnorms or [opnorm(G.plan) for G in self.groups]
         self.graph = None
         self.stream = torch.cuda.current_stream()
@@ -129,10 +125,36 @@ class BatchedSolver:
             _check(lib.pat_cp_primal(h, G.B, _ptr(G.f), _ptr(G.fbar), _ptr(G.grad), _ptr(G.p), G.tau, 1.0,
                                      _ptr(G.support), st), "pat_cp_primal")
 
+    def _updates(self, G: _Group, phase: int):
+        lib, P, st = self.lib, G.plan, _VP(torch.cuda.current_stream().cuda_stream)
+        h = P._h
+        if self.method == "nnls":
+            if phase == 0:
+                _check(lib.pat_axpby(h, G.Af.numel(), 1.0, _ptr(G.Af), -1.0, _ptr(G.g), _ptr(G.Af), st), "pat_axpby")
+            else:
+                _check(lib.pat_nnls_update(h, G.B, _ptr(G.f), _ptr(G.grad), G.tau, _ptr(G.support), st),
+                       "pat_nnls_update")
+        elif phase == 0:
+            _check(lib.pat_cp_dual_data(h, G.B, _ptr(G.q), _ptr(G.Af), _ptr(G.g), G.sigma, st), "pat_cp_dual_data")
+            _check(lib.pat_cp_dual_tv(h, G.B, _ptr(G.p), _ptr(G.fbar), G.sigma_tv, self.lam, st), "pat_cp_dual_tv")
+        else:
+            _check(lib.pat_cp_primal(h, G.B, _ptr(G.f), _ptr(G.fbar), _ptr(G.grad), _ptr(G.p), G.tau, 1.0,
+                                     _ptr(G.support), st), "pat_cp_primal")
+
     def step(self):
         """One iteration of every instance, launched eagerly."""
+        if self.opgroup is None:
+            for G in self.groups:
+                self._step_group(G)
+            return
+        src = [G.f if self.method == "nnls" else G.fbar for G in self.groups]
+        self.opgroup.forward(src, [G.Af for G in self.groups])
         for G in self.groups:
-            self._step_group(G)
+            self._updates(G, 0)
+        self.opgroup.adjoint([G.Af if self.method == "nnls" else G.q for G in self.groups],
+                             [G.grad for G in self.groups])
+        for G in self.groups:
+            self._updates(G, 1)
 
     def capture(self):
         """Capture one iteration of every instance in a HIP graph."""

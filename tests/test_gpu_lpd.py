@@ -216,22 +216,25 @@ def test_prelu_backward_and_bias_sums():
     assert abs(float(s) - 2 * v.sum()) < 1e-4 * np.abs(v).sum()
 
 
-def test_adam_matches_reference():
+@pytest.mark.parametrize("clip", [0.0, 30.0])
+def test_adam_matches_reference(clip):
     lib = pat.load()
     rng = np.random.default_rng(4)
     n = 5000
     p = f32(rng.standard_normal(n))
     pg, mg, vg = cuda32(p), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
     step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    scratch = torch.zeros(128, dtype=torch.float64, device="cuda")
     m, v, q = np.zeros(n), np.zeros(n), p.copy()
     for t in range(1, 6):
-        g = f32(rng.standard_normal(n))
+        g = f32(rng.standard_normal(n) * (1 + t))   # ||g|| ~ 70 (1 + t): clipped when clip = 30
         gg = cuda32(g)
         pat._check(lib.pat_adam(n, pg.data_ptr(), gg.data_ptr(), mg.data_ptr(), vg.data_ptr(), step.data_ptr(),
-                                1e-2, 1e-4, 8, 0.9, 0.999, 1e-8, st()), "adam")
-        q, m, v = OL.adam_reference(q, g, m, v, t, 1e-2, 1e-4, 8)
+                                1e-2, 1e-4, 8, 0.9, 0.999, 1e-8, clip, scratch.data_ptr(), st()), "adam")
+        q, m, v = OL.adam_reference(q, g, m, v, t, 1e-2, 1e-4, 8, clip=clip)
     assert int(step) == 5
     assert np.max(np.abs(pg.cpu().numpy() - q)) < 1e-6
+    assert rel(mg.cpu().numpy(), m) < 1e-5
 
 
 def _tiny_setup(K=3):

@@ -72,3 +72,22 @@ def test_fp64_nnls_iterates_match_oracle_driven_nnls():
         sol.step()
     f_g = sol.groups[0].f[0].cpu().numpy()
     assert np.linalg.norm(f_g - f_o) / np.linalg.norm(f_o) < 1e-8
+
+
+def test_opnorm_estimate_is_the_operator_norm():
+    """pat_opnorm_estimate against ||A||_{X->Y} = sqrt(s) sigma_max(A) from the
+    singular values of the oracle's dense matrix (n = 24, 180-degree arc).
+    The power iteration approaches it from below; the top two singular values
+    differ by 0.1 %, so 150 steps leave ~1e-5."""
+    geom = P.top_arc(24, 32, 32, 180.0)
+    n = 24
+    cols = []
+    for i in range(n * n):
+        e = np.zeros(n * n)
+        e[i] = 1.0
+        cols.append(O.forward(geom, e.reshape(n, n)).ravel())
+    exact = math.sqrt(O.adjoint_scale(geom)) * np.linalg.svd(np.array(cols).T, compute_uv=False)[0]
+    est = pat.Plan(geom, torch.float64).opnorm(150)
+    assert exact * (1 - 1e-4) < est <= exact * (1 + 1e-12)
+    est32 = pat.Plan(geom, torch.float32).opnorm(150)
+    assert exact * (1 - 1e-4) < est32 < exact * (1 + 1e-5)

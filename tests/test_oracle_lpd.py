@@ -125,3 +125,11 @@ def test_adam_reference_closed_forms():
     vh = g * g / (1 - 0.999 ** 6)
     assert np.allclose(p - qa, frac_mid * mh / np.sqrt(vh), rtol=1e-9)
     assert math.isclose(0.5 * (1e-2 - 1e-4) * (1 + math.cos(math.pi * 0.5)) + 1e-4, frac_mid)
+
+
+def test_adam_reference_clipping():
+    g = np.array([3.0, 4.0])                      # ||g|| = 5
+    _, m1, v1 = OL.adam_reference(np.zeros(2), g, np.zeros(2), np.zeros(2), 1, 1e-2, 1e-4, 10, clip=1.0)
+    assert np.allclose(m1, 0.1 * g / 5.0) and np.allclose(v1, 0.001 * (g / 5.0) ** 2)
+    _, m2, _ = OL.adam_reference(np.zeros(2), g, np.zeros(2), np.zeros(2), 1, 1e-2, 1e-4, 10, clip=10.0)
+    assert np.allclose(m2, 0.1 * g)               # below the threshold: unchanged
