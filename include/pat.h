@@ -232,10 +232,11 @@ int pat_cp_primal(pat_plan p, int B, void* f, void* fbar, const void* Astar_q, c
 /* ---- Learned primal-dual reconstructor (Sec. 4.2.1, eqs. eq:LPD_dual,
  * eq:LPD_primal, loss eq:emp_loss) -----------------------------------------
  * The dual and primal networks are stacks of 3x3 convolutions (stride 1,
- * zero padding 1, cross-correlation) between FP32 tensors of two layouts:
- *   planar: up to 4 separate B x H x W planes (batch stride H*W), e.g. the
- *           LPD inputs q, A f, y or f, A* q, and the 1-channel outputs;
- *   NHWC:   B x H x W x 32 hidden feature maps (channel fastest).
+ * zero padding 1, cross-correlation) between tensors of two layouts:
+ *   planar: up to 4 separate FP32 B x H x W planes (batch stride H*W), e.g.
+ *           the LPD inputs q, A f, y or f, A* q, and the 1-channel outputs;
+ *   NHWC:   B x H x W x 32 hidden feature maps or their gradients, channel
+ *           fastest, stored as bfloat16 (the precision the matrix cores take).
  * Operands are rounded to bfloat16 (nearest-even) and multiplied on the
  * matrix cores with FP32 accumulation.  Weights are FP32 masters
  * w[cout][cin][3][3] packed by pat_conv_pack_weights.  All calls are
@@ -248,15 +249,26 @@ typedef struct {
     int cin, cout;        /* planar: 1..4; NHWC: 32                                */
     int in_planar;        /* input layout                                          */
     int out_planar;       /* output layout                                         */
-    const void* in[4];    /* planar: in[0..cin-1]; NHWC: in[0]                      */
-    void* out[4];         /* planar: out[c] (NULL = channel not written); NHWC: out[0] */
+    const void* in[4];    /* planar: FP32 in[0..cin-1]; NHWC: bf16 in[0]            */
+    void* out[4];         /* planar: FP32 out[c] (NULL = not written); NHWC: bf16 out[0] */
     const void* residual[4]; /* planar outputs: added after scaling (NULL = none)   */
     float scale[4];       /* planar input: plane c is multiplied by scale[c];
                              planar output: out[c] = residual[c] + scale[c] * (conv + bias) */
     const void* weight;   /* packed bf16 weights (pat_conv_pack_weights)            */
     const void* bias;     /* FP32 [cout] or NULL                                    */
     const void* alpha;    /* FP32 [cout] PReLU slopes or NULL (NHWC outputs only)   */
-    void* pre;            /* NHWC outputs: copy of the pre-activation, or NULL      */
+    void* pre;            /* forward, NHWC outputs: FP32 NHWC copy of the
+                             pre-activation, or NULL                                */
+    const void* bwd_pre;  /* non-NULL selects the backward epilogue (NHWC output):
+                             the convolution is an input gradient ga, and the
+                             output is gx = ga * (bwd_pre > 0 ? 1 : alpha), the
+                             gradient before the PReLU whose FP32 pre-activation
+                             is bwd_pre; grad_bias_alpha[0..31] (+)= sum gx and
+                             grad_bias_alpha[32..63] (+)= sum ga * bwd_pre *
+                             [bwd_pre <= 0] (the bias and slope gradients)      */
+    void* partials;       /* backward epilogue: pat_conv_bwd_partials floats      */
+    void* grad_bias_alpha;/* backward epilogue: 64 FP32 outputs                   */
+    int accumulate;       /* backward epilogue: 0 overwrite, 1 add               */
 } pat_conv_desc;
 
 /* Elements (bf16) of a packed weight array for an effective convolution with
@@ -270,10 +282,13 @@ long pat_conv_packed_size(int cout_e, int cin_e, int in_planar);
  * in_planar is the layout of the effective convolution's input. */
 int pat_conv_pack_weights(const void* w, int cout, int cin, int transpose, int in_planar, void* dst, void* stream);
 
-/* out = act(conv3x3(in) + bias) (NHWC out; act = PReLU if alpha, pre gets the
- * value before it) or out[c] = residual[c] + scale[c] (conv3x3(in) + bias)[c]
- * (planar out). */
+/* Forward epilogue: out = act(conv3x3(in) + bias) (NHWC out; act = PReLU if
+ * alpha, pre gets the value before it) or out[c] = residual[c] + scale[c]
+ * (conv3x3(in) + bias)[c] (planar out).  Backward epilogue: see bwd_pre. */
 int pat_conv3x3(const pat_conv_desc* d, void* stream);
+
+/* Floats of FP32 scratch the backward epilogue of pat_conv3x3 needs. */
+long pat_conv_bwd_partials(const pat_conv_desc* d);
 
 /* Floats of FP32 scratch pat_conv3x3_wgrad needs for this layer and chunking. */
 long pat_conv_wgrad_partials(const pat_conv_desc* d, int rows_per_chunk);
@@ -283,18 +298,10 @@ long pat_conv_wgrad_partials(const pat_conv_desc* d, int rows_per_chunk);
  * x+kx-1, ci] (scaled planar inputs as in the forward), with operands rounded
  * to bf16 and the sum taken per chunk of rows_per_chunk image rows on the
  * matrix cores, then over chunks in FP64 in a fixed order (deterministic).
- * grad_out has d's output layout; a planar grad_out needs cout == 1.
+ * grad_out has d's output layout (planar FP32 needs cout == 1; NHWC bf16).
  * accumulate = 0 overwrites grad_w, 1 adds to it. */
 int pat_conv3x3_wgrad(const pat_conv_desc* d, const void* grad_out, int rows_per_chunk, void* partials,
                       void* grad_w, int accumulate, void* stream);
-
-/* PReLU backward over npix NHWC 32-channel pixels: grad_pre = grad_act *
- * (pre > 0 ? 1 : alpha); grad_bias_alpha[0..31] (+)= sum grad_pre (the bias
- * gradient of the producing convolution), grad_bias_alpha[32..63] (+)= sum
- * grad_act * pre * [pre <= 0] (the slope gradient).  partials: 64 * nblocks
- * floats of scratch. */
-int pat_prelu_backward(long npix, const void* grad_act, const void* pre, const void* alpha, void* grad_pre,
-                       void* partials, int nblocks, void* grad_bias_alpha, int accumulate, void* stream);
 
 /* out[0] (+)= sum of count FP32 values (the bias gradient of a 1-channel
  * planar layer); partials: nblocks floats of scratch. */

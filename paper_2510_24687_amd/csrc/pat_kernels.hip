@@ -289,8 +289,10 @@ struct Dev {
     int M, log2M, L, K, Kp, klow, lcorr, npts;
     int logNmax;
     int colsCW, dctCW;
+    int dct_stash;              // 1: the cosine transform stashes its input columns in LDS
     int fft_lr;                 // largest FFT pass radix is 2^fft_lr (3 or 4)
     T beta, shift, half;        // half = Ng / (2 Lambda): grid cells per unit lambda
+    T beta_l2e;                 // beta * log2(e)
     T lamh;                     // h: u = lambda h cos(phi)
     T dlam, pre_scale, adj_scale;
     double mask_r2, a, h;       // mask test in double (same decision as the oracle)
@@ -315,13 +317,22 @@ __device__ __forceinline__ bool in_mask(const Dev<T>& d, int p, int q)
     return x * x + y * y <= d.mask_r2;
 }
 
-// exponential-of-semicircle kernel at offset `dd` cells
-template <typename T>
-__device__ __forceinline__ T es_w(T dd, T two_over_w, T beta)
+// exponential-of-semicircle kernel at offset `dd` cells:
+// exp(beta (sqrt(1 - z^2) - 1)), z = 2 dd / w, zero for |z| >= 1.  The FP32
+// form uses the hardware square root and base-2 exponential (about 1e-7
+// relative error, far below the FP32 operator's error); the gather and the
+// spread evaluate the same function, so A* stays the transpose of A.
+__device__ __forceinline__ double es_w(double dd, double two_over_w, double beta, double)
 {
-    T z = dd * two_over_w;
-    T s = T(1) - z * z;
-    return s > T(0) ? exp_t(beta * (sqrt_t(s) - T(1))) : T(0);
+    double z = dd * two_over_w;
+    double s = 1.0 - z * z;
+    return s > 0.0 ? exp(beta * (sqrt(s) - 1.0)) : 0.0;
+}
+__device__ __forceinline__ float es_w(float dd, float two_over_w, float, float beta_log2e)
+{
+    const float z = dd * two_over_w;
+    const float s = 1.f - z * z;
+    return s > 0.f ? __builtin_amdgcn_exp2f(beta_log2e * (__builtin_amdgcn_sqrtf(s) - 1.f)) : 0.f;
 }
 
 // Grid position, first taps and weights of half-ring sample si of ring l
@@ -364,8 +375,8 @@ __device__ __forceinline__ void point_taps(const Dev<T>& d, int p, Taps<T, WMAX>
     T tw_ = T(2) / T(WMAX);
 #pragma unroll
     for (int j = 0; j < WMAX; ++j) {
-        tp.wx[j] = es_w(x - T(tp.gx0 + j), tw_, d.beta);
-        tp.wy[j] = es_w(y - T(tp.gy0 + j), tw_, d.beta);
+        tp.wx[j] = es_w(x - T(tp.gx0 + j), tw_, d.beta, d.beta_l2e);
+        tp.wy[j] = es_w(y - T(tp.gy0 + j), tw_, d.beta, d.beta_l2e);
     }
     tp.ph = point_phase(d, x, y);
 }
@@ -526,17 +537,27 @@ __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-    int bx_, b;
-    bx_ = bk.x;
-    b = bk.y;
+    const int bx_ = bk.x, b = bk.y;
     const int CW = d.dctCW, k0 = bx_ * CW;
     const int M = d.M, logM = d.log2M;
     const cx<T>* ib = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(in) + (size_t)b * ws_img);
     cx<T>* ob = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(out) + (size_t)b * ws_img);
     // valid input indices x in [x_lo, x_hi), stored at row x - x_lo
     const int x_lo = adjoint ? 1 : 0, x_hi = adjoint ? d.nt + 1 : d.L;
+    const int nx = x_hi - x_lo;
     const int nout = adjoint ? d.L : d.nt;
     const int sh = d.logNmax - logM - 1;  // e^{i pi x/M} = conj(tw[x << sh])
+    // With enough LDS the block's input columns are read from HBM once into a
+    // stash (column-major, CW x nx) and both parities are formed from it.
+    cx<T>* stash = buf + CW * M;
+    if (d.dct_stash) {
+        for (int i = threadIdx.x; i < CW * nx; i += blockDim.x) {
+            const int row = i / CW, c = i - row * CW;
+            const int k = k0 + c;
+            stash[c * nx + row] = k < d.Kp ? ib[(size_t)row * d.Kp + k] : cx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+    }
     for (int r = 0; r < 2; ++r) {
         for (int i = threadIdx.x; i < CW * M; i += blockDim.x) {
             const int xs = i / CW, c = i - xs * CW;  // slot xs = x mod M
@@ -545,7 +566,7 @@ __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<
             if (k < d.Kp) {
                 for (int x = xs; x < x_hi; x += M) {
                     if (x < x_lo) continue;
-                    cx<T> v = ib[(size_t)(x - x_lo) * d.Kp + k];
+                    cx<T> v = d.dct_stash ? stash[c * nx + (x - x_lo)] : ib[(size_t)(x - x_lo) * d.Kp + k];
                     if (r) v = cmul(v, conjg(d.tw[x << sh]));
                     acc = acc + v;
                 }
@@ -554,11 +575,15 @@ __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<
         }
         __syncthreads();
         lds_fft(buf, logM, CW, M, d.tw, d.logNmax, true, d.fft_lr);
-        for (int i = threadIdx.x; i < CW * nout; i += blockDim.x) {
-            const int orow = i / CW, c = i - orow * CW;
+        // output rows of parity r only: y = orow (+ 1 in the forward), y = 2 y' + r
+        const int o0 = adjoint ? r : 1 - r;
+        const int nr = o0 < nout ? (nout - o0 + 1) / 2 : 0;
+        for (int i = threadIdx.x; i < CW * nr; i += blockDim.x) {
+            const int j = i / CW, c = i - j * CW;
+            const int orow = o0 + 2 * j;
             const int k = k0 + c;
+            if (k >= d.Kp) continue;
             const int y = adjoint ? orow : orow + 1;
-            if (k >= d.Kp || (y & 1) != r) continue;
             const int yp = (y - r) >> 1;
             const int ypp = (M - yp - r) & (M - 1);
             ob[(size_t)orow * d.Kp + k] = (buf[c * M + yp] + buf[c * M + ypp]) * T(0.5);
@@ -724,42 +749,52 @@ __global__ __launch_bounds__(NT) void lowk_adj(Dev<T> d, const cx<T>* G, cx<T>* 
 // multiplied by the conjugate point phase, for the batched spread below.
 template <typename T, int WMAX>
 __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<T>* V, const cx<T>* Ulow, cx<T>* Pol, int B,
-                                               size_t ws_img)
+                                              int G, size_t ws_img)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     // no XCD renumbering here: contiguous ranges of rings would unbalance the XCDs
-    const int b = bk.x, l = bk.y;
+    const int grp = bk.x, l = bk.y;
+    const int b0 = grp * G, nb = min(G, B - b0);
     const int N = d.ringN[l], logN = d.ringLog[l], Kl = d.ringK[l];
-    const cx<T>* Vb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(V) + (size_t)b * ws_img);
-    const cx<T>* Ub = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(Ulow) + (size_t)b * ws_img);
     const T invN = T(1) / T(N);
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
-        cx<T> v = {T(0), T(0)};
-        if (k <= Kl) {
-            v = mul_ipow(Vb[(size_t)l * d.Kp + k] * d.Tb[(size_t)l * d.Kp + k], (4 - (k & 3)) & 3);
-            if (l < d.lcorr && k <= d.klow) v = v + Ub[(size_t)l * (d.klow + 1) + k] * invN;
+    for (int i = 0; i < nb; ++i) {
+        const cx<T>* Vb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(V) + (size_t)(b0 + i) * ws_img);
+        const cx<T>* Ub = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(Ulow) + (size_t)(b0 + i) * ws_img);
+        cx<T>* bi = buf + i * N;
+        for (int k = threadIdx.x; k < N; k += blockDim.x) {
+            cx<T> v = {T(0), T(0)};
+            if (k <= Kl) {
+                v = mul_ipow(Vb[(size_t)l * d.Kp + k] * d.Tb[(size_t)l * d.Kp + k], (4 - (k & 3)) & 3);
+                if (l < d.lcorr && k <= d.klow) v = v + Ub[(size_t)l * (d.klow + 1) + k] * invN;
+            }
+            bi[k] = v;
         }
-        buf[k] = v;
     }
     __syncthreads();
-    lds_fft(buf, logN, 1, 0, d.tw, d.logNmax, true, d.fft_lr);
+    const int per_call = max(1, min(nb, FFT_BLOCK_POINTS >> logN));
+    for (int i = 0; i < nb; i += per_call)
+        lds_fft(buf + i * N, logN, min(per_call, nb - i), N, d.tw, d.logNmax, true, d.fft_lr);
     const int off = d.ringOff[l];
     for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
         const int s = si - N / 4;
-        // transpose of the conjugate-symmetric fill, then of the point phase
-        const cx<T> uf = buf[s & (N - 1)] + conjg(buf[(s + N / 2) & (N - 1)]);
         T x, y;
         point_xy(d, off + si, x, y);
-        Pol[(size_t)(off + si) * B + b] = cmul(uf, conjg(point_phase(d, x, y)));
+        const cx<T> ph = conjg(point_phase(d, x, y));
+        cx<T>* dst = Pol + (size_t)(off + si) * B + b0;
+        for (int i = 0; i < nb; ++i) {
+            // transpose of the conjugate-symmetric fill, then of the point phase
+            const cx<T>* bi = buf + i * N;
+            dst[i] = cmul(bi[s & (N - 1)] + conjg(bi[(s + N / 2) & (N - 1)]), ph);
+        }
     }
 }
 
 template <typename T, int WMAX>
-__global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const cx<T>* Ulow, cx<T>* Pol, int B,
+__global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const cx<T>* Ulow, cx<T>* Pol, int B, int G,
                                                size_t ws_img)
 {
-    ring_adj_body<T, WMAX>(d, blk_plain(), V, Ulow, Pol, B, ws_img);
+    ring_adj_body<T, WMAX>(d, blk_plain(), V, Ulow, Pol, B, G, ws_img);
 }
 
 // Transpose of the gather.  Each wave owns an 8 x 8 tile of cells of the
@@ -854,21 +889,38 @@ __device__ __forceinline__ void spread_tiles_body(const Dev<T>& d, Blk bk, const
                     for (int part = 0; part < 2; ++part) {
                         const int plo = __builtin_amdgcn_readlane(part ? v_lo : u_lo, r);
                         const int phi = __builtin_amdgcn_readlane(part ? v_hi : u_hi, r);
+                        if (plo > phi) continue;
+                        // samples are walked with their position and image values loaded one
+                        // sample ahead (scalar loads complete in any order, so each wait covers
+                        // everything outstanding: the loads for sample p + 1 are issued right
+                        // after the wait for sample p and overlap its arithmetic).  Entries past
+                        // the batch are padding or the next point's values and only reach
+                        // accumulators that are never stored.
+                        cx<T> qn = d.pos[plo];
+                        cx<T> vn[BC];
+                        {
+                            const cx<T>* src = Pol + (size_t)plo * B + b0;
+#pragma unroll
+                            for (int k = 0; k < BC; ++k) vn[k] = src[k];
+                        }
                         for (int p = plo; p <= phi; ++p) {
-                            const cx<T> q = d.pos[p];
+                            const cx<T> q = qn;
+                            cx<T> val[BC];
+#pragma unroll
+                            for (int k = 0; k < BC; ++k) val[k] = vn[k];
+                            if (p < phi) {
+                                qn = d.pos[p + 1];
+                                const cx<T>* src = Pol + (size_t)(p + 1) * B + b0;
+#pragma unroll
+                                for (int k = 0; k < BC; ++k) vn[k] = src[k];
+                            }
                             const int gx0 = (int)ceil_t(q.x - hwf);
                             const int gy0 = (int)ceil_t(q.y - hwf);
                             const int jx = gx - gx0;
                             const int jy = (gy - gy0) & mask;
                             if (valid && (unsigned)jx < (unsigned)W && jy < W) {
-                                const T wgt = es_w(q.x - T(gx0 + jx), tw_, d.beta) * es_w(q.y - T(gy0 + jy), tw_, d.beta);
-                                // all BC values of the sample in one go (wide scalar loads, one
-                                // wait); entries past the batch are padding or the next point's
-                                // values and only reach accumulators that are never stored
-                                const cx<T>* src = Pol + (size_t)p * B + b0;
-                                cx<T> val[BC];
-#pragma unroll
-                                for (int k = 0; k < BC; ++k) val[k] = src[k];
+                                const T wgt = es_w(q.x - T(gx0 + jx), tw_, d.beta, d.beta_l2e) *
+                                              es_w(q.y - T(gy0 + jy), tw_, d.beta, d.beta_l2e);
 #pragma unroll
                                 for (int k = 0; k < BC; ++k) acc[k] = acc[k] + val[k] * wgt;
                             }
@@ -1044,6 +1096,20 @@ int ring_group_max(const pat::Params& P)
     return g;
 }
 
+// the cosine transform's LDS: CW columns of M points, plus the stash of the
+// CW input columns (max(L, nt) rows) when that still fits 64 KiB
+int dct_stash_ok(const pat::Params& P, int cw)
+{
+    const size_t cs = (P.dt == PAT_F64) ? 16 : 8;
+    return (size_t)cw * (P.M + std::max(P.L, P.nt)) * cs <= 65536 ? 1 : 0;
+}
+
+size_t dct_lds(const pat::Params& P, int cw)
+{
+    const size_t cs = (P.dt == PAT_F64) ? 16 : 8;
+    return cs * cw * ((size_t)P.M + (dct_stash_ok(P, cw) ? std::max(P.L, P.nt) : 0));
+}
+
 int lds_dct(const pat::Params& P)
 {
     size_t cs = (P.dt == PAT_F64) ? 16 : 8;
@@ -1100,8 +1166,9 @@ int upload(pat_plan_s* p, Dev<T>& d)
     d.npts = P.npts; d.logNmax = ilog2i(P.Nmax);
     d.colsCW = p->cols_cw;
     d.dctCW = p->dct_cw;
+    d.dct_stash = dct_stash_ok(P, p->dct_cw);
     d.fft_lr = p->fft_lr;
-    d.beta = (T)P.beta; d.shift = (T)P.shift; d.half = (T)(0.5 * P.Ng / P.Lam); d.lamh = (T)P.h;
+    d.beta = (T)P.beta; d.beta_l2e = (T)(P.beta * 1.4426950408889634); d.shift = (T)P.shift; d.half = (T)(0.5 * P.Ng / P.Lam); d.lamh = (T)P.h;
     d.dlam = (T)P.dlam; d.pre_scale = (T)P.pre_scale; d.adj_scale = (T)P.adj_scale;
     d.mask_r2 = P.g.mask_radius > 0 ? P.g.mask_radius * P.g.mask_radius : 0.0;
     d.a = P.g.a; d.h = P.h;
@@ -1176,7 +1243,7 @@ int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g
     if ((rc = check_launch("ring_fwd"))) return rc;
     {
         StageTimer tm(p, st, 3);
-        dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, cs * d.M * d.dctCW, st>>>(d, V, G, wi, 0);
+        dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, dct_lds(p->H.P, d.dctCW), st>>>(d, V, G, wi, 0);
     }
     if ((rc = check_launch("dct_fwd"))) return rc;
     {
@@ -1216,12 +1283,13 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
     if ((rc = check_launch("lowk_adj"))) return rc;
     {
         StageTimer tm(p, st, 8);
-        dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, cs * d.M * d.dctCW, st>>>(d, G, V, wi, 1);
+        dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, dct_lds(p->H.P, d.dctCW), st>>>(d, G, V, wi, 1);
     }
     if ((rc = check_launch("dct_adj"))) return rc;
     {
         StageTimer tm(p, st, 9);
-        ring_adj<T, WMAX><<<dim3(B, d.L), NT, cs * P.max_ring, st>>>(d, V, U, Pol, B, wi);
+        const int Gr = std::max(1, std::min(p->ring_g, B));
+        ring_adj<T, WMAX><<<dim3((B + Gr - 1) / Gr, d.L), NT, cs * Gr * P.max_ring, st>>>(d, V, U, Pol, B, Gr, wi);
     }
     if ((rc = check_launch("ring_adj"))) return rc;
     {
@@ -1292,7 +1360,7 @@ __host__ __device__ inline void stage_grid(const Dev<T>& d, int S, int B, int G,
         case PAT_STAGE_SYNTH_FWD:
         case PAT_STAGE_SYNTH_ADJ: nx = (d.nt + 1) / 2; ny = B; break;
         case PAT_STAGE_LOWK_ADJ: nx = d.lcorr; ny = B; break;
-        case PAT_STAGE_RING_ADJ: nx = B; ny = d.L; break;
+        case PAT_STAGE_RING_ADJ: nx = (B + G - 1) / G; ny = d.L; break;
         default: nx = (d.Ew + 15) / 16; ny = (d.Ng + 15) / 16; nz = (B + BC - 1) / BC; break;  // spread
     }
 }
@@ -1334,7 +1402,7 @@ __global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
     if constexpr (S == PAT_STAGE_SYNTH_ADJ) synth_adj_body<T>(q.d, bk, q.gin, q.gs, Gh, q.wi);
     if constexpr (S == PAT_STAGE_LOWK_ADJ) lowk_adj_body<T>(q.d, bk, Gh, U, q.wi);
     if constexpr (S == PAT_STAGE_DCT_ADJ) dct_cols_body<T>(q.d, bk, Gh, V, q.wi, 1);
-    if constexpr (S == PAT_STAGE_RING_ADJ) ring_adj_body<T, WMAX>(q.d, bk, V, U, Pol, q.B, q.wi);
+    if constexpr (S == PAT_STAGE_RING_ADJ) ring_adj_body<T, WMAX>(q.d, bk, V, U, Pol, q.B, q.G, q.wi);
     if constexpr (S == PAT_STAGE_SPREAD_ADJ) spread_tiles_body<T, WMAX, BC>(q.d, bk, Pol, q.B, E, q.wi);
     if constexpr (S == PAT_STAGE_COLS_ADJ) cols_adj_body<T>(q.d, bk, E, R, q.wi);
     if constexpr (S == PAT_STAGE_ROWS_ADJ) rows_adj_body<T>(q.d, bk, R, q.fout, q.fs, q.wi);
@@ -1355,10 +1423,10 @@ size_t stage_lds(const pat_plan_s* p, int S, int G)
         case PAT_STAGE_COLS_ADJ: return cs * P.Ng * p->cols_cw;
         case PAT_STAGE_RING_FWD: return cs * G * P.max_ring;
         case PAT_STAGE_DCT_FWD:
-        case PAT_STAGE_DCT_ADJ: return cs * P.M * p->dct_cw;
+        case PAT_STAGE_DCT_ADJ: return dct_lds(P, p->dct_cw);
         case PAT_STAGE_SYNTH_FWD: return cs * 2 * P.mf;
         case PAT_STAGE_SYNTH_ADJ: return cs * P.mf;
-        case PAT_STAGE_RING_ADJ: return cs * P.max_ring;
+        case PAT_STAGE_RING_ADJ: return cs * G * P.max_ring;
         default: return 0;
     }
 }
@@ -1454,6 +1522,7 @@ void apply_tune(pat_plan_s* p)
     p->df.colsCW = p->dd.colsCW = p->cols_cw;
     p->df.dctCW = p->dd.dctCW = p->dct_cw;
     p->df.fft_lr = p->dd.fft_lr = p->fft_lr;
+    p->df.dct_stash = p->dd.dct_stash = dct_stash_ok(p->H.P, p->dct_cw);
 }
 
 bool pow2_in(int v, int hi) { return v >= 1 && v <= hi && (v & (v - 1)) == 0; }

@@ -41,14 +41,18 @@ __device__ __forceinline__ short to_bf16(float x)
 
 struct ConvArgs {
     int B, H, W, cin, cout;
-    const float* in[4];      // planar planes (cin of them) or NHWC (in[0])
-    float* out[4];           // planar planes (cout of them; null = skip) or NHWC (out[0])
+    const float* in[4];      // planar input planes (FP32, cin of them)
+    const short* in16;       // NHWC input (bf16, 32 channels)
+    float* out[4];           // planar outputs (FP32; null = channel not written)
+    short* out16;            // NHWC output (bf16)
     const float* res[4];     // planar residuals (null = none)
     float scale[4];          // planar input scales (planar in) / planar output scales (planar out)
     const short* weight;     // packed bf16 [CT*16][9*CINP]
     const float* bias;       // [cout] or null
-    const float* alpha;      // [cout] PReLU slopes or null
-    float* pre;              // NHWC pre-activation copy or null
+    const float* alpha;      // PReLU slopes [cout] (forward) or of the PReLU being differentiated
+    float* pre;              // forward, NHWC out: FP32 copy of the pre-activation, or null
+    const float* bwd_pre;    // backward, NHWC out: pre-activation of the PReLU being differentiated
+    float* part;             // backward: per-block partial sums [block][64]
 };
 
 // 4 consecutive reduction entries k..k+3 (one tap, channels c..c+3) of pixel (y, x)
@@ -57,32 +61,40 @@ __device__ __forceinline__ bf16x4 gather4(const ConvArgs& a, int b, int y, int x
 {
     const int tap = k / CINP, c = k - tap * CINP;
     const int sy = y + tap / 3 - 1, sx = x + tap % 3 - 1;
-    float v[4] = {0.f, 0.f, 0.f, 0.f};
-    if (tap < 9 && x < a.W && sy >= 0 && sy < a.H && sx >= 0 && sx < a.W) {
-        const size_t p = ((size_t)b * a.H + sy) * a.W + sx;
-        if (PLANAR) {
+    const bool in = tap < 9 && x < a.W && sy >= 0 && sy < a.H && sx >= 0 && sx < a.W;
+    const size_t p = ((size_t)b * a.H + sy) * a.W + sx;
+    if (PLANAR) {
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        if (in) {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 if (c + e < a.cin) v[e] = a.in[c + e][p] * a.scale[c + e];
-        } else {
-            const float4 q = *reinterpret_cast<const float4*>(a.in[0] + p * HID + c);
-            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
         }
-    }
-    bf16x4 r;
+        bf16x4 r;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) r[e] = to_bf16(v[e]);
-    return r;
+        for (int e = 0; e < 4; ++e) r[e] = to_bf16(v[e]);
+        return r;
+    } else {
+        bf16x4 r = {0, 0, 0, 0};
+        if (in) r = *reinterpret_cast<const bf16x4*>(a.in16 + p * HID + c);
+        return r;
+    }
 }
 
 // Block: 256 consecutive pixels of one image row; wave w covers pixels
 // 64 w .. 64 w + 63 as GROUPS groups of 16.  Weights are staged in LDS once.
-template <int CINP, bool PLANAR_IN, int CT, bool PLANAR_OUT>
+// NHWC outputs have two epilogues: forward (bias, PReLU, bf16 activation and
+// optional FP32 pre-activation) and backward (the input gradient of a layer
+// followed by the PReLU backward of the layer below: gx = ga * (pre > 0 ? 1 :
+// alpha), stored bf16, with per-block partial sums of gx and ga * pre * [pre
+// <= 0] for the bias and slope gradients).
+template <int CINP, bool PLANAR_IN, int CT, bool PLANAR_OUT, bool BWD>
 __global__ __launch_bounds__(NT) void conv3x3_fwd(ConvArgs a)
 {
     constexpr int K = 9 * CINP;
     constexpr int KP = (K + 15) / 16 * 16;
     __shared__ short wl[CT * 16 * KP];
+    __shared__ float red[BWD ? 4 * 4 * 2 * CT * 16 : 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int b = blockIdx.z, y = blockIdx.y;
     const int xw = blockIdx.x * (64 * GROUPS) + wave * (16 * GROUPS);
@@ -91,54 +103,85 @@ __global__ __launch_bounds__(NT) void conv3x3_fwd(ConvArgs a)
         wl[i] = (k < K) ? a.weight[(size_t)co * K + k] : (short)0;
     }
     __syncthreads();
-    if (xw >= a.W) return;
+    const bool active = xw < a.W;
     f32x4 acc[GROUPS][CT];
 #pragma unroll
     for (int g = 0; g < GROUPS; ++g)
 #pragma unroll
         for (int t = 0; t < CT; ++t) acc[g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int kq = 4 * (lane >> 4);
-    for (int k0 = 0; k0 < KP; k0 += 16) {
-        bf16x4 bv[CT];
+    if (active) {
+        for (int k0 = 0; k0 < KP; k0 += 16) {
+            bf16x4 bv[CT];
 #pragma unroll
-        for (int t = 0; t < CT; ++t) {
-            const short* wp = wl + (t * 16 + (lane & 15)) * KP + k0 + kq;
-            bv[t][0] = wp[0]; bv[t][1] = wp[1]; bv[t][2] = wp[2]; bv[t][3] = wp[3];
-        }
+            for (int t = 0; t < CT; ++t) {
+                const short* wp = wl + (t * 16 + (lane & 15)) * KP + k0 + kq;
+                bv[t][0] = wp[0]; bv[t][1] = wp[1]; bv[t][2] = wp[2]; bv[t][3] = wp[3];
+            }
 #pragma unroll
-        for (int g = 0; g < GROUPS; ++g) {
-            const bf16x4 av = gather4<CINP, PLANAR_IN>(a, b, y, xw + 16 * g + (lane & 15), k0 + kq);
+            for (int g = 0; g < GROUPS; ++g) {
+                const bf16x4 av = gather4<CINP, PLANAR_IN>(a, b, y, xw + 16 * g + (lane & 15), k0 + kq);
 #pragma unroll
-            for (int t = 0; t < CT; ++t)
-                acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[t], acc[g][t], 0, 0, 0);
+                for (int t = 0; t < CT; ++t)
+                    acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[t], acc[g][t], 0, 0, 0);
+            }
         }
     }
+    float sb[CT], sa[CT];
 #pragma unroll
-    for (int g = 0; g < GROUPS; ++g) {
+    for (int t = 0; t < CT; ++t) sb[t] = sa[t] = 0.f;
+    if (active) {
 #pragma unroll
-        for (int t = 0; t < CT; ++t) {
-            const int co = t * 16 + (lane & 15);
-            if (co >= a.cout) continue;
-            const float bias = a.bias ? a.bias[co] : 0.f;
-            const float alpha = a.alpha ? a.alpha[co] : 1.f;
+        for (int g = 0; g < GROUPS; ++g) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int x = xw + 16 * g + 4 * (lane >> 4) + r;
-                if (x >= a.W) continue;
-                float v = acc[g][t][r] + bias;
-                const size_t pix = ((size_t)b * a.H + y) * a.W + x;
-                if (PLANAR_OUT) {
-                    float* o = a.out[co];
-                    if (!o) continue;
-                    v *= a.scale[co];
-                    if (a.res[co]) v += a.res[co][pix];
-                    o[pix] = v;
-                } else {
-                    if (a.pre) a.pre[pix * HID + co] = v;
-                    if (a.alpha) v = v > 0.f ? v : alpha * v;
-                    a.out[0][pix * HID + co] = v;
+            for (int t = 0; t < CT; ++t) {
+                const int co = t * 16 + (lane & 15);
+                if (co >= a.cout) continue;
+                const float bias = a.bias ? a.bias[co] : 0.f;
+                const float alpha = a.alpha ? a.alpha[co] : 1.f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int x = xw + 16 * g + 4 * (lane >> 4) + r;
+                    if (x >= a.W) continue;
+                    float v = acc[g][t][r] + bias;
+                    const size_t pix = ((size_t)b * a.H + y) * a.W + x;
+                    if (PLANAR_OUT) {
+                        float* o = a.out[co];
+                        if (!o) continue;
+                        v *= a.scale[co];
+                        if (a.res[co]) v += a.res[co][pix];
+                        o[pix] = v;
+                    } else if (BWD) {
+                        const float xp = a.bwd_pre[pix * HID + co];
+                        const float gx = xp > 0.f ? v : alpha * v;
+                        sb[t] += gx;
+                        if (!(xp > 0.f)) sa[t] += v * xp;
+                        a.out16[pix * HID + co] = to_bf16(gx);
+                    } else {
+                        if (a.pre) a.pre[pix * HID + co] = v;
+                        if (a.alpha) v = v > 0.f ? v : alpha * v;
+                        a.out16[pix * HID + co] = to_bf16(v);
+                    }
                 }
             }
+        }
+    }
+    if (BWD) {
+        // block partials: channel co = t*16 + (lane & 15), summed over the 4 lane
+        // groups and the 4 waves in a fixed order
+#pragma unroll
+        for (int t = 0; t < CT; ++t) {
+            red[((wave * 4 + (lane >> 4)) * 2 + 0) * CT * 16 + t * 16 + (lane & 15)] = sb[t];
+            red[((wave * 4 + (lane >> 4)) * 2 + 1) * CT * 16 + t * 16 + (lane & 15)] = sa[t];
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * HID) {
+            const int kind = threadIdx.x / HID, co = threadIdx.x % HID;
+            float s = 0.f;
+            if (co < CT * 16)
+                for (int q = 0; q < 16; ++q) s += red[(q * 2 + kind) * CT * 16 + co];
+            const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            a.part[blk * 64 + threadIdx.x] = s;
         }
     }
 }
@@ -151,14 +194,14 @@ __global__ __launch_bounds__(NT) void conv3x3_fwd(ConvArgs a)
 // CT = 1 the k tiles go round-robin over the 4 waves.  Accumulators stay in
 // registers for the whole chunk.
 struct WgradArgs {
-    ConvArgs x;              // x.in: layer input as in the forward; x.cout: output channels
-    const float* grad;       // gradient of the layer output: NHWC, or planar (cout == 1)
-    int grad_planar;
+    ConvArgs x;              // x.in / x.in16: layer input as in the forward; x.cout: output channels
+    const float* grad;       // planar gradient of the layer output (cout == 1), or null
+    const short* grad16;     // NHWC bf16 gradient of the layer output
     int rows;                // image rows per chunk
     float* part;             // [chunks][CT*16][KP]
 };
 
-template <int CINP, bool PLANAR_IN, int CT>
+template <int CINP, bool PLANAR_IN, int CT, bool PLANAR_G>
 __global__ __launch_bounds__(NT) void conv3x3_wgrad(WgradArgs w)
 {
     constexpr int K = 9 * CINP;
@@ -187,12 +230,12 @@ __global__ __launch_bounds__(NT) void conv3x3_wgrad(WgradArgs w)
             const int pl = p0 + 4 * (lane >> 4) + e;
             yy[e] = pl < npix ? y0 + pl / a.W : -10;
             xx[e] = pl < npix ? pl % a.W : 0;
-            float gv = 0.f;
+            short gv = 0;
             if (yy[e] >= 0 && co < a.cout) {
                 const size_t pix = ((size_t)b * a.H + yy[e]) * a.W + xx[e];
-                gv = w.grad_planar ? w.grad[pix] : w.grad[pix * HID + co];
+                gv = PLANAR_G ? to_bf16(w.grad[pix]) : w.grad16[pix * HID + co];
             }
-            av[e] = to_bf16(gv);
+            av[e] = gv;
         }
 #pragma unroll
         for (int j = 0; j < MAXT; ++j) {
@@ -203,14 +246,14 @@ __global__ __launch_bounds__(NT) void conv3x3_wgrad(WgradArgs w)
             bf16x4 bv;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                float pv = 0.f;
+                short pv = 0;
                 const int sy = yy[e] + tap / 3 - 1, sx = xx[e] + tap % 3 - 1;
                 if (kk < K && yy[e] >= 0 && sy >= 0 && sy < a.H && sx >= 0 && sx < a.W) {
                     const size_t sp = ((size_t)b * a.H + sy) * a.W + sx;
-                    if (PLANAR_IN) pv = c < a.cin ? a.in[c][sp] * a.scale[c] : 0.f;
-                    else pv = a.in[0][sp * HID + c];
+                    if (PLANAR_IN) pv = c < a.cin ? to_bf16(a.in[c][sp] * a.scale[c]) : (short)0;
+                    else pv = a.in16[sp * HID + c];
                 }
-                bv[e] = to_bf16(pv);
+                bv[e] = pv;
             }
             acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[j], 0, 0, 0);
         }
@@ -257,35 +300,6 @@ __global__ __launch_bounds__(NT) void reduce_partials(const float* part, int nro
             o = (co * cin + ci) * 9 + tap;
         }
         out[o] = accumulate ? out[o] + (float)t : (float)t;
-    }
-}
-
-// PReLU backward over NHWC 32-channel tensors: gx = ga * (x > 0 ? 1 : alpha);
-// per-block partials of sum gx (bias gradient) and sum ga * x * [x <= 0]
-// (slope gradient), 64 floats per block.
-__global__ __launch_bounds__(NT) void prelu_bwd(long npix, const float* ga, const float* x, const float* alpha,
-                                                float* gx, float* part)
-{
-    __shared__ float sb[8][HID], sa[8][HID];
-    const int c = threadIdx.x & 31, slot = threadIdx.x >> 5;
-    const float al = alpha[c];
-    float accb = 0.f, acca = 0.f;
-    for (long p = (long)blockIdx.x * 8 + slot; p < npix; p += (long)gridDim.x * 8) {
-        const size_t i = (size_t)p * HID + c;
-        const float xv = x[i], g = ga[i];
-        const float d = xv > 0.f ? g : al * g;
-        gx[i] = d;
-        accb += d;
-        if (!(xv > 0.f)) acca += g * xv;
-    }
-    sb[slot][c] = accb;
-    sa[slot][c] = acca;
-    __syncthreads();
-    if (threadIdx.x < HID) {
-        float tb = 0.f, ta = 0.f;
-        for (int s = 0; s < 8; ++s) { tb += sb[s][c]; ta += sa[s][c]; }
-        part[(size_t)blockIdx.x * 64 + c] = tb;
-        part[(size_t)blockIdx.x * 64 + HID + c] = ta;
     }
 }
 
@@ -408,10 +422,14 @@ ConvArgs make_args(const pat_conv_desc* d)
         a.res[i] = static_cast<const float*>(d->residual[i]);
         a.scale[i] = d->scale[i];
     }
+    a.in16 = d->in_planar ? nullptr : static_cast<const short*>(d->in[0]);
+    a.out16 = d->out_planar ? nullptr : static_cast<short*>(d->out[0]);
     a.weight = static_cast<const short*>(d->weight);
     a.bias = static_cast<const float*>(d->bias);
     a.alpha = static_cast<const float*>(d->alpha);
     a.pre = static_cast<float*>(d->pre);
+    a.bwd_pre = static_cast<const float*>(d->bwd_pre);
+    a.part = static_cast<float*>(d->partials);
     return a;
 }
 
@@ -430,9 +448,13 @@ int check_desc(const pat_conv_desc* d, const char* who)
     for (int i = 0; i < (d->in_planar ? d->cin : 1); ++i)
         if (!d->in[i]) return fail(PAT_EINVAL, "missing input plane");
     if (!d->weight) return fail(PAT_EINVAL, "missing weights");
-    if (d->out_planar && (d->pre || d->alpha)) return fail(PAT_EUNSUPPORTED, "PReLU needs an NHWC output");
+    if (d->out_planar && (d->pre || d->alpha || d->bwd_pre)) return fail(PAT_EUNSUPPORTED, "PReLU needs an NHWC output");
+    if (d->bwd_pre && (!d->alpha || !d->partials || !d->grad_bias_alpha || d->pre || d->bias))
+        return fail(PAT_EINVAL, "the PReLU-backward epilogue needs alpha, partials, grad_bias_alpha and no bias / pre");
     return PAT_OK;
 }
+
+dim3 conv_grid(const pat_conv_desc* d) { return dim3((d->W + 64 * GROUPS - 1) / (64 * GROUPS), d->H, d->B); }
 
 }  // namespace
 
@@ -458,6 +480,13 @@ int pat_conv_pack_weights(const void* w, int cout, int cin, int transpose, int i
     return status("pack_weights");
 }
 
+long pat_conv_bwd_partials(const pat_conv_desc* d)
+{
+    if (!d || d->B < 1 || d->H < 1 || d->W < 1) return -1;
+    const dim3 g = conv_grid(d);
+    return (long)g.x * g.y * g.z * 64;
+}
+
 int pat_conv3x3(const pat_conv_desc* d, void* stream)
 {
     int rc = check_desc(d, "pat_conv3x3");
@@ -465,16 +494,26 @@ int pat_conv3x3(const pat_conv_desc* d, void* stream)
     if (!d->out_planar && !d->out[0]) { pat::set_error("pat_conv3x3: missing output"); return PAT_EINVAL; }
     ConvArgs a = make_args(d);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    dim3 grid((d->W + 64 * GROUPS - 1) / (64 * GROUPS), d->H, d->B);
-    if (d->in_planar && !d->out_planar)
-        conv3x3_fwd<4, true, 2, false><<<grid, NT, 0, st>>>(a);
-    else if (!d->in_planar && !d->out_planar)
-        conv3x3_fwd<HID, false, 2, false><<<grid, NT, 0, st>>>(a);
-    else if (!d->in_planar && d->out_planar)
-        conv3x3_fwd<HID, false, 1, true><<<grid, NT, 0, st>>>(a);
-    else
-        conv3x3_fwd<4, true, 1, true><<<grid, NT, 0, st>>>(a);
-    return status("pat_conv3x3");
+    const dim3 grid = conv_grid(d);
+    const bool bwd = d->bwd_pre != nullptr;
+    if (d->in_planar && !d->out_planar) {
+        if (bwd) conv3x3_fwd<4, true, 2, false, true><<<grid, NT, 0, st>>>(a);
+        else conv3x3_fwd<4, true, 2, false, false><<<grid, NT, 0, st>>>(a);
+    } else if (!d->in_planar && !d->out_planar) {
+        if (bwd) conv3x3_fwd<HID, false, 2, false, true><<<grid, NT, 0, st>>>(a);
+        else conv3x3_fwd<HID, false, 2, false, false><<<grid, NT, 0, st>>>(a);
+    } else if (!d->in_planar && d->out_planar) {
+        conv3x3_fwd<HID, false, 1, true, false><<<grid, NT, 0, st>>>(a);
+    } else {
+        conv3x3_fwd<4, true, 1, true, false><<<grid, NT, 0, st>>>(a);
+    }
+    if ((rc = status("pat_conv3x3"))) return rc;
+    if (bwd) {
+        reduce_partials<<<4, NT, 0, st>>>(static_cast<const float*>(d->partials), (int)(grid.x * grid.y * grid.z), 64, 0,
+                                          0, 0, 0, static_cast<float*>(d->grad_bias_alpha), d->accumulate);
+        rc = status("reduce_partials");
+    }
+    return rc;
 }
 
 long pat_conv_wgrad_partials(const pat_conv_desc* d, int rows_per_chunk)
@@ -500,8 +539,8 @@ int pat_conv3x3_wgrad(const pat_conv_desc* d, const void* grad_out, int rows_per
     }
     WgradArgs w;
     w.x = make_args(d);
-    w.grad = static_cast<const float*>(grad_out);
-    w.grad_planar = d->out_planar;
+    w.grad = d->out_planar ? static_cast<const float*>(grad_out) : nullptr;
+    w.grad16 = d->out_planar ? nullptr : static_cast<const short*>(grad_out);
     w.rows = rows_per_chunk;
     w.part = static_cast<float*>(partials);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -509,32 +548,14 @@ int pat_conv3x3_wgrad(const pat_conv_desc* d, const void* grad_out, int rows_per
     dim3 grid(chunks, d->B);
     const int cinp = cinp_of(d->in_planar), ct = ct_of(d->cout);
     const int kp = (9 * cinp + 15) / 16 * 16;
-    if (d->in_planar && ct == 2) conv3x3_wgrad<4, true, 2><<<grid, NT, 0, st>>>(w);
-    else if (d->in_planar) conv3x3_wgrad<4, true, 1><<<grid, NT, 0, st>>>(w);
-    else if (ct == 2) conv3x3_wgrad<HID, false, 2><<<grid, NT, 0, st>>>(w);
-    else conv3x3_wgrad<HID, false, 1><<<grid, NT, 0, st>>>(w);
+    if (d->in_planar && ct == 2) conv3x3_wgrad<4, true, 2, false><<<grid, NT, 0, st>>>(w);
+    else if (d->in_planar) conv3x3_wgrad<4, true, 1, true><<<grid, NT, 0, st>>>(w);
+    else if (ct == 2) conv3x3_wgrad<HID, false, 2, false><<<grid, NT, 0, st>>>(w);
+    else conv3x3_wgrad<HID, false, 1, true><<<grid, NT, 0, st>>>(w);
     if ((rc = status("conv3x3_wgrad"))) return rc;
     const int ncols = ct * 16 * kp;
     reduce_partials<<<(ncols + 15) / 16, NT, 0, st>>>(static_cast<const float*>(partials), chunks * d->B, ncols, kp, cinp,
                                                       d->cout, d->cin, static_cast<float*>(grad_w), accumulate);
-    return status("reduce_partials");
-}
-
-int pat_prelu_backward(long npix, const void* grad_act, const void* pre, const void* alpha, void* grad_pre,
-                       void* partials, int nblocks, void* grad_bias_alpha, int accumulate, void* stream)
-{
-    if (!grad_act || !pre || !alpha || !grad_pre || !partials || !grad_bias_alpha || nblocks < 1 || npix < 1) {
-        pat::set_error("pat_prelu_backward: bad arguments");
-        return PAT_EINVAL;
-    }
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    prelu_bwd<<<nblocks, NT, 0, st>>>(npix, static_cast<const float*>(grad_act), static_cast<const float*>(pre),
-                                      static_cast<const float*>(alpha), static_cast<float*>(grad_pre),
-                                      static_cast<float*>(partials));
-    int rc = status("prelu_bwd");
-    if (rc) return rc;
-    reduce_partials<<<4, NT, 0, st>>>(static_cast<const float*>(partials), nblocks, 64, 0, 0, 0, 0,
-                                      static_cast<float*>(grad_bias_alpha), accumulate);
     return status("reduce_partials");
 }
 

@@ -15,9 +15,9 @@ empirical loss eq:emp_loss divided by the number of pixels).
 
 Everything that computes runs in libpat.so: A, A* (pat_forward_batched /
 pat_adjoint_batched), the BF16-MFMA convolutions with fused bias / PReLU /
-residual, the explicit reverse sweep (input-gradient convolutions, weight
-gradients, PReLU backward, 4K operator applications per step as the paper
-counts), the loss gradient (pat_axpby) and Adam.  The whole training step or
+residual, the explicit reverse sweep (input-gradient convolutions with the
+PReLU backward fused into their epilogue, weight gradients, 4K operator
+applications per step as the paper counts), the loss gradient (pat_axpby) and Adam.  The whole training step or
 inference pass is a fixed launch sequence, captured once in a HIP graph
 (torch.cuda.CUDAGraph) and replayed.  Python allocates buffers and marshals
 pointers only.
@@ -110,7 +110,7 @@ class _Layer:
 
 
 def _desc(B, H, W, cin, cout, in_planar, out_planar, inp, out, weight, bias=None, alpha=None, pre=None,
-          residual=None, scale=None):
+          residual=None, scale=None, bwd_pre=None, partials=None, grad_bias_alpha=None, accumulate=0):
     d = ConvDesc()
     d.B, d.H, d.W, d.cin, d.cout = B, H, W, cin, cout
     d.in_planar, d.out_planar = int(in_planar), int(out_planar)
@@ -125,6 +125,8 @@ def _desc(B, H, W, cin, cout, in_planar, out_planar, inp, out, weight, bias=None
     for i, s in enumerate(scale or []):
         d.scale[i] = float(s)
     d.weight, d.bias, d.alpha, d.pre = _p(weight), _p(bias), _p(alpha), _p(pre)
+    d.bwd_pre, d.partials, d.grad_bias_alpha = _p(bwd_pre), _p(partials), _p(grad_bias_alpha)
+    d.accumulate = int(accumulate)
     return d
 
 
@@ -139,18 +141,22 @@ class _Block:
         self.l3 = _Layer(lib, params, grads, offs, net, 3, HID, 1, False, True, dev)
         nk = K if train else 1
         shp = (nk, B, H, W, HID)
-        self.pre1 = torch.empty(shp, dtype=torch.float32, device=dev)
-        self.act1 = torch.empty(shp, dtype=torch.float32, device=dev)
-        self.pre2 = torch.empty(shp, dtype=torch.float32, device=dev)
-        self.act2 = torch.empty(shp, dtype=torch.float32, device=dev)
+        # hidden activations and gradients are bf16 (int16 storage); the
+        # pre-activations the PReLU backward needs stay FP32 (training only)
+        self.act1 = torch.empty(shp, dtype=torch.int16, device=dev)
+        self.act2 = torch.empty(shp, dtype=torch.int16, device=dev)
+        self.pre1 = torch.empty(shp, dtype=torch.float32, device=dev) if train else None
+        self.pre2 = torch.empty(shp, dtype=torch.float32, device=dev) if train else None
         if train:
-            self.g1 = torch.empty((B, H, W, HID), dtype=torch.float32, device=dev)
-            self.g2 = torch.empty((B, H, W, HID), dtype=torch.float32, device=dev)
+            self.g1 = torch.empty((B, H, W, HID), dtype=torch.int16, device=dev)
+            self.g2 = torch.empty((B, H, W, HID), dtype=torch.int16, device=dev)
             self.rows = max(1, min(H, 2048 // W))
             need = 0
-            for l, inp in ((self.l1, True), (self.l2, False), (self.l3, False)):
+            for l in (self.l1, self.l2, self.l3):
                 d = _desc(B, H, W, l.cin, l.cout, l.in_planar, l.out_planar, [], [], None)
                 need = max(need, lib.pat_conv_wgrad_partials(ctypes.byref(d), self.rows))
+            d = _desc(B, H, W, HID, HID, False, False, [], [], None)
+            need = max(need, lib.pat_conv_bwd_partials(ctypes.byref(d)))
             self.part = torch.empty(max(need, 64 * 1024), dtype=torch.float32, device=dev)
             self.nred = 512
 
@@ -161,10 +167,11 @@ class _Block:
         lib, B, H, W = self.lib, self.B, self.H, self.W
         j = min(k, self.pre1.shape[0] - 1)
         l1, l2, l3 = self.layers()
-        d = _desc(B, H, W, self.cin, HID, True, False, planes, [self.act1[j]], l1.wf, l1.b, l1.a, self.pre1[j],
-                  scale=scales)
+        pre1 = None if self.pre1 is None else self.pre1[j]
+        pre2 = None if self.pre2 is None else self.pre2[j]
+        d = _desc(B, H, W, self.cin, HID, True, False, planes, [self.act1[j]], l1.wf, l1.b, l1.a, pre1, scale=scales)
         _check(lib.pat_conv3x3(ctypes.byref(d), st), "pat_conv3x3")
-        d = _desc(B, H, W, HID, HID, False, False, [self.act1[j]], [self.act2[j]], l2.wf, l2.b, l2.a, self.pre2[j])
+        d = _desc(B, H, W, HID, HID, False, False, [self.act1[j]], [self.act2[j]], l2.wf, l2.b, l2.a, pre2)
         _check(lib.pat_conv3x3(ctypes.byref(d), st), "pat_conv3x3")
         d = _desc(B, H, W, HID, 1, False, True, [self.act2[j]], [state_out], l3.wf, l3.b, residual=[state_in])
         _check(lib.pat_conv3x3(ctypes.byref(d), st), "pat_conv3x3")
@@ -177,24 +184,23 @@ class _Block:
         l1, l2, l3 = self.layers()
         npix = B * H * W
         a = int(acc)
-        # layer 3 (no activation): bias, weights, input gradient
+        # layer 3 (no activation): bias, weights; its input gradient goes through
+        # the PReLU of layer 2 in the same launch (bias / slope gradients of layer 2)
         _check(lib.pat_plane_sum(npix, _p(g_out), _p(self.part), self.nred, _p(l3.gb), a, st), "pat_plane_sum")
         d3 = _desc(B, H, W, HID, 1, False, True, [self.act2[k]], [], l3.wf)
         _check(lib.pat_conv3x3_wgrad(ctypes.byref(d3), _p(g_out), self.rows, _p(self.part), _p(l3.gw), a, st),
                "pat_conv3x3_wgrad")
-        d = _desc(B, H, W, 1, HID, True, False, [g_out], [self.g1], l3.wb)
+        d = _desc(B, H, W, 1, HID, True, False, [g_out], [self.g1], l3.wb, alpha=l2.a, bwd_pre=self.pre2[k],
+                  partials=self.part, grad_bias_alpha=l2.gb, accumulate=a)
         _check(lib.pat_conv3x3(ctypes.byref(d), st), "pat_conv3x3")
-        # layer 2
-        _check(lib.pat_prelu_backward(npix, _p(self.g1), _p(self.pre2[k]), _p(l2.a), _p(self.g1), _p(self.part),
-                                      self.nred, _p(l2.gb), a, st), "pat_prelu_backward")
+        # layer 2: weights; input gradient through the PReLU of layer 1
         d2 = _desc(B, H, W, HID, HID, False, False, [self.act1[k]], [], l2.wf)
         _check(lib.pat_conv3x3_wgrad(ctypes.byref(d2), _p(self.g1), self.rows, _p(self.part), _p(l2.gw), a, st),
                "pat_conv3x3_wgrad")
-        d = _desc(B, H, W, HID, HID, False, False, [self.g1], [self.g2], l2.wb)
+        d = _desc(B, H, W, HID, HID, False, False, [self.g1], [self.g2], l2.wb, alpha=l1.a, bwd_pre=self.pre1[k],
+                  partials=self.part, grad_bias_alpha=l1.gb, accumulate=a)
         _check(lib.pat_conv3x3(ctypes.byref(d), st), "pat_conv3x3")
-        # layer 1
-        _check(lib.pat_prelu_backward(npix, _p(self.g2), _p(self.pre1[k]), _p(l1.a), _p(self.g2), _p(self.part),
-                                      self.nred, _p(l1.gb), a, st), "pat_prelu_backward")
+        # layer 1: weights and the gradients of the input planes
         d1 = _desc(B, H, W, self.cin, HID, True, False, planes, [], l1.wf, scale=scales)
         _check(lib.pat_conv3x3_wgrad(ctypes.byref(d1), _p(self.g2), self.rows, _p(self.part), _p(l1.gw), a, st),
                "pat_conv3x3_wgrad")

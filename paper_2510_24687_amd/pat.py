@@ -45,7 +45,7 @@ EXPORTED = ["pat_plan_create", "pat_plan_query", "pat_plan_destroy", "pat_plan_g
             "pat_workspace_size", "pat_forward", "pat_adjoint", "pat_forward_batched",
             "pat_adjoint_batched", "pat_adjoint_scale", "pat_status_string", "pat_last_error",
             "pat_debug_bessel", "pat_axpby", "pat_conv_packed_size", "pat_conv_pack_weights", "pat_conv3x3",
-            "pat_conv_wgrad_partials", "pat_conv3x3_wgrad", "pat_prelu_backward", "pat_plane_sum", "pat_adam", "pat_opnorm_estimate",
+            "pat_conv_wgrad_partials", "pat_conv3x3_wgrad", "pat_conv_bwd_partials", "pat_plane_sum", "pat_adam", "pat_opnorm_estimate",
             "pat_group_create", "pat_group_destroy", "pat_group_forward", "pat_group_adjoint"]
 
 
@@ -55,7 +55,8 @@ class ConvDesc(ctypes.Structure):
                 ("cout", ctypes.c_int), ("in_planar", ctypes.c_int), ("out_planar", ctypes.c_int),
                 ("inp", ctypes.c_void_p * 4), ("out", ctypes.c_void_p * 4), ("residual", ctypes.c_void_p * 4),
                 ("scale", ctypes.c_float * 4), ("weight", ctypes.c_void_p), ("bias", ctypes.c_void_p),
-                ("alpha", ctypes.c_void_p), ("pre", ctypes.c_void_p)]
+                ("alpha", ctypes.c_void_p), ("pre", ctypes.c_void_p), ("bwd_pre", ctypes.c_void_p),
+                ("partials", ctypes.c_void_p), ("grad_bias_alpha", ctypes.c_void_p), ("accumulate", ctypes.c_int)]
 
 
 def load():
@@ -93,7 +94,8 @@ def load():
     lib.pat_conv_wgrad_partials.argtypes = [cd, i]
     lib.pat_conv_wgrad_partials.restype = L
     lib.pat_conv3x3_wgrad.argtypes = [cd, vp, i, vp, vp, i, vp]
-    lib.pat_prelu_backward.argtypes = [L, vp, vp, vp, vp, vp, i, vp, i, vp]
+    lib.pat_conv_bwd_partials.argtypes = [cd]
+    lib.pat_conv_bwd_partials.restype = L
     lib.pat_plane_sum.argtypes = [L, vp, vp, i, vp, i, vp]
     lib.pat_adam.argtypes = [L, vp, vp, vp, vp, vp, D, D, i, D, D, D, D, vp, vp]
     lib.pat_opnorm_estimate.argtypes = [vp, i, ctypes.POINTER(D), vp, vp]

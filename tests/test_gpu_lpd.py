@@ -58,6 +58,24 @@ def f32(x):
     return np.asarray(x, dtype=np.float32).astype(np.float64)
 
 
+def bfv(x):
+    """values representable in bf16 (the NHWC tensors are stored as bf16)"""
+    return OL.bf16(torch.tensor(np.asarray(x, dtype=np.float64))).numpy()
+
+
+def cuda16(x):
+    """NHWC bf16 device tensor (int16 storage) holding the bf16 values x"""
+    return torch.tensor(np.asarray(x, dtype=np.float32)).to(torch.bfloat16).view(torch.int16).to("cuda")
+
+
+def host16(t):
+    return t.view(torch.bfloat16).float().cpu().numpy().astype(np.float64)
+
+
+# bf16 storage of an FP32 result: relative L2 of the rounding is ~2^-9 / sqrt(3)
+TOL_BF16 = 3e-3
+
+
 @pytest.mark.parametrize("B,H,W", [(2, 19, 300), (1, 7, 33)])
 def test_conv_forward_variants_vs_oracle(B, H, W):
     lib = pat.load()
@@ -70,7 +88,7 @@ def test_conv_forward_variants_vs_oracle(B, H, W):
     scales = [1.0, 0.5, 2.0]
     xs = [cuda32(x[:, c]) for c in range(3)]  # kept alive: descriptors hold raw pointers
     w1g, b1g, a1g = cuda32(w1), cuda32(b1), cuda32(a1)
-    out = torch.zeros((B, H, W, 32), device="cuda")
+    out = torch.zeros((B, H, W, 32), dtype=torch.int16, device="cuda")
     pre = torch.zeros((B, H, W, 32), device="cuda")
     wf = pack(lib, w1g, 32, 3, 0, True)
     d = L._desc(B, H, W, 3, 32, True, False, xs, [out], wf, b1g, a1g, pre, scale=scales)
@@ -78,18 +96,22 @@ def test_conv_forward_variants_vs_oracle(B, H, W):
     xsc = x * np.array(scales).reshape(1, 3, 1, 1)
     ref_pre = OL.conv3x3(torch.tensor(xsc), torch.tensor(w1), torch.tensor(b1)).numpy()
     ref = OL.prelu(torch.tensor(ref_pre), torch.tensor(a1)).numpy()
-    assert rel(nhwc_to_nchw(pre.cpu().numpy()), ref_pre) < TOL_CONV
-    assert rel(nhwc_to_nchw(out.cpu().numpy()), ref) < TOL_CONV
+    got_pre = pre.cpu()
+    assert rel(nhwc_to_nchw(got_pre.numpy()), ref_pre) < TOL_CONV
+    assert rel(nhwc_to_nchw(host16(out)), ref) < TOL_BF16
+    # the stored activation is exactly the nearest-even bf16 of PReLU(pre)
+    act = torch.where(got_pre > 0, got_pre, torch.tensor(a1, dtype=torch.float32) * got_pre)
+    assert torch.equal(act.to(torch.bfloat16).view(torch.int16), out.cpu())
     # NHWC 32 -> NHWC 32, no bias, no activation
-    h = f32(rng.standard_normal((B, H, W, 32)))
+    h = bfv(rng.standard_normal((B, H, W, 32)))
     w2 = f32(0.1 * rng.standard_normal((32, 32, 3, 3)))
-    out2 = torch.zeros((B, H, W, 32), device="cuda")
+    out2 = torch.zeros((B, H, W, 32), dtype=torch.int16, device="cuda")
     w2g = cuda32(w2)
-    hg = cuda32(h)
+    hg = cuda16(h)
     d = L._desc(B, H, W, 32, 32, False, False, [hg], [out2], pack(lib, w2g, 32, 32, 0, False))
     pat._check(lib.pat_conv3x3(ctypes.byref(d), st()), "conv")
     ref2 = OL.conv3x3(torch.tensor(nhwc_to_nchw(h)), torch.tensor(w2)).numpy()
-    assert rel(nhwc_to_nchw(out2.cpu().numpy()), ref2) < TOL_CONV
+    assert rel(nhwc_to_nchw(host16(out2)), ref2) < TOL_BF16
     # NHWC 32 -> planar 1 with bias and residual
     w3 = f32(0.1 * rng.standard_normal((1, 32, 3, 3)))
     b3 = f32([0.37])
@@ -104,29 +126,45 @@ def test_conv_forward_variants_vs_oracle(B, H, W):
 
 @pytest.mark.parametrize("B,H,W", [(2, 19, 300)])
 def test_input_gradient_convolutions_vs_oracle(B, H, W):
-    """pat_conv3x3 with transposed packing = conv_transpose2d of the oracle."""
+    """pat_conv3x3 with transposed packing = conv_transpose2d of the oracle,
+    with the PReLU backward fused into the NHWC epilogue."""
     lib = pat.load()
     rng = np.random.default_rng(7)
-    # layer 3 type: planar 1 -> NHWC 32 (gradient of a 32 -> 1 layer)
+    part = torch.zeros(1 << 20, device="cuda")
+    gba = torch.full((64,), 5.0, device="cuda")
+    # layer 3 type: planar 1 -> NHWC 32, then back through a PReLU (slopes al, pre-activation xp)
     w3 = f32(0.2 * rng.standard_normal((1, 32, 3, 3)))
     gy = f32(rng.standard_normal((B, H, W)))
-    gx = torch.zeros((B, H, W, 32), device="cuda")
-    gyg, w3g = cuda32(gy), cuda32(w3)
-    d = L._desc(B, H, W, 1, 32, True, False, [gyg], [gx], pack(lib, w3g, 1, 32, 1, True))
+    xp = f32(rng.standard_normal((B, H, W, 32)))
+    al = f32(0.1 + 0.3 * rng.random(32))
+    gx = torch.zeros((B, H, W, 32), dtype=torch.int16, device="cuda")
+    gyg, w3g, xpg, alg = cuda32(gy), cuda32(w3), cuda32(xp), cuda32(al)
+    d = L._desc(B, H, W, 1, 32, True, False, [gyg], [gx], pack(lib, w3g, 1, 32, 1, True), alpha=alg, bwd_pre=xpg,
+                partials=part, grad_bias_alpha=gba, accumulate=0)
+    assert lib.pat_conv_bwd_partials(ctypes.byref(d)) <= part.numel()
     pat._check(lib.pat_conv3x3(ctypes.byref(d), st()), "conv")
-    ref = torch.nn.functional.conv_transpose2d(OL.bf16(torch.tensor(gy[:, None])), OL.bf16(torch.tensor(w3)),
-                                               padding=1).numpy()
-    assert rel(nhwc_to_nchw(gx.cpu().numpy()), ref) < TOL_CONV
-    # layer 2 type: NHWC -> NHWC
+    ga = torch.nn.functional.conv_transpose2d(OL.bf16(torch.tensor(gy[:, None])), OL.bf16(torch.tensor(w3)),
+                                              padding=1).numpy()
+    xpn = nhwc_to_nchw(xp)
+    aln = al.reshape(1, 32, 1, 1)
+    ref_gx = np.where(xpn > 0, ga, aln * ga)
+    assert rel(nhwc_to_nchw(host16(gx)), ref_gx) < TOL_BF16
+    assert rel(gba[:32].cpu().numpy(), ref_gx.sum(axis=(0, 2, 3))) < 1e-4
+    assert rel(gba[32:].cpu().numpy(), np.where(xpn > 0, 0.0, ga * xpn).sum(axis=(0, 2, 3))) < 1e-4
+    # accumulate adds
+    d.accumulate = 1
+    pat._check(lib.pat_conv3x3(ctypes.byref(d), st()), "conv")
+    assert rel(gba[:32].cpu().numpy(), 2 * ref_gx.sum(axis=(0, 2, 3))) < 1e-4
+    # layer 2 type: NHWC -> NHWC (plain epilogue: the bf16 input gradient itself)
     w2 = f32(0.1 * rng.standard_normal((32, 32, 3, 3)))
-    g2 = f32(rng.standard_normal((B, H, W, 32)))
-    gx2 = torch.zeros((B, H, W, 32), device="cuda")
-    g2g, w2g = cuda32(g2), cuda32(w2)
+    g2 = bfv(rng.standard_normal((B, H, W, 32)))
+    gx2 = torch.zeros((B, H, W, 32), dtype=torch.int16, device="cuda")
+    g2g, w2g = cuda16(g2), cuda32(w2)
     d = L._desc(B, H, W, 32, 32, False, False, [g2g], [gx2], pack(lib, w2g, 32, 32, 1, False))
     pat._check(lib.pat_conv3x3(ctypes.byref(d), st()), "conv")
-    ref = torch.nn.functional.conv_transpose2d(OL.bf16(torch.tensor(nhwc_to_nchw(g2))), OL.bf16(torch.tensor(w2)),
+    ref = torch.nn.functional.conv_transpose2d(torch.tensor(nhwc_to_nchw(g2)), OL.bf16(torch.tensor(w2)),
                                                padding=1).numpy()
-    assert rel(nhwc_to_nchw(gx2.cpu().numpy()), ref) < TOL_CONV
+    assert rel(nhwc_to_nchw(host16(gx2)), ref) < TOL_BF16
     # layer 1 type: NHWC -> planar 3 with output scales, residual on plane 0, plane 2 skipped
     w1 = f32(0.3 * rng.standard_normal((32, 3, 3, 3)))
     res = f32(rng.standard_normal((B, H, W)))
@@ -136,7 +174,7 @@ def test_input_gradient_convolutions_vs_oracle(B, H, W):
     d = L._desc(B, H, W, 32, 3, False, True, [g2g], [o0, o1, None], pack(lib, w1g, 32, 3, 1, False),
                 residual=[resg, None, None], scale=[1.0, 0.5, 2.0])
     pat._check(lib.pat_conv3x3(ctypes.byref(d), st()), "conv")
-    ref = torch.nn.functional.conv_transpose2d(OL.bf16(torch.tensor(nhwc_to_nchw(g2))), OL.bf16(torch.tensor(w1)),
+    ref = torch.nn.functional.conv_transpose2d(torch.tensor(nhwc_to_nchw(g2)), OL.bf16(torch.tensor(w1)),
                                                padding=1).numpy()
     assert rel(o0.cpu().numpy(), res + ref[:, 0]) < TOL_CONV
     assert rel(o1.cpu().numpy(), 0.5 * ref[:, 1]) < TOL_CONV
@@ -149,18 +187,18 @@ def test_weight_gradients_vs_oracle():
     part = torch.zeros(4 << 20, device="cuda")
     # planar 3 (scaled) -> 32
     x = f32(rng.standard_normal((B, 3, H, W)))
-    g = f32(rng.standard_normal((B, H, W, 32)))
+    g = bfv(rng.standard_normal((B, H, W, 32)))
     gw = torch.zeros(32 * 3 * 9, device="cuda")
     scales = [1.0, 0.5, 2.0]
     xg = [cuda32(x[:, c]) for c in range(3)]
-    gg = cuda32(g)
+    gg = cuda16(g)
     d = L._desc(B, H, W, 3, 32, True, False, xg, [], None, scale=scales)
     d.weight = 1  # not read by the weight gradient; must be non-null for validation
     assert lib.pat_conv_wgrad_partials(ctypes.byref(d), rows) <= part.numel()
     pat._check(lib.pat_conv3x3_wgrad(ctypes.byref(d), gg.data_ptr(), rows, part.data_ptr(), gw.data_ptr(), 0,
                                      st()), "wgrad")
     xsc = x * np.array(scales).reshape(1, 3, 1, 1)
-    ref = torch.nn.grad.conv2d_weight(OL.bf16(torch.tensor(xsc)), (32, 3, 3, 3), OL.bf16(torch.tensor(nhwc_to_nchw(g))),
+    ref = torch.nn.grad.conv2d_weight(OL.bf16(torch.tensor(xsc)), (32, 3, 3, 3), torch.tensor(nhwc_to_nchw(g)),
                                       padding=1).numpy()
     assert rel(gw.cpu().numpy(), ref) < TOL_CONV
     # accumulate: a second call adds
@@ -168,15 +206,15 @@ def test_weight_gradients_vs_oracle():
                                      st()), "wgrad")
     assert rel(gw.cpu().numpy(), 2 * ref) < TOL_CONV
     # NHWC 32 -> 32
-    h = f32(rng.standard_normal((B, H, W, 32)))
+    h = bfv(rng.standard_normal((B, H, W, 32)))
     gw2 = torch.zeros(32 * 32 * 9, device="cuda")
-    hg = cuda32(h)
+    hg = cuda16(h)
     d = L._desc(B, H, W, 32, 32, False, False, [hg], [], None)
     d.weight = 1
     pat._check(lib.pat_conv3x3_wgrad(ctypes.byref(d), gg.data_ptr(), rows, part.data_ptr(), gw2.data_ptr(), 0,
                                      st()), "wgrad")
-    ref2 = torch.nn.grad.conv2d_weight(OL.bf16(torch.tensor(nhwc_to_nchw(h))), (32, 32, 3, 3),
-                                       OL.bf16(torch.tensor(nhwc_to_nchw(g))), padding=1).numpy()
+    ref2 = torch.nn.grad.conv2d_weight(torch.tensor(nhwc_to_nchw(h)), (32, 32, 3, 3),
+                                       torch.tensor(nhwc_to_nchw(g)), padding=1).numpy()
     assert rel(gw2.cpu().numpy(), ref2) < TOL_CONV
     # NHWC 32 -> planar 1
     g1 = f32(rng.standard_normal((B, H, W)))
@@ -186,28 +224,15 @@ def test_weight_gradients_vs_oracle():
     d.weight = 1
     pat._check(lib.pat_conv3x3_wgrad(ctypes.byref(d), g1g.data_ptr(), rows, part.data_ptr(), gw3.data_ptr(), 0,
                                      st()), "wgrad")
-    ref3 = torch.nn.grad.conv2d_weight(OL.bf16(torch.tensor(nhwc_to_nchw(h))), (1, 32, 3, 3),
+    ref3 = torch.nn.grad.conv2d_weight(torch.tensor(nhwc_to_nchw(h)), (1, 32, 3, 3),
                                        OL.bf16(torch.tensor(g1[:, None])), padding=1).numpy()
     assert rel(gw3.cpu().numpy(), ref3) < TOL_CONV
 
 
-def test_prelu_backward_and_bias_sums():
+def test_plane_sums():
     lib = pat.load()
     rng = np.random.default_rng(3)
-    npix = 3 * 17 * 29
-    ga = f32(rng.standard_normal((npix, 32)))
-    x = f32(rng.standard_normal((npix, 32)))
-    al = f32(0.1 + 0.3 * rng.random(32))
-    gx = torch.zeros((npix, 32), device="cuda")
     part = torch.zeros(64 * 37, device="cuda")
-    gba = torch.zeros(64, device="cuda")
-    gag, xg, alg = cuda32(ga), cuda32(x), cuda32(al)  # kept alive while the kernel may run
-    pat._check(lib.pat_prelu_backward(npix, gag.data_ptr(), xg.data_ptr(), alg.data_ptr(),
-                                      gx.data_ptr(), part.data_ptr(), 37, gba.data_ptr(), 0, st()), "prelu")
-    want = np.where(x > 0, ga, al * ga)
-    assert np.array_equal(gx.cpu().numpy(), want.astype(np.float32))
-    assert rel(gba[:32].cpu().numpy(), want.sum(0)) < 1e-5
-    assert rel(gba[32:].cpu().numpy(), np.where(x > 0, 0.0, ga * x).sum(0)) < 1e-5
     s = torch.zeros(1, device="cuda")
     v = f32(rng.standard_normal(12345))
     vg = cuda32(v)
