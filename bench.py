@@ -65,8 +65,8 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-SHAPE_KEYS = ["tune_fft_radix_log2", "tune_cols_per_block", "tune_dct_cols_per_block", "tune_ring_images",
-              "tune_spread_images"]
+SHAPE_KEYS = ["tune_fft_radix_log2", "tune_twiddle_table", "tune_cols_per_block", "tune_dct_cols_per_block",
+              "tune_ring_images", "tune_spread_images"]
 
 
 def measured_traffic(kernel: str, B: int, shapes: dict = None):

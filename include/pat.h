@@ -114,6 +114,8 @@ typedef struct {
     int tune_dct_cols_per_block;  /* harmonics per cosine-transform block           */
     int tune_ring_images;         /* images per ring-gather block                   */
     int tune_spread_images;       /* images per spread group                        */
+    int tune_twiddle_table;       /* 1: FFT passes read every twiddle from a table,
+                                     0: derive them from four table entries         */
     int tuned;                    /* 0 defaults, 1 measured at creation, 2 cached   */
     double tuned_ms;              /* forward + adjoint ms at max_batch when tuned   */
 } pat_plan_info;
@@ -126,8 +128,8 @@ typedef struct {
  * the plan looks up its key (device architecture, dtype, geometry, max_batch)
  * in that text file (one line per entry, "key | choices"; the last matching
  * line wins); if absent it times the candidate launch shapes (FFT pass radix,
- * columns per transform block, images per ring-gather block and per spread
- * group) one choice at a time with forward + adjoint at max_batch, keeps the
+ * twiddle source, columns per transform block, images per ring-gather block
+ * and per spread group) one choice at a time with forward + adjoint at max_batch, keeps the
  * fastest, and appends a line.  A missing or unreadable file is treated as
  * empty; a line that fails validation is ignored.  The search allocates and
  * frees a temporary workspace.

@@ -167,9 +167,23 @@ __device__ __forceinline__ void dft_reg<float, 16>(cx<float>* v, bool inv) { dft
 template <>
 __device__ __forceinline__ void dft_reg<double, 16>(cx<double>* v, bool inv) { dft_split<double, 16>(v, inv); }
 
+// The transform buffer is passed as an LDS (address space 3) pointer and the
+// twiddle table as a global (address space 1) pointer: the pass is not
+// inlined, and with generic pointers every access would become a FLAT
+// instruction with 64-bit address arithmetic.
+#define PAT_LDS __attribute__((address_space(3)))
+#define PAT_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ cx<T> ld_lds(const PAT_LDS cx<T>* p) { return {p->x, p->y}; }
+template <typename T>
+__device__ __forceinline__ void st_lds(PAT_LDS cx<T>* p, cx<T> v) { p->x = v.x; p->y = v.y; }
+template <typename T>
+__device__ __forceinline__ cx<T> ld_glb(const PAT_GLOBAL cx<T>* p) { return {p->x, p->y}; }
+
 template <typename T, int R>
-__device__ __noinline__ void stockham_pass(cx<T>* buf, int logN, int logNs, int nb, int stride,
-                                              const cx<T>* __restrict__ tw, int logNmax, bool inv)
+__device__ __noinline__ void stockham_pass(PAT_LDS cx<T>* buf, int logN, int logNs, int nb, int stride,
+                                              const PAT_GLOBAL cx<T>* __restrict__ tw, int logNmax, bool inv, bool twtab)
 {
     constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
     constexpr int BPT = FFT_REGS / R;
@@ -182,9 +196,9 @@ __device__ __noinline__ void stockham_pass(cx<T>* buf, int logN, int logNs, int 
         const int it = threadIdx.x + u * NT;
         if (it < total) {
             const int b = it >> lnbf, t = it & (nbf - 1);
-            const cx<T>* s = buf + b * stride;
+            const PAT_LDS cx<T>* s = buf + b * stride;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[u][r] = s[t + (r << lnbf)];
+            for (int r = 0; r < R; ++r) v[u][r] = ld_lds(s + t + (r << lnbf));
         }
     }
     __syncthreads();
@@ -195,34 +209,44 @@ __device__ __noinline__ void stockham_pass(cx<T>* buf, int logN, int logNs, int 
             const int b = it >> lnbf, t = it & (nbf - 1);
             const int k = t & ((1 << logNs) - 1);
             if (logNs > 0) {
-                // W^r for r = 1..R-1 from the table entries W^1, W^2, W^4, W^8 (at
-                // most three products each), instead of R-1 table reads
                 const int sh = logNmax - logNs - LR;
-                cx<T> wp[LR];
+                if (twtab) {
+                    // W^r read from the table for every r
 #pragma unroll
-                for (int e = 0; e < LR; ++e) {
-                    wp[e] = tw[(k << e) << sh];
-                    if (inv) wp[e].y = -wp[e].y;
-                }
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    cx<T> w = {T(1), T(0)};
-                    bool first = true;
+                    for (int r = 1; r < R; ++r) {
+                        cx<T> w = ld_glb(tw + ((r * k) << sh));
+                        if (inv) w.y = -w.y;
+                        v[u][r] = cmul(v[u][r], w);
+                    }
+                } else {
+                    // W^r for r = 1..R-1 from the table entries W^1, W^2, W^4, W^8 (at
+                    // most three products each): fewer table reads, more arithmetic
+                    cx<T> wp[LR];
 #pragma unroll
                     for (int e = 0; e < LR; ++e) {
-                        if (r & (1 << e)) {
-                            w = first ? wp[e] : cmul(w, wp[e]);
-                            first = false;
-                        }
+                        wp[e] = ld_glb(tw + ((k << e) << sh));
+                        if (inv) wp[e].y = -wp[e].y;
                     }
-                    v[u][r] = cmul(v[u][r], w);
+#pragma unroll
+                    for (int r = 1; r < R; ++r) {
+                        cx<T> w = {T(1), T(0)};
+                        bool first = true;
+#pragma unroll
+                        for (int e = 0; e < LR; ++e) {
+                            if (r & (1 << e)) {
+                                w = first ? wp[e] : cmul(w, wp[e]);
+                                first = false;
+                            }
+                        }
+                        v[u][r] = cmul(v[u][r], w);
+                    }
                 }
             }
             dft_reg<T, R>(v[u], inv);
-            cx<T>* s = buf + b * stride;
+            PAT_LDS cx<T>* s = buf + b * stride;
             const int base = ((t >> logNs) << (logNs + LR)) + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) s[base + (r << logNs)] = v[u][r];
+            for (int r = 0; r < R; ++r) st_lds(s + base + (r << logNs), v[u][r]);
         }
     }
     __syncthreads();
@@ -230,18 +254,20 @@ __device__ __noinline__ void stockham_pass(cx<T>* buf, int logN, int logNs, int 
 
 template <typename T>
 __device__ void lds_fft(cx<T>* buf, int logN, int nb, int stride, const cx<T>* __restrict__ tw, int logNmax,
-                        bool inverse, int maxlr)
+                        bool inverse, int maxlr, bool twtab)
 {
     if (logN == 0) return;
     const int P = (logN + maxlr - 1) / maxlr;  // passes; radices as equal as possible, at most 2^maxlr
+    PAT_LDS cx<T>* lbuf = (PAT_LDS cx<T>*)buf;
+    const PAT_GLOBAL cx<T>* gtw = (const PAT_GLOBAL cx<T>*)tw;
     int logNs = 0;
     for (int p = 0; p < P; ++p) {
         const int lr = logN / P + (p < logN % P ? 1 : 0);
         switch (lr) {
-            case 1: stockham_pass<T, 2>(buf, logN, logNs, nb, stride, tw, logNmax, inverse); break;
-            case 2: stockham_pass<T, 4>(buf, logN, logNs, nb, stride, tw, logNmax, inverse); break;
-            case 3: stockham_pass<T, 8>(buf, logN, logNs, nb, stride, tw, logNmax, inverse); break;
-            default: stockham_pass<T, 16>(buf, logN, logNs, nb, stride, tw, logNmax, inverse); break;
+            case 1: stockham_pass<T, 2>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab); break;
+            case 2: stockham_pass<T, 4>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab); break;
+            case 3: stockham_pass<T, 8>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab); break;
+            default: stockham_pass<T, 16>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab); break;
         }
         logNs += lr;
     }
@@ -291,6 +317,7 @@ struct Dev {
     int colsCW, dctCW;
     int dct_stash;              // 1: the cosine transform stashes its input columns in LDS
     int fft_lr;                 // largest FFT pass radix is 2^fft_lr (3 or 4)
+    int tw_table;               // 1: FFT passes read every twiddle from the table
     T beta, shift, half;        // half = Ng / (2 Lambda): grid cells per unit lambda
     T beta_l2e;                 // beta * log2(e)
     T lamh;                     // h: u = lambda h cos(phi)
@@ -408,7 +435,7 @@ __device__ __forceinline__ void rows_fwd_body(const Dev<T>& d, Blk bk, const T* 
         buf[qi] = {a, c};
     }
     __syncthreads();
-    lds_fft(buf, d.logNg, 1, 0, d.tw, d.logNmax, false, d.fft_lr);
+    lds_fft(buf, d.logNg, 1, 0, d.tw, d.logNmax, false, d.fft_lr, d.tw_table);
     for (int g = threadIdx.x; g <= Ng / 2; g += blockDim.x) {
         cx<T> zg = buf[g], zm = buf[(Ng - g) & (Ng - 1)];
         cx<T> x1 = {T(0.5) * (zg.x + zm.x), T(0.5) * (zg.y - zm.y)};
@@ -445,7 +472,7 @@ __device__ __forceinline__ void cols_fwd_body(const Dev<T>& d, Blk bk, const cx<
         if (gx < d.Rw) buf[c * Ng + ((p - n / 2 + Ng) & (Ng - 1))] = Rb[(size_t)p * d.Rw + gx];
     }
     __syncthreads();
-    lds_fft(buf, d.logNg, CW, Ng, d.tw, d.logNmax, false, d.fft_lr);
+    lds_fft(buf, d.logNg, CW, Ng, d.tw, d.logNmax, false, d.fft_lr, d.tw_table);
     for (int i = threadIdx.x; i < CW * Ng; i += blockDim.x) {
         int gy = i / CW, c = i - gy * CW;
         int gx = x0 + c;
@@ -503,7 +530,7 @@ __device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<
     __syncthreads();
     const int per_call = max(1, min(nb, FFT_BLOCK_POINTS >> logN));
     for (int i = 0; i < nb; i += per_call)
-        lds_fft(buf + i * N, logN, min(per_call, nb - i), N, d.tw, d.logNmax, false, d.fft_lr);
+        lds_fft(buf + i * N, logN, min(per_call, nb - i), N, d.tw, d.logNmax, false, d.fft_lr, d.tw_table);
     const T invN = T(1) / T(N);
     for (int i = 0; i < nb; ++i) {
         const cx<T>* bi = buf + i * N;
@@ -574,7 +601,7 @@ __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<
             buf[c * M + xs] = acc;
         }
         __syncthreads();
-        lds_fft(buf, logM, CW, M, d.tw, d.logNmax, true, d.fft_lr);
+        lds_fft(buf, logM, CW, M, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
         // output rows of parity r only: y = orow (+ 1 in the forward), y = 2 y' + r
         const int o0 = adjoint ? r : 1 - r;
         const int nr = o0 < nout ? (nout - o0 + 1) / 2 : 0;
@@ -658,7 +685,7 @@ __device__ __forceinline__ void synth_fwd_body(const Dev<T>& d, Blk bk, const cx
         if (rm != r) Z1[rm] = {h1.x + h2.y, h2.x - h1.y};
     }
     __syncthreads();
-    lds_fft(Z1, d.logmf, 1, 0, d.tw, d.logNmax, true, d.fft_lr);
+    lds_fft(Z1, d.logmf, 1, 0, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
     for (int i = threadIdx.x; i < d.m; i += blockDim.x) {
         gb[(size_t)j1 * d.m + i] = Z1[i].x;
         if (has2) gb[(size_t)j2 * d.m + i] = Z1[i].y;
@@ -693,7 +720,7 @@ __device__ __forceinline__ void synth_adj_body(const Dev<T>& d, Blk bk, const T*
         Z[i] = {a, c};
     }
     __syncthreads();
-    lds_fft(Z, d.logmf, 1, 0, d.tw, d.logNmax, false, d.fft_lr);
+    lds_fft(Z, d.logmf, 1, 0, d.tw, d.logNmax, false, d.fft_lr, d.tw_table);
     for (int k = threadIdx.x; k < d.Kp; k += blockDim.x) {
         cx<T> y1 = {T(0), T(0)}, y2 = {T(0), T(0)};
         if (k <= d.K) {
@@ -774,7 +801,7 @@ __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<
     __syncthreads();
     const int per_call = max(1, min(nb, FFT_BLOCK_POINTS >> logN));
     for (int i = 0; i < nb; i += per_call)
-        lds_fft(buf + i * N, logN, min(per_call, nb - i), N, d.tw, d.logNmax, true, d.fft_lr);
+        lds_fft(buf + i * N, logN, min(per_call, nb - i), N, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
     const int off = d.ringOff[l];
     for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
         const int s = si - N / 4;
@@ -971,7 +998,7 @@ __device__ __forceinline__ void cols_adj_body(const Dev<T>& d, Blk bk, const cx<
         buf[c * Ng + gy] = v;
     }
     __syncthreads();
-    lds_fft(buf, d.logNg, CW, Ng, d.tw, d.logNmax, true, d.fft_lr);
+    lds_fft(buf, d.logNg, CW, Ng, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
     for (int i = threadIdx.x; i < CW * n; i += blockDim.x) {
         int p = i / CW, c = i - p * CW;
         int gx = x0 + c;
@@ -1013,7 +1040,7 @@ __device__ __forceinline__ void rows_adj_body(const Dev<T>& d, Blk bk, const cx<
         buf[g] = {xa.x - xb.y, xa.y + xb.x};
     }
     __syncthreads();
-    lds_fft(buf, d.logNg, 1, 0, d.tw, d.logNmax, true, d.fft_lr);
+    lds_fft(buf, d.logNg, 1, 0, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
     const T s1 = d.Dq[p1] * d.pre_scale * d.adj_scale;
     const T s2 = has2 ? d.Dq[p2] * d.pre_scale * d.adj_scale : T(0);
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
@@ -1046,7 +1073,7 @@ struct pat_plan_s {
     Dev<float> df{};
     Dev<double> dd{};
     // launch-shape choices (defaults from LDS limits; replaced by the autotuner's)
-    int cols_cw = 1, dct_cw = 1, ring_g = 1, spread_bc = 16, fft_lr = 4;
+    int cols_cw = 1, dct_cw = 1, ring_g = 1, spread_bc = 16, fft_lr = 4, tw_table = 0;
     int tuned = 0;                        // 1: measured now, 2: read from the tuning cache
     double tuned_ms = 0.0;
     // optional per-stage timing with HIP events recorded on the launch stream
@@ -1168,6 +1195,7 @@ int upload(pat_plan_s* p, Dev<T>& d)
     d.dctCW = p->dct_cw;
     d.dct_stash = dct_stash_ok(P, p->dct_cw);
     d.fft_lr = p->fft_lr;
+    d.tw_table = p->tw_table;
     d.beta = (T)P.beta; d.beta_l2e = (T)(P.beta * 1.4426950408889634); d.shift = (T)P.shift; d.half = (T)(0.5 * P.Ng / P.Lam); d.lamh = (T)P.h;
     d.dlam = (T)P.dlam; d.pre_scale = (T)P.pre_scale; d.adj_scale = (T)P.adj_scale;
     d.mask_r2 = P.g.mask_radius > 0 ? P.g.mask_radius * P.g.mask_radius : 0.0;
@@ -1515,6 +1543,7 @@ void default_tune(pat_plan_s* p)
     p->ring_g = ring_group_max(P);
     p->spread_bc = (P.dt == PAT_F64) ? 8 : 16;
     p->fft_lr = 4;
+    p->tw_table = 0;
 }
 
 void apply_tune(pat_plan_s* p)
@@ -1522,6 +1551,7 @@ void apply_tune(pat_plan_s* p)
     p->df.colsCW = p->dd.colsCW = p->cols_cw;
     p->df.dctCW = p->dd.dctCW = p->dct_cw;
     p->df.fft_lr = p->dd.fft_lr = p->fft_lr;
+    p->df.tw_table = p->dd.tw_table = p->tw_table;
     p->df.dct_stash = p->dd.dct_stash = dct_stash_ok(p->H.P, p->dct_cw);
 }
 
@@ -1532,7 +1562,8 @@ bool tune_valid(const pat_plan_s* p)
     const pat::Params& P = p->H.P;
     const int bcl = (P.dt == PAT_F64) ? 8 : 16;
     return pow2_in(p->cols_cw, lds_cols(P)) && pow2_in(p->dct_cw, lds_dct(P)) && pow2_in(p->ring_g, ring_group_max(P)) &&
-           (p->spread_bc == bcl || p->spread_bc == bcl / 2) && (p->fft_lr == 3 || p->fft_lr == 4);
+           (p->spread_bc == bcl || p->spread_bc == bcl / 2) && (p->fft_lr == 3 || p->fft_lr == 4) &&
+           (p->tw_table == 0 || p->tw_table == 1);
 }
 
 std::string tune_key(const pat_plan_s* p)
@@ -1565,11 +1596,14 @@ bool tune_lookup(pat_plan_s* p, const char* path, const std::string& key)
         if (bar == std::string::npos || l.compare(0, bar, key) != 0 || bar != key.size()) continue;
         pat_plan_s t = *p;
         double ms = 0;
-        if (std::sscanf(l.c_str() + bar + 3, "cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=%lf",
-                        &t.cols_cw, &t.dct_cw, &t.ring_g, &t.spread_bc, &t.fft_lr, &ms) == 6 &&
-            tune_valid(&t)) {
+        t.tw_table = 0;
+        const int got = std::sscanf(l.c_str() + bar + 3,
+                                    "cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=%lf "
+                                    "twiddle_table=%d",
+                                    &t.cols_cw, &t.dct_cw, &t.ring_g, &t.spread_bc, &t.fft_lr, &ms, &t.tw_table);
+        if ((got == 6 || got == 7) && tune_valid(&t)) {
             p->cols_cw = t.cols_cw; p->dct_cw = t.dct_cw; p->ring_g = t.ring_g;
-            p->spread_bc = t.spread_bc; p->fft_lr = t.fft_lr; p->tuned_ms = ms;
+            p->spread_bc = t.spread_bc; p->fft_lr = t.fft_lr; p->tw_table = t.tw_table; p->tuned_ms = ms;
             found = true;  // keep scanning: the last matching line wins
         }
     }
@@ -1581,8 +1615,8 @@ void tune_store(const pat_plan_s* p, const char* path, const std::string& key)
 {
     FILE* fp = std::fopen(path, "a");
     if (!fp) return;
-    std::fprintf(fp, "%s | cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=%.6f\n", key.c_str(),
-                 p->cols_cw, p->dct_cw, p->ring_g, p->spread_bc, p->fft_lr, p->tuned_ms);
+    std::fprintf(fp, "%s | cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=%.6f twiddle_table=%d\n",
+                 key.c_str(), p->cols_cw, p->dct_cw, p->ring_g, p->spread_bc, p->fft_lr, p->tuned_ms, p->tw_table);
     std::fclose(fp);
 }
 
@@ -1643,6 +1677,7 @@ int tune_search(pat_plan_s* p, const Dev<T>& d)
     for (int v = lds_dct(P); v >= 1; v >>= 1) dw.push_back(v);
     for (int v = ring_group_max(P); v >= 1; v >>= 1) rg.push_back(v);
     std::vector<Choice> choices = {{&p->fft_lr, {4, 3}},
+                                   {&p->tw_table, {0, 1}},
                                    {&p->cols_cw, cw},
                                    {&p->dct_cw, dw},
                                    {&p->ring_g, rg},
@@ -1705,6 +1740,7 @@ void fill_info(const pat::Params& P, pat_plan_info* info, size_t ws_img, size_t 
         info->tune_dct_cols_per_block = p->dct_cw;
         info->tune_ring_images = p->ring_g;
         info->tune_spread_images = p->spread_bc;
+        info->tune_twiddle_table = p->tw_table;
         info->tuned = p->tuned;
         info->tuned_ms = p->tuned_ms;
     }

@@ -30,8 +30,8 @@ def test_tuner_measures_stores_and_reuses(tmp_path):
     assert len(lines) == 1 and " | " in lines[0]
     b = pat.Plan(geom, torch.float32, max_batch=5, tuning_cache=path)
     assert b.info["tuned"] == 2
-    keys = ["tune_fft_radix_log2", "tune_cols_per_block", "tune_dct_cols_per_block", "tune_ring_images",
-            "tune_spread_images"]
+    keys = ["tune_fft_radix_log2", "tune_twiddle_table", "tune_cols_per_block", "tune_dct_cols_per_block",
+            "tune_ring_images", "tune_spread_images"]
     assert [a.info[k] for k in keys] == [b.info[k] for k in keys]
     assert len(open(path).read().splitlines()) == 1
     # another batch size is another key
@@ -55,21 +55,22 @@ def test_every_launch_shape_meets_parity(tmp_path, dt):
     pat.Plan(geom, tdt, max_batch=B, tuning_cache=path)
     key = open(path).read().splitlines()[0].split(" | ")[0]
     bcl = base.info["tune_spread_images"]
-    shapes = [(3, 1, 1, 1, bcl // 2), (4, 1, base.info["tune_dct_cols_per_block"], 2, bcl),
-              (3, base.info["tune_cols_per_block"], 1, base.info["tune_ring_images"], bcl // 2)]
+    shapes = [(3, 1, 1, 1, bcl // 2, 1), (4, 1, base.info["tune_dct_cols_per_block"], 2, bcl, 0),
+              (3, base.info["tune_cols_per_block"], 1, base.info["tune_ring_images"], bcl // 2, 0),
+              (4, base.info["tune_cols_per_block"], base.info["tune_dct_cols_per_block"], 1, bcl, 1)]
     f = torch.tensor(f_np, dtype=tdt, device="cuda")
     g = torch.tensor(g_np, dtype=tdt, device="cuda")
-    for lr, cw, dw, rg, sb in shapes:
+    for lr, cw, dw, rg, sb, tt in shapes:
         with open(path, "a") as fp:
-            fp.write("%s | cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=1.0\n"
-                     % (key, cw, dw, rg, sb, lr))
+            fp.write("%s | cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=1.0 "
+                     "twiddle_table=%d\n" % (key, cw, dw, rg, sb, lr, tt))
         plan = pat.Plan(geom, tdt, max_batch=B, tuning_cache=path)
         got = [plan.info[k] for k in ("tune_fft_radix_log2", "tune_cols_per_block", "tune_dct_cols_per_block",
-                                      "tune_ring_images", "tune_spread_images")]
-        assert plan.info["tuned"] == 2 and got == [lr, cw, dw, rg, sb]
+                                      "tune_ring_images", "tune_spread_images", "tune_twiddle_table")]
+        assert plan.info["tuned"] == 2 and got == [lr, cw, dw, rg, sb, tt]
         ef = rel(plan.forward(f).cpu().numpy(), ref_f)
         ea = rel(plan.adjoint(g).cpu().numpy(), ref_a)
-        print(dt, (lr, cw, dw, rg, sb), "forward %.2e adjoint %.2e" % (ef, ea))
+        print(dt, (lr, cw, dw, rg, sb, tt), "forward %.2e adjoint %.2e" % (ef, ea))
         assert ef < tol and ea < tol
 
 
