@@ -66,7 +66,7 @@ def kernel_source_hash() -> str:
 
 
 SHAPE_KEYS = ["tune_fft_radix_log2", "tune_twiddle_table", "tune_cols_per_block", "tune_dct_cols_per_block",
-              "tune_ring_images", "tune_spread_images"]
+              "tune_ring_images", "tune_spread_images", "tune_spread_staged"]
 
 
 def measured_traffic(kernel: str, B: int, shapes: dict = None):

@@ -315,11 +315,13 @@ struct Dev {
     int M, log2M, L, K, Kp, klow, lcorr, npts;
     int logNmax;
     int colsCW, dctCW;
+    int colsLCW, dctLCW;        // log2 of the two (powers of two)
     int dct_stash;              // 1: the cosine transform stashes its input columns in LDS
     int fft_lr;                 // largest FFT pass radix is 2^fft_lr (3 or 4)
     int tw_table;               // 1: FFT passes read every twiddle from the table
     T beta, shift, half;        // half = Ng / (2 Lambda): grid cells per unit lambda
     T beta_l2e;                 // beta * log2(e)
+    T phase_k;                  // -shift * h / half: point phase per grid cell of x + y
     T lamh;                     // h: u = lambda h cos(phi)
     T dlam, pre_scale, adj_scale;
     double mask_r2, a, h;       // mask test in double (same decision as the oracle)
@@ -387,7 +389,7 @@ template <typename T>
 __device__ __forceinline__ cx<T> point_phase(const Dev<T>& d, T x, T y)
 {
     T ps, pc;
-    sincos_t(-d.shift * d.lamh * (x + y) / d.half, &ps, &pc);
+    sincos_t(d.phase_k * (x + y), &ps, &pc);
     return {pc, ps};
 }
 
@@ -460,21 +462,21 @@ __device__ __forceinline__ void cols_fwd_body(const Dev<T>& d, Blk bk, const cx<
     int bx_, b;
     bx_ = bk.x;
     b = bk.y;
-    const int CW = d.colsCW, x0 = bx_ * CW;
+    const int CW = d.colsCW, lcw = d.colsLCW, x0 = bx_ * CW;
     const int Ng = d.Ng, n = d.n;
     const cx<T>* Rb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(R) + (size_t)b * ws_img);
     cx<T>* Eb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(E) + (size_t)b * ws_img);
     for (int i = threadIdx.x; i < CW * Ng; i += blockDim.x) buf[i] = {T(0), T(0)};
     __syncthreads();
     for (int i = threadIdx.x; i < CW * n; i += blockDim.x) {
-        int p = i / CW, c = i - p * CW;
+        int p = i >> lcw, c = i & (CW - 1);
         int gx = x0 + c;
         if (gx < d.Rw) buf[c * Ng + ((p - n / 2 + Ng) & (Ng - 1))] = Rb[(size_t)p * d.Rw + gx];
     }
     __syncthreads();
     lds_fft(buf, d.logNg, CW, Ng, d.tw, d.logNmax, false, d.fft_lr, d.tw_table);
     for (int i = threadIdx.x; i < CW * Ng; i += blockDim.x) {
-        int gy = i / CW, c = i - gy * CW;
+        int gy = i >> lcw, c = i & (CW - 1);
         int gx = x0 + c;
         if (gx >= d.Rw) continue;
         cx<T> v = buf[c * Ng + gy];
@@ -565,7 +567,7 @@ __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<
     extern __shared__ unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     const int bx_ = bk.x, b = bk.y;
-    const int CW = d.dctCW, k0 = bx_ * CW;
+    const int CW = d.dctCW, lcw = d.dctLCW, k0 = bx_ * CW;
     const int M = d.M, logM = d.log2M;
     const cx<T>* ib = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(in) + (size_t)b * ws_img);
     cx<T>* ob = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(out) + (size_t)b * ws_img);
@@ -579,7 +581,7 @@ __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<
     cx<T>* stash = buf + CW * M;
     if (d.dct_stash) {
         for (int i = threadIdx.x; i < CW * nx; i += blockDim.x) {
-            const int row = i / CW, c = i - row * CW;
+            const int row = i >> lcw, c = i & (CW - 1);
             const int k = k0 + c;
             stash[c * nx + row] = k < d.Kp ? ib[(size_t)row * d.Kp + k] : cx<T>{T(0), T(0)};
         }
@@ -587,7 +589,7 @@ __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<
     }
     for (int r = 0; r < 2; ++r) {
         for (int i = threadIdx.x; i < CW * M; i += blockDim.x) {
-            const int xs = i / CW, c = i - xs * CW;  // slot xs = x mod M
+            const int xs = i >> lcw, c = i & (CW - 1);  // slot xs = x mod M
             const int k = k0 + c;
             cx<T> acc = {T(0), T(0)};
             if (k < d.Kp) {
@@ -606,7 +608,7 @@ __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<
         const int o0 = adjoint ? r : 1 - r;
         const int nr = o0 < nout ? (nout - o0 + 1) / 2 : 0;
         for (int i = threadIdx.x; i < CW * nr; i += blockDim.x) {
-            const int j = i / CW, c = i - j * CW;
+            const int j = i >> lcw, c = i & (CW - 1);
             const int orow = o0 + 2 * j;
             const int k = k0 + c;
             if (k >= d.Kp) continue;
@@ -836,10 +838,12 @@ __global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const c
 // current sample are the same for every lane (scalar loads, one cache line),
 // each lane tests the tap rule for its own cell and accumulates weight *
 // value.  No atomics; a fixed summation order per cell.
-template <typename T, int W, int BC>
+template <typename T, int W, int BC, bool STAGED>
 __device__ __forceinline__ void spread_tiles_body(const Dev<T>& d, Blk bk, const cx<T>* Pol, int B, cx<T>* E, size_t ws_img)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ cx<T> st_pos[STAGED ? 4 : 1][64];
+    __shared__ cx<T> st_val[STAGED ? 4 : 1][STAGED ? 64 * BC : 1];
     int bxt, byt;
     bxt = bk.x;
     byt = bk.y;
@@ -917,6 +921,40 @@ __device__ __forceinline__ void spread_tiles_body(const Dev<T>& d, Blk bk, const
                         const int plo = __builtin_amdgcn_readlane(part ? v_lo : u_lo, r);
                         const int phi = __builtin_amdgcn_readlane(part ? v_hi : u_hi, r);
                         if (plo > phi) continue;
+                        if constexpr (STAGED) {
+                            // up to 64 samples at a time: lane j stages sample base + j (its
+                            // position and BC image values, coalesced vector loads) in the
+                            // wave's LDS slots, then the wave walks them in lockstep reading
+                            // LDS (uniform addresses: broadcast).  Only this wave touches its
+                            // slots, so ordering within the wave is all that is needed.
+                            for (int base = plo; base <= phi; base += 64) {
+                                const int cnt = min(64, phi - base + 1);
+                                __builtin_amdgcn_wave_barrier();
+                                if (lane < cnt) {
+                                    const cx<T>* src = Pol + (size_t)(base + lane) * B + b0;
+                                    st_pos[wave][lane] = d.pos[base + lane];
+#pragma unroll
+                                    for (int k = 0; k < BC; ++k) st_val[wave][lane * BC + k] = src[k];
+                                }
+                                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                                __builtin_amdgcn_wave_barrier();
+                                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                                for (int j = 0; j < cnt; ++j) {
+                                    const cx<T> q = st_pos[wave][j];
+                                    const int gx0 = (int)ceil_t(q.x - hwf);
+                                    const int gy0 = (int)ceil_t(q.y - hwf);
+                                    const int jx = gx - gx0;
+                                    const int jy = (gy - gy0) & mask;
+                                    if (valid && (unsigned)jx < (unsigned)W && jy < W) {
+                                        const T wgt = es_w(q.x - T(gx0 + jx), tw_, d.beta, d.beta_l2e) *
+                                                      es_w(q.y - T(gy0 + jy), tw_, d.beta, d.beta_l2e);
+#pragma unroll
+                                        for (int k = 0; k < BC; ++k) acc[k] = acc[k] + st_val[wave][j * BC + k] * wgt;
+                                    }
+                                }
+                            }
+                            continue;
+                        }
                         // samples are walked with their position and image values loaded one
                         // sample ahead (scalar loads complete in any order, so each wait covers
                         // everything outstanding: the loads for sample p + 1 are issued right
@@ -967,10 +1005,10 @@ __device__ __forceinline__ void spread_tiles_body(const Dev<T>& d, Blk bk, const
     }
 }
 
-template <typename T, int W, int BC>
+template <typename T, int W, int BC, bool STAGED>
 __global__ __launch_bounds__(NT) void spread_tiles(Dev<T> d, const cx<T>* Pol, int B, cx<T>* E, size_t ws_img)
 {
-    spread_tiles_body<T, W, BC>(d, blk_xcd(), Pol, B, E, ws_img);
+    spread_tiles_body<T, W, BC, STAGED>(d, blk_xcd(), Pol, B, E, ws_img);
 }
 
 template <typename T>
@@ -981,12 +1019,12 @@ __device__ __forceinline__ void cols_adj_body(const Dev<T>& d, Blk bk, const cx<
     int bx_, b;
     bx_ = bk.x;
     b = bk.y;
-    const int CW = d.colsCW, x0 = bx_ * CW;
+    const int CW = d.colsCW, lcw = d.colsLCW, x0 = bx_ * CW;
     const int Ng = d.Ng, n = d.n;
     const cx<T>* Eb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(E) + (size_t)b * ws_img);
     cx<T>* Rb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(R) + (size_t)b * ws_img);
     for (int i = threadIdx.x; i < CW * Ng; i += blockDim.x) {
-        int gy = i / CW, c = i - gy * CW;
+        int gy = i >> lcw, c = i & (CW - 1);
         int gx = x0 + c;
         cx<T> v = {T(0), T(0)};
         if (gx < d.Rw) {
@@ -1000,7 +1038,7 @@ __device__ __forceinline__ void cols_adj_body(const Dev<T>& d, Blk bk, const cx<
     __syncthreads();
     lds_fft(buf, d.logNg, CW, Ng, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
     for (int i = threadIdx.x; i < CW * n; i += blockDim.x) {
-        int p = i / CW, c = i - p * CW;
+        int p = i >> lcw, c = i & (CW - 1);
         int gx = x0 + c;
         if (gx < d.Rw) Rb[(size_t)p * d.Rw + gx] = buf[c * Ng + ((p - n / 2 + Ng) & (Ng - 1))];
     }
@@ -1073,7 +1111,7 @@ struct pat_plan_s {
     Dev<float> df{};
     Dev<double> dd{};
     // launch-shape choices (defaults from LDS limits; replaced by the autotuner's)
-    int cols_cw = 1, dct_cw = 1, ring_g = 1, spread_bc = 16, fft_lr = 4, tw_table = 0;
+    int cols_cw = 1, dct_cw = 1, ring_g = 1, spread_bc = 16, fft_lr = 4, tw_table = 0, spread_staged = 1;
     int tuned = 0;                        // 1: measured now, 2: read from the tuning cache
     double tuned_ms = 0.0;
     // optional per-stage timing with HIP events recorded on the launch stream
@@ -1193,9 +1231,12 @@ int upload(pat_plan_s* p, Dev<T>& d)
     d.npts = P.npts; d.logNmax = ilog2i(P.Nmax);
     d.colsCW = p->cols_cw;
     d.dctCW = p->dct_cw;
+    d.colsLCW = ilog2i(p->cols_cw);
+    d.dctLCW = ilog2i(p->dct_cw);
     d.dct_stash = dct_stash_ok(P, p->dct_cw);
     d.fft_lr = p->fft_lr;
     d.tw_table = p->tw_table;
+    d.phase_k = (T)(-P.shift * P.h / (0.5 * P.Ng / P.Lam));
     d.beta = (T)P.beta; d.beta_l2e = (T)(P.beta * 1.4426950408889634); d.shift = (T)P.shift; d.half = (T)(0.5 * P.Ng / P.Lam); d.lamh = (T)P.h;
     d.dlam = (T)P.dlam; d.pre_scale = (T)P.pre_scale; d.adj_scale = (T)P.adj_scale;
     d.mask_r2 = P.g.mask_radius > 0 ? P.g.mask_radius * P.g.mask_radius : 0.0;
@@ -1324,11 +1365,14 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
         StageTimer tm(p, st, 10);
         constexpr int BCL = sizeof(T) == 4 ? 16 : 8;  // image group of the spread: BCL or BCL / 2
         const dim3 grid((d.Ew + 15) / 16, (d.Ng + 15) / 16, 1);
-        if (p->spread_bc >= BCL)
-            spread_tiles<T, WMAX, BCL><<<dim3(grid.x, grid.y, (B + BCL - 1) / BCL), NT, 0, st>>>(d, Pol, B, E, wi);
-        else
-            spread_tiles<T, WMAX, BCL / 2><<<dim3(grid.x, grid.y, (B + BCL / 2 - 1) / (BCL / 2)), NT, 0, st>>>(d, Pol, B,
-                                                                                                             E, wi);
+        const dim3 g1(grid.x, grid.y, (B + BCL - 1) / BCL), g2(grid.x, grid.y, (B + BCL / 2 - 1) / (BCL / 2));
+        if (p->spread_bc >= BCL) {
+            if (p->spread_staged) spread_tiles<T, WMAX, BCL, true><<<g1, NT, 0, st>>>(d, Pol, B, E, wi);
+            else spread_tiles<T, WMAX, BCL, false><<<g1, NT, 0, st>>>(d, Pol, B, E, wi);
+        } else {
+            if (p->spread_staged) spread_tiles<T, WMAX, BCL / 2, true><<<g2, NT, 0, st>>>(d, Pol, B, E, wi);
+            else spread_tiles<T, WMAX, BCL / 2, false><<<g2, NT, 0, st>>>(d, Pol, B, E, wi);
+        }
     }
     if ((rc = check_launch("spread_adj"))) return rc;
     {
@@ -1362,7 +1406,7 @@ struct GroupPlan {
     long fs, gs;
     char *R, *E, *V, *Gh, *U, *Pol;
     size_t wi;
-    int B, G;
+    int B, G, staged;
     int off[PAT_NUM_STAGES];
 };
 
@@ -1431,7 +1475,10 @@ __global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
     if constexpr (S == PAT_STAGE_LOWK_ADJ) lowk_adj_body<T>(q.d, bk, Gh, U, q.wi);
     if constexpr (S == PAT_STAGE_DCT_ADJ) dct_cols_body<T>(q.d, bk, Gh, V, q.wi, 1);
     if constexpr (S == PAT_STAGE_RING_ADJ) ring_adj_body<T, WMAX>(q.d, bk, V, U, Pol, q.B, q.G, q.wi);
-    if constexpr (S == PAT_STAGE_SPREAD_ADJ) spread_tiles_body<T, WMAX, BC>(q.d, bk, Pol, q.B, E, q.wi);
+    if constexpr (S == PAT_STAGE_SPREAD_ADJ) {
+        if (q.staged) spread_tiles_body<T, WMAX, BC, true>(q.d, bk, Pol, q.B, E, q.wi);
+        else spread_tiles_body<T, WMAX, BC, false>(q.d, bk, Pol, q.B, E, q.wi);
+    }
     if constexpr (S == PAT_STAGE_COLS_ADJ) cols_adj_body<T>(q.d, bk, E, R, q.wi);
     if constexpr (S == PAT_STAGE_ROWS_ADJ) rows_adj_body<T>(q.d, bk, R, q.fout, q.fs, q.wi);
 }
@@ -1487,6 +1534,7 @@ int group_run(const std::vector<pat_plan_s*>& plans, bool adjoint, const int* ba
         q.d = dev_of(p, (T*)nullptr);
         q.B = B;
         q.G = std::max(1, std::min(p->ring_g, B));
+        q.staged = p->spread_staged;
         q.fs = (long)P.n * P.n;
         q.gs = (long)P.nt * P.m;
         if (adjoint) {
@@ -1544,12 +1592,15 @@ void default_tune(pat_plan_s* p)
     p->spread_bc = (P.dt == PAT_F64) ? 8 : 16;
     p->fft_lr = 4;
     p->tw_table = 0;
+    p->spread_staged = 1;
 }
 
 void apply_tune(pat_plan_s* p)
 {
     p->df.colsCW = p->dd.colsCW = p->cols_cw;
     p->df.dctCW = p->dd.dctCW = p->dct_cw;
+    p->df.colsLCW = p->dd.colsLCW = ilog2i(p->cols_cw);
+    p->df.dctLCW = p->dd.dctLCW = ilog2i(p->dct_cw);
     p->df.fft_lr = p->dd.fft_lr = p->fft_lr;
     p->df.tw_table = p->dd.tw_table = p->tw_table;
     p->df.dct_stash = p->dd.dct_stash = dct_stash_ok(p->H.P, p->dct_cw);
@@ -1563,7 +1614,7 @@ bool tune_valid(const pat_plan_s* p)
     const int bcl = (P.dt == PAT_F64) ? 8 : 16;
     return pow2_in(p->cols_cw, lds_cols(P)) && pow2_in(p->dct_cw, lds_dct(P)) && pow2_in(p->ring_g, ring_group_max(P)) &&
            (p->spread_bc == bcl || p->spread_bc == bcl / 2) && (p->fft_lr == 3 || p->fft_lr == 4) &&
-           (p->tw_table == 0 || p->tw_table == 1);
+           (p->tw_table == 0 || p->tw_table == 1) && (p->spread_staged == 0 || p->spread_staged == 1);
 }
 
 std::string tune_key(const pat_plan_s* p)
@@ -1597,13 +1648,15 @@ bool tune_lookup(pat_plan_s* p, const char* path, const std::string& key)
         pat_plan_s t = *p;
         double ms = 0;
         t.tw_table = 0;
+        t.spread_staged = 0;
         const int got = std::sscanf(l.c_str() + bar + 3,
                                     "cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=%lf "
-                                    "twiddle_table=%d",
-                                    &t.cols_cw, &t.dct_cw, &t.ring_g, &t.spread_bc, &t.fft_lr, &ms, &t.tw_table);
-        if ((got == 6 || got == 7) && tune_valid(&t)) {
-            p->cols_cw = t.cols_cw; p->dct_cw = t.dct_cw; p->ring_g = t.ring_g;
-            p->spread_bc = t.spread_bc; p->fft_lr = t.fft_lr; p->tw_table = t.tw_table; p->tuned_ms = ms;
+                                    "twiddle_table=%d spread_staged=%d",
+                                    &t.cols_cw, &t.dct_cw, &t.ring_g, &t.spread_bc, &t.fft_lr, &ms, &t.tw_table,
+                                    &t.spread_staged);
+        if (got >= 6 && tune_valid(&t)) {
+            p->cols_cw = t.cols_cw; p->dct_cw = t.dct_cw; p->ring_g = t.ring_g; p->spread_bc = t.spread_bc;
+            p->fft_lr = t.fft_lr; p->tw_table = t.tw_table; p->spread_staged = t.spread_staged; p->tuned_ms = ms;
             found = true;  // keep scanning: the last matching line wins
         }
     }
@@ -1615,8 +1668,11 @@ void tune_store(const pat_plan_s* p, const char* path, const std::string& key)
 {
     FILE* fp = std::fopen(path, "a");
     if (!fp) return;
-    std::fprintf(fp, "%s | cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=%.6f twiddle_table=%d\n",
-                 key.c_str(), p->cols_cw, p->dct_cw, p->ring_g, p->spread_bc, p->fft_lr, p->tuned_ms, p->tw_table);
+    std::fprintf(fp,
+                 "%s | cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=%.6f twiddle_table=%d "
+                 "spread_staged=%d\n",
+                 key.c_str(), p->cols_cw, p->dct_cw, p->ring_g, p->spread_bc, p->fft_lr, p->tuned_ms, p->tw_table,
+                 p->spread_staged);
     std::fclose(fp);
 }
 
@@ -1681,7 +1737,8 @@ int tune_search(pat_plan_s* p, const Dev<T>& d)
                                    {&p->cols_cw, cw},
                                    {&p->dct_cw, dw},
                                    {&p->ring_g, rg},
-                                   {&p->spread_bc, {bcl, bcl / 2}}};
+                                   {&p->spread_bc, {bcl, bcl / 2}},
+                                   {&p->spread_staged, {1, 0}}};
     double best = 0;
     if ((rc = measure(best))) { cleanup(); return fail(rc, "autotuner: timing run failed"); }
     for (Choice& c : choices) {
@@ -1741,6 +1798,7 @@ void fill_info(const pat::Params& P, pat_plan_info* info, size_t ws_img, size_t 
         info->tune_ring_images = p->ring_g;
         info->tune_spread_images = p->spread_bc;
         info->tune_twiddle_table = p->tw_table;
+        info->tune_spread_staged = p->spread_staged;
         info->tuned = p->tuned;
         info->tuned_ms = p->tuned_ms;
     }

@@ -38,7 +38,8 @@ class PlanInfo(ctypes.Structure):
                 ("ws_per_image", ctypes.c_size_t), ("table_bytes", ctypes.c_size_t),
                 ("tune_fft_radix_log2", ctypes.c_int), ("tune_cols_per_block", ctypes.c_int),
                 ("tune_dct_cols_per_block", ctypes.c_int), ("tune_ring_images", ctypes.c_int),
-                ("tune_spread_images", ctypes.c_int), ("tune_twiddle_table", ctypes.c_int), ("tuned", ctypes.c_int),
+                ("tune_spread_images", ctypes.c_int), ("tune_twiddle_table", ctypes.c_int),
+                ("tune_spread_staged", ctypes.c_int), ("tuned", ctypes.c_int),
                 ("tuned_ms", ctypes.c_double)]
 
 
