@@ -120,8 +120,8 @@ def solver_bench(iters: int = 200, count: int = 64, lam: float = 1e-3, noise: fl
     out = {"instances": int(count), "sizes": {str(k): int(np.sum(sizes == k)) for k in (128, 256, 512)},
            "iterations": iters}
     norms = [solvers.opnorm(p) for p, _, _ in groups]
-    for method in ("nnls", "tv"):
-        sol = solvers.BatchedSolver(groups, method=method, lam=lam, opnorms=norms)
+    for method, grouped in (("nnls", False), ("tv", False), ("nnls", True), ("tv", True)):
+        sol = solvers.BatchedSolver(groups, method=method, lam=lam, opnorms=norms, grouped=grouped)
         sol.capture()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -135,9 +135,15 @@ def solver_bench(iters: int = 200, count: int = 64, lam: float = 1e-3, noise: fl
             d = (G.f - f).double()
             errs += list((torch.linalg.vector_norm(d.flatten(1), dim=1) /
                           torch.linalg.vector_norm(f.double().flatten(1), dim=1)).cpu().numpy())
-        out[method] = {"total_ms": ms, "ms_per_iteration": ms / iters,
-                       "mean_rel_l2_error": float(np.mean(errs)),
-                       "graph": "one captured iteration (all instances), replayed"}
+        psnr = []
+        for G, f in zip(sol.groups, truths):
+            mse = torch.mean((G.f.double() - f.double()) ** 2, dim=(1, 2))
+            psnr += list((10 * torch.log10(1.0 / mse)).cpu().numpy())
+        out[method + ("_grouped" if grouped else "")] = {
+            "total_ms": ms, "ms_per_iteration": ms / iters, "mean_rel_l2_error": float(np.mean(errs)),
+            "mean_psnr": float(np.mean(psnr)),
+            "graph": "one captured iteration (all instances), replayed",
+            "operator_launches": "one launch per stage for all sizes" if grouped else "one launch chain per size"}
     return out
 
 
