@@ -148,12 +148,14 @@ def solver_bench(iters: int = 200, count: int = 64, lam: float = 1e-3, noise: fl
 
 
 def lpd_bench(steps: int = 3000, n_train: int = 10000, n_test: int = 64, batch: int = 8, iters: int = 10,
-              noise: float = 0.02, lam: float = 1e-3, tv_iters: int = 200, lr: float = 1e-3, save: str = ""):
+              noise: float = 0.02, lam: float = 1e-3, tv_iters: int = 200, lr: float = 1e-3, save: str = "",
+              load: str = ""):
     """Learned primal-dual vs TV-LS time-to-PSNR: n = 256 images, m = 256
     detectors on the top 180-degree arc, nt = 512, 2% noise.  Trains the
     10-iteration LPD (batch 8) on seeded random-ellipse phantoms whose data the
     GPU forward operator generates, then reconstructs 64 held-out phantoms
-    with the trained network and with 200 graph-captured CP-TV iterations."""
+    with the trained network and with 200 graph-captured CP-TV iterations.
+    ``load``: weights written earlier with ``save`` (no training in this run)."""
     import torch
     from paper_2510_24687_amd import lpd as L
     from paper_2510_24687_amd import pat, solvers
@@ -174,11 +176,22 @@ def lpd_bench(steps: int = 3000, n_train: int = 10000, n_test: int = 64, batch: 
     s_A, s_U = L.input_scales(plan, train)
     net = L.LPD(plan, batch, iters, s_A=s_A, s_U=s_U, seed=0)
     untrained = L.evaluate(net, test)
-    t0 = time.time()
-    hist = L.train(net, train, steps, lr=lr, log_every=100, log=lambda it, loss: log("train", step=it, loss=loss))
-    torch.cuda.synchronize()
-    train_s = time.time() - t0
-    params = net.params.cpu().numpy()
+    if load:
+        z = np.load(load)
+        if json.loads(str(z["geometry"])) != geom:
+            raise ValueError("%s holds weights for another geometry" % load)
+        params, s_A, s_U, steps = z["params"], float(z["s_A"]), float(z["s_U"]), int(z["steps"])
+        training = {"loaded": os.path.basename(load), "steps": steps, "batch": batch, "phantoms": n_train}
+    else:
+        t0 = time.time()
+        hist = L.train(net, train, steps, lr=lr, log_every=100,
+                       log=lambda it, loss: log("train", step=it, loss=loss))
+        torch.cuda.synchronize()
+        train_s = time.time() - t0
+        params = net.params.cpu().numpy()
+        training = {"steps": steps, "batch": batch, "phantoms": n_train, "seconds": train_s,
+                    "steps_per_s": steps / train_s, "images_per_s": steps * batch / train_s,
+                    "operator_evaluations_per_step": 4 * iters, "loss_history": hist[-10:], "lr": lr}
     if save:
         np.savez(save, params=params, s_A=s_A, s_U=s_U, geometry=json.dumps(geom), steps=steps)
     del net
@@ -241,9 +254,7 @@ def lpd_bench(steps: int = 3000, n_train: int = 10000, n_test: int = 64, batch: 
         "nnls": {"psnr_200": traj[-1], "seconds_per_iteration": per_it},
         "ablation": {"untrained_lpd_psnr": untrained, "trained_lpd_psnr": psnr_lpd,
                      "backprojection_psnr": L.backprojection_psnr(plan, test, s_U)},
-        "training": {"steps": steps, "batch": batch, "phantoms": n_train, "seconds": train_s,
-                     "steps_per_s": steps / train_s, "images_per_s": steps * batch / train_s,
-                     "operator_evaluations_per_step": 4 * iters, "loss_history": hist[-10:], "lr": lr},
+        "training": training,
         "inference_images_per_s": n_test / t_lpd,
         "scales": {"s_A": s_A, "s_U": s_U},
     }
@@ -297,11 +308,16 @@ def main():
     ap.add_argument("--lpd-train", type=int, default=10000)
     ap.add_argument("--lpd-lr", type=float, default=1e-3)
     ap.add_argument("--lpd-save", default="", help="write the trained weights (npz) here")
+    ap.add_argument("--lpd-load", default="", help="evaluate weights written by --lpd-save (no training)")
     ap.add_argument("--tuning-cache", default="",
                     help="autotuner cache file (default: a fresh temporary file, i.e. tune at start-up)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for rocprofv3 counter calibration)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (the operators shard by image; "
+              "a multi-GPU run is not part of it)", file=sys.stderr)
+        sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
         return
@@ -310,12 +326,8 @@ def main():
         return
     if args.lpd:
         print(json.dumps({"lpd": lpd_bench(steps=args.lpd_steps, n_train=args.lpd_train, lr=args.lpd_lr,
-                                           save=args.lpd_save)}), flush=True)
+                                           save=args.lpd_save, load=args.lpd_load)}), flush=True)
         return
-    if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the operators shard by image; "
-              "a multi-GPU run is not part of it)", file=sys.stderr)
-        sys.exit(2)
 
     import torch
     from paper_2510_24687_amd import pat

@@ -23,7 +23,8 @@ struct Params {
     int Rw;                 // row-pass width Ng/2 + 1
     int Ew;                 // extended half-grid width Ng/2 + 1 + 2 hw
     double eps;             // target size of each neglected term
-    int M;                  // cosine transform via a 2M-point FFT
+    int M;                  // cosine transform via a 2M-point FFT; M = 2^a or 3 * 2^a
+    int m3;                 // 1 when M = 3 * 2^a
     double period, dlam;    // time period of the discrete cosine sum, ring spacing
     int L;                  // rings lambda_l = l dlam < Lam
     int K, Kp;              // largest harmonic, row pitch of the harmonic arrays
@@ -47,6 +48,7 @@ struct HostPlan {
     std::vector<double> Mk;                 // (klow+1) x nt x lcorr
     std::vector<double> phase;              // 2*Kp: e^{i k theta0} (re, im)
     std::vector<double> tw;                 // 2*Nmax: e^{-2 pi i k / Nmax} (re, im)
+    std::vector<double> twd;                // 2*(2M): e^{-2 pi i j / (2M)} (re, im), cosine-transform twiddles
     std::vector<double> pos;                // 2*npts: grid position (x, y) of each half-ring sample
 };
 

@@ -181,24 +181,27 @@ __device__ __forceinline__ void st_lds(PAT_LDS cx<T>* p, cx<T> v) { p->x = v.x; 
 template <typename T>
 __device__ __forceinline__ cx<T> ld_glb(const PAT_GLOBAL cx<T>* p) { return {p->x, p->y}; }
 
+// A power-of-two pass of a transform of length N = f 2^logN, f = 1 or 3 (f3):
+// the sequences' stride between butterfly inputs is N/R.
 template <typename T, int R>
 __device__ __noinline__ void stockham_pass(PAT_LDS cx<T>* buf, int logN, int logNs, int nb, int stride,
-                                              const PAT_GLOBAL cx<T>* __restrict__ tw, int logNmax, bool inv, bool twtab)
+                                              const PAT_GLOBAL cx<T>* __restrict__ tw, int logNmax, bool inv, bool twtab,
+                                              int f3)
 {
     constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
     constexpr int BPT = FFT_REGS / R;
     const int lnbf = logN - LR;
-    const int nbf = 1 << lnbf;
-    const int total = nb << lnbf;
+    const int nbf = f3 ? 3 << lnbf : 1 << lnbf;
+    const int total = nb * nbf;
     cx<T> v[BPT][R];
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
         const int it = threadIdx.x + u * NT;
         if (it < total) {
-            const int b = it >> lnbf, t = it & (nbf - 1);
+            const int b = f3 ? (it >> lnbf) / 3 : it >> lnbf, t = it - b * nbf;
             const PAT_LDS cx<T>* s = buf + b * stride;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[u][r] = ld_lds(s + t + (r << lnbf));
+            for (int r = 0; r < R; ++r) v[u][r] = ld_lds(s + t + r * nbf);
         }
     }
     __syncthreads();
@@ -206,7 +209,7 @@ __device__ __noinline__ void stockham_pass(PAT_LDS cx<T>* buf, int logN, int log
     for (int u = 0; u < BPT; ++u) {
         const int it = threadIdx.x + u * NT;
         if (it < total) {
-            const int b = it >> lnbf, t = it & (nbf - 1);
+            const int b = f3 ? (it >> lnbf) / 3 : it >> lnbf, t = it - b * nbf;
             const int k = t & ((1 << logNs) - 1);
             if (logNs > 0) {
                 const int sh = logNmax - logNs - LR;
@@ -254,7 +257,7 @@ __device__ __noinline__ void stockham_pass(PAT_LDS cx<T>* buf, int logN, int log
 
 template <typename T>
 __device__ void lds_fft(cx<T>* buf, int logN, int nb, int stride, const cx<T>* __restrict__ tw, int logNmax,
-                        bool inverse, int maxlr, bool twtab)
+                        bool inverse, int maxlr, bool twtab, int f3 = 0)
 {
     if (logN == 0) return;
     const int P = (logN + maxlr - 1) / maxlr;  // passes; radices as equal as possible, at most 2^maxlr
@@ -264,13 +267,68 @@ __device__ void lds_fft(cx<T>* buf, int logN, int nb, int stride, const cx<T>* _
     for (int p = 0; p < P; ++p) {
         const int lr = logN / P + (p < logN % P ? 1 : 0);
         switch (lr) {
-            case 1: stockham_pass<T, 2>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab); break;
-            case 2: stockham_pass<T, 4>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab); break;
-            case 3: stockham_pass<T, 8>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab); break;
-            default: stockham_pass<T, 16>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab); break;
+            case 1: stockham_pass<T, 2>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab, f3); break;
+            case 2: stockham_pass<T, 4>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab, f3); break;
+            case 3: stockham_pass<T, 8>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab, f3); break;
+            default: stockham_pass<T, 16>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab, f3); break;
         }
         logNs += lr;
     }
+}
+
+// The last pass of a length N = 3 * 2^logN2 transform (after the power-of-two
+// passes): radix 3 with sub-transform length Ns = 2^logN2, twiddles W_N^{r t}
+// read from twd (the 2N-th roots e^{-2 pi i j/(2N)}: W_N^{r t} = twd[2 r t]).
+template <typename T>
+__device__ __noinline__ void stockham_pass3(PAT_LDS cx<T>* buf, int logN2, int nb, int stride,
+                                               const PAT_GLOBAL cx<T>* __restrict__ twd, bool inv)
+{
+    constexpr int BPT = FFT_REGS / 3;
+    const int nbf = 1 << logN2;
+    const int total = nb << logN2;
+    const T h3 = T(0.86602540378443864676);  // sqrt(3)/2
+    cx<T> v[BPT][3];
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int it = threadIdx.x + u * NT;
+        if (it < total) {
+            const int b = it >> logN2, t = it & (nbf - 1);
+            const PAT_LDS cx<T>* s = buf + b * stride;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) v[u][r] = ld_lds(s + t + r * nbf);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int it = threadIdx.x + u * NT;
+        if (it < total) {
+            const int b = it >> logN2, t = it & (nbf - 1);
+            cx<T> w1 = ld_glb(twd + 2 * t), w2 = ld_glb(twd + 4 * t);
+            if (inv) { w1.y = -w1.y; w2.y = -w2.y; }
+            const cx<T> a0 = v[u][0], a1 = cmul(v[u][1], w1), a2 = cmul(v[u][2], w2);
+            const cx<T> sm = a1 + a2, df = a1 - a2;
+            const cx<T> m = {a0.x - T(0.5) * sm.x, a0.y - T(0.5) * sm.y};
+            // forward: y1 = m - i h3 df, y2 = m + i h3 df (inverse: signs swapped)
+            const cx<T> jd = inv ? cx<T>{-h3 * df.y, h3 * df.x} : cx<T>{h3 * df.y, -h3 * df.x};
+            PAT_LDS cx<T>* s = buf + b * stride;
+            st_lds(s + t, a0 + sm);
+            st_lds(s + t + nbf, m + jd);
+            st_lds(s + t + 2 * nbf, m - jd);
+        }
+    }
+    __syncthreads();
+}
+
+// Transform of nb sequences of length N = 3 * 2^logN2: the power-of-two passes
+// on the 2^logN2 factor, then the radix-3 pass.  The radix-3 pass keeps
+// FFT_REGS / 3 butterflies per thread, so nb * N <= (FFT_REGS / 3) * 3 * NT.
+template <typename T>
+__device__ void lds_fft3(cx<T>* buf, int logN2, int nb, int stride, const cx<T>* __restrict__ tw, int logNmax,
+                         const cx<T>* __restrict__ twd, bool inverse, int maxlr, bool twtab)
+{
+    lds_fft(buf, logN2, nb, stride, tw, logNmax, inverse, maxlr, twtab, 1);
+    stockham_pass3((PAT_LDS cx<T>*)buf, logN2, nb, stride, (const PAT_GLOBAL cx<T>*)twd, inverse);
 }
 
 // MI355X dispatches consecutive workgroups of a grid round-robin over its 8
@@ -335,6 +393,8 @@ struct Dev {
     const T* Mk;                // (klow+1) x nt x lcorr
     const cx<T>* phase;         // Kp
     const cx<T>* tw;            // Nmax
+    const cx<T>* twd;           // 2M: e^{-2 pi i j/(2M)} (cosine-transform twiddles)
+    int m3;                     // 1: M = 3 * 2^log2M
     const cx<T>* pos;           // npts: grid position (x, y) of each half-ring sample
 };
 
@@ -575,7 +635,6 @@ __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<
     const int x_lo = adjoint ? 1 : 0, x_hi = adjoint ? d.nt + 1 : d.L;
     const int nx = x_hi - x_lo;
     const int nout = adjoint ? d.L : d.nt;
-    const int sh = d.logNmax - logM - 1;  // e^{i pi x/M} = conj(tw[x << sh])
     // With enough LDS the block's input columns are read from HBM once into a
     // stash (column-major, CW x nx) and both parities are formed from it.
     cx<T>* stash = buf + CW * M;
@@ -596,14 +655,15 @@ __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<
                 for (int x = xs; x < x_hi; x += M) {
                     if (x < x_lo) continue;
                     cx<T> v = d.dct_stash ? stash[c * nx + (x - x_lo)] : ib[(size_t)(x - x_lo) * d.Kp + k];
-                    if (r) v = cmul(v, conjg(d.tw[x << sh]));
+                    if (r) v = cmul(v, conjg(d.twd[x]));  // e^{i pi x/M}, x < 2M
                     acc = acc + v;
                 }
             }
             buf[c * M + xs] = acc;
         }
         __syncthreads();
-        lds_fft(buf, logM, CW, M, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
+        if (d.m3) lds_fft3(buf, logM, CW, M, d.tw, d.logNmax, d.twd, true, d.fft_lr, d.tw_table);
+        else lds_fft(buf, logM, CW, M, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
         // output rows of parity r only: y = orow (+ 1 in the forward), y = 2 y' + r
         const int o0 = adjoint ? r : 1 - r;
         const int nr = o0 < nout ? (nout - o0 + 1) / 2 : 0;
@@ -614,7 +674,7 @@ __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<
             if (k >= d.Kp) continue;
             const int y = adjoint ? orow : orow + 1;
             const int yp = (y - r) >> 1;
-            const int ypp = (M - yp - r) & (M - 1);
+            const int ypp = (M - yp - r) == M ? 0 : M - yp - r;
             ob[(size_t)orow * d.Kp + k] = (buf[c * M + yp] + buf[c * M + ypp]) * T(0.5);
         }
         __syncthreads();
@@ -1175,11 +1235,15 @@ size_t dct_lds(const pat::Params& P, int cw)
     return cs * cw * ((size_t)P.M + (dct_stash_ok(P, cw) ? std::max(P.L, P.nt) : 0));
 }
 
+// points one lds_fft call holds: FFT_REGS per thread and pass, i.e. 16 NT for
+// power-of-two lengths, 15 NT when the radix-3 pass is needed
+int fft_points(const pat::Params& P) { return P.m3 ? (FFT_REGS / 3) * 3 * NT : FFT_BLOCK_POINTS; }
+
 int lds_dct(const pat::Params& P)
 {
     size_t cs = (P.dt == PAT_F64) ? 16 : 8;
     int cw = 16;
-    while (cw > 1 && ((size_t)cw * P.M * cs > 65536 || (size_t)cw * P.M > FFT_BLOCK_POINTS)) cw >>= 1;
+    while (cw > 1 && ((size_t)cw * P.M * cs > 65536 || cw * P.M > fft_points(P))) cw >>= 1;
     return cw;
 }
 
@@ -1223,11 +1287,13 @@ int upload(pat_plan_s* p, Dev<T>& d)
     if ((rc = put(Mk.data(), Mk.size() * sizeof(T), (const void**)&d.Mk))) return rc;
     if ((rc = put(ph.data(), ph.size() * sizeof(T), (const void**)&d.phase))) return rc;
     if ((rc = put(tw.data(), tw.size() * sizeof(T), (const void**)&d.tw))) return rc;
+    std::vector<T> twd = conv(H.twd);
+    if ((rc = put(twd.data(), twd.size() * sizeof(T), (const void**)&d.twd))) return rc;
     std::vector<T> pos = conv(H.pos);
     if ((rc = put(pos.data(), pos.size() * sizeof(T), (const void**)&d.pos))) return rc;
     d.n = P.n; d.m = P.m; d.nt = P.nt; d.mf = P.mf; d.logmf = ilog2i(P.mf);
     d.Ng = P.Ng; d.logNg = ilog2i(P.Ng); d.w = P.w; d.hw = P.hw; d.Rw = P.Rw; d.Ew = P.Ew;
-    d.M = P.M; d.log2M = ilog2i(P.M); d.L = P.L; d.K = P.K; d.Kp = P.Kp; d.klow = P.klow; d.lcorr = P.lcorr;
+    d.M = P.M; d.m3 = P.m3; d.log2M = ilog2i(P.m3 ? P.M / 3 : P.M); d.L = P.L; d.K = P.K; d.Kp = P.Kp; d.klow = P.klow; d.lcorr = P.lcorr;
     d.npts = P.npts; d.logNmax = ilog2i(P.Nmax);
     d.colsCW = p->cols_cw;
     d.dctCW = p->dct_cw;
@@ -1780,8 +1846,8 @@ int lds_ok(const pat::Params& P, std::string& err)
 {
     size_t cs = (P.dt == PAT_F64) ? 16 : 8;
     size_t need = std::max({cs * P.Ng, cs * (size_t)P.max_ring, cs * (size_t)P.M, cs * 2 * (size_t)P.mf});
-    int longest = std::max({P.Ng, P.max_ring, P.M, P.mf});
-    if (need > 65536 || longest > FFT_BLOCK_POINTS) {
+    int longest = std::max({P.Ng, P.max_ring, P.mf});
+    if (need > 65536 || longest > FFT_BLOCK_POINTS || P.M > fft_points(P)) {
         err = "problem too large for the single-block LDS transforms (64 KiB, 4096 points)";
         return PAT_EUNSUPPORTED;
     }

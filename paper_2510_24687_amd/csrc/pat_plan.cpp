@@ -195,7 +195,16 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
     double spread = 0.25 * lg * lg / ((1.0 - g.taper_rho) * P.Lam) + 0.25;
     double Pmin = g.c * g.T + P.rmax + g.R + spread;
     long Mneed = (long)std::ceil(Pmin / (2.0 * ct));
-    P.M = next_pow2(std::max<long>(Mneed, g.nt));
+    // the cosine transform's half length: the smallest 2^a or 3 * 2^a that covers
+    // the period and the time samples (the ring count L scales with M)
+    {
+        const long need = std::max<long>(Mneed, g.nt);
+        const long m2 = next_pow2(need);
+        long m3 = 3;
+        while (m3 < need) m3 *= 2;
+        P.M = (int)std::min(m2, m3);
+        P.m3 = (P.M % 3 == 0) ? 1 : 0;
+    }
     P.period = 2.0 * P.M * ct;
     P.dlam = 2.0 * M_PI / P.period;
     P.L = (int)std::ceil(P.Lam / P.dlam - 1e-9);
@@ -239,7 +248,7 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
     P.max_ring = maxN;
     P.K = K;
     P.Kp = ((K + 1 + 15) / 16) * 16;
-    P.Nmax = std::max({P.Ng, 2 * P.M, maxN, P.mf});
+    P.Nmax = (int)next_pow2(std::max({P.Ng, 2 * P.M, maxN, P.mf}));
 
     // pre-correction: 1/phi_hat(2 pi q'/Ng)
     {
@@ -324,6 +333,14 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
         double a = -2.0 * M_PI * k / P.Nmax;
         H.tw[2 * k] = std::cos(a);
         H.tw[2 * k + 1] = std::sin(a);
+    }
+
+    // cosine-transform twiddles e^{-2 pi i j/(2M)}
+    H.twd.resize(2 * 2 * (size_t)P.M);
+    for (int j = 0; j < 2 * P.M; ++j) {
+        double a = -M_PI * j / P.M;
+        H.twd[2 * j] = std::cos(a);
+        H.twd[2 * j + 1] = std::sin(a);
     }
 
     // grid positions (cells) of every half-ring sample, shared by the gather

@@ -165,7 +165,7 @@ class _Block:
 
     def forward(self, k, planes, scales, state_in, state_out, st):
         lib, B, H, W = self.lib, self.B, self.H, self.W
-        j = min(k, self.pre1.shape[0] - 1)
+        j = min(k, self.act1.shape[0] - 1)
         l1, l2, l3 = self.layers()
         pre1 = None if self.pre1 is None else self.pre1[j]
         pre2 = None if self.pre2 is None else self.pre2[j]

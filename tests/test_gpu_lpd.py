@@ -340,6 +340,28 @@ def test_lpd_graph_replay_equals_eager_training():
     assert int(b.step_count) == 3
 
 
+def test_inference_network_equals_training_network():
+    """An inference-only network (one set of activations, reused by every
+    iteration) gives f_K identical to the training network's, eager and as a
+    captured, replayed graph."""
+    geom, plan, f_true, y, params, K = _tiny_setup(K=3)
+    a = L.LPD(plan, 2, iters=K, params=params, s_A=0.9, s_U=1.7)
+    b = L.LPD(plan, 2, iters=K, params=params, s_A=0.9, s_U=1.7, train=False)
+    for net in (a, b):
+        net.set_batch(cuda32(y), cuda32(f_true))
+    fa = a.forward_pass().clone()
+    fb = b.forward_pass().clone()
+    torch.cuda.synchronize()
+    assert torch.equal(fa, fb)
+    b.capture_forward()
+    for _ in range(2):
+        b.f[K].zero_()
+        torch.cuda.synchronize()
+        b.graph_fwd.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(b.f[K], fa)
+
+
 def test_training_gains_over_untrained_network():
     """800 steps on 256 phantoms (n = 32, 180-degree arc) raise the held-out
     PSNR well above the untrained network and above the method without the

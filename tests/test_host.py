@@ -68,8 +68,10 @@ def test_invalid_geometries(lib, bad, code):
 def test_plan_parameters_for_the_workloads(lib):
     m512 = pat.plan_query(P.full_circle(512, 1024, 1024), "f32")
     assert m512["grid"] == 1024 and m512["stencil"] == 6 and m512["m_full"] == 1024
-    assert abs(m512["period"] - 8.0) < 1e-12           # 2 M c T/nt with M = 2048
-    assert m512["rings"] == 1024 and m512["dct_half"] == 2048
+    # M is the smallest 2^a or 3*2^a that covers the band and the time samples:
+    # 1536 here, so the period 2 M c T/nt is 6 and L = M/2 rings
+    assert abs(m512["period"] - 6.0) < 1e-12
+    assert m512["rings"] == 768 and m512["dct_half"] == 1536
     assert 820 <= m512["kmax"] <= 900                    # Lambda R = 804 plus the Bessel transition zone
     assert m512["max_ring"] == 2048
     arc = pat.plan_query(P.top_arc(256, 256, 512, 180.0), "f32")
@@ -82,6 +84,8 @@ def test_plan_parameters_for_the_workloads(lib):
         q = pat.plan_query(g, dt)
         assert q["period"] > g["T"] + 1 + math.sqrt(2)
         assert q["rings"] * q["dlam"] >= q["lambda_max"] - 1e-9
+        M = q["dct_half"]
+        assert M >= g["nt"] and (M & (M - 1) == 0 or (M % 3 == 0 and (M // 3) & (M // 3 - 1) == 0))
 
 
 def test_bessel_recurrence_against_mpmath(lib):
