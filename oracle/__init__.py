@@ -30,6 +30,14 @@ arXiv 2510.24687, that it follows):
 * ``fd_gauss`` -- brute-force second-order leapfrog in time with a 4th-order
   Laplacian (the finite-difference approach of Sec. 2.1.1) for Gaussian data
   on a small box.  Pins the physics of ``gauss_forward``.
+* ``ubp`` / ``inverse`` -- the approximate inverse of Sec. 2.4 (Alg. 3): the
+  back-projection of eq. E:approx_UBP with the band-limited fundamental
+  solution (C, direct quadrature of its J1 form), the constant of eq.
+  E:silly_integral and the restriction to the support.
+* ``kspace_ubp`` -- an independent route to the same back-projection: the
+  2D Fourier integral of the normal derivative of G (eq. E:Fourier_Green)
+  evaluated on a polar quadrature grid, with no Bessel functions.  Pins
+  ``ubp``.
 """
 from __future__ import annotations
 
@@ -75,6 +83,7 @@ def _load():
         gp = ctypes.POINTER(_Geom)
         lib.ora_forward.argtypes = [gp, dp, ctypes.c_int, dp, dp, ctypes.c_int, ip, dp]
         lib.ora_adjoint.argtypes = [gp, dp, ctypes.c_int, dp, dp, ctypes.c_int, ip, dp]
+        lib.ora_ubp.argtypes = [gp, dp, ctypes.c_int, dp, dp, ctypes.c_int, ip, dp]
         lib.ora_gauss.argtypes = [gp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_int, dp, dp, ctypes.c_int, ip, dp]
         lib.ora_taper.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
@@ -179,6 +188,108 @@ def adjoint_scale(geom: dict) -> float:
     g = full_geom(geom)
     h = 2 * g["a"] / g["n"]
     return (g["T"] / g["nt"]) * (g["R"] * g["arc"] / g["m"]) / h ** 2
+
+
+def ubp(geom: dict, gtr, pix=None, phase_per_panel: float = 10.0, nodes: int = 20):
+    """Back-projection v of eq. E:approx_UBP (Sec. 2.4) on the listed flat pixel
+    indices (all if None), before the constant and the restriction:
+
+        v(x) = 2 c^2 w_t w_th sum_{j,i} g[j][i] d/dn(z_i) G_W(t_j, x - z_i),
+
+    G_W the fundamental solution of the band-limited model (spectrum
+    W(|xi|) sin(c|xi|t) / (2 pi c |xi|)) and n(z_i) = -z_i/R the normal
+    pointing into the disk (the sign with which the formula is a left
+    inverse; the sign of eq. E:Four_coef_v).  Arc data count as the full
+    circle extended by zero (Alg. 3, first step).  Returns (n, n) or a
+    vector."""
+    lib = _load()
+    g = full_geom(geom)
+    gtr = np.ascontiguousarray(gtr, dtype=np.float64).reshape(g["nt"], g["m"])
+    lam, wl = quad_nodes(g, phase_per_panel, nodes)
+    p = None if pix is None else np.ascontiguousarray(pix, dtype=np.int32)
+    npix = g["n"] ** 2 if p is None else len(p)
+    out = np.zeros(npix)
+    rc = lib.ora_ubp(ctypes.byref(_cgeom(g)), _dptr(gtr), len(lam), _dptr(lam), _dptr(wl),
+                     npix, _iptr(p), _dptr(out))
+    if rc != 0:
+        raise RuntimeError("ora_ubp failed")
+    return out.reshape(g["n"], g["n"]) if p is None else out
+
+
+def support_masks(geom: dict):
+    """(omega0, annulus) boolean n x n masks: omega0 is the support Omega_0 of
+    f (the disk of radius mask_radius, or the whole image without a mask);
+    annulus = pixel centres in the detector disk Omega (|x| <= R) outside
+    Omega_0, where eq. E:silly_integral asks v + C to integrate to zero."""
+    g = full_geom(geom)
+    n = g["n"]
+    h = 2 * g["a"] / n
+    c = -g["a"] + (np.arange(n) + 0.5) * h
+    r2 = c[None, :] ** 2 + c[:, None] ** 2
+    omega0 = r2 <= g["mask_radius"] ** 2 if g["mask_radius"] > 0 else np.ones((n, n), bool)
+    annulus = (r2 <= g["R"] ** 2) & ~omega0
+    return omega0, annulus
+
+
+def ubp_constant(geom: dict, v) -> float:
+    """C of eq. E:silly_integral: the pixel-sum (midpoint rule) of v + C over
+    Omega minus Omega_0 vanishes; 0 when that set holds no pixel centre."""
+    _, ann = support_masks(geom)
+    cnt = int(ann.sum())
+    return 0.0 if cnt == 0 else -float(np.sum(np.asarray(v)[ann])) / cnt
+
+
+def inverse(geom: dict, gtr):
+    """Approximate inverse of Alg. 3: Pi_{Omega_0}(v + C) on the n x n grid."""
+    v = ubp(geom, gtr)
+    om0, _ = support_masks(geom)
+    return np.where(om0, v + ubp_constant(geom, v), 0.0)
+
+
+def kspace_ubp(geom: dict, gtr, pix=None, n_phi: int = 0, phase_per_panel: float = 10.0, nodes: int = 20):
+    """The back-projection v of ``ubp`` by another route: G_W(t, y) is the
+    inverse 2D transform (Sec. 2.1.1) of W sin(c|xi|t)/(2 pi c|xi|) (eq.
+    E:Fourier_Green with its 1/(2 pi)), so
+
+      d/dn(z) G_W(t, x - z) = (2 pi)^-2 int W(|xi|) sin(c|xi|t)/(c|xi|) (-i n.xi) e^{i xi.(x - z)} dxi,
+
+    and, with the inward normal n_i = -z_i/R, v(x) = int V(xi) e^{i xi.x} dxi,
+      V(xi) = 2 i c w_t w_th (2 pi)^-2 W(|xi|) sum_{j,i} g[j][i] sin(c|xi|t_j) (z_i.xi/(R|xi|)) e^{-i xi.z_i}.
+    The xi integral runs over the disk |xi| < Lambda in polar coordinates:
+    composite Gauss-Legendre in |xi| (``quad_nodes``) and the trapezoid rule
+    in angle (exact for the trigonometric polynomials of degree < n_phi that
+    appear).  Plain numpy, meant for small n."""
+    g = full_geom(geom)
+    n, m, nt = g["n"], g["m"], g["nt"]
+    h = 2 * g["a"] / n
+    Lam = np.pi / h
+    if n_phi <= 0:
+        n_phi = int(2 * np.ceil(Lam * (g["R"] + np.sqrt(2) * g["a"])) + 40)
+    lam, wl = quad_nodes(g, phase_per_panel, nodes)
+    Wl = np.array([_taper_np(x, Lam, g["rho"]) for x in lam])
+    phi = 2 * np.pi * np.arange(n_phi) / n_phi
+    gtr = np.asarray(gtr, dtype=np.float64).reshape(nt, m)
+    th = g["theta0"] + np.arange(m) * g["arc"] / m
+    zx, zy = g["R"] * np.cos(th), g["R"] * np.sin(th)
+    t = (np.arange(nt) + 1) * g["T"] / nt
+    xc = -g["a"] + (np.arange(n) + 0.5) * h
+    if pix is None:
+        pix = np.arange(n * n)
+    pix = np.asarray(pix)
+    px, py = xc[pix % n], xc[pix // n]
+    wt, wth = g["T"] / nt, g["R"] * g["arc"] / m
+    pref = 2j * g["c"] * wt * wth / (2 * np.pi) ** 2
+    out = np.zeros(len(pix), dtype=complex)
+    for l in range(len(lam)):
+        xi_x, xi_y = lam[l] * np.cos(phi), lam[l] * np.sin(phi)          # (n_phi,)
+        sj = np.sin(g["c"] * lam[l] * t)                                  # (nt,)
+        gi = sj @ gtr                                                     # (m,): sum_j g[j][i] sin
+        nxi = np.cos(th)[None, :] * np.cos(phi)[:, None] + np.sin(th)[None, :] * np.sin(phi)[:, None]
+        ez = np.exp(-1j * (xi_x[:, None] * zx[None, :] + xi_y[:, None] * zy[None, :]))
+        V = pref * Wl[l] * ((nxi * ez) @ gi)                              # (n_phi,)
+        ex = np.exp(1j * (px[:, None] * xi_x[None, :] + py[:, None] * xi_y[None, :]))
+        out += wl[l] * lam[l] * (2 * np.pi / n_phi) * (ex @ V)
+    return out.real.reshape(n, n) if len(pix) == n * n else out.real
 
 
 def gauss_forward(geom: dict, blobs, taper_grid: bool = False, dets=None,

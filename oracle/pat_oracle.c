@@ -1,6 +1,7 @@
 /*
  * pat_oracle.c -- plain CPU FP64 oracle for the circular-geometry
- * photoacoustic forward operator A and its weighted adjoint A*.
+ * photoacoustic forward operator A, its weighted adjoint A* and the
+ * back-projection of the approximate inverse A^-1.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link, call or
  * load this file; only the test-suite, the smoke check and the CPU-baseline
@@ -42,8 +43,8 @@
  *                  W = e^{-1/u} / (e^{-1/u} + e^{-1/(1-u)}),
  *                  u = (Lambda - l) / ((1-rho) Lambda); W = 0 beyond Lambda.
  *
- * Sums over pixels use Neumaier compensated summation.  J0 is the C
- * library's j0().  Loops are parallel over detectors / pixels with OpenMP,
+ * Sums over pixels use Neumaier compensated summation.  J0 and J1 are the
+ * C library's j0() and j1().  Loops are parallel over detectors / pixels with OpenMP,
  * which changes no arithmetic.
  */
 #define _DEFAULT_SOURCE
@@ -196,6 +197,87 @@ int ora_adjoint(const ora_geom* G, const double* g, int nl, const double* lam, c
         f[kk] = scale * (s + cmp);
     }
     free(cf); free(ct); free(Cg); free(zx); free(zy);
+    return 0;
+}
+
+/*
+ * Back-projection v of the universal inversion formula (eq. E:inverse,
+ * truncated to the measured times as in eq. E:approx_UBP) for the
+ * band-limited model: the fundamental solution G of eq. E:green_conv is
+ * replaced by G_W, the inverse transform of W(|xi|) sin(c|xi|t)/(2 pi c|xi|)
+ * (eq. E:Fourier_Green with the unitary transform of Sec. 2.1.1), so that
+ *
+ *   d/dn(z) G_W(t, x - z) = (n(z).(x - z)) / (2 pi c)
+ *                           int_0^Lambda W(l) l [J1(l d)/d] sin(c l t) dl,   d = |x - z|,
+ *
+ * for a unit normal n(z), and the time and arc integrals are the rectangle
+ * rules of eqn:innerProducts (w_t = T/nt, w_th = R arc/m).  With this G the
+ * formula returns f (not -f) when n(z) is the normal pointing INTO the disk,
+ * n_i = -z_i/R; that is also the sign of the paper's Fourier coefficients
+ * of v (eq. E:Four_coef_v), whose derivation (Appendix) differentiates
+ * e^{-i xi.z} with the opposite sign.  For a speed of sound c the formula
+ * (written for c = 1) becomes v = 2 c^2 int int g d/dn G_W, hence
+ *
+ *   v(x_pq) = (2 c w_t w_th / 2pi) sum_i (z_i/R).(z_i - x_pq)
+ *             sum_l w_l W(l) l [J1(l d_ipq)/d_ipq] sum_j g[j][i] sin(c l t_j).
+ *
+ * J1(l d)/d -> l/2 as d -> 0.  No mask and no constant here: the caller adds
+ * the constant of eq. E:silly_integral and restricts to the support.
+ *   g    : full nt x m traces
+ *   pix  : npix flat pixel indices p*n+q (NULL -> all n*n, npix ignored)
+ *   v    : output, npix values
+ */
+int ora_ubp(const ora_geom* G, const double* g, int nl, const double* lam, const double* wl,
+            int npix, const int* pix, double* v)
+{
+    if (!G || !v || !lam || !wl || !g || G->n <= 0 || G->m <= 0 || G->nt <= 0 || nl <= 0) return -1;
+    int n = G->n, m = G->m, nt = G->nt;
+    if (!pix) npix = n * n;
+    double h = 2.0 * G->a / n, Lam = M_PI / h;
+    double scale = 2.0 * G->c * (G->T / nt) * (G->R * G->arc / m) / (2.0 * M_PI);
+    /* Sg[i][l] = w_l W_l l * sum_j g[j][i] sin(c l t_j) */
+    double* Sg = malloc(sizeof(double) * (size_t)m * nl);
+    #pragma omp parallel for schedule(static)
+    for (int i = 0; i < m; ++i) {
+        for (int l = 0; l < nl; ++l) {
+            double s = 0.0, cmp = 0.0;
+            for (int j = 0; j < nt; ++j) {
+                double t = (j + 1) * G->T / nt;
+                neumaier_add(&s, &cmp, g[(size_t)j * m + i] * sin(G->c * lam[l] * t));
+            }
+            Sg[(size_t)i * nl + l] = (s + cmp) * wl[l] * ora_taper(lam[l], Lam, G->rho) * lam[l];
+        }
+    }
+    double* zx = malloc(sizeof(double) * m);
+    double* zy = malloc(sizeof(double) * m);
+    double* nx = malloc(sizeof(double) * m);
+    double* ny = malloc(sizeof(double) * m);
+    for (int i = 0; i < m; ++i) {
+        double th = G->theta0 + i * G->arc / m;
+        nx[i] = cos(th); ny[i] = sin(th);
+        zx[i] = G->R * nx[i]; zy[i] = G->R * ny[i];
+    }
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int kk = 0; kk < npix; ++kk) {
+        int idx = pix ? pix[kk] : kk;
+        int p = idx / n, q = idx % n;
+        double x = pix_x(G, q), y = pix_x(G, p);
+        double s = 0.0, cmp = 0.0;
+        for (int i = 0; i < m; ++i) {
+            double dx = x - zx[i], dy = y - zy[i];
+            double d = hypot(dx, dy);
+            double nd = -(nx[i] * dx + ny[i] * dy);   /* inward normal . (x - z_i) */
+            const double* row = Sg + (size_t)i * nl;
+            double si = 0.0, ci = 0.0;
+            for (int l = 0; l < nl; ++l) {
+                double k1 = d > 0.0 ? j1(lam[l] * d) / d : 0.5 * lam[l];
+                neumaier_add(&si, &ci, row[l] * k1);
+            }
+            neumaier_add(&s, &cmp, nd * (si + ci));
+        }
+        v[kk] = scale * (s + cmp);
+    }
+    free(Sg); free(zx); free(zy); free(nx); free(ny);
     return 0;
 }
 
