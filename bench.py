@@ -418,9 +418,60 @@ def main():
         "pair_effective_GBs": total_alg / (step_ms * 1e-3) / 1e9,
         "accuracy_vs_oracle": acc,
     }
+    out["inverse"] = inverse_bench(plan, y, args.steps, n, geom)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(geom)
     print(json.dumps(out), flush=True)
+
+
+def inverse_bench(plan, y, steps, n, geom):
+    """The approximate inverse (Alg. 3) on the same plan and batch of traces:
+    throughput, per-stage times (recorded under the adjoint's stage names; the
+    constant/restriction kernel is the remainder) and accuracy of image 0's
+    back-projection against the oracle's stored samples."""
+    import ctypes
+    import torch
+    from paper_2510_24687_amd import pat
+    from paper_2510_24687_amd import phantoms as P
+    B = y.shape[0]
+    fi = torch.empty((B, n, n), dtype=torch.float32, device=y.device)
+    acc = None
+    gold = os.path.join(ROOT, "tests", "golden", "inv_full_n%d.npz" % n)
+    if os.path.exists(gold):
+        z = np.load(gold)
+        y0 = torch.tensor(P.randn((geom["nt"], geom["m"]), int(z["trace_seed"])), dtype=torch.float32,
+                          device=y.device)
+        v0 = plan.inverse(y0).double().cpu().numpy().ravel()[z["pix"]]
+        acc = {"backprojection_rel_l2": float(np.linalg.norm(v0 - z["ubp"]) / np.linalg.norm(z["ubp"])),
+               "sample": "%d pixels" % len(z["pix"])}
+    plan.inverse(y, out=fi)
+    lib = pat.load()
+    torch.cuda.synchronize()
+    lib.pat_timing_start(plan._h)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.inverse(y, out=fi)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1) / steps
+    ms = (ctypes.c_double * 13)()
+    cnt = (ctypes.c_int * 13)()
+    if lib.pat_timing_stop(plan._h, ms, cnt, 13) != 0:
+        raise RuntimeError("pat_timing_stop failed")
+    stage = {STAGES[i]: ms[i] / max(cnt[i], 1) for i in range(6, 13)}
+    # the per-stage events serialise the launches slightly; the untimed loop below gives the throughput
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        plan.inverse(y, out=fi)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / steps
+    return {"what": "approximate inverse A^-1 (back-projection, constant, restriction), same plan and batch",
+            "images_per_s": B / (ms_batch * 1e-3), "ms_per_batch": ms_batch,
+            "stage_ms_per_launch": stage, "constant_and_restriction_ms": max(0.0, ms_total - sum(stage.values())),
+            "accuracy_vs_oracle": acc}
 
 
 if __name__ == "__main__":

@@ -163,6 +163,30 @@ int pat_forward_batched(pat_plan p, int B, const void* f, long f_stride, void* g
 int pat_adjoint_batched(pat_plan p, int B, const void* g, long g_stride, void* f, long f_stride,
                         void* ws, void* stream);
 
+/* f = A^-1 g: the approximate inverse of Sec. 2.4 (Algorithm 3), for one
+ * image and batched (same arguments and strides as pat_adjoint*).
+ *   v(x) = 2 c^2 sum_{j,i} w_t w_th g[j][i] d/dn(z_i) G_W(t_j, x - z_i)
+ * is the universal back-projection (eq. E:inverse truncated to the measured
+ * times, eq. E:approx_UBP) with G_W the fundamental solution of the
+ * band-limited model above (spectrum W(|xi|) sin(c|xi|t)/(2 pi c|xi|)),
+ * w_t = T/nt, w_th = R*arc/m, and the normal n(z) pointing into the disk
+ * (the sign with which the formula returns f; that of eq. E:Four_coef_v).
+ * Arc data count as the full circle extended by zero (Alg. 3, step 1).  It is
+ * evaluated like A*: angular FFT per time sample, sine transform per
+ * harmonic times (-i)^k J_k'(lambda R) (eq. E:Four_coef_v), ring synthesis,
+ * spread to the grid, inverse 2D FFT.  Then, with a mask (mask_radius > 0,
+ * Omega_0 = the disk |x| <= mask_radius): C = -(mean of v over the pixel
+ * centres with mask_radius < |x| <= R), eq. E:silly_integral, and
+ * f = v + C on Omega_0, 0 outside.  Without a mask, f = v (Omega_0 is the
+ * whole image, so no pixel lies in Omega \ Omega_0 and C = 0).
+ * A^-1 is a left inverse for data of the full circle recorded long enough
+ * (T well beyond the diameter), not the inverse of the discrete A.
+ * Asynchronous on `stream`; capturable in a HIP graph; uses the same
+ * workspace size as the adjoint. */
+int pat_inverse(pat_plan p, const void* g, void* f, void* ws, void* stream);
+int pat_inverse_batched(pat_plan p, int B, const void* g, long g_stride, void* f, long f_stride,
+                        void* ws, void* stream);
+
 /* ---- Groups of plans (batching of uneven image sizes) --------------------
  * A group runs the forward (or adjoint) chains of up to 6 plans of the same
  * precision together: each stage is ONE kernel launch whose blocks cover

@@ -235,19 +235,23 @@ int ora_ubp(const ora_geom* G, const double* g, int nl, const double* lam, const
     if (!pix) npix = n * n;
     double h = 2.0 * G->a / n, Lam = M_PI / h;
     double scale = 2.0 * G->c * (G->T / nt) * (G->R * G->arc / m) / (2.0 * M_PI);
-    /* Sg[i][l] = w_l W_l l * sum_j g[j][i] sin(c l t_j) */
+    /* st[j][l] = sin(c l t_j);  Sg[i][l] = w_l W_l l * sum_j g[j][i] st[j][l] */
+    double* st = malloc(sizeof(double) * (size_t)nt * nl);
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < nt; ++j) {
+        double t = (j + 1) * G->T / nt;
+        for (int l = 0; l < nl; ++l) st[(size_t)j * nl + l] = sin(G->c * lam[l] * t);
+    }
     double* Sg = malloc(sizeof(double) * (size_t)m * nl);
     #pragma omp parallel for schedule(static)
     for (int i = 0; i < m; ++i) {
         for (int l = 0; l < nl; ++l) {
             double s = 0.0, cmp = 0.0;
-            for (int j = 0; j < nt; ++j) {
-                double t = (j + 1) * G->T / nt;
-                neumaier_add(&s, &cmp, g[(size_t)j * m + i] * sin(G->c * lam[l] * t));
-            }
+            for (int j = 0; j < nt; ++j) neumaier_add(&s, &cmp, g[(size_t)j * m + i] * st[(size_t)j * nl + l]);
             Sg[(size_t)i * nl + l] = (s + cmp) * wl[l] * ora_taper(lam[l], Lam, G->rho) * lam[l];
         }
     }
+    free(st);
     double* zx = malloc(sizeof(double) * m);
     double* zy = malloc(sizeof(double) * m);
     double* nx = malloc(sizeof(double) * m);

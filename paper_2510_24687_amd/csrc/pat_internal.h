@@ -37,6 +37,7 @@ struct Params {
     int npts;               // half-ring samples over all rings
     double pre_scale;       // h^2 / (2 pi)
     double adj_scale;       // (T/nt)(R arc/m)/h^2
+    double inv_scale;       // -2 c adj_scale: the approximate inverse's back-projection
 };
 
 struct HostPlan {
@@ -46,6 +47,8 @@ struct HostPlan {
     std::vector<int> ringN, ringLog, ringOff, ringK;  // L
     std::vector<double> Tb;                 // L x Kp, real Bessel/taper/quadrature weights (1/N_l folded)
     std::vector<double> Mk;                 // (klow+1) x nt x lcorr
+    std::vector<double> Tbi;                // L x Kp: as Tb with J_k' in place of J_k (approximate inverse)
+    std::vector<double> Mki;                // (klow+1) x nt x lcorr: as Mk with J_k' and sin in place of J_k and cos
     std::vector<double> phase;              // 2*Kp: e^{i k theta0} (re, im)
     std::vector<double> tw;                 // 2*Nmax: e^{-2 pi i k / Nmax} (re, im)
     std::vector<double> twd;                // 2*(2M): e^{-2 pi i j / (2M)} (re, im), cosine-transform twiddles

@@ -396,6 +396,15 @@ struct Dev {
     const cx<T>* twd;           // 2M: e^{-2 pi i j/(2M)} (cosine-transform twiddles)
     int m3;                     // 1: M = 3 * 2^log2M
     const cx<T>* pos;           // npts: grid position (x, y) of each half-ring sample
+    // approximate inverse (Sec. 2.4): its tables, and the per-call switches of
+    // the adjoint kernels that it reuses
+    const T* Tbi;               // L x Kp: Tb with J_k' for J_k
+    const T* Mki;               // (klow+1) x nt x lcorr: Mk with J_k' and sin
+    double R2;                  // R^2: the detector disk Omega
+    int sine;                   // 1: the transform over t is the sine transform
+    int ubp;                    // 1: rows_adj writes v everywhere plus the partial sums of v over
+                                //    Omega \ Omega_0 (part, one double per block and image)
+    double* part;
 };
 
 template <typename T>
@@ -404,6 +413,17 @@ __device__ __forceinline__ bool in_mask(const Dev<T>& d, int p, int q)
     if (d.mask_r2 <= 0.0) return true;
     double x = -d.a + (q + 0.5) * d.h, y = -d.a + (p + 0.5) * d.h;
     return x * x + y * y <= d.mask_r2;
+}
+
+// Pixel centre in Omega \ Omega_0: inside the detector disk and outside the
+// mask disk (no mask: Omega_0 is the whole image and the set is empty).
+template <typename T>
+__device__ __forceinline__ bool in_annulus(const Dev<T>& d, int p, int q)
+{
+    if (d.mask_r2 <= 0.0) return false;
+    double x = -d.a + (q + 0.5) * d.h, y = -d.a + (p + 0.5) * d.h;
+    double r2 = x * x + y * y;
+    return r2 <= d.R2 && !(r2 <= d.mask_r2);
 }
 
 // exponential-of-semicircle kernel at offset `dd` cells:
@@ -617,7 +637,8 @@ __global__ __launch_bounds__(NT) void ring_fwd(Dev<T> d, const cx<T>* E, cx<T>* 
 // Cosine sum on CW columns of a row-major [rows][Kp] array:
 //   forward: in = V [L][Kp] (x = l),       out = G [nt][Kp] (y = j = 1..nt)
 //   adjoint: in = G [nt][Kp] (x = j),      out = V [L][Kp] (y = l = 0..L-1)
-//   out(y) = sum_x in(x) cos(pi x y / M) = (X(y) + X(-y))/2, X(y) = sum_x in(x) e^{i pi x y/M}.
+//   out(y) = sum_x in(x) cos(pi x y / M) = (X(y) + X(-y))/2, X(y) = sum_x in(x) e^{i pi x y/M},
+//   or with d.sine sum_x in(x) sin(pi x y / M) = (X(y) - X(-y))/(2i).
 // Outputs are split by parity, y = 2y' + r: X(2y'+r) is the M-point inverse DFT of
 // in(x) e^{i pi x r/M} (folded mod M) at y', and X(-y) = that DFT at (-y'-r) mod M.
 // Two M-point FFTs replace one 2M-point FFT of a zero-padded column.
@@ -675,7 +696,10 @@ __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<
             const int y = adjoint ? orow : orow + 1;
             const int yp = (y - r) >> 1;
             const int ypp = (M - yp - r) == M ? 0 : M - yp - r;
-            ob[(size_t)orow * d.Kp + k] = (buf[c * M + yp] + buf[c * M + ypp]) * T(0.5);
+            // cos: (X(y) + X(-y))/2;  sin: (X(y) - X(-y))/(2i)
+            const cx<T> xp = buf[c * M + yp], xm = buf[c * M + ypp];
+            ob[(size_t)orow * d.Kp + k] = d.sine ? cx<T>{T(0.5) * (xp.y - xm.y), T(0.5) * (xm.x - xp.x)}
+                                                 : (xp + xm) * T(0.5);
         }
         __syncthreads();
     }
@@ -1110,6 +1134,22 @@ __global__ __launch_bounds__(NT) void cols_adj(Dev<T> d, const cx<T>* E, cx<T>* 
     cols_adj_body<T>(d, blk_xcd(), E, R, ws_img);
 }
 
+// Sum of one double per thread over the block in a fixed order (lane
+// butterflies within each wave, then the waves in index order); every thread
+// returns the total.  Must be reached by all threads of the block.
+__device__ __forceinline__ double block_sum_fixed(double v)
+{
+    __shared__ double wsum[NT / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();  // wsum may still be read by a previous call
+    if ((threadIdx.x & 63) == 0) wsum[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < NT / 64; ++w) t += wsum[w];
+    return t;
+}
+
 template <typename T>
 __device__ __forceinline__ void rows_adj_body(const Dev<T>& d, Blk bk, const cx<T>* R, T* f, long fstride, size_t ws_img)
 {
@@ -1141,10 +1181,31 @@ __device__ __forceinline__ void rows_adj_body(const Dev<T>& d, Blk bk, const cx<
     lds_fft(buf, d.logNg, 1, 0, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
     const T s1 = d.Dq[p1] * d.pre_scale * d.adj_scale;
     const T s2 = has2 ? d.Dq[p2] * d.pre_scale * d.adj_scale : T(0);
+    if (!d.ubp) {
+        for (int q = threadIdx.x; q < n; q += blockDim.x) {
+            cx<T> v = buf[(q - n / 2 + Ng) & (Ng - 1)];
+            fb[(size_t)p1 * n + q] = in_mask(d, p1, q) ? v.x * d.Dq[q] * s1 : T(0);
+            if (has2) fb[(size_t)p2 * n + q] = in_mask(d, p2, q) ? v.y * d.Dq[q] * s2 : T(0);
+        }
+        return;
+    }
+    // back-projection of the approximate inverse: v everywhere, and this
+    // block's sum of v over Omega \ Omega_0 (fixed order: lanes, waves)
+    double acc = 0.0;
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
         cx<T> v = buf[(q - n / 2 + Ng) & (Ng - 1)];
-        fb[(size_t)p1 * n + q] = in_mask(d, p1, q) ? v.x * d.Dq[q] * s1 : T(0);
-        if (has2) fb[(size_t)p2 * n + q] = in_mask(d, p2, q) ? v.y * d.Dq[q] * s2 : T(0);
+        const T v1 = v.x * d.Dq[q] * s1, v2 = v.y * d.Dq[q] * s2;
+        fb[(size_t)p1 * n + q] = v1;
+        if (in_annulus(d, p1, q)) acc += (double)v1;
+        if (has2) {
+            fb[(size_t)p2 * n + q] = v2;
+            if (in_annulus(d, p2, q)) acc += (double)v2;
+        }
+    }
+    const double tot = block_sum_fixed(acc);
+    if (threadIdx.x == 0) {
+        double* pb = reinterpret_cast<double*>(reinterpret_cast<char*>(d.part) + (size_t)b * ws_img);
+        pb[bx_] = tot;
     }
 }
 
@@ -1152,6 +1213,28 @@ template <typename T>
 __global__ __launch_bounds__(NT) void rows_adj(Dev<T> d, const cx<T>* R, T* f, long fstride, size_t ws_img)
 {
     rows_adj_body<T>(d, blk_xcd(), R, f, fstride, ws_img);
+}
+
+// Last steps of the approximate inverse (Alg. 3): the constant C of eq.
+// E:silly_integral, C = -(sum of v over the pixel centres of Omega \ Omega_0)
+// / (their count), from rows_adj's per-block partial sums, then
+// f = v + C on Omega_0 and 0 elsewhere.  Every block reduces the same
+// partials in the same order, so all blocks use the same C.
+template <typename T>
+__global__ __launch_bounds__(NT) void ubp_apply(Dev<T> d, T* f, long fstride, int nparts, double inv_count,
+                                                size_t ws_img)
+{
+    const int b = blockIdx.y;
+    const double* pb = reinterpret_cast<const double*>(reinterpret_cast<const char*>(d.part) + (size_t)b * ws_img);
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += NT) acc += pb[i];
+    const T C = (T)(-block_sum_fixed(acc) * inv_count);
+    T* fb = f + (size_t)b * fstride;
+    const int n = d.n;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n * n; i += gridDim.x * NT) {
+        const int p = i / n, q = i - p * n;
+        fb[i] = in_mask(d, p, q) ? fb[i] + C : T(0);
+    }
 }
 
 }  // namespace
@@ -1165,7 +1248,8 @@ struct pat_plan_s {
     int device = 0;
     size_t ws_img = 0;                    // workspace bytes per image (pat_workspace_size / batch)
     size_t ws_stride = 0;                 // bytes between per-image slices; the batch's sample array follows them
-    size_t offR, offE, offV, offG, offU, offP;  // byte offsets inside one image's workspace
+    size_t offR, offE, offV, offG, offU, offC, offP;  // byte offsets inside one image's workspace
+    double inv_count = 0.0;               // 1 / (pixel centres in Omega \ Omega_0), 0 if none
     std::vector<void*> allocs;
     size_t table_bytes = 0;
     Dev<float> df{};
@@ -1197,6 +1281,7 @@ void layout(pat_plan_s* p)
     p->offV = o; o = align256(o + cs * (size_t)P.L * P.Kp);
     p->offG = o; o = align256(o + cs * (size_t)P.nt * P.Kp);
     p->offU = o; o = align256(o + cs * (size_t)P.lcorr * (P.klow + 1));
+    p->offC = o; o = align256(o + sizeof(double) * (size_t)((P.n + 1) / 2));  // inverse: rows_adj partial sums
     p->ws_stride = o;
     // the adjoint's half-ring samples, image-minor: B * npts values after the B slices
     // (plus SPREAD_PAD values: the spread reads whole groups of images per sample)
@@ -1291,6 +1376,9 @@ int upload(pat_plan_s* p, Dev<T>& d)
     if ((rc = put(twd.data(), twd.size() * sizeof(T), (const void**)&d.twd))) return rc;
     std::vector<T> pos = conv(H.pos);
     if ((rc = put(pos.data(), pos.size() * sizeof(T), (const void**)&d.pos))) return rc;
+    std::vector<T> Tbi = conv(H.Tbi), Mki = conv(H.Mki);
+    if ((rc = put(Tbi.data(), Tbi.size() * sizeof(T), (const void**)&d.Tbi))) return rc;
+    if ((rc = put(Mki.data(), Mki.size() * sizeof(T), (const void**)&d.Mki))) return rc;
     d.n = P.n; d.m = P.m; d.nt = P.nt; d.mf = P.mf; d.logmf = ilog2i(P.mf);
     d.Ng = P.Ng; d.logNg = ilog2i(P.Ng); d.w = P.w; d.hw = P.hw; d.Rw = P.Rw; d.Ew = P.Ew;
     d.M = P.M; d.m3 = P.m3; d.log2M = ilog2i(P.m3 ? P.M / 3 : P.M); d.L = P.L; d.K = P.K; d.Kp = P.Kp; d.klow = P.klow; d.lcorr = P.lcorr;
@@ -1307,6 +1395,18 @@ int upload(pat_plan_s* p, Dev<T>& d)
     d.dlam = (T)P.dlam; d.pre_scale = (T)P.pre_scale; d.adj_scale = (T)P.adj_scale;
     d.mask_r2 = P.g.mask_radius > 0 ? P.g.mask_radius * P.g.mask_radius : 0.0;
     d.a = P.g.a; d.h = P.h;
+    d.R2 = P.g.R * P.g.R;
+    d.sine = 0; d.ubp = 0; d.part = nullptr;
+    // pixel centres in Omega \ Omega_0, with the kernels' own test
+    long cnt = 0;
+    if (d.mask_r2 > 0.0)
+        for (int pp = 0; pp < P.n; ++pp)
+            for (int q = 0; q < P.n; ++q) {
+                double x = -d.a + (q + 0.5) * d.h, y = -d.a + (pp + 0.5) * d.h;
+                double r2 = x * x + y * y;
+                if (r2 <= d.R2 && !(r2 <= d.mask_r2)) ++cnt;
+            }
+    p->inv_count = cnt > 0 ? 1.0 / (double)cnt : 0.0;
     return PAT_OK;
 }
 
@@ -1451,6 +1551,28 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
         rows_adj<T><<<dim3((d.n + 1) / 2, B), NT, cs * d.Ng, st>>>(d, R, f, fs, wi);
     }
     return check_launch("rows_adj");
+}
+
+// Approximate inverse (Alg. 3): the adjoint chain with the inverse's tables
+// (J_k' for J_k, the sine transform over t, scale -2c s) computes the
+// back-projection v of every pixel and the partial sums over
+// Omega \ Omega_0; ubp_apply adds the constant and restricts to Omega_0.
+template <typename T, int WMAX>
+int run_inverse(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f, long fs, char* ws, hipStream_t st)
+{
+    Dev<T> di = d;
+    di.Tb = d.Tbi;
+    di.Mk = d.Mki;
+    di.sine = 1;
+    di.ubp = 1;
+    di.adj_scale = (T)p->H.P.inv_scale;
+    di.part = reinterpret_cast<double*>(ws + p->offC);
+    int rc = run_adjoint<T, WMAX>(p, di, B, g, gs, f, fs, ws, st);
+    if (rc) return rc;
+    const int n = d.n;
+    const int blocks = std::max(1, std::min((n * n + 4 * NT - 1) / (4 * NT), 256));
+    ubp_apply<T><<<dim3(blocks, B), NT, 0, st>>>(di, f, fs, (n + 1) / 2, p->inv_count, p->ws_stride);
+    return check_launch("ubp_apply");
 }
 
 // ---------------------------------------------------------------------------
@@ -2072,6 +2194,26 @@ int pat_adjoint_batched(pat_plan p, int B, const void* g, long g_stride, void* f
     if (P.dt == PAT_F64)
         return run_adjoint<double, 13>(p, p->dd, B, (const double*)g, g_stride, (double*)f, f_stride, (char*)ws, st);
     return run_adjoint<float, 6>(p, p->df, B, (const float*)g, g_stride, (float*)f, f_stride, (char*)ws, st);
+}
+
+int pat_inverse_batched(pat_plan p, int B, const void* g, long g_stride, void* f, long f_stride, void* ws,
+                        void* stream)
+{
+    if (!p || !f || !g || !ws) return fail(PAT_EINVAL, "pat_inverse_batched: null pointer");
+    const pat::Params& P = p->H.P;
+    if (B < 1 || B > p->max_batch) return fail(PAT_ESMALL, "pat_inverse_batched: B outside [1, max_batch]");
+    if (f_stride < (long)P.n * P.n || g_stride < (long)P.nt * P.m)
+        return fail(PAT_EINVAL, "pat_inverse_batched: stride smaller than one image");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (P.dt == PAT_F64)
+        return run_inverse<double, 13>(p, p->dd, B, (const double*)g, g_stride, (double*)f, f_stride, (char*)ws, st);
+    return run_inverse<float, 6>(p, p->df, B, (const float*)g, g_stride, (float*)f, f_stride, (char*)ws, st);
+}
+
+int pat_inverse(pat_plan p, const void* g, void* f, void* ws, void* stream)
+{
+    if (!p) return fail(PAT_EINVAL, "pat_inverse: NULL plan");
+    return pat_inverse_batched(p, 1, g, (long)p->H.P.nt * p->H.P.m, f, (long)p->H.P.n * p->H.P.n, ws, stream);
 }
 
 int pat_timing_start(pat_plan p)

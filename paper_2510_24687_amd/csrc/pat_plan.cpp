@@ -187,6 +187,10 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
     P.Ew = P.Ng / 2 + 1 + 2 * P.hw;
     P.pre_scale = P.h * P.h / (2.0 * M_PI);
     P.adj_scale = (g.T / g.nt) * (g.R * g.arc / g.m) / (P.h * P.h);
+    // The back-projection of the approximate inverse has the adjoint's form
+    // with J_k' for J_k, sin for cos and the factor 2c; its sign is that of
+    // the normal pointing into the disk (the left-inverse sign).
+    P.inv_scale = -2.0 * g.c * P.adj_scale;
 
     // time period of the discrete cosine sum: the part of g_k(t) that is not the
     // slow 2D tail lives in |c t| <= R + rmax plus the spread caused by the taper
@@ -262,24 +266,31 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
     }
 
     // Bessel/taper/trapezoid weights per ring and harmonic (1/N_l folded in)
+    // (Tbi: the same with the derivative J_k' = (J_{k-1} - J_{k+1})/2, J_0' = -J_1)
     H.Tb.assign((size_t)P.L * P.Kp, 0.0);
+    H.Tbi.assign((size_t)P.L * P.Kp, 0.0);
     {
-        std::vector<double> J(K + 1);
+        std::vector<double> J(K + 2);
         for (int l = 0; l < P.L; ++l) {
             double lam = H.lam[l];
-            bessel_j_all(lam * g.R, K, J.data());
+            bessel_j_all(lam * g.R, K + 1, J.data());
             double trap = (l == 0) ? 0.5 * P.dlam : P.dlam;
             double base = taper(lam, P.Lam, g.taper_rho) * lam * trap / H.ringN[l];
             double cut = 1.0 - chi(lam, P.lam_c, P.lam_s);
-            for (int k = 0; k <= H.ringK[l]; ++k)
-                H.Tb[(size_t)l * P.Kp + k] = base * J[k] * (k <= P.klow ? cut : 1.0);
+            for (int k = 0; k <= H.ringK[l]; ++k) {
+                double wk = base * (k <= P.klow ? cut : 1.0);
+                double dJ = k == 0 ? -J[1] : 0.5 * (J[k - 1] - J[k + 1]);
+                H.Tb[(size_t)l * P.Kp + k] = wk * J[k];
+                H.Tbi[(size_t)l * P.Kp + k] = wk * dJ;
+            }
         }
     }
 
     // low-frequency correction: exact quadrature over [0, lam_c + 6 lam_s] of
     // chi W lambda J_k(lambda R) cos(c lambda t_j) F_k(lambda), with F_k
     // interpolated from the ring samples (it is band-limited of type rmax;
-    // samples at negative lambda are (-1)^k times the mirrored ones).
+    // samples at negative lambda are (-1)^k times the mirrored ones); Mki is
+    // the same with J_k' and sin, for the approximate inverse.
     {
         int nq = 12;
         std::vector<double> gx, gw;
@@ -290,8 +301,9 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
         if (bfrac >= 0.95) { err = "internal: ring spacing too coarse for interpolation"; return PAT_EUNSUPPORTED; }
         double r = std::sqrt(P.Ls / ((1.0 - bfrac) * M_PI));
         H.Mk.assign((size_t)(P.klow + 1) * g.nt * P.lcorr, 0.0);
-        std::vector<double> Jn(P.klow + 1);
-        std::vector<double> cosv(g.nt);
+        H.Mki.assign((size_t)(P.klow + 1) * g.nt * P.lcorr, 0.0);
+        std::vector<double> Jn(P.klow + 2), dJn(P.klow + 1);
+        std::vector<double> cosv(g.nt), sinv(g.nt);
         for (int pi = 0; pi < npan; ++pi) {
             double lo = pi * pw, hi = std::min(lam_end, lo + pw);
             for (int qi = 0; qi < nq; ++qi) {
@@ -299,8 +311,12 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
                 double nu = 0.5 * (hi - lo) * gw[qi];
                 double base = nu * chi(mu, P.lam_c, P.lam_s) * taper(mu, P.Lam, g.taper_rho) * mu;
                 if (base == 0.0) continue;
-                bessel_j_all(mu * g.R, P.klow, Jn.data());
-                for (int j = 0; j < g.nt; ++j) cosv[j] = std::cos(g.c * mu * (j + 1) * g.T / g.nt);
+                bessel_j_all(mu * g.R, P.klow + 1, Jn.data());
+                for (int k = 0; k <= P.klow; ++k) dJn[k] = k == 0 ? -Jn[1] : 0.5 * (Jn[k - 1] - Jn[k + 1]);
+                for (int j = 0; j < g.nt; ++j) {
+                    cosv[j] = std::cos(g.c * mu * (j + 1) * g.T / g.nt);
+                    sinv[j] = std::sin(g.c * mu * (j + 1) * g.T / g.nt);
+                }
                 double xs = mu / P.dlam;
                 int l0 = std::max(0, (int)std::floor(xs - P.Ls) - 1);
                 int l1 = std::min(P.lcorr - 1, (int)std::ceil(xs + P.Ls) + 1);
@@ -309,10 +325,13 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
                     double sm = (l >= 1) ? sinc_kernel(xs + l, P.Ls, r) : 0.0;
                     for (int k = 0; k <= P.klow; ++k) {
                         double s = sp + ((k & 1) ? -sm : sm);
-                        double c = base * Jn[k] * s;
-                        if (c == 0.0) continue;
+                        double c = base * Jn[k] * s, ci = base * dJn[k] * s;
                         double* row = &H.Mk[((size_t)k * g.nt) * P.lcorr + l];
-                        for (int j = 0; j < g.nt; ++j) row[(size_t)j * P.lcorr] += c * cosv[j];
+                        double* rowi = &H.Mki[((size_t)k * g.nt) * P.lcorr + l];
+                        for (int j = 0; j < g.nt; ++j) {
+                            row[(size_t)j * P.lcorr] += c * cosv[j];
+                            rowi[(size_t)j * P.lcorr] += ci * sinv[j];
+                        }
                     }
                 }
                 // mirrored samples of rings l <= Ls near lambda = 0 are covered by sm above

@@ -45,7 +45,7 @@ class PlanInfo(ctypes.Structure):
 
 EXPORTED = ["pat_plan_create", "pat_plan_query", "pat_plan_destroy", "pat_plan_get_info",
             "pat_workspace_size", "pat_forward", "pat_adjoint", "pat_forward_batched",
-            "pat_adjoint_batched", "pat_adjoint_scale", "pat_status_string", "pat_last_error",
+            "pat_adjoint_batched", "pat_inverse", "pat_inverse_batched", "pat_adjoint_scale", "pat_status_string", "pat_last_error",
             "pat_debug_bessel", "pat_axpby", "pat_conv_packed_size", "pat_conv_pack_weights", "pat_conv3x3",
             "pat_conv_wgrad_partials", "pat_conv3x3_wgrad", "pat_conv_bwd_partials", "pat_plane_sum", "pat_adam", "pat_opnorm_estimate",
             "pat_group_create", "pat_group_destroy", "pat_group_forward", "pat_group_adjoint"]
@@ -81,6 +81,8 @@ def load():
     lib.pat_adjoint.argtypes = [vp, vp, vp, vp, vp]
     lib.pat_forward_batched.argtypes = [vp, i, vp, L, vp, L, vp, vp]
     lib.pat_adjoint_batched.argtypes = [vp, i, vp, L, vp, L, vp, vp]
+    lib.pat_inverse.argtypes = [vp, vp, vp, vp, vp]
+    lib.pat_inverse_batched.argtypes = [vp, i, vp, L, vp, L, vp, vp]
     lib.pat_adjoint_scale.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.pat_status_string.argtypes = [i]
     lib.pat_status_string.restype = ctypes.c_char_p
@@ -217,10 +219,22 @@ class Plan:
             raise ValueError("expected trailing shape %s, got %s" % (shape_tail, tuple(xb.shape[1:])))
         return xb.contiguous(), single
 
+    def _out(self, out, shape):
+        """The output tensor: a new one, or ``out`` after checking that the
+        library may write ``shape`` into it."""
+        t = self.torch
+        if out is None:
+            return t.empty(shape, dtype=self.dtype, device=self.device)
+        if not isinstance(out, t.Tensor) or out.device.type != "cuda" or out.dtype != self.dtype:
+            raise TypeError("out must be a CUDA tensor of the plan's dtype")
+        if not out.is_contiguous() or out.numel() != int(np.prod(shape)):
+            raise ValueError("out must be contiguous with %d elements" % int(np.prod(shape)))
+        return out.view(shape)
+
     def forward(self, f, out=None):
         fb, single = self._prep(f, (self.n, self.n))
         B = fb.shape[0]
-        g = out if out is not None else self.torch.empty((B, self.nt, self.m), dtype=self.dtype, device=self.device)
+        g = self._out(out, (B, self.nt, self.m))
         for s in range(0, B, self.max_batch):
             e = min(B, s + self.max_batch)
             ws = self.workspace(e - s)
@@ -228,20 +242,28 @@ class Plan:
                                                  ctypes.c_void_p(g[s].data_ptr()), self.nt * self.m,
                                                  ctypes.c_void_p(ws.data_ptr()), self._stream()),
                    "pat_forward_batched")
-        return g[0] if single and out is None else g
+        return g[0] if single and out is None else (out if out is not None else g)
 
     def adjoint(self, g, out=None):
+        return self._traces_to_image(self._lib.pat_adjoint_batched, "pat_adjoint_batched", g, out)
+
+    def inverse(self, g, out=None):
+        """Approximate inverse A^-1 of Sec. 2.4 (Alg. 3): the universal
+        back-projection with the constant of eq. E:silly_integral, restricted
+        to the mask disk (see pat_inverse in pat.h)."""
+        return self._traces_to_image(self._lib.pat_inverse_batched, "pat_inverse_batched", g, out)
+
+    def _traces_to_image(self, fn, what, g, out):
         gb, single = self._prep(g, (self.nt, self.m))
         B = gb.shape[0]
-        f = out if out is not None else self.torch.empty((B, self.n, self.n), dtype=self.dtype, device=self.device)
+        f = self._out(out, (B, self.n, self.n))
         for s in range(0, B, self.max_batch):
             e = min(B, s + self.max_batch)
             ws = self.workspace(e - s)
-            _check(self._lib.pat_adjoint_batched(self._h, e - s, ctypes.c_void_p(gb[s].data_ptr()), self.nt * self.m,
-                                                 ctypes.c_void_p(f[s].data_ptr()), self.n * self.n,
-                                                 ctypes.c_void_p(ws.data_ptr()), self._stream()),
-                   "pat_adjoint_batched")
-        return f[0] if single and out is None else f
+            _check(fn(self._h, e - s, ctypes.c_void_p(gb[s].data_ptr()), self.nt * self.m,
+                      ctypes.c_void_p(f[s].data_ptr()), self.n * self.n, ctypes.c_void_p(ws.data_ptr()),
+                      self._stream()), what)
+        return f[0] if single and out is None else (out if out is not None else f)
 
     def opnorm(self, iters: int = 30) -> float:
         """||A|| from the X to the Y inner products (power iteration in the library)."""

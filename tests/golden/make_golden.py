@@ -4,7 +4,10 @@ Calls only the CPU FP64 oracle (``oracle/``) and the seeded input generators;
 nothing here touches the GPU library.  Each case stores, for a seeded input,
 the oracle's forward traces at a seeded subset of detectors (all times) and
 the oracle's weighted adjoint of seeded N(0,1) traces at a seeded subset of
-pixels.  Run from the repository root:  python tests/golden/make_golden.py
+pixels.  The ``inv_*`` cases store the back-projection v of the approximate
+inverse (before its constant; no mask) of seeded N(0,1) traces at a seeded
+subset of pixels.  Run from the repository root:
+python tests/golden/make_golden.py [case names]
 """
 import os
 import sys
@@ -29,6 +32,26 @@ CASES = {
 }
 
 
+# name -> (geometry, trace seed, pixels sampled)
+INV_CASES = {
+    "inv_full_n256": (P.full_circle(256, 512, 512, T=2.0), 21, 128),
+    "inv_full_n512": (P.full_circle(512, 1024, 1024, T=2.0), 22, 128),
+}
+
+
+def make_inverse(name):
+    geom, gseed, npix = INV_CASES[name]
+    n, m, nt = geom["n"], geom["m"], geom["nt"]
+    rng = np.random.default_rng(2000 + gseed)
+    pix = np.sort(rng.choice(n * n, size=npix, replace=False)).astype(np.int32)
+    y = P.randn((nt, m), gseed)
+    t0 = time.time()
+    v = oracle.ubp(geom, y, pix=pix)
+    np.savez(os.path.join(HERE, name + ".npz"), pix=pix, ubp=v, trace_seed=gseed,
+             geometry=np.array(repr(sorted(geom.items()))))
+    print("%s: back-projection %.1fs" % (name, time.time() - t0), flush=True)
+
+
 def make(name):
     geom, fseed, gseed, ndet, npix = CASES[name]
     n, m, nt = geom["n"], geom["m"], geom["nt"]
@@ -48,5 +71,8 @@ def make(name):
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or CASES):
-        make(name)
+    for name in (sys.argv[1:] or list(CASES) + list(INV_CASES)):
+        if name in INV_CASES:
+            make_inverse(name)
+        else:
+            make(name)
