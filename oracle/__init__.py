@@ -34,6 +34,9 @@ arXiv 2510.24687, that it follows):
   back-projection of eq. E:approx_UBP with the band-limited fundamental
   solution (C, direct quadrature of its J1 form), the constant of eq.
   E:silly_integral and the restriction to the support.
+* ``measure`` -- the measurement operator B of eq. E:real_meas (Sec. 1):
+  attenuation e^{-gamma t}, then the 1D Fourier filter eta in t per detector
+  trace (numpy FFT of the zero-extended trace), and its adjoint.
 * ``kspace_ubp`` -- an independent route to the same back-projection: the
   2D Fourier integral of the normal derivative of G (eq. E:Fourier_Green)
   evaluated on a polar quadrature grid, with no Bessel functions.  Pins
@@ -445,3 +448,67 @@ def fd_gauss(blobs, dets_xy, times, dx: float, box: float, c: float = 1.0, nu: f
         prev, cur = cur, nxt
         k += 1
     return out
+
+
+# ---------------------------------------------------------------------------
+# Measurement operator B of eq. E:real_meas (Sec. 1): attenuation e^{-gamma t}
+# and a transducer response eta applied as a 1D Fourier filter in t.
+# ---------------------------------------------------------------------------
+def filter_length(nt: int) -> int:
+    """Length N of the discrete transform in t: the smallest power of two
+    >= 2 nt (each trace is zero-extended from nt to N samples, so the filter's
+    wrap-around never mixes the end of a record into its start)."""
+    N = 1
+    while N < 2 * nt:
+        N *= 2
+    return N
+
+
+def response_full(eta, N: int):
+    """eta at the N frequencies of the DFT, xi_k = 2 pi k / (N dt): the given
+    values for k = 0..N/2 and eta(-xi) = conj(eta(xi)) (a real filter) above;
+    eta_0 and eta_{N/2} contribute their real parts."""
+    eta = np.asarray(eta, dtype=complex)
+    if eta.shape != (N // 2 + 1,):
+        raise ValueError("eta must hold N/2 + 1 values")
+    H = np.zeros(N, dtype=complex)
+    H[:N // 2 + 1] = eta
+    H[0], H[N // 2] = eta[0].real, eta[N // 2].real
+    H[N // 2 + 1:] = np.conj(eta[1:N // 2][::-1])
+    return H
+
+
+def measure(geom: dict, g, gamma: float, eta, adjoint: bool = False):
+    """B (or its adjoint) on traces g (nt x m, time-major):
+
+        B g = D(e^{-gamma t} g),   D h = F^-1(eta F h)  per detector trace,
+
+    eq. E:real_meas with F the DFT of the trace zero-extended to
+    N = filter_length(nt) samples (t_j = (j+1) T/nt), the result cut back to
+    the nt measured samples.  Under the trace inner product (the same
+    weights w_t w_th on both sides) the adjoint is
+    B* g = e^{-gamma t} F^-1(conj(eta) F g), with the same extension and cut."""
+    gg = full_geom(geom)
+    nt, m = gg["nt"], gg["m"]
+    g = np.asarray(g, dtype=np.float64).reshape(nt, m)
+    N = filter_length(nt)
+    H = response_full(eta, N)
+    e = np.exp(-gamma * (np.arange(nt) + 1) * gg["T"] / nt)[:, None]
+    h = g if adjoint else e * g
+    pad = np.zeros((N, m))
+    pad[:nt] = h
+    out = np.fft.ifft((np.conj(H) if adjoint else H)[:, None] * np.fft.fft(pad, axis=0), axis=0).real[:nt]
+    return e * out if adjoint else out
+
+
+def transducer_response(nt: int, T: float, f0: float, bw: float):
+    """A smooth band-pass response for tests and benchmarks (the paper leaves
+    eta open): eta(xi) = exp(-(|xi| - 2 pi f0)^2 / (2 (2 pi bw)^2)) -
+    exp(-(|xi| + 2 pi f0)^2 / ...) times a half-sample delay phase, at the
+    N/2 + 1 non-negative DFT frequencies of filter_length(nt)."""
+    N = filter_length(nt)
+    dt = T / nt
+    xi = 2 * np.pi * np.arange(N // 2 + 1) / (N * dt)
+    w0, s = 2 * np.pi * f0, 2 * np.pi * bw
+    mag = np.exp(-(xi - w0) ** 2 / (2 * s * s)) - np.exp(-(xi + w0) ** 2 / (2 * s * s))
+    return mag * np.exp(-0.5j * xi * dt)
