@@ -187,6 +187,37 @@ int pat_inverse(pat_plan p, const void* g, void* f, void* ws, void* stream);
 int pat_inverse_batched(pat_plan p, int B, const void* g, long g_stride, void* f, long f_stride,
                         void* ws, void* stream);
 
+/* ---- Measurement operator B (eq. E:real_meas, Sec. 1) --------------------
+ * Real data are the ideal traces damped by e^{-gamma t} and passed through
+ * the transducer's frequency response eta (a 1D Fourier filter in t, the
+ * same for every detector):  B g = D(e^{-gamma t} g),  D h = F^-1(eta F h).
+ * Discretisation: each trace (t_j = (j+1) T/nt) is zero-extended to
+ * N = pat_filter_length(nt) samples (the smallest power of two >= 2 nt), so
+ * that the filter's wrap-around does not fold the end of a record into its
+ * start; F is the N-point DFT, the result is cut back to the nt samples.
+ * eta is given at the N/2 + 1 frequencies xi_k = 2 pi k / (N T/nt),
+ * k = 0..N/2, as (re, im) pairs; the negative frequencies are the
+ * conjugates (a real filter) and the imaginary parts at k = 0 and N/2 are
+ * ignored.  The adjoint under the trace inner product is
+ * B* g = e^{-gamma t} F^-1(conj(eta) F g) (same extension and cut).
+ * The operator acts on time-major traces (nt x m, detector fastest) and
+ * commutes with everything A does per time sample, so B A f is
+ * pat_forward then pat_filter_apply, and A* B* g the reverse.
+ * Limits: nt <= 2048 (one-block transform).  The filter keeps its own
+ * device tables (eta on the DFT circle, twiddles, e^{-gamma t_j}) on the
+ * device current at creation. */
+typedef struct pat_filter_s* pat_filter;
+int pat_filter_length(int nt, int* N);
+int pat_filter_create(pat_filter* out, int nt, double T, int m, double gamma, const double* eta, int neta,
+                      pat_dtype dt);
+int pat_filter_destroy(pat_filter f);
+/* B (adjoint = 0) or B* (adjoint = 1) on B traces: in / out device arrays of
+ * the filter's dtype, image b at in + b*in_stride (elements, >= nt*m).
+ * In place when out == in with the same stride; any other overlap is
+ * rejected (PAT_EINVAL).  Asynchronous on `stream`; capturable. */
+int pat_filter_apply(pat_filter f, int adjoint, int B, const void* in, long in_stride, void* out, long out_stride,
+                     void* stream);
+
 /* ---- Groups of plans (batching of uneven image sizes) --------------------
  * A group runs the forward (or adjoint) chains of up to 6 plans of the same
  * precision together: each stage is ONE kernel launch whose blocks cover

@@ -23,7 +23,9 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <memory>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -68,8 +70,6 @@ __device__ __forceinline__ cx<T> mul_ipow(cx<T> a, int k)
 
 __device__ __forceinline__ void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
-__device__ __forceinline__ float exp_t(float x) { return expf(x); }
-__device__ __forceinline__ double exp_t(double x) { return exp(x); }
 __device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
 __device__ __forceinline__ float ceil_t(float x) { return ceilf(x); }
@@ -1237,6 +1237,64 @@ __global__ __launch_bounds__(NT) void ubp_apply(Dev<T> d, T* f, long fstride, in
     }
 }
 
+// ---------------------------------------------------------------------------
+// Measurement operator B of eq. E:real_meas on detector traces (time-major
+// nt x m): B g = D(e^{-gamma t} g), D the Fourier filter eta in t applied to
+// each trace zero-extended to N = 2^ceil(log2(2 nt)) samples and cut back to
+// nt; B* g = e^{-gamma t} D_conj(eta) g.  One block owns CW adjacent
+// detectors (coalesced row segments) and packs them in pairs as the real and
+// imaginary parts of CW/2 complex sequences: since eta(-xi) = conj(eta(xi)),
+// filtering the packed sequence by eta on the whole DFT circle filters both
+// real traces at once.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct FiltDev {
+    int nt, m, N, logN, CW, lcw, fft_lr;
+    const cx<T>* H;    // N: eta on the DFT circle (conjugate-symmetric), 1/N folded in
+    const cx<T>* tw;   // N: e^{-2 pi i k / N}
+    const T* att;      // nt: e^{-gamma t_j}
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void trace_filter(FiltDev<T> d, const T* in, long istride, T* out, long ostride,
+                                                   int adjoint)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    const Blk bk = blk_xcd();
+    const int i0 = bk.x * d.CW, b = bk.y;
+    const int N = d.N, CW = d.CW, np = CW >> 1;
+    const T* ib = in + (size_t)b * istride;
+    T* ob = out + (size_t)b * ostride;
+    T* bre = reinterpret_cast<T*>(buf);
+    for (int idx = threadIdx.x; idx < CW * N; idx += NT) {
+        const int j = idx >> d.lcw, c = idx & (CW - 1);
+        T v = T(0);
+        if (j < d.nt && i0 + c < d.m) {
+            v = ib[(size_t)j * d.m + i0 + c];
+            if (!adjoint) v *= d.att[j];
+        }
+        bre[2 * ((c >> 1) * N + j) + (c & 1)] = v;   // pair c/2: even -> real, odd -> imaginary
+    }
+    __syncthreads();
+    lds_fft(buf, d.logN, np, N, d.tw, d.logN, false, d.fft_lr, true);
+    for (int idx = threadIdx.x; idx < np * N; idx += NT) {
+        const int k = idx & (N - 1);
+        cx<T> h = d.H[k];
+        if (adjoint) h.y = -h.y;
+        buf[idx] = cmul(buf[idx], h);
+    }
+    __syncthreads();
+    lds_fft(buf, d.logN, np, N, d.tw, d.logN, true, d.fft_lr, true);
+    for (int idx = threadIdx.x; idx < CW * d.nt; idx += NT) {
+        const int j = idx >> d.lcw, c = idx & (CW - 1);
+        if (i0 + c >= d.m) continue;
+        T v = bre[2 * ((c >> 1) * N + j) + (c & 1)];
+        if (adjoint) v *= d.att[j];
+        ob[(size_t)j * d.m + i0 + c] = v;
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1263,6 +1321,14 @@ struct pat_plan_s {
     std::vector<hipEvent_t> ev_pool;       // pairs (start, end)
     std::vector<int> ev_stage;             // stage of each recorded pair
     size_t ev_used = 0;
+};
+
+struct pat_filter_s {
+    int nt = 0, m = 0, N = 0, cw = 2, device = 0;
+    pat_dtype dt = PAT_F32;
+    std::vector<void*> allocs;
+    FiltDev<float> df{};
+    FiltDev<double> dd{};
 };
 
 namespace {
@@ -2239,6 +2305,126 @@ int pat_timing_stop(pat_plan p, double* ms, int* launches, int nstages)
     p->timing = false;
     p->ev_used = 0;
     return PAT_OK;
+}
+
+int pat_filter_length(int nt, int* N)
+{
+    if (!N || nt < 1) return fail(PAT_EINVAL, "pat_filter_length: bad arguments");
+    long L = 1;
+    while (L < 2L * nt) L *= 2;
+    *N = (int)std::min<long>(L, 1L << 30);
+    return PAT_OK;
+}
+
+int pat_filter_create(pat_filter* out, int nt, double T, int m, double gamma, const double* eta, int neta,
+                      pat_dtype dt)
+{
+    if (!out || !eta) return fail(PAT_EINVAL, "pat_filter_create: null argument");
+    *out = nullptr;
+    if (nt < 1 || m < 1 || !(T > 0.0) || !std::isfinite(T) || !std::isfinite(gamma))
+        return fail(PAT_EINVAL, "pat_filter_create: need nt >= 1, m >= 1, finite T > 0 and finite gamma");
+    if (dt != PAT_F32 && dt != PAT_F64) return fail(PAT_EINVAL, "pat_filter_create: bad dtype");
+    int N = 0;
+    pat_filter_length(nt, &N);
+    if (N > FFT_BLOCK_POINTS)
+        return fail(PAT_EUNSUPPORTED, "pat_filter_create: nt > " + std::to_string(FFT_BLOCK_POINTS / 2) +
+                                          " (single-block transform)");
+    if (neta != N / 2 + 1)
+        return fail(PAT_EINVAL, "pat_filter_create: eta must hold N/2 + 1 = " + std::to_string(N / 2 + 1) +
+                                    " complex values (N = pat_filter_length(nt))");
+    for (int k = 0; k < 2 * neta; ++k)
+        if (!std::isfinite(eta[k])) return fail(PAT_EINVAL, "pat_filter_create: eta is not finite");
+    // the response on the whole DFT circle (real filter: eta(-xi) = conj(eta(xi)),
+    // real at 0 and N/2), with the inverse transform's 1/N folded in
+    std::vector<double> H(2 * (size_t)N), tw(2 * (size_t)N), att(nt);
+    for (int k = 0; k < N; ++k) {
+        const int kk = k <= N / 2 ? k : N - k;
+        double re = eta[2 * kk], im = (kk == 0 || kk == N / 2) ? 0.0 : eta[2 * kk + 1];
+        if (k > N / 2) im = -im;
+        H[2 * k] = re / N;
+        H[2 * k + 1] = im / N;
+        const double a = -2.0 * M_PI * k / N;
+        tw[2 * k] = std::cos(a);
+        tw[2 * k + 1] = std::sin(a);
+    }
+    for (int j = 0; j < nt; ++j) att[j] = std::exp(-gamma * (j + 1) * T / nt);
+    auto* f = new (std::nothrow) pat_filter_s();
+    if (!f) return fail(PAT_ENOMEM, "pat_filter_create: out of host memory");
+    f->nt = nt; f->m = m; f->N = N; f->dt = dt;
+    int cw = std::max(2, std::min(16, 2 * (FFT_BLOCK_POINTS / N)));
+    f->cw = cw;
+    if (hipGetDevice(&f->device) != hipSuccess) { delete f; return fail(PAT_EHIP, "pat_filter_create: no device"); }
+    auto put = [&](const std::vector<double>& v, bool f64, const void** dst) -> int {
+        const size_t es = f64 ? 8 : 4;
+        void* ptr = nullptr;
+        if (hipMalloc(&ptr, std::max<size_t>(16, v.size() * es)) != hipSuccess) return PAT_ENOMEM;
+        f->allocs.push_back(ptr);
+        hipError_t e;
+        if (f64) {
+            e = hipMemcpy(ptr, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+        } else {
+            std::vector<float> c(v.begin(), v.end());
+            e = hipMemcpy(ptr, c.data(), c.size() * 4, hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) return PAT_EHIP;
+        *dst = ptr;
+        return PAT_OK;
+    };
+    const bool f64 = dt == PAT_F64;
+    const void *dH = nullptr, *dtw = nullptr, *datt = nullptr;
+    int rc;
+    if ((rc = put(H, f64, &dH)) || (rc = put(tw, f64, &dtw)) || (rc = put(att, f64, &datt))) {
+        pat_filter_destroy(f);
+        return fail(rc, "pat_filter_create: device allocation or copy failed");
+    }
+    int lcw = 0;
+    while ((1 << lcw) < cw) ++lcw;
+    int logN = 0;
+    while ((1 << logN) < N) ++logN;
+    if (f64) f->dd = FiltDev<double>{nt, m, N, logN, cw, lcw, 4, (const cx<double>*)dH, (const cx<double>*)dtw,
+                                     (const double*)datt};
+    else f->df = FiltDev<float>{nt, m, N, logN, cw, lcw, 4, (const cx<float>*)dH, (const cx<float>*)dtw,
+                                (const float*)datt};
+    *out = f;
+    return PAT_OK;
+}
+
+int pat_filter_destroy(pat_filter f)
+{
+    if (!f) return PAT_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev != f->device) (void)hipSetDevice(f->device);
+    for (void* ptr : f->allocs) (void)hipFree(ptr);
+    if (dev != f->device) (void)hipSetDevice(dev);
+    delete f;
+    return PAT_OK;
+}
+
+int pat_filter_apply(pat_filter f, int adjoint, int B, const void* in, long in_stride, void* out, long out_stride,
+                     void* stream)
+{
+    if (!f || !in || !out) return fail(PAT_EINVAL, "pat_filter_apply: null pointer");
+    const long img = (long)f->nt * f->m;
+    if (B < 1 || in_stride < img || out_stride < img)
+        return fail(PAT_EINVAL, "pat_filter_apply: need B >= 1 and strides >= nt*m");
+    const size_t es = f->dt == PAT_F64 ? 8 : 4;
+    const char* a0 = (const char*)in;
+    const char* a1 = a0 + ((size_t)(B - 1) * in_stride + img) * es;
+    const char* b0 = (const char*)out;
+    const char* b1 = b0 + ((size_t)(B - 1) * out_stride + img) * es;
+    const bool overlap = a0 < b1 && b0 < a1;
+    if (overlap && !(a0 == b0 && in_stride == out_stride))
+        return fail(PAT_EINVAL, "pat_filter_apply: input and output overlap (in place needs the same pointer and stride)");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const dim3 grid((f->m + f->cw - 1) / f->cw, B);
+    const size_t lds = (size_t)(f->cw / 2) * f->N * (f->dt == PAT_F64 ? 16 : 8);
+    if (f->dt == PAT_F64)
+        trace_filter<double><<<grid, NT, lds, st>>>(f->dd, (const double*)in, in_stride, (double*)out, out_stride,
+                                                   adjoint ? 1 : 0);
+    else
+        trace_filter<float><<<grid, NT, lds, st>>>(f->df, (const float*)in, in_stride, (float*)out, out_stride,
+                                                  adjoint ? 1 : 0);
+    return check_launch("trace_filter");
 }
 
 int pat_forward(pat_plan p, const void* f, void* g, void* ws, void* stream)

@@ -48,7 +48,8 @@ EXPORTED = ["pat_plan_create", "pat_plan_query", "pat_plan_destroy", "pat_plan_g
             "pat_adjoint_batched", "pat_inverse", "pat_inverse_batched", "pat_adjoint_scale", "pat_status_string", "pat_last_error",
             "pat_debug_bessel", "pat_axpby", "pat_conv_packed_size", "pat_conv_pack_weights", "pat_conv3x3",
             "pat_conv_wgrad_partials", "pat_conv3x3_wgrad", "pat_conv_bwd_partials", "pat_plane_sum", "pat_adam", "pat_opnorm_estimate",
-            "pat_group_create", "pat_group_destroy", "pat_group_forward", "pat_group_adjoint"]
+            "pat_group_create", "pat_group_destroy", "pat_group_forward", "pat_group_adjoint",
+            "pat_filter_length", "pat_filter_create", "pat_filter_destroy", "pat_filter_apply"]
 
 
 class ConvDesc(ctypes.Structure):
@@ -83,6 +84,11 @@ def load():
     lib.pat_adjoint_batched.argtypes = [vp, i, vp, L, vp, L, vp, vp]
     lib.pat_inverse.argtypes = [vp, vp, vp, vp, vp]
     lib.pat_inverse_batched.argtypes = [vp, i, vp, L, vp, L, vp, vp]
+    lib.pat_filter_length.argtypes = [i, ctypes.POINTER(i)]
+    lib.pat_filter_create.argtypes = [ctypes.POINTER(vp), i, ctypes.c_double, i, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double), i, i]
+    lib.pat_filter_destroy.argtypes = [vp]
+    lib.pat_filter_apply.argtypes = [vp, i, i, vp, L, vp, L, vp]
     lib.pat_adjoint_scale.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.pat_status_string.argtypes = [i]
     lib.pat_status_string.restype = ctypes.c_char_p
@@ -330,3 +336,66 @@ class Group:
     def adjoint(self, gs, outs):
         """outs[i] = A*_i gs[i]."""
         return self._run(self._lib.pat_group_adjoint, gs, outs, lambda p: (p.nt, p.m), "pat_group_adjoint")
+
+
+def filter_length(nt: int) -> int:
+    """N of the measurement filter: the smallest power of two >= 2 nt."""
+    lib = load()
+    N = ctypes.c_int()
+    _check(lib.pat_filter_length(int(nt), ctypes.byref(N)), "pat_filter_length")
+    return N.value
+
+
+class Filter:
+    """Measurement operator B of eq. E:real_meas on time-major traces
+    (attenuation e^{-gamma t}, transducer response eta given at the N/2 + 1
+    non-negative DFT frequencies of the zero-extended trace; see
+    pat_filter_create).  apply(g) = B g, apply(g, adjoint=True) = B* g."""
+
+    def __init__(self, nt: int, T: float, m: int, gamma: float, eta, dtype=None, device=None):
+        import torch
+        self.torch = torch
+        self.dtype = dtype if dtype is not None else torch.float32
+        if self.dtype not in (torch.float32, torch.float64):
+            raise TypeError("dtype must be float32 or float64")
+        self.device = torch.device(device if device is not None else "cuda")
+        self.nt, self.m, self.T, self.gamma = int(nt), int(m), float(T), float(gamma)
+        eta = np.asarray(eta, dtype=np.complex128).ravel()
+        buf = np.ascontiguousarray(np.stack([eta.real, eta.imag], axis=1).ravel())
+        self._lib = load()
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self._lib.pat_filter_create(ctypes.byref(h), self.nt, self.T, self.m, self.gamma,
+                                               buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(eta),
+                                               1 if self.dtype == torch.float64 else 0), "pat_filter_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and getattr(self, "_lib", None) is not None:
+            self._lib.pat_filter_destroy(h)
+            self._h = None
+
+    def apply(self, g, adjoint: bool = False, out=None):
+        t = self.torch
+        if not isinstance(g, t.Tensor) or g.device.type != "cuda" or g.dtype != self.dtype:
+            raise TypeError("expected a CUDA tensor of the filter's dtype")
+        single = g.dim() == 2
+        gb = (g.unsqueeze(0) if single else g).contiguous()
+        if tuple(gb.shape[1:]) != (self.nt, self.m):
+            raise ValueError("expected traces of shape (nt, m) = (%d, %d)" % (self.nt, self.m))
+        B = gb.shape[0]
+        if out is None:
+            res = t.empty_like(gb)
+        else:
+            if (not isinstance(out, t.Tensor) or out.dtype != self.dtype or out.device != gb.device
+                    or not out.is_contiguous() or out.numel() != gb.numel()):
+                raise ValueError("out must be a contiguous tensor like the input")
+            res = out.view(gb.shape)
+        stream = ctypes.c_void_p(t.cuda.current_stream(gb.device).cuda_stream)
+        img = self.nt * self.m
+        _check(self._lib.pat_filter_apply(self._h, 1 if adjoint else 0, B, ctypes.c_void_p(gb.data_ptr()), img,
+                                          ctypes.c_void_p(res.data_ptr()), img, stream), "pat_filter_apply")
+        if out is not None:
+            return out
+        return res[0] if single else res
