@@ -15,6 +15,7 @@ struct Params {
     pat_geometry g;
     pat_dtype dt;
     int n, m, nt, mf;       // image side, detectors, time samples, full-circle detector count
+    int mf3;                // 1 when mf = 3 * 2^a (else a power of two)
     double h, Lam, rmax;    // pixel size, Nyquist radius pi/h, largest |x| entering A
     double shift;           // x_q = h (q' + shift), q' = q - n/2 (integer division)
     int Ng;                 // oversampled Cartesian grid (per side), power of two
@@ -52,6 +53,7 @@ struct HostPlan {
     std::vector<double> phase;              // 2*Kp: e^{i k theta0} (re, im)
     std::vector<double> tw;                 // 2*Nmax: e^{-2 pi i k / Nmax} (re, im)
     std::vector<double> twd;                // 2*(2M): e^{-2 pi i j / (2M)} (re, im), cosine-transform twiddles
+    std::vector<double> twm;                // 2*(2mf): e^{-2 pi i j / (2mf)}, angular-transform twiddles
     std::vector<double> pos;                // 2*npts: grid position (x, y) of each half-ring sample
 };
 

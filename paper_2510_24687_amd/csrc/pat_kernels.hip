@@ -395,6 +395,8 @@ struct Dev {
     const cx<T>* tw;            // Nmax
     const cx<T>* twd;           // 2M: e^{-2 pi i j/(2M)} (cosine-transform twiddles)
     int m3;                     // 1: M = 3 * 2^log2M
+    int mf3;                    // 1: mf = 3 * 2^logmf
+    const cx<T>* twm;           // 2 mf: e^{-2 pi i j/(2 mf)} (angular-transform twiddles)
     const cx<T>* pos;           // npts: grid position (x, y) of each half-ring sample
     // approximate inverse (Sec. 2.4): its tables, and the per-call switches of
     // the adjoint kernels that it reuses
@@ -763,7 +765,7 @@ __device__ __forceinline__ void synth_fwd_body(const Dev<T>& d, Blk bk, const cx
     // Q_r = Herm(Z1)_r + i Herm(Z2)_r,  Herm(Z)_r = (Z_r + conj(Z_{-r}))/2.
     // Each thread owns the pair (r, mf - r) and rewrites both entries of Z1 in place.
     for (int r = threadIdx.x; r <= mf / 2; r += blockDim.x) {
-        int rm = (mf - r) & (mf - 1);
+        int rm = r == 0 ? 0 : mf - r;
         cx<T> a = Z1[r], am = Z1[rm], c = Z2[r], cm = Z2[rm];
         cx<T> h1 = {T(0.5) * (a.x + am.x), T(0.5) * (a.y - am.y)};
         cx<T> h2 = {T(0.5) * (c.x + cm.x), T(0.5) * (c.y - cm.y)};
@@ -771,7 +773,8 @@ __device__ __forceinline__ void synth_fwd_body(const Dev<T>& d, Blk bk, const cx
         if (rm != r) Z1[rm] = {h1.x + h2.y, h2.x - h1.y};
     }
     __syncthreads();
-    lds_fft(Z1, d.logmf, 1, 0, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
+    if (d.mf3) lds_fft3(Z1, d.logmf, 1, 0, d.tw, d.logNmax, d.twm, true, d.fft_lr, d.tw_table);
+    else lds_fft(Z1, d.logmf, 1, 0, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
     for (int i = threadIdx.x; i < d.m; i += blockDim.x) {
         gb[(size_t)j1 * d.m + i] = Z1[i].x;
         if (has2) gb[(size_t)j2 * d.m + i] = Z1[i].y;
@@ -806,11 +809,12 @@ __device__ __forceinline__ void synth_adj_body(const Dev<T>& d, Blk bk, const T*
         Z[i] = {a, c};
     }
     __syncthreads();
-    lds_fft(Z, d.logmf, 1, 0, d.tw, d.logNmax, false, d.fft_lr, d.tw_table);
+    if (d.mf3) lds_fft3(Z, d.logmf, 1, 0, d.tw, d.logNmax, d.twm, false, d.fft_lr, d.tw_table);
+    else lds_fft(Z, d.logmf, 1, 0, d.tw, d.logNmax, false, d.fft_lr, d.tw_table);
     for (int k = threadIdx.x; k < d.Kp; k += blockDim.x) {
         cx<T> y1 = {T(0), T(0)}, y2 = {T(0), T(0)};
         if (k <= d.K) {
-            int r = k & (mf - 1), rm = (mf - r) & (mf - 1);
+            const int r = k % mf, rm = r == 0 ? 0 : mf - r;
             cx<T> zr = Z[r], zm = Z[rm];
             y1 = {T(0.5) * (zr.x + zm.x), T(0.5) * (zr.y - zm.y)};
             y2 = {T(0.5) * (zr.y + zm.y), T(0.5) * (zm.x - zr.x)};
@@ -1440,12 +1444,14 @@ int upload(pat_plan_s* p, Dev<T>& d)
     if ((rc = put(tw.data(), tw.size() * sizeof(T), (const void**)&d.tw))) return rc;
     std::vector<T> twd = conv(H.twd);
     if ((rc = put(twd.data(), twd.size() * sizeof(T), (const void**)&d.twd))) return rc;
+    std::vector<T> twm = conv(H.twm);
+    if ((rc = put(twm.data(), twm.size() * sizeof(T), (const void**)&d.twm))) return rc;
     std::vector<T> pos = conv(H.pos);
     if ((rc = put(pos.data(), pos.size() * sizeof(T), (const void**)&d.pos))) return rc;
     std::vector<T> Tbi = conv(H.Tbi), Mki = conv(H.Mki);
     if ((rc = put(Tbi.data(), Tbi.size() * sizeof(T), (const void**)&d.Tbi))) return rc;
     if ((rc = put(Mki.data(), Mki.size() * sizeof(T), (const void**)&d.Mki))) return rc;
-    d.n = P.n; d.m = P.m; d.nt = P.nt; d.mf = P.mf; d.logmf = ilog2i(P.mf);
+    d.n = P.n; d.m = P.m; d.nt = P.nt; d.mf = P.mf; d.mf3 = P.mf3; d.logmf = ilog2i(P.mf3 ? P.mf / 3 : P.mf);
     d.Ng = P.Ng; d.logNg = ilog2i(P.Ng); d.w = P.w; d.hw = P.hw; d.Rw = P.Rw; d.Ew = P.Ew;
     d.M = P.M; d.m3 = P.m3; d.log2M = ilog2i(P.m3 ? P.M / 3 : P.M); d.L = P.L; d.K = P.K; d.Kp = P.Kp; d.klow = P.klow; d.lcorr = P.lcorr;
     d.npts = P.npts; d.logNmax = ilog2i(P.Nmax);
@@ -2034,8 +2040,9 @@ int lds_ok(const pat::Params& P, std::string& err)
 {
     size_t cs = (P.dt == PAT_F64) ? 16 : 8;
     size_t need = std::max({cs * P.Ng, cs * (size_t)P.max_ring, cs * (size_t)P.M, cs * 2 * (size_t)P.mf});
-    int longest = std::max({P.Ng, P.max_ring, P.mf});
-    if (need > 65536 || longest > FFT_BLOCK_POINTS || P.M > fft_points(P)) {
+    int longest = std::max({P.Ng, P.max_ring, P.mf3 ? 0 : P.mf});
+    const int mf3_points = (FFT_REGS / 3) * 3 * NT;   // with a radix-3 pass
+    if (need > 65536 || longest > FFT_BLOCK_POINTS || P.M > fft_points(P) || (P.mf3 && P.mf > mf3_points)) {
         err = "problem too large for the single-block LDS transforms (64 KiB, 4096 points)";
         return PAT_EUNSUPPORTED;
     }

@@ -167,12 +167,14 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
         err = "2*pi*m/arc must be an integer >= m (detectors on a uniform full-circle grid)";
         return PAT_EINVAL;
     }
-    if ((mf & (mf - 1)) != 0 || mf < 4 || mf > 65536) {
-        err = "full-circle detector count 2*pi*m/arc must be a power of two in [4, 65536]";
+    const bool mf_pow2 = (mf & (mf - 1)) == 0;
+    const bool mf_3pow2 = mf % 3 == 0 && ((mf / 3) & (mf / 3 - 1)) == 0;
+    if (!(mf_pow2 || mf_3pow2) || mf < 4 || mf > 65536) {
+        err = "full-circle detector count 2*pi*m/arc must be 2^a or 3*2^a in [4, 65536]";
         return PAT_EUNSUPPORTED;
     }
     const bool f64 = (dt == PAT_F64);
-    P.n = g.n; P.m = g.m; P.nt = g.nt; P.mf = (int)mf;
+    P.n = g.n; P.m = g.m; P.nt = g.nt; P.mf = (int)mf; P.mf3 = mf_pow2 ? 0 : 1;
     P.h = 2.0 * g.a / g.n;
     P.Lam = M_PI / P.h;
     P.rmax = std::sqrt(2.0) * (g.a - 0.5 * P.h);
@@ -352,6 +354,14 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
         double a = -2.0 * M_PI * k / P.Nmax;
         H.tw[2 * k] = std::cos(a);
         H.tw[2 * k + 1] = std::sin(a);
+    }
+
+    // angular-transform twiddles e^{-2 pi i j/(2 m_full)} (its radix-3 pass)
+    H.twm.resize(2 * 2 * (size_t)P.mf);
+    for (int j = 0; j < 2 * P.mf; ++j) {
+        double a = -M_PI * j / P.mf;
+        H.twm[2 * j] = std::cos(a);
+        H.twm[2 * j + 1] = std::sin(a);
     }
 
     // cosine-transform twiddles e^{-2 pi i j/(2M)}

@@ -40,6 +40,7 @@ CASES = [
     ("f32_n64_nomask", "f32", P.full_circle(64, 128, 128)),
     ("f32_arc180_n48", "f32", P.top_arc(48, 64, 96, 180.0, mask_radius=0.8)),
     ("f64_arc90_n32", "f64", P.top_arc(32, 32, 64, 90.0)),
+    ("f32_arc120_n32", "f32", P.top_arc(32, 32, 64, 120.0, mask_radius=0.9)),
 ]
 
 

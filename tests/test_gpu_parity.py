@@ -55,6 +55,9 @@ CASES = [
     ("f32_odd_n33_odd_nt", "f32", P.full_circle(33, 64, 63, T=1.7, c=1.2, R=1.1), "randn"),
     ("f64_arc90_mask", "f64", P.top_arc(48, 32, 50, 90.0, mask_radius=0.8), "randn"),
     ("f32_n128_full", "f32", P.full_circle(128, 256, 256), "ellipse"),
+    # full-circle grids of 3 * 2^a points (radix-3 angular transform)
+    ("f32_arc120_n48", "f32", P.top_arc(48, 64, 96, 120.0), "ellipse"),
+    ("f64_full_m96", "f64", P.full_circle(40, 96, 80, mask_radius=0.95), "randn"),
 ]
 
 

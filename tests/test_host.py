@@ -54,7 +54,7 @@ def test_null_arguments_are_rejected_without_device_work(lib):
 
 
 @pytest.mark.parametrize("bad,code", [
-    (dict(n=4), -1), (dict(c=-1.0), -1), (dict(rho=1.0), -1), (dict(m=360), -2),
+    (dict(n=4), -1), (dict(c=-1.0), -1), (dict(rho=1.0), -1), (dict(m=360), -2), (dict(m=80), -2),
     (dict(arc=2.0), -1), (dict(mask_radius=-0.1), -1), (dict(nt=0), -1),
 ])
 def test_invalid_geometries(lib, bad, code):
@@ -76,6 +76,8 @@ def test_plan_parameters_for_the_workloads(lib):
     assert m512["max_ring"] == 2048
     arc = pat.plan_query(P.top_arc(256, 256, 512, 180.0), "f32")
     assert arc["m_full"] == 512
+    # a 120-degree arc: the full-circle grid has 3 m = 3 * 2^8 points
+    assert pat.plan_query(P.top_arc(256, 256, 512, 120.0), "f32")["m_full"] == 768
     c1 = pat.plan_query(P.full_circle(64, 128, 128), "f64")
     assert c1["stencil"] == 13 and c1["period"] >= 16.0
     # the period always leaves room for the compact part of every harmonic's time signal
