@@ -309,6 +309,11 @@ def main():
     ap.add_argument("--lpd-lr", type=float, default=1e-3)
     ap.add_argument("--lpd-save", default="", help="write the trained weights (npz) here")
     ap.add_argument("--lpd-load", default="", help="evaluate weights written by --lpd-save (no training)")
+    ap.add_argument("--suite", action="store_true",
+                    help="Table-1-style experiments: inverse / NNLS / TV / LPD on 360, 180 and 120 degree schemes")
+    ap.add_argument("--suite-tests", type=int, default=4)
+    ap.add_argument("--suite-lpd-steps", type=int, default=3000)
+    ap.add_argument("--suite-schemes", default="", help="comma-separated scheme names (default: all)")
     ap.add_argument("--tuning-cache", default="",
                     help="autotuner cache file (default: a fresh temporary file, i.e. tune at start-up)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -323,6 +328,17 @@ def main():
         return
     if args.solvers:
         print(json.dumps({"solvers": solver_bench()}), flush=True)
+        return
+    if args.suite:
+        from paper_2510_24687_amd import experiments as X
+        t_start = time.time()
+
+        def log(row):
+            print(json.dumps({"suite_progress": round(time.time() - t_start, 1), "row": row}), flush=True)
+
+        names = [x.strip() for x in args.suite_schemes.split(",") if x.strip()] or None
+        res = X.run_suite(tests=args.suite_tests, schemes=names, lpd_steps=args.suite_lpd_steps, log=log)
+        print(json.dumps({"suite": res}), flush=True)
         return
     if args.lpd:
         print(json.dumps({"lpd": lpd_bench(steps=args.lpd_steps, n_train=args.lpd_train, lr=args.lpd_lr,

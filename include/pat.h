@@ -6,7 +6,7 @@
  *
  * Operators
  *   A  : initial pressure f on an n x n grid  ->  traces g(t_j, z_i) on the
- *        detector circle (the wave operator of Sec. 1, eq. E:green_conv),
+ *        detector circle (the wave operator of Sec. 2.1, eq. E:green_conv),
  *        evaluated in O(n^2 log n) by the harmonic route of Sec. 3.1
  *        (Algorithm 1: 2D FFT, Cartesian->polar interpolation, angular FFT
  *        per ring, Bessel-weighted cosine transform per harmonic, angular
@@ -69,7 +69,7 @@ enum {
 
 typedef enum { PAT_F32 = 0, PAT_F64 = 1 } pat_dtype;
 
-/* Acquisition geometry (problem statement of Sec. 1-2: speed of sound c,
+/* Acquisition geometry (problem statement of Sec. 2: speed of sound c,
  * detector circle of radius R, m detectors on an arc Gamma of the circle,
  * nt samples on (0, T]); image grid n x n on [-a, a]^2. */
 typedef struct {
@@ -163,7 +163,7 @@ int pat_forward_batched(pat_plan p, int B, const void* f, long f_stride, void* g
 int pat_adjoint_batched(pat_plan p, int B, const void* g, long g_stride, void* f, long f_stride,
                         void* ws, void* stream);
 
-/* f = A^-1 g: the approximate inverse of Sec. 2.4 (Algorithm 3), for one
+/* f = A^-1 g: the approximate inverse of Sec. 3.3 (Algorithm 3), for one
  * image and batched (same arguments and strides as pat_adjoint*).
  *   v(x) = 2 c^2 sum_{j,i} w_t w_th g[j][i] d/dn(z_i) G_W(t_j, x - z_i)
  * is the universal back-projection (eq. E:inverse truncated to the measured
@@ -187,7 +187,7 @@ int pat_inverse(pat_plan p, const void* g, void* f, void* ws, void* stream);
 int pat_inverse_batched(pat_plan p, int B, const void* g, long g_stride, void* f, long f_stride,
                         void* ws, void* stream);
 
-/* ---- Measurement operator B (eq. E:real_meas, Sec. 1) --------------------
+/* ---- Measurement operator B (eq. E:real_meas, Sec. 2) --------------------
  * Real data are the ideal traces damped by e^{-gamma t} and passed through
  * the transducer's frequency response eta (a 1D Fourier filter in t, the
  * same for every detector):  B g = D(e^{-gamma t} g),  D h = F^-1(eta F h).
@@ -268,6 +268,13 @@ int pat_timing_stop(pat_plan p, double* ms, int* launches, int nstages);
 
 /* r = a x + b y over `count` elements (y may be NULL: r = a x). */
 int pat_axpby(pat_plan p, long count, double a, const void* x, double b, const void* y, void* r, void* stream);
+
+/* out[b] = sum_{i < count} x[b*stride + i] * y[b*stride + i] for b < B, in FP64
+ * with a fixed summation order (deterministic); x, y of the plan's
+ * precision.  out: B device doubles; scratch: 64*B device doubles.  Used for
+ * the iterations' stopping rule (norm of an update, Sec. 4.3) and objectives. */
+int pat_dot_batched(pat_plan p, int B, long count, long stride, const void* x, const void* y, double* out,
+                    double* scratch, void* stream);
 
 /* Projected gradient step of NNLS (eq:NNLS-projstep, eqn:projectionHalfCircle):
  * f = support * max(0, f - tau * grad) for B images. */

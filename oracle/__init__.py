@@ -30,11 +30,11 @@ arXiv 2510.24687, that it follows):
 * ``fd_gauss`` -- brute-force second-order leapfrog in time with a 4th-order
   Laplacian (the finite-difference approach of Sec. 2.1.1) for Gaussian data
   on a small box.  Pins the physics of ``gauss_forward``.
-* ``ubp`` / ``inverse`` -- the approximate inverse of Sec. 2.4 (Alg. 3): the
+* ``ubp`` / ``inverse`` -- the approximate inverse of Sec. 3.3 (Alg. 3): the
   back-projection of eq. E:approx_UBP with the band-limited fundamental
   solution (C, direct quadrature of its J1 form), the constant of eq.
   E:silly_integral and the restriction to the support.
-* ``measure`` -- the measurement operator B of eq. E:real_meas (Sec. 1):
+* ``measure`` -- the measurement operator B of eq. E:real_meas (Sec. 2):
   attenuation e^{-gamma t}, then the 1D Fourier filter eta in t per detector
   trace (numpy FFT of the zero-extended trace), and its adjoint.
 * ``kspace_ubp`` -- an independent route to the same back-projection: the
@@ -194,7 +194,7 @@ def adjoint_scale(geom: dict) -> float:
 
 
 def ubp(geom: dict, gtr, pix=None, phase_per_panel: float = 10.0, nodes: int = 20):
-    """Back-projection v of eq. E:approx_UBP (Sec. 2.4) on the listed flat pixel
+    """Back-projection v of eq. E:approx_UBP (Sec. 3.3) on the listed flat pixel
     indices (all if None), before the constant and the restriction:
 
         v(x) = 2 c^2 w_t w_th sum_{j,i} g[j][i] d/dn(z_i) G_W(t_j, x - z_i),
@@ -451,7 +451,7 @@ def fd_gauss(blobs, dets_xy, times, dx: float, box: float, c: float = 1.0, nu: f
 
 
 # ---------------------------------------------------------------------------
-# Measurement operator B of eq. E:real_meas (Sec. 1): attenuation e^{-gamma t}
+# Measurement operator B of eq. E:real_meas (Sec. 2): attenuation e^{-gamma t}
 # and a transducer response eta applied as a 1D Fourier filter in t.
 # ---------------------------------------------------------------------------
 def filter_length(nt: int) -> int:

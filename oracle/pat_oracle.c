@@ -12,7 +12,7 @@
  *
  *   The paper writes the pressure as the inverse 2D Fourier transform of
  *   f^(xi) cos(c|xi| t) (Sec. 2.1.1, eq. E:kwave) and measures it on the
- *   detector circle (problem statement, Sec. 1-2).  A sampled image f_pq is
+ *   detector circle (problem statement, Sec. 2).  A sampled image f_pq is
  *   read as the band-limited function whose transform is
  *       W(|xi|) F(xi),   F(xi) = (h^2/2pi) sum_pq f_pq exp(-i xi.x_pq),
  *   (F is the unitary transform of Sec. 2.1.1 applied to the samples, W a

@@ -126,6 +126,42 @@ __global__ __launch_bounds__(NT) void k_dot_final(const double* part, int nparts
     if (threadIdx.x == 0) out[0] = red[0];
 }
 
+// Batched inner products: out[b] = sum_i x_b[i] y_b[i] in FP64, blocks (DOT_PARTS, B),
+// a fixed summation order (grid-stride per thread, tree per block, tree over blocks).
+constexpr int DOT_PARTS = 64;
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_dotb_partial(long count, long stride, const T* x, const T* y, double* part)
+{
+    __shared__ double red[NT];
+    const int b = blockIdx.y;
+    const T* xb = x + (size_t)b * stride;
+    const T* yb = y + (size_t)b * stride;
+    double acc = 0.0;
+    for (long i = blockIdx.x * (long)NT + threadIdx.x; i < count; i += (long)gridDim.x * NT)
+        acc += (double)xb[i] * (double)yb[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = NT / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)b * DOT_PARTS + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(NT) void k_dotb_final(const double* part, int nparts, double* out)
+{
+    __shared__ double red[NT];
+    const int b = blockIdx.x;
+    red[threadIdx.x] = threadIdx.x < nparts ? part[(size_t)b * DOT_PARTS + threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int k = NT / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[b] = red[0];
+}
+
 // x *= 1 / sqrt(*ss) (ss on the device)
 template <typename T>
 __global__ __launch_bounds__(NT) void k_scale_rsqrt(long count, T* x, const double* ss)
@@ -179,6 +215,27 @@ int pat_axpby(pat_plan p, long count, double a, const void* x, double b, const v
     else
         k_axpby<float><<<grid_for(count), NT, 0, st>>>(count, (float)a, (const float*)x, (float)b, (const float*)y, (float*)r);
     return launch_status("pat_axpby");
+}
+
+int pat_dot_batched(pat_plan p, int B, long count, long stride, const void* x, const void* y, double* out,
+                    double* scratch, void* stream)
+{
+    int n, nt, m, f64;
+    double h;
+    if (!p || !x || !y || !out || !scratch || B < 1 || count < 1 || stride < count) {
+        pat::set_error("pat_dot_batched: bad arguments");
+        return PAT_EINVAL;
+    }
+    if (pat::plan_image_size(p, &n, &nt, &m, &h, &f64)) return PAT_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int parts = std::min(DOT_PARTS, grid_for(count));
+    const dim3 grid(parts, B);
+    if (f64)
+        k_dotb_partial<double><<<grid, NT, 0, st>>>(count, stride, (const double*)x, (const double*)y, scratch);
+    else
+        k_dotb_partial<float><<<grid, NT, 0, st>>>(count, stride, (const float*)x, (const float*)y, scratch);
+    k_dotb_final<<<B, NT, 0, st>>>(scratch, parts, out);
+    return launch_status("pat_dot_batched");
 }
 
 int pat_nnls_update(pat_plan p, int B, void* f, const void* grad, double tau, const void* support, void* stream)

@@ -254,7 +254,7 @@ class Plan:
         return self._traces_to_image(self._lib.pat_adjoint_batched, "pat_adjoint_batched", g, out)
 
     def inverse(self, g, out=None):
-        """Approximate inverse A^-1 of Sec. 2.4 (Alg. 3): the universal
+        """Approximate inverse A^-1 of Sec. 3.3 (Alg. 3): the universal
         back-projection with the constant of eq. E:silly_integral, restricted
         to the mask disk (see pat_inverse in pat.h)."""
         return self._traces_to_image(self._lib.pat_inverse_batched, "pat_inverse_batched", g, out)

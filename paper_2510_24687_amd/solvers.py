@@ -43,6 +43,7 @@ def _bind(lib):
     lib.pat_cp_dual_data.argtypes = [_VP, I, _VP, _VP, _VP, D, _VP]
     lib.pat_cp_dual_tv.argtypes = [_VP, I, _VP, _VP, D, D, _VP]
     lib.pat_cp_primal.argtypes = [_VP, I, _VP, _VP, _VP, _VP, D, D, _VP, _VP]
+    lib.pat_dot_batched.argtypes = [_VP, I, L, L, _VP, _VP, _VP, _VP, _VP]
     lib._solver_bound = True
     return lib
 
@@ -199,3 +200,76 @@ class BatchedSolver:
                 val = val + self.lam * h * h * torch.sqrt(gx * gx + gy * gy).sum(dim=(1, 2))
             out.append(val)
         return out
+
+
+class StoppingRule:
+    """Iterate a one-group solver until the update is small (Sec. 4.3): stop
+    after iteration k when ||f_k - f_{k-1}||_2 < tol ||f_1||_2, f_1 the first
+    non-zero iterate, per instance.  One captured HIP graph per iteration
+    holds the copy of the previous iterate, the solver's iteration, the
+    difference (pat_axpby) and its squared norm per instance
+    (pat_dot_batched); the host reads B doubles per iteration."""
+
+    def __init__(self, solver: BatchedSolver, tol: float = 3e-3):
+        if len(solver.groups) != 1:
+            raise ValueError("one group of instances")
+        self.solver, self.tol = solver, float(tol)
+        G = solver.groups[0]
+        self.G = G
+        self.prev = torch.zeros_like(G.f)
+        self.diff = torch.zeros_like(G.f)
+        self.out = torch.zeros(G.B, dtype=torch.float64, device=G.f.device)
+        self.scratch = torch.zeros(64 * G.B, dtype=torch.float64, device=G.f.device)
+        self.lib = solver.lib
+        self.graph = None
+
+    def _iteration(self):
+        lib, G = self.lib, self.G
+        P = G.plan
+        st = _VP(torch.cuda.current_stream().cuda_stream)
+        cnt = G.f.numel()
+        _check(lib.pat_axpby(P._h, cnt, 1.0, _ptr(G.f), 0.0, None, _ptr(self.prev), st), "pat_axpby")
+        self.solver.step()
+        _check(lib.pat_axpby(P._h, cnt, 1.0, _ptr(G.f), -1.0, _ptr(self.prev), _ptr(self.diff), st), "pat_axpby")
+        img = P.n * P.n
+        _check(lib.pat_dot_batched(P._h, G.B, img, img, _ptr(self.diff), _ptr(self.diff), _ptr(self.out),
+                                   _ptr(self.scratch), st), "pat_dot_batched")
+
+    def capture(self):
+        self._iteration()
+        torch.cuda.synchronize()
+        self.solver.reset()
+        self.graph = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(self.graph, stream=s):
+                self._iteration()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.solver.reset()
+
+    def run(self, max_iter: int = 1000):
+        """Returns (iterations per instance, final update norms); the
+        instances' iterates stay in solver.groups[0].f.  All instances
+        iterate until every one has stopped, so run one instance per call
+        when per-instance iterates at their own stopping points matter."""
+        if self.graph is None:
+            self.capture()
+        B = self.G.B
+        first = None
+        stopped = [0] * B
+        last = None
+        for k in range(1, max_iter + 1):
+            self.graph.replay()
+            d = self.out.sqrt().cpu().numpy()
+            last = d
+            if first is None:
+                first = d.copy()
+                continue
+            for b in range(B):
+                if not stopped[b] and d[b] <= self.tol * first[b]:
+                    stopped[b] = k
+            if all(stopped):
+                break
+        return [s if s else max_iter for s in stopped], last

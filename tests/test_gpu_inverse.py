@@ -1,4 +1,4 @@
-"""The approximate inverse A^-1 of Sec. 2.4 (Alg. 3) on the GPU, through the
+"""The approximate inverse A^-1 of Sec. 3.3 (Alg. 3) on the GPU, through the
 C ABI (pat_inverse / pat_inverse_batched), against the CPU FP64 oracle
 (oracle.inverse / oracle.ubp): full tensors at small sizes (with and without
 the mask that brings in the constant of eq. E:silly_integral), sampled

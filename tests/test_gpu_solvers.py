@@ -91,3 +91,36 @@ def test_opnorm_estimate_is_the_operator_norm():
     assert exact * (1 - 1e-4) < est <= exact * (1 + 1e-12)
     est32 = pat.Plan(geom, torch.float32).opnorm(150)
     assert exact * (1 - 1e-4) < est32 < exact * (1 + 1e-5)
+
+
+def test_batched_dot_and_stopping_rule():
+    """pat_dot_batched against FP64 sums; the stopping rule stops NNLS the
+    first time the update is below 0.3 % of the first iterate."""
+    import ctypes
+    geom = P.top_arc(32, 32, 64, 180.0)
+    plan = pat.Plan(geom, torch.float32, max_batch=3)
+    lib = S._bind(pat.load())
+    x = torch.tensor(np.stack([P.randn((32, 32), 5 + b) for b in range(3)]), dtype=torch.float32, device="cuda")
+    y = torch.tensor(np.stack([P.randn((32, 32), 9 + b) for b in range(3)]), dtype=torch.float32, device="cuda")
+    out = torch.zeros(3, dtype=torch.float64, device="cuda")
+    scr = torch.zeros(64 * 3, dtype=torch.float64, device="cuda")
+    rc = lib.pat_dot_batched(plan._h, 3, 1024, 1024, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                             ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(scr.data_ptr()), None)
+    assert rc == 0
+    want = (x.double() * y.double()).sum(dim=(1, 2))
+    assert torch.allclose(out, want, rtol=1e-12, atol=1e-12)
+    # stopping rule on one instance: replaying the same iterations eagerly reproduces the count
+    f = torch.tensor(P.ellipse_phantom(32, 4), dtype=torch.float32, device="cuda")
+    g = plan.forward(f.unsqueeze(0))
+    sol = S.BatchedSolver([(plan, g, None)], method="nnls")
+    rule = S.StoppingRule(sol, 3e-3)
+    iters, last = rule.run(500)
+    assert 2 <= iters[0] < 500
+    ref = S.BatchedSolver([(plan, g, None)], method="nnls", opnorms=sol.norms)
+    norms = []
+    for k in range(iters[0]):
+        prev = ref.groups[0].f.clone()
+        ref.step()
+        norms.append(float((ref.groups[0].f - prev).double().norm()))
+    assert torch.equal(ref.groups[0].f, sol.groups[0].f)
+    assert norms[-1] <= 3e-3 * norms[0] and all(v > 3e-3 * norms[0] for v in norms[1:-1])

@@ -1,4 +1,4 @@
-"""Pins of the approximate-inverse oracle (Sec. 2.4, Alg. 3): the direct J1
+"""Pins of the approximate-inverse oracle (Sec. 3.3, Alg. 3): the direct J1
 form of the back-projection against an independent Fourier-integral route,
 the left-inverse property of the universal back-projection formula (eq.
 E:inverse) on exact wave data, and the constant of eq. E:silly_integral."""
