@@ -398,7 +398,7 @@ struct Dev {
     int mf3;                    // 1: mf = 3 * 2^logmf
     const cx<T>* twm;           // 2 mf: e^{-2 pi i j/(2 mf)} (angular-transform twiddles)
     const cx<T>* pos;           // npts: grid position (x, y) of each half-ring sample
-    // approximate inverse (Sec. 2.4): its tables, and the per-call switches of
+    // approximate inverse (Sec. 3.3): its tables, and the per-call switches of
     // the adjoint kernels that it reuses
     const T* Tbi;               // L x Kp: Tb with J_k' for J_k
     const T* Mki;               // (klow+1) x nt x lcorr: Mk with J_k' and sin
