@@ -1281,15 +1281,15 @@ __global__ __launch_bounds__(NT) void trace_filter(FiltDev<T> d, const T* in, lo
         bre[2 * ((c >> 1) * N + j) + (c & 1)] = v;   // pair c/2: even -> real, odd -> imaginary
     }
     __syncthreads();
-    lds_fft(buf, d.logN, np, N, d.tw, d.logN, false, d.fft_lr, true);
-    for (int idx = threadIdx.x; idx < np * N; idx += NT) {
-        const int k = idx & (N - 1);
+    const int per = max(1, min(np, FFT_BLOCK_POINTS >> d.logN));   // sequences per lds_fft call
+    for (int q = 0; q < np; q += per) lds_fft(buf + q * N, d.logN, min(per, np - q), N, d.tw, d.logN, false, d.fft_lr, true);
+    for (int k = threadIdx.x; k < N; k += NT) {
         cx<T> h = d.H[k];
         if (adjoint) h.y = -h.y;
-        buf[idx] = cmul(buf[idx], h);
+        for (int q = 0; q < np; ++q) buf[q * N + k] = cmul(buf[q * N + k], h);
     }
     __syncthreads();
-    lds_fft(buf, d.logN, np, N, d.tw, d.logN, true, d.fft_lr, true);
+    for (int q = 0; q < np; q += per) lds_fft(buf + q * N, d.logN, min(per, np - q), N, d.tw, d.logN, true, d.fft_lr, true);
     for (int idx = threadIdx.x; idx < CW * d.nt; idx += NT) {
         const int j = idx >> d.lcw, c = idx & (CW - 1);
         if (i0 + c >= d.m) continue;
@@ -2358,7 +2358,10 @@ int pat_filter_create(pat_filter* out, int nt, double T, int m, double gamma, co
     auto* f = new (std::nothrow) pat_filter_s();
     if (!f) return fail(PAT_ENOMEM, "pat_filter_create: out of host memory");
     f->nt = nt; f->m = m; f->N = N; f->dt = dt;
-    int cw = std::max(2, std::min(16, 2 * (FFT_BLOCK_POINTS / N)));
+    // detectors per block: pairs of traces, as many sequences as 32 KiB of LDS
+    // holds (at most 8; more LDS per block costs occupancy: measured slower)
+    const size_t cs = dt == PAT_F64 ? 16 : 8;
+    int cw = 2 * (int)std::max<size_t>(1, std::min<size_t>(8, 32768 / (cs * (size_t)N)));
     f->cw = cw;
     if (hipGetDevice(&f->device) != hipSuccess) { delete f; return fail(PAT_EHIP, "pat_filter_create: no device"); }
     auto put = [&](const std::vector<double>& v, bool f64, const void** dst) -> int {
