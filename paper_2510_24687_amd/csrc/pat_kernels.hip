@@ -375,6 +375,7 @@ struct Dev {
     int colsCW, dctCW;
     int colsLCW, dctLCW;        // log2 of the two (powers of two)
     int dct_stash;              // 1: the cosine transform stashes its input columns in LDS
+    int dct_one;                // 1: the cosine transform uses one M-point FFT per column (dct_cos_body)
     int fft_lr;                 // largest FFT pass radix is 2^fft_lr (3 or 4)
     int tw_table;               // 1: FFT passes read every twiddle from the table
     T beta, shift, half;        // half = Ng / (2 Lambda): grid cells per unit lambda
@@ -636,6 +637,144 @@ __global__ __launch_bounds__(NT) void ring_fwd(Dev<T> d, const cx<T>* E, cx<T>* 
     ring_fwd_body<T, WMAX>(d, blk_xcd(), E, V, Ulow, ws_img, B, G);
 }
 
+// Sum over aligned groups of W consecutive lanes (W a power of two <= 64),
+// butterfly order: every lane of a group returns the group's sum.
+template <typename T>
+__device__ __forceinline__ cx<T> group_sum(cx<T> v, int W)
+{
+    for (int o = 1; o < W; o <<= 1) {
+        v.x += __shfl_xor(v.x, o, W);
+        v.y += __shfl_xor(v.y, o, W);
+    }
+    return v;
+}
+
+// Inclusive prefix sum over aligned groups of W consecutive lanes.
+template <typename T>
+__device__ __forceinline__ cx<T> group_scan(cx<T> v, int W)
+{
+    const int lane = threadIdx.x & (W - 1);
+    for (int o = 1; o < W; o <<= 1) {
+        const T ux = __shfl_up(v.x, o, W), uy = __shfl_up(v.y, o, W);
+        if (lane >= o) { v.x += ux; v.y += uy; }
+    }
+    return v;
+}
+
+// The cosine sum with ONE M-point FFT per column (the DCT-I of each column's
+// real and imaginary parts at once).  With f_j = in(j), j = 0..M (zero outside
+// the valid rows) and s_j = sin(pi j/M), the sequence
+//   g_j = (f_j + f_{M-j})/2 - s_j (f_j - f_{M-j}),  j = 0..M-1  (f_{M-0} = f_M)
+// has the transform G_q = sum_j g_j e^{2 pi i j q/M}, and the interior sums
+// F_y = (f_0 + (-1)^y f_M)/2 + sum_{0<x<M} f_x cos(pi x y/M) satisfy
+//   F_{2q} = (G_q + G_{M-q})/2,   F_{2q+1} = F_{2q-1} - (i/2)(G_q - G_{M-q}),
+// F_1 = (f_0 - f_M)/2 + sum_{0<x<M} f_x cos(pi x/M) (a direct sum); the odd
+// outputs are a prefix sum over q, done per column in a fixed order (serial
+// chunks, then a scan of the chunk totals).  out(y) = F_y + (f_0 + (-1)^y f_M)/2.
+template <typename T>
+__device__ __forceinline__ void dct_cos_body(const Dev<T>& d, Blk bk, const cx<T>* in, cx<T>* out, size_t ws_img,
+                                             int adjoint)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+    __shared__ cx<T> red[16];     // one entry per lane group (a column's lanes inside one wave;
+    __shared__ cx<T> red2[16];    // at most 16 groups: CW <= 16, or 4 waves)
+    const int bx_ = bk.x, b = bk.y;
+    const int CW = d.dctCW, lcw = d.dctLCW, k0 = bx_ * CW;
+    const int M = d.M, logM = d.log2M;
+    const cx<T>* ib = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(in) + (size_t)b * ws_img);
+    cx<T>* ob = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(out) + (size_t)b * ws_img);
+    const int x_lo = adjoint ? 1 : 0, x_hi = adjoint ? d.nt + 1 : d.L;
+    const int nx = x_hi - x_lo;
+    const int nout = adjoint ? d.L : d.nt;
+    const int ymax = adjoint ? d.L - 1 : d.nt;                 // outputs y = y0 .. ymax
+    const int Q = ymax >= 1 ? ((ymax - 1) >> 1) : 0;          // odd outputs need S_0 .. S_Q
+    const int SQ = (M >> 1) + 1;                               // scan row pitch (Q < SQ)
+    cx<T>* scan = buf + CW * M;                                // CW x SQ
+    cx<T>* stash = scan + CW * SQ;                             // CW x nx (with d.dct_stash)
+    if (d.dct_stash) {
+        for (int i = threadIdx.x; i < CW * nx; i += blockDim.x) {
+            const int row = i >> lcw, c = i & (CW - 1);
+            const int k = k0 + c;
+            stash[c * nx + row] = k < d.Kp ? ib[(size_t)row * d.Kp + k] : cx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+    }
+    auto fval = [&](int c, int j) -> cx<T> {
+        if (j < x_lo || j >= x_hi || k0 + c >= d.Kp) return cx<T>{T(0), T(0)};
+        return d.dct_stash ? stash[c * nx + (j - x_lo)] : ib[(size_t)(j - x_lo) * d.Kp + k0 + c];
+    };
+    // thread group of each column: TC = NT / CW consecutive threads
+    const int TC = NT / CW, c_me = threadIdx.x / TC, lt = threadIdx.x - c_me * TC;
+    // F_1's interior sum, reduced in a fixed order: lanes of the column's group
+    // within each wave (butterfly), then the column's waves in index order
+    const int GW = TC < 64 ? TC : 64;          // lanes of one column inside a wave
+    const int NW = TC / GW;                    // waves of one column
+    {
+        cx<T> acc = {T(0), T(0)};
+        for (int j = 1 + lt; j < M; j += TC) acc = acc + fval(c_me, j) * d.twd[j].x;   // cos(pi j/M)
+        acc = group_sum(acc, GW);
+        if ((lt & (GW - 1)) == 0) red[threadIdx.x / GW] = acc;
+    }
+    // g into buf
+    for (int i = threadIdx.x; i < CW * M; i += blockDim.x) {
+        const int j = i >> lcw, c = i & (CW - 1);
+        const cx<T> fj = fval(c, j), fm = fval(c, M - j);
+        const T sj = -d.twd[j].y;                                                     // sin(pi j/M)
+        buf[c * M + j] = {T(0.5) * (fj.x + fm.x) - sj * (fj.x - fm.x), T(0.5) * (fj.y + fm.y) - sj * (fj.y - fm.y)};
+    }
+    __syncthreads();
+    // F_1 of each column (every thread of the column's group)
+    const cx<T> f0 = fval(c_me, 0), fM = fval(c_me, M);
+    cx<T> F1 = {T(0.5) * (f0.x - fM.x), T(0.5) * (f0.y - fM.y)};
+    for (int w = 0; w < NW; ++w) F1 = F1 + red[c_me * NW + w];
+    if (d.m3) lds_fft3(buf, logM, CW, M, d.tw, d.logNmax, d.twd, true, d.fft_lr, d.tw_table);
+    else lds_fft(buf, logM, CW, M, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
+    // S_q = sum_{p=1..q} D_p, D_p = -(i/2)(G_p - G_{M-p}): serial chunks of CH values per thread
+    const int CH = (Q + TC - 1) / TC;
+    {
+        const cx<T>* Gc = buf + c_me * M;
+        cx<T> run = {T(0), T(0)};
+        const int q0 = 1 + lt * CH;
+        for (int q = q0; q < q0 + CH && q <= Q; ++q) {
+            const cx<T> dg = Gc[q] - Gc[M - q];
+            run = run + cx<T>{T(0.5) * dg.y, T(-0.5) * dg.x};
+            scan[c_me * SQ + q] = run;
+        }
+        // scan of the chunk totals over the column's lanes: within each wave by
+        // shuffles, then the totals of the column's earlier waves
+        const cx<T> incl = group_scan(run, GW);
+        if ((lt & (GW - 1)) == GW - 1) red2[threadIdx.x / GW] = incl;
+        cx<T> offs = {__shfl_up(incl.x, 1, GW), __shfl_up(incl.y, 1, GW)};   // exclusive prefix in the wave
+        if ((lt & (GW - 1)) == 0) offs = {T(0), T(0)};
+        __syncthreads();
+        for (int w = 0; w < (lt / GW); ++w) offs = offs + red2[c_me * NW + w];
+        for (int q = q0; q < q0 + CH && q <= Q; ++q) scan[c_me * SQ + q] = scan[c_me * SQ + q] + offs;
+        if (lt == 0) scan[c_me * SQ] = F1;                            // slot 0 holds F_1
+        __syncthreads();
+    }
+    // outputs: y = orow (+1 in the forward)
+    for (int i = threadIdx.x; i < CW * nout; i += blockDim.x) {
+        const int orow = i >> lcw, c = i & (CW - 1);
+        const int k = k0 + c;
+        if (k >= d.Kp) continue;
+        const int y = adjoint ? orow : orow + 1;
+        cx<T> F;
+        if (y & 1) {
+            const int q = y >> 1;
+            F = scan[c * SQ];
+            if (q > 0) F = F + scan[c * SQ + q];
+        } else {
+            const int q = y >> 1;
+            const cx<T> a = buf[c * M + q], bq = buf[c * M + (q == 0 ? 0 : M - q)];
+            F = (a + bq) * T(0.5);
+        }
+        const cx<T> e0 = fval(c, 0), eM = fval(c, M);
+        const T sgn = (y & 1) ? T(-1) : T(1);
+        ob[(size_t)orow * d.Kp + k] = {F.x + T(0.5) * (e0.x + sgn * eM.x), F.y + T(0.5) * (e0.y + sgn * eM.y)};
+    }
+}
+
 // Cosine sum on CW columns of a row-major [rows][Kp] array:
 //   forward: in = V [L][Kp] (x = l),       out = G [nt][Kp] (y = j = 1..nt)
 //   adjoint: in = G [nt][Kp] (x = j),      out = V [L][Kp] (y = l = 0..L-1)
@@ -710,7 +849,8 @@ __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<
 template <typename T>
 __global__ __launch_bounds__(NT) void dct_cols(Dev<T> d, const cx<T>* in, cx<T>* out, size_t ws_img, int adjoint)
 {
-    dct_cols_body<T>(d, blk_xcd(), in, out, ws_img, adjoint);
+    if (d.sine || !d.dct_one) dct_cols_body<T>(d, blk_xcd(), in, out, ws_img, adjoint);
+    else dct_cos_body<T>(d, blk_xcd(), in, out, ws_img, adjoint);
 }
 
 // G_k(t_j) += i^k sum_l Mk[k][j][l] Ulow[l][k], k = 0..klow
@@ -1378,16 +1518,37 @@ int ring_group_max(const pat::Params& P)
 
 // the cosine transform's LDS: CW columns of M points, plus the stash of the
 // CW input columns (max(L, nt) rows) when that still fits 64 KiB
+// cosine-transform block LDS per column: the FFT buffer (M), with the one-FFT
+// form also the prefix sums (M/2 + 1), and, if it fits, the stashed input.
+// The one-FFT kernel also holds two NT-entry reduction arrays (static LDS),
+// which count against the same 64 KiB.
+size_t dct_budget(const pat::Params& P)
+{
+    const size_t cs = (P.dt == PAT_F64) ? 16 : 8;
+    return 65536 - 2 * (size_t)NT * cs;
+}
+
+int dct_one_ok(const pat::Params& P, int cw)
+{
+    const size_t cs = (P.dt == PAT_F64) ? 16 : 8;
+    return (size_t)cw * ((size_t)P.M + P.M / 2 + 1) * cs <= dct_budget(P) ? 1 : 0;
+}
+
+size_t dct_base(const pat::Params& P, int cw)
+{
+    return (size_t)P.M + (dct_one_ok(P, cw) ? (size_t)(P.M / 2 + 1) : 0);
+}
+
 int dct_stash_ok(const pat::Params& P, int cw)
 {
     const size_t cs = (P.dt == PAT_F64) ? 16 : 8;
-    return (size_t)cw * (P.M + std::max(P.L, P.nt)) * cs <= 65536 ? 1 : 0;
+    return (size_t)cw * (dct_base(P, cw) + std::max(P.L, P.nt)) * cs <= dct_budget(P) ? 1 : 0;
 }
 
 size_t dct_lds(const pat::Params& P, int cw)
 {
     const size_t cs = (P.dt == PAT_F64) ? 16 : 8;
-    return cs * cw * ((size_t)P.M + (dct_stash_ok(P, cw) ? std::max(P.L, P.nt) : 0));
+    return cs * cw * (dct_base(P, cw) + (dct_stash_ok(P, cw) ? std::max(P.L, P.nt) : 0));
 }
 
 // points one lds_fft call holds: FFT_REGS per thread and pass, i.e. 16 NT for
@@ -1460,6 +1621,7 @@ int upload(pat_plan_s* p, Dev<T>& d)
     d.colsLCW = ilog2i(p->cols_cw);
     d.dctLCW = ilog2i(p->dct_cw);
     d.dct_stash = dct_stash_ok(P, p->dct_cw);
+    d.dct_one = dct_one_ok(P, p->dct_cw);
     d.fft_lr = p->fft_lr;
     d.tw_table = p->tw_table;
     d.phase_k = (T)(-P.shift * P.h / (0.5 * P.Ng / P.Lam));
@@ -1728,12 +1890,18 @@ __global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
     if constexpr (S == PAT_STAGE_ROWS_FWD) rows_fwd_body<T>(q.d, bk, q.fin, q.fs, R, q.wi);
     if constexpr (S == PAT_STAGE_COLS_FWD) cols_fwd_body<T>(q.d, bk, R, E, q.wi);
     if constexpr (S == PAT_STAGE_RING_FWD) ring_fwd_body<T, WMAX>(q.d, bk, E, V, U, q.wi, q.B, q.G);
-    if constexpr (S == PAT_STAGE_DCT_FWD) dct_cols_body<T>(q.d, bk, V, Gh, q.wi, 0);
+    if constexpr (S == PAT_STAGE_DCT_FWD) {
+        if (q.d.dct_one) dct_cos_body<T>(q.d, bk, V, Gh, q.wi, 0);
+        else dct_cols_body<T>(q.d, bk, V, Gh, q.wi, 0);
+    }
     if constexpr (S == PAT_STAGE_LOWK_FWD) lowk_fwd_body<T>(q.d, bk, U, Gh, q.wi);
     if constexpr (S == PAT_STAGE_SYNTH_FWD) synth_fwd_body<T>(q.d, bk, Gh, q.gout, q.gs, q.wi);
     if constexpr (S == PAT_STAGE_SYNTH_ADJ) synth_adj_body<T>(q.d, bk, q.gin, q.gs, Gh, q.wi);
     if constexpr (S == PAT_STAGE_LOWK_ADJ) lowk_adj_body<T>(q.d, bk, Gh, U, q.wi);
-    if constexpr (S == PAT_STAGE_DCT_ADJ) dct_cols_body<T>(q.d, bk, Gh, V, q.wi, 1);
+    if constexpr (S == PAT_STAGE_DCT_ADJ) {
+        if (q.d.dct_one) dct_cos_body<T>(q.d, bk, Gh, V, q.wi, 1);
+        else dct_cols_body<T>(q.d, bk, Gh, V, q.wi, 1);
+    }
     if constexpr (S == PAT_STAGE_RING_ADJ) ring_adj_body<T, WMAX>(q.d, bk, V, U, Pol, q.B, q.G, q.wi);
     if constexpr (S == PAT_STAGE_SPREAD_ADJ) {
         if (q.staged) spread_tiles_body<T, WMAX, BC, true>(q.d, bk, Pol, q.B, E, q.wi);
@@ -1864,6 +2032,7 @@ void apply_tune(pat_plan_s* p)
     p->df.fft_lr = p->dd.fft_lr = p->fft_lr;
     p->df.tw_table = p->dd.tw_table = p->tw_table;
     p->df.dct_stash = p->dd.dct_stash = dct_stash_ok(p->H.P, p->dct_cw);
+    p->df.dct_one = p->dd.dct_one = dct_one_ok(p->H.P, p->dct_cw);
 }
 
 bool pow2_in(int v, int hi) { return v >= 1 && v <= hi && (v & (v - 1)) == 0; }
