@@ -79,7 +79,13 @@ def measured_traffic(kernel: str, B: int, shapes: dict = None):
     z = json.load(open(path))
     if z.get("source_hash") != kernel_source_hash() or kernel not in z.get("kernels", {}) or z.get("batch") != B:
         return None
-    if shapes is not None and z.get("launch_shapes") not in (None, shapes):
+    # the launch-shape choices that change what this kernel reads and writes
+    relevant = {"spread_adj": ("tune_spread_images", "tune_spread_staged"),
+                "dct_fwd": ("tune_dct_cols_per_block",), "dct_adj": ("tune_dct_cols_per_block",),
+                "ring_fwd": ("tune_ring_images",), "ring_adj": ("tune_ring_images",),
+                "cols_fwd": ("tune_cols_per_block",), "cols_adj": ("tune_cols_per_block",)}.get(kernel, ())
+    recorded = z.get("launch_shapes")
+    if shapes is not None and recorded is not None and any(recorded.get(k) != shapes.get(k) for k in relevant):
         return None
     k = z["kernels"][kernel]
     return (k["fetch_kib"] * z["fetch_scale"] + k["write_kib"] * z["write_scale"]) * 1024.0
