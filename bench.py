@@ -319,7 +319,7 @@ def main():
                     help="Table-1-style experiments: inverse / NNLS / TV / LPD on 360, 180 and 120 degree schemes")
     ap.add_argument("--suite-tests", type=int, default=4)
     ap.add_argument("--suite-lpd-steps", type=int, default=3000)
-    ap.add_argument("--suite-schemes", default="", help="comma-separated scheme names (default: all)")
+    ap.add_argument("--suite-schemes", default="", help="semicolon-separated scheme names (default: all)")
     ap.add_argument("--tuning-cache", default="",
                     help="autotuner cache file (default: a fresh temporary file, i.e. tune at start-up)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -342,7 +342,7 @@ def main():
         def log(row):
             print(json.dumps({"suite_progress": round(time.time() - t_start, 1), "row": row}), flush=True)
 
-        names = [x.strip() for x in args.suite_schemes.split(",") if x.strip()] or None
+        names = [x.strip() for x in args.suite_schemes.split(";") if x.strip()] or None
         res = X.run_suite(tests=args.suite_tests, schemes=names, lpd_steps=args.suite_lpd_steps, log=log)
         print(json.dumps({"suite": res}), flush=True)
         return

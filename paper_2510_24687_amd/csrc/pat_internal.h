@@ -35,6 +35,7 @@ struct Params {
     int lcorr;              // rings feeding the low-frequency correction
     int Nmax;               // twiddle table length (largest FFT)
     int max_ring;           // largest ring FFT
+    int Nr3 = 0;            // largest ring of 3 * 2^a points (0: none)
     int npts;               // half-ring samples over all rings
     double pre_scale;       // h^2 / (2 pi)
     double adj_scale;       // (T/nt)(R arc/m)/h^2
@@ -45,7 +46,9 @@ struct HostPlan {
     Params P;
     std::vector<double> Dq;                 // n: 1/phi_hat(2 pi q'/Ng)
     std::vector<double> lam;                // L
-    std::vector<int> ringN, ringLog, ringOff, ringK;  // L
+    std::vector<int> ringN, ringLog, ringOff, ringK;  // L (ringLog: log2 of N, or of N/3 when ringM3)
+    std::vector<int> ringM3;                          // L: 1 when the ring has 3 * 2^a points
+    std::vector<double> twr;                          // 2*(2 Nr3): e^{-2 pi i j/(2 Nr3)}, ring radix-3 twiddles
     std::vector<double> Tb;                 // L x Kp, real Bessel/taper/quadrature weights (1/N_l folded)
     std::vector<double> Mk;                 // (klow+1) x nt x lcorr
     std::vector<double> Tbi;                // L x Kp: as Tb with J_k' in place of J_k (approximate inverse)

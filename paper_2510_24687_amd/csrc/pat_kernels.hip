@@ -281,7 +281,7 @@ __device__ void lds_fft(cx<T>* buf, int logN, int nb, int stride, const cx<T>* _
 // read from twd (the 2N-th roots e^{-2 pi i j/(2N)}: W_N^{r t} = twd[2 r t]).
 template <typename T>
 __device__ __noinline__ void stockham_pass3(PAT_LDS cx<T>* buf, int logN2, int nb, int stride,
-                                               const PAT_GLOBAL cx<T>* __restrict__ twd, bool inv)
+                                               const PAT_GLOBAL cx<T>* __restrict__ twd, bool inv, int tsh)
 {
     constexpr int BPT = FFT_REGS / 3;
     const int nbf = 1 << logN2;
@@ -304,7 +304,7 @@ __device__ __noinline__ void stockham_pass3(PAT_LDS cx<T>* buf, int logN2, int n
         const int it = threadIdx.x + u * NT;
         if (it < total) {
             const int b = it >> logN2, t = it & (nbf - 1);
-            cx<T> w1 = ld_glb(twd + 2 * t), w2 = ld_glb(twd + 4 * t);
+            cx<T> w1 = ld_glb(twd + ((2 * t) << tsh)), w2 = ld_glb(twd + ((4 * t) << tsh));
             if (inv) { w1.y = -w1.y; w2.y = -w2.y; }
             const cx<T> a0 = v[u][0], a1 = cmul(v[u][1], w1), a2 = cmul(v[u][2], w2);
             const cx<T> sm = a1 + a2, df = a1 - a2;
@@ -323,12 +323,13 @@ __device__ __noinline__ void stockham_pass3(PAT_LDS cx<T>* buf, int logN2, int n
 // Transform of nb sequences of length N = 3 * 2^logN2: the power-of-two passes
 // on the 2^logN2 factor, then the radix-3 pass.  The radix-3 pass keeps
 // FFT_REGS / 3 butterflies per thread, so nb * N <= (FFT_REGS / 3) * 3 * NT.
+// twd holds the 2N'-th roots of unity of a length N' = N 2^tsh.
 template <typename T>
 __device__ void lds_fft3(cx<T>* buf, int logN2, int nb, int stride, const cx<T>* __restrict__ tw, int logNmax,
-                         const cx<T>* __restrict__ twd, bool inverse, int maxlr, bool twtab)
+                         const cx<T>* __restrict__ twd, bool inverse, int maxlr, bool twtab, int tsh = 0)
 {
     lds_fft(buf, logN2, nb, stride, tw, logNmax, inverse, maxlr, twtab, 1);
-    stockham_pass3((PAT_LDS cx<T>*)buf, logN2, nb, stride, (const PAT_GLOBAL cx<T>*)twd, inverse);
+    stockham_pass3((PAT_LDS cx<T>*)buf, logN2, nb, stride, (const PAT_GLOBAL cx<T>*)twd, inverse, tsh);
 }
 
 // MI355X dispatches consecutive workgroups of a grid round-robin over its 8
@@ -390,6 +391,9 @@ struct Dev {
     const int* ringLog;         // L
     const int* ringOff;         // L
     const int* ringK;           // L
+    const int* ringM3;          // L: 1 when ring l has 3 * 2^ringLog[l] points
+    const cx<T>* twr;           // 2 Nr3: e^{-2 pi i j/(2 Nr3)} (ring radix-3 twiddles)
+    int logNr3;                 // log2(Nr3 / 3)
     const T* Tb;                // L x Kp
     const T* Mk;                // (klow+1) x nt x lcorr
     const cx<T>* phase;         // Kp
@@ -576,6 +580,23 @@ __global__ __launch_bounds__(NT) void cols_fwd(Dev<T> d, const cx<T>* R, cx<T>* 
     cols_fwd_body<T>(d, blk_xcd(), R, E, ws_img);
 }
 
+// The ring transforms of nb images (ring l: N = 2^logN or 3 * 2^logN points),
+// as many sequences per lds_fft call as its register budget allows.
+template <typename T>
+__device__ __forceinline__ void ring_fft(const Dev<T>& d, int l, cx<T>* buf, int N, int logN, int nb, bool inverse)
+{
+    if (d.ringM3[l]) {
+        const int per_call = max(1, min(nb, ((FFT_REGS / 3) * 3 * NT) / N));
+        for (int i = 0; i < nb; i += per_call)
+            lds_fft3(buf + i * N, logN, min(per_call, nb - i), N, d.tw, d.logNmax, d.twr, inverse, d.fft_lr,
+                     d.tw_table, d.logNr3 - logN);
+    } else {
+        const int per_call = max(1, min(nb, FFT_BLOCK_POINTS >> logN));
+        for (int i = 0; i < nb; i += per_call)
+            lds_fft(buf + i * N, logN, min(per_call, nb - i), N, d.tw, d.logNmax, inverse, d.fft_lr, d.tw_table);
+    }
+}
+
 // One block per (ring, group of up to G images): the taps, weights and phase
 // of each half-ring sample are computed once and applied to every image of
 // the group (the transcendental work does not depend on the image).
@@ -608,14 +629,12 @@ __device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<
             }
             const cx<T> v = cmul(acc, tp.ph);
             cx<T>* bi = buf + i * N;
-            bi[s & (N - 1)] = v;
-            bi[(s + N / 2) & (N - 1)] = conjg(v);
+            bi[s < 0 ? s + N : s] = v;          // s in [-N/4, N/4)
+            bi[s + N / 2] = conjg(v);
         }
     }
     __syncthreads();
-    const int per_call = max(1, min(nb, FFT_BLOCK_POINTS >> logN));
-    for (int i = 0; i < nb; i += per_call)
-        lds_fft(buf + i * N, logN, min(per_call, nb - i), N, d.tw, d.logNmax, false, d.fft_lr, d.tw_table);
+    ring_fft(d, l, buf, N, logN, nb, false);
     const T invN = T(1) / T(N);
     for (int i = 0; i < nb; ++i) {
         const cx<T>* bi = buf + i * N;
@@ -1029,9 +1048,7 @@ __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<
         }
     }
     __syncthreads();
-    const int per_call = max(1, min(nb, FFT_BLOCK_POINTS >> logN));
-    for (int i = 0; i < nb; i += per_call)
-        lds_fft(buf + i * N, logN, min(per_call, nb - i), N, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
+    ring_fft(d, l, buf, N, logN, nb, true);
     const int off = d.ringOff[l];
     for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
         const int s = si - N / 4;
@@ -1042,7 +1059,7 @@ __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<
         for (int i = 0; i < nb; ++i) {
             // transpose of the conjugate-symmetric fill, then of the point phase
             const cx<T>* bi = buf + i * N;
-            dst[i] = cmul(bi[s & (N - 1)] + conjg(bi[(s + N / 2) & (N - 1)]), ph);
+            dst[i] = cmul(bi[s < 0 ? s + N : s] + conjg(bi[s + N / 2]), ph);
         }
     }
 }
@@ -1599,6 +1616,12 @@ int upload(pat_plan_s* p, Dev<T>& d)
     if ((rc = put(H.ringLog.data(), H.ringLog.size() * sizeof(int), (const void**)&d.ringLog))) return rc;
     if ((rc = put(H.ringOff.data(), H.ringOff.size() * sizeof(int), (const void**)&d.ringOff))) return rc;
     if ((rc = put(H.ringK.data(), H.ringK.size() * sizeof(int), (const void**)&d.ringK))) return rc;
+    if ((rc = put(H.ringM3.data(), H.ringM3.size() * sizeof(int), (const void**)&d.ringM3))) return rc;
+    {
+        std::vector<T> twr = conv(H.twr);
+        if ((rc = put(twr.data(), twr.size() * sizeof(T), (const void**)&d.twr))) return rc;
+        d.logNr3 = ilog2i(std::max(P.Nr3, 3) / 3);
+    }
     if ((rc = put(Tb.data(), Tb.size() * sizeof(T), (const void**)&d.Tb))) return rc;
     if ((rc = put(Mk.data(), Mk.size() * sizeof(T), (const void**)&d.Mk))) return rc;
     if ((rc = put(ph.data(), ph.size() * sizeof(T), (const void**)&d.phase))) return rc;

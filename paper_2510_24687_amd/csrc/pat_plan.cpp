@@ -231,6 +231,7 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
     H.lam.resize(P.L);
     H.ringN.resize(P.L);
     H.ringLog.resize(P.L);
+    H.ringM3.resize(P.L);
     H.ringOff.resize(P.L);
     H.ringK.resize(P.L);
     int off = 0, K = 0, maxN = 0;
@@ -239,11 +240,17 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
         double x = lam * g.R;
         double kedge = x + cA * std::cbrt(x) + 4.0;
         double need = std::max({16.0, lam * (g.R + P.rmax) + mphi, 2.0 * kedge + 2.0});
-        int N = next_pow2((long)std::ceil(need));
+        // ring length: the smallest 2^a or 3 * 2^a (a >= 2) covering `need`
+        const long need_i = (long)std::ceil(need);
+        long N3 = 12;
+        while (N3 < need_i) N3 *= 2;
+        int N = (int)std::min<long>(next_pow2(need_i), N3);
         int Kl = std::min(N / 2 - 1, (int)std::ceil(kedge));
         H.lam[l] = lam;
         H.ringN[l] = N;
-        H.ringLog[l] = ilog2(N);
+        H.ringM3[l] = (N % 3 == 0) ? 1 : 0;
+        H.ringLog[l] = ilog2(H.ringM3[l] ? N / 3 : N);
+        if (H.ringM3[l]) P.Nr3 = std::max(P.Nr3, N);
         H.ringOff[l] = off;
         H.ringK[l] = Kl;
         off += N / 2;
@@ -362,6 +369,17 @@ int build_host_plan(const pat_geometry& g, pat_dtype dt, HostPlan& H, std::strin
         double a = -M_PI * j / P.mf;
         H.twm[2 * j] = std::cos(a);
         H.twm[2 * j + 1] = std::sin(a);
+    }
+
+    // ring-transform twiddles e^{-2 pi i j/(2 Nr3)} (radix-3 pass of 3 * 2^a rings)
+    {
+        const int Nr = std::max(P.Nr3, 3);
+        H.twr.resize(2 * 2 * (size_t)Nr);
+        for (int j = 0; j < 2 * Nr; ++j) {
+            double a = -M_PI * j / Nr;
+            H.twr[2 * j] = std::cos(a);
+            H.twr[2 * j + 1] = std::sin(a);
+        }
     }
 
     // cosine-transform twiddles e^{-2 pi i j/(2M)}

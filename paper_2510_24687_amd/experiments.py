@@ -33,9 +33,12 @@ from . import solvers as S
 
 SUPPORT_RADIUS = 0.98   # the disk D of Sec. 4.4
 
-# name -> (arc in degrees, support kind, relative noise, methods)
+# name -> (arc in degrees, support kind, relative noise, methods); "smooth" schemes
+# use ellipses with smoothed boundaries (boundary layer about EDGE wide)
+EDGE = 0.03
 SCHEMES = {
     "360, no noise": (360.0, "disk", 0.0, ("inverse",)),
+    "360, no noise, smooth edges": (360.0, "disk smooth", 0.0, ("inverse",)),
     "360, 30% noise": (360.0, "disk", 0.3, ("inverse", "tv")),
     "180 (partial), no noise": (180.0, "upper", 0.0, ("inverse", "nnls")),
     "180 (partial), 30% noise": (180.0, "upper", 0.3, ("nnls", "tv")),
@@ -61,14 +64,14 @@ def support(kind: str, n: int, device) -> torch.Tensor:
     xs = torch.tensor(PH.pixel_centres(n, 1.0), dtype=torch.float64, device=device)
     Y, X = torch.meshgrid(xs, xs, indexing="ij")
     m = (X * X + Y * Y) <= SUPPORT_RADIUS ** 2
-    if kind == "upper":
+    if kind.startswith("upper"):
         m &= Y > 0
     return m.to(torch.float32)
 
 
 def phantoms(seeds, n: int, kind: str, device) -> torch.Tensor:
     prm = np.stack([PH.ellipse_params(int(s)) for s in seeds])
-    f = PH.ellipse_images(prm, n, 1.0, device=device)
+    f = PH.ellipse_images(prm, n, 1.0, device=device, edge=EDGE if "smooth" in kind else 0.0)
     return f * support(kind, n, device)
 
 

@@ -82,12 +82,18 @@ def ellipse_phantom(n: int, seed: int, count: int = 10, support: float = 0.9,
     return np.clip(f, 0.0, 1.0)
 
 
-def ellipse_images(params: np.ndarray, n: int, a: float = 1.0, device="cuda"):
+def ellipse_images(params: np.ndarray, n: int, a: float = 1.0, device="cuda", edge: float = 0.0):
     """The same rasterisation as ellipse_phantom for a stack of parameter sets
     (N, count, 6), done with torch on ``device`` in float64 and returned as
     float32 (N, n, n).  Used to generate large training sets in device memory;
     pixels on an ellipse boundary may differ from the numpy version by the
-    last-bit differences of the two sine/cosine implementations."""
+    last-bit differences of the two sine/cosine implementations.
+
+    ``edge`` > 0 smooths the boundaries (the smoothed ellipses of the paper's
+    training data, Sec. 4.2.1): each ellipse contributes
+    val * (1 + tanh((1 - rho) sqrt(a1 a2) / edge)) / 2 with
+    rho = sqrt((u/a1)^2 + (v/a2)^2) its normalised radius, so the boundary
+    layer is about ``edge`` wide (in the units of a)."""
     import torch
     xs = torch.tensor(pixel_centres(n, a), dtype=torch.float64, device=device)
     Y, X = torch.meshgrid(xs, xs, indexing="ij")
@@ -98,7 +104,11 @@ def ellipse_images(params: np.ndarray, n: int, a: float = 1.0, device="cuda"):
         cr, sr = torch.cos(rot), torch.sin(rot)
         u = (X - cx) * cr + (Y - cy) * sr
         v = -(X - cx) * sr + (Y - cy) * cr
-        f += val * (((u / ax1) ** 2 + (v / ax2) ** 2) <= 1.0)
+        rho2 = (u / ax1) ** 2 + (v / ax2) ** 2
+        if edge > 0:
+            f += val * 0.5 * (1.0 + torch.tanh((1.0 - torch.sqrt(rho2)) * torch.sqrt(ax1 * ax2) / edge))
+        else:
+            f += val * (rho2 <= 1.0)
     return torch.clamp(f, 0.0, 1.0).to(torch.float32)
 
 

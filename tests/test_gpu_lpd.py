@@ -290,8 +290,12 @@ def test_lpd_loss_gradient_vs_oracle(K):
     ~1e-4 and the results agree to ~2e-5; every further iteration feeds the
     flipped values forward through a network of gain > 1, so at K = 3 the
     agreement is bounded by the size of the bf16 effect itself, which the
-    test measures as the distance to the unrounded FP64 network and requires
-    the GPU to be several times closer to the rounded oracle than that."""
+    test measures as the distance to the unrounded FP64 network: f_K must be
+    at least twice closer to the rounded oracle than that and the whole
+    gradient closer than that.  Per parameter block only a loose bound holds
+    (a few times the bf16 effect): small gradients such as the last layer's
+    bias are sums with cancellation, and which roundings flip moves with the
+    operators' last FP32 bits."""
     geom, plan, f_true, y, params, _ = _tiny_setup()
     s_A, s_U = 0.9, 1.7
     net = L.LPD(plan, 2, iters=K, params=params, s_A=s_A, s_U=s_U)
@@ -317,10 +321,17 @@ def test_lpd_loss_gradient_vs_oracle(K):
         for k in g_o:
             assert e_g[k] < 1e-4, k
     else:
-        assert e_f < 0.25 * e_fx
+        assert e_f < 0.5 * e_fx
         assert abs(net.loss() - loss_o) < 1e-2 * loss_o
+        # the whole gradient is closer to the rounded oracle than the bf16 effect;
+        # each parameter block within a few times it (catches wrong terms or signs,
+        # which give O(1) errors)
+        allg = np.concatenate([np.ravel(grads[k]) for k in g_o])
+        allo = np.concatenate([np.ravel(g_o[k]) for k in g_o])
+        allx = np.concatenate([np.ravel(g_x[k]) for k in g_o])
+        assert rel(allg, allo) < rel(allx, allo)
         for k in g_o:
-            assert e_g[k] < 0.5 * e_gx[k] or e_g[k] < 2e-3, k
+            assert e_g[k] < 3 * e_gx[k] or e_g[k] < 1e-2, k
 
 
 def test_lpd_graph_replay_equals_eager_training():
