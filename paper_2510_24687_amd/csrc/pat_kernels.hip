@@ -395,7 +395,8 @@ struct Dev {
     const cx<T>* twr;           // 2 Nr3: e^{-2 pi i j/(2 Nr3)} (ring radix-3 twiddles)
     int logNr3;                 // log2(Nr3 / 3)
     const T* Tb;                // L x Kp
-    const T* Mk;                // (klow+1) x nt x lcorr
+    const T* Mk;                // (klow+1) x nt x lcorr (forward: each t_j's row contiguous)
+    const T* MkT;               // (klow+1) x lcorr x nt, the same values (adjoint: t_j fastest)
     const cx<T>* phase;         // Kp
     const cx<T>* tw;            // Nmax
     const cx<T>* twd;           // 2M: e^{-2 pi i j/(2M)} (cosine-transform twiddles)
@@ -406,7 +407,7 @@ struct Dev {
     // approximate inverse (Sec. 3.3): its tables, and the per-call switches of
     // the adjoint kernels that it reuses
     const T* Tbi;               // L x Kp: Tb with J_k' for J_k
-    const T* Mki;               // (klow+1) x nt x lcorr: Mk with J_k' and sin
+    const T* MkiT;              // (klow+1) x lcorr x nt: MkT with J_k' and sin
     double R2;                  // R^2: the detector disk Omega
     int sine;                   // 1: the transform over t is the sine transform
     int ubp;                    // 1: rows_adj writes v everywhere plus the partial sums of v over
@@ -992,7 +993,8 @@ __global__ __launch_bounds__(NT) void synth_adj(Dev<T> d, const T* g, long gstri
     synth_adj_body<T>(d, blk_xcd(), g, gstride, G, ws_img);
 }
 
-// Ulow_hat[l][k] = conj(i^k) sum_j Mk[k][j][l] G_hat[j][k]; one block per ring l.
+// Ulow_hat[l][k] = conj(i^k) sum_j Mk[k][j][l] G_hat[j][k]; one block per ring l
+// (the transposed copy MkT, so that the block's threads read consecutive t_j).
 template <typename T>
 __device__ __forceinline__ void lowk_adj_body(const Dev<T>& d, Blk bk, const cx<T>* G, cx<T>* Ulow, size_t ws_img)
 {
@@ -1003,7 +1005,7 @@ __device__ __forceinline__ void lowk_adj_body(const Dev<T>& d, Blk bk, const cx<
     for (int k = 0; k <= d.klow; ++k) {
         cx<T> acc = {T(0), T(0)};
         for (int j = threadIdx.x; j < d.nt; j += blockDim.x)
-            acc = acc + Gb[(size_t)j * d.Kp + k] * d.Mk[((size_t)k * d.nt + j) * d.lcorr + l];
+            acc = acc + Gb[(size_t)j * d.Kp + k] * d.MkT[((size_t)k * d.lcorr + l) * d.nt + j];
         red[threadIdx.x] = acc;
         __syncthreads();
         for (int s = blockDim.x / 2; s > 0; s >>= 1) {
@@ -1624,6 +1626,19 @@ int upload(pat_plan_s* p, Dev<T>& d)
     }
     if ((rc = put(Tb.data(), Tb.size() * sizeof(T), (const void**)&d.Tb))) return rc;
     if ((rc = put(Mk.data(), Mk.size() * sizeof(T), (const void**)&d.Mk))) return rc;
+    // the low-k matrices of the adjoint direction with t_j fastest
+    auto transpose_lowk = [&](const std::vector<double>& src) {
+        std::vector<T> o(src.size());
+        for (int k = 0; k <= P.klow; ++k)
+            for (int j = 0; j < P.nt; ++j)
+                for (int l = 0; l < P.lcorr; ++l)
+                    o[((size_t)k * P.lcorr + l) * P.nt + j] = (T)src[((size_t)k * P.nt + j) * P.lcorr + l];
+        return o;
+    };
+    {
+        std::vector<T> MkT = transpose_lowk(H.Mk);
+        if ((rc = put(MkT.data(), MkT.size() * sizeof(T), (const void**)&d.MkT))) return rc;
+    }
     if ((rc = put(ph.data(), ph.size() * sizeof(T), (const void**)&d.phase))) return rc;
     if ((rc = put(tw.data(), tw.size() * sizeof(T), (const void**)&d.tw))) return rc;
     std::vector<T> twd = conv(H.twd);
@@ -1632,9 +1647,9 @@ int upload(pat_plan_s* p, Dev<T>& d)
     if ((rc = put(twm.data(), twm.size() * sizeof(T), (const void**)&d.twm))) return rc;
     std::vector<T> pos = conv(H.pos);
     if ((rc = put(pos.data(), pos.size() * sizeof(T), (const void**)&d.pos))) return rc;
-    std::vector<T> Tbi = conv(H.Tbi), Mki = conv(H.Mki);
+    std::vector<T> Tbi = conv(H.Tbi), MkiT = transpose_lowk(H.Mki);
     if ((rc = put(Tbi.data(), Tbi.size() * sizeof(T), (const void**)&d.Tbi))) return rc;
-    if ((rc = put(Mki.data(), Mki.size() * sizeof(T), (const void**)&d.Mki))) return rc;
+    if ((rc = put(MkiT.data(), MkiT.size() * sizeof(T), (const void**)&d.MkiT))) return rc;
     d.n = P.n; d.m = P.m; d.nt = P.nt; d.mf = P.mf; d.mf3 = P.mf3; d.logmf = ilog2i(P.mf3 ? P.mf / 3 : P.mf);
     d.Ng = P.Ng; d.logNg = ilog2i(P.Ng); d.w = P.w; d.hw = P.hw; d.Rw = P.Rw; d.Ew = P.Ew;
     d.M = P.M; d.m3 = P.m3; d.log2M = ilog2i(P.m3 ? P.M / 3 : P.M); d.L = P.L; d.K = P.K; d.Kp = P.Kp; d.klow = P.klow; d.lcorr = P.lcorr;
@@ -1819,7 +1834,7 @@ int run_inverse(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
 {
     Dev<T> di = d;
     di.Tb = d.Tbi;
-    di.Mk = d.Mki;
+    di.MkT = d.MkiT;
     di.sine = 1;
     di.ubp = 1;
     di.adj_scale = (T)p->H.P.inv_scale;
