@@ -1186,6 +1186,7 @@ __device__ __forceinline__ void spread_tiles_body(const Dev<T>& d, Blk bk, const
                                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                                 __builtin_amdgcn_wave_barrier();
                                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 4
                                 for (int j = 0; j < cnt; ++j) {
                                     const cx<T> q = st_pos[wave][j];
                                     const int gx0 = (int)ceil_t(q.x - hwf);
