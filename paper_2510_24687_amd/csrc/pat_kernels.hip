@@ -613,6 +613,7 @@ __device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<
     const int b0 = grp * G, nb = min(G, B - b0);
     const int N = d.ringN[l], logN = d.ringLog[l], Kl = d.ringK[l];
     const int mask = d.Ng - 1;
+#pragma unroll 2
     for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
         Taps<T, WMAX> tp;
         point_taps<T, WMAX>(d, d.ringOff[l] + si, tp);
