@@ -1,0 +1,149 @@
+"""Pins of the FP64 U-Net oracle (oracle/unet.py) against definitions,
+brute force, adjoint identities, finite differences and the parameter count
+the paper states (Sec. 4.2.1)."""
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+import oracle.unet as U
+
+
+def test_parameter_count_matches_the_paper():
+    # Sec. 4.2.1: the full reconstruction operator (dual network with inputs
+    # q, A f, y and primal network with f, A* q) has around 3.9e6 parameters
+    total = U.count_params(3) + U.count_params(2)
+    assert 3.8e6 <= total <= 4.0e6, total
+    assert dict(U.layout(3))["e3c2.w"] == (256, 256, 3, 3)     # 256 filters at the coarsest scale
+
+
+def test_transposed_convolution_matches_its_definition():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((2, 3, 2, 3))
+    w = rng.standard_normal((3, 4, 2, 2))
+    out = np.zeros((2, 4, 4, 6))
+    for b in range(2):
+        for o in range(4):
+            for y in range(2):
+                for xx in range(3):
+                    for i in range(2):
+                        for j in range(2):
+                            out[b, o, 2 * y + i, 2 * xx + j] = sum(x[b, c, y, xx] * w[c, o, i, j] for c in range(3))
+    got = U.tconv2(torch.tensor(x), torch.tensor(w), rounding=False).numpy()
+    assert np.max(np.abs(got - out)) < 1e-13
+
+
+def test_transposed_convolution_backward_is_its_adjoint_and_gradient():
+    rng = np.random.default_rng(1)
+    x = torch.tensor(rng.standard_normal((2, 4, 3, 5)), requires_grad=True)
+    w = torch.tensor(rng.standard_normal((4, 3, 2, 2)), requires_grad=True)
+    y = torch.tensor(rng.standard_normal((2, 3, 6, 10)))
+    out = U.tconv2(x, w, rounding=False)
+    # <T x, y> = <x, S y> with S the stride-2 2x2 correlation (its adjoint)
+    lhs = float((out * y).sum())
+    rhs = float((x * F.conv2d(y, w, stride=2)).sum())
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    assert torch.autograd.gradcheck(lambda a, b: U.tconv2(a, b, rounding=False), (x, w))
+
+
+def test_max_pooling_brute_force_and_first_maximum_routing():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((1, 2, 4, 6))
+    x[0, 0, 0:2, 0:2] = [[1.0, 1.0], [1.0, 0.5]]          # a tie: (0,0) wins
+    x[0, 1, 2:4, 4:6] = [[0.0, 2.0], [2.0, 2.0]]          # a tie: (0,1) wins
+    xt = torch.tensor(x, requires_grad=True)
+    out = U.maxpool2(xt)
+    ref = np.zeros((1, 2, 2, 3))
+    for c in range(2):
+        for y in range(2):
+            for xx in range(3):
+                ref[0, c, y, xx] = max(x[0, c, 2 * y + i, 2 * xx + j] for i in range(2) for j in range(2))
+    assert np.array_equal(out.detach().numpy(), ref)
+    out.sum().backward()
+    g = xt.grad.numpy()
+    assert g[0, 0, 0, 0] == 1 and g[0, 0, 0, 1] == 0 and g[0, 0, 1, 0] == 0
+    assert g[0, 1, 2, 5] == 1 and g[0, 1, 3, 4] == 0 and g[0, 1, 3, 5] == 0
+    assert g.sum() == 12                                   # one routed unit per window
+
+
+def test_batch_norm_statistics_and_running_averages():
+    rng = np.random.default_rng(3)
+    z = torch.tensor(rng.standard_normal((3, 4, 5, 6)) * 2.0 + 1.5)
+    gamma = torch.ones(4, dtype=torch.float64)
+    beta = torch.full((4,), 50.0, dtype=torch.float64)       # ReLU inactive
+    run = {"mean": torch.zeros(4, dtype=torch.float64), "var": torch.ones(4, dtype=torch.float64)}
+    y = U.batch_norm_relu(z, gamma, beta, run, training=True) - 50.0
+    m = y.mean(dim=(0, 2, 3))
+    v = (y ** 2).mean(dim=(0, 2, 3))
+    var = z.var(dim=(0, 2, 3), unbiased=False)
+    assert torch.max(torch.abs(m)) < 1e-12
+    assert torch.max(torch.abs(v - var / (var + U.BN_EPS))) < 1e-12
+    # running averages as torch's own batch_norm keeps them
+    rm, rv = torch.zeros(4, dtype=torch.float64), torch.ones(4, dtype=torch.float64)
+    F.batch_norm(z, rm, rv, training=True, momentum=U.BN_MOMENTUM, eps=U.BN_EPS)
+    assert torch.max(torch.abs(run["mean"] - rm)) < 1e-14
+    assert torch.max(torch.abs(run["var"] - rv)) < 1e-14
+    # inference with the running averages
+    ye = U.batch_norm_relu(z, gamma, beta, run, training=False) - 50.0
+    ref = (z - rm.view(1, -1, 1, 1)) / torch.sqrt(rv.view(1, -1, 1, 1) + U.BN_EPS)
+    assert torch.max(torch.abs(ye - ref)) < 1e-12
+
+
+def _small_params(cin, seed):
+    rng = np.random.default_rng(seed)
+    P = {}
+    for name, shape in U.layout(cin):
+        kind = name.split(".")[1]
+        if kind == "w":
+            fan = shape[1] * shape[2] * shape[3] if not name.startswith("u") else shape[0]
+            v = rng.uniform(-1, 1, shape) * np.sqrt(3.0 / fan)
+        elif kind == "g":
+            v = 1.0 + 0.1 * rng.standard_normal(shape)
+        else:
+            v = 0.1 * rng.standard_normal(shape)
+        P["n." + name] = torch.tensor(v, requires_grad=True)
+    return P
+
+
+def test_unet_gradient_against_finite_differences():
+    """Directional derivative of <unet(x), r> along random directions in
+    parameter and input space against a central difference (FP64, batch
+    statistics).  Catches a wrong backward anywhere in the network.  The step
+    is small (1e-8) so that no ReLU or max-pooling switch lies inside it: at
+    1e-6 a few of the ~1e5 kinks are crossed and the difference quotient is
+    off by up to 0.5 %."""
+    torch.manual_seed(0)
+    P = _small_params(2, 4)
+    rng = np.random.default_rng(5)
+    x = torch.tensor(rng.standard_normal((2, 2, 8, 16)), requires_grad=True)
+    r = torch.tensor(rng.standard_normal((2, 1, 8, 16)))
+
+    def loss(Pd, xd):
+        return (U.unet(xd, Pd, "n.", None, training=True, rounding=False) * r).sum()
+
+    L = loss(P, x)
+    L.backward()
+    for trial in range(3):
+        d = {k: torch.tensor(rng.standard_normal(v.shape)) for k, v in P.items()}
+        dx = torch.tensor(rng.standard_normal(x.shape))
+        ana = sum(float((P[k].grad * d[k]).sum()) for k in P) + float((x.grad * dx).sum())
+        eps = 1e-8
+        with torch.no_grad():
+            Pp = {k: P[k] + eps * d[k] for k in P}
+            Pm = {k: P[k] - eps * d[k] for k in P}
+            num = (float(loss(Pp, x + eps * dx)) - float(loss(Pm, x - eps * dx))) / (2 * eps)
+        assert abs(ana - num) <= 1e-7 * abs(num) + 1e-4, (trial, ana, num)
+
+
+def test_unet_shapes_and_inference_mode():
+    P = _small_params(3, 6)
+    x = torch.tensor(np.random.default_rng(7).standard_normal((2, 3, 16, 8)))
+    run = U.fresh_running()
+    run = {"n." + k: v for k, v in run.items()}
+    with torch.no_grad():
+        out = U.unet(x, P, "n.", run, training=True, rounding=True)
+        assert out.shape == (2, 1, 16, 8)
+        # every batch-normalised layer moved its running mean away from 0
+        assert all(float(torch.abs(v["mean"]).sum()) > 0 for v in run.values())
+        out_e = U.unet(x, P, "n.", run, training=False, rounding=True)
+    assert out_e.shape == out.shape and torch.isfinite(out_e).all()
