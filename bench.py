@@ -155,13 +155,14 @@ def solver_bench(iters: int = 200, count: int = 64, lam: float = 1e-3, noise: fl
 
 def lpd_bench(steps: int = 3000, n_train: int = 10000, n_test: int = 64, batch: int = 8, iters: int = 10,
               noise: float = 0.02, lam: float = 1e-3, tv_iters: int = 200, lr: float = 1e-3, save: str = "",
-              load: str = ""):
+              load: str = "", arch: str = "cnn"):
     """Learned primal-dual vs TV-LS time-to-PSNR: n = 256 images, m = 256
     detectors on the top 180-degree arc, nt = 512, 2% noise.  Trains the
     10-iteration LPD (batch 8) on seeded random-ellipse phantoms whose data the
     GPU forward operator generates, then reconstructs 64 held-out phantoms
     with the trained network and with 200 graph-captured CP-TV iterations.
-    ``load``: weights written earlier with ``save`` (no training in this run)."""
+    ``load``: weights written earlier with ``save`` (no training in this run).
+    ``arch``: "cnn" (3-layer networks) or "unet" (the paper's U-Nets)."""
     import torch
     from paper_2510_24687_amd import lpd as L
     from paper_2510_24687_amd import pat, solvers
@@ -180,13 +181,16 @@ def lpd_bench(steps: int = 3000, n_train: int = 10000, n_test: int = 64, batch: 
     torch.cuda.synchronize()
     log("data", train=n_train, test=n_test)
     s_A, s_U = L.input_scales(plan, train)
-    net = L.LPD(plan, batch, iters, s_A=s_A, s_U=s_U, seed=0)
-    untrained = L.evaluate(net, test)
+    net = L.LPD(plan, batch, iters, s_A=s_A, s_U=s_U, seed=0, arch=arch)
+    stats = None if net.stats is None else net.stats.cpu().numpy()
+    untrained = L.evaluate(L.LPD(plan, batch, iters, params=net.params.cpu().numpy(), stats=stats, train=False,
+                                 s_A=s_A, s_U=s_U, arch=arch) if arch == "unet" else net, test)
     if load:
         z = np.load(load)
         if json.loads(str(z["geometry"])) != geom:
             raise ValueError("%s holds weights for another geometry" % load)
         params, s_A, s_U, steps = z["params"], float(z["s_A"]), float(z["s_U"]), int(z["steps"])
+        stats = z["stats"] if "stats" in z.files else None
         training = {"loaded": os.path.basename(load), "steps": steps, "batch": batch, "phantoms": n_train}
     else:
         t0 = time.time()
@@ -195,14 +199,16 @@ def lpd_bench(steps: int = 3000, n_train: int = 10000, n_test: int = 64, batch: 
         torch.cuda.synchronize()
         train_s = time.time() - t0
         params = net.params.cpu().numpy()
+        stats = None if net.stats is None else net.stats.cpu().numpy()
         training = {"steps": steps, "batch": batch, "phantoms": n_train, "seconds": train_s,
                     "steps_per_s": steps / train_s, "images_per_s": steps * batch / train_s,
                     "operator_evaluations_per_step": 4 * iters, "loss_history": hist[-10:], "lr": lr}
     if save:
-        np.savez(save, params=params, s_A=s_A, s_U=s_U, geometry=json.dumps(geom), steps=steps)
+        extra = {} if stats is None else {"stats": stats}
+        np.savez(save, params=params, s_A=s_A, s_U=s_U, geometry=json.dumps(geom), steps=steps, arch=arch, **extra)
     del net
     torch.cuda.empty_cache()
-    inf = L.LPD(plan, batch, iters, params=params, train=False, s_A=s_A, s_U=s_U)
+    inf = L.LPD(plan, batch, iters, params=params, stats=stats, train=False, s_A=s_A, s_U=s_U, arch=arch)
     inf.capture_forward()
     nb = n_test // batch
     for _ in range(2):
@@ -252,7 +258,7 @@ def lpd_bench(steps: int = 3000, n_train: int = 10000, n_test: int = 64, batch: 
     tv = out_tv["%g" % lam]
     res = {
         "workload": "n=256, m=256 on the top 180-degree arc, nt=512, 2%% noise; %d test phantoms (seeds 1e6..), "
-                    "LPD batch %d, K=%d" % (n_test, batch, iters),
+                    "LPD batch %d, K=%d, %s networks (%d parameters)" % (n_test, batch, iters, arch, params.size),
         "psnr_lpd": psnr_lpd, "psnr_tv200": tv["psnr_200"], "t_lpd_s": t_lpd,
         "t_tv_s": tv["time_to_own_200_psnr_s"],
         "pass": bool(psnr_lpd >= tv["psnr_200"] and t_lpd < tv["time_to_own_200_psnr_s"]),
@@ -315,6 +321,8 @@ def main():
     ap.add_argument("--lpd-lr", type=float, default=1e-3)
     ap.add_argument("--lpd-save", default="", help="write the trained weights (npz) here")
     ap.add_argument("--lpd-load", default="", help="evaluate weights written by --lpd-save (no training)")
+    ap.add_argument("--lpd-arch", default="cnn", choices=["cnn", "unet"],
+                    help="networks of the learned primal-dual: 3-layer CNNs or the paper's U-Nets")
     ap.add_argument("--suite", action="store_true",
                     help="Table-1-style experiments: inverse / NNLS / TV / LPD on 360, 180 and 120 degree schemes")
     ap.add_argument("--suite-tests", type=int, default=4)
@@ -348,7 +356,8 @@ def main():
         return
     if args.lpd:
         print(json.dumps({"lpd": lpd_bench(steps=args.lpd_steps, n_train=args.lpd_train, lr=args.lpd_lr,
-                                           save=args.lpd_save, load=args.lpd_load)}), flush=True)
+                                           save=args.lpd_save, load=args.lpd_load, arch=args.lpd_arch)}),
+              flush=True)
         return
 
     import torch

@@ -383,6 +383,129 @@ int pat_plane_sum(long count, const void* g, void* partials, int nblocks, void* 
 int pat_adam(long count, void* param, const void* grad, void* m, void* v, void* step, double lr, double lr_min,
              int total_steps, double beta1, double beta2, double eps, double clip, void* scratch, void* stream);
 
+/* ---- U-Net networks of the learned primal-dual reconstructor (Sec. 4.2.1:
+ * four scales, three window-2 down- and up-sampling steps, two 3x3
+ * convolutions each followed by batch normalisation and ReLU per scale, 32
+ * filters at the first scale doubled at every down-sampling) ---------------
+ * Layouts: activations are NHWC bfloat16 (B x H x W x C, channel fastest),
+ * convolution outputs and activation gradients NHWC FP32.  Every product runs
+ * on the matrix cores with bf16 operands and FP32 accumulation; every sum
+ * (statistics, weight gradients) is deterministic.  Pointers are device
+ * pointers owned by the caller; calls are asynchronous on `stream` and
+ * capturable.  Errors: PAT_EINVAL for null or inconsistent arguments,
+ * PAT_EUNSUPPORTED for channel counts the kernels do not take, PAT_EHIP on
+ * a launch failure. */
+
+/* A generic convolution as an implicit GEMM.  GEMM rows are the pixels
+ * (b, y, x) of the iteration grid B x H x W.  Tap t (of ntaps) reads the
+ * source pixel (in_stride y + dy[t], in_stride x + dx[t]) of the Hs x Ws
+ * source grid (zero outside it); the reduction index is k = t cin + c over
+ * the concatenated channels [src[0] (csrc[0]) | src[1] (csrc[1])], cin =
+ * csrc[0] + csrc[1].  The row's cout results go to destination pixel
+ * (out_stride y + oy, out_stride x + ox) of the Ho x Wo grid: channels
+ * [0, cdst[0]) to dst[0] (pitch cdst[0]), the rest to dst[1] (pitch cdst[1]),
+ * each either bf16 (dst_bf16) or FP32 (overwritten or, with accumulate,
+ * added to).  Examples: a 3x3 convolution (zero padding 1) has taps
+ * (t/3 - 1, t%3 - 1); its input gradient is the same with transposed,
+ * flipped weights; the 2x2 stride-2 transposed convolution is one 1-tap GEMM
+ * per output parity (out_stride 2, offset (i, j)); its input gradient has the
+ * 4 taps (i, j) read at in_stride 2.  csrc[] and cout must be multiples of 16. */
+typedef struct {
+    int B, H, W;                 /* iteration grid                           */
+    const void* src[2];          /* NHWC bf16 sources (src[1] may be NULL)   */
+    int csrc[2];                 /* their channel counts (csrc[1] may be 0)  */
+    int Hs, Ws, in_stride;       /* source grid and stride                   */
+    int ntaps;                   /* 1..9                                     */
+    int dy[9], dx[9];            /* tap offsets                              */
+    const void* weight;          /* pat_gconv_pack output for (cout, cin, ntaps) */
+    int cout;                    /* GEMM columns                             */
+    void* dst[2];                /* destinations                              */
+    int cdst[2];                 /* channel split: cdst[0] + cdst[1] = cout   */
+    int dst_bf16[2];             /* 1: store bf16, 0: FP32                    */
+    int accumulate[2];           /* FP32 destinations: add instead of store   */
+    int Ho, Wo;                  /* destination grid                          */
+    int out_stride, oy, ox;      /* destination mapping                       */
+} pat_gconv_desc;
+
+/* bf16 elements of a packed weight array: cout * ntaps * cip (cout, cip
+ * multiples of 16, ntaps 1..9), or -1. */
+long pat_gconv_packed_size(int cout, int cip, int ntaps);
+
+/* Pack FP32 weights to the layout pat_gconv reads: the effective weight of
+ * output column co < co_e, input channel ci < ci_e and tap t is
+ * w[off + co s_co + ci s_ci + t' s_t] with t' = flip ? ntaps - 1 - t : t;
+ * columns co_e..cout-1 and channels ci_e..cip-1 are zero (padding). */
+int pat_gconv_pack(const void* w, int co_e, int ci_e, int cout, int cip, int ntaps, long off, long s_co, long s_ci,
+                   long s_t, int flip, void* dst, void* stream);
+
+/* The convolution d (see pat_gconv_desc). */
+int pat_gconv(const pat_gconv_desc* d, void* stream);
+
+/* FP32 scratch floats pat_gconv_wgrad needs with `chunks` row chunks. */
+long pat_gconv_wgrad_partials(const pat_gconv_desc* d, int chunks);
+
+/* Weight gradient of the convolution d: for every column co and reduction
+ * index k = t cin + ci, sum over the rows of grad[dest(row)][co] *
+ * src[source(row, t)][ci] (grad: NHWC bf16 with pitch cout on d's
+ * destination grid; d's dst fields are ignored), accumulated on the matrix
+ * cores per chunk of rows, then over the chunks in FP64 in a fixed order;
+ * written (accumulate = 0) or added to dw[off + co s_co + ci s_ci + t s_t]
+ * for ci < ci_real. */
+int pat_gconv_wgrad(const pat_gconv_desc* d, const void* grad, int chunks, void* partials, void* dw, int ci_real,
+                    long off, long s_co, long s_ci, long s_t, int accumulate, void* stream);
+
+/* Scratch (doubles) of the batch-normalisation calls for rows x channels
+ * (channels must divide 256), or -1. */
+long pat_bn_partials(long rows, int channels);
+
+/* Batch normalisation and ReLU of z (rows x channels, NHWC FP32): training =
+ * 1 takes the batch mean and biased variance over the rows (FP64 sums) into
+ * mean / invstd = 1 / sqrt(var + eps) and, if running_mean is not NULL,
+ * updates running_mean += momentum (mean - running_mean), running_var +=
+ * momentum (var rows / (rows - 1) - running_var); training = 0 uses the
+ * running statistics.  out = bf16(max(0, gamma (z - mean) invstd + beta)). */
+int pat_bn_forward(long rows, int channels, const void* z, const void* gamma, const void* beta, void* mean,
+                   void* invstd, void* running_mean, void* running_var, double momentum, double eps, int training,
+                   void* out, void* partials, void* stream);
+
+/* Backward of pat_bn_forward (training mode) given grad_act = d loss / d out
+ * (FP32 NHWC): gy = grad_act [gamma xhat + beta > 0], xhat = (z - mean)
+ * invstd; dbeta (+)= sum gy, dgamma (+)= sum gy xhat; grad_z = bf16(gamma
+ * invstd (gy - mean(gy) - xhat mean(gy xhat))). */
+int pat_bn_backward(long rows, int channels, const void* z, const void* grad_act, const void* gamma, const void* beta,
+                    const void* mean, const void* invstd, void* grad_z, void* dgamma, void* dbeta, int accumulate,
+                    void* partials, void* stream);
+
+/* 2x2 max pooling of NHWC bf16 (H, W even); the first maximum in the order
+ * (0,0), (0,1), (1,0), (1,1) is taken.  The backward adds grad_out (FP32,
+ * H/2 x W/2) to grad_in (FP32, H x W) at each window's maximum. */
+int pat_maxpool2(int B, int H, int W, int C, const void* in, void* out, void* stream);
+int pat_maxpool2_backward(int B, int H, int W, int C, const void* in, const void* grad_out, void* grad_in, void* stream);
+
+/* Network inputs: out[p][c] = bf16(scales[c] planes[c][p]) for c < cin (1..4),
+ * zero for cin <= c < cpad.  The backward writes grad_planes[c][p] =
+ * residual[c][p] + scales[c] grad[p][c] (grad: FP32 NHWC with pitch cpad;
+ * NULL entries of grad_planes are skipped, NULL residual entries add 0);
+ * scales is a host array. */
+int pat_nhwc_pack(long pixels, int cin, int cpad, const void* const* planes, const float* scales, void* out,
+                  void* stream);
+int pat_nhwc_unpack_grad(long pixels, int cin, int cpad, const void* grad, const float* scales, void* const* grad_planes,
+                         const void* const* residual, void* stream);
+
+/* 1x1 output layer: out[p] = residual[p] + b[0] + sum_c w[c] act[p][c]
+ * (act NHWC bf16 with C channels; b, residual may be NULL). */
+int pat_head_forward(long pixels, int C, const void* act, const void* w, const void* b, const void* residual,
+                     void* out, void* stream);
+
+/* Scratch (doubles) of pat_head_backward, or -1 (C must divide 256). */
+long pat_head_partials(long pixels, int C);
+
+/* Backward of the head: grad_act[p][c] = w[c] grad_out[p] (FP32 NHWC);
+ * grad_wb[c] (+)= sum_p grad_out[p] act[p][c] for c < C and grad_wb[C] (+)=
+ * sum_p grad_out[p] (the bias), FP64 sums in a fixed order. */
+int pat_head_backward(long pixels, int C, const void* act, const void* w, const void* grad_out, void* grad_act,
+                      void* grad_wb, int accumulate, void* partials, void* stream);
+
 /* ||A|| (operator norm from the X to the Y inner products of
  * eqn:innerProducts) by power iteration on A*A: `iters` steps from a fixed
  * pseudo-random start, the Rayleigh quotient <f, A*A f>_X / <f, f>_X of the

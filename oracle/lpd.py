@@ -111,10 +111,21 @@ def block(x, P, net, rounding=True):
     return conv3x3(h, P[net + ".w3"], P[net + ".b3"], rounding)
 
 
-def reconstruct(geom, P, y, iters, s_A=1.0, s_U=1.0, rounding=True, ops=None):
+def _network(x, P, net, rounding, arch, running, training):
+    if arch == "unet":
+        from .unet import unet
+        return unet(x, P, net + ".", running, training, rounding)
+    return block(x, P, net, rounding)
+
+
+def reconstruct(geom, P, y, iters, s_A=1.0, s_U=1.0, rounding=True, ops=None, arch="cnn", running=None,
+                training=True):
     """f_K for data y (B, nt, m).  ``ops`` = (A, A*) callables on batches may
     replace the direct-quadrature operators (used by gradcheck on tiny
-    explicit matrices)."""
+    explicit matrices).  ``arch = "unet"``: the U-Nets of oracle/unet.py with
+    running statistics ``running`` (keys "dual.<layer>", "primal.<layer>";
+    batch statistics and updated averages in training, the averages
+    otherwise)."""
     A, As = ops if ops is not None else ((lambda f: _A.apply(f, geom)), (lambda g: _Astar.apply(g, geom)))
     B = y.shape[0]
     n = geom["n"]
@@ -122,18 +133,19 @@ def reconstruct(geom, P, y, iters, s_A=1.0, s_U=1.0, rounding=True, ops=None):
     f = torch.zeros((B, n, n), dtype=torch.float64)
     for _ in range(iters):
         Af = A(f)
-        q = q + block(torch.stack([q, s_A * Af, s_A * y], dim=1), P, "dual", rounding)[:, 0]
+        q = q + _network(torch.stack([q, s_A * Af, s_A * y], dim=1), P, "dual", rounding, arch, running,
+                         training)[:, 0]
         u = As(q)
-        f = f + block(torch.stack([f, s_U * u], dim=1), P, "primal", rounding)[:, 0]
+        f = f + _network(torch.stack([f, s_U * u], dim=1), P, "primal", rounding, arch, running, training)[:, 0]
     return f
 
 
-def loss_and_grads(geom, P, y, target, iters, s_A=1.0, s_U=1.0, rounding=True):
+def loss_and_grads(geom, P, y, target, iters, s_A=1.0, s_U=1.0, rounding=True, arch="cnn", running=None):
     """mean((f_K - target)^2) and its gradient with respect to every parameter."""
     Pt = {k: torch.tensor(np.asarray(v, dtype=np.float64), requires_grad=True) for k, v in P.items()}
     yt = torch.tensor(np.asarray(y, dtype=np.float64))
     tt = torch.tensor(np.asarray(target, dtype=np.float64))
-    fK = reconstruct(geom, Pt, yt, iters, s_A, s_U, rounding)
+    fK = reconstruct(geom, Pt, yt, iters, s_A, s_U, rounding, arch=arch, running=running)
     loss = torch.mean((fK - tt) ** 2)
     loss.backward()
     return float(loss.detach()), fK.detach().numpy(), {k: v.grad.numpy() for k, v in Pt.items()}

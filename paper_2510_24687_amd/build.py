@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpat.so")
 SOURCES = [os.path.join(CSRC, "pat_kernels.hip"), os.path.join(CSRC, "pat_solvers.hip"),
-           os.path.join(CSRC, "pat_lpd.hip"),
+           os.path.join(CSRC, "pat_lpd.hip"), os.path.join(CSRC, "pat_unet.hip"),
            os.path.join(CSRC, "pat_plan.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

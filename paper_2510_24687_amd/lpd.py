@@ -41,10 +41,17 @@ def _p(t: Optional[torch.Tensor]):
     return None if t is None else t.data_ptr()
 
 
-def param_layout(dual_in: int = 3, primal_in: int = 2) -> List[Tuple[str, tuple]]:
-    """Names and shapes of the flat parameter vector, in storage order.  Each
-    layer's bias is followed by its PReLU slopes (the PReLU backward writes
-    both gradients as one 64-float block)."""
+def param_layout(dual_in: int = 3, primal_in: int = 2, arch: str = "cnn") -> List[Tuple[str, tuple]]:
+    """Names and shapes of the flat parameter vector, in storage order.  For
+    the 3-layer CNN each layer's bias is followed by its PReLU slopes (the
+    PReLU backward writes both gradients as one 64-float block); ``arch =
+    "unet"`` gives the U-Net layout of unet.layout per network."""
+    if arch == "unet":
+        from . import unet as U
+        return [(net + "." + name, shape) for net, cin in (("dual", dual_in), ("primal", primal_in))
+                for name, shape in U.layout(cin)]
+    if arch != "cnn":
+        raise ValueError("arch must be 'cnn' or 'unet'")
     out = []
     for net, cin in (("dual", dual_in), ("primal", primal_in)):
         out += [(net + ".w1", (HID, cin, 3, 3)), (net + ".b1", (HID,)), (net + ".a1", (HID,)),
@@ -53,12 +60,17 @@ def param_layout(dual_in: int = 3, primal_in: int = 2) -> List[Tuple[str, tuple]
     return out
 
 
-def init_params(seed: int, dual_in: int = 3, primal_in: int = 2) -> np.ndarray:
+def init_params(seed: int, dual_in: int = 3, primal_in: int = 2, arch: str = "cnn") -> np.ndarray:
     """Seeded initial weights: He-uniform for the hidden layers, PReLU slopes
     0.25, zero biases, and a last layer scaled down so that the untrained
-    network starts close to the identity update."""
+    network starts close to the identity update (U-Net: unet.init_values)."""
     rng = np.random.default_rng(seed)
     parts = []
+    if arch == "unet":
+        from . import unet as U
+        for name, shape in param_layout(dual_in, primal_in, arch):
+            parts.append(U.init_values(name, shape, rng))
+        return np.concatenate(parts).astype(np.float32)
     for name, shape in param_layout(dual_in, primal_in):
         size = int(np.prod(shape))
         kind = name.split(".")[1]
@@ -73,10 +85,10 @@ def init_params(seed: int, dual_in: int = 3, primal_in: int = 2) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def unpack(flat, dual_in: int = 3, primal_in: int = 2) -> Dict[str, np.ndarray]:
+def unpack(flat, dual_in: int = 3, primal_in: int = 2, arch: str = "cnn") -> Dict[str, np.ndarray]:
     out, o = {}, 0
     flat = np.asarray(flat)
-    for name, shape in param_layout(dual_in, primal_in):
+    for name, shape in param_layout(dual_in, primal_in, arch):
         size = int(np.prod(shape))
         out[name] = flat[o:o + size].reshape(shape)
         o += size
@@ -213,11 +225,13 @@ class LPD:
 
     ``plan``: an FP32 Plan (max_batch >= batch).  ``params``: flat FP32
     initial weights (init_params).  ``train``: keep the activations of all K
-    iterations and allocate gradients / Adam state.
+    iterations and allocate gradients / Adam state.  ``arch``: "cnn" (3-layer
+    CNNs) or "unet" (the paper's U-Nets, unet.UNetBlock, with batch
+    normalisation; ``stats``: flat running statistics, unet.init_stats).
     """
 
     def __init__(self, plan: Plan, batch: int, iters: int = 10, params=None, seed: int = 0, train: bool = True,
-                 s_A: float = 1.0, s_U: float = 1.0):
+                 s_A: float = 1.0, s_U: float = 1.0, arch: str = "cnn", stats=None):
         if plan.dtype != torch.float32:
             raise TypeError("the learned reconstructor runs on an FP32 plan")
         if batch > plan.max_batch:
@@ -226,13 +240,15 @@ class LPD:
         self.plan, self.B, self.K, self.train_mode = plan, batch, iters, train
         dev = plan.device
         self.dev = dev
-        self.layout = param_layout()
+        self.arch = arch
+        self.layout = param_layout(arch=arch)
+        self.shapes = dict(self.layout)
         self.offs, o = {}, 0
         for name, shape in self.layout:
             self.offs[name] = o
             o += int(np.prod(shape))
         self.nparams = o
-        p0 = init_params(seed) if params is None else np.asarray(params, dtype=np.float32)
+        p0 = init_params(seed, arch=arch) if params is None else np.asarray(params, dtype=np.float32)
         if p0.size != o:
             raise ValueError("expected %d parameters" % o)
         self.params = torch.tensor(p0, device=dev)
@@ -246,8 +262,25 @@ class LPD:
         self.f = z(K + 1, B, n, n)
         self.Af = z(K, B, nt, m)
         self.u = z(K, B, n, n)
-        self.dual = _Block(self.lib, self.params, self.grads, self.offs, "dual", 3, B, nt, m, K, dev, train)
-        self.primal = _Block(self.lib, self.params, self.grads, self.offs, "primal", 2, B, n, n, K, dev, train)
+        if arch == "unet":
+            from . import unet as U
+            slay = U.stats_layout()
+            self.soffs, so = {}, 0
+            for name, c in slay:
+                self.soffs[name] = so
+                so += c
+            st0 = U.init_stats() if stats is None else np.asarray(stats, dtype=np.float32)
+            if st0.size != so:
+                raise ValueError("expected %d running statistics" % so)
+            self.stats = torch.tensor(st0, device=dev)
+            mk = lambda net, cin, H, W: U.UNetBlock(self.lib, self.params, self.grads, self.offs, self.shapes,
+                                                    self.stats, self.soffs, net, cin, B, H, W, K, dev, train)
+            self.dual = mk("dual", 3, nt, m)
+            self.primal = mk("primal", 2, n, n)
+        else:
+            self.stats = None
+            self.dual = _Block(self.lib, self.params, self.grads, self.offs, "dual", 3, B, nt, m, K, dev, train)
+            self.primal = _Block(self.lib, self.params, self.grads, self.offs, "primal", 2, B, n, n, K, dev, train)
         if train:
             self.dq = z(B, nt, m)
             self.dq2 = z(B, nt, m)
@@ -357,11 +390,14 @@ class LPD:
 
     def capture_train(self):
         """Capture one training step.  The warm-up call performs a real step;
-        the optimiser state is reset afterwards so replays start from the
-        initial weights."""
+        the optimiser state (and the U-Net's running statistics) is reset
+        afterwards so replays start from the initial weights."""
         p0 = self.params.clone()
+        s0 = None if self.stats is None else self.stats.clone()
         self.graph_train = self._capture(self.train_step)
         self.params.copy_(p0)
+        if s0 is not None:
+            self.stats.copy_(s0)
         self.adam_m.zero_()
         self.adam_v.zero_()
         self.step_count.zero_()

@@ -49,7 +49,10 @@ EXPORTED = ["pat_plan_create", "pat_plan_query", "pat_plan_destroy", "pat_plan_g
             "pat_debug_bessel", "pat_axpby", "pat_conv_packed_size", "pat_conv_pack_weights", "pat_conv3x3",
             "pat_conv_wgrad_partials", "pat_conv3x3_wgrad", "pat_conv_bwd_partials", "pat_plane_sum", "pat_adam", "pat_opnorm_estimate",
             "pat_group_create", "pat_group_destroy", "pat_group_forward", "pat_group_adjoint",
-            "pat_filter_length", "pat_filter_create", "pat_filter_destroy", "pat_filter_apply"]
+            "pat_filter_length", "pat_filter_create", "pat_filter_destroy", "pat_filter_apply",
+            "pat_gconv_packed_size", "pat_gconv_pack", "pat_gconv", "pat_gconv_wgrad_partials", "pat_gconv_wgrad",
+            "pat_bn_partials", "pat_bn_forward", "pat_bn_backward", "pat_maxpool2", "pat_maxpool2_backward",
+            "pat_nhwc_pack", "pat_nhwc_unpack_grad", "pat_head_forward", "pat_head_partials", "pat_head_backward"]
 
 
 class ConvDesc(ctypes.Structure):
@@ -60,6 +63,18 @@ class ConvDesc(ctypes.Structure):
                 ("scale", ctypes.c_float * 4), ("weight", ctypes.c_void_p), ("bias", ctypes.c_void_p),
                 ("alpha", ctypes.c_void_p), ("pre", ctypes.c_void_p), ("bwd_pre", ctypes.c_void_p),
                 ("partials", ctypes.c_void_p), ("grad_bias_alpha", ctypes.c_void_p), ("accumulate", ctypes.c_int)]
+
+
+class GConvDesc(ctypes.Structure):
+    """pat_gconv_desc: one implicit-GEMM convolution between NHWC tensors."""
+    _fields_ = [("B", ctypes.c_int), ("H", ctypes.c_int), ("W", ctypes.c_int),
+                ("src", ctypes.c_void_p * 2), ("csrc", ctypes.c_int * 2),
+                ("Hs", ctypes.c_int), ("Ws", ctypes.c_int), ("in_stride", ctypes.c_int), ("ntaps", ctypes.c_int),
+                ("dy", ctypes.c_int * 9), ("dx", ctypes.c_int * 9), ("weight", ctypes.c_void_p),
+                ("cout", ctypes.c_int), ("dst", ctypes.c_void_p * 2), ("cdst", ctypes.c_int * 2),
+                ("dst_bf16", ctypes.c_int * 2), ("accumulate", ctypes.c_int * 2),
+                ("Ho", ctypes.c_int), ("Wo", ctypes.c_int), ("out_stride", ctypes.c_int), ("oy", ctypes.c_int),
+                ("ox", ctypes.c_int)]
 
 
 def load():
@@ -114,6 +129,27 @@ def load():
     ip, vpp = ctypes.POINTER(i), ctypes.POINTER(vp)
     lib.pat_group_forward.argtypes = [vp, ip, vpp, vpp, vpp, vp]
     lib.pat_group_adjoint.argtypes = [vp, ip, vpp, vpp, vpp, vp]
+    gd = ctypes.POINTER(GConvDesc)
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.pat_gconv_packed_size.argtypes = [i, i, i]
+    lib.pat_gconv_packed_size.restype = L
+    lib.pat_gconv_pack.argtypes = [vp, i, i, i, i, i, L, L, L, L, i, vp, vp]
+    lib.pat_gconv.argtypes = [gd, vp]
+    lib.pat_gconv_wgrad_partials.argtypes = [gd, i]
+    lib.pat_gconv_wgrad_partials.restype = L
+    lib.pat_gconv_wgrad.argtypes = [gd, vp, i, vp, vp, i, L, L, L, L, i, vp]
+    lib.pat_bn_partials.argtypes = [L, i]
+    lib.pat_bn_partials.restype = L
+    lib.pat_bn_forward.argtypes = [L, i, vp, vp, vp, vp, vp, vp, vp, D, D, i, vp, vp, vp]
+    lib.pat_bn_backward.argtypes = [L, i, vp, vp, vp, vp, vp, vp, vp, vp, vp, i, vp, vp]
+    lib.pat_maxpool2.argtypes = [i, i, i, i, vp, vp, vp]
+    lib.pat_maxpool2_backward.argtypes = [i, i, i, i, vp, vp, vp, vp]
+    lib.pat_nhwc_pack.argtypes = [L, i, i, vpp, fp, vp, vp]
+    lib.pat_nhwc_unpack_grad.argtypes = [L, i, i, vp, fp, vpp, vpp, vp]
+    lib.pat_head_forward.argtypes = [L, i, vp, vp, vp, vp, vp, vp]
+    lib.pat_head_partials.argtypes = [L, i]
+    lib.pat_head_partials.restype = L
+    lib.pat_head_backward.argtypes = [L, i, vp, vp, vp, vp, vp, i, vp, vp]
     _lib = lib
     return lib
 
