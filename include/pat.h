@@ -409,7 +409,9 @@ int pat_adam(long count, void* param, const void* grad, void* m, void* v, void* 
  * (t/3 - 1, t%3 - 1); its input gradient is the same with transposed,
  * flipped weights; the 2x2 stride-2 transposed convolution is one 1-tap GEMM
  * per output parity (out_stride 2, offset (i, j)); its input gradient has the
- * 4 taps (i, j) read at in_stride 2.  csrc[] and cout must be multiples of 16. */
+ * 4 taps (i, j) read at in_stride 2.  csrc[] and cout must be multiples of 16;
+ * when csrc[0] + csrc[1] is a multiple of 32 each csrc[] must be one too
+ * (the weights are then packed for the 32-deep matrix instruction). */
 typedef struct {
     int B, H, W;                 /* iteration grid                           */
     const void* src[2];          /* NHWC bf16 sources (src[1] may be NULL)   */

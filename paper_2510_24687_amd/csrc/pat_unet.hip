@@ -14,12 +14,14 @@
 // reduction index is k = tap * cin + channel, channels of a two-source input
 // are the concatenation [src0 | src1] (the skip connection, without a copy).
 //
-// Matrix core: v_mfma_f32_16x16x16_bf16, FP32 accumulation.  Wave operand
-// layout (lane l):
-//   A (16 x 16, rows i, reduction k): lane l holds A[l % 16][4 (l / 16) + e]
-//   B (16 x 16, reduction k, cols j): lane l holds B[4 (l / 16) + e][l % 16]
+// Matrix cores: v_mfma_f32_16x16x32_bf16 (gfx950) where every source has a
+// multiple of 32 channels, v_mfma_f32_16x16x16_bf16 otherwise (the 16-channel
+// padded network input); FP32 accumulation.  Wave operand layout (lane l,
+// KS = 32 or 16 reduction entries per instruction, V = KS / 4 per lane):
+//   A (16 x KS, rows i, reduction k): lane l holds A[l % 16][V (l / 16) + e]
+//   B (KS x 16, reduction k, cols j): lane l holds B[V (l / 16) + e][l % 16]
 //   D (16 x 16):                      lane l holds D[4 (l / 16) + r][l % 16]
-// Weights are packed so that one wave's B operand is 512 contiguous bytes.
+// Weights are packed so that one wave's B operand is 64 V contiguous bf16.
 //
 // Activations are NHWC bf16 (the MFMA operands), convolution outputs and
 // activation gradients NHWC FP32.  Batch-normalisation statistics, weight
@@ -34,6 +36,8 @@
 #include "pat_internal.h"
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
@@ -160,22 +164,117 @@ __global__ __launch_bounds__(NT) void gconv_kernel(GConv a)
     }
 }
 
-// Packed weights: entry ((ctile * KT + kt) * 64 + lane) * 4 + e holds the
-// effective weight W_e[co][k] with co = 16 ctile + lane % 16 and
-// k = 16 kt + 4 (lane / 16) + e, k = tap * cip + ci; W_e[co][ci][tap] =
-// w[off + co s_co + ci s_ci + tap' s_t] (tap' = ntaps - 1 - tap when
-// flipped), zero for co >= co_e or ci >= ci_e.
+// The same GEMM with 32 reduction entries per instruction (c0, c1 multiples
+// of 32): 16-byte operand loads, and the loads of step kt + 1 are issued
+// before the matrix instructions of step kt so that they overlap.
+template <int CTW>
+__global__ __launch_bounds__(NT) void gconv32_kernel(GConv a)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nct = a.cout / (16 * CTW);
+    const long gw = (long)blockIdx.x * 4 + wave;
+    const long R = (long)a.B * a.H * a.W;
+    const long rt = gw / nct;
+    const int ct = (int)(gw - rt * nct);
+    if (rt * 64 >= R) return;
+    const int cs32 = (a.c0 + a.c1) >> 5, KT = a.ntaps * cs32;
+    int by[4], bx[4], bb[4];
+    bool rv[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const long row = rt * 64 + g * 16 + (lane & 15);
+        rv[g] = row < R;
+        const long r = rv[g] ? row : 0;
+        bx[g] = (int)(r % a.W);
+        const long t = r / a.W;
+        by[g] = (int)(t % a.H);
+        bb[g] = (int)(t / a.H);
+    }
+    f32x4 acc[4][CTW];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int j = 0; j < CTW; ++j) acc[g][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kq = 8 * (lane >> 4);
+    const short* wbase = a.wp + (size_t)ct * CTW * KT * 512 + lane * 8;
+    s16x8 an[4], bn[CTW];
+    auto load = [&](int kt) {
+        const int t = kt / cs32, cs = kt - t * cs32;
+        const short* base;
+        int pitch;
+        if (cs * 32 < a.c0) {
+            base = a.src0 + cs * 32 + kq;
+            pitch = a.c0;
+        } else {
+            base = a.src1 + (cs * 32 - a.c0) + kq;
+            pitch = a.c1;
+        }
+        const int dy = a.dy[t], dx = a.dx[t];
+#pragma unroll
+        for (int j = 0; j < CTW; ++j) bn[j] = *reinterpret_cast<const s16x8*>(wbase + ((size_t)j * KT + kt) * 512);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int sy = a.istr * by[g] + dy, sx = a.istr * bx[g] + dx;
+            s16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (rv[g] && sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws)
+                v = *reinterpret_cast<const s16x8*>(base + (((size_t)bb[g] * a.Hs + sy) * a.Ws + sx) * pitch);
+            an[g] = v;
+        }
+    };
+    load(0);
+    for (int kt = 0; kt < KT; ++kt) {
+        s16x8 ac[4], bc[CTW];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) ac[g] = an[g];
+#pragma unroll
+        for (int j = 0; j < CTW; ++j) bc[j] = bn[j];
+        if (kt + 1 < KT) load(kt + 1);
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int j = 0; j < CTW; ++j)
+                acc[g][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ac[g]),
+                                                                     __builtin_bit_cast(bf16x8, bc[j]), acc[g][j], 0, 0,
+                                                                     0);
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long row = rt * 64 + g * 16 + 4 * (lane >> 4) + r;
+            if (row >= R) continue;
+            const int x = (int)(row % a.W);
+            const long tt = row / a.W;
+            const int y = (int)(tt % a.H), b = (int)(tt / a.H);
+            const size_t op = ((size_t)b * a.Ho + a.ostr * y + a.oy) * a.Wo + a.ostr * x + a.ox;
+#pragma unroll
+            for (int j = 0; j < CTW; ++j) {
+                const int co = (ct * CTW + j) * 16 + (lane & 15);
+                const float v = acc[g][j][r];
+                if (co < a.d0) store_out(a.dst0, op * a.d0 + co, v, a.bf0, a.acc0);
+                else store_out(a.dst1, op * a.d1 + (co - a.d0), v, a.bf1, a.acc1);
+            }
+        }
+    }
+}
+
+// Packed weights (V = 8 when cip is a multiple of 32, else 4; KS = 4 V):
+// entry ((ctile * KT + kt) * 64 + lane) * V + e holds the effective weight
+// W_e[co][k] with co = 16 ctile + lane % 16 and k = KS kt + V (lane / 16) + e,
+// k = tap * cip + ci; W_e[co][ci][tap] = w[off + co s_co + ci s_ci + tap' s_t]
+// (tap' = ntaps - 1 - tap when flipped), zero for co >= co_e or ci >= ci_e.
 __global__ __launch_bounds__(NT) void gconv_pack(const float* w, int co_e, int ci_e, int cip, int ntaps, long off,
                                                  long s_co, long s_ci, long s_t, int flip, long total, short* dst)
 {
     const long i = (long)blockIdx.x * NT + threadIdx.x;
     if (i >= total) return;
-    const int e = (int)(i & 3), lane = (int)((i >> 2) & 63);
-    const long rest = i >> 8;
-    const int KT = ntaps * cip / 16;
+    const int lv = cip % 32 == 0 ? 3 : 2, V = 1 << lv;        // bf16 per lane: 8 or 4
+    const int e = (int)(i & (V - 1)), lane = (int)((i >> lv) & 63);
+    const long rest = i >> (lv + 6);
+    const int KT = ntaps * cip / (4 * V);
     const int kt = (int)(rest % KT), ctile = (int)(rest / KT);
     const int co = ctile * 16 + (lane & 15);
-    const int k = kt * 16 + 4 * (lane >> 4) + e;
+    const int k = kt * 4 * V + V * (lane >> 4) + e;
     const int tap = k / cip, ci = k - tap * cip;
     float v = 0.f;
     if (co < co_e && ci < ci_e) v = w[off + co * s_co + ci * s_ci + (long)(flip ? ntaps - 1 - tap : tap) * s_t];
@@ -185,9 +284,10 @@ __global__ __launch_bounds__(NT) void gconv_pack(const float* w, int co_e, int c
 // Weight-gradient partials of one chunk of rows:
 //   part[chunk][co][k] = sum_rows g[out(row)][co] * src[in(row, tap(k))][ci(k)]
 // as an MFMA contraction (rows of A = output channels, columns of B = k,
-// reduction over the chunk's rows).  A block computes a 64 x 64 tile; 32 rows
-// at a time are staged in LDS with 16-byte loads (8 channels per thread);
-// wave w owns output channels 16 w .. 16 w + 15 of the tile.
+// reduction over the chunk's rows, 32 per 16x16x32 instruction).  A block
+// computes a 64 x 64 tile; 32 rows at a time are staged in LDS with 16-byte
+// loads (8 channels per thread); wave w owns output channels 16 w .. 16 w + 15
+// of the tile.
 struct GWgrad {
     GConv a;
     const short* g;          // NHWC bf16 gradient of the output, pitch cout, on the destination grid
@@ -248,18 +348,16 @@ __global__ __launch_bounds__(NT) void gwgrad_kernel(GWgrad w)
         *reinterpret_cast<int4*>(&Gs[sr][s8]) = gv;
         *reinterpret_cast<int4*>(&Ps[sr][s8]) = pv;
         __syncthreads();
+        s16x8 av;
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            bf16x4 av;
+        for (int e = 0; e < 8; ++e) av[e] = Gs[8 * (lane >> 4) + e][wave * 16 + (lane & 15)];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) av[e] = Gs[s * 16 + 4 * (lane >> 4) + e][wave * 16 + (lane & 15)];
+        for (int j = 0; j < 4; ++j) {
+            s16x8 bv;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                bf16x4 bv;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) bv[e] = Ps[s * 16 + 4 * (lane >> 4) + e][j * 16 + (lane & 15)];
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[j], 0, 0, 0);
-            }
+            for (int e = 0; e < 8; ++e) bv[e] = Ps[8 * (lane >> 4) + e][j * 16 + (lane & 15)];
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
+                                                             acc[j], 0, 0, 0);
         }
     }
 #pragma unroll
@@ -667,6 +765,10 @@ int pat_gconv(const pat_gconv_desc* d, void* stream)
         return fail("pat_gconv", "destination channel split must cover cout");
     if ((d->dst_bf16[0] && d->accumulate[0]) || (d->dst_bf16[1] && d->accumulate[1]))
         return fail("pat_gconv", "bf16 destinations cannot accumulate", PAT_EUNSUPPORTED);
+    const bool x32 = d->csrc[0] % 32 == 0 && d->csrc[1] % 32 == 0;
+    if (!x32 && (d->csrc[0] + d->csrc[1]) % 32 == 0)
+        return fail("pat_gconv", "when the channel total is a multiple of 32 every source must be one",
+                    PAT_EUNSUPPORTED);
     GConv a = make_gconv(d);
     const int ctw = d->cout % 64 == 0 ? 4 : (d->cout % 32 == 0 ? 2 : 1);
     const long rows = (long)d->B * d->H * d->W;
@@ -674,9 +776,15 @@ int pat_gconv(const pat_gconv_desc* d, void* stream)
     const long blocks = (waves + 3) / 4;
     if (blocks > 0x7fffffffL) return fail("pat_gconv", "grid too large", PAT_EUNSUPPORTED);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (ctw == 4) gconv_kernel<4><<<(unsigned)blocks, NT, 0, st>>>(a);
-    else if (ctw == 2) gconv_kernel<2><<<(unsigned)blocks, NT, 0, st>>>(a);
-    else gconv_kernel<1><<<(unsigned)blocks, NT, 0, st>>>(a);
+    if (x32) {
+        if (ctw == 4) gconv32_kernel<4><<<(unsigned)blocks, NT, 0, st>>>(a);
+        else if (ctw == 2) gconv32_kernel<2><<<(unsigned)blocks, NT, 0, st>>>(a);
+        else gconv32_kernel<1><<<(unsigned)blocks, NT, 0, st>>>(a);
+    } else {
+        if (ctw == 4) gconv_kernel<4><<<(unsigned)blocks, NT, 0, st>>>(a);
+        else if (ctw == 2) gconv_kernel<2><<<(unsigned)blocks, NT, 0, st>>>(a);
+        else gconv_kernel<1><<<(unsigned)blocks, NT, 0, st>>>(a);
+    }
     return status("gconv_kernel");
 }
 

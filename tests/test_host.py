@@ -118,3 +118,22 @@ def test_plan_needs_a_gpu_and_says_so():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError, match="GPU"):
         pat.Plan(P.full_circle(32, 64, 64))
+
+
+def test_gconv_rejects_mixed_channel_packing_without_device_work(lib):
+    """Two 16-channel sources total 32 channels, whose weights pack for the
+    32-deep instruction; the kernel needs every source to be a multiple of 32,
+    so the call is refused before any launch."""
+    d = pat.GConvDesc()
+    d.B, d.H, d.W, d.Hs, d.Ws, d.Ho, d.Wo = 1, 8, 8, 8, 8, 8, 8
+    d.src[0], d.src[1] = 16, 32            # never dereferenced: rejected on the host
+    d.csrc[0], d.csrc[1] = 16, 16
+    d.in_stride, d.out_stride, d.ntaps = 1, 1, 1
+    d.weight, d.cout = 64, 16
+    d.dst[0], d.cdst[0] = 128, 16
+    assert lib.pat_gconv(ctypes.byref(d), None) == -2
+    assert b"multiple of 32" in lib.pat_last_error()
+    d.csrc[1] = 0
+    d.cout = 24
+    assert lib.pat_gconv(ctypes.byref(d), None) == -2      # cout not a multiple of 16
+    assert lib.pat_gconv(None, None) == -1
