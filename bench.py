@@ -273,6 +273,59 @@ def lpd_bench(steps: int = 3000, n_train: int = 10000, n_test: int = 64, batch: 
     return res
 
 
+def lpd_speed(arch: str = "unet", batch: int = 8, iters: int = 10, train_steps: int = 10, infer_reps: int = 5):
+    """Training and inference speed of the learned primal-dual reconstructor
+    on the time-to-PSNR workload (n = 256, m = 256 on the top 180-degree arc,
+    nt = 512) with untrained weights: captured training steps and captured
+    inference passes, timed with events.  For the U-Net, the matrix-core
+    flops of one inference pass (all 2 K network applications) are reported
+    with the achieved rate over the whole pass."""
+    import torch
+    from paper_2510_24687_amd import lpd as L
+    from paper_2510_24687_amd import pat
+    from paper_2510_24687_amd import phantoms as P
+    geom = P.top_arc(256, 256, 512, 180.0)
+    plan = pat.Plan(geom, torch.float32, max_batch=batch)
+    ds = L.make_dataset(plan, range(2 * batch), 0.02, noise_seed=1)
+    s_A, s_U = L.input_scales(plan, ds, count=2 * batch)
+    net = L.LPD(plan, batch, iters, s_A=s_A, s_U=s_U, seed=0, arch=arch)
+    net.set_batch(ds["y"][:batch], ds["f"][:batch])
+    net.opt.update(total=max(train_steps, 1))
+    net.capture_train()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(train_steps):
+        net.graph_train.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    t_train = e0.elapsed_time(e1) / 1e3 / max(train_steps, 1)
+    stats = None if net.stats is None else net.stats.cpu().numpy()
+    params = net.params.cpu().numpy()
+    del net
+    torch.cuda.empty_cache()
+    inf = L.LPD(plan, batch, iters, params=params, stats=stats, train=False, s_A=s_A, s_U=s_U, arch=arch)
+    inf.set_batch(ds["y"][:batch])
+    inf.capture_forward()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(infer_reps):
+        inf.graph_fwd.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    t_inf = e0.elapsed_time(e1) / 1e3 / max(infer_reps, 1)
+    out = {"workload": "n=256, m=256 on the top 180-degree arc, nt=512; batch %d, K=%d, %s networks" % (batch, iters, arch),
+           "train_step_s": t_train, "train_images_per_s": batch / t_train,
+           "inference_batch_s": t_inf, "inference_images_per_s": batch / t_inf,
+           "operator_evaluations_per_train_step": 4 * iters}
+    if arch == "unet":
+        flops = iters * (inf.dual.forward_flops() + inf.primal.forward_flops())
+        out["inference_matrix_flops"] = flops
+        out["inference_matrix_tflops_over_pass"] = flops / t_inf / 1e12
+        out["peak_bf16_dense_tflops"] = 2500.0
+    return out
+
+
 def cpu_baseline(geom: dict, seconds_budget: float = 20.0) -> dict:
     """Time the FP64 oracle on a bounded sample of the workload and extrapolate:
     forward on a few detectors (all times) and adjoint on a few pixels."""
@@ -321,6 +374,8 @@ def main():
     ap.add_argument("--lpd-lr", type=float, default=1e-3)
     ap.add_argument("--lpd-save", default="", help="write the trained weights (npz) here")
     ap.add_argument("--lpd-load", default="", help="evaluate weights written by --lpd-save (no training)")
+    ap.add_argument("--lpd-speed", action="store_true",
+                    help="time captured training steps and inference passes of the learned primal-dual")
     ap.add_argument("--lpd-arch", default="cnn", choices=["cnn", "unet"],
                     help="networks of the learned primal-dual: 3-layer CNNs or the paper's U-Nets")
     ap.add_argument("--suite", action="store_true",
@@ -353,6 +408,10 @@ def main():
         names = [x.strip() for x in args.suite_schemes.split(";") if x.strip()] or None
         res = X.run_suite(tests=args.suite_tests, schemes=names, lpd_steps=args.suite_lpd_steps, log=log)
         print(json.dumps({"suite": res}), flush=True)
+        return
+    if args.lpd_speed:
+        print(json.dumps({"lpd_speed": lpd_speed(arch=args.lpd_arch, train_steps=args.steps, infer_reps=args.steps)}),
+              flush=True)
         return
     if args.lpd:
         print(json.dumps({"lpd": lpd_bench(steps=args.lpd_steps, n_train=args.lpd_train, lr=args.lpd_lr,

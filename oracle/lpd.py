@@ -123,20 +123,21 @@ def reconstruct(geom, P, y, iters, s_A=1.0, s_U=1.0, rounding=True, ops=None, ar
     """f_K for data y (B, nt, m).  ``ops`` = (A, A*) callables on batches may
     replace the direct-quadrature operators (used by gradcheck on tiny
     explicit matrices).  ``arch = "unet"``: the U-Nets of oracle/unet.py with
-    running statistics ``running`` (keys "dual.<layer>", "primal.<layer>";
-    batch statistics and updated averages in training, the averages
-    otherwise)."""
+    running statistics ``running[k]`` for unrolled iteration k (keys
+    "dual.<layer>", "primal.<layer>"; batch statistics and updated averages
+    in training, the averages otherwise)."""
     A, As = ops if ops is not None else ((lambda f: _A.apply(f, geom)), (lambda g: _Astar.apply(g, geom)))
     B = y.shape[0]
     n = geom["n"]
     q = torch.zeros_like(y)
     f = torch.zeros((B, n, n), dtype=torch.float64)
-    for _ in range(iters):
+    for k in range(iters):
         Af = A(f)
-        q = q + _network(torch.stack([q, s_A * Af, s_A * y], dim=1), P, "dual", rounding, arch, running,
+        run_k = None if running is None else running[k]
+        q = q + _network(torch.stack([q, s_A * Af, s_A * y], dim=1), P, "dual", rounding, arch, run_k,
                          training)[:, 0]
         u = As(q)
-        f = f + _network(torch.stack([f, s_U * u], dim=1), P, "primal", rounding, arch, running, training)[:, 0]
+        f = f + _network(torch.stack([f, s_U * u], dim=1), P, "primal", rounding, arch, run_k, training)[:, 0]
     return f
 
 

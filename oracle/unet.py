@@ -20,7 +20,10 @@ Readings (where the paper leaves the layer details open, the usual U-Net):
   * batch normalisation: batch statistics (mean, biased variance over batch
     and pixels, eps = 1e-5) in training, running averages with momentum 0.1
     (unbiased variance) updated at every application and used at inference,
-    gamma = 1 and beta = 0 initially;
+    gamma = 1 and beta = 0 initially; inside the unrolled reconstructor each
+    iteration keeps its own running averages (buffers, not parameters: the
+    parameters stay shared), since the iterations' activations have
+    different statistics;
   * output: a 1x1 convolution 32 -> 1 with bias.
 With these readings the two networks (3 and 2 input channels) hold 3.85e6
 parameters, the "around 3.9e6" the paper states.
@@ -29,8 +32,10 @@ Precision: with ``rounding=True`` the oracle stores what the GPU stores in
 bfloat16 (network inputs, activations after batch normalisation and ReLU,
 up-sampled maps) rounded to bfloat16 and rounds the operands of every
 convolution product (forward, input gradient, weight gradient) to bfloat16,
-as the matrix-core kernels do; sums are float64.  ``rounding=False`` is the
-plain FP64 network.
+as the matrix-core kernels do; sums are float64.  The storage rounding passes
+gradients through unchanged (the GPU keeps activation gradients in FP32; only
+the gradients that enter a product are rounded, inside the products).
+``rounding=False`` is the plain FP64 network.
 """
 from __future__ import annotations
 
@@ -139,11 +144,16 @@ def tconv2(x, w, rounding=True):
     return _TConv2.apply(x, w, rounding)
 
 
+def stored_bf16(x):
+    """bf16 storage of a value: rounded forward, gradient passed through."""
+    return x + (bf16(x.detach()) - x.detach())
+
+
 def unet(x, P: dict, prefix: str, running: Optional[dict] = None, training: bool = True, rounding: bool = True):
     """The U-Net on x (B, cin, H, W), H and W divisible by 8; parameters
     P[prefix + name] (float64 tensors); running statistics
     running[prefix + layer] (updated in training).  Returns (B, 1, H, W)."""
-    store = bf16 if rounding else (lambda t: t)
+    store = stored_bf16 if rounding else (lambda t: t)
 
     def cbr(name, h):
         z = conv3x3(h, P[prefix + name + ".w"], None, rounding)

@@ -54,6 +54,43 @@ __device__ __forceinline__ short f2bf(float x)
 
 __device__ __forceinline__ float bf2f(short v) { return __uint_as_float(((uint32_t)(uint16_t)v) << 16); }
 
+// Sum over chunks q < chunks of part[q * stride + col] for the 16 columns
+// col0 .. col0 + 15 of a block: thread (c = tid % 16, g = tid / 16) adds chunks
+// g, g + 16, ... in FP64; the 16 group sums of column c are then added in
+// order by thread (c, 0).  Returns the column sum on threads with g == 0
+// (col0 + c < ncols), 0 elsewhere.  Every thread of the block must call it.
+__device__ double chunk_sum16(const double* part, int chunks, long stride, long col0, long ncols, double* red)
+{
+    const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const long col = col0 + c;
+    double s = 0.0;
+    if (col < ncols)
+        for (int q = g; q < chunks; q += 16) s += part[(size_t)q * stride + col];
+    __syncthreads();
+    red[threadIdx.x] = s;
+    __syncthreads();
+    double t = 0.0;
+    if (g == 0)
+        for (int k = 0; k < 16; ++k) t += red[k * 16 + c];
+    return t;
+}
+
+__device__ double chunk_sum16f(const float* part, int chunks, long stride, long col0, long ncols, double* red)
+{
+    const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const long col = col0 + c;
+    double s = 0.0;
+    if (col < ncols)
+        for (int q = g; q < chunks; q += 16) s += part[(size_t)q * stride + col];
+    __syncthreads();
+    red[threadIdx.x] = s;
+    __syncthreads();
+    double t = 0.0;
+    if (g == 0)
+        for (int k = 0; k < 16; ++k) t += red[k * 16 + c];
+    return t;
+}
+
 struct GConv {
     int B, H, W;             // iteration grid
     const short* src0;       // NHWC bf16, c0 channels
@@ -371,16 +408,18 @@ __global__ __launch_bounds__(NT) void gwgrad_kernel(GWgrad w)
 }
 
 // dw[off + co s_co + ci s_ci + tap s_t] (+)= sum over chunks of part[chunk][co][k]
-// (FP64, chunks in order); entries with ci >= ci_real are padding.
+// (FP64, fixed order: chunk_sum16); entries with ci >= ci_real are padding.
+// A block reduces 16 consecutive (co, k) entries.
 __global__ __launch_bounds__(NT) void gwgrad_reduce(const float* part, int chunks, int cout, int K, int cin,
                                                     int ci_real, float* dw, long off, long s_co, long s_ci, long s_t,
                                                     int accumulate)
 {
+    __shared__ double red[NT];
     const long total = (long)cout * K;
-    const long idx = (long)blockIdx.x * NT + threadIdx.x;
-    if (idx >= total) return;
-    double s = 0.0;
-    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * total + idx];
+    const long idx0 = (long)blockIdx.x * 16;
+    const double s = chunk_sum16f(part, chunks, total, idx0, total, red);
+    const long idx = idx0 + (threadIdx.x & 15);
+    if ((threadIdx.x >> 4) != 0 || idx >= total) return;
     const int co = (int)(idx / K), k = (int)(idx - (long)co * K);
     const int tap = k / cin, ci = k - tap * cin;
     if (ci >= ci_real) return;
@@ -418,18 +457,17 @@ __global__ __launch_bounds__(NT) void bn_partial(long R, int C, const float* z, 
     }
 }
 
+// block b finishes channels 16 b .. 16 b + 15
 __global__ __launch_bounds__(NT) void bn_final(int chunks, int C, long R, const double* part, float* mean,
                                                float* invstd, float* rmean, float* rvar, double momentum, double eps,
                                                int training)
 {
-    const int c = threadIdx.x;
-    if (c >= C) return;
+    __shared__ double red[NT];
+    const int c = blockIdx.x * 16 + (threadIdx.x & 15);
     if (training) {
-        double s = 0.0, ss = 0.0;
-        for (int q = 0; q < chunks; ++q) {
-            s += part[(size_t)q * 2 * C + c];
-            ss += part[(size_t)q * 2 * C + C + c];
-        }
+        const double s = chunk_sum16(part, chunks, 2L * C, blockIdx.x * 16, C, red);
+        const double ss = chunk_sum16(part + C, chunks, 2L * C, blockIdx.x * 16, C, red);
+        if ((threadIdx.x >> 4) != 0 || c >= C) return;
         const double mu = s / (double)R;
         const double var = fmax(ss / (double)R - mu * mu, 0.0);
         mean[c] = (float)mu;
@@ -439,6 +477,7 @@ __global__ __launch_bounds__(NT) void bn_final(int chunks, int C, long R, const 
             rvar[c] = (float)((1.0 - momentum) * rvar[c] + momentum * var * (double)R / (double)(R > 1 ? R - 1 : 1));
         }
     } else {
+        if ((threadIdx.x >> 4) != 0 || c >= C) return;
         mean[c] = rmean[c];
         invstd[c] = (float)(1.0 / sqrt((double)rvar[c] + eps));
     }
@@ -487,16 +526,15 @@ __global__ __launch_bounds__(NT) void bn_bwd_partial(long R, int C, const float*
 
 // sums[c] = sum gy, sums[C + c] = sum gy xhat (kept for the apply pass);
 // dbeta (+)= sum gy, dgamma (+)= sum gy xhat
+// block b finishes channels 16 b .. 16 b + 15
 __global__ __launch_bounds__(NT) void bn_bwd_final(int chunks, int C, double* part, float* dgamma, float* dbeta,
                                                    int accumulate)
 {
-    const int c = threadIdx.x;
-    if (c >= C) return;
-    double s1 = 0.0, s2 = 0.0;
-    for (int q = 0; q < chunks; ++q) {
-        s1 += part[(size_t)q * 2 * C + c];
-        s2 += part[(size_t)q * 2 * C + C + c];
-    }
+    __shared__ double red[NT];
+    const int c = blockIdx.x * 16 + (threadIdx.x & 15);
+    const double s1 = chunk_sum16(part, chunks, 2L * C, blockIdx.x * 16, C, red);
+    const double s2 = chunk_sum16(part + C, chunks, 2L * C, blockIdx.x * 16, C, red);
+    if ((threadIdx.x >> 4) != 0 || c >= C) return;
     double* sums = part + (size_t)chunks * 2 * C;
     sums[c] = s1;
     sums[C + c] = s2;
@@ -652,13 +690,14 @@ __global__ __launch_bounds__(NT) void head_bwd_partial(long R, int C, const shor
     }
 }
 
-// out[c] (+)= sum over chunks of part[chunk][c], c < ncols (FP64, in order)
+// out[c] (+)= sum over chunks of part[chunk][c], c < ncols (FP64, fixed order:
+// chunk_sum16); a block reduces 16 columns
 __global__ __launch_bounds__(NT) void col_reduce(const double* part, int chunks, int ncols, float* out, int accumulate)
 {
-    const int c = blockIdx.x * NT + threadIdx.x;
-    if (c >= ncols) return;
-    double s = 0.0;
-    for (int q = 0; q < chunks; ++q) s += part[(size_t)q * ncols + c];
+    __shared__ double red[NT];
+    const double s = chunk_sum16(part, chunks, ncols, blockIdx.x * 16L, ncols, red);
+    const int c = blockIdx.x * 16 + (threadIdx.x & 15);
+    if ((threadIdx.x >> 4) != 0 || c >= ncols) return;
     out[c] = accumulate ? out[c] + (float)s : (float)s;
 }
 
@@ -815,7 +854,7 @@ int pat_gconv_wgrad(const pat_gconv_desc* d, const void* grad, int chunks, void*
     gwgrad_kernel<<<grid, NT, 0, st>>>(w);
     if ((rc = status("gwgrad_kernel"))) return rc;
     const long total = (long)d->cout * K;
-    gwgrad_reduce<<<(int)((total + NT - 1) / NT), NT, 0, st>>>(w.part, used, d->cout, K, cin, ci_real,
+    gwgrad_reduce<<<(int)((total + 15) / 16), NT, 0, st>>>(w.part, used, d->cout, K, cin, ci_real,
                                                                static_cast<float*>(dw), off, s_co, s_ci, s_t,
                                                                accumulate);
     return status("gwgrad_reduce");
@@ -845,7 +884,7 @@ int pat_bn_forward(long rows, int channels, const void* z, const void* gamma, co
         int rc = status("bn_partial");
         if (rc) return rc;
     }
-    bn_final<<<1, NT, 0, st>>>(chunks, channels, rows, static_cast<const double*>(partials), static_cast<float*>(mean),
+    bn_final<<<(channels + 15) / 16, NT, 0, st>>>(chunks, channels, rows, static_cast<const double*>(partials), static_cast<float*>(mean),
                                static_cast<float*>(invstd), static_cast<float*>(running_mean),
                                static_cast<float*>(running_var), momentum, eps, training);
     int rc = status("bn_final");
@@ -878,7 +917,7 @@ int pat_bn_backward(long rows, int channels, const void* z, const void* grad_act
     bn_bwd_partial<<<chunks, NT, 0, st>>>(rows, channels, zf, gf, mf, sf, gm, bt, rpc, part);
     int rc = status("bn_bwd_partial");
     if (rc) return rc;
-    bn_bwd_final<<<1, NT, 0, st>>>(chunks, channels, part, static_cast<float*>(dgamma), static_cast<float*>(dbeta),
+    bn_bwd_final<<<(channels + 15) / 16, NT, 0, st>>>(chunks, channels, part, static_cast<float*>(dgamma), static_cast<float*>(dbeta),
                                    accumulate);
     if ((rc = status("bn_bwd_final"))) return rc;
     const long total = rows * channels;
@@ -963,7 +1002,7 @@ int pat_head_backward(long pixels, int C, const void* act, const void* w, const 
     head_bwd_partial<<<chunks, NT, 0, st>>>(pixels, C, static_cast<const short*>(act),
                                             static_cast<const float*>(grad_out), rpc, static_cast<double*>(partials));
     if ((rc = status("head_bwd_partial"))) return rc;
-    col_reduce<<<(C + 1 + NT - 1) / NT, NT, 0, st>>>(static_cast<const double*>(partials), chunks, C + 1,
+    col_reduce<<<(C + 1 + 15) / 16, NT, 0, st>>>(static_cast<const double*>(partials), chunks, C + 1,
                                                      static_cast<float*>(grad_wb), accumulate);
     return status("col_reduce");
 }

@@ -227,7 +227,8 @@ class LPD:
     initial weights (init_params).  ``train``: keep the activations of all K
     iterations and allocate gradients / Adam state.  ``arch``: "cnn" (3-layer
     CNNs) or "unet" (the paper's U-Nets, unet.UNetBlock, with batch
-    normalisation; ``stats``: flat running statistics, unet.init_stats).
+    normalisation; ``stats``: flat running statistics of every unrolled
+    iteration, unet.init_stats(iters)).
     """
 
     def __init__(self, plan: Plan, batch: int, iters: int = 10, params=None, seed: int = 0, train: bool = True,
@@ -264,12 +265,12 @@ class LPD:
         self.u = z(K, B, n, n)
         if arch == "unet":
             from . import unet as U
-            slay = U.stats_layout()
+            slay = U.stats_layout(K)
             self.soffs, so = {}, 0
             for name, c in slay:
                 self.soffs[name] = so
                 so += c
-            st0 = U.init_stats() if stats is None else np.asarray(stats, dtype=np.float32)
+            st0 = U.init_stats(K) if stats is None else np.asarray(stats, dtype=np.float32)
             if st0.size != so:
                 raise ValueError("expected %d running statistics" % so)
             self.stats = torch.tensor(st0, device=dev)

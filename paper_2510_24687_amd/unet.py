@@ -11,7 +11,11 @@ stride-2 transposed convolutions halving the channels, concatenated after
 the skip connection; bias-free convolutions (batch normalisation follows);
 batch statistics in training, running averages (momentum 0.1) at inference; a
 1x1 output convolution with bias.  Both networks together hold 3.85e6
-parameters.
+parameters, shared by all unrolled iterations.  The running averages are
+buffers, not parameters, and the activations of the K unrolled iterations
+have different statistics, so each iteration keeps its own running averages
+(one shared set would average over all iterations and normalise none of them
+as in training).
 
 Every step runs in libpat.so: the generic implicit-GEMM convolution on the
 BF16 matrix cores (pat_gconv) for the 3x3 convolutions, the transposed
@@ -74,18 +78,21 @@ def bn_layers() -> List[Tuple[str, int]]:
     return out
 
 
-def stats_layout(nets=(("dual", 3), ("primal", 2))) -> List[Tuple[str, int]]:
-    """Running statistics: per network and layer, mean then variance."""
+def stats_layout(iters: int, nets=(("dual", 3), ("primal", 2))) -> List[Tuple[str, int]]:
+    """Running statistics "<net>.it<k>.<layer>.mean|var": per network,
+    unrolled iteration k < iters and layer, mean then variance."""
     out = []
     for net, _ in nets:
-        for name, c in bn_layers():
-            out += [(net + "." + name + ".mean", c), (net + "." + name + ".var", c)]
+        for k in range(iters):
+            for name, c in bn_layers():
+                key = "%s.it%d.%s" % (net, k, name)
+                out += [(key + ".mean", c), (key + ".var", c)]
     return out
 
 
-def init_stats(nets=(("dual", 3), ("primal", 2))) -> np.ndarray:
+def init_stats(iters: int, nets=(("dual", 3), ("primal", 2))) -> np.ndarray:
     return np.concatenate([np.zeros(c) if name.endswith(".mean") else np.ones(c)
-                           for name, c in stats_layout(nets)]).astype(np.float32)
+                           for name, c in stats_layout(iters, nets)]).astype(np.float32)
 
 
 def init_values(name: str, shape: tuple, rng) -> np.ndarray:
@@ -207,10 +214,14 @@ class UNetBlock:
             self.convs["d%dc2" % s] = _Conv(lib, P, "d%dc2" % s, [c], c, dev)
         self.head_w, self.head_gw = P.view("head.w")
         self.head_b, self.head_gb = P.view("head.b")
-        self.stats = {}
-        for name, c in bn_layers():
-            o_m, o_v = soffs[net + "." + name + ".mean"], soffs[net + "." + name + ".var"]
-            self.stats[name] = (stats[o_m:o_m + c], stats[o_v:o_v + c])
+        self.stats = []
+        for k in range(K):
+            d = {}
+            for name, c in bn_layers():
+                key = "%s.it%d.%s" % (net, k, name)
+                o_m, o_v = soffs[key + ".mean"], soffs[key + ".var"]
+                d[name] = (stats[o_m:o_m + c], stats[o_v:o_v + c])
+            self.stats.append(d)
         self.hs = [H >> s for s in range(4)]
         self.ws = [W >> s for s in range(4)]
         self.rows = [B * self.hs[s] * self.ws[s] for s in range(4)]
@@ -285,19 +296,30 @@ class UNetBlock:
     def layers(self):
         return list(self.convs.values()) + list(self.ups.values())
 
+    def forward_flops(self) -> float:
+        """Multiply-add flops (2 per product) of one application's matrix-core
+        products (3x3 and transposed convolutions, real channels only)."""
+        total = 0.0
+        for name, L in self.convs.items():
+            total += 2.0 * self.rows[self._scale(name)] * L.cout * 9 * L.cin_real
+        for s, U in self.ups.items():
+            total += 2.0 * self.rows[s + 1] * 4 * U.cout * U.cin
+        return total
+
     # ---- forward ------------------------------------------------------------
-    def _conv_bn(self, name, j, bn_train, st):
+    def _conv_bn(self, name, j, k, bn_train, st):
         lib, L = self.lib, self.convs[name]
         s = self._scale(name)
         d = self._fwd_desc(L, j, [(self.z[name][j], L.cout, False, False)])
         _check(lib.pat_gconv(ctypes.byref(d), st), "pat_gconv")
-        rm, rv = self.stats[name]
+        rm, rv = self.stats[k][name]
         _check(lib.pat_bn_forward(self.rows[s], L.cout, _p(self.z[name][j]), _p(L.g), _p(L.b), _p(self.mean[name][j]),
                                   _p(self.invstd[name][j]), _p(rm), _p(rv), BN_MOMENTUM, BN_EPS, int(bn_train),
                                   _p(self.a[name][j]), _p(self.bn_part), st), "pat_bn_forward")
 
     def forward(self, k, planes, scales, state_in, state_out, st):
-        """state_out = state_in + U-Net(scales * planes) for application k."""
+        """state_out = state_in + U-Net(scales * planes) for application
+        (unrolled iteration) k, normalised with iteration k's statistics."""
         lib = self.lib
         j = min(k, len(self.x0) - 1)
         bn_train = self.train
@@ -305,8 +327,8 @@ class UNetBlock:
         sca = (ctypes.c_float * 4)(*([float(v) for v in scales] + [1.0] * (4 - len(scales))))
         _check(lib.pat_nhwc_pack(self.rows[0], self.cin, CPAD, vpa, sca, _p(self.x0[j]), st), "pat_nhwc_pack")
         for s in range(4):
-            self._conv_bn("e%dc1" % s, j, bn_train, st)
-            self._conv_bn("e%dc2" % s, j, bn_train, st)
+            self._conv_bn("e%dc1" % s, j, k, bn_train, st)
+            self._conv_bn("e%dc2" % s, j, k, bn_train, st)
             if s < 3:
                 _check(lib.pat_maxpool2(self.B, self.hs[s], self.ws[s], WIDTHS[s], _p(self.a["e%dc2" % s][j]),
                                         _p(self.pool[s][j]), st), "pat_maxpool2")
@@ -315,8 +337,8 @@ class UNetBlock:
             for p in range(4):
                 d = self._up_desc(U, s, j, p, [(self.up[s][j], U.cout, True, False)])
                 _check(lib.pat_gconv(ctypes.byref(d), st), "pat_gconv")
-            self._conv_bn("d%dc1" % s, j, bn_train, st)
-            self._conv_bn("d%dc2" % s, j, bn_train, st)
+            self._conv_bn("d%dc1" % s, j, k, bn_train, st)
+            self._conv_bn("d%dc2" % s, j, k, bn_train, st)
         _check(lib.pat_head_forward(self.rows[0], WIDTHS[0], _p(self.a["d0c2"][j]), _p(self.head_w), _p(self.head_b),
                                     _p(state_in), _p(state_out), st), "pat_head_forward")
 

@@ -306,10 +306,10 @@ def _block(lib, cin, B, H, W, seed, train=True, shift=0.0):
     params = torch.tensor(p0, device=DEV)
     grads = torch.zeros_like(params)
     soffs, so = {}, 0
-    for name, c in UN.stats_layout():
+    for name, c in UN.stats_layout(1):
         soffs[name] = so
         so += c
-    stats = torch.tensor(UN.init_stats(), device=DEV)
+    stats = torch.tensor(UN.init_stats(1), device=DEV)
     net = "dual" if cin == 3 else "primal"
     blk = UN.UNetBlock(lib, params, grads, offs, dict(layout), stats, soffs, net, cin, B, H, W, 1, DEV, train)
     return blk, params, grads, stats, offs, soffs, dict(layout), net
@@ -364,7 +364,7 @@ def test_unet_forward_backward_against_the_oracle(lib, cin, B, H, W, shift):
     # running statistics
     e_stats = 0.0
     for name, c in UN.bn_layers():
-        o = soffs[net + "." + name + ".mean"]
+        o = soffs[net + ".it0." + name + ".mean"]
         e_stats = max(e_stats, rel_max(stats[o:o + c].cpu().double(), run_r[net + "." + name]["mean"]))
     print("running means: max relative deviation %.3e" % e_stats)
     # parameter gradients, whole vector and per tensor
@@ -429,8 +429,20 @@ def _tiny(K):
     return geom, plan, f_true.astype(np.float32), y.astype(np.float32), params
 
 
-def _oracle_running():
-    return {net + "." + k: v for net in ("dual", "primal") for k, v in OU.fresh_running().items()}
+def _oracle_running(K):
+    """Per unrolled iteration, fresh running statistics of both networks."""
+    return [{net + "." + k: v for net in ("dual", "primal") for k, v in OU.fresh_running().items()}
+            for _ in range(K)]
+
+
+def _running_from(stats_np, K):
+    run = [{} for _ in range(K)]
+    o = 0
+    for name, c in UN.stats_layout(K):
+        net_, it, layer, kind = name.split(".")
+        run[int(it[2:])].setdefault(net_ + "." + layer, {})[kind] = torch.tensor(stats_np[o:o + c].astype(np.float64))
+        o += c
+    return run
 
 
 def test_unet_lpd_loss_gradient_against_the_oracle():
@@ -449,11 +461,11 @@ def test_unet_lpd_loss_gradient_against_the_oracle():
     net.backward_pass()
     torch.cuda.synchronize()
     Pd = {k: v.astype(np.float64) for k, v in LPDM.unpack(params, arch="unet").items()}
-    run_o = _oracle_running()
+    run_o = _oracle_running(K)
     loss_o, fK_o, g_o = OL.loss_and_grads(geom, Pd, y, f_true, K, s_A, s_U, rounding=True, arch="unet",
                                           running=run_o)
     loss_x, fK_x, g_x = OL.loss_and_grads(geom, Pd, y, f_true, K, s_A, s_U, rounding=False, arch="unet",
-                                          running=_oracle_running())
+                                          running=_oracle_running(K))
     grads = LPDM.unpack(net.grads.cpu().numpy(), arch="unet")
     fK = net.f[K].cpu().numpy()
     e_f, e_fx = _rel(fK, fK_o), _rel(fK_x, fK_o)
@@ -468,14 +480,12 @@ def test_unet_lpd_loss_gradient_against_the_oracle():
     for k in g_o:
         e, ex = _rel(grads[k], g_o[k]), _rel(g_x[k], g_o[k])
         assert e < 3 * ex or e < 2e-2, (k, e, ex)
-    # running statistics after the 2 K network applications
-    stats = net.stats.cpu().numpy()
-    o = 0
-    for name, c in UN.stats_layout():
-        net_, layer, kind = name.split(".")
-        ref = run_o[net_ + "." + layer][kind].numpy()
-        assert _rel(stats[o:o + c], ref) < 5e-2, name
-        o += c
+    # running statistics of every iteration after one application each
+    got = _running_from(net.stats.cpu().numpy(), K)
+    for k in range(K):
+        for key, v in run_o[k].items():
+            for kind in ("mean", "var"):
+                assert _rel(got[k][key][kind].numpy(), v[kind].numpy()) < 5e-2, (k, key, kind)
 
 
 def test_unet_lpd_graph_replay_and_inference():
@@ -503,13 +513,7 @@ def test_unet_lpd_graph_replay_and_inference():
     f_e = inf.forward_pass().clone()
     torch.cuda.synchronize()
     Pd = {k: v.astype(np.float64) for k, v in LPDM.unpack(a.params.cpu().numpy(), arch="unet").items()}
-    st_np = a.stats.cpu().numpy()
-    run = {}
-    o = 0
-    for name, c in UN.stats_layout():
-        net_, layer, kind = name.split(".")
-        run.setdefault(net_ + "." + layer, {})[kind] = torch.tensor(st_np[o:o + c].astype(np.float64))
-        o += c
+    run = _running_from(a.stats.cpu().numpy(), K)
     Pt = {k: torch.tensor(v) for k, v in Pd.items()}
     with torch.no_grad():
         f_o = OL.reconstruct(geom, Pt, torch.tensor(y.astype(np.float64)), K, rounding=True, arch="unet",
