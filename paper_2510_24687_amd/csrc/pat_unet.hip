@@ -295,6 +295,108 @@ __global__ __launch_bounds__(NT) void gconv32_kernel(GConv a)
     }
 }
 
+// The 3x3 stride-1 convolution (zero padding 1, destination = iteration grid)
+// with LDS tiles, for sources with multiples of 32 channels and W divisible by
+// 16.  A block owns 256 output pixels of one image, a TH x TW tile (TW = 64,
+// 32 or 16 dividing W, TH = 256 / TW), and 16 NCT output channels.  For each
+// 32-channel chunk it stages the input tile with its one-pixel halo,
+// (TH + 2) x (TW + 2) pixels x 32 channels, and the chunk's packed weights
+// of all 9 taps, then every wave runs the 9 taps from LDS: wave w computes
+// tile pixels 64 w .. 64 w + 63 (4 groups of 16, row-major in the tile).  The
+// four 16-byte pieces of a staged pixel p are rotated by p / 4, so that the
+// 16 consecutive pixels a quarter-wave reads land in distinct banks.
+constexpr int LDS_A_SHORTS = 6 * 66 * 32;   // largest staged tile: TW = 64, TH = 4
+
+template <int NCT>
+__global__ __launch_bounds__(NT) void gconv3_lds(GConv a, int TW)
+{
+    __shared__ __align__(16) short As[LDS_A_SHORTS];
+    __shared__ __align__(16) short Bs[9 * NCT * 512];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int TH = 256 / TW, PW = TW + 2, NP = (TH + 2) * PW;
+    const int tilesX = a.W / TW, tilesY = (a.H + TH - 1) / TH;
+    int tile = blockIdx.x;
+    const int tx0 = (tile % tilesX) * TW;
+    tile /= tilesX;
+    const int ty0 = (tile % tilesY) * TH;
+    const int b = tile / tilesY;
+    const int ct0 = blockIdx.y * NCT;
+    const int cs32 = (a.c0 + a.c1) >> 5, KT = 9 * cs32;
+    int oy[4], ox[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int p = wave * 64 + g * 16 + (lane & 15);
+        oy[g] = p / TW;
+        ox[g] = p - oy[g] * TW;
+    }
+    f32x4 acc[4][NCT];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int j = 0; j < NCT; ++j) acc[g][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int q = lane >> 4;
+    for (int cs = 0; cs < cs32; ++cs) {
+        const short* base;
+        int pitch;
+        if (cs * 32 < a.c0) {
+            base = a.src0 + cs * 32;
+            pitch = a.c0;
+        } else {
+            base = a.src1 + (cs * 32 - a.c0);
+            pitch = a.c1;
+        }
+        __syncthreads();   // the previous chunk's reads are done
+        for (int i = threadIdx.x; i < NP * 4; i += NT) {
+            const int pp = i >> 2, pc = i & 3;
+            const int yy = ty0 - 1 + pp / PW, xx = tx0 - 1 + pp % PW;
+            s16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                v = *reinterpret_cast<const s16x8*>(base + (((size_t)b * a.H + yy) * a.W + xx) * pitch + pc * 8);
+            *reinterpret_cast<s16x8*>(As + pp * 32 + ((pc + (pp >> 2)) & 3) * 8) = v;
+        }
+        for (int i = threadIdx.x; i < 9 * NCT * 64; i += NT) {
+            const int ln = i & 63, rest = i >> 6;
+            const int j = rest % NCT, t = rest / NCT;
+            *reinterpret_cast<s16x8*>(Bs + (t * NCT + j) * 512 + ln * 8) =
+                *reinterpret_cast<const s16x8*>(a.wp + (((size_t)(ct0 + j) * KT + t * cs32 + cs) * 64 + ln) * 8);
+        }
+        __syncthreads();
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3, dx = t - 3 * (t / 3);   // staged tile starts one pixel up and left
+            s16x8 bv[NCT];
+#pragma unroll
+            for (int j = 0; j < NCT; ++j) bv[j] = *reinterpret_cast<const s16x8*>(Bs + (t * NCT + j) * 512 + lane * 8);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int pp = (oy[g] + dy) * PW + ox[g] + dx;
+                const s16x8 av = *reinterpret_cast<const s16x8*>(As + pp * 32 + ((q + (pp >> 2)) & 3) * 8);
+#pragma unroll
+                for (int j = 0; j < NCT; ++j)
+                    acc[g][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                                         __builtin_bit_cast(bf16x8, bv[j]), acc[g][j],
+                                                                         0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = wave * 64 + g * 16 + 4 * (lane >> 4) + r;
+            const int ty = p / TW, y = ty0 + ty, x = tx0 + (p - ty * TW);
+            if (y >= a.H) continue;
+            const size_t op = ((size_t)b * a.H + y) * a.W + x;
+#pragma unroll
+            for (int j = 0; j < NCT; ++j) {
+                const int co = (ct0 + j) * 16 + (lane & 15);
+                const float v = acc[g][j][r];
+                if (co < a.d0) store_out(a.dst0, op * a.d0 + co, v, a.bf0, a.acc0);
+                else store_out(a.dst1, op * a.d1 + (co - a.d0), v, a.bf1, a.acc1);
+            }
+        }
+    }
+}
+
 // Packed weights (V = 8 when cip is a multiple of 32, else 4; KS = 4 V):
 // entry ((ctile * KT + kt) * 64 + lane) * V + e holds the effective weight
 // W_e[co][k] with co = 16 ctile + lane % 16 and k = KS kt + V (lane / 16) + e,
@@ -322,20 +424,22 @@ __global__ __launch_bounds__(NT) void gconv_pack(const float* w, int co_e, int c
 //   part[chunk][co][k] = sum_rows g[out(row)][co] * src[in(row, tap(k))][ci(k)]
 // as an MFMA contraction (rows of A = output channels, columns of B = k,
 // reduction over the chunk's rows, 32 per 16x16x32 instruction).  A block
-// computes a 64 x 64 tile; 32 rows at a time are staged in LDS with 16-byte
-// loads (8 channels per thread); wave w owns output channels 16 w .. 16 w + 15
-// of the tile.
+// computes a 64 x 64 tile; WG_ROWS rows at a time are staged in LDS with
+// 16-byte loads (8 channels per thread and row); wave w owns output channels
+// 16 w .. 16 w + 15 of the tile.
 struct GWgrad {
     GConv a;
     const short* g;          // NHWC bf16 gradient of the output, pitch cout, on the destination grid
-    long rpc;                // rows per chunk (multiple of 32)
+    long rpc;                // rows per chunk (multiple of WG_ROWS)
     float* part;
 };
 
+constexpr int WG_ROWS = 128;
+
 __global__ __launch_bounds__(NT) void gwgrad_kernel(GWgrad w)
 {
-    __shared__ __align__(16) short Gs[32][64];
-    __shared__ __align__(16) short Ps[32][64];
+    __shared__ __align__(16) short Gs[WG_ROWS][64];
+    __shared__ __align__(16) short Ps[WG_ROWS][64];
     const GConv& a = w.a;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int cin = a.c0 + a.c1, K = a.ntaps * cin;
@@ -343,7 +447,7 @@ __global__ __launch_bounds__(NT) void gwgrad_kernel(GWgrad w)
     const long chunk = blockIdx.z;
     const long R = (long)a.B * a.H * a.W;
     const long r0 = chunk * w.rpc, r1 = min(R, r0 + w.rpc);
-    // this thread stages row sr of each 32-row step, columns s8 .. s8 + 7
+    // this thread stages rows sr, sr + 32, ... of each step, columns s8 .. s8 + 7
     const int sr = threadIdx.x >> 3, s8 = (threadIdx.x & 7) * 8;
     const int ks = k0 + s8, co_s = co0 + s8;
     const bool kin = ks < K, cin_ok = co_s < a.cout;
@@ -364,37 +468,54 @@ __global__ __launch_bounds__(NT) void gwgrad_kernel(GWgrad w)
     f32x4 acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (long rb = r0; rb < r1; rb += 32) {
-        const long row = rb + sr;
-        int4 gv = {0, 0, 0, 0}, pv = {0, 0, 0, 0};
-        if (row < r1) {
-            const int x = (int)(row % a.W);
-            const long tt = row / a.W;
-            const int y = (int)(tt % a.H), b = (int)(tt / a.H);
-            if (cin_ok) {
-                const size_t op = ((size_t)b * a.Ho + a.ostr * y + a.oy) * a.Wo + a.ostr * x + a.ox;
-                gv = *reinterpret_cast<const int4*>(w.g + op * a.cout + co_s);
-            }
-            if (kin) {
-                const int sy = a.istr * y + tdy, sx = a.istr * x + tdx;
-                if (sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws)
-                    pv = *reinterpret_cast<const int4*>(sbase + (((size_t)b * a.Hs + sy) * a.Ws + sx) * pitch);
+    // the global loads of step rb + WG_ROWS are issued before the matrix
+    // instructions of step rb, so that they overlap
+    int4 gv[WG_ROWS / 32], pv[WG_ROWS / 32];
+    auto load = [&](long rb) {
+#pragma unroll
+        for (int h = 0; h < WG_ROWS / 32; ++h) {
+            const long row = rb + sr + 32 * h;
+            gv[h] = int4{0, 0, 0, 0};
+            pv[h] = int4{0, 0, 0, 0};
+            if (row < r1) {
+                const int x = (int)(row % a.W);
+                const long tt = row / a.W;
+                const int y = (int)(tt % a.H), b = (int)(tt / a.H);
+                if (cin_ok) {
+                    const size_t op = ((size_t)b * a.Ho + a.ostr * y + a.oy) * a.Wo + a.ostr * x + a.ox;
+                    gv[h] = *reinterpret_cast<const int4*>(w.g + op * a.cout + co_s);
+                }
+                if (kin) {
+                    const int sy = a.istr * y + tdy, sx = a.istr * x + tdx;
+                    if (sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws)
+                        pv[h] = *reinterpret_cast<const int4*>(sbase + (((size_t)b * a.Hs + sy) * a.Ws + sx) * pitch);
+                }
             }
         }
+    };
+    if (r0 < r1) load(r0);
+    for (long rb = r0; rb < r1; rb += WG_ROWS) {
         __syncthreads();
-        *reinterpret_cast<int4*>(&Gs[sr][s8]) = gv;
-        *reinterpret_cast<int4*>(&Ps[sr][s8]) = pv;
+#pragma unroll
+        for (int h = 0; h < WG_ROWS / 32; ++h) {
+            *reinterpret_cast<int4*>(&Gs[sr + 32 * h][s8]) = gv[h];
+            *reinterpret_cast<int4*>(&Ps[sr + 32 * h][s8]) = pv[h];
+        }
         __syncthreads();
-        s16x8 av;
+        if (rb + WG_ROWS < r1) load(rb + WG_ROWS);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) av[e] = Gs[8 * (lane >> 4) + e][wave * 16 + (lane & 15)];
+        for (int h = 0; h < WG_ROWS / 32; ++h) {
+            s16x8 av;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            s16x8 bv;
+            for (int e = 0; e < 8; ++e) av[e] = Gs[32 * h + 8 * (lane >> 4) + e][wave * 16 + (lane & 15)];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) bv[e] = Ps[8 * (lane >> 4) + e][j * 16 + (lane & 15)];
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
-                                                             acc[j], 0, 0, 0);
+            for (int j = 0; j < 4; ++j) {
+                s16x8 bv;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bv[e] = Ps[32 * h + 8 * (lane >> 4) + e][j * 16 + (lane & 15)];
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                                 __builtin_bit_cast(bf16x8, bv), acc[j], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
@@ -437,14 +558,20 @@ __global__ __launch_bounds__(NT) void bn_partial(long R, int C, const float* z, 
     __shared__ double red[2][NT];
     const int G = NT / C, g = threadIdx.x / C, c = threadIdx.x - g * C;
     const long r0 = (long)blockIdx.x * rpc, r1 = min(R, r0 + rpc);
-    double s = 0.0, ss = 0.0;
-    for (long r = r0 + g; r < r1; r += G) {
-        const double v = z[(size_t)r * C + c];
-        s += v;
-        ss += v * v;
+    // four independent accumulator pairs (rows r0 + g + G (4 i + u)), added
+    // in order at the end: loads of four rows are in flight at once
+    double s4[4] = {0.0, 0.0, 0.0, 0.0}, ss4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long r = r0 + g; r < r1; r += 4 * G) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long rr = r + u * G;
+            const double v = rr < r1 ? (double)z[(size_t)rr * C + c] : 0.0;
+            s4[u] += v;
+            ss4[u] += v * v;
+        }
     }
-    red[0][threadIdx.x] = s;
-    red[1][threadIdx.x] = ss;
+    red[0][threadIdx.x] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    red[1][threadIdx.x] = (ss4[0] + ss4[1]) + (ss4[2] + ss4[3]);
     __syncthreads();
     if (threadIdx.x < C) {
         double a = 0.0, b = 0.0;
@@ -501,17 +628,23 @@ __global__ __launch_bounds__(NT) void bn_bwd_partial(long R, int C, const float*
     const int G = NT / C, g = threadIdx.x / C, c = threadIdx.x - g * C;
     const long r0 = (long)blockIdx.x * rpc, r1 = min(R, r0 + rpc);
     const float mu = mean[c], is = invstd[c], gm = gamma[c], bt = beta[c];
-    double s1 = 0.0, s2 = 0.0;
-    for (long r = r0 + g; r < r1; r += G) {
-        const size_t i = (size_t)r * C + c;
-        const float xh = (z[i] - mu) * is;
-        const float y = gm * xh + bt;
-        const float gy = y > 0.f ? ga[i] : 0.f;
-        s1 += gy;
-        s2 += (double)gy * xh;
+    double a4[4] = {0.0, 0.0, 0.0, 0.0}, b4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long r = r0 + g; r < r1; r += 4 * G) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long rr = r + u * G;
+            if (rr < r1) {
+                const size_t i = (size_t)rr * C + c;
+                const float xh = (z[i] - mu) * is;
+                const float y = gm * xh + bt;
+                const float gy = y > 0.f ? ga[i] : 0.f;
+                a4[u] += gy;
+                b4[u] += (double)gy * xh;
+            }
+        }
     }
-    red[0][threadIdx.x] = s1;
-    red[1][threadIdx.x] = s2;
+    red[0][threadIdx.x] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    red[1][threadIdx.x] = (b4[0] + b4[1]) + (b4[2] + b4[3]);
     __syncthreads();
     if (threadIdx.x < C) {
         double a = 0.0, b = 0.0;
@@ -669,14 +802,20 @@ __global__ __launch_bounds__(NT) void head_bwd_partial(long R, int C, const shor
     __shared__ double red[2][NT];
     const int G = NT / C, q = threadIdx.x / C, c = threadIdx.x - q * C;
     const long r0 = (long)blockIdx.x * rpc, r1 = min(R, r0 + rpc);
-    double s = 0.0, sg = 0.0;
-    for (long p = r0 + q; p < r1; p += G) {
-        const double gp = g[p];
-        s += gp * bf2f(act[(size_t)p * C + c]);
-        sg += gp;
+    double s4[4] = {0.0, 0.0, 0.0, 0.0}, g4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long p = r0 + q; p < r1; p += 4 * G) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long pp = p + u * G;
+            if (pp < r1) {
+                const double gp = g[pp];
+                s4[u] += gp * bf2f(act[(size_t)pp * C + c]);
+                g4[u] += gp;
+            }
+        }
     }
-    red[0][threadIdx.x] = s;
-    red[1][threadIdx.x] = sg;
+    red[0][threadIdx.x] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    red[1][threadIdx.x] = (g4[0] + g4[1]) + (g4[2] + g4[3]);
     __syncthreads();
     if (threadIdx.x < C) {
         double a = 0.0;
@@ -719,8 +858,9 @@ int fail(const char* who, const char* why, int code = PAT_EINVAL)
 
 int grid_of(long total) { return (int)std::min<long>(std::max<long>((total + NT - 1) / NT, 1), 8192); }
 
-// chunk count for the row-partitioned reductions: rows per chunk >= 256
-int bn_chunks(long R) { return (int)std::max<long>(1, std::min<long>(512, R / 256)); }
+// chunk count for the row-partitioned reductions: rows per chunk >= 256, at
+// most 4096 chunks (enough blocks in flight for these memory-bound passes)
+int bn_chunks(long R) { return (int)std::max<long>(1, std::min<long>(4096, R / 256)); }
 
 int check_gconv(const pat_gconv_desc* d, const char* who)
 {
@@ -815,6 +955,18 @@ int pat_gconv(const pat_gconv_desc* d, void* stream)
     const long blocks = (waves + 3) / 4;
     if (blocks > 0x7fffffffL) return fail("pat_gconv", "grid too large", PAT_EUNSUPPORTED);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    bool plain3 = x32 && d->ntaps == 9 && d->in_stride == 1 && d->out_stride == 1 && d->oy == 0 && d->ox == 0 &&
+                  d->Hs == d->H && d->Ws == d->W && d->Ho == d->H && d->Wo == d->W && d->W % 16 == 0 &&
+                  d->cout % 32 == 0;
+    for (int t = 0; plain3 && t < 9; ++t) plain3 = d->dy[t] == t / 3 - 1 && d->dx[t] == t % 3 - 1;
+    if (plain3) {
+        const int TW = d->W % 64 == 0 ? 64 : (d->W % 32 == 0 ? 32 : 16), TH = 256 / TW;
+        const long tiles = (long)d->B * ((d->H + TH - 1) / TH) * (d->W / TW);
+        if (tiles > 0x7fffffffL) return fail("pat_gconv", "grid too large", PAT_EUNSUPPORTED);
+        if (d->cout % 64 == 0) gconv3_lds<4><<<dim3((unsigned)tiles, d->cout / 64), NT, 0, st>>>(a, TW);
+        else gconv3_lds<2><<<dim3((unsigned)tiles, d->cout / 32), NT, 0, st>>>(a, TW);
+        return status("gconv3_lds");
+    }
     if (x32) {
         if (ctw == 4) gconv32_kernel<4><<<(unsigned)blocks, NT, 0, st>>>(a);
         else if (ctw == 2) gconv32_kernel<2><<<(unsigned)blocks, NT, 0, st>>>(a);
@@ -845,7 +997,7 @@ int pat_gconv_wgrad(const pat_gconv_desc* d, const void* grad, int chunks, void*
     w.a = make_gconv(d);
     w.g = static_cast<const short*>(grad);
     const long rows = (long)d->B * d->H * d->W;
-    w.rpc = ((rows + chunks - 1) / chunks + 31) / 32 * 32;
+    w.rpc = ((rows + chunks - 1) / chunks + WG_ROWS - 1) / WG_ROWS * WG_ROWS;
     w.part = static_cast<float*>(partials);
     const int K = d->ntaps * cin;
     const int used = (int)((rows + w.rpc - 1) / w.rpc);   // chunks that hold rows

@@ -107,6 +107,32 @@ def test_gconv_3x3_two_sources_split_destinations(lib, c0, c1, co):
     assert float(((got1 - ref[..., 32:]).abs() / ref[..., 32:].abs().clamp_min(1e-3)).max()) < 2 ** -8
 
 
+@pytest.mark.parametrize("B,H,W,c0,c1,co", [(2, 13, 128, 32, 32, 64), (1, 20, 96, 64, 0, 32), (3, 7, 48, 32, 0, 96),
+                                              (2, 9, 64, 128, 128, 128)])
+def test_gconv_3x3_lds_tiles(lib, B, H, W, c0, c1, co):
+    """The LDS-tiled 3x3 path (W divisible by 16, 32-multiple channels): tile
+    widths 64 / 32 / 16, rows that do not fill the last tile, one or two
+    sources, 2 or 4 column tiles per block, split destinations."""
+    g = torch.Generator().manual_seed(H * W + co)
+    x0, x0d = bfrand((B, H, W, c0), g)
+    srcs, xs = [(x0d, c0)], x0
+    if c1:
+        x1, x1d = bfrand((B, H, W, c1), g)
+        srcs, xs = [(x0d, c0), (x1d, c1)], torch.cat([x0, x1], dim=3)
+    ci = c0 + c1
+    w = torch.randn((co, ci, 3, 3), generator=g) * 0.1
+    wf = pack(lib, w.to(DEV), co, ci, co, ci, 9, 0, ci * 9, 9, 1, 0)
+    d0 = co - 16
+    out0 = torch.full((B, H, W, d0), -0.25, device=DEV)
+    out1 = torch.empty((B, H, W, 16), dtype=torch.int16, device=DEV)
+    run(lib, UN._gdesc(B, H, W, srcs, H, W, 1, UN.TAPS3, wf, co, [(out0, d0, False, True), (out1, 16, True, False)],
+                       H, W))
+    ref = nhwc(F.conv2d(nchw(xs), obf16(w.double()), padding=1))
+    assert rel_max(out0.cpu().double() + 0.25, ref[..., :d0]) < 1e-5
+    got1 = from_bf(out1)
+    assert float(((got1 - ref[..., d0:]).abs() / ref[..., d0:].abs().clamp_min(1e-3)).max()) < 2 ** -8
+
+
 def test_gconv_input_gradient_is_the_transposed_convolution(lib):
     g = torch.Generator().manual_seed(1)
     B, H, W, cin, co = 2, 8, 24, 3, 32                   # first-layer shape: 3 real inputs padded to 16
