@@ -383,6 +383,8 @@ def main():
     ap.add_argument("--suite-tests", type=int, default=4)
     ap.add_argument("--suite-lpd-steps", type=int, default=3000)
     ap.add_argument("--suite-schemes", default="", help="semicolon-separated scheme names (default: all)")
+    ap.add_argument("--suite-methods", default="", help="comma-separated methods (inverse, nnls, tv, lpd; default: all)")
+    ap.add_argument("--suite-lpd-arch", default="cnn", choices=["cnn", "unet"])
     ap.add_argument("--tuning-cache", default="",
                     help="autotuner cache file (default: a fresh temporary file, i.e. tune at start-up)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -406,7 +408,13 @@ def main():
             print(json.dumps({"suite_progress": round(time.time() - t_start, 1), "row": row}), flush=True)
 
         names = [x.strip() for x in args.suite_schemes.split(";") if x.strip()] or None
-        res = X.run_suite(tests=args.suite_tests, schemes=names, lpd_steps=args.suite_lpd_steps, log=log)
+        meths = [x.strip() for x in args.suite_methods.split(",") if x.strip()] or None
+        def train_log(step, loss):
+            print(json.dumps({"suite_progress": round(time.time() - t_start, 1), "lpd_train_step": step,
+                              "loss": loss}), flush=True)
+
+        res = X.run_suite(tests=args.suite_tests, schemes=names, lpd_steps=args.suite_lpd_steps, log=log,
+                          lpd_arch=args.suite_lpd_arch, methods=meths, train_log=train_log)
         print(json.dumps({"suite": res}), flush=True)
         return
     if args.lpd_speed:

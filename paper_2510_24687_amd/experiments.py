@@ -129,9 +129,11 @@ def run_iterative(plan: Plan, y: torch.Tensor, method: str, supp: torch.Tensor, 
     return sol.groups[0].f[0].clone(), iters[0], dt
 
 
-def train_lpd(plan: Plan, kind: str, noise: float, steps: int, n_train: int, lr: float, log=None):
+def train_lpd(plan: Plan, kind: str, noise: float, steps: int, n_train: int, lr: float, log=None,
+              arch: str = "cnn"):
     """A learned primal-dual network (K = 10, batch 8) for one scheme, trained
-    on phantoms of the scheme's support with data from the plan's operator."""
+    on phantoms of the scheme's support with data from the plan's operator
+    (``arch``: "cnn" 3-layer networks or the paper's "unet")."""
     from . import lpd as L
     seeds = list(range(n_train))
     f = phantoms(seeds, plan.n, kind, plan.device)
@@ -147,17 +149,19 @@ def train_lpd(plan: Plan, kind: str, noise: float, steps: int, n_train: int, lr:
         y[s:e] += (noise * ny / ne).view(-1, 1, 1) * eps
     ds = {"f": f, "y": y}
     s_A, s_U = L.input_scales(plan, ds)
-    net = L.LPD(plan, 8, 10, s_A=s_A, s_U=s_U, seed=0)
+    net = L.LPD(plan, 8, 10, s_A=s_A, s_U=s_U, seed=0, arch=arch)
     t0 = time.perf_counter()
     hist = L.train(net, ds, steps, lr=lr, log_every=max(1, steps // 10), log=log)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     params = net.params.cpu().numpy()
+    stats = None if net.stats is None else net.stats.cpu().numpy()
     del net, ds
     torch.cuda.empty_cache()
-    inf = L.LPD(plan, 1, 10, params=params, train=False, s_A=s_A, s_U=s_U)
+    inf = L.LPD(plan, 1, 10, params=params, stats=stats, train=False, s_A=s_A, s_U=s_U, arch=arch)
     inf.capture_forward()
-    return inf, {"steps": steps, "phantoms": n_train, "seconds": train_s, "loss_last": hist[-1][1] if hist else None}
+    return inf, {"steps": steps, "phantoms": n_train, "seconds": train_s, "loss_last": hist[-1][1] if hist else None,
+                 "arch": arch}
 
 
 def run_lpd(net, y: torch.Tensor):
@@ -169,18 +173,33 @@ def run_lpd(net, y: torch.Tensor):
     return f[0].clone(), 10, time.perf_counter() - t0
 
 
+def methods_filter(methods, selected):
+    """The scheme's methods that are also selected (all of them when none are)."""
+    if not selected:
+        return tuple(methods)
+    return tuple(m for m in methods if m in selected)
+
+
 def run_suite(n: int = 256, nt: int = 512, T: float = 4.0, tests: int = 4, schemes: Optional[List[str]] = None,
               lpd_steps: int = 3000, lpd_train: int = 4000, lpd_lr: float = 1e-3,
-              tv_lams=(1e-4, 3e-4, 1e-3, 3e-3, 1e-2), max_iter: int = 1000, device="cuda", log=None) -> dict:
+              tv_lams=(1e-4, 3e-4, 1e-3, 3e-3, 1e-2), max_iter: int = 1000, device="cuda", log=None,
+              lpd_arch: str = "cnn", methods: Optional[List[str]] = None, train_log=None) -> dict:
     """Runs the schemes; per method the mean over ``tests`` held-out phantoms
     of iterations, time, time per iteration and errors.  The TV weight is
-    chosen per scheme from ``tv_lams`` on a separate validation phantom."""
+    chosen per scheme from ``tv_lams`` on a separate validation phantom.
+    ``methods`` restricts every scheme to those methods; ``lpd_arch`` picks
+    the learned networks (the paper's Table 1 uses U-Nets); ``train_log(step,
+    loss)`` receives the training progress."""
     device = torch.device(device)
+    methods_sel = list(methods) if methods else []
     out = {"grid": n, "data_grid": 2 * n, "nt": nt, "T": T, "test_phantoms": tests, "rows": []}
     test_seeds = [10 ** 6 + i for i in range(tests)]
     val_seed = [2 * 10 ** 6]
     for name in (schemes or list(SCHEMES)):
         arc, kind, noise, methods = SCHEMES[name]
+        methods = methods_filter(methods, methods_sel)
+        if not methods:
+            continue
         geom = geometry(arc, n, detectors(arc, n), nt, T)
         t0 = time.perf_counter()
         plan = Plan(geom, torch.float32, max_batch=8, device=device)
@@ -200,7 +219,7 @@ def run_suite(n: int = 256, nt: int = 512, T: float = 4.0, tests: int = 4, schem
             lam = float(min(tv_lams, key=lambda v: sweep["%g" % v]))
         net, train_info = None, None
         if "lpd" in methods:
-            net, train_info = train_lpd(plan, kind, noise, lpd_steps, lpd_train, lpd_lr)
+            net, train_info = train_lpd(plan, kind, noise, lpd_steps, lpd_train, lpd_lr, log=train_log, arch=lpd_arch)
         for meth in methods:
             recs = []
             for i in range(tests):
@@ -212,7 +231,7 @@ def run_suite(n: int = 256, nt: int = 512, T: float = 4.0, tests: int = 4, schem
                     fr, it, dt = run_iterative(plan, y[i], meth, supp, lam=lam or 0.0, opnorm=L, max_iter=max_iter)
                 e = errors(fr, truth[i])
                 recs.append(dict(e, iterations=it, seconds=dt))
-            row = {"scheme": name, "method": meth,
+            row = {"scheme": name, "method": meth if meth != "lpd" else "lpd (%s)" % lpd_arch,
                    "iterations": float(np.mean([r["iterations"] for r in recs])),
                    "seconds": float(np.mean([r["seconds"] for r in recs])),
                    "seconds_per_iteration": float(np.mean([r["seconds"] / r["iterations"] for r in recs])),
