@@ -351,10 +351,13 @@ def _oracle_params(p0, offs, shapes, net, requires_grad=True):
     return P
 
 
-@pytest.mark.parametrize("cin,B,H,W,shift", [(2, 2, 32, 32, 0.0), (3, 2, 48, 24, 0.0), (2, 2, 32, 32, 2.0)])
+@pytest.mark.parametrize("cin,B,H,W,shift", [(2, 2, 32, 32, 0.0), (3, 2, 48, 24, 0.0), (2, 2, 32, 32, 2.0),
+                                             (2, 1, 256, 256, 2.0), (3, 1, 512, 256, 2.0)])
 def test_unet_forward_backward_against_the_oracle(lib, cin, B, H, W, shift):
     """shift: every batch-normalisation shift beta raised by this much, so that
-    ReLU masks rarely sit near a flip (a less chaotic regime, tighter bar)."""
+    ReLU masks rarely sit near a flip (a less chaotic regime, tighter bar).
+    The 256 x 256 (primal) and 512 x 256 (dual) cases are the networks of the
+    time-to-PSNR workload at their real sizes, on the LDS-tiled path."""
     blk, params, grads, stats, offs, soffs, shapes, net = _block(lib, cin, B, H, W, seed=10 + cin, shift=shift)
     g = torch.Generator().manual_seed(20 + cin)
     planes = [torch.randn((B, H, W), generator=g) for _ in range(cin)]

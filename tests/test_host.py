@@ -137,3 +137,19 @@ def test_gconv_rejects_mixed_channel_packing_without_device_work(lib):
     d.cout = 24
     assert lib.pat_gconv(ctypes.byref(d), None) == -2      # cout not a multiple of 16
     assert lib.pat_gconv(None, None) == -1
+
+
+def test_unet_entry_points_validate_on_the_host(lib):
+    """Unsupported channel counts and bad shapes are refused before any launch."""
+    assert lib.pat_bn_partials(1000, 48) == -1          # channels must divide 256
+    assert lib.pat_bn_partials(0, 32) == -1
+    assert lib.pat_bn_partials(1000, 32) > 0
+    assert lib.pat_head_partials(100, 33) == -1
+    assert lib.pat_gconv_packed_size(24, 32, 9) == -1   # cout not a multiple of 16
+    assert lib.pat_gconv_packed_size(32, 32, 10) == -1  # at most 9 taps
+    assert lib.pat_gconv_packed_size(32, 48, 9) == 32 * 48 * 9
+    assert lib.pat_maxpool2(1, 7, 8, 32, 16, 32, None) == -1     # odd H
+    assert lib.pat_bn_forward(1000, 48, 16, 16, 16, 16, 16, None, None, 0.1, 1e-5, 1, 16, 16, None) == -2
+    assert lib.pat_bn_forward(1000, 32, 16, 16, 16, 16, 16, None, None, 0.1, 1e-5, 0, 16, 16, None) == -1
+    assert lib.pat_gconv_pack(None, 16, 16, 16, 16, 9, 0, 1, 1, 1, 0, 16, None) == -1
+    assert lib.pat_nhwc_pack(10, 5, 16, None, None, 16, None) == -1
