@@ -858,9 +858,14 @@ int fail(const char* who, const char* why, int code = PAT_EINVAL)
 
 int grid_of(long total) { return (int)std::min<long>(std::max<long>((total + NT - 1) / NT, 1), 8192); }
 
-// chunk count for the row-partitioned reductions: rows per chunk >= 256, at
-// most 4096 chunks (enough blocks in flight for these memory-bound passes)
-int bn_chunks(long R) { return (int)std::max<long>(1, std::min<long>(4096, R / 256)); }
+// chunk count for the row-partitioned reductions over R rows of C channels:
+// about 16 K elements per chunk (at least 8 rows), at most 4096 chunks, so
+// that narrow and wide layers alike put enough blocks in flight
+int bn_chunks(long R, int C)
+{
+    const long rows = std::max<long>(8, 16384 / std::max(C, 1));
+    return (int)std::max<long>(1, std::min<long>(4096, R / rows));
+}
 
 int check_gconv(const pat_gconv_desc* d, const char* who)
 {
@@ -1015,7 +1020,7 @@ int pat_gconv_wgrad(const pat_gconv_desc* d, const void* grad, int chunks, void*
 long pat_bn_partials(long rows, int channels)
 {
     if (rows < 1 || channels < 1 || channels > 256 || 256 % channels) return -1;
-    return ((long)bn_chunks(rows) + 1) * 2 * channels;
+    return ((long)bn_chunks(rows, channels) + 1) * 2 * channels;
 }
 
 int pat_bn_forward(long rows, int channels, const void* z, const void* gamma, const void* beta, void* mean,
@@ -1028,7 +1033,7 @@ int pat_bn_forward(long rows, int channels, const void* z, const void* gamma, co
         ((running_mean == nullptr) != (running_var == nullptr)))
         return fail("pat_bn_forward", "bad arguments");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const int chunks = bn_chunks(rows);
+    const int chunks = bn_chunks(rows, channels);
     const long rpc = (rows + chunks - 1) / chunks;
     if (training) {
         bn_partial<<<chunks, NT, 0, st>>>(rows, channels, static_cast<const float*>(z), rpc,
@@ -1057,7 +1062,7 @@ int pat_bn_backward(long rows, int channels, const void* z, const void* grad_act
     if (!z || !grad_act || !gamma || !beta || !mean || !invstd || !grad_z || !dgamma || !dbeta || !partials)
         return fail("pat_bn_backward", "bad arguments");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const int chunks = bn_chunks(rows);
+    const int chunks = bn_chunks(rows, channels);
     const long rpc = (rows + chunks - 1) / chunks;
     const float* zf = static_cast<const float*>(z);
     const float* gf = static_cast<const float*>(grad_act);
@@ -1135,7 +1140,7 @@ int pat_head_forward(long pixels, int C, const void* act, const void* w, const v
 long pat_head_partials(long pixels, int C)
 {
     if (pixels < 1 || C < 1 || C > 256 || 256 % C) return -1;
-    return (long)bn_chunks(pixels) * (C + 1);
+    return (long)bn_chunks(pixels, C) * (C + 1);
 }
 
 int pat_head_backward(long pixels, int C, const void* act, const void* w, const void* grad_out, void* grad_act,
@@ -1149,7 +1154,7 @@ int pat_head_backward(long pixels, int C, const void* act, const void* w, const 
                                                   static_cast<const float*>(grad_out), static_cast<float*>(grad_act));
     int rc = status("head_bwd_input");
     if (rc) return rc;
-    const int chunks = bn_chunks(pixels);
+    const int chunks = bn_chunks(pixels, C);
     const long rpc = (pixels + chunks - 1) / chunks;
     head_bwd_partial<<<chunks, NT, 0, st>>>(pixels, C, static_cast<const short*>(act),
                                             static_cast<const float*>(grad_out), rpc, static_cast<double*>(partials));
