@@ -2,7 +2,6 @@
 brute force, adjoint identities, finite differences and the parameter count
 the paper states (Sec. 4.2.1)."""
 import numpy as np
-import pytest
 import torch
 import torch.nn.functional as F
 
