@@ -429,6 +429,30 @@ def test_unet_forward_backward_against_the_oracle(lib, cin, B, H, W, shift):
         assert e_x < 1.5 * b_x
 
 
+def test_unet_forward_backward_is_bit_reproducible(lib):
+    """No atomics and fixed summation orders: two runs of the same forward
+    and backward give identical outputs, input gradients, parameter
+    gradients and running statistics."""
+    B, H, W, cin = 2, 64, 32, 2
+    g = torch.Generator().manual_seed(99)
+    planes = [torch.randn((B, H, W), generator=g).to(DEV) for _ in range(cin)]
+    res = torch.randn((B, H, W), generator=g).to(DEV)
+    gout = torch.randn((B, H, W), generator=g).to(DEV)
+    results = []
+    for _ in range(2):
+        blk, params, grads, stats, *_ = _block(lib, cin, B, H, W, seed=5, shift=0.5)
+        for layer in blk.layers():
+            layer.pack(lib, st())
+        out = torch.empty((B, H, W), device=DEV)
+        blk.forward(0, planes, [1.0, 0.8], res, out, st())
+        gpl = [torch.empty((B, H, W), device=DEV) for _ in range(cin)]
+        blk.backward(0, planes, [1.0, 0.8], gout, gpl, [None] * cin, False, st())
+        torch.cuda.synchronize()
+        results.append([out.clone(), grads.clone(), stats.clone()] + [t.clone() for t in gpl])
+    for a, b in zip(*results):
+        assert torch.equal(a, b)
+
+
 # ---- the learned primal-dual reconstructor with U-Nets -------------------------
 
 def _rel(a, b):
