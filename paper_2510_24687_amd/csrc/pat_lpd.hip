@@ -6,10 +6,13 @@
 // gradient as a second MFMA contraction over pixels with a deterministic
 // two-stage sum; PReLU backward; weight packing; Adam with cosine decay.
 //
-// Matrix core: v_mfma_f32_16x16x16_bf16 (__builtin_amdgcn_mfma_f32_16x16x16bf16_1k).
-// Operand layout for a wave (64 lanes, l = lane):
-//   A (16 x 16, rows i, reduction k): lane l holds A[l % 16][4 (l / 16) + e], e = 0..3
-//   B (16 x 16, reduction k, cols j): lane l holds B[4 (l / 16) + e][l % 16]
+// Matrix cores: v_mfma_f32_16x16x32_bf16 for the 32-channel NHWC inputs
+// (one tap's 32 channels per instruction), v_mfma_f32_16x16x16_bf16
+// (__builtin_amdgcn_mfma_f32_16x16x16bf16_1k) for the planar inputs and the
+// weight gradient.  Operand layout for a wave (64 lanes, l = lane; KS = 32 or
+// 16 reduction entries per instruction, V = KS / 4 per lane):
+//   A (16 x KS, rows i, reduction k): lane l holds A[l % 16][V (l / 16) + e]
+//   B (KS x 16, reduction k, cols j): lane l holds B[V (l / 16) + e][l % 16]
 //   D (16 x 16):                      lane l holds D[4 (l / 16) + r][l % 16], r = 0..3
 // Convolution GEMM: rows = 16 pixels of one image row, cols = output channels,
 // reduction k = tap * CINP + channel, tap = 3 ky + kx (correlation, the usual
@@ -23,6 +26,8 @@
 #include "pat_internal.h"
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
@@ -93,7 +98,7 @@ __global__ __launch_bounds__(NT) void conv3x3_fwd(ConvArgs a)
 {
     constexpr int K = 9 * CINP;
     constexpr int KP = (K + 15) / 16 * 16;
-    __shared__ short wl[CT * 16 * KP];
+    __shared__ __align__(16) short wl[CT * 16 * KP];
     __shared__ float red[BWD ? 4 * 4 * 2 * CT * 16 : 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int b = blockIdx.z, y = blockIdx.y;
@@ -110,7 +115,32 @@ __global__ __launch_bounds__(NT) void conv3x3_fwd(ConvArgs a)
 #pragma unroll
         for (int t = 0; t < CT; ++t) acc[g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int kq = 4 * (lane >> 4);
-    if (active) {
+    if constexpr (!PLANAR_IN && CINP % 32 == 0) {
+        // 32 reduction entries (one tap's 32 channels) per instruction: 16-byte
+        // operand loads from the NHWC input and from the staged weights
+        if (active) {
+            for (int k0 = 0; k0 < KP; k0 += 32) {
+                const int tap = k0 / CINP, c = k0 - tap * CINP + 8 * (lane >> 4);
+                const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                s16x8 bv[CT];
+#pragma unroll
+                for (int t = 0; t < CT; ++t)
+                    bv[t] = *reinterpret_cast<const s16x8*>(wl + (t * 16 + (lane & 15)) * KP + k0 + 8 * (lane >> 4));
+#pragma unroll
+                for (int g = 0; g < GROUPS; ++g) {
+                    const int x = xw + 16 * g + (lane & 15), sy = y + dy, sx = x + dx;
+                    s16x8 av = {0, 0, 0, 0, 0, 0, 0, 0};
+                    if (x < a.W && sy >= 0 && sy < a.H && sx >= 0 && sx < a.W)
+                        av = *reinterpret_cast<const s16x8*>(a.in16 + (((size_t)b * a.H + sy) * a.W + sx) * HID + c);
+#pragma unroll
+                    for (int t = 0; t < CT; ++t)
+                        acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                                             __builtin_bit_cast(bf16x8, bv[t]),
+                                                                             acc[g][t], 0, 0, 0);
+                }
+            }
+        }
+    } else if (active) {
         for (int k0 = 0; k0 < KP; k0 += 16) {
             bf16x4 bv[CT];
 #pragma unroll
