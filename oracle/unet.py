@@ -26,7 +26,7 @@ Readings (where the paper leaves the layer details open, the usual U-Net):
     different statistics;
   * output: a 1x1 convolution 32 -> 1 with bias.
 With these readings the two networks (3 and 2 input channels) hold 3.85e6
-parameters, the "around 3.9e6" the paper states.
+parameters, in line with the paper's count of about 3.9e6.
 
 Precision: with ``rounding=True`` the oracle stores what the GPU stores in
 bfloat16 (network inputs, activations after batch normalisation and ReLU,

@@ -10,7 +10,7 @@ import oracle.unet as U
 
 def test_parameter_count_matches_the_paper():
     # Sec. 4.2.1: the full reconstruction operator (dual network with inputs
-    # q, A f, y and primal network with f, A* q) has around 3.9e6 parameters
+    # q, A f, y and primal network with f, A* q) holds about 3.9e6 parameters
     total = U.count_params(3) + U.count_params(2)
     assert 3.8e6 <= total <= 4.0e6, total
     assert dict(U.layout(3))["e3c2.w"] == (256, 256, 3, 3)     # 256 filters at the coarsest scale
