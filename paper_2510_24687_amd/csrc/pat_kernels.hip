@@ -1254,10 +1254,18 @@ __device__ __forceinline__ void spread_tiles_body(const Dev<T>& d, Blk bk, const
     }
 }
 
+// Tiles walk very different sample counts: the rows of tiles next to y = 0
+// (block rows 0 and gridDim.y - 1, the two sides of the periodic grid) hold the
+// densest, smallest rings.  Blocks are therefore dispatched in the row order
+// 0, last, 1, last - 1, ... (hardware order, no XCD remapping), so that the
+// longest walks start first instead of last.
 template <typename T, int W, int BC, bool STAGED>
 __global__ __launch_bounds__(NT) void spread_tiles(Dev<T> d, const cx<T>* Pol, int B, cx<T>* E, size_t ws_img)
 {
-    spread_tiles_body<T, W, BC, STAGED>(d, blk_xcd(), Pol, B, E, ws_img);
+    Blk bk = blk_plain();
+    const int k = bk.y;
+    bk.y = (k & 1) ? (int)gridDim.y - 1 - (k >> 1) : (k >> 1);
+    spread_tiles_body<T, W, BC, STAGED>(d, bk, Pol, B, E, ws_img);
 }
 
 template <typename T>
