@@ -153,3 +153,12 @@ def test_unet_entry_points_validate_on_the_host(lib):
     assert lib.pat_bn_forward(1000, 32, 16, 16, 16, 16, 16, None, None, 0.1, 1e-5, 0, 16, 16, None) == -1
     assert lib.pat_gconv_pack(None, 16, 16, 16, 16, 9, 0, 1, 1, 1, 0, 16, None) == -1
     assert lib.pat_nhwc_pack(10, 5, 16, None, None, 16, None) == -1
+
+
+def test_suite_method_selection():
+    from paper_2510_24687_amd import experiments as X
+    meths = ("inverse", "nnls", "tv", "lpd")
+    assert X.methods_filter(meths, []) == meths
+    assert X.methods_filter(meths, ["lpd"]) == ("lpd",)
+    assert X.methods_filter(("inverse",), ["lpd", "tv"]) == ()
+    assert X.methods_filter(meths, ["tv", "inverse"]) == ("inverse", "tv")   # the scheme's order

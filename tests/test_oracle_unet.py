@@ -146,3 +146,27 @@ def test_unet_shapes_and_inference_mode():
         assert all(float(torch.abs(v["mean"]).sum()) > 0 for v in run.values())
         out_e = U.unet(x, P, "n.", run, training=False, rounding=True)
     assert out_e.shape == out.shape and torch.isfinite(out_e).all()
+
+
+def test_product_layout_matches_the_oracle_layout():
+    """The product's parameter and statistics layouts agree with the oracle's,
+    name by name and shape by shape (the GPU parity tests map parameters
+    between the two by these names)."""
+    from paper_2510_24687_amd import lpd as L
+    from paper_2510_24687_amd import unet as PU
+    for cin in (2, 3):
+        assert PU.layout(cin) == U.layout(cin)
+    assert PU.bn_layers() == U.bn_layers()
+    flat = L.param_layout(arch="unet")
+    assert [n for n, _ in flat] == (["dual." + n for n, _ in U.layout(3)] + ["primal." + n for n, _ in U.layout(2)])
+    assert L.init_params(0, arch="unet").size == U.count_params(3) + U.count_params(2)
+    K = 4
+    stats = PU.stats_layout(K)
+    assert len(stats) == 2 * K * 2 * len(U.bn_layers())
+    init = PU.init_stats(K)
+    o = 0
+    for name, c in stats:
+        want = 0.0 if name.endswith(".mean") else 1.0
+        assert np.all(init[o:o + c] == want), name
+        o += c
+    assert o == init.size
