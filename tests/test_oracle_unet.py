@@ -170,3 +170,100 @@ def test_product_layout_matches_the_oracle_layout():
         assert np.all(init[o:o + c] == want), name
         o += c
     assert o == init.size
+
+
+class _TorchUNet(torch.nn.Module):
+    """The same network assembled from stock torch.nn modules (Conv2d without
+    bias, BatchNorm2d, ReLU, MaxPool2d, ConvTranspose2d without bias, 1x1
+    Conv2d head), written independently of the oracle's functional form."""
+
+    def __init__(self, cin):
+        super().__init__()
+        nn = torch.nn
+
+        def cbr(a, b):
+            return nn.Sequential(nn.Conv2d(a, b, 3, padding=1, bias=False),
+                                 nn.BatchNorm2d(b, eps=1e-5, momentum=0.1), nn.ReLU())
+
+        w = (32, 64, 128, 256)
+        self.enc = nn.ModuleList()
+        c = cin
+        for s in range(4):
+            self.enc.append(nn.Sequential(cbr(c, w[s]), cbr(w[s], w[s])))
+            c = w[s]
+        self.up = nn.ModuleList([nn.ConvTranspose2d(2 * w[s], w[s], 2, stride=2, bias=False) for s in range(3)])
+        self.dec = nn.ModuleList([nn.Sequential(cbr(2 * w[s], w[s]), cbr(w[s], w[s])) for s in range(3)])
+        self.pool = nn.MaxPool2d(2)
+        self.head = nn.Conv2d(w[0], 1, 1)
+
+    def forward(self, x):
+        skips = []
+        for s in range(4):
+            x = self.enc[s](x)
+            if s < 3:
+                skips.append(x)
+                x = self.pool(x)
+        for s in (2, 1, 0):
+            x = self.dec[s](torch.cat([skips[s], self.up[s](x)], dim=1))
+        return self.head(x)
+
+    def named_like_oracle(self):
+        """(oracle parameter name, module tensor) pairs; batch-norm layers as
+        (oracle layer name, BatchNorm2d)."""
+        params, bns = [], []
+        for part, blocks in (("e", self.enc), ("d", self.dec)):
+            for s, blk in enumerate(blocks):
+                for j in (1, 2):
+                    conv, bn = blk[j - 1][0], blk[j - 1][1]
+                    nm = "%s%dc%d" % (part, s, j)
+                    params += [(nm + ".w", conv.weight), (nm + ".g", bn.weight), (nm + ".b", bn.bias)]
+                    bns.append((nm, bn))
+        params += [("u%d.w" % s, self.up[s].weight) for s in range(3)]
+        params += [("head.w", self.head.weight), ("head.b", self.head.bias)]
+        return params, bns
+
+
+def test_unet_matches_a_network_of_stock_torch_modules():
+    """The oracle's U-Net (rounding off) equals the network assembled from
+    torch.nn modules with the same parameters: outputs and every gradient in
+    training mode over two applications (batch statistics, running averages
+    updated each time), then outputs at inference with the running averages.
+    Catches a wrong skip order, a missing or misplaced layer, pooling or
+    up-sampling on the wrong scale, or a running-average mistake."""
+    cin = 3
+    P = _small_params(cin, 8)
+    net = _TorchUNet(cin).double()
+    params, bns = net.named_like_oracle()
+    assert sorted(n for n, _ in params) == sorted(n for n, _ in U.layout(cin))
+    with torch.no_grad():
+        for name, t in params:
+            t.copy_(P["n." + name].detach())
+    run = {"n." + k: v for k, v in U.fresh_running().items()}
+    rng = np.random.default_rng(9)
+    net.train()
+    for step in range(2):
+        x = torch.tensor(rng.standard_normal((2, cin, 16, 8)))
+        r = torch.tensor(rng.standard_normal((2, 1, 16, 8)))
+        xo = x.clone().requires_grad_(True)
+        xt = x.clone().requires_grad_(True)
+        for t in P.values():
+            t.grad = None
+        net.zero_grad()
+        out_o = U.unet(xo, P, "n.", run, training=True, rounding=False)
+        out_t = net(xt)
+        assert torch.max(torch.abs(out_o - out_t)) < 1e-10 * float(torch.max(torch.abs(out_t.detach())))
+        (out_o * r).sum().backward()
+        (out_t * r).sum().backward()
+        assert torch.max(torch.abs(xo.grad - xt.grad)) < 1e-9 * float(torch.max(torch.abs(xt.grad)))
+        for name, t in params:
+            go, gt = P["n." + name].grad, t.grad
+            assert torch.max(torch.abs(go - gt)) <= 1e-9 * float(torch.max(torch.abs(gt))) + 1e-12, (step, name)
+        for name, bn in bns:
+            assert torch.max(torch.abs(run["n." + name]["mean"] - bn.running_mean)) < 1e-12, (step, name)
+            assert torch.max(torch.abs(run["n." + name]["var"] - bn.running_var)) < 1e-12, (step, name)
+    net.eval()
+    x = torch.tensor(rng.standard_normal((3, cin, 8, 16)))
+    with torch.no_grad():
+        out_o = U.unet(x, P, "n.", run, training=False, rounding=False)
+        out_t = net(x)
+    assert torch.max(torch.abs(out_o - out_t)) < 1e-10 * float(torch.max(torch.abs(out_t.detach())))
