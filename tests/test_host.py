@@ -120,6 +120,18 @@ def test_plan_needs_a_gpu_and_says_so():
         pat.Plan(P.full_circle(32, 64, 64))
 
 
+def test_bench_measures_one_gpu_only():
+    """The benchmark runs on one GPU; asked for more it exits with status 2
+    and says why, before touching any device."""
+    import subprocess
+    import sys
+    for n in (2, 8):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)],
+                           capture_output=True, text=True, timeout=120, cwd=ROOT)
+        assert r.returncode == 2, (n, r.returncode, r.stderr)
+        assert "one GPU" in r.stderr and r.stdout == ""
+
+
 def test_gconv_rejects_mixed_channel_packing_without_device_work(lib):
     """Two 16-channel sources total 32 channels, whose weights pack for the
     32-deep instruction; the kernel needs every source to be a multiple of 32,
