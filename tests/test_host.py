@@ -2,6 +2,7 @@
 every symbol the header declares, validates geometries, and its plan logic
 (parameter choices, Bessel recurrence) is sound."""
 import ctypes
+import json
 import math
 import os
 import re
@@ -174,3 +175,28 @@ def test_suite_method_selection():
     assert X.methods_filter(meths, ["lpd"]) == ("lpd",)
     assert X.methods_filter(("inverse",), ["lpd", "tv"]) == ()
     assert X.methods_filter(meths, ["tv", "inverse"]) == ("inverse", "tv")   # the scheme's order
+
+
+def test_bench_byte_model_and_traffic_record():
+    """The benchmark's algorithmic bytes for the cosine transform at n = 512,
+    m = 1024, nt = 1024, batch 16 are the harmonic columns' ring values read
+    and time values written once (complex64), and the committed HBM traffic
+    record is used only for the batch, launch shape and kernel sources it was
+    taken with."""
+    import bench
+    geom = P.full_circle(512, 1024, 1024)
+    info = pat.plan_query(geom)
+    per = bench.stage_bytes(info, 16, geom)
+    assert per["dct_fwd"] == per["dct_adj"] == 16 * 8 * (info["rings"] + 1024) * info["kpad"]
+    assert per["spread_adj"] == 16 * 8 * (info["ring_points"] + info["grid"] * (info["grid"] // 2 + 1 + 2 * ((info["stencil"] + 1) // 2)))
+    assert bench.measured_traffic("dct_fwd", 8) is None                     # other batch
+    z = json.load(open(os.path.join(ROOT, "profiles", "traffic_n512.json")))
+    shapes = dict(z["launch_shapes"])
+    if z["source_hash"] != bench.kernel_source_hash():
+        assert bench.measured_traffic("dct_fwd", 16, shapes) is None
+        pytest.skip("kernel sources changed since the traffic record was taken")
+    t = bench.measured_traffic("dct_fwd", 16, shapes)
+    assert 0.95 * per["dct_fwd"] <= t <= 1.05 * per["dct_fwd"]               # no re-reads
+    shapes["tune_dct_cols_per_block"] += 1
+    assert bench.measured_traffic("dct_fwd", 16, shapes) is None            # other launch shape
+    assert bench.measured_traffic("rows_fwd", 16, shapes) is not None       # shape irrelevant to it
