@@ -17,13 +17,15 @@ SOURCES = [os.path.join(CSRC, "pat_kernels.hip"), os.path.join(CSRC, "pat_solver
            os.path.join(CSRC, "pat_plan.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
+# code-generation flags shared by every source: packed FP32 arithmetic is
+# switched off in the device code
+FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wall", "-Wno-unused-result", "-o", tmp] + SOURCES
+    cmd = [HIPCC] + FLAGS + ["-fPIC", "-shared", "-Wall", "-Wno-unused-result", "-o", tmp] + SOURCES
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -200,3 +200,23 @@ def test_bench_byte_model_and_traffic_record():
     shapes["tune_dct_cols_per_block"] += 1
     assert bench.measured_traffic("dct_fwd", 16, shapes) is None            # other launch shape
     assert bench.measured_traffic("rows_fwd", 16, shapes) is not None       # shape irrelevant to it
+
+
+def test_device_code_has_no_packed_fp32_arithmetic(tmp_path):
+    """Every HIP source, compiled for gfx950 with the library's own flags,
+    contains no packed FP32 add / multiply / fma instruction (the build turns
+    that target feature off; without it the compiler emits them from plain
+    float code)."""
+    import subprocess
+    from paper_2510_24687_amd import build as Bd
+    if not os.path.exists(Bd.HIPCC):
+        pytest.skip("hipcc not installed")
+    packed = re.compile(r"\bv_pk_(fma|mul|add)_f32\b")
+    for src in Bd.SOURCES:
+        if not src.endswith(".hip"):
+            continue
+        out = tmp_path / (os.path.basename(src) + ".s")
+        subprocess.check_call([Bd.HIPCC] + Bd.FLAGS + ["--cuda-device-only", "-S", "-w", "-o", str(out), src],
+                              timeout=900)
+        hits = [ln for ln in open(out) if packed.search(ln)]
+        assert not hits, (src, hits[:3])
