@@ -118,6 +118,8 @@ typedef struct {
                                      0: derive them from four table entries         */
     int tune_spread_staged;       /* 1: the spread stages samples through LDS, 0: it
                                      reads them with scalar loads one ahead         */
+    int tune_dct_wave;            /* 1: the FP32 cosine transform runs one wave per
+                                     column group with compile-time lengths         */
     int tuned;                    /* 0 defaults, 1 measured at creation, 2 cached   */
     double tuned_ms;              /* forward + adjoint ms at max_batch when tuned   */
 } pat_plan_info;
@@ -131,7 +133,8 @@ typedef struct {
  * in that text file (one line per entry, "key | choices"; the last matching
  * line wins); if absent it times the candidate launch shapes (FFT pass radix,
  * twiddle source, columns per transform block, images per ring-gather block
- * and per spread group, spread sample staging) one choice at a time with forward + adjoint at max_batch, keeps the
+ * and per spread group, spread sample staging, the wave-per-column cosine
+ * transform) one choice at a time with forward + adjoint at max_batch, keeps the
  * fastest, and appends a line.  A missing or unreadable file is treated as
  * empty; a line that fails validation is ignored.  The search allocates and
  * frees a temporary workspace.

@@ -23,6 +23,14 @@ as the GPU kernels do: in the forward product (input, weight), in the input
 gradient (output gradient, weight) and in the weight gradient (output
 gradient, input).  Sums are exact-ish (float64).  ``rounding=False`` gives
 the plain FP64 network, whose gradients torch.autograd.gradcheck verifies.
+
+``perturb`` (a Perturb) multiplies every operator output (A f, A* q and
+their transposes in the backward pass) and every convolution product by
+(1 + level * xi), xi i.i.d. N(0,1) from a seeded generator: a model of FP32
+arithmetic noise.  The tests use an ensemble of such runs to measure how far
+FP32-level differences alone move the bf16-rounded network (roundings that
+land on the other side of a midpoint), which sets their tolerance for the
+GPU network; it is never part of the network's definition.
 """
 from __future__ import annotations
 
@@ -39,6 +47,19 @@ from . import forward as _forward_np
 HID = 32
 
 
+class Perturb:
+    """Seeded relative noise for operator outputs (op) and convolution products (conv)."""
+
+    def __init__(self, seed: int, op: float = 1e-6, conv: float = 1e-7):
+        self.gen = torch.Generator().manual_seed(int(seed))
+        self.op, self.conv = float(op), float(conv)
+
+    def apply(self, x: torch.Tensor, level: float) -> torch.Tensor:
+        if level <= 0:
+            return x
+        return x * (1.0 + level * torch.randn(x.shape, generator=self.gen, dtype=torch.float64))
+
+
 def bf16(x: torch.Tensor) -> torch.Tensor:
     """Round float values to bfloat16 (through float32) and return float64."""
     return x.to(torch.float32).to(torch.bfloat16).to(torch.float64)
@@ -48,11 +69,13 @@ class _Conv3x3(torch.autograd.Function):
     """conv2d(x, w, b, padding=1) with bf16-rounded operands in every product."""
 
     @staticmethod
-    def forward(ctx, x, w, b, rounding):
+    def forward(ctx, x, w, b, rounding, perturb):
         xr, wr = (bf16(x), bf16(w)) if rounding else (x, w)
         ctx.save_for_backward(xr, wr)
         ctx.rounding = rounding
-        return F.conv2d(xr, wr, b, padding=1)
+        ctx.perturb = perturb
+        y = F.conv2d(xr, wr, b, padding=1)
+        return perturb.apply(y, perturb.conv) if perturb is not None else y
 
     @staticmethod
     def backward(ctx, gy):
@@ -61,14 +84,17 @@ class _Conv3x3(torch.autograd.Function):
         gx = F.conv_transpose2d(gyr, wr, padding=1)
         gw = torch.nn.grad.conv2d_weight(xr, wr.shape, gyr, padding=1)
         gb = gy.sum(dim=(0, 2, 3))
-        return gx, gw, gb, None
+        pt = ctx.perturb
+        if pt is not None:
+            gx, gw = pt.apply(gx, pt.conv), pt.apply(gw, pt.conv)
+        return gx, gw, gb, None, None
 
 
-def conv3x3(x, w, b=None, rounding=True):
+def conv3x3(x, w, b=None, rounding=True, perturb=None):
     """x: (B, cin, H, W), w: (cout, cin, 3, 3), b: (cout,) or None."""
     if b is None:
         b = torch.zeros(w.shape[0], dtype=x.dtype)
-    return _Conv3x3.apply(x, w, b, rounding)
+    return _Conv3x3.apply(x, w, b, rounding, perturb)
 
 
 def prelu(x, alpha):
@@ -76,57 +102,64 @@ def prelu(x, alpha):
     return torch.where(x > 0, x, alpha.view(1, -1, 1, 1) * x)
 
 
+def _op_noise(x, perturb):
+    return perturb.apply(x, perturb.op) if perturb is not None else x
+
+
 class _A(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, f, geom):
+    def forward(ctx, f, geom, perturb):
         ctx.geom = geom
+        ctx.perturb = perturb
         out = [_forward_np(geom, fi.detach().numpy()) for fi in f]
-        return torch.tensor(np.stack(out), dtype=torch.float64)
+        return _op_noise(torch.tensor(np.stack(out), dtype=torch.float64), perturb)
 
     @staticmethod
     def backward(ctx, g):
         s = adjoint_scale(ctx.geom)
         out = [_adjoint_np(ctx.geom, gi.numpy()) / s for gi in g]
-        return torch.tensor(np.stack(out), dtype=torch.float64), None
+        return _op_noise(torch.tensor(np.stack(out), dtype=torch.float64), ctx.perturb), None, None
 
 
 class _Astar(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, g, geom):
+    def forward(ctx, g, geom, perturb):
         ctx.geom = geom
+        ctx.perturb = perturb
         out = [_adjoint_np(geom, gi.detach().numpy()) for gi in g]
-        return torch.tensor(np.stack(out), dtype=torch.float64)
+        return _op_noise(torch.tensor(np.stack(out), dtype=torch.float64), perturb)
 
     @staticmethod
     def backward(ctx, f):
         s = adjoint_scale(ctx.geom)
         out = [s * _forward_np(ctx.geom, fi.numpy()) for fi in f]
-        return torch.tensor(np.stack(out), dtype=torch.float64), None
+        return _op_noise(torch.tensor(np.stack(out), dtype=torch.float64), ctx.perturb), None, None
 
 
-def block(x, P, net, rounding=True):
+def block(x, P, net, rounding=True, perturb=None):
     """3-layer CNN: conv-PReLU, conv-PReLU, conv.  P: dict of float64 tensors."""
-    h = prelu(conv3x3(x, P[net + ".w1"], P[net + ".b1"], rounding), P[net + ".a1"])
-    h = prelu(conv3x3(h, P[net + ".w2"], P[net + ".b2"], rounding), P[net + ".a2"])
-    return conv3x3(h, P[net + ".w3"], P[net + ".b3"], rounding)
+    h = prelu(conv3x3(x, P[net + ".w1"], P[net + ".b1"], rounding, perturb), P[net + ".a1"])
+    h = prelu(conv3x3(h, P[net + ".w2"], P[net + ".b2"], rounding, perturb), P[net + ".a2"])
+    return conv3x3(h, P[net + ".w3"], P[net + ".b3"], rounding, perturb)
 
 
-def _network(x, P, net, rounding, arch, running, training):
+def _network(x, P, net, rounding, arch, running, training, perturb=None):
     if arch == "unet":
         from .unet import unet
-        return unet(x, P, net + ".", running, training, rounding)
-    return block(x, P, net, rounding)
+        return unet(x, P, net + ".", running, training, rounding, perturb=perturb)
+    return block(x, P, net, rounding, perturb)
 
 
 def reconstruct(geom, P, y, iters, s_A=1.0, s_U=1.0, rounding=True, ops=None, arch="cnn", running=None,
-                training=True):
+                training=True, perturb=None):
     """f_K for data y (B, nt, m).  ``ops`` = (A, A*) callables on batches may
     replace the direct-quadrature operators (used by gradcheck on tiny
     explicit matrices).  ``arch = "unet"``: the U-Nets of oracle/unet.py with
     running statistics ``running[k]`` for unrolled iteration k (keys
     "dual.<layer>", "primal.<layer>"; batch statistics and updated averages
     in training, the averages otherwise)."""
-    A, As = ops if ops is not None else ((lambda f: _A.apply(f, geom)), (lambda g: _Astar.apply(g, geom)))
+    A, As = ops if ops is not None else ((lambda f: _A.apply(f, geom, perturb)),
+                                         (lambda g: _Astar.apply(g, geom, perturb)))
     B = y.shape[0]
     n = geom["n"]
     q = torch.zeros_like(y)
@@ -135,18 +168,20 @@ def reconstruct(geom, P, y, iters, s_A=1.0, s_U=1.0, rounding=True, ops=None, ar
         Af = A(f)
         run_k = None if running is None else running[k]
         q = q + _network(torch.stack([q, s_A * Af, s_A * y], dim=1), P, "dual", rounding, arch, run_k,
-                         training)[:, 0]
+                         training, perturb)[:, 0]
         u = As(q)
-        f = f + _network(torch.stack([f, s_U * u], dim=1), P, "primal", rounding, arch, run_k, training)[:, 0]
+        f = f + _network(torch.stack([f, s_U * u], dim=1), P, "primal", rounding, arch, run_k, training,
+                         perturb)[:, 0]
     return f
 
 
-def loss_and_grads(geom, P, y, target, iters, s_A=1.0, s_U=1.0, rounding=True, arch="cnn", running=None):
+def loss_and_grads(geom, P, y, target, iters, s_A=1.0, s_U=1.0, rounding=True, arch="cnn", running=None,
+                   perturb=None):
     """mean((f_K - target)^2) and its gradient with respect to every parameter."""
     Pt = {k: torch.tensor(np.asarray(v, dtype=np.float64), requires_grad=True) for k, v in P.items()}
     yt = torch.tensor(np.asarray(y, dtype=np.float64))
     tt = torch.tensor(np.asarray(target, dtype=np.float64))
-    fK = reconstruct(geom, Pt, yt, iters, s_A, s_U, rounding, arch=arch, running=running)
+    fK = reconstruct(geom, Pt, yt, iters, s_A, s_U, rounding, arch=arch, running=running, perturb=perturb)
     loss = torch.mean((fK - tt) ** 2)
     loss.backward()
     return float(loss.detach()), fK.detach().numpy(), {k: v.grad.numpy() for k, v in Pt.items()}

@@ -123,11 +123,13 @@ class _TConv2(torch.autograd.Function):
     in every product when rounding."""
 
     @staticmethod
-    def forward(ctx, x, w, rounding):
+    def forward(ctx, x, w, rounding, perturb):
         xr, wr = (bf16(x), bf16(w)) if rounding else (x, w)
         ctx.save_for_backward(xr, wr)
         ctx.rounding = rounding
-        return F.conv_transpose2d(xr, wr, stride=2)
+        ctx.perturb = perturb
+        y = F.conv_transpose2d(xr, wr, stride=2)
+        return perturb.apply(y, perturb.conv) if perturb is not None else y
 
     @staticmethod
     def backward(ctx, gy):
@@ -137,11 +139,14 @@ class _TConv2(torch.autograd.Function):
         gx = F.conv2d(gyr, wr, stride=2)
         g6 = gyr.reshape(B, Co, H2 // 2, 2, W2 // 2, 2)
         gw = torch.einsum("bchw,bdhiwj->cdij", xr, g6)
-        return gx, gw, None
+        pt = ctx.perturb
+        if pt is not None:
+            gx, gw = pt.apply(gx, pt.conv), pt.apply(gw, pt.conv)
+        return gx, gw, None, None
 
 
-def tconv2(x, w, rounding=True):
-    return _TConv2.apply(x, w, rounding)
+def tconv2(x, w, rounding=True, perturb=None):
+    return _TConv2.apply(x, w, rounding, perturb)
 
 
 def stored_bf16(x):
@@ -149,14 +154,16 @@ def stored_bf16(x):
     return x + (bf16(x.detach()) - x.detach())
 
 
-def unet(x, P: dict, prefix: str, running: Optional[dict] = None, training: bool = True, rounding: bool = True):
+def unet(x, P: dict, prefix: str, running: Optional[dict] = None, training: bool = True, rounding: bool = True,
+         perturb=None):
     """The U-Net on x (B, cin, H, W), H and W divisible by 8; parameters
     P[prefix + name] (float64 tensors); running statistics
-    running[prefix + layer] (updated in training).  Returns (B, 1, H, W)."""
+    running[prefix + layer] (updated in training).  Returns (B, 1, H, W).
+    ``perturb``: the FP32 noise model of oracle/lpd.py (tests only)."""
     store = stored_bf16 if rounding else (lambda t: t)
 
     def cbr(name, h):
-        z = conv3x3(h, P[prefix + name + ".w"], None, rounding)
+        z = conv3x3(h, P[prefix + name + ".w"], None, rounding, perturb)
         r = None if running is None else running[prefix + name]
         return store(batch_norm_relu(z, P[prefix + name + ".g"], P[prefix + name + ".b"], r, training))
 
@@ -168,7 +175,7 @@ def unet(x, P: dict, prefix: str, running: Optional[dict] = None, training: bool
             skips.append(h)
             h = maxpool2(h)
     for s in (2, 1, 0):
-        up = store(tconv2(h, P[prefix + "u%d.w" % s], rounding))
+        up = store(tconv2(h, P[prefix + "u%d.w" % s], rounding, perturb))
         h = torch.cat([skips[s], up], dim=1)
         h = cbr("d%dc2" % s, cbr("d%dc1" % s, h))
     return F.conv2d(h, P[prefix + "head.w"], P[prefix + "head.b"])

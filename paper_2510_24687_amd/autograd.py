@@ -15,6 +15,10 @@ import torch
 from .pat import Plan
 
 
+# Each backward applies the opposite operator through its own Function, so the
+# backward pass is itself differentiable: under create_graph=True the second
+# derivative of a loss through A is built from A and A^T again (the operators
+# are linear, so that is exact), not silently zero.
 class _Forward(torch.autograd.Function):
     @staticmethod
     def forward(ctx, f, plan):
@@ -23,7 +27,7 @@ class _Forward(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_g):
-        return ctx.plan.transpose(grad_g.contiguous()), None
+        return _Transpose.apply(grad_g, ctx.plan), None
 
 
 class _Transpose(torch.autograd.Function):
@@ -34,7 +38,21 @@ class _Transpose(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_f):
-        return ctx.plan.forward(grad_f.contiguous()), None
+        return _Forward.apply(grad_f, ctx.plan), None
+
+
+class _ScaledForward(torch.autograd.Function):
+    """s A f with s the plan's adjoint scale (the transpose of A* = s A^T)."""
+
+    @staticmethod
+    def forward(ctx, f, plan):
+        ctx.plan = plan
+        out = plan.forward(f.contiguous())
+        return plan.scale_(out, plan.adjoint_scale)
+
+    @staticmethod
+    def backward(ctx, grad_g):
+        return _Adjoint.apply(grad_g, ctx.plan), None
 
 
 class _Adjoint(torch.autograd.Function):
@@ -45,8 +63,7 @@ class _Adjoint(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_f):
-        out = ctx.plan.forward(grad_f.contiguous())
-        return ctx.plan.scale_(out, ctx.plan.adjoint_scale), None
+        return _ScaledForward.apply(grad_f, ctx.plan), None
 
 
 def forward(f: torch.Tensor, plan: Plan) -> torch.Tensor:

@@ -377,6 +377,9 @@ struct Dev {
     int colsLCW, dctLCW;        // log2 of the two (powers of two)
     int dct_stash;              // 1: the cosine transform stashes its input columns in LDS
     int dct_one;                // 1: the cosine transform uses one M-point FFT per column (dct_cos_body)
+    int dct_wave;               // FP32 cosine transform with one wave per column group: variant
+                                // (M3 << 8) | log2 of M's power-of-two factor; 0: not used
+    int dwCB;                   // columns per block of dct_wave
     int fft_lr;                 // largest FFT pass radix is 2^fft_lr (3 or 4)
     int tw_table;               // 1: FFT passes read every twiddle from the table
     T beta, shift, half;        // half = Ng / (2 Lambda): grid cells per unit lambda
@@ -872,6 +875,300 @@ __global__ __launch_bounds__(NT) void dct_cols(Dev<T> d, const cx<T>* in, cx<T>*
 {
     if (d.sine || !d.dct_one) dct_cols_body<T>(d, blk_xcd(), in, out, ws_img, adjoint);
     else dct_cos_body<T>(d, blk_xcd(), in, out, ws_img, adjoint);
+}
+
+// ---------------------------------------------------------------------------
+// Cosine transform, FP32, one wave per column group, lengths fixed at compile
+// time.  The same sums as dct_cos_body (the DCT-I of each column's real and
+// imaginary parts by ONE M-point FFT, the odd outputs as a prefix sum), laid
+// out for a 64-lane wave:
+//   * a block of DW_WAVES waves owns DW_WAVES * NC adjacent columns (NC columns
+//     per wave when M is short, so that every wave transforms WPTS = NC * M
+//     points); it loads their input rows into LDS with row-segment loads and
+//     writes the output rows back the same way, so HBM sees contiguous
+//     segments of all the block's columns at once;
+//   * each wave then works on its own columns with wave-level ordering only:
+//     the pre-processing g_j, the Stockham passes (radix 8, a radix-4 or -2
+//     remainder, then radix 3 for M = 3 * 2^a) with the butterfly counts and
+//     strides known at compile time, and the post-processing, whose prefix
+//     sum is a per-lane serial chunk plus a fixed-order wave scan of the
+//     chunk totals;
+//   * column buffers are padded by one entry in eight, which keeps the
+//     early passes' scattered writes (stride 8 entries) on distinct banks.
+// ---------------------------------------------------------------------------
+constexpr int DW_WAVES = 4;  // waves per block (NT / 64)
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ constexpr int dw_phys(int i) { return i + (i >> 3); }
+
+template <int M3, int LOGP>
+struct DwShape {
+    static constexpr int M = (M3 ? 3 : 1) << LOGP;
+    static constexpr int WPTS = M3 ? (M >= 1536 ? M : 1536) : (M >= 1024 ? M : 1024);
+    static constexpr int NC = WPTS / M;                       // columns per wave
+    static constexpr int CB = NC * DW_WAVES;                  // columns per block
+    static constexpr int CP = dw_phys(M) + 2;                 // column pitch in LDS (slots 0..M, padded)
+    static constexpr int PER = WPTS / 64;                     // points per lane
+    static constexpr size_t LDS = sizeof(cx<float>) * (size_t)CB * CP;
+};
+
+template <bool INV>
+__device__ __forceinline__ void dft3_f(cx<float>& a0, cx<float>& a1, cx<float>& a2)
+{
+    const float h3 = 0.86602540378443864676f;
+    const cx<float> sm = a1 + a2, df = a1 - a2;
+    const cx<float> m = {a0.x - 0.5f * sm.x, a0.y - 0.5f * sm.y};
+    const cx<float> jd = INV ? cx<float>{-h3 * df.y, h3 * df.x} : cx<float>{h3 * df.y, -h3 * df.x};
+    a0 = a0 + sm;
+    a1 = m + jd;
+    a2 = m - jd;
+}
+
+// One Stockham pass over the wave's NC sequences of length M (radix R,
+// sub-transform length NS), inverse direction (e^{+2 pi i ...}), in place:
+// every lane reads all its inputs before any lane writes.  twd holds
+// e^{-2 pi i j / (2M)}.
+template <int M, int NC, int CP, int R, int NS>
+__device__ __forceinline__ void dw_pass(PAT_LDS cx<float>* buf, const PAT_GLOBAL cx<float>* __restrict__ twd, int lane)
+{
+    constexpr int NBS = M / R;               // butterflies per sequence
+    constexpr int PER = NC * NBS / 64;       // butterflies per lane
+    static_assert(NC * NBS % 64 == 0, "butterflies must fill the wave");
+    cx<float> v[PER][R];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = lane + 64 * u;
+        const int b = t / NBS, tt = t - b * NBS;
+        const PAT_LDS cx<float>* s = buf + b * CP;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[u][r] = ld_lds(s + dw_phys(tt + r * NBS));
+    }
+    wave_sync();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = lane + 64 * u;
+        const int b = t / NBS, tt = t - b * NBS;
+        const int k = tt % NS;
+        if constexpr (NS > 1) {
+            constexpr int STEP = 2 * M / (R * NS);   // W_{R NS}^{r k} = twd[r k STEP] (conjugated: inverse)
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cx<float> w = ld_glb(twd + r * k * STEP);
+                w.y = -w.y;
+                v[u][r] = cmul(v[u][r], w);
+            }
+        }
+        if constexpr (R == 3) dft3_f<true>(v[u][0], v[u][1], v[u][2]);
+        else dft_reg<float, R>(v[u], true);
+        PAT_LDS cx<float>* s = buf + b * CP;
+        const int base = (tt / NS) * NS * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) st_lds(s + dw_phys(base + r * NS), v[u][r]);
+    }
+    wave_sync();
+}
+
+// radix of pass p of the power-of-two factor 2^LOGP: radix 8 while at least
+// three bits remain, then 4 or 2
+__host__ __device__ constexpr int dw_radix(int LOGP, int p)
+{
+    return (LOGP - 3 * p >= 3) ? 8 : (LOGP - 3 * p == 2 ? 4 : 2);
+}
+__host__ __device__ constexpr int dw_npass(int LOGP) { return LOGP / 3 + (LOGP % 3 ? 1 : 0); }
+__host__ __device__ constexpr int dw_ns(int LOGP, int p) { return p == 0 ? 1 : dw_ns(LOGP, p - 1) * dw_radix(LOGP, p - 1); }
+
+template <int M, int NC, int CP, int LOGP, int P>
+__device__ __forceinline__ void dw_pow2_passes(PAT_LDS cx<float>* buf, const PAT_GLOBAL cx<float>* twd, int lane)
+{
+    if constexpr (P < dw_npass(LOGP)) {
+        dw_pass<M, NC, CP, dw_radix(LOGP, P), dw_ns(LOGP, P)>(buf, twd, lane);
+        dw_pow2_passes<M, NC, CP, LOGP, P + 1>(buf, twd, lane);
+    }
+}
+
+// Fixed-order sum over the 64 lanes (butterfly); every lane gets the total.
+__device__ __forceinline__ cx<float> wave_sum(cx<float> v)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        v.x += __shfl_xor(v.x, o, 64);
+        v.y += __shfl_xor(v.y, o, 64);
+    }
+    return v;
+}
+
+// Exclusive prefix over the 64 lanes in lane order (Hillis-Steele; fixed order).
+__device__ __forceinline__ cx<float> wave_excl_scan(cx<float> v, int lane)
+{
+    cx<float> s = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const float ux = __shfl_up(s.x, o, 64), uy = __shfl_up(s.y, o, 64);
+        if (lane >= o) { s.x += ux; s.y += uy; }
+    }
+    return s - v;
+}
+
+// Column block: forward (adjoint = 0) in = V [L][Kp] -> out = G [nt][Kp],
+// out row j holds y = j + 1; adjoint in = G (x = j + 1) -> out = V, row y.
+template <int M3, int LOGP>
+__device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const cx<float>* in, cx<float>* out,
+                                              size_t ws_img, int adjoint)
+{
+    using S = DwShape<M3, LOGP>;
+    constexpr int M = S::M, NC = S::NC, CB = S::CB, CP = S::CP;
+    extern __shared__ unsigned char smem_raw[];
+    PAT_LDS cx<float>* lbuf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw);
+    const PAT_GLOBAL cx<float>* twd = (const PAT_GLOBAL cx<float>*)d.twd;
+    const int k0 = bk.x * CB, b = bk.y;
+    const cx<float>* ib = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(in) + (size_t)b * ws_img);
+    cx<float>* ob = reinterpret_cast<cx<float>*>(reinterpret_cast<char*>(out) + (size_t)b * ws_img);
+    const int x_lo = adjoint ? 1 : 0, x_hi = adjoint ? d.nt + 1 : d.L;   // f_x = in row x - x_lo
+    const int nx = x_hi - x_lo;
+    const int nout = adjoint ? d.L : d.nt;
+    const int y0 = adjoint ? 0 : 1, ymax = adjoint ? d.L - 1 : d.nt;
+    const int Kp = d.Kp;
+    // (1) block: input rows of the CB columns -> column buffers, slots x = 0..M
+    for (int i = threadIdx.x; i < CB * nx; i += NT) {
+        const int row = i / CB, c = i - row * CB;
+        st_lds(lbuf + c * CP + dw_phys(row + x_lo), ld_glb((const PAT_GLOBAL cx<float>*)(ib + (size_t)row * Kp + k0 + c)));
+    }
+    const int nzero = x_lo + (M + 1 - x_hi);   // slots [0, x_lo) and [x_hi, M]
+    for (int i = threadIdx.x; i < CB * nzero; i += NT) {
+        const int z = i / CB, c = i - z * CB;
+        const int x = z < x_lo ? z : x_hi + (z - x_lo);
+        st_lds(lbuf + c * CP + dw_phys(x), cx<float>{0.f, 0.f});
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    PAT_LDS cx<float>* wb = lbuf + wave * NC * CP;
+    // (2) per column: F_1's interior sum and g_j = (f_j + f_{M-j})/2 - sin(pi j/M) (f_j - f_{M-j})
+    cx<float> F1[NC], e0[NC], eM[NC];
+    {
+        constexpr int PJ = M / 64;
+        static_assert(M % 64 == 0, "M must be a multiple of 64");
+        cx<float> gv[NC][PJ];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const PAT_LDS cx<float>* col = wb + c * CP;
+            e0[c] = ld_lds(col);
+            eM[c] = ld_lds(col + dw_phys(M));
+            cx<float> acc = {0.f, 0.f};
+#pragma unroll
+            for (int v = 0; v < PJ; ++v) {
+                const int j = lane + 64 * v;
+                const cx<float> fj = ld_lds(col + dw_phys(j));
+                const cx<float> fm = ld_lds(col + dw_phys(M - j));
+                const cx<float> w = ld_glb(twd + j);      // (cos(pi j/M), -sin(pi j/M))
+                acc = acc + fj * w.x;
+                const float sj = -w.y;
+                gv[c][v] = {0.5f * (fj.x + fm.x) - sj * (fj.x - fm.x), 0.5f * (fj.y + fm.y) - sj * (fj.y - fm.y)};
+            }
+            acc = wave_sum(acc);
+            // sum over x = 0..M-1 of f_x cos(pi x/M) minus f_0, plus (f_0 - f_M)/2
+            F1[c] = {acc.x - 0.5f * (e0[c].x + eM[c].x), acc.y - 0.5f * (e0[c].y + eM[c].y)};
+        }
+        wave_sync();
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int v = 0; v < PJ; ++v) st_lds(wb + c * CP + dw_phys(lane + 64 * v), gv[c][v]);
+        wave_sync();
+    }
+    // (3) G_q = sum_j g_j e^{2 pi i j q/M}
+    dw_pow2_passes<M, NC, CP, LOGP, 0>(wb, twd, lane);
+    if constexpr (M3) dw_pass<M, NC, CP, 3, (1 << LOGP)>(wb, twd, lane);
+    // (4) outputs: lane l owns q = CH l + 1 .. CH (l + 1): F_{2q} = (G_q + G_{M-q})/2,
+    // F_{2q+1} = F_1 + S_q, S_q = sum_{p=1..q} -(i/2)(G_p - G_{M-p});
+    // out(y) = F_y + (f_0 + (-1)^y f_M)/2, written to slot y - y0
+    const int Q = (ymax + 1) >> 1;             // q needed: even y = 2q <= ymax, odd y = 2q + 1 <= ymax
+    constexpr int CHMAX = (M / 2 + 63) / 64;   // Q <= M/2
+    const int CH = (Q + 63) >> 6;
+    cx<float> outv[NC][CHMAX][2];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const PAT_LDS cx<float>* col = wb + c * CP;
+        cx<float> run = {0.f, 0.f};
+        cx<float> pre[CHMAX];
+#pragma unroll
+        for (int i = 0; i < CHMAX; ++i) {
+            const int q = lane * CH + 1 + i;
+            cx<float> ev = {0.f, 0.f};
+            if (i < CH && q <= M / 2) {
+                const cx<float> gq = ld_lds(col + dw_phys(q)), gm = ld_lds(col + dw_phys(M - q));
+                run = run + cx<float>{0.5f * (gq.y - gm.y), -0.5f * (gq.x - gm.x)};
+                ev = (gq + gm) * 0.5f;
+            }
+            pre[i] = run;
+            outv[c][i][0] = ev;
+        }
+        const cx<float> off = wave_excl_scan(run, lane);
+        const float hx0 = 0.5f * e0[c].x, hy0 = 0.5f * e0[c].y, hxM = 0.5f * eM[c].x, hyM = 0.5f * eM[c].y;
+#pragma unroll
+        for (int i = 0; i < CHMAX; ++i) {
+            const cx<float> S = off + pre[i];
+            // y = 2q (even) and y = 2q + 1 (odd)
+            outv[c][i][0] = {outv[c][i][0].x + hx0 + hxM, outv[c][i][0].y + hy0 + hyM};
+            outv[c][i][1] = {F1[c].x + S.x + hx0 - hxM, F1[c].y + S.y + hy0 - hyM};
+        }
+    }
+    cx<float> G0[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) G0[c] = ld_lds(wb + c * CP);
+    wave_sync();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        PAT_LDS cx<float>* col = wb + c * CP;
+#pragma unroll
+        for (int i = 0; i < CHMAX; ++i) {
+            const int q = lane * CH + 1 + i;
+            if (i < CH) {
+                const int ye = 2 * q, yo = 2 * q + 1;
+                if (ye <= ymax) st_lds(col + dw_phys(ye - y0), outv[c][i][0]);
+                if (yo <= ymax) st_lds(col + dw_phys(yo - y0), outv[c][i][1]);
+            }
+        }
+        if (lane == 0) {
+            // y = 1: F_1 + (f_0 - f_M)/2; y = 0 (adjoint only): G_0 + (f_0 + f_M)/2
+            st_lds(col + dw_phys(1 - y0), cx<float>{F1[c].x + 0.5f * (e0[c].x - eM[c].x), F1[c].y + 0.5f * (e0[c].y - eM[c].y)});
+            if (y0 == 0) st_lds(col, cx<float>{G0[c].x + 0.5f * (e0[c].x + eM[c].x), G0[c].y + 0.5f * (e0[c].y + eM[c].y)});
+        }
+    }
+    __syncthreads();
+    // (5) block: output rows of the CB columns
+    for (int i = threadIdx.x; i < CB * nout; i += NT) {
+        const int row = i / CB, c = i - row * CB;
+        const cx<float> v = ld_lds(lbuf + c * CP + dw_phys(row));
+        ob[(size_t)row * Kp + k0 + c] = v;
+    }
+}
+
+template <int M3, int LOGP>
+__global__ __launch_bounds__(NT) void dct_wave(Dev<float> d, const cx<float>* in, cx<float>* out, size_t ws_img,
+                                               int adjoint)
+{
+    dct_wave_body<M3, LOGP>(d, blk_xcd(), in, out, ws_img, adjoint);
+}
+
+// variant code of dct_wave: (M3 << 8) | LOGP, 0 = none
+#define PAT_DW_VARIANTS(X) X(1, 7) X(1, 8) X(1, 9) X(0, 8) X(0, 9) X(0, 10)
+
+__device__ __forceinline__ void dct_wave_dispatch(const Dev<float>& d, Blk bk, const cx<float>* in, cx<float>* out,
+                                                  size_t ws_img, int adjoint)
+{
+    switch (d.dct_wave) {
+#define PAT_DW_CASE(a, b) \
+    case ((a) << 8) | (b): dct_wave_body<a, b>(d, bk, in, out, ws_img, adjoint); break;
+        PAT_DW_VARIANTS(PAT_DW_CASE)
+#undef PAT_DW_CASE
+        default: break;
+    }
 }
 
 // G_k(t_j) += i^k sum_l Mk[k][j][l] Ulow[l][k], k = 0..klow
@@ -1487,6 +1784,7 @@ struct pat_plan_s {
     Dev<double> dd{};
     // launch-shape choices (defaults from LDS limits; replaced by the autotuner's)
     int cols_cw = 1, dct_cw = 1, ring_g = 1, spread_bc = 16, fft_lr = 4, tw_table = 0, spread_staged = 1;
+    int dct_wave_on = 1;                  // 1: use dct_wave where the plan's lengths allow it
     int tuned = 0;                        // 1: measured now, 2: read from the tuning cache
     double tuned_ms = 0.0;
     // optional per-stage timing with HIP events recorded on the launch stream
@@ -1563,6 +1861,68 @@ int dct_one_ok(const pat::Params& P, int cw)
     return (size_t)cw * ((size_t)P.M + P.M / 2 + 1) * cs <= dct_budget(P) ? 1 : 0;
 }
 
+int ilog2i(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+// dct_wave variant for the plan's cosine-transform length (FP32; M = 384, 768,
+// 1536 or 256 .. 1024; the forward input rows must fit the M + 1 slots), 0 if none
+int dw_variant(const pat::Params& P)
+{
+    if (P.dt != PAT_F32 || P.L > P.M + 1 || P.nt > P.M) return 0;
+    const int m3 = P.m3 ? 1 : 0;
+    const int logp = ilog2i(m3 ? P.M / 3 : P.M);
+    const int code = (m3 << 8) | logp;
+    switch (code) {
+#define PAT_DW_OK(a, b) case ((a) << 8) | (b):
+        PAT_DW_VARIANTS(PAT_DW_OK)
+#undef PAT_DW_OK
+            break;
+        default: return 0;
+    }
+    return code;
+}
+
+// columns per block and dynamic LDS bytes of a dct_wave variant
+int dw_columns(int code)
+{
+    switch (code) {
+#define PAT_DW_CB(a, b) \
+    case ((a) << 8) | (b): return DwShape<a, b>::CB;
+        PAT_DW_VARIANTS(PAT_DW_CB)
+#undef PAT_DW_CB
+        default: return 1;
+    }
+}
+size_t dw_lds(int code)
+{
+    switch (code) {
+#define PAT_DW_LDS(a, b) \
+    case ((a) << 8) | (b): return DwShape<a, b>::LDS;
+        PAT_DW_VARIANTS(PAT_DW_LDS)
+#undef PAT_DW_LDS
+        default: return 0;
+    }
+}
+
+int launch_dct_wave(const Dev<float>& d, int B, const cx<float>* in, cx<float>* out, size_t wi, int adjoint,
+                    hipStream_t st)
+{
+    switch (d.dct_wave) {
+#define PAT_DW_LAUNCH(a, b) \
+    case ((a) << 8) | (b): \
+        dct_wave<a, b><<<dim3(d.Kp / DwShape<a, b>::CB, B), NT, DwShape<a, b>::LDS, st>>>(d, in, out, wi, adjoint); \
+        break;
+        PAT_DW_VARIANTS(PAT_DW_LAUNCH)
+#undef PAT_DW_LAUNCH
+        default: return PAT_EINVAL;
+    }
+    return PAT_OK;
+}
+
 size_t dct_base(const pat::Params& P, int cw)
 {
     return (size_t)P.M + (dct_one_ok(P, cw) ? (size_t)(P.M / 2 + 1) : 0);
@@ -1590,13 +1950,6 @@ int lds_dct(const pat::Params& P)
     int cw = 16;
     while (cw > 1 && ((size_t)cw * P.M * cs > 65536 || cw * P.M > fft_points(P))) cw >>= 1;
     return cw;
-}
-
-int ilog2i(int v)
-{
-    int l = 0;
-    while ((1 << l) < v) ++l;
-    return l;
 }
 
 template <typename T>
@@ -1670,6 +2023,8 @@ int upload(pat_plan_s* p, Dev<T>& d)
     d.dctLCW = ilog2i(p->dct_cw);
     d.dct_stash = dct_stash_ok(P, p->dct_cw);
     d.dct_one = dct_one_ok(P, p->dct_cw);
+    d.dct_wave = p->dct_wave_on ? dw_variant(P) : 0;
+    d.dwCB = dw_columns(d.dct_wave);
     d.fft_lr = p->fft_lr;
     d.tw_table = p->tw_table;
     d.phase_k = (T)(-P.shift * P.h / (0.5 * P.Ng / P.Lam));
@@ -1760,7 +2115,15 @@ int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g
     if ((rc = check_launch("ring_fwd"))) return rc;
     {
         StageTimer tm(p, st, 3);
-        dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, dct_lds(p->H.P, d.dctCW), st>>>(d, V, G, wi, 0);
+        if constexpr (sizeof(T) == 4) {
+            if (d.dct_wave && !d.sine) {
+                if ((rc = launch_dct_wave(d, B, V, G, wi, 0, st))) return fail(rc, "dct_fwd: no dct_wave variant");
+            } else {
+                dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, dct_lds(p->H.P, d.dctCW), st>>>(d, V, G, wi, 0);
+            }
+        } else {
+            dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, dct_lds(p->H.P, d.dctCW), st>>>(d, V, G, wi, 0);
+        }
     }
     if ((rc = check_launch("dct_fwd"))) return rc;
     {
@@ -1800,7 +2163,15 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
     if ((rc = check_launch("lowk_adj"))) return rc;
     {
         StageTimer tm(p, st, 8);
-        dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, dct_lds(p->H.P, d.dctCW), st>>>(d, G, V, wi, 1);
+        if constexpr (sizeof(T) == 4) {
+            if (d.dct_wave && !d.sine) {
+                if ((rc = launch_dct_wave(d, B, G, V, wi, 1, st))) return fail(rc, "dct_adj: no dct_wave variant");
+            } else {
+                dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, dct_lds(p->H.P, d.dctCW), st>>>(d, G, V, wi, 1);
+            }
+        } else {
+            dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, dct_lds(p->H.P, d.dctCW), st>>>(d, G, V, wi, 1);
+        }
     }
     if ((rc = check_launch("dct_adj"))) return rc;
     {
@@ -1897,7 +2268,7 @@ __host__ __device__ inline void stage_grid(const Dev<T>& d, int S, int B, int G,
         case PAT_STAGE_COLS_ADJ: nx = (d.Rw + d.colsCW - 1) / d.colsCW; ny = B; break;
         case PAT_STAGE_RING_FWD: nx = d.L; ny = (B + G - 1) / G; break;
         case PAT_STAGE_DCT_FWD:
-        case PAT_STAGE_DCT_ADJ: nx = (d.Kp + d.dctCW - 1) / d.dctCW; ny = B; break;
+        case PAT_STAGE_DCT_ADJ: nx = d.dct_wave ? d.Kp / d.dwCB : (d.Kp + d.dctCW - 1) / d.dctCW; ny = B; break;
         case PAT_STAGE_LOWK_FWD: nx = (d.nt * (d.klow + 1) + NT - 1) / NT; ny = B; break;
         case PAT_STAGE_SYNTH_FWD:
         case PAT_STAGE_SYNTH_ADJ: nx = (d.nt + 1) / 2; ny = B; break;
@@ -1939,6 +2310,9 @@ __global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
     if constexpr (S == PAT_STAGE_COLS_FWD) cols_fwd_body<T>(q.d, bk, R, E, q.wi);
     if constexpr (S == PAT_STAGE_RING_FWD) ring_fwd_body<T, WMAX>(q.d, bk, E, V, U, q.wi, q.B, q.G);
     if constexpr (S == PAT_STAGE_DCT_FWD) {
+        if constexpr (sizeof(T) == 4) {
+            if (q.d.dct_wave) { dct_wave_dispatch(q.d, bk, V, Gh, q.wi, 0); return; }
+        }
         if (q.d.dct_one) dct_cos_body<T>(q.d, bk, V, Gh, q.wi, 0);
         else dct_cols_body<T>(q.d, bk, V, Gh, q.wi, 0);
     }
@@ -1947,6 +2321,9 @@ __global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
     if constexpr (S == PAT_STAGE_SYNTH_ADJ) synth_adj_body<T>(q.d, bk, q.gin, q.gs, Gh, q.wi);
     if constexpr (S == PAT_STAGE_LOWK_ADJ) lowk_adj_body<T>(q.d, bk, Gh, U, q.wi);
     if constexpr (S == PAT_STAGE_DCT_ADJ) {
+        if constexpr (sizeof(T) == 4) {
+            if (q.d.dct_wave) { dct_wave_dispatch(q.d, bk, Gh, V, q.wi, 1); return; }
+        }
         if (q.d.dct_one) dct_cos_body<T>(q.d, bk, Gh, V, q.wi, 1);
         else dct_cols_body<T>(q.d, bk, Gh, V, q.wi, 1);
     }
@@ -1974,7 +2351,7 @@ size_t stage_lds(const pat_plan_s* p, int S, int G)
         case PAT_STAGE_COLS_ADJ: return cs * P.Ng * p->cols_cw;
         case PAT_STAGE_RING_FWD: return cs * G * P.max_ring;
         case PAT_STAGE_DCT_FWD:
-        case PAT_STAGE_DCT_ADJ: return dct_lds(P, p->dct_cw);
+        case PAT_STAGE_DCT_ADJ: return p->df.dct_wave ? dw_lds(p->df.dct_wave) : dct_lds(P, p->dct_cw);
         case PAT_STAGE_SYNTH_FWD: return cs * 2 * P.mf;
         case PAT_STAGE_SYNTH_ADJ: return cs * P.mf;
         case PAT_STAGE_RING_ADJ: return cs * G * P.max_ring;
@@ -2069,6 +2446,7 @@ void default_tune(pat_plan_s* p)
     p->fft_lr = 4;
     p->tw_table = 0;
     p->spread_staged = 1;
+    p->dct_wave_on = 1;
 }
 
 void apply_tune(pat_plan_s* p)
@@ -2081,6 +2459,8 @@ void apply_tune(pat_plan_s* p)
     p->df.tw_table = p->dd.tw_table = p->tw_table;
     p->df.dct_stash = p->dd.dct_stash = dct_stash_ok(p->H.P, p->dct_cw);
     p->df.dct_one = p->dd.dct_one = dct_one_ok(p->H.P, p->dct_cw);
+    p->df.dct_wave = p->dd.dct_wave = p->dct_wave_on ? dw_variant(p->H.P) : 0;
+    p->df.dwCB = p->dd.dwCB = dw_columns(p->df.dct_wave);
 }
 
 bool pow2_in(int v, int hi) { return v >= 1 && v <= hi && (v & (v - 1)) == 0; }
@@ -2091,7 +2471,8 @@ bool tune_valid(const pat_plan_s* p)
     const int bcl = (P.dt == PAT_F64) ? 8 : 16;
     return pow2_in(p->cols_cw, lds_cols(P)) && pow2_in(p->dct_cw, lds_dct(P)) && pow2_in(p->ring_g, ring_group_max(P)) &&
            (p->spread_bc == bcl || p->spread_bc == bcl / 2) && (p->fft_lr == 3 || p->fft_lr == 4) &&
-           (p->tw_table == 0 || p->tw_table == 1) && (p->spread_staged == 0 || p->spread_staged == 1);
+           (p->tw_table == 0 || p->tw_table == 1) && (p->spread_staged == 0 || p->spread_staged == 1) &&
+           (p->dct_wave_on == 0 || p->dct_wave_on == 1);
 }
 
 std::string tune_key(const pat_plan_s* p)
@@ -2126,14 +2507,16 @@ bool tune_lookup(pat_plan_s* p, const char* path, const std::string& key)
         double ms = 0;
         t.tw_table = 0;
         t.spread_staged = 0;
+        t.dct_wave_on = 0;
         const int got = std::sscanf(l.c_str() + bar + 3,
                                     "cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=%lf "
-                                    "twiddle_table=%d spread_staged=%d",
+                                    "twiddle_table=%d spread_staged=%d dct_wave=%d",
                                     &t.cols_cw, &t.dct_cw, &t.ring_g, &t.spread_bc, &t.fft_lr, &ms, &t.tw_table,
-                                    &t.spread_staged);
+                                    &t.spread_staged, &t.dct_wave_on);
         if (got >= 6 && tune_valid(&t)) {
             p->cols_cw = t.cols_cw; p->dct_cw = t.dct_cw; p->ring_g = t.ring_g; p->spread_bc = t.spread_bc;
             p->fft_lr = t.fft_lr; p->tw_table = t.tw_table; p->spread_staged = t.spread_staged; p->tuned_ms = ms;
+            p->dct_wave_on = t.dct_wave_on;
             found = true;  // keep scanning: the last matching line wins
         }
     }
@@ -2147,9 +2530,9 @@ void tune_store(const pat_plan_s* p, const char* path, const std::string& key)
     if (!fp) return;
     std::fprintf(fp,
                  "%s | cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=%.6f twiddle_table=%d "
-                 "spread_staged=%d\n",
+                 "spread_staged=%d dct_wave=%d\n",
                  key.c_str(), p->cols_cw, p->dct_cw, p->ring_g, p->spread_bc, p->fft_lr, p->tuned_ms, p->tw_table,
-                 p->spread_staged);
+                 p->spread_staged, p->dct_wave_on);
     std::fclose(fp);
 }
 
@@ -2215,7 +2598,8 @@ int tune_search(pat_plan_s* p, const Dev<T>& d)
                                    {&p->dct_cw, dw},
                                    {&p->ring_g, rg},
                                    {&p->spread_bc, {bcl, bcl / 2}},
-                                   {&p->spread_staged, {1, 0}}};
+                                   {&p->spread_staged, {1, 0}},
+                                   {&p->dct_wave_on, {1, 0}}};
     double best = 0;
     if ((rc = measure(best))) { cleanup(); return fail(rc, "autotuner: timing run failed"); }
     for (Choice& c : choices) {
@@ -2277,6 +2661,7 @@ void fill_info(const pat::Params& P, pat_plan_info* info, size_t ws_img, size_t 
         info->tune_spread_images = p->spread_bc;
         info->tune_twiddle_table = p->tw_table;
         info->tune_spread_staged = p->spread_staged;
+        info->tune_dct_wave = p->df.dct_wave ? 1 : 0;
         info->tuned = p->tuned;
         info->tuned_ms = p->tuned_ms;
     }
@@ -2291,6 +2676,8 @@ void fill_info(const pat::Params& P, pat_plan_info* info, size_t ws_img, size_t 
 }  // namespace
 
 namespace pat {
+int plan_device(pat_plan p) { return p ? p->device : -1; }
+
 int plan_image_size(pat_plan p, int* n, int* nt, int* m, double* h, int* is_f64)
 {
     if (!p) return PAT_EINVAL;

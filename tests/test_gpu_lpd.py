@@ -276,6 +276,30 @@ def _tiny_setup(K=3):
     return geom, plan, f32(f_true), f32(y), params, K
 
 
+ENSEMBLE = 16  # perturbed oracle runs that measure the bf16 rounding-flip spread
+
+
+def flip_spread(geom, Pd, y, f_true, K, s_A, s_U, ref_loss, ref_fK, ref_g, draws=ENSEMBLE):
+    """The spread that FP32-level differences alone cause in the bf16-rounded
+    oracle network: ``draws`` runs with every operator output perturbed by
+    1e-6 and every convolution product by 1e-7 relative (seeded Gaussian
+    noise, oracle.lpd.Perturb), each compared with the unperturbed run.
+    Returns the largest relative loss difference, f_K distance and
+    whole-gradient distance and the largest distance of each parameter block
+    over the draws."""
+    e_l, e_f, e_all, e_blk = 0.0, 0.0, 0.0, {k: 0.0 for k in ref_g}
+    allo = np.concatenate([np.ravel(ref_g[k]) for k in ref_g])
+    for s in range(draws):
+        lo, fk, g = OL.loss_and_grads(geom, Pd, y, f_true, K, s_A, s_U, rounding=True,
+                                      perturb=OL.Perturb(1000 + s, op=1e-6, conv=1e-7))
+        e_l = max(e_l, abs(lo - ref_loss) / ref_loss)
+        e_f = max(e_f, rel(fk, ref_fK))
+        e_all = max(e_all, rel(np.concatenate([np.ravel(g[k]) for k in ref_g]), allo))
+        for k in ref_g:
+            e_blk[k] = max(e_blk[k], rel(g[k], ref_g[k]))
+    return e_l, e_f, e_all, e_blk
+
+
 @pytest.mark.parametrize("K", [1, 3])
 def test_lpd_loss_gradient_vs_oracle(K):
     """Loss, f_K and every parameter gradient of K unrolled iterations at
@@ -283,19 +307,19 @@ def test_lpd_loss_gradient_vs_oracle(K):
     network run on the oracle's A / A* with the same bf16 rounding.
 
     Tolerances.  Both sides round the convolution operands to bf16 from FP32
-    values, but those FP32 values differ by the operators' FP32 error (~1e-6
-    relative here) and by FP32 accumulation, so a small fraction of the
-    roundings land on the other side of a rounding midpoint, each moving one
-    operand by up to 2^-8 relative.  With one iteration that fraction is
-    ~1e-4 and the results agree to ~2e-5; every further iteration feeds the
-    flipped values forward through a network of gain > 1, so at K = 3 the
-    agreement is bounded by the size of the bf16 effect itself, which the
-    test measures as the distance to the unrounded FP64 network: f_K must be
-    at least twice closer to the rounded oracle than that and the whole
-    gradient closer than that.  Per parameter block only a loose bound holds
-    (a few times the bf16 effect): small gradients such as the last layer's
-    bias are sums with cancellation, and which roundings flip moves with the
-    operators' last FP32 bits."""
+    values that differ by the operators' FP32 error and by FP32 accumulation,
+    so a few roundings land on the other side of a midpoint, each moving one
+    operand by up to 2^-8 relative.  With one iteration the results agree to
+    ~2e-5 (bar 1e-4).  Every further iteration feeds the flipped values
+    through the network and flips more roundings, so at K = 3 both sides are
+    draws of the same bf16 noise.  The bar there is measured on the oracle
+    side alone: an ensemble of oracle runs whose operator outputs (1e-6) and
+    convolution products (1e-7) carry seeded relative noise, compared with
+    the unperturbed run (flip_spread; the spread hardly depends on the noise
+    level, 1e-5 gives the same).  The GPU is one more such draw: f_K, the
+    whole gradient and each parameter block must lie within twice the
+    largest distance of the ensemble (16 draws; twice covers the sampling
+    error of a maximum).  A wrong term or sign gives O(1) errors."""
     geom, plan, f_true, y, params, _ = _tiny_setup()
     s_A, s_U = 0.9, 1.7
     net = L.LPD(plan, 2, iters=K, params=params, s_A=s_A, s_U=s_U)
@@ -306,32 +330,29 @@ def test_lpd_loss_gradient_vs_oracle(K):
     torch.cuda.synchronize()
     Pd = {k: v.astype(np.float64) for k, v in L.unpack(params).items()}
     loss_o, fK_o, g_o = OL.loss_and_grads(geom, Pd, y, f_true, K, s_A, s_U, rounding=True)
-    loss_x, fK_x, g_x = OL.loss_and_grads(geom, Pd, y, f_true, K, s_A, s_U, rounding=False)
     grads = L.unpack(net.grads.cpu().numpy())
     fK = net.f[K].cpu().numpy()
-    e_f, e_fx = rel(fK, fK_o), rel(fK_x, fK_o)
+    e_f = rel(fK, fK_o)
     e_g = {k: rel(grads[k], g_o[k]) for k in g_o}
-    e_gx = {k: rel(g_x[k], g_o[k]) for k in g_o}
-    print("K=%d f_K: gpu %.2e, bf16 effect %.2e" % (K, e_f, e_fx))
-    for k in g_o:
-        print("  %-10s gpu %.2e  bf16 effect %.2e" % (k, e_g[k], e_gx[k]))
+    allg = np.concatenate([np.ravel(grads[k]) for k in g_o])
+    allo = np.concatenate([np.ravel(g_o[k]) for k in g_o])
     if K == 1:
+        print("K=1 f_K: gpu %.2e" % e_f)
         assert e_f < 1e-4
         assert abs(net.loss() - loss_o) < 1e-4 * loss_o
         for k in g_o:
             assert e_g[k] < 1e-4, k
-    else:
-        assert e_f < 0.5 * e_fx
-        assert abs(net.loss() - loss_o) < 1e-2 * loss_o
-        # the whole gradient is closer to the rounded oracle than the bf16 effect;
-        # each parameter block within a few times it (catches wrong terms or signs,
-        # which give O(1) errors)
-        allg = np.concatenate([np.ravel(grads[k]) for k in g_o])
-        allo = np.concatenate([np.ravel(g_o[k]) for k in g_o])
-        allx = np.concatenate([np.ravel(g_x[k]) for k in g_o])
-        assert rel(allg, allo) < rel(allx, allo)
-        for k in g_o:
-            assert e_g[k] < 3 * e_gx[k] or e_g[k] < 1e-2, k
+        return
+    s_l, s_f, s_all, s_blk = flip_spread(geom, Pd, y, f_true, K, s_A, s_U, loss_o, fK_o, g_o)
+    print("K=%d f_K: gpu %.2e, flip spread %.2e; gradient: gpu %.2e, flip spread %.2e"
+          % (K, e_f, s_f, rel(allg, allo), s_all))
+    for k in g_o:
+        print("  %-10s gpu %.2e  flip spread %.2e" % (k, e_g[k], s_blk[k]))
+    assert e_f < 2 * s_f
+    assert abs(net.loss() - loss_o) < 2 * s_l * loss_o
+    assert rel(allg, allo) < 2 * s_all
+    for k in g_o:
+        assert e_g[k] < 2 * s_blk[k], k
 
 
 def test_lpd_graph_replay_equals_eager_training():

@@ -90,26 +90,65 @@ def test_full_tensor_parity(cid, dt, geom, kind):
     assert abs(lhs - rhs) / denom <= (1e-6 if dt == "f32" else 1e-14)
 
 
-@pytest.mark.parametrize("name,B", [("full_n256", 1), ("arc180_n256", 8), ("arc180_n128", 4), ("full_n512", 16)])
-def test_sampled_parity_at_full_size(name, B):
-    """Oracle samples at the workloads' full sizes; the batch is run in the
-    launch configuration the benchmark times (image 0 is the sampled one)."""
+def weighted_identity(geom, f, g, y, a):
+    """Per image |<A f, y>_Y - <f, A* y>_X| / (||A f||_Y ||y||_Y) of a batch."""
+    n = geom["n"]
+    h = 2 * geom["a"] / n
+    wy = yweights(geom)
+    out = []
+    for b in range(len(f)):
+        lhs = np.sum(g[b] * y[b]) * wy
+        rhs = np.sum(f[b] * a[b]) * h * h
+        out.append(abs(lhs - rhs) / (np.linalg.norm(g[b]) * np.linalg.norm(y[b]) * wy))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("name,B,shapes", [("full_n256", 1, "default"), ("arc180_n256", 8, "default"),
+                                           ("arc180_n128", 4, "default"), ("full_n512", 16, "default"),
+                                           ("full_n512", 16, "autotuned")])
+def test_sampled_parity_at_full_size(name, B, shapes, tmp_path):
+    """Oracle samples at the workloads' full sizes (image 0 is the sampled
+    one).  At n = 512 the batch is the benchmark's own (phantom seeds
+    0..15, trace seeds 1, 101..115), once in the default launch shapes and
+    once in the shapes the autotuner picks at plan creation from a fresh
+    cache -- the procedure the benchmark uses before it times."""
     z = np.load(os.path.join(HERE, "golden", name + ".npz"))
     geom, fseed, gseed, _, _ = golden_cases()[name]
-    print("case", name, "B", B, flush=True)
+    print("case", name, "B", B, shapes, flush=True)
     n, m, nt = geom["n"], geom["m"], geom["nt"]
-    plan = pat.Plan(geom, torch.float32, max_batch=B)
-    f = np.stack([P.ellipse_phantom(n, fseed)] + [P.ellipse_phantom(n, 500 + b) for b in range(B - 1)])
-    y = np.stack([P.randn((nt, m), gseed)] + [P.randn((nt, m), 600 + b) for b in range(B - 1)])
+    cache = str(tmp_path / "tune.txt") if shapes == "autotuned" else None
+    plan = pat.Plan(geom, torch.float32, max_batch=B, tuning_cache=cache)
+    if name == "full_n512":
+        assert fseed == 0 and gseed == 1
+        f = P.ellipse_batch(n, range(B))
+        y = np.stack([P.randn((nt, m), 1 if b == 0 else 100 + b) for b in range(B)])
+    else:
+        f = np.stack([P.ellipse_phantom(n, fseed)] + [P.ellipse_phantom(n, 500 + b) for b in range(B - 1)])
+        y = np.stack([P.randn((nt, m), gseed)] + [P.randn((nt, m), 600 + b) for b in range(B - 1)])
     g = plan.forward(on_gpu(f, "f32")).double().cpu().numpy()
     a = plan.adjoint(on_gpu(y, "f32")).double().cpu().numpy()
     ef = rel(g[0][:, z["dets"]], z["forward"])
     ea = rel(a[0].ravel()[z["pix"]], z["adjoint"])
-    print("  forward %.3e adjoint %.3e" % (ef, ea), flush=True)
+    info = plan.info
+    print("  forward %.3e adjoint %.3e shapes %s" % (
+        ef, ea, {k: info[k] for k in info if k.startswith("tune_")}), flush=True)
     assert ef <= 1e-4 and ea <= 1e-4
-    # the other images of the batch equal their own single-image results
+    # adjoint identity on the whole batch, full tensors
+    ident = weighted_identity(geom, f, g, y, a)
+    print("  adjoint identity max %.3e" % ident.max(), flush=True)
+    assert ident.max() <= 1e-6
+    # the other images of the batch equal their own single-image results, on a
+    # single-image plan with the same launch shapes (the autotuned batch's cache
+    # line, re-keyed for batch 1)
     if B > 1:
-        plan1 = pat.Plan(geom, torch.float32, max_batch=1)
+        cache1 = None
+        if cache is not None:
+            cache1 = str(tmp_path / "tune1.txt")
+            with open(cache) as src, open(cache1, "w") as dst:
+                for line in src:
+                    dst.write(line.replace(" batch=%d | " % B, " batch=1 | "))
+        plan1 = pat.Plan(geom, torch.float32, max_batch=1, tuning_cache=cache1)
+        assert cache1 is None or plan1.info["tuned"] == 2
         gl = plan1.forward(on_gpu(f[B - 1], "f32")).double().cpu().numpy()
         assert np.array_equal(gl, g[B - 1])
         al = plan1.adjoint(on_gpu(y[B - 1], "f32")).double().cpu().numpy()

@@ -74,6 +74,57 @@ def test_fp64_nnls_iterates_match_oracle_driven_nnls():
     assert np.linalg.norm(f_g - f_o) / np.linalg.norm(f_o) < 1e-8
 
 
+def oracle_power_norm(geom, n, seed=5, iters=40):
+    """||A||_{X->Y} from the oracle's own power iteration on A*A."""
+    x = P.randn((n, n), seed)
+    lam = 0.0
+    for _ in range(iters):
+        x = x / np.sqrt(np.sum(x * x))
+        y = O.adjoint(geom, O.forward(geom, x))
+        lam = float(np.sum(x * y))
+        x = y
+    return math.sqrt(lam)
+
+
+@pytest.mark.parametrize("lam", [1e-3, 1e-2])
+def test_fp64_cp_tv_iterates_match_oracle_driven_cp(lam):
+    """Ten Chambolle-Pock TV-LS steps (pat_cp_dual_data, pat_cp_dual_tv,
+    pat_cp_primal around the GPU operators, eqs. eqn:PDHG-dual,
+    eqn:PDHG-primal, eqn:PDHG-relaxation in the fully split reading) equal
+    the same steps driven by the oracle's A and A* with numpy grad_h / div_h
+    (oracle/solvers.py), with the library's own step sizes, at n = 24 on the
+    180-degree arc.  At both lam the TV term moves the iterate by more than
+    ten percent against lam = 0, and the dual projection is active (the
+    iterate differs from one with an unreachable radius), so a wrong sign or
+    scale in the TV dual or its projection fails."""
+    from oracle import solvers as OS
+    geom = P.top_arc(24, 32, 32, 180.0)
+    n = 24
+    h = 2.0 * geom["a"] / n
+    f_true = P.ellipse_phantom(24, 3)
+    g = O.forward(geom, f_true) + 0.01 * P.randn((32, 32), 4)
+    L = oracle_power_norm(geom, n)
+    plan = pat.Plan(geom, torch.float64)
+    sol = S.BatchedSolver([(plan, torch.tensor(g[None], dtype=torch.float64, device="cuda"), None)],
+                          method="tv", lam=lam, opnorms=[L])
+    G = sol.groups[0]
+    mu = math.sqrt(G.sigma_tv / G.sigma)
+    iters = 10
+    for _ in range(iters):
+        sol.step()
+    f_g = G.f[0].cpu().numpy()
+    A = lambda f: O.forward(geom, f)  # noqa: E731
+    As = lambda y: O.adjoint(geom, y)  # noqa: E731
+    f_o = OS.cp_tv(A, As, g, n, h, lam, G.tau, G.sigma, mu, iters)
+    err = np.linalg.norm(f_g - f_o) / np.linalg.norm(f_o)
+    print("lam %g: CP-TV iterate vs oracle-driven %.3e" % (lam, err), flush=True)
+    assert err < 1e-8
+    f_0 = OS.cp_tv(A, As, g, n, h, 0.0, G.tau, G.sigma, mu, iters)
+    assert np.linalg.norm(f_o - f_0) > 1e-1 * np.linalg.norm(f_0)
+    f_free = OS.cp_tv(A, As, g, n, h, 1e3, G.tau, G.sigma, mu, iters)
+    assert np.linalg.norm(f_o - f_free) > 1e-2 * np.linalg.norm(f_free)
+
+
 def test_opnorm_estimate_is_the_operator_norm():
     """pat_opnorm_estimate against ||A||_{X->Y} = sqrt(s) sigma_max(A) from the
     singular values of the oracle's dense matrix (n = 24, 180-degree arc).

@@ -14,11 +14,15 @@ another draw of the same bf16 rounding noise (measured: with batch-norm shifts
 of +2, where ReLU masks rarely flip, the GPU is 0.99 % from the rounded oracle
 and the rounded oracle 0.92 % from the unrounded one).  Flips also move ReLU
 masks and max-pooling choices, which reroute gradients by O(1) amounts, so
-with zero shifts the bf16 effect on gradients is ~36 %.  The bar is therefore
-the size of the bf16 effect itself, measured as the distance from the rounded
-to the unrounded FP64 oracle: the GPU must stay within 1.5 times it.  The
-shifted case (bf16 effect ~3 % on gradients) is the discriminating one: a
-wrong connection, term or sign gives O(1) errors there."""
+with zero shifts the bf16 effect on gradients is ~36 %.  The bar is measured
+on the oracle side alone: an ensemble of rounded oracle runs whose
+convolution products (and, in the unrolled network, operator outputs) carry
+seeded relative noise at FP32 level (oracle.lpd.Perturb: 1e-7 and 1e-6),
+each compared with the unperturbed run.  The GPU is one more such draw, so
+every compared quantity must lie within twice the largest distance of the
+ensemble (twice covers the sampling error of a maximum over the draws).  The
+shifted case is the discriminating one: a wrong connection, term or sign
+gives O(1) errors there."""
 import ctypes
 
 import numpy as np
@@ -375,21 +379,37 @@ def test_unet_forward_backward_against_the_oracle(lib, cin, B, H, W, shift):
     torch.cuda.synchronize()
     p0 = params.cpu().numpy()
 
-    def oracle(rounding):
+    def oracle(perturb=None):
         P = _oracle_params(p0, offs, shapes, net)
         xs = [planes[c].double().requires_grad_(True) for c in range(cin)]
         x = torch.stack([scales[c] * xs[c] for c in range(cin)], dim=1)
         running = {net + "." + k: v for k, v in OU.fresh_running().items()}
-        y = OU.unet(x, P, net + ".", running, training=True, rounding=rounding)[:, 0] + res.double()
+        y = OU.unet(x, P, net + ".", running, training=True, rounding=True, perturb=perturb)[:, 0] + res.double()
         (y * gout.double()).sum().backward()
         return y.detach(), P, xs, running
 
-    y_r, P_r, xs_r, run_r = oracle(True)
-    y_u, P_u, xs_u, _ = oracle(False)
+    def gradients(P):
+        return {name: P[name].grad.numpy().ravel() for name in P}
+
+    y_r, P_r, xs_r, run_r = oracle()
+    g_r = gradients(P_r)
     rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+    nrel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+    allr = np.concatenate([g_r[k] for k in P_r])
+    # the FP32-noise ensemble of the rounded oracle (fewer draws at the full sizes)
+    draws = 8 if H * W <= 4096 else 3
+    s_out, s_g, s_blk, s_x = 0.0, 0.0, {k: 0.0 for k in P_r}, [0.0] * cin
+    for d in range(draws):
+        y_p, P_p, xs_p, _ = oracle(OL.Perturb(2000 + d, op=0.0, conv=1e-7))
+        g_p = gradients(P_p)
+        s_out = max(s_out, rel(y_p - res.double(), y_r - res.double()))
+        s_g = max(s_g, nrel(np.concatenate([g_p[k] for k in P_r]), allr))
+        for k in P_r:
+            s_blk[k] = max(s_blk[k], nrel(g_p[k], g_r[k]))
+        for c in range(cin):
+            s_x[c] = max(s_x[c], rel(xs_p[c].grad, xs_r[c].grad))
     e_out = rel(out.cpu().double() - res.double(), y_r - res.double())
-    b_out = rel(y_u - res.double(), y_r - res.double())
-    print("output: gpu vs oracle %.3e, bf16 effect %.3e" % (e_out, b_out))
+    print("output: gpu vs oracle %.3e, flip spread %.3e" % (e_out, s_out))
     # running statistics
     e_stats = 0.0
     for name, c in UN.bn_layers():
@@ -398,35 +418,28 @@ def test_unet_forward_backward_against_the_oracle(lib, cin, B, H, W, shift):
     print("running means: max relative deviation %.3e" % e_stats)
     # parameter gradients, whole vector and per tensor
     gcpu = grads.cpu().double().numpy()
-    gg, gr, gu, blocks = [], [], [], {}
+    gg, blocks = [], {}
     for name in P_r:
         size = int(np.prod(shapes[name]))
         gg.append(gcpu[offs[name]:offs[name] + size])
-        gr.append(P_r[name].grad.numpy().ravel())
-        gu.append(P_u[name].grad.numpy().ravel())
-        nr = max(np.linalg.norm(gr[-1]), 1e-30)
-        blocks[name] = (np.linalg.norm(gg[-1] - gr[-1]) / nr, np.linalg.norm(gu[-1] - gr[-1]) / nr)
-    worst = sorted(blocks.items(), key=lambda kv: -kv[1][0])[:5]
-    print("worst blocks (gpu, bf16 effect):", ["%s %.2e %.2e" % (k, a, b) for k, (a, b) in worst])
-    gg, gr, gu = np.concatenate(gg), np.concatenate(gr), np.concatenate(gu)
-    e_g = np.linalg.norm(gg - gr) / np.linalg.norm(gr)
-    b_g = np.linalg.norm(gu - gr) / np.linalg.norm(gr)
-    print("parameter gradient: gpu vs oracle %.3e, bf16 effect %.3e" % (e_g, b_g))
+        blocks[name] = (nrel(gg[-1], g_r[name]), s_blk[name])
+    worst = sorted(blocks.items(), key=lambda kv: -kv[1][0] / max(kv[1][1], 1e-30))[:5]
+    print("worst blocks (gpu, flip spread):", ["%s %.2e %.2e" % (k, a, b) for k, (a, b) in worst])
+    e_g = nrel(np.concatenate(gg), allr)
+    print("parameter gradient: gpu vs oracle %.3e, flip spread %.3e" % (e_g, s_g))
     ex = []
     for c in range(cin):
         e_x = rel(gpl[c].cpu().double(), xs_r[c].grad)
-        b_x = rel(xs_u[c].grad, xs_r[c].grad)
-        ex.append((e_x, b_x))
-        print("input gradient %d: gpu vs oracle %.3e, bf16 effect %.3e" % (c, e_x, b_x))
-    # see the module docstring: within 1.5 times the bf16 effect, each
-    # parameter block within twice it
-    assert e_out < 1.5 * b_out and e_out < 3e-2
+        ex.append((e_x, s_x[c]))
+        print("input gradient %d: gpu vs oracle %.3e, flip spread %.3e" % (c, e_x, s_x[c]))
+    # see the module docstring: within twice the ensemble's largest distance
+    assert e_out < 2 * s_out
     assert e_stats < 5e-2
-    assert e_g < 1.5 * b_g and e_g < 0.4
+    assert e_g < 2 * s_g
     for name, (a, b) in blocks.items():
-        assert a < 2 * b or a < 1e-2, (name, a, b)
-    for e_x, b_x in ex:
-        assert e_x < 1.5 * b_x
+        assert a < 2 * b, (name, a, b)
+    for e_x, s in ex:
+        assert e_x < 2 * s
 
 
 def test_unet_forward_backward_is_bit_reproducible(lib):
@@ -502,9 +515,9 @@ def test_unet_lpd_loss_gradient_against_the_oracle():
     """f_K, the loss and the whole parameter gradient of K = 2 unrolled
     iterations with U-Nets (batch-norm shifts +2) against the oracle run on
     its own A / A* with the same bf16 storage.  Roundings that flip between
-    the two sides feed forward (module docstring), so the bar is the size of
-    the bf16 effect itself (distance to the unrounded FP64 network): f_K and
-    the whole gradient within 1.5 times it, each block within 3 times it."""
+    the two sides feed forward (module docstring), so the bar is the spread
+    of an FP32-noise ensemble of the rounded oracle (8 draws): f_K, the loss,
+    the whole gradient and each block within twice its largest distance."""
     K = 2
     geom, plan, f_true, y, params = _tiny(K)
     s_A, s_U = 0.9, 1.7
@@ -517,22 +530,28 @@ def test_unet_lpd_loss_gradient_against_the_oracle():
     run_o = _oracle_running(K)
     loss_o, fK_o, g_o = OL.loss_and_grads(geom, Pd, y, f_true, K, s_A, s_U, rounding=True, arch="unet",
                                           running=run_o)
-    loss_x, fK_x, g_x = OL.loss_and_grads(geom, Pd, y, f_true, K, s_A, s_U, rounding=False, arch="unet",
-                                          running=_oracle_running(K))
+    allo = np.concatenate([np.ravel(g_o[k]) for k in g_o])
+    s_l, s_f, s_g, s_blk = 0.0, 0.0, 0.0, {k: 0.0 for k in g_o}
+    for d in range(8):
+        l_p, f_p, g_p = OL.loss_and_grads(geom, Pd, y, f_true, K, s_A, s_U, rounding=True, arch="unet",
+                                          running=_oracle_running(K), perturb=OL.Perturb(3000 + d))
+        s_l = max(s_l, abs(l_p - loss_o) / loss_o)
+        s_f = max(s_f, _rel(f_p, fK_o))
+        s_g = max(s_g, _rel(np.concatenate([np.ravel(g_p[k]) for k in g_o]), allo))
+        for k in g_o:
+            s_blk[k] = max(s_blk[k], _rel(g_p[k], g_o[k]))
     grads = LPDM.unpack(net.grads.cpu().numpy(), arch="unet")
     fK = net.f[K].cpu().numpy()
-    e_f, e_fx = _rel(fK, fK_o), _rel(fK_x, fK_o)
+    e_f = _rel(fK, fK_o)
     allg = np.concatenate([np.ravel(grads[k]) for k in g_o])
-    allo = np.concatenate([np.ravel(g_o[k]) for k in g_o])
-    allx = np.concatenate([np.ravel(g_x[k]) for k in g_o])
-    print("K=%d f_K: gpu %.2e, bf16 effect %.2e; gradient: gpu %.2e, bf16 effect %.2e"
-          % (K, e_f, e_fx, _rel(allg, allo), _rel(allx, allo)))
-    assert e_f < 1.5 * e_fx and e_f < 2e-2
-    assert abs(net.loss() - loss_o) < 1e-2 * loss_o
-    assert _rel(allg, allo) < 1.5 * _rel(allx, allo)
+    print("K=%d f_K: gpu %.2e, flip spread %.2e; gradient: gpu %.2e, flip spread %.2e"
+          % (K, e_f, s_f, _rel(allg, allo), s_g))
+    assert e_f < 2 * s_f
+    assert abs(net.loss() - loss_o) < 2 * s_l * loss_o
+    assert _rel(allg, allo) < 2 * s_g
     for k in g_o:
-        e, ex = _rel(grads[k], g_o[k]), _rel(g_x[k], g_o[k])
-        assert e < 3 * ex or e < 2e-2, (k, e, ex)
+        e = _rel(grads[k], g_o[k])
+        assert e < 2 * s_blk[k], (k, e, s_blk[k])
     # running statistics of every iteration after one application each
     got = _running_from(net.stats.cpu().numpy(), K)
     for k in range(K):
@@ -568,14 +587,14 @@ def test_unet_lpd_graph_replay_and_inference():
     Pd = {k: v.astype(np.float64) for k, v in LPDM.unpack(a.params.cpu().numpy(), arch="unet").items()}
     run = _running_from(a.stats.cpu().numpy(), K)
     Pt = {k: torch.tensor(v) for k, v in Pd.items()}
+    yt = torch.tensor(y.astype(np.float64))
     with torch.no_grad():
-        f_o = OL.reconstruct(geom, Pt, torch.tensor(y.astype(np.float64)), K, rounding=True, arch="unet",
-                             running=run, training=False).numpy()
-        f_x = OL.reconstruct(geom, Pt, torch.tensor(y.astype(np.float64)), K, rounding=False, arch="unet",
-                             running=run, training=False).numpy()
-    e, ex = _rel(f_e.cpu().numpy(), f_o), _rel(f_x, f_o)
-    print("inference f_K: gpu %.2e, bf16 effect %.2e" % (e, ex))
-    assert e < 1.5 * ex and e < 2e-2
+        f_o = OL.reconstruct(geom, Pt, yt, K, rounding=True, arch="unet", running=run, training=False).numpy()
+        spread = max(_rel(OL.reconstruct(geom, Pt, yt, K, rounding=True, arch="unet", running=run, training=False,
+                                         perturb=OL.Perturb(4000 + d)).numpy(), f_o) for d in range(8))
+    e = _rel(f_e.cpu().numpy(), f_o)
+    print("inference f_K: gpu %.2e, flip spread %.2e" % (e, spread))
+    assert e < 2 * spread
     inf.capture_forward()
     for _ in range(2):
         inf.f[K].zero_()

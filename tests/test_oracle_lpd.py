@@ -87,8 +87,8 @@ def test_direct_quadrature_operators_backward_is_their_transpose():
     geom = P.top_arc(6, 8, 8, 180.0)
     f = torch.tensor(P.randn((1, 6, 6), 3), requires_grad=True)
     g = torch.tensor(P.randn((1, 8, 8), 4), requires_grad=True)
-    assert torch.autograd.gradcheck(lambda x: OL._A.apply(x, geom), (f,), eps=1e-6, atol=1e-8, rtol=1e-6)
-    assert torch.autograd.gradcheck(lambda x: OL._Astar.apply(x, geom), (g,), eps=1e-6, atol=1e-8, rtol=1e-6)
+    assert torch.autograd.gradcheck(lambda x: OL._A.apply(x, geom, None), (f,), eps=1e-6, atol=1e-8, rtol=1e-6)
+    assert torch.autograd.gradcheck(lambda x: OL._Astar.apply(x, geom, None), (g,), eps=1e-6, atol=1e-8, rtol=1e-6)
 
 
 def test_rounded_network_gradient_is_close_to_exact():
