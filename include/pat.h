@@ -279,6 +279,18 @@ int pat_axpby(pat_plan p, long count, double a, const void* x, double b, const v
 int pat_dot_batched(pat_plan p, int B, long count, long stride, const void* x, const void* y, double* out,
                     double* scratch, void* stream);
 
+/* pat_dot_batched without a scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the 64 partial sums per image live in a
+ * static device array of the library (2 MiB, one per GPU, held until the
+ * process ends), so B <= 4096 (else PAT_EINVAL with a message).  Same
+ * arguments, layout and result as pat_dot_batched (bit-identical); the plan's
+ * device must be the current device.  Calls on one GPU share that array:
+ * calls that overlap in time on one GPU (different streams, threads) race and
+ * must be serialised by the caller.  Allocates nothing. */
+int pat_dot_batched_noalloc(pat_plan p, int B, long count, long stride, const void* x, const void* y, double* out,
+                            void* stream);
+
 /* Projected gradient step of NNLS (eq:NNLS-projstep, eqn:projectionHalfCircle):
  * f = support * max(0, f - tau * grad) for B images. */
 int pat_nnls_update(pat_plan p, int B, void* f, const void* grad, double tau, const void* support, void* stream);

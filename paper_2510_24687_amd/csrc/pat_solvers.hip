@@ -16,8 +16,11 @@
 
 #include "pat_internal.h"
 
+#include <mutex>
+
 namespace pat {
 int plan_image_size(pat_plan p, int* n, int* nt, int* m, double* h, int* is_f64);
+int plan_device(pat_plan p);
 }
 
 namespace {
@@ -181,6 +184,45 @@ __global__ __launch_bounds__(NT) void k_hash_fill(long count, T* x, unsigned see
     }
 }
 
+// Partial sums of pat_dot_batched_noalloc: DOT_PARTS doubles per image for at
+// most DOT_NOALLOC_MAX_B images (2 MiB), one copy per GPU that the library
+// runs on, held until the process ends.  Host code never passes the symbol
+// itself to a kernel (in host code it names a host-side stand-in): it uses the
+// device address that hipGetSymbolAddress returns for the current device.
+constexpr int DOT_NOALLOC_MAX_B = 4096;
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[DOT_PARTS * DOT_NOALLOC_MAX_B];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on device dev (which must be current), looked up
+// once per device and kept.
+int scratch_address(int dev, double** out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        pat::set_error("pat_dot_batched_noalloc: device index out of range");
+        return PAT_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            pat::set_error(std::string("pat_dot_batched_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+            return PAT_EHIP;
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return PAT_OK;
+}
+
 int grid_for(long count)
 {
     long g = (count + NT - 1) / NT;
@@ -236,6 +278,47 @@ int pat_dot_batched(pat_plan p, int B, long count, long stride, const void* x, c
         k_dotb_partial<float><<<grid, NT, 0, st>>>(count, stride, (const float*)x, (const float*)y, scratch);
     k_dotb_final<<<B, NT, 0, st>>>(scratch, parts, out);
     return launch_status("pat_dot_batched");
+}
+
+int pat_dot_batched_noalloc(pat_plan p, int B, long count, long stride, const void* x, const void* y, double* out,
+                            void* stream)
+{
+    int n, nt, m, f64;
+    double h;
+    if (!p || !x || !y || !out || B < 1 || count < 1 || stride < count) {
+        pat::set_error("pat_dot_batched_noalloc: bad arguments");
+        return PAT_EINVAL;
+    }
+    if (B > DOT_NOALLOC_MAX_B) {
+        pat::set_error("pat_dot_batched_noalloc: batch " + std::to_string(B) + " exceeds the static scratch limit of " +
+                       std::to_string(DOT_NOALLOC_MAX_B) + " images (use pat_dot_batched with a scratch buffer)");
+        return PAT_EINVAL;
+    }
+    if (pat::plan_image_size(p, &n, &nt, &m, &h, &f64)) return PAT_EINVAL;
+    const int dev = pat::plan_device(p);
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) {
+        pat::set_error("pat_dot_batched_noalloc: no HIP device");
+        return PAT_EHIP;
+    }
+    if (cur != dev) {
+        pat::set_error("pat_dot_batched_noalloc: the plan's device is not the current device");
+        return PAT_EINVAL;
+    }
+    double* part = nullptr;
+    int rc = scratch_address(dev, &part);
+    if (rc) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // every partial that k_dotb_final reads is written by k_dotb_partial first,
+    // so the scratch needs no clearing between calls
+    const int parts = std::min(DOT_PARTS, grid_for(count));
+    const dim3 grid(parts, B);
+    if (f64)
+        k_dotb_partial<double><<<grid, NT, 0, st>>>(count, stride, (const double*)x, (const double*)y, part);
+    else
+        k_dotb_partial<float><<<grid, NT, 0, st>>>(count, stride, (const float*)x, (const float*)y, part);
+    k_dotb_final<<<B, NT, 0, st>>>(part, parts, out);
+    return launch_status("pat_dot_batched_noalloc");
 }
 
 int pat_nnls_update(pat_plan p, int B, void* f, const void* grad, double tau, const void* support, void* stream)

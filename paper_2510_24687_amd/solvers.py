@@ -44,6 +44,7 @@ def _bind(lib):
     lib.pat_cp_dual_tv.argtypes = [_VP, I, _VP, _VP, D, D, _VP]
     lib.pat_cp_primal.argtypes = [_VP, I, _VP, _VP, _VP, _VP, D, D, _VP, _VP]
     lib.pat_dot_batched.argtypes = [_VP, I, L, L, _VP, _VP, _VP, _VP, _VP]
+    lib.pat_dot_batched_noalloc.argtypes = [_VP, I, L, L, _VP, _VP, _VP, _VP]
     lib._solver_bound = True
     return lib
 
