@@ -75,7 +75,8 @@ def kernel_source_hash() -> str:
 
 
 SHAPE_KEYS = ["tune_fft_radix_log2", "tune_twiddle_table", "tune_cols_per_block", "tune_dct_cols_per_block",
-              "tune_ring_images", "tune_spread_images", "tune_spread_staged", "tune_dct_wave"]
+              "tune_ring_images", "tune_spread_images", "tune_spread_staged", "tune_dct_wave",
+              "tune_wave_fft"]
 
 
 def measured_traffic(kernel: str, B: int, shapes: dict = None):
@@ -93,7 +94,10 @@ def measured_traffic(kernel: str, B: int, shapes: dict = None):
                 "dct_fwd": ("tune_dct_cols_per_block", "tune_dct_wave"),
                 "dct_adj": ("tune_dct_cols_per_block", "tune_dct_wave"),
                 "ring_fwd": ("tune_ring_images",), "ring_adj": ("tune_ring_images",),
-                "cols_fwd": ("tune_cols_per_block",), "cols_adj": ("tune_cols_per_block",)}.get(kernel, ())
+                "cols_fwd": ("tune_cols_per_block", "tune_wave_fft"),
+                "cols_adj": ("tune_cols_per_block", "tune_wave_fft"),
+                "rows_fwd": ("tune_wave_fft",), "rows_adj": ("tune_wave_fft",),
+                "synth_fwd": ("tune_wave_fft",), "synth_adj": ("tune_wave_fft",)}.get(kernel, ())
     recorded = z.get("launch_shapes")
     if shapes is not None and recorded is not None and any(recorded.get(k) != shapes.get(k) for k in relevant):
         return None
@@ -136,6 +140,34 @@ def solver_bench(iters: int = 200, count: int = 64, lam: float = 1e-3, noise: fl
     out = {"instances": int(count), "sizes": {str(k): int(np.sum(sizes == k)) for k in (128, 256, 512)},
            "iterations": iters}
     norms = [solvers.opnorm(p) for p, _, _ in groups]
+    # the same instances in FP64 plans: the FP32 iterates and objective curves
+    # are compared with the FP64 ones (same step sizes)
+    groups64 = [(pat.Plan(p.geom, torch.float64, max_batch=g.shape[0]), g.double(), None) for p, g, _ in groups]
+    for method in ("nnls", "tv"):
+        curves = {}
+        finals = {}
+        for tag, grp in (("f32", groups), ("f64", groups64)):
+            sol = solvers.BatchedSolver(grp, method=method, lam=lam, opnorms=norms)
+            sol.capture()
+            curve = []
+            for it in range(iters):
+                sol.replay(1)
+                if (it + 1) % 20 == 0:
+                    torch.cuda.synchronize()
+                    curve.append(float(sum(float(o.sum()) for o in sol.objective())))
+            torch.cuda.synchronize()
+            curves[tag] = curve
+            finals[tag] = [G.f.double() for G in sol.groups]
+        diff = []
+        for a, b in zip(finals["f32"], finals["f64"]):
+            diff += list((torch.linalg.vector_norm((a - b).flatten(1), dim=1) /
+                          torch.linalg.vector_norm(b.flatten(1), dim=1)).cpu().numpy())
+        out[method + "_fp32_vs_fp64"] = {
+            "iterations": iters, "max_rel_l2_iterate_difference": float(np.max(diff)),
+            "mean_rel_l2_iterate_difference": float(np.mean(diff)),
+            "objective_every_20_iterations": curves,
+            "objective_max_rel_difference": float(np.max(np.abs(np.array(curves["f32"]) - np.array(curves["f64"])) /
+                                                         np.abs(np.array(curves["f64"]))))}
     for method, grouped in (("nnls", False), ("tv", False), ("nnls", True), ("tv", True)):
         sol = solvers.BatchedSolver(groups, method=method, lam=lam, opnorms=norms, grouped=grouped)
         sol.capture()

@@ -120,6 +120,8 @@ typedef struct {
                                      reads them with scalar loads one ahead         */
     int tune_dct_wave;            /* 1: the FP32 cosine transform runs one wave per
                                      column group with compile-time lengths         */
+    int tune_wave_fft;            /* 1: the FP32 row / column / angular FFT kernels
+                                     run one wave per sequence                      */
     int tuned;                    /* 0 defaults, 1 measured at creation, 2 cached   */
     double tuned_ms;              /* forward + adjoint ms at max_batch when tuned   */
 } pat_plan_info;

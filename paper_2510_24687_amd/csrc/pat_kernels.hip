@@ -380,6 +380,10 @@ struct Dev {
     int dct_wave;               // FP32 cosine transform with one wave per column group: variant
                                 // (M3 << 8) | log2 of M's power-of-two factor; 0: not used
     int dwCB;                   // columns per block of dct_wave
+    int wfRows;                 // log2 Ng when the FP32 row and column FFT passes run one wave per
+                                // sequence (rows_fwd_w, cols_fwd_w, ...), else 0
+    int wfSynth;                // log2 m_full for the wave form of the angular synthesis, else 0
+    int ring_ct;                // 1: FP32 ring transforms with compile-time lengths (ring_fft_ct)
     int fft_lr;                 // largest FFT pass radix is 2^fft_lr (3 or 4)
     int tw_table;               // 1: FFT passes read every twiddle from the table
     T beta, shift, half;        // half = Ng / (2 Lambda): grid cells per unit lambda
@@ -584,11 +588,177 @@ __global__ __launch_bounds__(NT) void cols_fwd(Dev<T> d, const cx<T>* R, cx<T>* 
     cols_fwd_body<T>(d, blk_xcd(), R, E, ws_img);
 }
 
+// Ring transforms with their length known at compile time (FP32): the same
+// Stockham passes as lds_fft / lds_fft3 (radix 8 while three bits remain,
+// then 4 or 2, then radix 3 for 3 * 2^a points; the same twiddle tables), but
+// with constant strides, sequence counts and shifts, and each thread's
+// twiddles loaded once per pass while the sub-transform length divides the
+// block.  nb * N <= FFT_BLOCK_POINTS.
+__host__ __device__ constexpr int rc_radix(int LOGN, int p)
+{
+    return (LOGN - 3 * p >= 3) ? 8 : (LOGN - 3 * p == 2 ? 4 : 2);
+}
+__host__ __device__ constexpr int rc_npass(int LOGN) { return LOGN / 3 + (LOGN % 3 ? 1 : 0); }
+__host__ __device__ constexpr int rc_ns(int LOGN, int p) { return p == 0 ? 1 : rc_ns(LOGN, p - 1) * rc_radix(LOGN, p - 1); }
+__host__ __device__ constexpr int rc_log2(int v) { return v <= 1 ? 0 : 1 + rc_log2(v / 2); }
+
+// one power-of-two pass over nb sequences of length N (stride N); for a
+// 3 * 2^a ring, N is that length and the pass works on its 2^a factor as
+// lds_fft does with f3 (butterfly inputs N / R apart)
+template <int N, int R, int NS, bool INV>
+__device__ __forceinline__ void rc_pass(PAT_LDS cx<float>* buf, int nb, const PAT_GLOBAL cx<float>* __restrict__ tw,
+                                        int logNmax)
+{
+    constexpr int NBS = N / R;                  // butterflies per sequence
+    constexpr int PER = FFT_REGS / R;           // nb * N <= FFT_BLOCK_POINTS
+    const int total = nb * NBS;
+    cx<float> v[PER][R];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = threadIdx.x + NT * u;
+        if (t < total) {
+            const int b = t / NBS, tt = t - b * NBS;
+            const PAT_LDS cx<float>* s = buf + b * N;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[u][r] = ld_lds(s + tt + r * NBS);
+        }
+    }
+    __syncthreads();
+    const int sh = logNmax - rc_log2(R * NS);
+    cx<float> wl[R];
+    if constexpr (NS > 1 && NS <= NT) {
+        const int k = threadIdx.x & (NS - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            wl[r] = ld_glb(tw + ((r * k) << sh));
+            if (INV) wl[r].y = -wl[r].y;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = threadIdx.x + NT * u;
+        if (t < total) {
+            const int b = t / NBS, tt = t - b * NBS;
+            const int k = tt & (NS - 1);
+            if constexpr (NS > NT) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cx<float> w = ld_glb(tw + ((r * k) << sh));
+                    if (INV) w.y = -w.y;
+                    v[u][r] = cmul(v[u][r], w);
+                }
+            } else if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[u][r] = cmul(v[u][r], wl[r]);
+            }
+            dft_reg<float, R>(v[u], INV);
+            PAT_LDS cx<float>* s = buf + b * N;
+            const int base = (tt / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) st_lds(s + base + r * NS, v[u][r]);
+        }
+    }
+    __syncthreads();
+}
+
+template <int N, int LOGP, bool INV, int P = 0>
+__device__ __forceinline__ void rc_passes(PAT_LDS cx<float>* buf, int nb, const PAT_GLOBAL cx<float>* tw, int logNmax)
+{
+    if constexpr (P < rc_npass(LOGP)) {
+        rc_pass<N, rc_radix(LOGP, P), rc_ns(LOGP, P), INV>(buf, nb, tw, logNmax);
+        rc_passes<N, LOGP, INV, P + 1>(buf, nb, tw, logNmax);
+    }
+}
+
+// radix-3 pass of a 3 * 2^LOGP ring (sub-transform length 2^LOGP); twr holds
+// the 2 Nr3-th roots, W_N^{r t} = twr[(2 r t) << tsh]
+template <int LOGP, bool INV>
+__device__ __forceinline__ void rc_pass3(PAT_LDS cx<float>* buf, int nb, const PAT_GLOBAL cx<float>* __restrict__ twr,
+                                         int tsh)
+{
+    constexpr int NS = 1 << LOGP, N = 3 * NS;
+    constexpr int PER = FFT_REGS / 3;
+    const int total = nb * NS;
+    const float h3 = 0.86602540378443864676f;
+    cx<float> v[PER][3];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = threadIdx.x + NT * u;
+        if (t < total) {
+            const int b = t >> LOGP, tt = t & (NS - 1);
+            const PAT_LDS cx<float>* s = buf + b * N;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) v[u][r] = ld_lds(s + tt + r * NS);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = threadIdx.x + NT * u;
+        if (t < total) {
+            const int b = t >> LOGP, tt = t & (NS - 1);
+            cx<float> w1 = ld_glb(twr + ((2 * tt) << tsh)), w2 = ld_glb(twr + ((4 * tt) << tsh));
+            if (INV) { w1.y = -w1.y; w2.y = -w2.y; }
+            const cx<float> a0 = v[u][0], a1 = cmul(v[u][1], w1), a2 = cmul(v[u][2], w2);
+            const cx<float> sm = a1 + a2, df = a1 - a2;
+            const cx<float> m = {a0.x - 0.5f * sm.x, a0.y - 0.5f * sm.y};
+            const cx<float> jd = INV ? cx<float>{-h3 * df.y, h3 * df.x} : cx<float>{h3 * df.y, -h3 * df.x};
+            PAT_LDS cx<float>* s = buf + b * N;
+            st_lds(s + tt, a0 + sm);
+            st_lds(s + tt + NS, m + jd);
+            st_lds(s + tt + 2 * NS, m - jd);
+        }
+    }
+    __syncthreads();
+}
+
+template <int M3, int LOGP, bool INV>
+__device__ __forceinline__ void ring_fft_ct(const Dev<float>& d, cx<float>* buf, int nb)
+{
+    constexpr int N = (M3 ? 3 : 1) << LOGP;
+    PAT_LDS cx<float>* lb = (PAT_LDS cx<float>*)buf;
+    rc_passes<N, LOGP, INV>(lb, nb, (const PAT_GLOBAL cx<float>*)d.tw, d.logNmax);
+    if constexpr (M3) rc_pass3<LOGP, INV>(lb, nb, (const PAT_GLOBAL cx<float>*)d.twr, d.logNr3 - LOGP);
+}
+
+// FP32 rings of 16 .. 2048 points (2^a) and 24 .. 1536 points (3 * 2^a): the
+// compile-time transforms, as many sequences per call as the registers allow
+// (FFT_BLOCK_POINTS points, (FFT_REGS / 3) * 3 * NT with the radix-3 pass);
+// returns false for other lengths and for FP64
+#define PAT_RC_SIZES(X) \
+    X(0, 4) X(0, 5) X(0, 6) X(0, 7) X(0, 8) X(0, 9) X(0, 10) X(0, 11) X(1, 3) X(1, 4) X(1, 5) X(1, 6) X(1, 7) X(1, 8) X(1, 9)
+
+template <typename T>
+__device__ __forceinline__ bool ring_fft_fixed(const Dev<T>& d, int l, cx<T>* buf, int N, int logN, int nb, bool inverse)
+{
+    if constexpr (sizeof(T) != 4) {
+        return false;
+    } else {
+        if (!d.ring_ct) return false;
+        const int m3 = d.ringM3[l];
+        const int per_call = max(1, min(nb, (m3 ? (FFT_REGS / 3) * 3 * NT : FFT_BLOCK_POINTS) / N));
+        const int code = (m3 << 8) | logN;
+        switch (code) {
+#define PAT_RC_CASE(a, b)                                                            \
+    case ((a) << 8) | (b):                                                           \
+        for (int i = 0; i < nb; i += per_call) {                                     \
+            if (inverse) ring_fft_ct<a, b, true>(d, buf + i * N, min(per_call, nb - i));  \
+            else ring_fft_ct<a, b, false>(d, buf + i * N, min(per_call, nb - i));         \
+        }                                                                            \
+        return true;
+            PAT_RC_SIZES(PAT_RC_CASE)
+#undef PAT_RC_CASE
+            default: return false;
+        }
+    }
+}
+
 // The ring transforms of nb images (ring l: N = 2^logN or 3 * 2^logN points),
 // as many sequences per lds_fft call as its register budget allows.
 template <typename T>
 __device__ __forceinline__ void ring_fft(const Dev<T>& d, int l, cx<T>* buf, int N, int logN, int nb, bool inverse)
 {
+    if (ring_fft_fixed(d, l, buf, N, logN, nb, inverse)) return;
     if (d.ringM3[l]) {
         const int per_call = max(1, min(nb, ((FFT_REGS / 3) * 3 * NT) / N));
         for (int i = 0; i < nb; i += per_call)
@@ -896,7 +1066,8 @@ __global__ __launch_bounds__(NT) void dct_cols(Dev<T> d, const cx<T>* in, cx<T>*
 //   * column buffers are padded by one entry in eight, which keeps the
 //     early passes' scattered writes (stride 8 entries) on distinct banks.
 // ---------------------------------------------------------------------------
-constexpr int DW_WAVES = 4;  // waves per block (NT / 64)
+constexpr int DW_LPC = 128;             // lanes (two waves) per column group
+constexpr int DW_GROUPS = NT / DW_LPC;  // column groups per block
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -905,16 +1076,17 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ constexpr int dw_phys(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int dw_phys(int i) { return i + (i >> 3); }
 
 template <int M3, int LOGP>
 struct DwShape {
     static constexpr int M = (M3 ? 3 : 1) << LOGP;
     static constexpr int WPTS = M3 ? (M >= 1536 ? M : 1536) : (M >= 1024 ? M : 1024);
-    static constexpr int NC = WPTS / M;                       // columns per wave
-    static constexpr int CB = NC * DW_WAVES;                  // columns per block
-    static constexpr int CP = dw_phys(M) + 2;                 // column pitch in LDS (slots 0..M, padded)
-    static constexpr int PER = WPTS / 64;                     // points per lane
+    static constexpr int NC = WPTS / M;                       // columns per column group
+    static constexpr int CB = NC * DW_GROUPS;                 // columns per block
+    // column pitch in LDS: slots 0..M (padded), rounded to 8 mod 32 entries so
+    // that the block's columns start 16 banks apart in the row-segment phases
+    static constexpr int CP = (dw_phys(M) + 1 + 23) / 32 * 32 + 8;
     static constexpr size_t LDS = sizeof(cx<float>) * (size_t)CB * CP;
 };
 
@@ -930,6 +1102,27 @@ __device__ __forceinline__ void dft3_f(cx<float>& a0, cx<float>& a1, cx<float>& 
     a2 = m - jd;
 }
 
+// Twiddles W^r, r = 1 .. R-1, of a radix-R butterfly from the table entries
+// W^(2^e) that tab(e) returns (at most three products each, no further loads).
+template <int R, typename Tab>
+__device__ __forceinline__ void tw_powers(Tab tab, cx<float> (&w)[R])
+{
+    constexpr int LR = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+    cx<float> wp[LR];
+#pragma unroll
+    for (int e = 0; e < LR; ++e) wp[e] = tab(e);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        bool first = true;
+#pragma unroll
+        for (int e = 0; e < LR; ++e)
+            if (r & (1 << e)) {
+                w[r] = first ? wp[e] : cmul(w[r], wp[e]);
+                first = false;
+            }
+    }
+}
+
 // One Stockham pass over the wave's NC sequences of length M (radix R,
 // sub-transform length NS), inverse direction (e^{+2 pi i ...}), in place:
 // every lane reads all its inputs before any lane writes.  twd holds
@@ -937,32 +1130,57 @@ __device__ __forceinline__ void dft3_f(cx<float>& a0, cx<float>& a1, cx<float>& 
 template <int M, int NC, int CP, int R, int NS>
 __device__ __forceinline__ void dw_pass(PAT_LDS cx<float>* buf, const PAT_GLOBAL cx<float>* __restrict__ twd, int lane)
 {
+    constexpr int L = DW_LPC;
     constexpr int NBS = M / R;               // butterflies per sequence
-    constexpr int PER = NC * NBS / 64;       // butterflies per lane
-    static_assert(NC * NBS % 64 == 0, "butterflies must fill the wave");
+    constexpr int NBT = NC * NBS;            // butterflies of the column group
+    constexpr int PER = (NBT + L - 1) / L;   // butterflies per lane (the last round may be partial)
     cx<float> v[PER][R];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        const int t = lane + 64 * u;
+        const int t = lane + L * u;
+        if (NBT % L != 0 && t >= NBT) continue;
         const int b = t / NBS, tt = t - b * NBS;
         const PAT_LDS cx<float>* s = buf + b * CP;
 #pragma unroll
         for (int r = 0; r < R; ++r) v[u][r] = ld_lds(s + dw_phys(tt + r * NBS));
     }
-    wave_sync();
+    __syncthreads();
+    // twiddles W_{R NS}^{r k} = twd[r k STEP], conjugated (inverse direction).
+    // k = t mod NS: for NS <= L it is lane mod NS for every butterfly of the
+    // lane (loaded once); for the radix-3 pass (NS = 2^LOGP >= L) it is
+    // lane + L u' and W_M^k = W_M^lane W_M^{L u'} (the second factor uniform).
+    constexpr int STEP = 2 * M / (R * NS);
+    cx<float> wl[R];
+    if constexpr (NS > 1 && NS <= L && R != 3) {
+        const int k = lane & (NS - 1);
+        tw_powers<R>([&](int e) { cx<float> w = ld_glb(twd + ((k * STEP) << e)); w.y = -w.y; return w; }, wl);
+    }
+    cx<float> wlane = {1.f, 0.f};
+    if constexpr (R == 3) {
+        static_assert(NS >= L, "radix-3 pass after sub-transforms of at least L points");
+        wlane = ld_glb(twd + 2 * lane);
+        wlane.y = -wlane.y;
+    }
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        const int t = lane + 64 * u;
+        const int t = lane + L * u;
+        if (NBT % L != 0 && t >= NBT) continue;
         const int b = t / NBS, tt = t - b * NBS;
         const int k = tt % NS;
-        if constexpr (NS > 1) {
-            constexpr int STEP = 2 * M / (R * NS);   // W_{R NS}^{r k} = twd[r k STEP] (conjugated: inverse)
+        if constexpr (R == 3) {
+            cx<float> wu = ld_glb(twd + 2 * L * ((u % (NS / L))));   // uniform: W_M^{L u'}
+            wu.y = -wu.y;
+            const cx<float> w1 = cmul(wlane, wu), w2 = cmul(w1, w1);
+            v[u][1] = cmul(v[u][1], w1);
+            v[u][2] = cmul(v[u][2], w2);
+        } else if constexpr (NS > L) {
+            cx<float> w[R];
+            tw_powers<R>([&](int e) { cx<float> x = ld_glb(twd + ((k * STEP) << e)); x.y = -x.y; return x; }, w);
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                cx<float> w = ld_glb(twd + r * k * STEP);
-                w.y = -w.y;
-                v[u][r] = cmul(v[u][r], w);
-            }
+            for (int r = 1; r < R; ++r) v[u][r] = cmul(v[u][r], w[r]);
+        } else if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[u][r] = cmul(v[u][r], wl[r]);
         }
         if constexpr (R == 3) dft3_f<true>(v[u][0], v[u][1], v[u][2]);
         else dft_reg<float, R>(v[u], true);
@@ -971,7 +1189,7 @@ __device__ __forceinline__ void dw_pass(PAT_LDS cx<float>* buf, const PAT_GLOBAL
 #pragma unroll
         for (int r = 0; r < R; ++r) st_lds(s + dw_phys(base + r * NS), v[u][r]);
     }
-    wave_sync();
+    __syncthreads();
 }
 
 // radix of pass p of the power-of-two factor 2^LOGP: radix 8 while at least
@@ -1046,14 +1264,19 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
         st_lds(lbuf + c * CP + dw_phys(x), cx<float>{0.f, 0.f});
     }
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    PAT_LDS cx<float>* wb = lbuf + wave * NC * CP;
+    constexpr int L = DW_LPC;
+    // block-wide partial results of the two waves of each column group
+    __shared__ cx<float> red[DW_GROUPS][4][2];
+    const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L, wv = lane >> 6;
+    PAT_LDS cx<float>* wb = lbuf + grp * NC * CP;
     // (2) per column: F_1's interior sum and g_j = (f_j + f_{M-j})/2 - sin(pi j/M) (f_j - f_{M-j})
     cx<float> F1[NC], e0[NC], eM[NC];
     {
-        constexpr int PJ = M / 64;
-        static_assert(M % 64 == 0, "M must be a multiple of 64");
+        constexpr int PJ = M / L;
+        static_assert(M % L == 0 && NC <= 4, "M must be a multiple of the column group");
         cx<float> gv[NC][PJ];
+        // e^{-i pi j/M} for j = lane + L v: the lane's factor times a uniform one
+        const cx<float> wlane = ld_glb(twd + lane);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const PAT_LDS cx<float>* col = wb + c * CP;
@@ -1062,24 +1285,30 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
             cx<float> acc = {0.f, 0.f};
 #pragma unroll
             for (int v = 0; v < PJ; ++v) {
-                const int j = lane + 64 * v;
+                const int j = lane + L * v;
                 const cx<float> fj = ld_lds(col + dw_phys(j));
                 const cx<float> fm = ld_lds(col + dw_phys(M - j));
-                const cx<float> w = ld_glb(twd + j);      // (cos(pi j/M), -sin(pi j/M))
+                const cx<float> w = cmul(wlane, ld_glb(twd + L * v));   // (cos(pi j/M), -sin(pi j/M))
                 acc = acc + fj * w.x;
                 const float sj = -w.y;
                 gv[c][v] = {0.5f * (fj.x + fm.x) - sj * (fj.x - fm.x), 0.5f * (fj.y + fm.y) - sj * (fj.y - fm.y)};
             }
             acc = wave_sum(acc);
-            // sum over x = 0..M-1 of f_x cos(pi x/M) minus f_0, plus (f_0 - f_M)/2
+            if ((lane & 63) == 0) red[grp][c][wv] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            // the group's two wave sums in a fixed order; sum over x = 0..M-1 of
+            // f_x cos(pi x/M) minus f_0, plus (f_0 - f_M)/2
+            const cx<float> acc = red[grp][c][0] + red[grp][c][1];
             F1[c] = {acc.x - 0.5f * (e0[c].x + eM[c].x), acc.y - 0.5f * (e0[c].y + eM[c].y)};
         }
-        wave_sync();
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
-            for (int v = 0; v < PJ; ++v) st_lds(wb + c * CP + dw_phys(lane + 64 * v), gv[c][v]);
-        wave_sync();
+            for (int v = 0; v < PJ; ++v) st_lds(wb + c * CP + dw_phys(lane + L * v), gv[c][v]);
+        __syncthreads();
     }
     // (3) G_q = sum_j g_j e^{2 pi i j q/M}
     dw_pow2_passes<M, NC, CP, LOGP, 0>(wb, twd, lane);
@@ -1088,8 +1317,8 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
     // F_{2q+1} = F_1 + S_q, S_q = sum_{p=1..q} -(i/2)(G_p - G_{M-p});
     // out(y) = F_y + (f_0 + (-1)^y f_M)/2, written to slot y - y0
     const int Q = (ymax + 1) >> 1;             // q needed: even y = 2q <= ymax, odd y = 2q + 1 <= ymax
-    constexpr int CHMAX = (M / 2 + 63) / 64;   // Q <= M/2
-    const int CH = (Q + 63) >> 6;
+    constexpr int CHMAX = (M / 2 + L - 1) / L; // Q <= M/2
+    const int CH = (Q + L - 1) / L;
     cx<float> outv[NC][CHMAX][2];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -1108,7 +1337,14 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
             pre[i] = run;
             outv[c][i][0] = ev;
         }
-        const cx<float> off = wave_excl_scan(run, lane);
+        // exclusive prefix of the chunk totals over the group's lanes: within each
+        // wave, then the first wave's total for the second (fixed order)
+        cx<float> off = wave_excl_scan(run, lane & 63);
+        const cx<float> incl = off + run;
+        if ((lane & 63) == 63) red[grp][c][wv] = incl;
+        __syncthreads();
+        if (wv == 1) off = off + red[grp][c][0];
+        __syncthreads();
         const float hx0 = 0.5f * e0[c].x, hy0 = 0.5f * e0[c].y, hxM = 0.5f * eM[c].x, hyM = 0.5f * eM[c].y;
 #pragma unroll
         for (int i = 0; i < CHMAX; ++i) {
@@ -1121,7 +1357,7 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
     cx<float> G0[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) G0[c] = ld_lds(wb + c * CP);
-    wave_sync();
+    __syncthreads();
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         PAT_LDS cx<float>* col = wb + c * CP;
@@ -1171,7 +1407,423 @@ __device__ __forceinline__ void dct_wave_dispatch(const Dev<float>& d, Blk bk, c
     }
 }
 
-// G_k(t_j) += i^k sum_l Mk[k][j][l] Ulow[l][k], k = 0..klow
+// ---------------------------------------------------------------------------
+// Power-of-two transforms of one 64-lane wave (FP32): the 2D FFT's row and
+// column passes and the angular synthesis, with lengths known at compile time.
+// Each wave owns one sequence of N = 2^LOGN points in a padded LDS buffer
+// (dw_phys: one pad entry every eight) and runs Stockham passes whose
+// butterfly counts, strides and radices (8 and 16, or 4 for N = 256) are
+// constants; only wave-level ordering is needed between passes.  Twiddles come
+// from the plan's table e^{-2 pi i j / Nmax}.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int wf_radix(int LOGN, int p)
+{
+    return LOGN == 8 ? 4 : LOGN == 9 ? 8 : LOGN == 10 ? (p < 2 ? 8 : 16) : LOGN == 11 ? (p < 1 ? 8 : 16) : 16;
+}
+__host__ __device__ constexpr int wf_npass(int LOGN) { return LOGN == 8 ? 4 : 3; }
+__host__ __device__ constexpr int wf_ns(int LOGN, int p) { return p == 0 ? 1 : wf_ns(LOGN, p - 1) * wf_radix(LOGN, p - 1); }
+__host__ __device__ constexpr int wf_log2(int v) { return v <= 1 ? 0 : 1 + wf_log2(v / 2); }
+
+template <int N, int R, int NS, bool INV>
+__device__ __forceinline__ void wf_pass(PAT_LDS cx<float>* buf, const PAT_GLOBAL cx<float>* __restrict__ tw, int logNmax,
+                                        int lane)
+{
+    constexpr int NB = N / R;
+    constexpr int PER = NB / 64;
+    static_assert(NB % 64 == 0, "butterflies must fill the wave");
+    cx<float> v[PER][R];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = lane + 64 * u;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[u][r] = ld_lds(buf + dw_phys(t + r * NB));
+    }
+    wave_sync();
+    // twiddles W_{R NS}^{r k} = tw[(r k) << sh] from W^1, W^2, W^4 (, W^8);
+    // for NS <= 64, k = lane mod NS for every butterfly of the lane
+    const int sh = logNmax - wf_log2(R * NS);
+    auto tab = [&](int k, int e) {
+        cx<float> w = ld_glb(tw + ((k << e) << sh));
+        if (INV) w.y = -w.y;
+        return w;
+    };
+    cx<float> wl[R];
+    if constexpr (NS > 1 && NS <= 64) tw_powers<R>([&](int e) { return tab(lane & (NS - 1), e); }, wl);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = lane + 64 * u;
+        const int k = t % NS;
+        if constexpr (NS > 64) {
+            cx<float> w[R];
+            tw_powers<R>([&](int e) { return tab(k, e); }, w);
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[u][r] = cmul(v[u][r], w[r]);
+        } else if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[u][r] = cmul(v[u][r], wl[r]);
+        }
+        dft_reg<float, R>(v[u], INV);
+        const int base = (t / NS) * NS * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) st_lds(buf + dw_phys(base + r * NS), v[u][r]);
+    }
+    wave_sync();
+}
+
+template <int LOGN, bool INV, int P = 0>
+__device__ __forceinline__ void wf_fft(PAT_LDS cx<float>* buf, const PAT_GLOBAL cx<float>* tw, int logNmax, int lane)
+{
+    if constexpr (P < wf_npass(LOGN)) {
+        wf_pass<(1 << LOGN), wf_radix(LOGN, P), wf_ns(LOGN, P), INV>(buf, tw, logNmax, lane);
+        wf_fft<LOGN, INV, P + 1>(buf, tw, logNmax, lane);
+    }
+}
+
+constexpr int WF_WAVES = 4;                 // waves (sequences) per block
+__host__ __device__ constexpr int wf_pitch(int LOGN) { return (dw_phys(1 << LOGN) + 1 + 23) / 32 * 32 + 8; }
+
+// rows_fwd with one wave per pair of image rows (p1 = 2 pair, p2 = p1 + 1): the
+// pre-corrected rows, zero-extended to Ng and packed as one complex sequence,
+// one FFT, then the half spectra of both rows.
+template <int LOGN>
+__device__ __forceinline__ void rows_fwd_w_body(const Dev<float>& d, Blk bk, const float* __restrict__ f, long fstride,
+                                                cx<float>* R, size_t ws_img)
+{
+    constexpr int Ng = 1 << LOGN;
+    extern __shared__ unsigned char smem_raw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    PAT_LDS cx<float>* buf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw) + wave * wf_pitch(LOGN);
+    const int pair = bk.x * WF_WAVES + wave, b = bk.y;
+    const int n = d.n, p1 = 2 * pair, p2 = p1 + 1;
+    if (p1 >= n) return;   // whole wave: no block-wide synchronisation follows
+    const float* fb = f + (size_t)b * fstride;
+    cx<float>* Rb = reinterpret_cast<cx<float>*>(reinterpret_cast<char*>(R) + (size_t)b * ws_img);
+    const float s1 = d.Dq[p1] * d.pre_scale;
+    const float s2 = p2 < n ? d.Dq[p2] * d.pre_scale : 0.f;
+    const int h = n / 2;
+    for (int i = lane; i < Ng; i += 64) {
+        // position i holds column q = i + n/2 (i < n - n/2) or q = i - Ng + n/2 (i >= Ng - n/2)
+        const int q = i < n - h ? i + h : (i >= Ng - h ? i - Ng + h : -1);
+        cx<float> v = {0.f, 0.f};
+        if (q >= 0) {
+            const float dq = d.Dq[q];
+            v.x = in_mask(d, p1, q) ? fb[(size_t)p1 * n + q] * dq * s1 : 0.f;
+            v.y = (p2 < n && in_mask(d, p2, q)) ? fb[(size_t)p2 * n + q] * dq * s2 : 0.f;
+        }
+        st_lds(buf + dw_phys(i), v);
+    }
+    wave_sync();
+    wf_fft<LOGN, false>(buf, (const PAT_GLOBAL cx<float>*)d.tw, d.logNmax, lane);
+    for (int g = lane; g <= Ng / 2; g += 64) {
+        const cx<float> zg = ld_lds(buf + dw_phys(g)), zm = ld_lds(buf + dw_phys((Ng - g) & (Ng - 1)));
+        const cx<float> x1 = {0.5f * (zg.x + zm.x), 0.5f * (zg.y - zm.y)};
+        const cx<float> x2 = {0.5f * (zg.y + zm.y), 0.5f * (zm.x - zg.x)};
+        Rb[(size_t)p1 * d.Rw + g] = x1;
+        if (p2 < n) Rb[(size_t)p2 * d.Rw + g] = x2;
+    }
+}
+
+// rows_adj with one wave per pair of image rows (transpose of rows_fwd_w_body).
+template <int LOGN>
+__device__ __forceinline__ void rows_adj_w_body(const Dev<float>& d, Blk bk, const cx<float>* R, float* f, long fstride,
+                                                size_t ws_img)
+{
+    constexpr int Ng = 1 << LOGN, hN = Ng / 2;
+    extern __shared__ unsigned char smem_raw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    PAT_LDS cx<float>* buf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw) + wave * wf_pitch(LOGN);
+    const int pair = bk.x * WF_WAVES + wave, b = bk.y;
+    const int n = d.n, p1 = 2 * pair, p2 = p1 + 1;
+    if (p1 >= n) return;
+    const bool has2 = p2 < n;
+    const cx<float>* Rb = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(R) + (size_t)b * ws_img);
+    float* fb = f + (size_t)b * fstride;
+    for (int g = lane; g < Ng; g += 64) {
+        cx<float> xa, xb;
+        if (g == 0 || g == hN) {
+            xa = {Rb[(size_t)p1 * d.Rw + g].x, 0.f};
+            xb = {has2 ? Rb[(size_t)p2 * d.Rw + g].x : 0.f, 0.f};
+        } else if (g < hN) {
+            xa = Rb[(size_t)p1 * d.Rw + g] * 0.5f;
+            xb = has2 ? Rb[(size_t)p2 * d.Rw + g] * 0.5f : cx<float>{0.f, 0.f};
+        } else {
+            xa = conjg(Rb[(size_t)p1 * d.Rw + (Ng - g)]) * 0.5f;
+            xb = has2 ? conjg(Rb[(size_t)p2 * d.Rw + (Ng - g)]) * 0.5f : cx<float>{0.f, 0.f};
+        }
+        st_lds(buf + dw_phys(g), cx<float>{xa.x - xb.y, xa.y + xb.x});
+    }
+    wave_sync();
+    wf_fft<LOGN, true>(buf, (const PAT_GLOBAL cx<float>*)d.tw, d.logNmax, lane);
+    const float s1 = d.Dq[p1] * d.pre_scale * d.adj_scale;
+    const float s2 = has2 ? d.Dq[p2] * d.pre_scale * d.adj_scale : 0.f;
+    for (int q = lane; q < n; q += 64) {
+        const cx<float> v = ld_lds(buf + dw_phys((q - n / 2 + Ng) & (Ng - 1)));
+        fb[(size_t)p1 * n + q] = in_mask(d, p1, q) ? v.x * d.Dq[q] * s1 : 0.f;
+        if (has2) fb[(size_t)p2 * n + q] = in_mask(d, p2, q) ? v.y * d.Dq[q] * s2 : 0.f;
+    }
+}
+
+// cols_fwd with one wave per spectrum column: the block's WF_WAVES adjacent
+// columns are loaded and stored as row segments, each wave transforms its own.
+template <int LOGN>
+__device__ __forceinline__ void cols_fwd_w_body(const Dev<float>& d, Blk bk, const cx<float>* R, cx<float>* E,
+                                                size_t ws_img)
+{
+    constexpr int Ng = 1 << LOGN, CB = WF_WAVES, CP = wf_pitch(LOGN);
+    extern __shared__ unsigned char smem_raw[];
+    PAT_LDS cx<float>* lbuf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw);
+    const int x0 = bk.x * CB, b = bk.y, n = d.n;
+    const cx<float>* Rb = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(R) + (size_t)b * ws_img);
+    cx<float>* Eb = reinterpret_cast<cx<float>*>(reinterpret_cast<char*>(E) + (size_t)b * ws_img);
+    // rows p of R land at (p - n/2) mod Ng; positions [n - n/2, Ng - n/2) stay zero
+    const int h = n / 2, nz = Ng - n;
+    for (int i = threadIdx.x; i < CB * n; i += NT) {
+        const int p = i / CB, c = i - p * CB;
+        const int gx = x0 + c;
+        const cx<float> v = gx < d.Rw ? Rb[(size_t)p * d.Rw + gx] : cx<float>{0.f, 0.f};
+        st_lds(lbuf + c * CP + dw_phys((p - h + Ng) & (Ng - 1)), v);
+    }
+    for (int i = threadIdx.x; i < CB * nz; i += NT) {
+        const int z = i / CB, c = i - z * CB;
+        st_lds(lbuf + c * CP + dw_phys(n - h + z), cx<float>{0.f, 0.f});
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    wf_fft<LOGN, false>(lbuf + wave * CP, (const PAT_GLOBAL cx<float>*)d.tw, d.logNmax, lane);
+    __syncthreads();
+    for (int i = threadIdx.x; i < CB * Ng; i += NT) {
+        const int gy = i / CB, c = i - gy * CB;
+        const int gx = x0 + c;
+        if (gx >= d.Rw) continue;
+        const cx<float> v = ld_lds(lbuf + c * CP + dw_phys(gy));
+        Eb[(size_t)gy * d.Ew + gx + d.hw] = v;
+        const int gym = (Ng - gy) & (Ng - 1);
+        if (gx >= 1 && gx <= d.hw) Eb[(size_t)gym * d.Ew + d.hw - gx] = conjg(v);
+        if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) Eb[(size_t)gym * d.Ew + d.hw + Ng - gx] = conjg(v);
+    }
+}
+
+// cols_adj with one wave per spectrum column (transpose of cols_fwd_w_body).
+template <int LOGN>
+__device__ __forceinline__ void cols_adj_w_body(const Dev<float>& d, Blk bk, const cx<float>* E, cx<float>* R,
+                                                size_t ws_img)
+{
+    constexpr int Ng = 1 << LOGN, CB = WF_WAVES, CP = wf_pitch(LOGN);
+    extern __shared__ unsigned char smem_raw[];
+    PAT_LDS cx<float>* lbuf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw);
+    const int x0 = bk.x * CB, b = bk.y, n = d.n;
+    const cx<float>* Eb = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(E) + (size_t)b * ws_img);
+    cx<float>* Rb = reinterpret_cast<cx<float>*>(reinterpret_cast<char*>(R) + (size_t)b * ws_img);
+    for (int i = threadIdx.x; i < CB * Ng; i += NT) {
+        const int gy = i / CB, c = i - gy * CB;
+        const int gx = x0 + c;
+        cx<float> v = {0.f, 0.f};
+        if (gx < d.Rw) {
+            v = Eb[(size_t)gy * d.Ew + gx + d.hw];
+            const int gym = (Ng - gy) & (Ng - 1);
+            if (gx >= 1 && gx <= d.hw) v = v + conjg(Eb[(size_t)gym * d.Ew + d.hw - gx]);
+            if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) v = v + conjg(Eb[(size_t)gym * d.Ew + d.hw + Ng - gx]);
+        }
+        st_lds(lbuf + c * CP + dw_phys(gy), v);
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    wf_fft<LOGN, true>(lbuf + wave * CP, (const PAT_GLOBAL cx<float>*)d.tw, d.logNmax, lane);
+    __syncthreads();
+    for (int i = threadIdx.x; i < CB * n; i += NT) {
+        const int p = i / CB, c = i - p * CB;
+        const int gx = x0 + c;
+        if (gx < d.Rw) Rb[(size_t)p * d.Rw + gx] = ld_lds(lbuf + c * CP + dw_phys((p - n / 2 + Ng) & (Ng - 1)));
+    }
+}
+
+// synth_fwd with one wave per pair of time rows (j1 = 2 pair, j2 = j1 + 1):
+// Q_r = Herm(Z1)_r + i Herm(Z2)_r from the folded harmonics (each lane owns the
+// pair r, mf - r and reads both straight from G), one inverse FFT of mf points,
+// real and imaginary parts to the two trace rows.
+template <int LOGM>
+__device__ __forceinline__ void synth_fwd_w_body(const Dev<float>& d, Blk bk, const cx<float>* G, float* g, long gstride,
+                                                 size_t ws_img)
+{
+    constexpr int mf = 1 << LOGM;
+    extern __shared__ unsigned char smem_raw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    PAT_LDS cx<float>* buf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw) + wave * wf_pitch(LOGM);
+    const int pair = bk.x * WF_WAVES + wave, b = bk.y;
+    const int j1 = 2 * pair, j2 = j1 + 1;
+    if (j1 >= d.nt) return;
+    const bool has2 = j2 < d.nt;
+    const cx<float>* Gb = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(G) + (size_t)b * ws_img);
+    float* gb = g + (size_t)b * gstride;
+    const cx<float>* G1 = Gb + (size_t)j1 * d.Kp;
+    const cx<float>* G2 = Gb + (size_t)j2 * d.Kp;
+    auto fold = [&](const cx<float>* row, int r) -> cx<float> {
+        cx<float> z = {0.f, 0.f};
+        for (int k = r; k <= d.K; k += mf) z = z + cmul(d.phase[k] * (k == 0 ? 1.f : 2.f), row[k]);
+        return z;
+    };
+    for (int r = lane; r <= mf / 2; r += 64) {
+        const int rm = r == 0 ? 0 : mf - r;
+        const cx<float> a = fold(G1, r), am = fold(G1, rm);
+        const cx<float> c = has2 ? fold(G2, r) : cx<float>{0.f, 0.f};
+        const cx<float> cm = has2 ? fold(G2, rm) : cx<float>{0.f, 0.f};
+        const cx<float> h1 = {0.5f * (a.x + am.x), 0.5f * (a.y - am.y)};
+        const cx<float> h2 = {0.5f * (c.x + cm.x), 0.5f * (c.y - cm.y)};
+        st_lds(buf + dw_phys(r), cx<float>{h1.x - h2.y, h1.y + h2.x});
+        if (rm != r) st_lds(buf + dw_phys(rm), cx<float>{h1.x + h2.y, h2.x - h1.y});
+    }
+    wave_sync();
+    wf_fft<LOGM, true>(buf, (const PAT_GLOBAL cx<float>*)d.tw, d.logNmax, lane);
+    for (int i = lane; i < d.m; i += 64) {
+        const cx<float> v = ld_lds(buf + dw_phys(i));
+        gb[(size_t)j1 * d.m + i] = v.x;
+        if (has2) gb[(size_t)j2 * d.m + i] = v.y;
+    }
+}
+
+// synth_adj with one wave per pair of time rows (transpose of synth_fwd_w_body).
+template <int LOGM>
+__device__ __forceinline__ void synth_adj_w_body(const Dev<float>& d, Blk bk, const float* g, long gstride, cx<float>* G,
+                                                 size_t ws_img)
+{
+    constexpr int mf = 1 << LOGM;
+    extern __shared__ unsigned char smem_raw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    PAT_LDS cx<float>* buf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw) + wave * wf_pitch(LOGM);
+    const int pair = bk.x * WF_WAVES + wave, b = bk.y;
+    const int j1 = 2 * pair, j2 = j1 + 1;
+    if (j1 >= d.nt) return;
+    const bool has2 = j2 < d.nt;
+    const float* gb = g + (size_t)b * gstride;
+    cx<float>* Gb = reinterpret_cast<cx<float>*>(reinterpret_cast<char*>(G) + (size_t)b * ws_img);
+    for (int i = lane; i < mf; i += 64) {
+        const float a = i < d.m ? gb[(size_t)j1 * d.m + i] : 0.f;
+        const float c = (i < d.m && has2) ? gb[(size_t)j2 * d.m + i] : 0.f;
+        st_lds(buf + dw_phys(i), cx<float>{a, c});
+    }
+    wave_sync();
+    wf_fft<LOGM, false>(buf, (const PAT_GLOBAL cx<float>*)d.tw, d.logNmax, lane);
+    for (int k = lane; k < d.Kp; k += 64) {
+        cx<float> y1 = {0.f, 0.f}, y2 = {0.f, 0.f};
+        if (k <= d.K) {
+            const int r = k & (mf - 1), rm = r == 0 ? 0 : mf - r;
+            const cx<float> zr = ld_lds(buf + dw_phys(r)), zm = ld_lds(buf + dw_phys(rm));
+            y1 = {0.5f * (zr.x + zm.x), 0.5f * (zr.y - zm.y)};
+            y2 = {0.5f * (zr.y + zm.y), 0.5f * (zm.x - zr.x)};
+            const cx<float> ph = conjg(d.phase[k]) * (k == 0 ? 1.f : 2.f);
+            y1 = cmul(ph, y1);
+            y2 = cmul(ph, y2);
+        }
+        Gb[(size_t)j1 * d.Kp + k] = y1;
+        if (has2) Gb[(size_t)j2 * d.Kp + k] = y2;
+    }
+}
+
+#define PAT_WF_SIZES(X) X(8) X(9) X(10) X(11)
+
+template <int LOGN>
+__global__ __launch_bounds__(NT) void rows_fwd_w(Dev<float> d, const float* __restrict__ f, long fstride, cx<float>* R,
+                                                 size_t ws_img)
+{
+    rows_fwd_w_body<LOGN>(d, blk_xcd(), f, fstride, R, ws_img);
+}
+template <int LOGN>
+__global__ __launch_bounds__(NT) void rows_adj_w(Dev<float> d, const cx<float>* R, float* f, long fstride, size_t ws_img)
+{
+    rows_adj_w_body<LOGN>(d, blk_xcd(), R, f, fstride, ws_img);
+}
+template <int LOGN>
+__global__ __launch_bounds__(NT) void cols_fwd_w(Dev<float> d, const cx<float>* R, cx<float>* E, size_t ws_img)
+{
+    cols_fwd_w_body<LOGN>(d, blk_xcd(), R, E, ws_img);
+}
+template <int LOGN>
+__global__ __launch_bounds__(NT) void cols_adj_w(Dev<float> d, const cx<float>* E, cx<float>* R, size_t ws_img)
+{
+    cols_adj_w_body<LOGN>(d, blk_xcd(), E, R, ws_img);
+}
+template <int LOGM>
+__global__ __launch_bounds__(NT) void synth_fwd_w(Dev<float> d, const cx<float>* G, float* g, long gstride, size_t ws_img)
+{
+    synth_fwd_w_body<LOGM>(d, blk_xcd(), G, g, gstride, ws_img);
+}
+template <int LOGM>
+__global__ __launch_bounds__(NT) void synth_adj_w(Dev<float> d, const float* g, long gstride, cx<float>* G, size_t ws_img)
+{
+    synth_adj_w_body<LOGM>(d, blk_xcd(), g, gstride, G, ws_img);
+}
+
+__device__ __forceinline__ void rows_fwd_w_dispatch(const Dev<float>& d, Blk bk, const float* f, long fs, cx<float>* R,
+                                                    size_t wi)
+{
+    switch (d.wfRows) {
+#define PAT_WF_CASE(L) \
+    case L: rows_fwd_w_body<L>(d, bk, f, fs, R, wi); break;
+        PAT_WF_SIZES(PAT_WF_CASE)
+#undef PAT_WF_CASE
+        default: break;
+    }
+}
+__device__ __forceinline__ void rows_adj_w_dispatch(const Dev<float>& d, Blk bk, const cx<float>* R, float* f, long fs,
+                                                    size_t wi)
+{
+    switch (d.wfRows) {
+#define PAT_WF_CASE(L) \
+    case L: rows_adj_w_body<L>(d, bk, R, f, fs, wi); break;
+        PAT_WF_SIZES(PAT_WF_CASE)
+#undef PAT_WF_CASE
+        default: break;
+    }
+}
+__device__ __forceinline__ void cols_fwd_w_dispatch(const Dev<float>& d, Blk bk, const cx<float>* R, cx<float>* E, size_t wi)
+{
+    switch (d.wfRows) {
+#define PAT_WF_CASE(L) \
+    case L: cols_fwd_w_body<L>(d, bk, R, E, wi); break;
+        PAT_WF_SIZES(PAT_WF_CASE)
+#undef PAT_WF_CASE
+        default: break;
+    }
+}
+__device__ __forceinline__ void cols_adj_w_dispatch(const Dev<float>& d, Blk bk, const cx<float>* E, cx<float>* R, size_t wi)
+{
+    switch (d.wfRows) {
+#define PAT_WF_CASE(L) \
+    case L: cols_adj_w_body<L>(d, bk, E, R, wi); break;
+        PAT_WF_SIZES(PAT_WF_CASE)
+#undef PAT_WF_CASE
+        default: break;
+    }
+}
+__device__ __forceinline__ void synth_fwd_w_dispatch(const Dev<float>& d, Blk bk, const cx<float>* G, float* g, long gs,
+                                                     size_t wi)
+{
+    switch (d.wfSynth) {
+#define PAT_WF_CASE(L) \
+    case L: synth_fwd_w_body<L>(d, bk, G, g, gs, wi); break;
+        PAT_WF_SIZES(PAT_WF_CASE)
+#undef PAT_WF_CASE
+        default: break;
+    }
+}
+__device__ __forceinline__ void synth_adj_w_dispatch(const Dev<float>& d, Blk bk, const float* g, long gs, cx<float>* G,
+                                                     size_t wi)
+{
+    switch (d.wfSynth) {
+#define PAT_WF_CASE(L) \
+    case L: synth_adj_w_body<L>(d, bk, g, gs, G, wi); break;
+        PAT_WF_SIZES(PAT_WF_CASE)
+#undef PAT_WF_CASE
+        default: break;
+    }
+}
+
+// G_k(t_j) += i^k sum_l Mk[k][j][l] Ulow[l][k], k = 0..klow.  Each group of
+// LK_LANES consecutive lanes owns one (j, k) output: lane p sums the terms
+// l = p, p + LK_LANES, ..., then the group adds its partial sums in a fixed
+// (butterfly) order, so every output is a short chain of loads.
+constexpr int LK_LANES = 8;
+
 template <typename T>
 __device__ __forceinline__ void lowk_fwd_body(const Dev<T>& d, Blk bk, const cx<T>* Ulow, cx<T>* G, size_t ws_img)
 {
@@ -1179,13 +1831,17 @@ __device__ __forceinline__ void lowk_fwd_body(const Dev<T>& d, Blk bk, const cx<
     const cx<T>* Ub = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(Ulow) + (size_t)b * ws_img);
     cx<T>* Gb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(G) + (size_t)b * ws_img);
     const int items = d.nt * (d.klow + 1);
-    for (int it = bk.x * blockDim.x + threadIdx.x; it < items; it += bk.nx * blockDim.x) {
-        int j = it / (d.klow + 1), k = it - j * (d.klow + 1);
+    const int p = threadIdx.x & (LK_LANES - 1);
+    for (int it = (bk.x * NT + (int)threadIdx.x) / LK_LANES; it < items; it += bk.nx * NT / LK_LANES) {
+        const int j = it / (d.klow + 1), k = it - j * (d.klow + 1);
         const T* row = d.Mk + ((size_t)k * d.nt + j) * d.lcorr;
         cx<T> acc = {T(0), T(0)};
-        for (int l = 0; l < d.lcorr; ++l) acc = acc + Ub[(size_t)l * (d.klow + 1) + k] * row[l];
-        cx<T>* dst = Gb + (size_t)j * d.Kp + k;
-        *dst = *dst + mul_ipow(acc, k);
+        for (int l = p; l < d.lcorr; l += LK_LANES) acc = acc + Ub[(size_t)l * (d.klow + 1) + k] * row[l];
+        acc = group_sum(acc, LK_LANES);
+        if (p == 0) {
+            cx<T>* dst = Gb + (size_t)j * d.Kp + k;
+            *dst = *dst + mul_ipow(acc, k);
+        }
     }
 }
 
@@ -1292,26 +1948,22 @@ __global__ __launch_bounds__(NT) void synth_adj(Dev<T> d, const T* g, long gstri
 }
 
 // Ulow_hat[l][k] = conj(i^k) sum_j Mk[k][j][l] G_hat[j][k]; one block per ring l
-// (the transposed copy MkT, so that the block's threads read consecutive t_j).
+// (the transposed copy MkT, so that lanes read consecutive t_j).  Wave w of the
+// block handles k = w, w + 4, ...: its lanes sum strided runs of j, then the wave
+// adds them in a fixed (butterfly) order -- no block-wide synchronisation.
 template <typename T>
 __device__ __forceinline__ void lowk_adj_body(const Dev<T>& d, Blk bk, const cx<T>* G, cx<T>* Ulow, size_t ws_img)
 {
-    __shared__ cx<T> red[NT];
     const int b = bk.y, l = bk.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const cx<T>* Gb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(G) + (size_t)b * ws_img);
     cx<T>* Ub = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(Ulow) + (size_t)b * ws_img);
-    for (int k = 0; k <= d.klow; ++k) {
+    for (int k = wave; k <= d.klow; k += NT / 64) {
+        const T* row = d.MkT + ((size_t)k * d.lcorr + l) * d.nt;
         cx<T> acc = {T(0), T(0)};
-        for (int j = threadIdx.x; j < d.nt; j += blockDim.x)
-            acc = acc + Gb[(size_t)j * d.Kp + k] * d.MkT[((size_t)k * d.lcorr + l) * d.nt + j];
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) Ub[(size_t)l * (d.klow + 1) + k] = mul_ipow(red[0], (4 - (k & 3)) & 3);
-        __syncthreads();
+        for (int j = lane; j < d.nt; j += 64) acc = acc + Gb[(size_t)j * d.Kp + k] * row[j];
+        acc = group_sum(acc, 64);
+        if (lane == 0) Ub[(size_t)l * (d.klow + 1) + k] = mul_ipow(acc, (4 - (k & 3)) & 3);
     }
 }
 
@@ -1785,6 +2437,8 @@ struct pat_plan_s {
     // launch-shape choices (defaults from LDS limits; replaced by the autotuner's)
     int cols_cw = 1, dct_cw = 1, ring_g = 1, spread_bc = 16, fft_lr = 4, tw_table = 0, spread_staged = 1;
     int dct_wave_on = 1;                  // 1: use dct_wave where the plan's lengths allow it
+    int wave_fft_on = 1;                  // 1: wave forms of the row / column / synthesis FFT kernels and
+                                          //    compile-time-length ring transforms
     int tuned = 0;                        // 1: measured now, 2: read from the tuning cache
     double tuned_ms = 0.0;
     // optional per-stage timing with HIP events recorded on the launch stream
@@ -1886,6 +2540,20 @@ int dw_variant(const pat::Params& P)
     return code;
 }
 
+// log2 of the row / column FFT length and of the angular transform length for
+// the wave-form kernels (FP32, powers of two 256 .. 2048), 0 where they do not apply
+int wf_rows_variant(const pat::Params& P)
+{
+    const int l = ilog2i(P.Ng);
+    return (P.dt == PAT_F32 && (1 << l) == P.Ng && l >= 8 && l <= 11) ? l : 0;
+}
+int wf_synth_variant(const pat::Params& P)
+{
+    const int l = ilog2i(P.mf);
+    return (P.dt == PAT_F32 && !P.mf3 && (1 << l) == P.mf && l >= 8 && l <= 11) ? l : 0;
+}
+size_t wf_lds(int logn) { return sizeof(cx<float>) * WF_WAVES * (size_t)wf_pitch(logn); }
+
 // columns per block and dynamic LDS bytes of a dct_wave variant
 int dw_columns(int code)
 {
@@ -1906,6 +2574,51 @@ size_t dw_lds(int code)
 #undef PAT_DW_LDS
         default: return 0;
     }
+}
+
+// launches of the wave-form row / column / synthesis kernels (FP32 plans)
+#define PAT_WF_SWITCH(var, KERNEL, grid, lds, ...)                         \
+    switch (var) {                                                         \
+        case 8: KERNEL<8><<<grid, NT, lds, st>>>(__VA_ARGS__); break;      \
+        case 9: KERNEL<9><<<grid, NT, lds, st>>>(__VA_ARGS__); break;      \
+        case 10: KERNEL<10><<<grid, NT, lds, st>>>(__VA_ARGS__); break;    \
+        case 11: KERNEL<11><<<grid, NT, lds, st>>>(__VA_ARGS__); break;    \
+        default: return PAT_EINVAL;                                        \
+    }
+
+dim3 wf_grid_rows(const Dev<float>& d, int B) { return dim3(((d.n + 1) / 2 + WF_WAVES - 1) / WF_WAVES, B); }
+dim3 wf_grid_cols(const Dev<float>& d, int B) { return dim3((d.Rw + WF_WAVES - 1) / WF_WAVES, B); }
+dim3 wf_grid_synth(const Dev<float>& d, int B) { return dim3(((d.nt + 1) / 2 + WF_WAVES - 1) / WF_WAVES, B); }
+
+int launch_rows_fwd_w(const Dev<float>& d, int B, const float* f, long fs, cx<float>* R, size_t wi, hipStream_t st)
+{
+    PAT_WF_SWITCH(d.wfRows, rows_fwd_w, wf_grid_rows(d, B), wf_lds(d.wfRows), d, f, fs, R, wi)
+    return PAT_OK;
+}
+int launch_rows_adj_w(const Dev<float>& d, int B, const cx<float>* R, float* f, long fs, size_t wi, hipStream_t st)
+{
+    PAT_WF_SWITCH(d.wfRows, rows_adj_w, wf_grid_rows(d, B), wf_lds(d.wfRows), d, R, f, fs, wi)
+    return PAT_OK;
+}
+int launch_cols_fwd_w(const Dev<float>& d, int B, const cx<float>* R, cx<float>* E, size_t wi, hipStream_t st)
+{
+    PAT_WF_SWITCH(d.wfRows, cols_fwd_w, wf_grid_cols(d, B), wf_lds(d.wfRows), d, R, E, wi)
+    return PAT_OK;
+}
+int launch_cols_adj_w(const Dev<float>& d, int B, const cx<float>* E, cx<float>* R, size_t wi, hipStream_t st)
+{
+    PAT_WF_SWITCH(d.wfRows, cols_adj_w, wf_grid_cols(d, B), wf_lds(d.wfRows), d, E, R, wi)
+    return PAT_OK;
+}
+int launch_synth_fwd_w(const Dev<float>& d, int B, const cx<float>* G, float* g, long gs, size_t wi, hipStream_t st)
+{
+    PAT_WF_SWITCH(d.wfSynth, synth_fwd_w, wf_grid_synth(d, B), wf_lds(d.wfSynth), d, G, g, gs, wi)
+    return PAT_OK;
+}
+int launch_synth_adj_w(const Dev<float>& d, int B, const float* g, long gs, cx<float>* G, size_t wi, hipStream_t st)
+{
+    PAT_WF_SWITCH(d.wfSynth, synth_adj_w, wf_grid_synth(d, B), wf_lds(d.wfSynth), d, g, gs, G, wi)
+    return PAT_OK;
 }
 
 int launch_dct_wave(const Dev<float>& d, int B, const cx<float>* in, cx<float>* out, size_t wi, int adjoint,
@@ -2025,6 +2738,9 @@ int upload(pat_plan_s* p, Dev<T>& d)
     d.dct_one = dct_one_ok(P, p->dct_cw);
     d.dct_wave = p->dct_wave_on ? dw_variant(P) : 0;
     d.dwCB = dw_columns(d.dct_wave);
+    d.wfRows = p->wave_fft_on ? wf_rows_variant(P) : 0;
+    d.wfSynth = p->wave_fft_on ? wf_synth_variant(P) : 0;
+    d.ring_ct = p->wave_fft_on && sizeof(T) == 4;
     d.fft_lr = p->fft_lr;
     d.tw_table = p->tw_table;
     d.phase_k = (T)(-P.shift * P.h / (0.5 * P.Ng / P.Lam));
@@ -2099,12 +2815,28 @@ int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g
     int rc;
     {
         StageTimer tm(p, st, 0);
-        rows_fwd<T><<<dim3((d.n + 1) / 2, B), NT, cs * d.Ng, st>>>(d, f, fs, R, wi);
+        if constexpr (sizeof(T) == 4) {
+            if (d.wfRows) {
+                if ((rc = launch_rows_fwd_w(d, B, f, fs, R, wi, st))) return fail(rc, "rows_fwd: no wave variant");
+            } else {
+                rows_fwd<T><<<dim3((d.n + 1) / 2, B), NT, cs * d.Ng, st>>>(d, f, fs, R, wi);
+            }
+        } else {
+            rows_fwd<T><<<dim3((d.n + 1) / 2, B), NT, cs * d.Ng, st>>>(d, f, fs, R, wi);
+        }
     }
     if ((rc = check_launch("rows_fwd"))) return rc;
     {
         StageTimer tm(p, st, 1);
-        cols_fwd<T><<<dim3((d.Rw + d.colsCW - 1) / d.colsCW, B), NT, cs * d.Ng * d.colsCW, st>>>(d, R, E, wi);
+        if constexpr (sizeof(T) == 4) {
+            if (d.wfRows) {
+                if ((rc = launch_cols_fwd_w(d, B, R, E, wi, st))) return fail(rc, "cols_fwd: no wave variant");
+            } else {
+                cols_fwd<T><<<dim3((d.Rw + d.colsCW - 1) / d.colsCW, B), NT, cs * d.Ng * d.colsCW, st>>>(d, R, E, wi);
+            }
+        } else {
+            cols_fwd<T><<<dim3((d.Rw + d.colsCW - 1) / d.colsCW, B), NT, cs * d.Ng * d.colsCW, st>>>(d, R, E, wi);
+        }
     }
     if ((rc = check_launch("cols_fwd"))) return rc;
     {
@@ -2128,12 +2860,20 @@ int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g
     if ((rc = check_launch("dct_fwd"))) return rc;
     {
         StageTimer tm(p, st, 4);
-        lowk_fwd<T><<<dim3((d.nt * (d.klow + 1) + NT - 1) / NT, B), NT, 0, st>>>(d, U, G, wi);
+        lowk_fwd<T><<<dim3((d.nt * (d.klow + 1) * LK_LANES + NT - 1) / NT, B), NT, 0, st>>>(d, U, G, wi);
     }
     if ((rc = check_launch("lowk_fwd"))) return rc;
     {
         StageTimer tm(p, st, 5);
-        synth_fwd<T><<<dim3((d.nt + 1) / 2, B), NT, cs * 2 * d.mf, st>>>(d, G, g, gs, wi);
+        if constexpr (sizeof(T) == 4) {
+            if (d.wfSynth) {
+                if ((rc = launch_synth_fwd_w(d, B, G, g, gs, wi, st))) return fail(rc, "synth_fwd: no wave variant");
+            } else {
+                synth_fwd<T><<<dim3((d.nt + 1) / 2, B), NT, cs * 2 * d.mf, st>>>(d, G, g, gs, wi);
+            }
+        } else {
+            synth_fwd<T><<<dim3((d.nt + 1) / 2, B), NT, cs * 2 * d.mf, st>>>(d, G, g, gs, wi);
+        }
     }
     return check_launch("synth_fwd");
 }
@@ -2153,7 +2893,15 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
     int rc;
     {
         StageTimer tm(p, st, 6);
-        synth_adj<T><<<dim3((d.nt + 1) / 2, B), NT, cs * d.mf, st>>>(d, g, gs, G, wi);
+        if constexpr (sizeof(T) == 4) {
+            if (d.wfSynth) {
+                if ((rc = launch_synth_adj_w(d, B, g, gs, G, wi, st))) return fail(rc, "synth_adj: no wave variant");
+            } else {
+                synth_adj<T><<<dim3((d.nt + 1) / 2, B), NT, cs * d.mf, st>>>(d, g, gs, G, wi);
+            }
+        } else {
+            synth_adj<T><<<dim3((d.nt + 1) / 2, B), NT, cs * d.mf, st>>>(d, g, gs, G, wi);
+        }
     }
     if ((rc = check_launch("synth_adj"))) return rc;
     {
@@ -2196,12 +2944,28 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
     if ((rc = check_launch("spread_adj"))) return rc;
     {
         StageTimer tm(p, st, 11);
-        cols_adj<T><<<dim3((d.Rw + d.colsCW - 1) / d.colsCW, B), NT, cs * d.Ng * d.colsCW, st>>>(d, E, R, wi);
+        if constexpr (sizeof(T) == 4) {
+            if (d.wfRows) {
+                if ((rc = launch_cols_adj_w(d, B, E, R, wi, st))) return fail(rc, "cols_adj: no wave variant");
+            } else {
+                cols_adj<T><<<dim3((d.Rw + d.colsCW - 1) / d.colsCW, B), NT, cs * d.Ng * d.colsCW, st>>>(d, E, R, wi);
+            }
+        } else {
+            cols_adj<T><<<dim3((d.Rw + d.colsCW - 1) / d.colsCW, B), NT, cs * d.Ng * d.colsCW, st>>>(d, E, R, wi);
+        }
     }
     if ((rc = check_launch("cols_adj"))) return rc;
     {
         StageTimer tm(p, st, 12);
-        rows_adj<T><<<dim3((d.n + 1) / 2, B), NT, cs * d.Ng, st>>>(d, R, f, fs, wi);
+        if constexpr (sizeof(T) == 4) {
+            if (d.wfRows && !d.ubp) {
+                if ((rc = launch_rows_adj_w(d, B, R, f, fs, wi, st))) return fail(rc, "rows_adj: no wave variant");
+            } else {
+                rows_adj<T><<<dim3((d.n + 1) / 2, B), NT, cs * d.Ng, st>>>(d, R, f, fs, wi);
+            }
+        } else {
+            rows_adj<T><<<dim3((d.n + 1) / 2, B), NT, cs * d.Ng, st>>>(d, R, f, fs, wi);
+        }
     }
     return check_launch("rows_adj");
 }
@@ -2263,15 +3027,24 @@ __host__ __device__ inline void stage_grid(const Dev<T>& d, int S, int B, int G,
     nz = 1;
     switch (S) {
         case PAT_STAGE_ROWS_FWD:
-        case PAT_STAGE_ROWS_ADJ: nx = (d.n + 1) / 2; ny = B; break;
+        case PAT_STAGE_ROWS_ADJ:
+            nx = d.wfRows ? ((d.n + 1) / 2 + WF_WAVES - 1) / WF_WAVES : (d.n + 1) / 2;
+            ny = B;
+            break;
         case PAT_STAGE_COLS_FWD:
-        case PAT_STAGE_COLS_ADJ: nx = (d.Rw + d.colsCW - 1) / d.colsCW; ny = B; break;
+        case PAT_STAGE_COLS_ADJ:
+            nx = d.wfRows ? (d.Rw + WF_WAVES - 1) / WF_WAVES : (d.Rw + d.colsCW - 1) / d.colsCW;
+            ny = B;
+            break;
         case PAT_STAGE_RING_FWD: nx = d.L; ny = (B + G - 1) / G; break;
         case PAT_STAGE_DCT_FWD:
         case PAT_STAGE_DCT_ADJ: nx = d.dct_wave ? d.Kp / d.dwCB : (d.Kp + d.dctCW - 1) / d.dctCW; ny = B; break;
-        case PAT_STAGE_LOWK_FWD: nx = (d.nt * (d.klow + 1) + NT - 1) / NT; ny = B; break;
+        case PAT_STAGE_LOWK_FWD: nx = (d.nt * (d.klow + 1) * LK_LANES + NT - 1) / NT; ny = B; break;
         case PAT_STAGE_SYNTH_FWD:
-        case PAT_STAGE_SYNTH_ADJ: nx = (d.nt + 1) / 2; ny = B; break;
+        case PAT_STAGE_SYNTH_ADJ:
+            nx = d.wfSynth ? ((d.nt + 1) / 2 + WF_WAVES - 1) / WF_WAVES : (d.nt + 1) / 2;
+            ny = B;
+            break;
         case PAT_STAGE_LOWK_ADJ: nx = d.lcorr; ny = B; break;
         case PAT_STAGE_RING_ADJ: nx = (B + G - 1) / G; ny = d.L; break;
         default: nx = (d.Ew + 15) / 16; ny = (d.Ng + 15) / 16; nz = (B + BC - 1) / BC; break;  // spread
@@ -2306,6 +3079,20 @@ __global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
     cx<T>* Gh = reinterpret_cast<cx<T>*>(q.Gh);
     cx<T>* U = reinterpret_cast<cx<T>*>(q.U);
     cx<T>* Pol = reinterpret_cast<cx<T>*>(q.Pol);
+    if constexpr (sizeof(T) == 4) {
+        if constexpr (S == PAT_STAGE_ROWS_FWD)
+            if (q.d.wfRows) { rows_fwd_w_dispatch(q.d, bk, q.fin, q.fs, R, q.wi); return; }
+        if constexpr (S == PAT_STAGE_COLS_FWD)
+            if (q.d.wfRows) { cols_fwd_w_dispatch(q.d, bk, R, E, q.wi); return; }
+        if constexpr (S == PAT_STAGE_SYNTH_FWD)
+            if (q.d.wfSynth) { synth_fwd_w_dispatch(q.d, bk, Gh, q.gout, q.gs, q.wi); return; }
+        if constexpr (S == PAT_STAGE_SYNTH_ADJ)
+            if (q.d.wfSynth) { synth_adj_w_dispatch(q.d, bk, q.gin, q.gs, Gh, q.wi); return; }
+        if constexpr (S == PAT_STAGE_COLS_ADJ)
+            if (q.d.wfRows) { cols_adj_w_dispatch(q.d, bk, E, R, q.wi); return; }
+        if constexpr (S == PAT_STAGE_ROWS_ADJ)
+            if (q.d.wfRows && !q.d.ubp) { rows_adj_w_dispatch(q.d, bk, R, q.fout, q.fs, q.wi); return; }
+    }
     if constexpr (S == PAT_STAGE_ROWS_FWD) rows_fwd_body<T>(q.d, bk, q.fin, q.fs, R, q.wi);
     if constexpr (S == PAT_STAGE_COLS_FWD) cols_fwd_body<T>(q.d, bk, R, E, q.wi);
     if constexpr (S == PAT_STAGE_RING_FWD) ring_fwd_body<T, WMAX>(q.d, bk, E, V, U, q.wi, q.B, q.G);
@@ -2346,14 +3133,16 @@ size_t stage_lds(const pat_plan_s* p, int S, int G)
     const size_t cs = (P.dt == PAT_F64) ? 16 : 8;
     switch (S) {
         case PAT_STAGE_ROWS_FWD:
-        case PAT_STAGE_ROWS_ADJ: return cs * P.Ng;
+        case PAT_STAGE_ROWS_ADJ:
         case PAT_STAGE_COLS_FWD:
-        case PAT_STAGE_COLS_ADJ: return cs * P.Ng * p->cols_cw;
+        case PAT_STAGE_COLS_ADJ:
+            if (p->df.wfRows) return wf_lds(p->df.wfRows);
+            return cs * P.Ng * ((S == PAT_STAGE_COLS_FWD || S == PAT_STAGE_COLS_ADJ) ? p->cols_cw : 1);
         case PAT_STAGE_RING_FWD: return cs * G * P.max_ring;
         case PAT_STAGE_DCT_FWD:
         case PAT_STAGE_DCT_ADJ: return p->df.dct_wave ? dw_lds(p->df.dct_wave) : dct_lds(P, p->dct_cw);
-        case PAT_STAGE_SYNTH_FWD: return cs * 2 * P.mf;
-        case PAT_STAGE_SYNTH_ADJ: return cs * P.mf;
+        case PAT_STAGE_SYNTH_FWD: return p->df.wfSynth ? wf_lds(p->df.wfSynth) : cs * 2 * P.mf;
+        case PAT_STAGE_SYNTH_ADJ: return p->df.wfSynth ? wf_lds(p->df.wfSynth) : cs * P.mf;
         case PAT_STAGE_RING_ADJ: return cs * G * P.max_ring;
         default: return 0;
     }
@@ -2447,6 +3236,7 @@ void default_tune(pat_plan_s* p)
     p->tw_table = 0;
     p->spread_staged = 1;
     p->dct_wave_on = 1;
+    p->wave_fft_on = 1;
 }
 
 void apply_tune(pat_plan_s* p)
@@ -2461,6 +3251,10 @@ void apply_tune(pat_plan_s* p)
     p->df.dct_one = p->dd.dct_one = dct_one_ok(p->H.P, p->dct_cw);
     p->df.dct_wave = p->dd.dct_wave = p->dct_wave_on ? dw_variant(p->H.P) : 0;
     p->df.dwCB = p->dd.dwCB = dw_columns(p->df.dct_wave);
+    p->df.wfRows = p->dd.wfRows = p->wave_fft_on ? wf_rows_variant(p->H.P) : 0;
+    p->df.wfSynth = p->dd.wfSynth = p->wave_fft_on ? wf_synth_variant(p->H.P) : 0;
+    p->df.ring_ct = p->wave_fft_on;
+    p->dd.ring_ct = 0;
 }
 
 bool pow2_in(int v, int hi) { return v >= 1 && v <= hi && (v & (v - 1)) == 0; }
@@ -2472,7 +3266,7 @@ bool tune_valid(const pat_plan_s* p)
     return pow2_in(p->cols_cw, lds_cols(P)) && pow2_in(p->dct_cw, lds_dct(P)) && pow2_in(p->ring_g, ring_group_max(P)) &&
            (p->spread_bc == bcl || p->spread_bc == bcl / 2) && (p->fft_lr == 3 || p->fft_lr == 4) &&
            (p->tw_table == 0 || p->tw_table == 1) && (p->spread_staged == 0 || p->spread_staged == 1) &&
-           (p->dct_wave_on == 0 || p->dct_wave_on == 1);
+           (p->dct_wave_on == 0 || p->dct_wave_on == 1) && (p->wave_fft_on == 0 || p->wave_fft_on == 1);
 }
 
 std::string tune_key(const pat_plan_s* p)
@@ -2508,15 +3302,17 @@ bool tune_lookup(pat_plan_s* p, const char* path, const std::string& key)
         t.tw_table = 0;
         t.spread_staged = 0;
         t.dct_wave_on = 0;
+        t.wave_fft_on = 0;
         const int got = std::sscanf(l.c_str() + bar + 3,
                                     "cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=%lf "
-                                    "twiddle_table=%d spread_staged=%d dct_wave=%d",
+                                    "twiddle_table=%d spread_staged=%d dct_wave=%d wave_fft=%d",
                                     &t.cols_cw, &t.dct_cw, &t.ring_g, &t.spread_bc, &t.fft_lr, &ms, &t.tw_table,
-                                    &t.spread_staged, &t.dct_wave_on);
+                                    &t.spread_staged, &t.dct_wave_on, &t.wave_fft_on);
         if (got >= 6 && tune_valid(&t)) {
             p->cols_cw = t.cols_cw; p->dct_cw = t.dct_cw; p->ring_g = t.ring_g; p->spread_bc = t.spread_bc;
             p->fft_lr = t.fft_lr; p->tw_table = t.tw_table; p->spread_staged = t.spread_staged; p->tuned_ms = ms;
             p->dct_wave_on = t.dct_wave_on;
+            p->wave_fft_on = t.wave_fft_on;
             found = true;  // keep scanning: the last matching line wins
         }
     }
@@ -2530,9 +3326,9 @@ void tune_store(const pat_plan_s* p, const char* path, const std::string& key)
     if (!fp) return;
     std::fprintf(fp,
                  "%s | cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=%.6f twiddle_table=%d "
-                 "spread_staged=%d dct_wave=%d\n",
+                 "spread_staged=%d dct_wave=%d wave_fft=%d\n",
                  key.c_str(), p->cols_cw, p->dct_cw, p->ring_g, p->spread_bc, p->fft_lr, p->tuned_ms, p->tw_table,
-                 p->spread_staged, p->dct_wave_on);
+                 p->spread_staged, p->dct_wave_on, p->wave_fft_on);
     std::fclose(fp);
 }
 
@@ -2571,7 +3367,7 @@ int tune_search(pat_plan_s* p, const Dev<T>& d)
     }
     auto measure = [&](double& ms) -> int {
         apply_tune(p);
-        for (int rep = 0; rep < 4; ++rep) {
+        for (int rep = 0; rep < 6; ++rep) {
             if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) return PAT_EHIP;
             int r = run_forward<T, WMAX>(p, d, B, (const T*)f, fsz, (T*)g, gsz, (char*)ws, st);
             if (!r) r = run_adjoint<T, WMAX>(p, d, B, (const T*)g, gsz, (T*)f, fsz, (char*)ws, st);
@@ -2580,7 +3376,7 @@ int tune_search(pat_plan_s* p, const Dev<T>& d)
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return PAT_EHIP;
         float t = 0;
         if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) return PAT_EHIP;
-        ms = t / 3.0;
+        ms = t / 5.0;
         return PAT_OK;
     };
     const int bcl = (P.dt == PAT_F64) ? 8 : 16;
@@ -2599,7 +3395,8 @@ int tune_search(pat_plan_s* p, const Dev<T>& d)
                                    {&p->ring_g, rg},
                                    {&p->spread_bc, {bcl, bcl / 2}},
                                    {&p->spread_staged, {1, 0}},
-                                   {&p->dct_wave_on, {1, 0}}};
+                                   {&p->dct_wave_on, {1, 0}},
+                                   {&p->wave_fft_on, {1, 0}}};
     double best = 0;
     if ((rc = measure(best))) { cleanup(); return fail(rc, "autotuner: timing run failed"); }
     for (Choice& c : choices) {
@@ -2662,6 +3459,7 @@ void fill_info(const pat::Params& P, pat_plan_info* info, size_t ws_img, size_t 
         info->tune_twiddle_table = p->tw_table;
         info->tune_spread_staged = p->spread_staged;
         info->tune_dct_wave = p->df.dct_wave ? 1 : 0;
+        info->tune_wave_fft = (p->df.wfRows || p->df.wfSynth) ? 1 : 0;
         info->tuned = p->tuned;
         info->tuned_ms = p->tuned_ms;
     }

@@ -39,7 +39,8 @@ class PlanInfo(ctypes.Structure):
                 ("tune_fft_radix_log2", ctypes.c_int), ("tune_cols_per_block", ctypes.c_int),
                 ("tune_dct_cols_per_block", ctypes.c_int), ("tune_ring_images", ctypes.c_int),
                 ("tune_spread_images", ctypes.c_int), ("tune_twiddle_table", ctypes.c_int),
-                ("tune_spread_staged", ctypes.c_int), ("tune_dct_wave", ctypes.c_int), ("tuned", ctypes.c_int),
+                ("tune_spread_staged", ctypes.c_int), ("tune_dct_wave", ctypes.c_int),
+                ("tune_wave_fft", ctypes.c_int), ("tuned", ctypes.c_int),
                 ("tuned_ms", ctypes.c_double)]
 
 

@@ -277,6 +277,12 @@ def _tiny_setup(K=3):
 
 
 ENSEMBLE = 16  # perturbed oracle runs that measure the bf16 rounding-flip spread
+FLOOR = 1e-5   # FP32 vs FP64 accumulation: the floor under every ensemble-derived bar
+
+
+def within(err, spread):
+    """The GPU's distance against twice the ensemble's largest, never below FLOOR."""
+    return err < max(2 * spread, FLOOR)
 
 
 def flip_spread(geom, Pd, y, f_true, K, s_A, s_U, ref_loss, ref_fK, ref_g, draws=ENSEMBLE):
@@ -319,7 +325,9 @@ def test_lpd_loss_gradient_vs_oracle(K):
     level, 1e-5 gives the same).  The GPU is one more such draw: f_K, the
     whole gradient and each parameter block must lie within twice the
     largest distance of the ensemble (16 draws; twice covers the sampling
-    error of a maximum).  A wrong term or sign gives O(1) errors."""
+    error of a maximum), never below 1e-5 (FP32 against FP64 accumulation,
+    for quantities the flips cannot reach).  A wrong term or sign gives O(1)
+    errors."""
     geom, plan, f_true, y, params, _ = _tiny_setup()
     s_A, s_U = 0.9, 1.7
     net = L.LPD(plan, 2, iters=K, params=params, s_A=s_A, s_U=s_U)
@@ -348,11 +356,11 @@ def test_lpd_loss_gradient_vs_oracle(K):
           % (K, e_f, s_f, rel(allg, allo), s_all))
     for k in g_o:
         print("  %-10s gpu %.2e  flip spread %.2e" % (k, e_g[k], s_blk[k]))
-    assert e_f < 2 * s_f
-    assert abs(net.loss() - loss_o) < 2 * s_l * loss_o
-    assert rel(allg, allo) < 2 * s_all
+    assert within(e_f, s_f)
+    assert within(abs(net.loss() - loss_o) / loss_o, s_l)
+    assert within(rel(allg, allo), s_all)
     for k in g_o:
-        assert e_g[k] < 2 * s_blk[k], k
+        assert within(e_g[k], s_blk[k]), k
 
 
 def test_lpd_graph_replay_equals_eager_training():

@@ -55,15 +55,19 @@ def test_every_launch_shape_meets_parity(tmp_path, dt):
     pat.Plan(geom, tdt, max_batch=B, tuning_cache=path)
     key = open(path).read().splitlines()[0].split(" | ")[0]
     bcl = base.info["tune_spread_images"]
-    shapes = [(3, 1, 1, 1, bcl // 2, 1, 0), (4, 1, base.info["tune_dct_cols_per_block"], 2, bcl, 0, 1),
-              (3, base.info["tune_cols_per_block"], 1, base.info["tune_ring_images"], bcl // 2, 0, 1),
-              (4, base.info["tune_cols_per_block"], base.info["tune_dct_cols_per_block"], 1, bcl, 1, 0)]
+    # (radix, cols, dct cols, ring images, spread images, twiddle table, spread staging,
+    #  wave cosine transform, wave FFT kernels)
+    shapes = [(3, 1, 1, 1, bcl // 2, 1, 0, 0, 0), (4, 1, base.info["tune_dct_cols_per_block"], 2, bcl, 0, 1, 0, 0),
+              (3, base.info["tune_cols_per_block"], 1, base.info["tune_ring_images"], bcl // 2, 0, 1, 0, 0),
+              (4, base.info["tune_cols_per_block"], base.info["tune_dct_cols_per_block"], 1, bcl, 1, 0, 0, 0),
+              (3, 1, 1, 1, bcl, 0, 1, 1, 1), (4, 1, 1, 2, bcl // 2, 0, 0, 1, 0), (3, 1, 1, 1, bcl // 2, 0, 1, 0, 1)]
     f = torch.tensor(f_np, dtype=tdt, device="cuda")
     g = torch.tensor(g_np, dtype=tdt, device="cuda")
-    for lr, cw, dw, rg, sb, tt, ss in shapes:
+    for lr, cw, dw, rg, sb, tt, ss, dwv, wf in shapes:
         with open(path, "a") as fp:
             fp.write("%s | cols_cw=%d dct_cw=%d ring_group=%d spread_images=%d fft_radix_log2=%d ms=1.0 "
-                     "twiddle_table=%d spread_staged=%d\n" % (key, cw, dw, rg, sb, lr, tt, ss))
+                     "twiddle_table=%d spread_staged=%d dct_wave=%d wave_fft=%d\n"
+                     % (key, cw, dw, rg, sb, lr, tt, ss, dwv, wf))
         plan = pat.Plan(geom, tdt, max_batch=B, tuning_cache=path)
         got = [plan.info[k] for k in ("tune_fft_radix_log2", "tune_cols_per_block", "tune_dct_cols_per_block",
                                       "tune_ring_images", "tune_spread_images", "tune_twiddle_table",
@@ -71,7 +75,7 @@ def test_every_launch_shape_meets_parity(tmp_path, dt):
         assert plan.info["tuned"] == 2 and got == [lr, cw, dw, rg, sb, tt, ss]
         ef = rel(plan.forward(f).cpu().numpy(), ref_f)
         ea = rel(plan.adjoint(g).cpu().numpy(), ref_a)
-        print(dt, (lr, cw, dw, rg, sb, tt, ss), "forward %.2e adjoint %.2e" % (ef, ea))
+        print(dt, (lr, cw, dw, rg, sb, tt, ss, dwv, wf), "forward %.2e adjoint %.2e" % (ef, ea))
         assert ef < tol and ea < tol
 
 

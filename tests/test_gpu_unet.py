@@ -20,9 +20,12 @@ convolution products (and, in the unrolled network, operator outputs) carry
 seeded relative noise at FP32 level (oracle.lpd.Perturb: 1e-7 and 1e-6),
 each compared with the unperturbed run.  The GPU is one more such draw, so
 every compared quantity must lie within twice the largest distance of the
-ensemble (twice covers the sampling error of a maximum over the draws).  The
-shifted case is the discriminating one: a wrong connection, term or sign
-gives O(1) errors there."""
+ensemble (twice covers the sampling error of a maximum over the draws), or
+within FLOOR = 1e-5 for quantities that the flips cannot reach (the head's
+bias gradient is a plain sum, equal in every draw): FP32 against FP64
+accumulation, the bar of the unit tests.  The shifted case is the
+discriminating one: a wrong connection, term or sign gives O(1) errors
+there."""
 import ctypes
 
 import numpy as np
@@ -42,6 +45,12 @@ from paper_2510_24687_amd import unet as UN
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
+FLOOR = 1e-5  # FP32 vs FP64 accumulation: the floor under every ensemble-derived bar
+
+
+def within(err, spread):
+    """The GPU's distance against twice the ensemble's largest, never below FLOOR."""
+    return err < max(2 * spread, FLOOR)
 
 
 @pytest.fixture(scope="module")
@@ -433,13 +442,13 @@ def test_unet_forward_backward_against_the_oracle(lib, cin, B, H, W, shift):
         ex.append((e_x, s_x[c]))
         print("input gradient %d: gpu vs oracle %.3e, flip spread %.3e" % (c, e_x, s_x[c]))
     # see the module docstring: within twice the ensemble's largest distance
-    assert e_out < 2 * s_out
+    assert within(e_out, s_out)
     assert e_stats < 5e-2
-    assert e_g < 2 * s_g
+    assert within(e_g, s_g)
     for name, (a, b) in blocks.items():
-        assert a < 2 * b, (name, a, b)
+        assert within(a, b), (name, a, b)
     for e_x, s in ex:
-        assert e_x < 2 * s
+        assert within(e_x, s)
 
 
 def test_unet_forward_backward_is_bit_reproducible(lib):
@@ -546,12 +555,12 @@ def test_unet_lpd_loss_gradient_against_the_oracle():
     allg = np.concatenate([np.ravel(grads[k]) for k in g_o])
     print("K=%d f_K: gpu %.2e, flip spread %.2e; gradient: gpu %.2e, flip spread %.2e"
           % (K, e_f, s_f, _rel(allg, allo), s_g))
-    assert e_f < 2 * s_f
-    assert abs(net.loss() - loss_o) < 2 * s_l * loss_o
-    assert _rel(allg, allo) < 2 * s_g
+    assert within(e_f, s_f)
+    assert within(abs(net.loss() - loss_o) / loss_o, s_l)
+    assert within(_rel(allg, allo), s_g)
     for k in g_o:
         e = _rel(grads[k], g_o[k])
-        assert e < 2 * s_blk[k], (k, e, s_blk[k])
+        assert within(e, s_blk[k]), (k, e, s_blk[k])
     # running statistics of every iteration after one application each
     got = _running_from(net.stats.cpu().numpy(), K)
     for k in range(K):
@@ -594,7 +603,7 @@ def test_unet_lpd_graph_replay_and_inference():
                                          perturb=OL.Perturb(4000 + d)).numpy(), f_o) for d in range(8))
     e = _rel(f_e.cpu().numpy(), f_o)
     print("inference f_K: gpu %.2e, flip spread %.2e" % (e, spread))
-    assert e < 2 * spread
+    assert within(e, spread)
     inf.capture_forward()
     for _ in range(2):
         inf.f[K].zero_()
