@@ -37,14 +37,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 STAGES = ["rows_fwd", "cols_fwd", "ring_fwd", "dct_fwd", "lowk_fwd", "synth_fwd", "synth_adj", "lowk_adj",
-          "dct_adj", "ring_adj", "spread_adj", "cols_adj", "rows_adj"]
+          "dct_adj", "ring_adj", "spread_adj", "cols_adj", "rows_adj", "gather_fwd"]
+NSTAGES = len(STAGES)
 HBM_PEAK_GBS = 8000.0
 ACC_TOL = 1e-4  # relative L2 bar of the FP32 operators against the FP64 oracle
 
 
 def stage_bytes(info: dict, B: int, geom: dict) -> dict:
     """Algorithmic HBM bytes per launch (B images, FP32): each kernel's compulsory
-    reads of its inputs and writes of its outputs, once each."""
+    reads of its inputs and writes of its outputs, once each.  With the binned
+    forms (tune_spread_staged == 2) the forward gather is its own kernel
+    (E -> the half-ring samples P), and ring_fwd reads P instead of E."""
     n, m, nt = info["n"], info["m"], info["nt"]
     Ng, L, Kp, K = info["grid"], info["rings"], info["kpad"], info["kmax"]
     w = info["stencil"]
@@ -59,10 +62,15 @@ def stage_bytes(info: dict, B: int, geom: dict) -> dict:
     P = c8 * info["ring_points"]
     per = {
         "rows_fwd": r4 * n * n + R, "cols_fwd": R + E, "ring_fwd": E + V + tb, "dct_fwd": V + G,
+        "gather_fwd": E + P,
         "lowk_fwd": 2 * c8 * nt * (info["klow"] + 1), "synth_fwd": G + r4 * nt * m,
         "synth_adj": r4 * nt * m + G, "lowk_adj": c8 * nt * (info["klow"] + 1),
         "dct_adj": G + V, "ring_adj": V + tb + P, "spread_adj": P + E, "cols_adj": E + R, "rows_adj": R + r4 * n * n,
     }
+    if info.get("tune_spread_staged") == 2:
+        per["ring_fwd"] = P + V + tb
+    else:
+        del per["gather_fwd"]
     return {k: v * B for k, v in per.items()}
 
 
@@ -93,7 +101,8 @@ def measured_traffic(kernel: str, B: int, shapes: dict = None):
     relevant = {"spread_adj": ("tune_spread_images", "tune_spread_staged"),
                 "dct_fwd": ("tune_dct_cols_per_block", "tune_dct_wave"),
                 "dct_adj": ("tune_dct_cols_per_block", "tune_dct_wave"),
-                "ring_fwd": ("tune_ring_images",), "ring_adj": ("tune_ring_images",),
+                "ring_fwd": ("tune_ring_images", "tune_spread_staged"), "ring_adj": ("tune_ring_images",),
+                "gather_fwd": ("tune_spread_staged",),
                 "cols_fwd": ("tune_cols_per_block", "tune_wave_fft"),
                 "cols_adj": ("tune_cols_per_block", "tune_wave_fft"),
                 "rows_fwd": ("tune_wave_fft",), "rows_adj": ("tune_wave_fft",),
@@ -103,6 +112,67 @@ def measured_traffic(kernel: str, B: int, shapes: dict = None):
         return None
     k = z["kernels"][kernel]
     return (k["fetch_kib"] * z["fetch_scale"] + k["write_kib"] * z["write_scale"]) * 1024.0
+
+
+def _stage_of(kernel: str, prev: str):
+    """Stage of a pair kernel from its (demangled) name; the cosine transform
+    serves both directions and is told apart by the stage launched before it."""
+    name = kernel.split("(")[0]
+    for key, stage in (("rows_fwd", "rows_fwd"), ("cols_fwd", "cols_fwd"), ("gather_bins", "gather_fwd"),
+                       ("ring_fwd", "ring_fwd"), ("lowk_fwd", "lowk_fwd"), ("synth_fwd", "synth_fwd"),
+                       ("synth_adj", "synth_adj"), ("lowk_adj", "lowk_adj"), ("ring_adj", "ring_adj"),
+                       ("spread_", "spread_adj"), ("cols_adj", "cols_adj"), ("rows_adj", "rows_adj")):
+        if key in name:
+            return stage
+    if "dct_" in name:
+        return "dct_fwd" if prev in ("ring_fwd", "gather_fwd") else "dct_adj"
+    return None
+
+
+def _counter_rows(directory: str, counter: str):
+    """(dispatch id, kernel name, value) of one counter from the rocprofv3 CSVs under `directory`."""
+    import csv
+    import glob
+    out = []
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)):
+        for r in csv.DictReader(open(path)):
+            if r.get("Counter_Name") == counter:
+                out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    out.sort()
+    return out
+
+
+def traffic_summary(prefix: str, bench_json: str) -> dict:
+    """profiles/traffic_n512.json from four rocprofv3 counter runs under
+    `prefix` (pmc_fetch, pmc_write: FETCH_SIZE / WRITE_SIZE of
+    `bench.py --pair-only`; pmc_copy_fetch, pmc_copy_write: the same counters
+    of `bench.py --copy-calibration`): per stage, the median KiB per dispatch,
+    and the factors that turn the copy's counts into its known 2 x 1 GiB.
+    `bench_json`: the JSON line of the profiled configuration (launch shapes)."""
+    import statistics
+    shapes = json.load(open(bench_json))["launch_shapes"]
+    res = {"source_hash": kernel_source_hash(), "batch": None, "launch_shapes": shapes, "kernels": {}}
+    for counter, sub, key in (("FETCH_SIZE", "pmc_fetch", "fetch_kib"), ("WRITE_SIZE", "pmc_write", "write_kib")):
+        per = {}
+        prev = None
+        for _, kern, val in _counter_rows(os.path.join(prefix, sub), counter):
+            st = _stage_of(kern, prev)
+            if st is None:
+                continue
+            prev = st
+            per.setdefault(st, ([], kern.split("(")[0]))[0].append(val)
+        for st, (vals, kern) in per.items():
+            d = res["kernels"].setdefault(st, {})
+            d[key] = statistics.median(vals)
+            d["kernel"] = kern
+            d["dispatches"] = len(vals)
+    copy = 1 << 30
+    for counter, sub, key in (("FETCH_SIZE", "pmc_copy_fetch", "fetch_scale"),
+                              ("WRITE_SIZE", "pmc_copy_write", "write_scale")):
+        vals = [v for _, k, v in _counter_rows(os.path.join(prefix, sub), counter) if "copy" in k.lower()]
+        res[key] = (copy / 1024.0) / max(vals)
+    res["batch"] = json.load(open(bench_json))["config"]["batch"]
+    return res
 
 
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
@@ -527,7 +597,18 @@ def main():
                     help="autotuner cache file (default: a fresh temporary file, i.e. tune at start-up)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for rocprofv3 counter calibration)")
+    ap.add_argument("--pair-only", action="store_true",
+                    help="only the A+A* pair line (no inverse, filter, learned primal-dual or CPU blocks): "
+                         "the run that the kernel profiles are taken from")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("PMC_DIR", "BENCH_JSON"),
+                    help="write profiles/traffic_n512.json from rocprofv3 FETCH_SIZE / WRITE_SIZE runs")
     args = ap.parse_args()
+    if args.traffic_summary:
+        res = traffic_summary(*args.traffic_summary)
+        with open(os.path.join(ROOT, "profiles", "traffic_n512.json"), "w") as fp:
+            json.dump(res, fp, indent=1)
+        print(json.dumps(res), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only (the operators shard by image; "
               "a multi-GPU run is not part of it)", file=sys.stderr)
@@ -632,12 +713,12 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     import ctypes
-    ms = (ctypes.c_double * 13)()
-    cnt = (ctypes.c_int * 13)()
-    rc = lib.pat_timing_stop(plan._h, ms, cnt, 13)
+    ms = (ctypes.c_double * NSTAGES)()
+    cnt = (ctypes.c_int * NSTAGES)()
+    rc = lib.pat_timing_stop(plan._h, ms, cnt, NSTAGES)
     if rc != 0:
         raise RuntimeError("pat_timing_stop failed")
-    stage_ms = {STAGES[i]: ms[i] / max(cnt[i], 1) for i in range(13)}
+    stage_ms = {STAGES[i]: ms[i] / cnt[i] for i in range(NSTAGES) if cnt[i] > 0}
     bytes_ = stage_bytes(info, B, geom)
     dom = max(stage_ms, key=stage_ms.get)
     achieved = bytes_[dom] / (stage_ms[dom] * 1e-3) / 1e9
@@ -678,6 +759,9 @@ def main():
         print("bench.py: results exceed the 1e-4 accuracy bar against the oracle (or no oracle samples); "
               "throughput withheld", file=sys.stderr)
         sys.exit(3)
+    if args.pair_only:
+        print(json.dumps(out), flush=True)
+        return
     out["inverse"] = inverse_bench(plan, y, args.steps, n, geom)
     out["measurement_filter"] = filter_bench(g, args.steps, geom)
     if not args.no_lpd:
@@ -752,9 +836,9 @@ def inverse_bench(plan, y, steps, n, geom):
     e1.record()
     torch.cuda.synchronize()
     ms_total = e0.elapsed_time(e1) / steps
-    ms = (ctypes.c_double * 13)()
-    cnt = (ctypes.c_int * 13)()
-    if lib.pat_timing_stop(plan._h, ms, cnt, 13) != 0:
+    ms = (ctypes.c_double * NSTAGES)()
+    cnt = (ctypes.c_int * NSTAGES)()
+    if lib.pat_timing_stop(plan._h, ms, cnt, NSTAGES) != 0:
         raise RuntimeError("pat_timing_stop failed")
     stage = {STAGES[i]: ms[i] / max(cnt[i], 1) for i in range(6, 13)}
     # the per-stage events serialise the launches slightly; the untimed loop below gives the throughput

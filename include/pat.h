@@ -116,8 +116,10 @@ typedef struct {
     int tune_spread_images;       /* images per spread group                        */
     int tune_twiddle_table;       /* 1: FFT passes read every twiddle from a table,
                                      0: derive them from four table entries         */
-    int tune_spread_staged;       /* 1: the spread stages samples through LDS, 0: it
-                                     reads them with scalar loads one ahead         */
+    int tune_spread_staged;       /* spread form: 2 (FP32 only) samples sorted by
+                                     the cell of their first tap, each lane walking
+                                     its own runs; 1 tiles staging samples through
+                                     LDS; 0 tiles reading them with scalar loads    */
     int tune_dct_wave;            /* 1: the FP32 cosine transform runs one wave per
                                      column group with compile-time lengths         */
     int tune_wave_fft;            /* 1: the FP32 row / column / angular FFT kernels
@@ -249,11 +251,13 @@ int pat_adjoint_scale(pat_plan p, double* s);
 const char* pat_status_string(int code);
 const char* pat_last_error(void);
 
-/* Stage timing.  Stages of the forward and adjoint chains, in launch order. */
+/* Stage timing.  Stages of the forward and adjoint chains, in launch order;
+ * PAT_STAGE_GATHER_FWD (the FP32 binned gather, launched between COLS_FWD and
+ * RING_FWD when tune_spread_staged == 2) is numbered last. */
 enum {
     PAT_STAGE_ROWS_FWD = 0, PAT_STAGE_COLS_FWD, PAT_STAGE_RING_FWD, PAT_STAGE_DCT_FWD, PAT_STAGE_LOWK_FWD,
     PAT_STAGE_SYNTH_FWD, PAT_STAGE_SYNTH_ADJ, PAT_STAGE_LOWK_ADJ, PAT_STAGE_DCT_ADJ, PAT_STAGE_RING_ADJ,
-    PAT_STAGE_SPREAD_ADJ, PAT_STAGE_COLS_ADJ, PAT_STAGE_ROWS_ADJ, PAT_NUM_STAGES
+    PAT_STAGE_SPREAD_ADJ, PAT_STAGE_COLS_ADJ, PAT_STAGE_ROWS_ADJ, PAT_STAGE_GATHER_FWD, PAT_NUM_STAGES
 };
 
 /* Start recording a HIP event pair on the launch stream around every kernel

@@ -383,7 +383,6 @@ struct Dev {
     int wfRows;                 // log2 Ng when the FP32 row and column FFT passes run one wave per
                                 // sequence (rows_fwd_w, cols_fwd_w, ...), else 0
     int wfSynth;                // log2 m_full for the wave form of the angular synthesis, else 0
-    int ring_ct;                // 1: FP32 ring transforms with compile-time lengths (ring_fft_ct)
     int fft_lr;                 // largest FFT pass radix is 2^fft_lr (3 or 4)
     int tw_table;               // 1: FFT passes read every twiddle from the table
     T beta, shift, half;        // half = Ng / (2 Lambda): grid cells per unit lambda
@@ -411,6 +410,12 @@ struct Dev {
     int mf3;                    // 1: mf = 3 * 2^logmf
     const cx<T>* twm;           // 2 mf: e^{-2 pi i j/(2 mf)} (angular-transform twiddles)
     const cx<T>* pos;           // npts: grid position (x, y) of each half-ring sample
+    // bin order of the FP32 spread (spread_bins): samples sorted by the cell of
+    // their first tap, (gy0 mod Ng) * Ew + gx0 + hw, ring order within a bin
+    const int* binRing;         // npts: ring-order index of the sample in each bin-order slot
+    const int* binStart;        // Ng * Ew + 1: first slot of each bin
+    const cx<T>* binPos;        // npts: positions in bin order
+    int binned;                 // 1: the adjoint spreads with spread_bins
     // approximate inverse (Sec. 3.3): its tables, and the per-call switches of
     // the adjoint kernels that it reuses
     const T* Tbi;               // L x Kp: Tb with J_k' for J_k
@@ -512,7 +517,7 @@ template <typename T>
 __device__ __forceinline__ void rows_fwd_body(const Dev<T>& d, Blk bk, const T* __restrict__ f, long fstride, cx<T>* R,
                                                size_t ws_img)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     int bx_, b;
     bx_ = bk.x;
@@ -552,7 +557,7 @@ __global__ __launch_bounds__(NT) void rows_fwd(Dev<T> d, const T* __restrict__ f
 template <typename T>
 __device__ __forceinline__ void cols_fwd_body(const Dev<T>& d, Blk bk, const cx<T>* R, cx<T>* E, size_t ws_img)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     int bx_, b;
     bx_ = bk.x;
@@ -588,177 +593,11 @@ __global__ __launch_bounds__(NT) void cols_fwd(Dev<T> d, const cx<T>* R, cx<T>* 
     cols_fwd_body<T>(d, blk_xcd(), R, E, ws_img);
 }
 
-// Ring transforms with their length known at compile time (FP32): the same
-// Stockham passes as lds_fft / lds_fft3 (radix 8 while three bits remain,
-// then 4 or 2, then radix 3 for 3 * 2^a points; the same twiddle tables), but
-// with constant strides, sequence counts and shifts, and each thread's
-// twiddles loaded once per pass while the sub-transform length divides the
-// block.  nb * N <= FFT_BLOCK_POINTS.
-__host__ __device__ constexpr int rc_radix(int LOGN, int p)
-{
-    return (LOGN - 3 * p >= 3) ? 8 : (LOGN - 3 * p == 2 ? 4 : 2);
-}
-__host__ __device__ constexpr int rc_npass(int LOGN) { return LOGN / 3 + (LOGN % 3 ? 1 : 0); }
-__host__ __device__ constexpr int rc_ns(int LOGN, int p) { return p == 0 ? 1 : rc_ns(LOGN, p - 1) * rc_radix(LOGN, p - 1); }
-__host__ __device__ constexpr int rc_log2(int v) { return v <= 1 ? 0 : 1 + rc_log2(v / 2); }
-
-// one power-of-two pass over nb sequences of length N (stride N); for a
-// 3 * 2^a ring, N is that length and the pass works on its 2^a factor as
-// lds_fft does with f3 (butterfly inputs N / R apart)
-template <int N, int R, int NS, bool INV>
-__device__ __forceinline__ void rc_pass(PAT_LDS cx<float>* buf, int nb, const PAT_GLOBAL cx<float>* __restrict__ tw,
-                                        int logNmax)
-{
-    constexpr int NBS = N / R;                  // butterflies per sequence
-    constexpr int PER = FFT_REGS / R;           // nb * N <= FFT_BLOCK_POINTS
-    const int total = nb * NBS;
-    cx<float> v[PER][R];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int t = threadIdx.x + NT * u;
-        if (t < total) {
-            const int b = t / NBS, tt = t - b * NBS;
-            const PAT_LDS cx<float>* s = buf + b * N;
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[u][r] = ld_lds(s + tt + r * NBS);
-        }
-    }
-    __syncthreads();
-    const int sh = logNmax - rc_log2(R * NS);
-    cx<float> wl[R];
-    if constexpr (NS > 1 && NS <= NT) {
-        const int k = threadIdx.x & (NS - 1);
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-            wl[r] = ld_glb(tw + ((r * k) << sh));
-            if (INV) wl[r].y = -wl[r].y;
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int t = threadIdx.x + NT * u;
-        if (t < total) {
-            const int b = t / NBS, tt = t - b * NBS;
-            const int k = tt & (NS - 1);
-            if constexpr (NS > NT) {
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    cx<float> w = ld_glb(tw + ((r * k) << sh));
-                    if (INV) w.y = -w.y;
-                    v[u][r] = cmul(v[u][r], w);
-                }
-            } else if constexpr (NS > 1) {
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[u][r] = cmul(v[u][r], wl[r]);
-            }
-            dft_reg<float, R>(v[u], INV);
-            PAT_LDS cx<float>* s = buf + b * N;
-            const int base = (tt / NS) * NS * R + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) st_lds(s + base + r * NS, v[u][r]);
-        }
-    }
-    __syncthreads();
-}
-
-template <int N, int LOGP, bool INV, int P = 0>
-__device__ __forceinline__ void rc_passes(PAT_LDS cx<float>* buf, int nb, const PAT_GLOBAL cx<float>* tw, int logNmax)
-{
-    if constexpr (P < rc_npass(LOGP)) {
-        rc_pass<N, rc_radix(LOGP, P), rc_ns(LOGP, P), INV>(buf, nb, tw, logNmax);
-        rc_passes<N, LOGP, INV, P + 1>(buf, nb, tw, logNmax);
-    }
-}
-
-// radix-3 pass of a 3 * 2^LOGP ring (sub-transform length 2^LOGP); twr holds
-// the 2 Nr3-th roots, W_N^{r t} = twr[(2 r t) << tsh]
-template <int LOGP, bool INV>
-__device__ __forceinline__ void rc_pass3(PAT_LDS cx<float>* buf, int nb, const PAT_GLOBAL cx<float>* __restrict__ twr,
-                                         int tsh)
-{
-    constexpr int NS = 1 << LOGP, N = 3 * NS;
-    constexpr int PER = FFT_REGS / 3;
-    const int total = nb * NS;
-    const float h3 = 0.86602540378443864676f;
-    cx<float> v[PER][3];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int t = threadIdx.x + NT * u;
-        if (t < total) {
-            const int b = t >> LOGP, tt = t & (NS - 1);
-            const PAT_LDS cx<float>* s = buf + b * N;
-#pragma unroll
-            for (int r = 0; r < 3; ++r) v[u][r] = ld_lds(s + tt + r * NS);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int t = threadIdx.x + NT * u;
-        if (t < total) {
-            const int b = t >> LOGP, tt = t & (NS - 1);
-            cx<float> w1 = ld_glb(twr + ((2 * tt) << tsh)), w2 = ld_glb(twr + ((4 * tt) << tsh));
-            if (INV) { w1.y = -w1.y; w2.y = -w2.y; }
-            const cx<float> a0 = v[u][0], a1 = cmul(v[u][1], w1), a2 = cmul(v[u][2], w2);
-            const cx<float> sm = a1 + a2, df = a1 - a2;
-            const cx<float> m = {a0.x - 0.5f * sm.x, a0.y - 0.5f * sm.y};
-            const cx<float> jd = INV ? cx<float>{-h3 * df.y, h3 * df.x} : cx<float>{h3 * df.y, -h3 * df.x};
-            PAT_LDS cx<float>* s = buf + b * N;
-            st_lds(s + tt, a0 + sm);
-            st_lds(s + tt + NS, m + jd);
-            st_lds(s + tt + 2 * NS, m - jd);
-        }
-    }
-    __syncthreads();
-}
-
-template <int M3, int LOGP, bool INV>
-__device__ __forceinline__ void ring_fft_ct(const Dev<float>& d, cx<float>* buf, int nb)
-{
-    constexpr int N = (M3 ? 3 : 1) << LOGP;
-    PAT_LDS cx<float>* lb = (PAT_LDS cx<float>*)buf;
-    rc_passes<N, LOGP, INV>(lb, nb, (const PAT_GLOBAL cx<float>*)d.tw, d.logNmax);
-    if constexpr (M3) rc_pass3<LOGP, INV>(lb, nb, (const PAT_GLOBAL cx<float>*)d.twr, d.logNr3 - LOGP);
-}
-
-// FP32 rings of 16 .. 2048 points (2^a) and 24 .. 1536 points (3 * 2^a): the
-// compile-time transforms, as many sequences per call as the registers allow
-// (FFT_BLOCK_POINTS points, (FFT_REGS / 3) * 3 * NT with the radix-3 pass);
-// returns false for other lengths and for FP64
-#define PAT_RC_SIZES(X) \
-    X(0, 4) X(0, 5) X(0, 6) X(0, 7) X(0, 8) X(0, 9) X(0, 10) X(0, 11) X(1, 3) X(1, 4) X(1, 5) X(1, 6) X(1, 7) X(1, 8) X(1, 9)
-
-template <typename T>
-__device__ __forceinline__ bool ring_fft_fixed(const Dev<T>& d, int l, cx<T>* buf, int N, int logN, int nb, bool inverse)
-{
-    if constexpr (sizeof(T) != 4) {
-        return false;
-    } else {
-        if (!d.ring_ct) return false;
-        const int m3 = d.ringM3[l];
-        const int per_call = max(1, min(nb, (m3 ? (FFT_REGS / 3) * 3 * NT : FFT_BLOCK_POINTS) / N));
-        const int code = (m3 << 8) | logN;
-        switch (code) {
-#define PAT_RC_CASE(a, b)                                                            \
-    case ((a) << 8) | (b):                                                           \
-        for (int i = 0; i < nb; i += per_call) {                                     \
-            if (inverse) ring_fft_ct<a, b, true>(d, buf + i * N, min(per_call, nb - i));  \
-            else ring_fft_ct<a, b, false>(d, buf + i * N, min(per_call, nb - i));         \
-        }                                                                            \
-        return true;
-            PAT_RC_SIZES(PAT_RC_CASE)
-#undef PAT_RC_CASE
-            default: return false;
-        }
-    }
-}
-
 // The ring transforms of nb images (ring l: N = 2^logN or 3 * 2^logN points),
 // as many sequences per lds_fft call as its register budget allows.
 template <typename T>
 __device__ __forceinline__ void ring_fft(const Dev<T>& d, int l, cx<T>* buf, int N, int logN, int nb, bool inverse)
 {
-    if (ring_fft_fixed(d, l, buf, N, logN, nb, inverse)) return;
     if (d.ringM3[l]) {
         const int per_call = max(1, min(nb, ((FFT_REGS / 3) * 3 * NT) / N));
         for (int i = 0; i < nb; i += per_call)
@@ -775,10 +614,10 @@ __device__ __forceinline__ void ring_fft(const Dev<T>& d, int l, cx<T>* buf, int
 // of each half-ring sample are computed once and applied to every image of
 // the group (the transcendental work does not depend on the image).
 template <typename T, int WMAX>
-__device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<T>* E, cx<T>* V, cx<T>* Ulow, size_t ws_img, int B,
-                                               int G)
+__device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<T>* E, const cx<T>* Pin, cx<T>* V,
+                                               cx<T>* Ulow, size_t ws_img, int B, int G)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     int l, grp;
     l = bk.x;
@@ -786,6 +625,19 @@ __device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<
     const int b0 = grp * G, nb = min(G, B - b0);
     const int N = d.ringN[l], logN = d.ringLog[l], Kl = d.ringK[l];
     const int mask = d.Ng - 1;
+    if (Pin) {
+        // samples gathered by gather_bins: Pin[(ringOff[l] + si) * B + b], phase applied
+        const cx<T>* src = Pin + (size_t)d.ringOff[l] * B + b0;
+        for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
+            const int s = si - N / 4;
+            for (int i = 0; i < nb; ++i) {
+                const cx<T> v = src[(size_t)si * B + i];
+                cx<T>* bi = buf + i * N;
+                bi[s < 0 ? s + N : s] = v;
+                bi[s + N / 2] = conjg(v);
+            }
+        }
+    } else
 #pragma unroll 2
     for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
         Taps<T, WMAX> tp;
@@ -825,10 +677,141 @@ __device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<
 }
 
 template <typename T, int WMAX>
-__global__ __launch_bounds__(NT) void ring_fwd(Dev<T> d, const cx<T>* E, cx<T>* V, cx<T>* Ulow, size_t ws_img, int B,
-                                               int G)
+__global__ __launch_bounds__(NT) void ring_fwd(Dev<T> d, const cx<T>* E, const cx<T>* Pin, cx<T>* V, cx<T>* Ulow,
+                                               size_t ws_img, int B, int G)
 {
-    ring_fwd_body<T, WMAX>(d, blk_xcd(), E, V, Ulow, ws_img, B, G);
+    ring_fwd_body<T, WMAX>(d, blk_xcd(), E, Pin, V, Ulow, ws_img, B, G);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 gather over samples sorted by bin (the order of spread_bins): a block
+// owns the 16 x 16 bins of a tile and BC images, stages the 21 x 21 cells
+// their stencils reach (rows mod Ng; each cell's BC values as one padded row)
+// in LDS with coalesced 16-byte loads, and each thread then interpolates
+// whole samples from LDS: the taps, weights and phase of point_taps and the
+// summation order of ring_fwd (row sums over x, then over y), so the values
+// equal those of ring_fwd's own gather.  Writes Pout[p * B + b], p the
+// sample's ring-order index (BC contiguous values per sample).
+// ---------------------------------------------------------------------------
+constexpr int GB_TILE = 16;
+constexpr int GB_BC = 8;  // images per block (35 KB of LDS: 4 blocks per CU)
+__host__ __device__ constexpr int gather_bins_row(int bc) { return bc + 2; }   // cx per staged cell
+__host__ __device__ constexpr size_t gather_bins_lds(int bc)
+{
+    return 256 + 8 * (size_t)(GB_TILE + 5) * (GB_TILE + 5) * (size_t)gather_bins_row(bc);
+}
+
+template <int BC>
+__device__ __forceinline__ void gather_bins_body(const Dev<float>& d, Blk bk, const cx<float>* E, cx<float>* Pout, int B,
+                                                 size_t ws_img)
+{
+    constexpr int W = 6, TS = GB_TILE, NC = TS + W - 1, CR = gather_bins_row(BC), TPS = BC / 2;
+    static_assert(TS <= 32 && CR % 2 == 0, "tile and LDS layout");
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    int* s_vo = reinterpret_cast<int*>(smem_raw);           // TS + 1 run offsets
+    int* s_gs = s_vo + 32;                                   // TS first slots
+    float4* s_cell = reinterpret_cast<float4*>(smem_raw + 256);  // NC x NC cells of CR / 2 float4
+    const int tid = threadIdx.x;
+    const int ex0 = bk.x * TS, ty0 = bk.y * TS;
+    const int Ng = d.Ng, mask = Ng - 1, Ew = d.Ew;
+    const int b0 = bk.z * BC, nb = min(BC, B - b0);
+    const int e_end = min(ex0 + TS, Ew);
+    if (tid < TS) {
+        const int row = (ty0 + tid) & mask;
+        const int a = d.binStart[(size_t)row * Ew + ex0], b = d.binStart[(size_t)row * Ew + e_end];
+        s_gs[tid] = a;
+        s_vo[tid + 1] = b - a;
+    }
+    // stage the cells: (row, column, image pair) tasks, coalesced along the row
+    for (int t = tid; t < NC * NC * TPS; t += NT) {
+        const int m = t % TPS, c = t / TPS;
+        const int lx = c % NC, ly = c / NC;
+        const int ex = ex0 + lx, gy = (ty0 + ly) & mask;
+        float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ex < Ew) {
+            const int k = 2 * m;
+            if (k < nb) {
+                const cx<float> v = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(E) +
+                                                                     (size_t)(b0 + k) * ws_img)[(size_t)gy * Ew + ex];
+                x.x = v.x; x.y = v.y;
+            }
+            if (k + 1 < nb) {
+                const cx<float> v = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(E) +
+                                                                     (size_t)(b0 + k + 1) * ws_img)[(size_t)gy * Ew + ex];
+                x.z = v.x; x.w = v.y;
+            }
+        }
+        s_cell[c * (CR / 2) + m] = x;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        s_vo[0] = 0;
+        for (int q = 0; q < TS; ++q) s_vo[q + 1] += s_vo[q];
+    }
+    __syncthreads();
+    const int S = s_vo[TS];
+    const float hwf = 0.5f * float(W), tw_ = 2.f / float(W);
+    for (int v = tid; v < S; v += NT) {
+        int q = 0;
+        while (q + 1 < TS && s_vo[q + 1] <= v) ++q;
+        const int g = s_gs[q] + v - s_vo[q];
+        const cx<float> pq = d.binPos[g];
+        const int gx0 = (int)ceil_t(pq.x - hwf);
+        const int gy0 = (int)ceil_t(pq.y - hwf);
+        float wx[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) wx[j] = es_w(pq.x - float(gx0 + j), tw_, d.beta, d.beta_l2e);
+        const cx<float> ph = point_phase(d, pq.x, pq.y);
+        const int lx0 = gx0 + d.hw - ex0, ly0 = (gy0 - ty0) & mask;  // both in [0, TS)
+        cx<float>* dst = Pout + (size_t)d.binRing[g] * B + b0;
+        const float4* base = s_cell + (ly0 * NC + lx0) * (CR / 2);
+        // four images at a time (two float4 per cell) and one stencil row at a
+        // time (its y-weight evaluated there), so that the reads in flight fit
+        // the registers of 4 waves per SIMD
+#pragma unroll 1
+        for (int mc = 0; mc < TPS; mc += 2) {
+            float4 acc[2] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
+#pragma unroll 1
+            for (int jy = 0; jy < W; ++jy) {
+                const float wyj = es_w(pq.y - float(gy0 + jy), tw_, d.beta, d.beta_l2e);
+                const float4* rowp = base + jy * NC * (CR / 2) + mc;
+                float4 racc[2] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
+#pragma unroll
+                for (int jx = 0; jx < W; ++jx) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const float4 c = rowp[jx * (CR / 2) + h];
+                        racc[h].x += c.x * wx[jx];
+                        racc[h].y += c.y * wx[jx];
+                        racc[h].z += c.z * wx[jx];
+                        racc[h].w += c.w * wx[jx];
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    acc[h].x += racc[h].x * wyj;
+                    acc[h].y += racc[h].y * wyj;
+                    acc[h].z += racc[h].z * wyj;
+                    acc[h].w += racc[h].w * wyj;
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = 2 * (mc + h);
+                const cx<float> v0 = cmul(cx<float>{acc[h].x, acc[h].y}, ph);
+                const cx<float> v1 = cmul(cx<float>{acc[h].z, acc[h].w}, ph);
+                if (k < nb) dst[k] = v0;
+                if (k + 1 < nb) dst[k + 1] = v1;
+            }
+        }
+    }
+}
+
+// at least 4 waves per SIMD: caps the registers the unrolled tap reads may take
+template <int BC>
+__global__ __launch_bounds__(NT, 4) void gather_bins(Dev<float> d, const cx<float>* E, cx<float>* Pout, int B, size_t ws_img)
+{
+    gather_bins_body<BC>(d, blk_xcd(), E, Pout, B, ws_img);
 }
 
 // Sum over aligned groups of W consecutive lanes (W a power of two <= 64),
@@ -869,7 +852,7 @@ template <typename T>
 __device__ __forceinline__ void dct_cos_body(const Dev<T>& d, Blk bk, const cx<T>* in, cx<T>* out, size_t ws_img,
                                              int adjoint)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     __shared__ cx<T> red[16];     // one entry per lane group (a column's lanes inside one wave;
     __shared__ cx<T> red2[16];    // at most 16 groups: CW <= 16, or 4 waves)
@@ -980,7 +963,7 @@ __device__ __forceinline__ void dct_cos_body(const Dev<T>& d, Blk bk, const cx<T
 template <typename T>
 __device__ __forceinline__ void dct_cols_body(const Dev<T>& d, Blk bk, const cx<T>* in, cx<T>* out, size_t ws_img, int adjoint)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     const int bx_ = bk.x, b = bk.y;
     const int CW = d.dctCW, lcw = d.dctLCW, k0 = bx_ * CW;
@@ -1241,7 +1224,7 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
 {
     using S = DwShape<M3, LOGP>;
     constexpr int M = S::M, NC = S::NC, CB = S::CB, CP = S::CP;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     PAT_LDS cx<float>* lbuf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw);
     const PAT_GLOBAL cx<float>* twd = (const PAT_GLOBAL cx<float>*)d.twd;
     const int k0 = bk.x * CB, b = bk.y;
@@ -1490,7 +1473,7 @@ __device__ __forceinline__ void rows_fwd_w_body(const Dev<float>& d, Blk bk, con
                                                 cx<float>* R, size_t ws_img)
 {
     constexpr int Ng = 1 << LOGN;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     PAT_LDS cx<float>* buf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw) + wave * wf_pitch(LOGN);
     const int pair = bk.x * WF_WAVES + wave, b = bk.y;
@@ -1529,7 +1512,7 @@ __device__ __forceinline__ void rows_adj_w_body(const Dev<float>& d, Blk bk, con
                                                 size_t ws_img)
 {
     constexpr int Ng = 1 << LOGN, hN = Ng / 2;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     PAT_LDS cx<float>* buf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw) + wave * wf_pitch(LOGN);
     const int pair = bk.x * WF_WAVES + wave, b = bk.y;
@@ -1570,7 +1553,7 @@ __device__ __forceinline__ void cols_fwd_w_body(const Dev<float>& d, Blk bk, con
                                                 size_t ws_img)
 {
     constexpr int Ng = 1 << LOGN, CB = WF_WAVES, CP = wf_pitch(LOGN);
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     PAT_LDS cx<float>* lbuf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw);
     const int x0 = bk.x * CB, b = bk.y, n = d.n;
     const cx<float>* Rb = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(R) + (size_t)b * ws_img);
@@ -1609,7 +1592,7 @@ __device__ __forceinline__ void cols_adj_w_body(const Dev<float>& d, Blk bk, con
                                                 size_t ws_img)
 {
     constexpr int Ng = 1 << LOGN, CB = WF_WAVES, CP = wf_pitch(LOGN);
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     PAT_LDS cx<float>* lbuf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw);
     const int x0 = bk.x * CB, b = bk.y, n = d.n;
     const cx<float>* Eb = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(E) + (size_t)b * ws_img);
@@ -1646,7 +1629,7 @@ __device__ __forceinline__ void synth_fwd_w_body(const Dev<float>& d, Blk bk, co
                                                  size_t ws_img)
 {
     constexpr int mf = 1 << LOGM;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     PAT_LDS cx<float>* buf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw) + wave * wf_pitch(LOGM);
     const int pair = bk.x * WF_WAVES + wave, b = bk.y;
@@ -1687,7 +1670,7 @@ __device__ __forceinline__ void synth_adj_w_body(const Dev<float>& d, Blk bk, co
                                                  size_t ws_img)
 {
     constexpr int mf = 1 << LOGM;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     PAT_LDS cx<float>* buf = (PAT_LDS cx<float>*)reinterpret_cast<cx<float>*>(smem_raw) + wave * wf_pitch(LOGM);
     const int pair = bk.x * WF_WAVES + wave, b = bk.y;
@@ -1854,7 +1837,7 @@ __global__ __launch_bounds__(NT) void lowk_fwd(Dev<T> d, const cx<T>* Ulow, cx<T
 template <typename T>
 __device__ __forceinline__ void synth_fwd_body(const Dev<T>& d, Blk bk, const cx<T>* G, T* g, long gstride, size_t ws_img)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cx<T>* Z1 = reinterpret_cast<cx<T>*>(smem_raw);
     cx<T>* Z2 = Z1 + d.mf;
     int bx_, b;
@@ -1907,7 +1890,7 @@ __global__ __launch_bounds__(NT) void synth_fwd(Dev<T> d, const cx<T>* G, T* g, 
 template <typename T>
 __device__ __forceinline__ void synth_adj_body(const Dev<T>& d, Blk bk, const T* g, long gstride, cx<T>* G, size_t ws_img)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cx<T>* Z = reinterpret_cast<cx<T>*>(smem_raw);
     int bx_, b;
     bx_ = bk.x;
@@ -1974,12 +1957,12 @@ __global__ __launch_bounds__(NT) void lowk_adj(Dev<T> d, const cx<T>* G, cx<T>* 
 }
 
 // Samples are written image-minor, Pol[(ringOff[l] + si) * B + b], already
-// multiplied by the conjugate point phase, for the batched spread below.
+// multiplied by the conjugate point phase, for the batched spreads below.
 template <typename T, int WMAX>
 __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<T>* V, const cx<T>* Ulow, cx<T>* Pol, int B,
                                               int G, size_t ws_img)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     // no XCD renumbering here: contiguous ranges of rings would unbalance the XCDs
     const int grp = bk.x, l = bk.y;
@@ -2039,8 +2022,12 @@ template <typename T, int W, int BC, bool STAGED>
 __device__ __forceinline__ void spread_tiles_body(const Dev<T>& d, Blk bk, const cx<T>* Pol, int B, cx<T>* E, size_t ws_img)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __shared__ cx<T> st_pos[STAGED ? 4 : 1][64];
-    __shared__ cx<T> st_val[STAGED ? 4 : 1][STAGED ? 64 * BC : 1];
+    // staging slots (dynamic LDS, spread_tiles_lds bytes): 64 positions and
+    // 64 * BC values per wave
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+    cx<T>* st_pos = lds + wave * 64;
+    cx<T>* st_val = lds + 4 * 64 + wave * 64 * BC;
     int bxt, byt;
     bxt = bk.x;
     byt = bk.y;
@@ -2129,16 +2116,16 @@ __device__ __forceinline__ void spread_tiles_body(const Dev<T>& d, Blk bk, const
                                 __builtin_amdgcn_wave_barrier();
                                 if (lane < cnt) {
                                     const cx<T>* src = Pol + (size_t)(base + lane) * B + b0;
-                                    st_pos[wave][lane] = d.pos[base + lane];
+                                    st_pos[lane] = d.pos[base + lane];
 #pragma unroll
-                                    for (int k = 0; k < BC; ++k) st_val[wave][lane * BC + k] = src[k];
+                                    for (int k = 0; k < BC; ++k) st_val[lane * BC + k] = src[k];
                                 }
                                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                                 __builtin_amdgcn_wave_barrier();
                                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll 4
                                 for (int j = 0; j < cnt; ++j) {
-                                    const cx<T> q = st_pos[wave][j];
+                                    const cx<T> q = st_pos[j];
                                     const int gx0 = (int)ceil_t(q.x - hwf);
                                     const int gy0 = (int)ceil_t(q.y - hwf);
                                     const int jx = gx - gx0;
@@ -2147,7 +2134,7 @@ __device__ __forceinline__ void spread_tiles_body(const Dev<T>& d, Blk bk, const
                                         const T wgt = es_w(q.x - T(gx0 + jx), tw_, d.beta, d.beta_l2e) *
                                                       es_w(q.y - T(gy0 + jy), tw_, d.beta, d.beta_l2e);
 #pragma unroll
-                                        for (int k = 0; k < BC; ++k) acc[k] = acc[k] + st_val[wave][j * BC + k] * wgt;
+                                        for (int k = 0; k < BC; ++k) acc[k] = acc[k] + st_val[j * BC + k] * wgt;
                                     }
                                 }
                             }
@@ -2217,10 +2204,165 @@ __global__ __launch_bounds__(NT) void spread_tiles(Dev<T> d, const cx<T>* Pol, i
     spread_tiles_body<T, W, BC, STAGED>(d, bk, Pol, B, E, ws_img);
 }
 
+// Dynamic LDS bytes of spread_tiles with image group bc (element size cs).
+__host__ __device__ constexpr size_t spread_tiles_lds(bool staged, int bc, size_t cs)
+{
+    return staged ? cs * 4 * 64 * (size_t)(bc + 1) : 0;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 transpose of the gather over samples sorted by bin: the bin of a sample
+// is the cell of its first tap, gy0 = ceil(y - w/2) mod Ng and
+// gx0 = ceil(x - w/2) (ring order within a bin; binRing maps the bin order
+// back to the ring order of Pol).  Cell (gx, gy) receives exactly the samples
+// of the bins gx0 in [gx - w + 1, gx], gy0 in [gy - w + 1, gy]: in each of
+// those w bin rows, one contiguous run of slots.  A block owns a 16 x 16 tile
+// of cells (one per thread) and BC images.  It stages the runs of the tile's
+// 21 bin rows in LDS (positions, and each sample's BC values as one padded
+// row read with 16-byte loads), at most SB samples per pass, and then every
+// lane walks its own w runs: a lane visits only the ~31 samples that feed
+// its cell, where the lockstep walk of spread_tiles visits the union of the
+// tile's windows (~5x more).  Summation order per cell: bin row, then slot,
+// whatever the pass split; no atomics.
+// ---------------------------------------------------------------------------
+constexpr int SB_TILE = 16;
+__host__ __device__ constexpr int spread_bins_cap(int bc) { return bc >= 16 ? 256 : 384; }
+// sample row of the staged values: BC values and 16 bytes of padding, so
+// that the 16-byte reads of lanes on neighbouring samples use other banks
+__host__ __device__ constexpr int spread_bins_row(int bc) { return bc + 2; }
+__host__ __device__ constexpr size_t spread_bins_lds(int bc)
+{
+    return 256 + (size_t)spread_bins_cap(bc) * (4 + 8 + 8 * (size_t)spread_bins_row(bc));
+}
+
+template <int BC>
+__device__ __forceinline__ void spread_bins_body(const Dev<float>& d, Blk bk, const cx<float>* Pol, int B, cx<float>* E,
+                                                 size_t ws_img)
+{
+    constexpr int W = 6, TS = SB_TILE, NR = TS + W - 1;
+    constexpr int SB = spread_bins_cap(BC), SR = spread_bins_row(BC), TPS = BC / 2;
+    static_assert(NR <= 32 && TS * TS == NT && SB % 4 == 0 && SR % 2 == 0, "tile and LDS layout");
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    unsigned char* lds = smem_raw;
+    int* s_vo = reinterpret_cast<int*>(lds);                  // NR + 1 run offsets (virtual index)
+    int* s_gs = s_vo + 32;                                    // NR first slots
+    int* s_map = reinterpret_cast<int*>(lds + 256);           // SB: slot of each staged sample
+    cx<float>* s_pos = reinterpret_cast<cx<float>*>(lds + 256 + 4 * SB);
+    float4* s_val = reinterpret_cast<float4*>(lds + 256 + 12 * SB);   // SB rows of SR / 2 float4
+    const int tid = threadIdx.x, cx_ = tid & (TS - 1), cy = tid / TS;
+    const int ex0 = bk.x * TS, ty0 = bk.y * TS;
+    const int e = ex0 + cx_, gy = ty0 + cy;
+    const int Ng = d.Ng, mask = Ng - 1, Ew = d.Ew;
+    const int b0 = bk.z * BC, nb = min(BC, B - b0);
+    const bool valid = e < Ew;  // Ng is a multiple of the tile
+    const int gx = e - d.hw;
+    const int e_lo = max(ex0 - (W - 1), 0), e_hi = min(ex0 + TS - 1, Ew - 1);
+    if (tid < NR) {
+        const int row = (ty0 - (W - 1) + tid) & mask;
+        const int a = d.binStart[(size_t)row * Ew + e_lo], b = d.binStart[(size_t)row * Ew + e_hi + 1];
+        s_gs[tid] = a;
+        s_vo[tid + 1] = b - a;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        s_vo[0] = 0;
+        for (int q = 0; q < NR; ++q) s_vo[q + 1] += s_vo[q];
+    }
+    __syncthreads();
+    const int S = s_vo[NR];
+    // this lane's runs (virtual indices) in its bin rows q = cy .. cy + W - 1
+    int lo[W], hi[W];
+#pragma unroll
+    for (int r = 0; r < W; ++r) {
+        lo[r] = 0;
+        hi[r] = 0;
+        if (valid) {
+            const int q = cy + r, row = (ty0 - (W - 1) + q) & mask;
+            const int a = d.binStart[(size_t)row * Ew + max(e - (W - 1), 0)];
+            const int b = d.binStart[(size_t)row * Ew + e + 1];
+            lo[r] = s_vo[q] + a - s_gs[q];
+            hi[r] = s_vo[q] + b - s_gs[q];
+        }
+    }
+    const float hwf = 0.5f * float(W), tw_ = 2.f / float(W);
+    float4 acc[TPS];
+#pragma unroll
+    for (int m = 0; m < TPS; ++m) acc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int pv = 0; pv < S; pv += SB) {
+        const int cnt = min(SB, S - pv);
+        __syncthreads();  // the previous pass's walk is done with the slots
+        for (int q = 0; q < NR; ++q) {
+            const int a = max(s_vo[q], pv), b = min(s_vo[q + 1], pv + cnt);
+            for (int v = a + tid; v < b; v += NT) s_map[v - pv] = s_gs[q] + v - s_vo[q];
+        }
+        __syncthreads();
+        // every load of this loop is independent of the others
+#pragma unroll 4
+        for (int t = tid; t < cnt * TPS; t += NT) {
+            const int v = t / TPS, m = t - v * TPS;
+            const int g = s_map[v];
+            const cx<float>* src = Pol + (size_t)d.binRing[g] * B + b0 + 2 * m;
+            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (2 * m < nb) { x.x = src[0].x; x.y = src[0].y; }
+            if (2 * m + 1 < nb) { x.z = src[1].x; x.w = src[1].y; }
+            s_val[v * (SR / 2) + m] = x;
+            if (m == 0) s_pos[v] = d.binPos[g];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < W; ++r) {
+            const int a = max(lo[r], pv) - pv, b = min(hi[r], pv + cnt) - pv;
+            for (int j = a; j < b; ++j) {
+                // the binning puts every staged sample of this run inside the
+                // cell's stencil: gx - gx0 and (gy - gy0) mod Ng lie in [0, W)
+                const cx<float> q = s_pos[j];
+                float4 val[TPS];
+#pragma unroll
+                for (int m = 0; m < TPS; ++m) val[m] = s_val[j * (SR / 2) + m];
+                const int gy0 = (int)ceil_t(q.y - hwf);
+                const int jy = (gy - gy0) & mask;
+                const float wgt = es_w(q.x - float(gx), tw_, d.beta, d.beta_l2e) *
+                                  es_w(q.y - float(gy0 + jy), tw_, d.beta, d.beta_l2e);
+#pragma unroll
+                for (int m = 0; m < TPS; ++m) {
+                    acc[m].x += val[m].x * wgt;
+                    acc[m].y += val[m].y * wgt;
+                    acc[m].z += val[m].z * wgt;
+                    acc[m].w += val[m].w * wgt;
+                }
+            }
+        }
+    }
+    if (valid) {
+#pragma unroll
+        for (int m = 0; m < TPS; ++m) {
+            const cx<float> lo2[2] = {{acc[m].x, acc[m].y}, {acc[m].z, acc[m].w}};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = 2 * m + h;
+                if (k < nb) {
+                    cx<float>* Eb = reinterpret_cast<cx<float>*>(reinterpret_cast<char*>(E) + (size_t)(b0 + k) * ws_img);
+                    Eb[(size_t)gy * Ew + e] = lo2[h];
+                }
+            }
+        }
+    }
+}
+
+// Heaviest tiles first, as spread_tiles: block rows 0, last, 1, last - 1, ...
+template <int BC>
+__global__ __launch_bounds__(NT) void spread_bins(Dev<float> d, const cx<float>* Pol, int B, cx<float>* E, size_t ws_img)
+{
+    Blk bk = blk_plain();
+    const int k = bk.y;
+    bk.y = (k & 1) ? (int)gridDim.y - 1 - (k >> 1) : (k >> 1);
+    spread_bins_body<BC>(d, bk, Pol, B, E, ws_img);
+}
+
 template <typename T>
 __device__ __forceinline__ void cols_adj_body(const Dev<T>& d, Blk bk, const cx<T>* E, cx<T>* R, size_t ws_img)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     int bx_, b;
     bx_ = bk.x;
@@ -2275,7 +2417,7 @@ __device__ __forceinline__ double block_sum_fixed(double v)
 template <typename T>
 __device__ __forceinline__ void rows_adj_body(const Dev<T>& d, Blk bk, const cx<T>* R, T* f, long fstride, size_t ws_img)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     int bx_, b;
     bx_ = bk.x;
@@ -2381,7 +2523,7 @@ template <typename T>
 __global__ __launch_bounds__(NT) void trace_filter(FiltDev<T> d, const T* in, long istride, T* out, long ostride,
                                                    int adjoint)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
     const Blk bk = blk_xcd();
     const int i0 = bk.x * d.CW, b = bk.y;
@@ -2437,8 +2579,8 @@ struct pat_plan_s {
     // launch-shape choices (defaults from LDS limits; replaced by the autotuner's)
     int cols_cw = 1, dct_cw = 1, ring_g = 1, spread_bc = 16, fft_lr = 4, tw_table = 0, spread_staged = 1;
     int dct_wave_on = 1;                  // 1: use dct_wave where the plan's lengths allow it
-    int wave_fft_on = 1;                  // 1: wave forms of the row / column / synthesis FFT kernels and
-                                          //    compile-time-length ring transforms
+    int wave_fft_on = 1;                  // 1: wave forms of the row / column / synthesis FFT kernels
+    int bin_ok = 0;                       // 1: the bin tables of spread_bins exist (FP32 plans)
     int tuned = 0;                        // 1: measured now, 2: read from the tuning cache
     double tuned_ms = 0.0;
     // optional per-stage timing with HIP events recorded on the launch stream
@@ -2723,6 +2865,40 @@ int upload(pat_plan_s* p, Dev<T>& d)
     if ((rc = put(twm.data(), twm.size() * sizeof(T), (const void**)&d.twm))) return rc;
     std::vector<T> pos = conv(H.pos);
     if ((rc = put(pos.data(), pos.size() * sizeof(T), (const void**)&d.pos))) return rc;
+    d.binRing = nullptr; d.binStart = nullptr; d.binPos = nullptr; d.binned = 0;
+    if constexpr (sizeof(T) == 4) {
+        // counting sort of the samples by the cell of their first tap, computed
+        // with the same FP32 operations as the kernels' tap rule
+        const size_t nb = (size_t)P.Ng * P.Ew;
+        std::vector<int> key(P.npts), start(nb + 1, 0), ring(P.npts);
+        bool ok = true;
+        const float hwf = 0.5f * (float)P.w;
+        for (int q = 0; q < P.npts && ok; ++q) {
+            const int gx0 = (int)std::ceil(pos[2 * (size_t)q] - hwf);
+            const int gy0 = (int)std::ceil(pos[2 * (size_t)q + 1] - hwf);
+            const int e0 = gx0 + P.hw, row = gy0 & (P.Ng - 1);
+            if (e0 < 0 || e0 >= P.Ew) ok = false;
+            key[q] = row * P.Ew + e0;
+        }
+        if (ok) {
+            for (int q = 0; q < P.npts; ++q) ++start[(size_t)key[q] + 1];
+            for (size_t k = 0; k < nb; ++k) start[k + 1] += start[k];
+            std::vector<int> fill(start.begin(), start.end() - 1);
+            std::vector<T> bpos(2 * (size_t)P.npts);
+            for (int q = 0; q < P.npts; ++q) {
+                const int slot = fill[key[q]]++;
+                ring[slot] = q;
+                bpos[2 * (size_t)slot] = pos[2 * (size_t)q];
+                bpos[2 * (size_t)slot + 1] = pos[2 * (size_t)q + 1];
+            }
+            if ((rc = put(ring.data(), ring.size() * sizeof(int), (const void**)&d.binRing))) return rc;
+            if ((rc = put(start.data(), start.size() * sizeof(int), (const void**)&d.binStart))) return rc;
+            if ((rc = put(bpos.data(), bpos.size() * sizeof(T), (const void**)&d.binPos))) return rc;
+            p->bin_ok = 1;
+        }
+    }
+    if (!p->bin_ok && p->spread_staged == 2) p->spread_staged = 1;
+    d.binned = p->spread_staged == 2 ? 1 : 0;
     std::vector<T> Tbi = conv(H.Tbi), MkiT = transpose_lowk(H.Mki);
     if ((rc = put(Tbi.data(), Tbi.size() * sizeof(T), (const void**)&d.Tbi))) return rc;
     if ((rc = put(MkiT.data(), MkiT.size() * sizeof(T), (const void**)&d.MkiT))) return rc;
@@ -2740,7 +2916,6 @@ int upload(pat_plan_s* p, Dev<T>& d)
     d.dwCB = dw_columns(d.dct_wave);
     d.wfRows = p->wave_fft_on ? wf_rows_variant(P) : 0;
     d.wfSynth = p->wave_fft_on ? wf_synth_variant(P) : 0;
-    d.ring_ct = p->wave_fft_on && sizeof(T) == 4;
     d.fft_lr = p->fft_lr;
     d.tw_table = p->tw_table;
     d.phase_k = (T)(-P.shift * P.h / (0.5 * P.Ng / P.Lam));
@@ -2840,9 +3015,21 @@ int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g
     }
     if ((rc = check_launch("cols_fwd"))) return rc;
     {
+        const cx<T>* Pin = nullptr;
+        if constexpr (sizeof(T) == 4) {
+            if (d.binned) {
+                // the batch's sample array (the adjoint's Pol) holds the gathered samples
+                StageTimer tg(p, st, PAT_STAGE_GATHER_FWD);
+                cx<T>* Pg = reinterpret_cast<cx<T>*>(ws + (size_t)B * p->ws_stride);
+                const dim3 grid((d.Ew + GB_TILE - 1) / GB_TILE, d.Ng / GB_TILE, (B + GB_BC - 1) / GB_BC);
+                gather_bins<GB_BC><<<grid, NT, gather_bins_lds(GB_BC), st>>>(d, E, Pg, B, wi);
+                Pin = Pg;
+            }
+            if ((rc = check_launch("gather_bins"))) return rc;
+        }
         StageTimer tm(p, st, 2);
         const int G = std::max(1, std::min(p->ring_g, B));
-        ring_fwd<T, WMAX><<<dim3(d.L, (B + G - 1) / G), NT, cs * G * p->H.P.max_ring, st>>>(d, E, V, U, wi, B, G);
+        ring_fwd<T, WMAX><<<dim3(d.L, (B + G - 1) / G), NT, cs * G * p->H.P.max_ring, st>>>(d, E, Pin, V, U, wi, B, G);
     }
     if ((rc = check_launch("ring_fwd"))) return rc;
     {
@@ -2933,12 +3120,23 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
         constexpr int BCL = sizeof(T) == 4 ? 16 : 8;  // image group of the spread: BCL or BCL / 2
         const dim3 grid((d.Ew + 15) / 16, (d.Ng + 15) / 16, 1);
         const dim3 g1(grid.x, grid.y, (B + BCL - 1) / BCL), g2(grid.x, grid.y, (B + BCL / 2 - 1) / (BCL / 2));
-        if (p->spread_bc >= BCL) {
-            if (p->spread_staged) spread_tiles<T, WMAX, BCL, true><<<g1, NT, 0, st>>>(d, Pol, B, E, wi);
-            else spread_tiles<T, WMAX, BCL, false><<<g1, NT, 0, st>>>(d, Pol, B, E, wi);
-        } else {
-            if (p->spread_staged) spread_tiles<T, WMAX, BCL / 2, true><<<g2, NT, 0, st>>>(d, Pol, B, E, wi);
-            else spread_tiles<T, WMAX, BCL / 2, false><<<g2, NT, 0, st>>>(d, Pol, B, E, wi);
+        const size_t l1 = spread_tiles_lds(true, BCL, cs), l2 = spread_tiles_lds(true, BCL / 2, cs);
+        bool done = false;
+        if constexpr (sizeof(T) == 4) {
+            if (d.binned) {
+                if (p->spread_bc >= BCL) spread_bins<BCL><<<g1, NT, spread_bins_lds(BCL), st>>>(d, Pol, B, E, wi);
+                else spread_bins<BCL / 2><<<g2, NT, spread_bins_lds(BCL / 2), st>>>(d, Pol, B, E, wi);
+                done = true;
+            }
+        }
+        if (!done) {
+            if (p->spread_bc >= BCL) {
+                if (p->spread_staged) spread_tiles<T, WMAX, BCL, true><<<g1, NT, l1, st>>>(d, Pol, B, E, wi);
+                else spread_tiles<T, WMAX, BCL, false><<<g1, NT, 0, st>>>(d, Pol, B, E, wi);
+            } else {
+                if (p->spread_staged) spread_tiles<T, WMAX, BCL / 2, true><<<g2, NT, l2, st>>>(d, Pol, B, E, wi);
+                else spread_tiles<T, WMAX, BCL / 2, false><<<g2, NT, 0, st>>>(d, Pol, B, E, wi);
+            }
         }
     }
     if ((rc = check_launch("spread_adj"))) return rc;
@@ -3015,6 +3213,9 @@ struct GroupPlan {
     int off[PAT_NUM_STAGES];
 };
 
+// the binned gather (FP32 plans with binned samples), launched before RING_FWD
+constexpr int STAGE_GATHER = PAT_STAGE_GATHER_FWD;
+
 template <typename T>
 struct GroupArgs {
     GroupPlan<T> p[GROUP_MAX];
@@ -3047,6 +3248,10 @@ __host__ __device__ inline void stage_grid(const Dev<T>& d, int S, int B, int G,
             break;
         case PAT_STAGE_LOWK_ADJ: nx = d.lcorr; ny = B; break;
         case PAT_STAGE_RING_ADJ: nx = (B + G - 1) / G; ny = d.L; break;
+        case STAGE_GATHER:
+            if (d.binned) { nx = (d.Ew + GB_TILE - 1) / GB_TILE; ny = d.Ng / GB_TILE; nz = (B + GB_BC - 1) / GB_BC; }
+            else { nx = 0; ny = 1; }
+            break;
         default: nx = (d.Ew + 15) / 16; ny = (d.Ng + 15) / 16; nz = (B + BC - 1) / BC; break;  // spread
     }
 }
@@ -3095,7 +3300,10 @@ __global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
     }
     if constexpr (S == PAT_STAGE_ROWS_FWD) rows_fwd_body<T>(q.d, bk, q.fin, q.fs, R, q.wi);
     if constexpr (S == PAT_STAGE_COLS_FWD) cols_fwd_body<T>(q.d, bk, R, E, q.wi);
-    if constexpr (S == PAT_STAGE_RING_FWD) ring_fwd_body<T, WMAX>(q.d, bk, E, V, U, q.wi, q.B, q.G);
+    if constexpr (S == STAGE_GATHER) {
+        if constexpr (sizeof(T) == 4) gather_bins_body<GB_BC>(q.d, bk, E, Pol, q.B, q.wi);
+    }
+    if constexpr (S == PAT_STAGE_RING_FWD) ring_fwd_body<T, WMAX>(q.d, bk, E, q.d.binned ? Pol : nullptr, V, U, q.wi, q.B, q.G);
     if constexpr (S == PAT_STAGE_DCT_FWD) {
         if constexpr (sizeof(T) == 4) {
             if (q.d.dct_wave) { dct_wave_dispatch(q.d, bk, V, Gh, q.wi, 0); return; }
@@ -3116,6 +3324,15 @@ __global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
     }
     if constexpr (S == PAT_STAGE_RING_ADJ) ring_adj_body<T, WMAX>(q.d, bk, V, U, Pol, q.B, q.G, q.wi);
     if constexpr (S == PAT_STAGE_SPREAD_ADJ) {
+        if constexpr (sizeof(T) == 4) {
+            if (q.d.binned) {
+                // heaviest tile rows first, as the single-plan launch
+                const int ny = (q.d.Ng + 15) / 16, k = bk.y;
+                bk.y = (k & 1) ? ny - 1 - (k >> 1) : (k >> 1);
+                spread_bins_body<BC>(q.d, bk, Pol, q.B, E, q.wi);
+                return;
+            }
+        }
         if (q.staged) spread_tiles_body<T, WMAX, BC, true>(q.d, bk, Pol, q.B, E, q.wi);
         else spread_tiles_body<T, WMAX, BC, false>(q.d, bk, Pol, q.B, E, q.wi);
     }
@@ -3144,6 +3361,12 @@ size_t stage_lds(const pat_plan_s* p, int S, int G)
         case PAT_STAGE_SYNTH_FWD: return p->df.wfSynth ? wf_lds(p->df.wfSynth) : cs * 2 * P.mf;
         case PAT_STAGE_SYNTH_ADJ: return p->df.wfSynth ? wf_lds(p->df.wfSynth) : cs * P.mf;
         case PAT_STAGE_RING_ADJ: return cs * G * P.max_ring;
+        case PAT_STAGE_SPREAD_ADJ: {
+            const int bc = (P.dt == PAT_F64) ? 8 : 16;  // the grouped launch's image group
+            if (P.dt == PAT_F32 && p->spread_staged == 2) return spread_bins_lds(bc);
+            return spread_tiles_lds(p->spread_staged != 0, bc, cs);
+        }
+        case STAGE_GATHER: return (P.dt == PAT_F32 && p->spread_staged == 2) ? gather_bins_lds(GB_BC) : 0;
         default: return 0;
     }
 }
@@ -3202,6 +3425,9 @@ int group_run(const std::vector<pat_plan_s*>& plans, bool adjoint, const int* ba
     if (!adjoint) {
         if ((rc = launch_grouped<PAT_STAGE_ROWS_FWD, T, WMAX>(ga, total[0], lds[0], st))) return rc;
         if ((rc = launch_grouped<PAT_STAGE_COLS_FWD, T, WMAX>(ga, total[1], lds[1], st))) return rc;
+        if (total[STAGE_GATHER] > 0 &&
+            (rc = launch_grouped<STAGE_GATHER, T, WMAX>(ga, total[STAGE_GATHER], lds[STAGE_GATHER], st)))
+            return rc;
         if ((rc = launch_grouped<PAT_STAGE_RING_FWD, T, WMAX>(ga, total[2], lds[2], st))) return rc;
         if ((rc = launch_grouped<PAT_STAGE_DCT_FWD, T, WMAX>(ga, total[3], lds[3], st))) return rc;
         if ((rc = launch_grouped<PAT_STAGE_LOWK_FWD, T, WMAX>(ga, total[4], lds[4], st))) return rc;
@@ -3234,7 +3460,7 @@ void default_tune(pat_plan_s* p)
     p->spread_bc = (P.dt == PAT_F64) ? 8 : 16;
     p->fft_lr = 4;
     p->tw_table = 0;
-    p->spread_staged = 1;
+    p->spread_staged = (P.dt == PAT_F64) ? 1 : 2;  // FP32: the binned spread (if its tables build)
     p->dct_wave_on = 1;
     p->wave_fft_on = 1;
 }
@@ -3253,8 +3479,8 @@ void apply_tune(pat_plan_s* p)
     p->df.dwCB = p->dd.dwCB = dw_columns(p->df.dct_wave);
     p->df.wfRows = p->dd.wfRows = p->wave_fft_on ? wf_rows_variant(p->H.P) : 0;
     p->df.wfSynth = p->dd.wfSynth = p->wave_fft_on ? wf_synth_variant(p->H.P) : 0;
-    p->df.ring_ct = p->wave_fft_on;
-    p->dd.ring_ct = 0;
+    p->df.binned = (p->spread_staged == 2 && p->bin_ok) ? 1 : 0;
+    p->dd.binned = 0;
 }
 
 bool pow2_in(int v, int hi) { return v >= 1 && v <= hi && (v & (v - 1)) == 0; }
@@ -3265,7 +3491,8 @@ bool tune_valid(const pat_plan_s* p)
     const int bcl = (P.dt == PAT_F64) ? 8 : 16;
     return pow2_in(p->cols_cw, lds_cols(P)) && pow2_in(p->dct_cw, lds_dct(P)) && pow2_in(p->ring_g, ring_group_max(P)) &&
            (p->spread_bc == bcl || p->spread_bc == bcl / 2) && (p->fft_lr == 3 || p->fft_lr == 4) &&
-           (p->tw_table == 0 || p->tw_table == 1) && (p->spread_staged == 0 || p->spread_staged == 1) &&
+           (p->tw_table == 0 || p->tw_table == 1) &&
+           (p->spread_staged == 0 || p->spread_staged == 1 || (p->spread_staged == 2 && p->bin_ok)) &&
            (p->dct_wave_on == 0 || p->dct_wave_on == 1) && (p->wave_fft_on == 0 || p->wave_fft_on == 1);
 }
 
@@ -3394,7 +3621,7 @@ int tune_search(pat_plan_s* p, const Dev<T>& d)
                                    {&p->dct_cw, dw},
                                    {&p->ring_g, rg},
                                    {&p->spread_bc, {bcl, bcl / 2}},
-                                   {&p->spread_staged, {1, 0}},
+                                   {&p->spread_staged, p->bin_ok ? std::vector<int>{2, 1, 0} : std::vector<int>{1, 0}},
                                    {&p->dct_wave_on, {1, 0}},
                                    {&p->wave_fft_on, {1, 0}}};
     double best = 0;

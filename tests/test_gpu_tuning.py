@@ -55,12 +55,15 @@ def test_every_launch_shape_meets_parity(tmp_path, dt):
     pat.Plan(geom, tdt, max_batch=B, tuning_cache=path)
     key = open(path).read().splitlines()[0].split(" | ")[0]
     bcl = base.info["tune_spread_images"]
-    # (radix, cols, dct cols, ring images, spread images, twiddle table, spread staging,
-    #  wave cosine transform, wave FFT kernels)
+    # (radix, cols, dct cols, ring images, spread images, twiddle table, spread form
+    #  (0 unstaged, 1 staged tiles, 2 binned), wave cosine transform, wave FFT kernels)
     shapes = [(3, 1, 1, 1, bcl // 2, 1, 0, 0, 0), (4, 1, base.info["tune_dct_cols_per_block"], 2, bcl, 0, 1, 0, 0),
               (3, base.info["tune_cols_per_block"], 1, base.info["tune_ring_images"], bcl // 2, 0, 1, 0, 0),
               (4, base.info["tune_cols_per_block"], base.info["tune_dct_cols_per_block"], 1, bcl, 1, 0, 0, 0),
               (3, 1, 1, 1, bcl, 0, 1, 1, 1), (4, 1, 1, 2, bcl // 2, 0, 0, 1, 0), (3, 1, 1, 1, bcl // 2, 0, 1, 0, 1)]
+    if dt == "f32":
+        # the binned spread (FP32 only), both image groups
+        shapes += [(3, 1, 1, 1, bcl, 0, 2, 1, 1), (4, base.info["tune_cols_per_block"], 1, 2, bcl // 2, 1, 2, 0, 0)]
     f = torch.tensor(f_np, dtype=tdt, device="cuda")
     g = torch.tensor(g_np, dtype=tdt, device="cuda")
     for lr, cw, dw, rg, sb, tt, ss, dwv, wf in shapes:
