@@ -117,7 +117,7 @@ def measured_traffic(kernel: str, B: int, shapes: dict = None):
 def _stage_of(kernel: str, prev: str):
     """Stage of a pair kernel from its (demangled) name; the cosine transform
     serves both directions and is told apart by the stage launched before it."""
-    name = kernel.split("(")[0]
+    name = kernel.replace("(anonymous namespace)::", "").split("(")[0]
     for key, stage in (("rows_fwd", "rows_fwd"), ("cols_fwd", "cols_fwd"), ("gather_bins", "gather_fwd"),
                        ("ring_fwd", "ring_fwd"), ("lowk_fwd", "lowk_fwd"), ("synth_fwd", "synth_fwd"),
                        ("synth_adj", "synth_adj"), ("lowk_adj", "lowk_adj"), ("ring_adj", "ring_adj"),
@@ -160,7 +160,7 @@ def traffic_summary(prefix: str, bench_json: str) -> dict:
             if st is None:
                 continue
             prev = st
-            per.setdefault(st, ([], kern.split("(")[0]))[0].append(val)
+            per.setdefault(st, ([], kern.replace("(anonymous namespace)::", "").split("(")[0]))[0].append(val)
         for st, (vals, kern) in per.items():
             d = res["kernels"].setdefault(st, {})
             d[key] = statistics.median(vals)

@@ -118,8 +118,9 @@ typedef struct {
                                      0: derive them from four table entries         */
     int tune_spread_staged;       /* spread form: 2 (FP32 only) samples sorted by
                                      the cell of their first tap, each lane walking
-                                     its own runs; 1 tiles staging samples through
-                                     LDS; 0 tiles reading them with scalar loads    */
+                                     its own runs, with the binned gather in the
+                                     forward; 1 tiles staging samples through LDS;
+                                     0 tiles reading them with scalar loads         */
     int tune_dct_wave;            /* 1: the FP32 cosine transform runs one wave per
                                      column group with compile-time lengths         */
     int tune_wave_fft;            /* 1: the FP32 row / column / angular FFT kernels
@@ -226,10 +227,11 @@ int pat_filter_apply(pat_filter f, int adjoint, int B, const void* in, long in_s
                      void* stream);
 
 /* ---- Groups of plans (batching of uneven image sizes) --------------------
- * A group runs the forward (or adjoint) chains of up to 6 plans of the same
+ * A group runs the forward (or adjoint) chains of up to 5 plans of the same
  * precision together: each stage is ONE kernel launch whose blocks cover
- * every plan's grid (13 launches per A + A* pair for the whole group instead
- * of 13 per plan), with results identical to per-plan calls.  The group
+ * every plan's grid (13 launches per A + A* pair for the whole group, 14
+ * with binned FP32 plans, instead of that many per plan), with results
+ * identical to per-plan calls.  The group
  * keeps pointers to the plans (they must outlive it; each plan at most once)
  * and uses their launch shapes, except that the spread takes its widest image
  * group.  Per plan i: batch[i] images (1..max_batch),
@@ -315,6 +317,30 @@ int pat_cp_dual_tv(pat_plan p, int B, void* pgrad, const void* fbar, double sigm
  * fbar = f_new + theta (f_new - f), f = f_new. */
 int pat_cp_primal(pat_plan p, int B, void* f, void* fbar, const void* Astar_q, const void* pgrad, double tau,
                   double theta, const void* support, void* stream);
+
+/* The operators with an update step fused into their last launch (the
+ * synthesis of A, the row transforms of A*): one launch chain per iteration
+ * half instead of the chain plus a separate pass over the traces or images.
+ * Contiguous batches (B <= max_batch, images n*n apart, traces nt*m apart),
+ * `workspace` as for pat_forward_batched; the arithmetic of the update equals
+ * that of the separate kernels above. */
+
+/* r = A f - g (the NNLS residual); r may be g. */
+int pat_forward_residual(pat_plan p, int B, const void* f, const void* g, void* r, void* workspace, void* stream);
+
+/* q = (q + sigma (A fbar - g)) / (1 + sigma) (eqn:PDHG-dual, data part); sigma > 0. */
+int pat_forward_cp_dual(pat_plan p, int B, const void* fbar, const void* g, void* q, double sigma, void* workspace,
+                        void* stream);
+
+/* f = support * max(0, f - tau A* r) (eq:NNLS-projstep with the gradient A* r). */
+int pat_adjoint_nnls(pat_plan p, int B, const void* r, void* f, double tau, const void* support, void* workspace,
+                     void* stream);
+
+/* f_new = support * max(0, f - tau (A* q - div_h p)), fbar = f_new + theta (f_new - f),
+ * f = f_new (eqn:PDHG-primal, eqn:PDHG-relaxation as pat_cp_primal, with A* q
+ * computed in the same chain); pgrad as in pat_cp_dual_tv. */
+int pat_adjoint_cp_primal(pat_plan p, int B, const void* q, const void* pgrad, void* f, void* fbar, double tau,
+                          double theta, const void* support, void* workspace, void* stream);
 
 /* ---- Learned primal-dual reconstructor (Sec. 4.2.1, eqs. eq:LPD_dual,
  * eq:LPD_primal, loss eq:emp_loss) -----------------------------------------

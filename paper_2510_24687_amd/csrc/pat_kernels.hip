@@ -366,6 +366,24 @@ __device__ __forceinline__ Blk blk_xcd()
 }
 __device__ __forceinline__ Blk blk_plain() { return {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, (int)gridDim.x}; }
 
+// The update step of an iterative reconstruction (Sec. 4.2) fused into the
+// last launch of an operator chain: synth_fwd's trace stores for A, rows_adj's
+// image stores for A*.  Element indices run over a contiguous batch (traces
+// nt * m apart, images n * n apart); the arithmetic is that of the separate
+// update kernels (pat_axpby, pat_cp_dual_data, pat_nnls_update, pat_cp_primal).
+enum { EPI_NONE = 0, EPI_RESIDUAL, EPI_CP_DUAL, EPI_NNLS, EPI_CP_PRIMAL };
+template <typename T>
+struct Epi {
+    int kind;
+    const T* g;           // RESIDUAL, CP_DUAL: the data
+    T sigma, inv1ps;      // CP_DUAL: q <- (q + sigma (A fbar - g)) / (1 + sigma), inv1ps = 1 / (1 + sigma)
+    T* f;                 // NNLS, CP_PRIMAL: the iterate, updated in place
+    T* fbar;              // CP_PRIMAL: the relaxed iterate
+    const T* p;           // CP_PRIMAL: the TV dual, two n x n planes per image
+    const T* support;     // NNLS, CP_PRIMAL: optional mask multiplied into f
+    T tau, theta, inv_h;
+};
+
 // Plan data as seen by the kernels.
 template <typename T>
 struct Dev {
@@ -425,7 +443,52 @@ struct Dev {
     int ubp;                    // 1: rows_adj writes v everywhere plus the partial sums of v over
                                 //    Omega \ Omega_0 (part, one double per block and image)
     double* part;
+    Epi<T> epi;                 // fused update step (kind EPI_NONE outside the fused entry points)
 };
+
+// Trace element out[o] (o: its offset from the output's base, contiguous batch) of A applied to the iterate.
+template <typename T>
+__device__ __forceinline__ void put_trace(const Dev<T>& d, T* out, size_t o, T v)
+{
+    const Epi<T>& e = d.epi;
+    if (e.kind == EPI_RESIDUAL) {
+        out[o] = v - e.g[o];
+    } else if (e.kind == EPI_CP_DUAL) {
+        out[o] = (out[o] + e.sigma * (v - e.g[o])) * e.inv1ps;  // out is the dual variable q
+    } else {
+        out[o] = v;
+    }
+}
+
+// Image element (image b, row r, column c) of A* applied to the traces; out:
+// the image output of a plain adjoint call.
+template <typename T>
+__device__ __forceinline__ void put_image(const Dev<T>& d, T* out, int b, int r, int c, T a)
+{
+    const Epi<T>& e = d.epi;
+    const int n = d.n;
+    const long per = (long)n * n;
+    const long k = (long)r * n + c, i = (long)b * per + k;
+    if (e.kind == EPI_NNLS) {
+        T v = e.f[i] - e.tau * a;
+        v = v > T(0) ? v : T(0);
+        e.f[i] = e.support ? v * e.support[i] : v;
+    } else if (e.kind == EPI_CP_PRIMAL) {
+        const T* px = e.p + (long)b * 2 * per;
+        const T* py = px + per;
+        T dx = (c < n - 1 ? px[k] : T(0)) - (c > 0 ? px[k - 1] : T(0));
+        T dy = (r < n - 1 ? py[k] : T(0)) - (r > 0 ? py[k - n] : T(0));
+        const T div = (dx + dy) * e.inv_h;
+        const T f_old = e.f[i];
+        T v = f_old - e.tau * (a - div);
+        v = v > T(0) ? v : T(0);
+        if (e.support) v *= e.support[i];
+        e.f[i] = v;
+        e.fbar[i] = v + e.theta * (v - f_old);
+    } else {
+        out[k] = a;
+    }
+}
 
 template <typename T>
 __device__ __forceinline__ bool in_mask(const Dev<T>& d, int p, int q)
@@ -626,12 +689,13 @@ __device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<
     const int N = d.ringN[l], logN = d.ringLog[l], Kl = d.ringK[l];
     const int mask = d.Ng - 1;
     if (Pin) {
-        // samples gathered by gather_bins: Pin[(ringOff[l] + si) * B + b], phase applied
-        const cx<T>* src = Pin + (size_t)d.ringOff[l] * B + b0;
+        // samples gathered by gather_bins, phase applied, grouped as this
+        // kernel reads them: image group grp holds npts x nb values, sample-major
+        const cx<T>* src = Pin + (size_t)b0 * d.npts + (size_t)d.ringOff[l] * nb;
         for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
             const int s = si - N / 4;
             for (int i = 0; i < nb; ++i) {
-                const cx<T> v = src[(size_t)si * B + i];
+                const cx<T> v = src[(size_t)si * nb + i];
                 cx<T>* bi = buf + i * N;
                 bi[s < 0 ? s + N : s] = v;
                 bi[s + N / 2] = conjg(v);
@@ -690,8 +754,10 @@ __global__ __launch_bounds__(NT) void ring_fwd(Dev<T> d, const cx<T>* E, const c
 // in LDS with coalesced 16-byte loads, and each thread then interpolates
 // whole samples from LDS: the taps, weights and phase of point_taps and the
 // summation order of ring_fwd (row sums over x, then over y), so the values
-// equal those of ring_fwd's own gather.  Writes Pout[p * B + b], p the
-// sample's ring-order index (BC contiguous values per sample).
+// equal those of ring_fwd's own gather.  Output in the image groups of
+// ring_fwd (G images per block): image b of group c = b / G (nc images) goes
+// to Pout[c G npts + p nc + b - c G], p the sample's ring-order index, so
+// that ring_fwd reads contiguous runs.
 // ---------------------------------------------------------------------------
 constexpr int GB_TILE = 16;
 constexpr int GB_BC = 8;  // images per block (35 KB of LDS: 4 blocks per CU)
@@ -703,7 +769,7 @@ __host__ __device__ constexpr size_t gather_bins_lds(int bc)
 
 template <int BC>
 __device__ __forceinline__ void gather_bins_body(const Dev<float>& d, Blk bk, const cx<float>* E, cx<float>* Pout, int B,
-                                                 size_t ws_img)
+                                                 int G, size_t ws_img)
 {
     constexpr int W = 6, TS = GB_TILE, NC = TS + W - 1, CR = gather_bins_row(BC), TPS = BC / 2;
     static_assert(TS <= 32 && CR % 2 == 0, "tile and LDS layout");
@@ -763,7 +829,7 @@ __device__ __forceinline__ void gather_bins_body(const Dev<float>& d, Blk bk, co
         for (int j = 0; j < W; ++j) wx[j] = es_w(pq.x - float(gx0 + j), tw_, d.beta, d.beta_l2e);
         const cx<float> ph = point_phase(d, pq.x, pq.y);
         const int lx0 = gx0 + d.hw - ex0, ly0 = (gy0 - ty0) & mask;  // both in [0, TS)
-        cx<float>* dst = Pout + (size_t)d.binRing[g] * B + b0;
+        const size_t pr = (size_t)d.binRing[g];
         const float4* base = s_cell + (ly0 * NC + lx0) * (CR / 2);
         // four images at a time (two float4 per cell) and one stencil row at a
         // time (its y-weight evaluated there), so that the reads in flight fit
@@ -800,8 +866,14 @@ __device__ __forceinline__ void gather_bins_body(const Dev<float>& d, Blk bk, co
                 const int k = 2 * (mc + h);
                 const cx<float> v0 = cmul(cx<float>{acc[h].x, acc[h].y}, ph);
                 const cx<float> v1 = cmul(cx<float>{acc[h].z, acc[h].w}, ph);
-                if (k < nb) dst[k] = v0;
-                if (k + 1 < nb) dst[k + 1] = v1;
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int bi = b0 + k + u;
+                    if (k + u < nb) {
+                        const int c = bi / G, nc = min(G, B - c * G);
+                        Pout[(size_t)c * G * d.npts + pr * nc + (bi - c * G)] = u ? v1 : v0;
+                    }
+                }
             }
         }
     }
@@ -809,9 +881,10 @@ __device__ __forceinline__ void gather_bins_body(const Dev<float>& d, Blk bk, co
 
 // at least 4 waves per SIMD: caps the registers the unrolled tap reads may take
 template <int BC>
-__global__ __launch_bounds__(NT, 4) void gather_bins(Dev<float> d, const cx<float>* E, cx<float>* Pout, int B, size_t ws_img)
+__global__ __launch_bounds__(NT, 4) void gather_bins(Dev<float> d, const cx<float>* E, cx<float>* Pout, int B, int G,
+                                                     size_t ws_img)
 {
-    gather_bins_body<BC>(d, blk_xcd(), E, Pout, B, ws_img);
+    gather_bins_body<BC>(d, blk_xcd(), E, Pout, B, G, ws_img);
 }
 
 // Sum over aligned groups of W consecutive lanes (W a power of two <= 64),
@@ -1541,8 +1614,8 @@ __device__ __forceinline__ void rows_adj_w_body(const Dev<float>& d, Blk bk, con
     const float s2 = has2 ? d.Dq[p2] * d.pre_scale * d.adj_scale : 0.f;
     for (int q = lane; q < n; q += 64) {
         const cx<float> v = ld_lds(buf + dw_phys((q - n / 2 + Ng) & (Ng - 1)));
-        fb[(size_t)p1 * n + q] = in_mask(d, p1, q) ? v.x * d.Dq[q] * s1 : 0.f;
-        if (has2) fb[(size_t)p2 * n + q] = in_mask(d, p2, q) ? v.y * d.Dq[q] * s2 : 0.f;
+        put_image(d, fb, b, p1, q, in_mask(d, p1, q) ? v.x * d.Dq[q] * s1 : 0.f);
+        if (has2) put_image(d, fb, b, p2, q, in_mask(d, p2, q) ? v.y * d.Dq[q] * s2 : 0.f);
     }
 }
 
@@ -1637,7 +1710,6 @@ __device__ __forceinline__ void synth_fwd_w_body(const Dev<float>& d, Blk bk, co
     if (j1 >= d.nt) return;
     const bool has2 = j2 < d.nt;
     const cx<float>* Gb = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(G) + (size_t)b * ws_img);
-    float* gb = g + (size_t)b * gstride;
     const cx<float>* G1 = Gb + (size_t)j1 * d.Kp;
     const cx<float>* G2 = Gb + (size_t)j2 * d.Kp;
     auto fold = [&](const cx<float>* row, int r) -> cx<float> {
@@ -1659,8 +1731,8 @@ __device__ __forceinline__ void synth_fwd_w_body(const Dev<float>& d, Blk bk, co
     wf_fft<LOGM, true>(buf, (const PAT_GLOBAL cx<float>*)d.tw, d.logNmax, lane);
     for (int i = lane; i < d.m; i += 64) {
         const cx<float> v = ld_lds(buf + dw_phys(i));
-        gb[(size_t)j1 * d.m + i] = v.x;
-        if (has2) gb[(size_t)j2 * d.m + i] = v.y;
+        put_trace(d, g, (size_t)b * gstride + (size_t)j1 * d.m + i, v.x);
+        if (has2) put_trace(d, g, (size_t)b * gstride + (size_t)j2 * d.m + i, v.y);
     }
 }
 
@@ -1846,7 +1918,6 @@ __device__ __forceinline__ void synth_fwd_body(const Dev<T>& d, Blk bk, const cx
     const int j1 = 2 * bx_, j2 = j1 + 1;
     const int mf = d.mf;
     const cx<T>* Gb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(G) + (size_t)b * ws_img);
-    T* gb = g + (size_t)b * gstride;
     const bool has2 = j2 < d.nt;
     for (int r = threadIdx.x; r < mf; r += blockDim.x) {
         cx<T> z1 = {T(0), T(0)}, z2 = {T(0), T(0)};
@@ -1873,8 +1944,8 @@ __device__ __forceinline__ void synth_fwd_body(const Dev<T>& d, Blk bk, const cx
     if (d.mf3) lds_fft3(Z1, d.logmf, 1, 0, d.tw, d.logNmax, d.twm, true, d.fft_lr, d.tw_table);
     else lds_fft(Z1, d.logmf, 1, 0, d.tw, d.logNmax, true, d.fft_lr, d.tw_table);
     for (int i = threadIdx.x; i < d.m; i += blockDim.x) {
-        gb[(size_t)j1 * d.m + i] = Z1[i].x;
-        if (has2) gb[(size_t)j2 * d.m + i] = Z1[i].y;
+        put_trace(d, g, (size_t)b * gstride + (size_t)j1 * d.m + i, Z1[i].x);
+        if (has2) put_trace(d, g, (size_t)b * gstride + (size_t)j2 * d.m + i, Z1[i].y);
     }
 }
 
@@ -1957,7 +2028,8 @@ __global__ __launch_bounds__(NT) void lowk_adj(Dev<T> d, const cx<T>* G, cx<T>* 
 }
 
 // Samples are written image-minor, Pol[(ringOff[l] + si) * B + b], already
-// multiplied by the conjugate point phase, for the batched spreads below.
+// multiplied by the conjugate point phase, for the batched spreads below
+// (whole rows of B values per sample: the spreads' staging reads them whole).
 template <typename T, int WMAX>
 __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<T>* V, const cx<T>* Ulow, cx<T>* Pol, int B,
                                               int G, size_t ws_img)
@@ -1999,11 +2071,22 @@ __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<
     }
 }
 
+// The image groups of one ring write disjoint parts of the same Pol rows; with
+// a ring count that is a multiple of the XCD count, all groups of ring l run
+// back to back on XCD l mod 8, so those partial rows meet in one L2 before
+// they are written back (rings stay spread round-robin over the XCDs).
 template <typename T, int WMAX>
 __global__ __launch_bounds__(NT) void ring_adj(Dev<T> d, const cx<T>* V, const cx<T>* Ulow, cx<T>* Pol, int B, int G,
                                                size_t ws_img)
 {
-    ring_adj_body<T, WMAX>(d, blk_plain(), V, Ulow, Pol, B, G, ws_img);
+    Blk bk = blk_plain();
+    if (gridDim.y % NUM_XCD == 0) {
+        const int lin = blockIdx.x + gridDim.x * blockIdx.y;
+        const int xcd = lin % NUM_XCD, slot = lin / NUM_XCD, ng = gridDim.x;
+        bk.x = slot % ng;
+        bk.y = (slot / ng) * NUM_XCD + xcd;
+    }
+    ring_adj_body<T, WMAX>(d, bk, V, Ulow, Pol, B, G, ws_img);
 }
 
 // Transpose of the gather.  Each wave owns an 8 x 8 tile of cells of the
@@ -2350,6 +2433,8 @@ __device__ __forceinline__ void spread_bins_body(const Dev<float>& d, Blk bk, co
 }
 
 // Heaviest tiles first, as spread_tiles: block rows 0, last, 1, last - 1, ...
+// in hardware order (contiguous bands of tile rows per XCD, for L2 reuse of
+// the shared bin rows, measured slower: the heavy rows then start on two XCDs)
 template <int BC>
 __global__ __launch_bounds__(NT) void spread_bins(Dev<float> d, const cx<float>* Pol, int B, cx<float>* E, size_t ws_img)
 {
@@ -2448,8 +2533,8 @@ __device__ __forceinline__ void rows_adj_body(const Dev<T>& d, Blk bk, const cx<
     if (!d.ubp) {
         for (int q = threadIdx.x; q < n; q += blockDim.x) {
             cx<T> v = buf[(q - n / 2 + Ng) & (Ng - 1)];
-            fb[(size_t)p1 * n + q] = in_mask(d, p1, q) ? v.x * d.Dq[q] * s1 : T(0);
-            if (has2) fb[(size_t)p2 * n + q] = in_mask(d, p2, q) ? v.y * d.Dq[q] * s2 : T(0);
+            put_image(d, fb, b, p1, q, in_mask(d, p1, q) ? v.x * d.Dq[q] * s1 : T(0));
+            if (has2) put_image(d, fb, b, p2, q, in_mask(d, p2, q) ? v.y * d.Dq[q] * s2 : T(0));
         }
         return;
     }
@@ -2925,6 +3010,7 @@ int upload(pat_plan_s* p, Dev<T>& d)
     d.a = P.g.a; d.h = P.h;
     d.R2 = P.g.R * P.g.R;
     d.sine = 0; d.ubp = 0; d.part = nullptr;
+    d.epi = Epi<T>{};
     // pixel centres in Omega \ Omega_0, with the kernels' own test
     long cnt = 0;
     if (d.mask_r2 > 0.0)
@@ -3016,19 +3102,19 @@ int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g
     if ((rc = check_launch("cols_fwd"))) return rc;
     {
         const cx<T>* Pin = nullptr;
+        const int G = std::max(1, std::min(p->ring_g, B));
         if constexpr (sizeof(T) == 4) {
             if (d.binned) {
                 // the batch's sample array (the adjoint's Pol) holds the gathered samples
                 StageTimer tg(p, st, PAT_STAGE_GATHER_FWD);
                 cx<T>* Pg = reinterpret_cast<cx<T>*>(ws + (size_t)B * p->ws_stride);
                 const dim3 grid((d.Ew + GB_TILE - 1) / GB_TILE, d.Ng / GB_TILE, (B + GB_BC - 1) / GB_BC);
-                gather_bins<GB_BC><<<grid, NT, gather_bins_lds(GB_BC), st>>>(d, E, Pg, B, wi);
+                gather_bins<GB_BC><<<grid, NT, gather_bins_lds(GB_BC), st>>>(d, E, Pg, B, G, wi);
                 Pin = Pg;
             }
             if ((rc = check_launch("gather_bins"))) return rc;
         }
         StageTimer tm(p, st, 2);
-        const int G = std::max(1, std::min(p->ring_g, B));
         ring_fwd<T, WMAX><<<dim3(d.L, (B + G - 1) / G), NT, cs * G * p->H.P.max_ring, st>>>(d, E, Pin, V, U, wi, B, G);
     }
     if ((rc = check_launch("ring_fwd"))) return rc;
@@ -3197,7 +3283,7 @@ int run_inverse(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
 // of the XCD count), rebuilds its stage coordinates and runs the same kernel
 // body as the single-plan launch, so results are identical to per-plan calls.
 // ---------------------------------------------------------------------------
-constexpr int GROUP_MAX = 6;
+constexpr int GROUP_MAX = 5;  // plans per group: their Dev copies fill the 4 KB of kernel arguments
 
 template <typename T>
 struct GroupPlan {
@@ -3301,7 +3387,7 @@ __global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
     if constexpr (S == PAT_STAGE_ROWS_FWD) rows_fwd_body<T>(q.d, bk, q.fin, q.fs, R, q.wi);
     if constexpr (S == PAT_STAGE_COLS_FWD) cols_fwd_body<T>(q.d, bk, R, E, q.wi);
     if constexpr (S == STAGE_GATHER) {
-        if constexpr (sizeof(T) == 4) gather_bins_body<GB_BC>(q.d, bk, E, Pol, q.B, q.wi);
+        if constexpr (sizeof(T) == 4) gather_bins_body<GB_BC>(q.d, bk, E, Pol, q.B, q.G, q.wi);
     }
     if constexpr (S == PAT_STAGE_RING_FWD) ring_fwd_body<T, WMAX>(q.d, bk, E, q.d.binned ? Pol : nullptr, V, U, q.wi, q.B, q.G);
     if constexpr (S == PAT_STAGE_DCT_FWD) {
@@ -3715,6 +3801,49 @@ int plan_image_size(pat_plan p, int* n, int* nt, int* m, double* h, int* is_f64)
 }
 }  // namespace pat
 
+namespace {
+
+// operators with a fused update step (contiguous batches)
+int fused_args(pat_plan p, int B, const void* a, const void* b, const void* c, const void* ws, const char* who)
+{
+    if (!p || !a || !b || !c || !ws) return fail(PAT_EINVAL, std::string(who) + ": null pointer");
+    if (B < 1 || B > p->max_batch) return fail(PAT_ESMALL, std::string(who) + ": B outside [1, max_batch]");
+    return PAT_OK;
+}
+
+template <typename T, int WMAX>
+int fused_call(pat_plan_s* p, bool adjoint, int B, const void* in, void* out, Epi<T> e, void* ws, void* stream)
+{
+    const pat::Params& P = p->H.P;
+    Dev<T> d = dev_of(p, (T*)nullptr);
+    d.epi = e;
+    const long fs = (long)P.n * P.n, gs = (long)P.nt * P.m;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (adjoint) return run_adjoint<T, WMAX>(p, d, B, (const T*)in, gs, (T*)out, fs, (char*)ws, st);
+    return run_forward<T, WMAX>(p, d, B, (const T*)in, fs, (T*)out, gs, (char*)ws, st);
+}
+
+template <typename T>
+Epi<T> epi_of(int kind, const void* g, double sigma, void* f, void* fbar, const void* pgrad, const void* support,
+                     double tau, double theta, double h)
+{
+    Epi<T> e{};
+    e.kind = kind;
+    e.g = static_cast<const T*>(g);
+    e.sigma = (T)sigma;
+    e.inv1ps = T(1) / (T(1) + e.sigma);
+    e.f = static_cast<T*>(f);
+    e.fbar = static_cast<T*>(fbar);
+    e.p = static_cast<const T*>(pgrad);
+    e.support = static_cast<const T*>(support);
+    e.tau = (T)tau;
+    e.theta = (T)theta;
+    e.inv_h = (T)(1.0 / h);
+    return e;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* pat_status_string(int code)
@@ -3896,6 +4025,51 @@ int pat_adjoint_batched(pat_plan p, int B, const void* g, long g_stride, void* f
     if (P.dt == PAT_F64)
         return run_adjoint<double, 13>(p, p->dd, B, (const double*)g, g_stride, (double*)f, f_stride, (char*)ws, st);
     return run_adjoint<float, 6>(p, p->df, B, (const float*)g, g_stride, (float*)f, f_stride, (char*)ws, st);
+}
+
+int pat_forward_residual(pat_plan p, int B, const void* f, const void* g, void* r, void* ws, void* stream)
+{
+    int rc;
+    if ((rc = fused_args(p, B, f, g, r, ws, "pat_forward_residual"))) return rc;
+    if (p->H.P.dt == PAT_F64)
+        return fused_call<double, 13>(p, false, B, f, r, epi_of<double>(EPI_RESIDUAL, g, 0, 0, 0, 0, 0, 0, 0, 1), ws, stream);
+    return fused_call<float, 6>(p, false, B, f, r, epi_of<float>(EPI_RESIDUAL, g, 0, 0, 0, 0, 0, 0, 0, 1), ws, stream);
+}
+
+int pat_forward_cp_dual(pat_plan p, int B, const void* fbar, const void* g, void* q, double sigma, void* ws, void* stream)
+{
+    int rc;
+    if ((rc = fused_args(p, B, fbar, g, q, ws, "pat_forward_cp_dual"))) return rc;
+    if (!(sigma > 0)) return fail(PAT_EINVAL, "pat_forward_cp_dual: sigma must be positive");
+    if (p->H.P.dt == PAT_F64)
+        return fused_call<double, 13>(p, false, B, fbar, q, epi_of<double>(EPI_CP_DUAL, g, sigma, 0, 0, 0, 0, 0, 0, 1),
+                                      ws, stream);
+    return fused_call<float, 6>(p, false, B, fbar, q, epi_of<float>(EPI_CP_DUAL, g, sigma, 0, 0, 0, 0, 0, 0, 1), ws,
+                                stream);
+}
+
+int pat_adjoint_nnls(pat_plan p, int B, const void* r, void* f, double tau, const void* support, void* ws, void* stream)
+{
+    int rc;
+    if ((rc = fused_args(p, B, r, f, f, ws, "pat_adjoint_nnls"))) return rc;
+    if (p->H.P.dt == PAT_F64)
+        return fused_call<double, 13>(p, true, B, r, f, epi_of<double>(EPI_NNLS, 0, 0, f, 0, 0, support, tau, 0, 1), ws,
+                                      stream);
+    return fused_call<float, 6>(p, true, B, r, f, epi_of<float>(EPI_NNLS, 0, 0, f, 0, 0, support, tau, 0, 1), ws, stream);
+}
+
+int pat_adjoint_cp_primal(pat_plan p, int B, const void* q, const void* pgrad, void* f, void* fbar, double tau,
+                          double theta, const void* support, void* ws, void* stream)
+{
+    int rc;
+    if ((rc = fused_args(p, B, q, pgrad, f, ws, "pat_adjoint_cp_primal"))) return rc;
+    if (!fbar) return fail(PAT_EINVAL, "pat_adjoint_cp_primal: null pointer");
+    const double h = p->H.P.h;
+    if (p->H.P.dt == PAT_F64)
+        return fused_call<double, 13>(p, true, B, q, f,
+                                      epi_of<double>(EPI_CP_PRIMAL, 0, 0, f, fbar, pgrad, support, tau, theta, h), ws, stream);
+    return fused_call<float, 6>(p, true, B, q, f, epi_of<float>(EPI_CP_PRIMAL, 0, 0, f, fbar, pgrad, support, tau, theta, h),
+                                ws, stream);
 }
 
 int pat_inverse_batched(pat_plan p, int B, const void* g, long g_stride, void* f, long f_stride, void* ws,

@@ -45,6 +45,10 @@ def _bind(lib):
     lib.pat_cp_primal.argtypes = [_VP, I, _VP, _VP, _VP, _VP, D, D, _VP, _VP]
     lib.pat_dot_batched.argtypes = [_VP, I, L, L, _VP, _VP, _VP, _VP, _VP]
     lib.pat_dot_batched_noalloc.argtypes = [_VP, I, L, L, _VP, _VP, _VP, _VP]
+    lib.pat_forward_residual.argtypes = [_VP, I, _VP, _VP, _VP, _VP, _VP]
+    lib.pat_forward_cp_dual.argtypes = [_VP, I, _VP, _VP, _VP, D, _VP, _VP]
+    lib.pat_adjoint_nnls.argtypes = [_VP, I, _VP, _VP, D, _VP, _VP, _VP]
+    lib.pat_adjoint_cp_primal.argtypes = [_VP, I, _VP, _VP, _VP, _VP, D, D, _VP, _VP, _VP]
     lib._solver_bound = True
     return lib
 
@@ -84,13 +88,18 @@ class BatchedSolver:
     ``groups`` is a list of (plan, g, support) with g of shape (B, nt, m).
     """
 
-    def __init__(self, groups, method: str = "nnls", lam: float = 1e-3, opnorms=None, grouped: bool = False):
+    def __init__(self, groups, method: str = "nnls", lam: float = 1e-3, opnorms=None, grouped: bool = False,
+                 fused: bool = True):
         """grouped: run the operators of all plans as one grouped launch per
         stage (pat_group_forward / pat_group_adjoint) instead of one launch
-        chain per plan."""
+        chain per plan.  fused (per-plan chains only): the data-term updates
+        run inside the operators' last launches (pat_forward_residual /
+        pat_adjoint_nnls, pat_forward_cp_dual / pat_adjoint_cp_primal)
+        instead of as separate kernels."""
         if method not in ("nnls", "tv"):
             raise ValueError("method must be 'nnls' or 'tv'")
         self.method, self.lam = method, float(lam)
+        self.fused = bool(fused) and not grouped
         self.lib = _bind(load())
         self.groups: List[_Group] = [_Group(p, g, s) for p, g, s in groups]
         self.opgroup = Group([G.plan for G in self.groups]) if grouped else None
@@ -114,6 +123,19 @@ class BatchedSolver:
     def _step_group(self, G: _Group):
         lib, P, st = self.lib, G.plan, _VP(torch.cuda.current_stream().cuda_stream)
         h = P._h
+        if self.fused:
+            ws = _ptr(P.workspace(G.B))
+            if self.method == "nnls":
+                _check(lib.pat_forward_residual(h, G.B, _ptr(G.f), _ptr(G.g), _ptr(G.Af), ws, st), "pat_forward_residual")
+                _check(lib.pat_adjoint_nnls(h, G.B, _ptr(G.Af), _ptr(G.f), G.tau, _ptr(G.support), ws, st),
+                       "pat_adjoint_nnls")
+            else:
+                _check(lib.pat_forward_cp_dual(h, G.B, _ptr(G.fbar), _ptr(G.g), _ptr(G.q), G.sigma, ws, st),
+                       "pat_forward_cp_dual")
+                _check(lib.pat_cp_dual_tv(h, G.B, _ptr(G.p), _ptr(G.fbar), G.sigma_tv, self.lam, st), "pat_cp_dual_tv")
+                _check(lib.pat_adjoint_cp_primal(h, G.B, _ptr(G.q), _ptr(G.p), _ptr(G.f), _ptr(G.fbar), G.tau, 1.0,
+                                                 _ptr(G.support), ws, st), "pat_adjoint_cp_primal")
+            return
         if self.method == "nnls":
             P.forward(G.f, out=G.Af)
             _check(lib.pat_axpby(h, G.Af.numel(), 1.0, _ptr(G.Af), -1.0, _ptr(G.g), _ptr(G.Af), st), "pat_axpby")

@@ -48,6 +48,53 @@ def test_graph_replay_equals_eager_and_objective_decreases(method):
     assert np.all(objs[-1] < 0.5 * objs[0])
 
 
+@pytest.mark.parametrize("method", ["nnls", "tv"])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_fused_updates_equal_separate_kernels(method, dtype):
+    """The operators with the update fused into their last launch
+    (pat_forward_residual + pat_adjoint_nnls, pat_forward_cp_dual +
+    pat_adjoint_cp_primal) against the same iterations with separate update
+    kernels: 8 iterations on two instances with a support mask (n = 48 on the
+    180-degree arc).  Same arithmetic in both, so they agree to rounding of
+    the (possibly differently contracted) update expressions."""
+    geom = P.top_arc(48, 64, 96, 180.0)
+    plan = pat.Plan(geom, dtype, max_batch=2)
+    _, g = data(plan, [3, 4])
+    yy, xx = np.mgrid[0:48, 0:48]
+    supp = ((xx - 23.5) ** 2 + (yy - 23.5) ** 2 <= 22.0 ** 2).astype(np.float64)
+    support = torch.tensor(np.stack([supp, supp]), dtype=dtype, device="cuda")
+    runs = []
+    for fused in (True, False):
+        sol = S.BatchedSolver([(plan, g, support)], method=method, lam=1e-3, opnorms=[plan.opnorm(60)], fused=fused)
+        for _ in range(8):
+            sol.step()
+        torch.cuda.synchronize()
+        G = sol.groups[0]
+        runs.append((G.f.clone(), G.fbar.clone(), G.q.clone()))
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    for a, b in zip(runs[0], runs[1]):
+        scale = float(b.abs().max()) or 1.0
+        assert float((a - b).abs().max()) <= tol * scale
+    assert float(runs[0][0].abs().max()) > 0
+    # the mask is applied: nothing outside the support
+    assert float((runs[0][0] * (1 - support)).abs().max()) == 0.0
+
+
+def test_fused_entry_points_reject_bad_arguments():
+    import ctypes
+    geom = P.top_arc(32, 32, 64, 180.0)
+    plan = pat.Plan(geom, torch.float32, max_batch=2)
+    lib = S._bind(pat.load())
+    f = torch.zeros((3, 32, 32), device="cuda")
+    g = torch.zeros((3, 64, 32), device="cuda")
+    ws = ctypes.c_void_p(plan.workspace(2).data_ptr())
+    p_ = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    assert lib.pat_forward_residual(plan._h, 3, p_(f), p_(g), p_(g), ws, None) != 0       # B > max_batch
+    assert lib.pat_forward_residual(plan._h, 2, p_(f), None, p_(g), ws, None) != 0        # null data
+    assert lib.pat_forward_cp_dual(plan._h, 2, p_(f), p_(g), p_(g), 0.0, ws, None) != 0   # sigma <= 0
+    assert lib.pat_adjoint_cp_primal(plan._h, 2, p_(g), p_(f), p_(f), None, 0.1, 1.0, None, ws, None) != 0
+
+
 def test_fp64_nnls_iterates_match_oracle_driven_nnls():
     """Ten projected-gradient steps with the GPU operators equal the same ten
     steps computed with the CPU oracle's A and A* (same step size)."""

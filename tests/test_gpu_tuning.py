@@ -63,7 +63,8 @@ def test_every_launch_shape_meets_parity(tmp_path, dt):
               (3, 1, 1, 1, bcl, 0, 1, 1, 1), (4, 1, 1, 2, bcl // 2, 0, 0, 1, 0), (3, 1, 1, 1, bcl // 2, 0, 1, 0, 1)]
     if dt == "f32":
         # the binned spread (FP32 only), both image groups
-        shapes += [(3, 1, 1, 1, bcl, 0, 2, 1, 1), (4, base.info["tune_cols_per_block"], 1, 2, bcl // 2, 1, 2, 0, 0)]
+        shapes += [(3, 1, 1, 1, bcl, 0, 2, 1, 1), (4, base.info["tune_cols_per_block"], 1, 2, bcl // 2, 1, 2, 0, 0),
+                   (3, 1, 1, 4, bcl, 0, 2, 1, 1)]
     f = torch.tensor(f_np, dtype=tdt, device="cuda")
     g = torch.tensor(g_np, dtype=tdt, device="cuda")
     for lr, cw, dw, rg, sb, tt, ss, dwv, wf in shapes:
