@@ -114,6 +114,40 @@ def measured_traffic(kernel: str, B: int, shapes: dict = None):
     return (k["fetch_kib"] * z["fetch_scale"] + k["write_kib"] * z["write_scale"]) * 1024.0
 
 
+def launch_mode_rates(plan, f, g, y, fa, steps: int, B: int) -> dict:
+    """The same pairs without the per-stage events of the timed loop, launched
+    eagerly and as one captured HIP graph (forward then adjoint) replayed."""
+    import torch
+    res = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.forward(f, out=g)
+        plan.adjoint(y, out=fa)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res["eager_no_events"] = {"pairs_per_s": B * steps / el, "ms_per_step": el / steps * 1e3}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.forward(f, out=g)
+        plan.adjoint(y, out=fa)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.forward(f, out=g)
+        plan.adjoint(y, out=fa)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res["graph_replay"] = {"pairs_per_s": B * steps / el, "ms_per_step": el / steps * 1e3}
+    return res
+
+
 def _stage_of(kernel: str, prev: str):
     """Stage of a pair kernel from its (demangled) name; the cosine transform
     serves both directions and is told apart by the stage launched before it."""
@@ -173,6 +207,58 @@ def traffic_summary(prefix: str, bench_json: str) -> dict:
         res[key] = (copy / 1024.0) / max(vals)
     res["batch"] = json.load(open(bench_json))["config"]["batch"]
     return res
+
+
+def counter_summary(directory: str) -> str:
+    """Markdown table of rocprofv3 SQ counters (one or more runs under
+    `directory`, all counters of a run in one CSV) for the pair kernels:
+    medians over dispatches per stage, per wave where the counter counts
+    instructions, and as fractions of the waves' resident cycles for the
+    SQ_WAIT / SQ_ACTIVE counters."""
+    import csv
+    import glob
+    import statistics
+    per = {}
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)):
+        disp = {}
+        for r in csv.DictReader(open(path)):
+            d = disp.setdefault(int(r["Dispatch_Id"]), {"kernel": r["Kernel_Name"]})
+            d[r["Counter_Name"]] = float(r["Counter_Value"])
+        prev = None
+        for _, d in sorted(disp.items()):
+            st = _stage_of(d["kernel"], prev)
+            if st is None:
+                continue
+            prev = st
+            per.setdefault(st, []).append(d)
+    cols = []
+    for st in per:
+        for d in per[st]:
+            cols += [k for k in d if k not in ("kernel", "SQ_WAVES") and k not in cols]
+    lines = ["| stage | kernel | waves | " + " | ".join(c.replace("SQ_", "") for c in cols) + " |",
+             "|---" * (3 + len(cols)) + "|"]
+    for st in STAGES:
+        if st not in per:
+            continue
+        ds = per[st]
+        waves = statistics.median([d.get("SQ_WAVES", 0) for d in ds if "SQ_WAVES" in d] or [0])
+        cyc = statistics.median([d["SQ_WAVE_CYCLES"] for d in ds if "SQ_WAVE_CYCLES" in d] or [0])
+        row = []
+        for c in cols:
+            vals = [d[c] for d in ds if c in d]
+            if not vals:
+                row.append("")
+                continue
+            v = statistics.median(vals)
+            if c.startswith("SQ_INSTS") or c == "SQ_WAVE_CYCLES":
+                row.append("%.0f" % (v / max(waves, 1)))
+            elif c.startswith("SQ_WAIT") or c.startswith("SQ_ACTIVE") or c == "SQ_BUSY_CYCLES":
+                row.append("%.3f" % (v / cyc) if cyc else "%.0f" % v)
+            else:
+                row.append("%.4g" % v)
+        kern = ds[0]["kernel"].replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+        lines.append("| %s | `%s` | %.0f | %s |" % (st, kern, waves, " | ".join(row)))
+    return "\n".join(lines)
 
 
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
@@ -411,7 +497,7 @@ def tv_sweep(plan, test, t_lpd, tv_iters=200, lams=TV_LAMBDAS):
         out_tv["%g" % lam_] = {"psnr_200": final, "best_psnr": max(traj), "seconds_per_iteration": per_it,
                               "time_to_own_200_psnr_s": (first + 1) * per_it,
                               "psnr_at_lpd_time": traj[min(max(lpd_time_its, 1), tv_iters) - 1]}
-        print(json.dumps({"lpd_progress": "tv", "lam": lam_, "psnr": final}), flush=True)
+        print(json.dumps({"lpd_progress": "tv", "lam": lam_, "psnr": final}), file=sys.stderr, flush=True)
     per_it, traj = solve("nnls", 0.0)
     best = max(out_tv, key=lambda k: out_tv[k]["psnr_200"])
     inner = best not in ("%g" % lams[0], "%g" % lams[-1])
@@ -457,7 +543,7 @@ def lpd_eval(path: str = LPD_WEIGHTS, n_test: int = 64, batch: int = 8, tv_iters
     torch.cuda.synchronize()
     t_lpd = e0.elapsed_time(e1) / 1e3
     psnr_lpd = float(np.mean(vals))
-    res = {"workload": "n=256, m=256 on the top 180-degree arc, nt=512, 2% noise; 64 held-out phantoms "
+    res = {"workload": "n=256, m=256 on the top 180-degree arc, nt=512, 2%% noise; 64 held-out phantoms "
                        "(seeds 1e6..), LPD batch %d, K=%d, %s networks" % (batch, iters, arch),
            "weights": os.path.relpath(path, ROOT), "training_steps": steps,
            "psnr_lpd": psnr_lpd, "t_lpd_s": t_lpd, "inference_images_per_s": n_test / t_lpd}
@@ -602,7 +688,12 @@ def main():
                          "the run that the kernel profiles are taken from")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("PMC_DIR", "BENCH_JSON"),
                     help="write profiles/traffic_n512.json from rocprofv3 FETCH_SIZE / WRITE_SIZE runs")
+    ap.add_argument("--counter-summary", metavar="PMC_DIR",
+                    help="print a markdown table of the SQ counters of rocprofv3 runs under PMC_DIR")
     args = ap.parse_args()
+    if args.counter_summary:
+        print(counter_summary(args.counter_summary))
+        return
     if args.traffic_summary:
         res = traffic_summary(*args.traffic_summary)
         with open(os.path.join(ROOT, "profiles", "traffic_n512.json"), "w") as fp:
@@ -704,7 +795,27 @@ def main():
         acc["adjoint_identity_max_rel"] = ident
 
     lib = pat.load()
+    import ctypes
+    lib.pat_timing_start_stages.argtypes = [ctypes.c_void_p, ctypes.c_uint]
+
+    def stage_times():
+        ms = (ctypes.c_double * NSTAGES)()
+        cnt = (ctypes.c_int * NSTAGES)()
+        if lib.pat_timing_stop(plan._h, ms, cnt, NSTAGES) != 0:
+            raise RuntimeError("pat_timing_stop failed")
+        return {STAGES[i]: ms[i] / cnt[i] for i in range(NSTAGES) if cnt[i] > 0}
+
+    # per-stage means: K steps with HIP events around every launch
     lib.pat_timing_start(plan._h)
+    for _ in range(args.steps):
+        plan.forward(f, out=g)
+        plan.adjoint(y, out=fa)
+    stage_ms = stage_times()
+    bytes_ = stage_bytes(info, B, geom)
+    dom = max(stage_ms, key=stage_ms.get)
+    # the timed region: K steps, events only around the dominant kernel's
+    # launches (events around all 14 would add ~0.1 ms per pair)
+    lib.pat_timing_start_stages(plan._h, 1 << STAGES.index(dom))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -712,16 +823,9 @@ def main():
         plan.adjoint(y, out=fa)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    import ctypes
-    ms = (ctypes.c_double * NSTAGES)()
-    cnt = (ctypes.c_int * NSTAGES)()
-    rc = lib.pat_timing_stop(plan._h, ms, cnt, NSTAGES)
-    if rc != 0:
-        raise RuntimeError("pat_timing_stop failed")
-    stage_ms = {STAGES[i]: ms[i] / cnt[i] for i in range(NSTAGES) if cnt[i] > 0}
-    bytes_ = stage_bytes(info, B, geom)
-    dom = max(stage_ms, key=stage_ms.get)
-    achieved = bytes_[dom] / (stage_ms[dom] * 1e-3) / 1e9
+    dom_ms = stage_times()[dom]
+    launch_modes = launch_mode_rates(plan, f, g, y, fa, args.steps, B)
+    achieved = bytes_[dom] / (dom_ms * 1e-3) / 1e9
     pairs = B * args.steps / elapsed
     step_ms = elapsed / args.steps * 1e3
     total_alg = sum(bytes_.values())
@@ -743,12 +847,13 @@ def main():
                    "batch": B, "n": n, "m": geom["m"], "nt": geom["nt"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, B, shapes),
-                     "alg_bytes_per_launch": bytes_[dom]},
+                     "alg_bytes_per_launch": bytes_[dom], "ms_per_launch": dom_ms},
         "launch_shapes": dict(shapes, tuned=info["tuned"]),
         "stage_ms_per_launch": stage_ms,
         "pair_alg_bytes_per_image": total_alg / B,
         "pair_effective_GBs": total_alg / (step_ms * 1e-3) / 1e9,
         "accuracy_vs_oracle": acc,
+        "launch_modes": launch_modes,
     }
     # accuracy gate: the throughput only counts for results within 1e-4 of the oracle
     gate_ok = acc is not None and acc["forward_rel_l2"] <= ACC_TOL and acc["adjoint_rel_l2"] <= ACC_TOL

@@ -270,6 +270,9 @@ enum {
  * used from several threads at once. */
 int pat_timing_start(pat_plan p);
 int pat_timing_stop(pat_plan p, double* ms, int* launches, int nstages);
+/* As pat_timing_start, with events only around the launches of the stages
+ * whose bit (1u << stage) is set in stage_mask (the others run unrecorded). */
+int pat_timing_start_stages(pat_plan p, unsigned stage_mask);
 
 /* ---- Fused update steps of the iterative reconstructions (Sec. 4.2) ------
  * All operate on device arrays of the plan's precision, asynchronously on

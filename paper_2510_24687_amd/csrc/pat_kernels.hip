@@ -2670,6 +2670,7 @@ struct pat_plan_s {
     double tuned_ms = 0.0;
     // optional per-stage timing with HIP events recorded on the launch stream
     bool timing = false;
+    unsigned timing_mask = ~0u;            // stages whose launches get events
     std::vector<hipEvent_t> ev_pool;       // pairs (start, end)
     std::vector<int> ev_stage;             // stage of each recorded pair
     size_t ev_used = 0;
@@ -3042,9 +3043,11 @@ struct StageTimer {
     pat_plan_s* p;
     hipStream_t st;
     int stage;
-    StageTimer(pat_plan_s* p_, hipStream_t st_, int stage_) : p(p_), st(st_), stage(stage_)
+    bool on;
+    StageTimer(pat_plan_s* p_, hipStream_t st_, int stage_)
+        : p(p_), st(st_), stage(stage_), on(p_->timing && ((p_->timing_mask >> stage_) & 1u))
     {
-        if (!p->timing) return;
+        if (!on) return;
         if (p->ev_used * 2 + 2 > p->ev_pool.size()) {
             hipEvent_t a, b;
             if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { p->timing = false; return; }
@@ -3055,7 +3058,7 @@ struct StageTimer {
     }
     ~StageTimer()
     {
-        if (!p->timing) return;
+        if (!on || !p->timing) return;
         (void)hipEventRecord(p->ev_pool[2 * p->ev_used + 1], st);
         if (p->ev_stage.size() <= p->ev_used) p->ev_stage.resize(p->ev_used + 1);
         p->ev_stage[p->ev_used] = stage;
@@ -4094,8 +4097,14 @@ int pat_inverse(pat_plan p, const void* g, void* f, void* ws, void* stream)
 
 int pat_timing_start(pat_plan p)
 {
+    return pat_timing_start_stages(p, ~0u);
+}
+
+int pat_timing_start_stages(pat_plan p, unsigned stage_mask)
+{
     if (!p) return fail(PAT_EINVAL, "pat_timing_start: NULL plan");
     p->timing = true;
+    p->timing_mask = stage_mask;
     p->ev_used = 0;
     return PAT_OK;
 }

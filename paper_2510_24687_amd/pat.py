@@ -55,7 +55,8 @@ EXPORTED = ["pat_plan_create", "pat_plan_query", "pat_plan_destroy", "pat_plan_g
             "pat_bn_partials", "pat_bn_forward", "pat_bn_backward", "pat_maxpool2", "pat_maxpool2_backward",
             "pat_nhwc_pack", "pat_nhwc_unpack_grad", "pat_head_forward", "pat_head_partials", "pat_head_backward",
             "pat_dot_batched", "pat_dot_batched_noalloc", "pat_forward_residual", "pat_forward_cp_dual",
-            "pat_adjoint_nnls", "pat_adjoint_cp_primal"]
+            "pat_adjoint_nnls", "pat_adjoint_cp_primal", "pat_timing_start", "pat_timing_start_stages",
+            "pat_timing_stop"]
 
 
 class ConvDesc(ctypes.Structure):
