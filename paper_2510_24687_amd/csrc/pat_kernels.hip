@@ -181,9 +181,16 @@ __device__ __forceinline__ void st_lds(PAT_LDS cx<T>* p, cx<T> v) { p->x = v.x; 
 template <typename T>
 __device__ __forceinline__ cx<T> ld_glb(const PAT_GLOBAL cx<T>* p) { return {p->x, p->y}; }
 
+// LDS index of element i of an FFT buffer: with PAD one slot of padding
+// after every 8 entries, so that the strided stores of the first radix-8
+// passes (stride 8 and 64 entries) fall in distinct banks.  Sequence starts
+// and strides are multiples of 8, so phys(a + i) = phys(a) + phys(i).
+template <bool PAD>
+__host__ __device__ constexpr int lds_phys(int i) { return PAD ? i + (i >> 3) : i; }
+
 // A power-of-two pass of a transform of length N = f 2^logN, f = 1 or 3 (f3):
 // the sequences' stride between butterfly inputs is N/R.
-template <typename T, int R>
+template <typename T, int R, bool PAD = false>
 __device__ __noinline__ void stockham_pass(PAT_LDS cx<T>* buf, int logN, int logNs, int nb, int stride,
                                               const PAT_GLOBAL cx<T>* __restrict__ tw, int logNmax, bool inv, bool twtab,
                                               int f3)
@@ -199,9 +206,9 @@ __device__ __noinline__ void stockham_pass(PAT_LDS cx<T>* buf, int logN, int log
         const int it = threadIdx.x + u * NT;
         if (it < total) {
             const int b = f3 ? (it >> lnbf) / 3 : it >> lnbf, t = it - b * nbf;
-            const PAT_LDS cx<T>* s = buf + b * stride;
+            const PAT_LDS cx<T>* s = buf + lds_phys<PAD>(b * stride);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[u][r] = ld_lds(s + t + r * nbf);
+            for (int r = 0; r < R; ++r) v[u][r] = ld_lds(s + lds_phys<PAD>(t + r * nbf));
         }
     }
     __syncthreads();
@@ -246,16 +253,16 @@ __device__ __noinline__ void stockham_pass(PAT_LDS cx<T>* buf, int logN, int log
                 }
             }
             dft_reg<T, R>(v[u], inv);
-            PAT_LDS cx<T>* s = buf + b * stride;
+            PAT_LDS cx<T>* s = buf + lds_phys<PAD>(b * stride);
             const int base = ((t >> logNs) << (logNs + LR)) + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) st_lds(s + base + (r << logNs), v[u][r]);
+            for (int r = 0; r < R; ++r) st_lds(s + lds_phys<PAD>(base + (r << logNs)), v[u][r]);
         }
     }
     __syncthreads();
 }
 
-template <typename T>
+template <typename T, bool PAD = false>
 __device__ void lds_fft(cx<T>* buf, int logN, int nb, int stride, const cx<T>* __restrict__ tw, int logNmax,
                         bool inverse, int maxlr, bool twtab, int f3 = 0)
 {
@@ -267,10 +274,10 @@ __device__ void lds_fft(cx<T>* buf, int logN, int nb, int stride, const cx<T>* _
     for (int p = 0; p < P; ++p) {
         const int lr = logN / P + (p < logN % P ? 1 : 0);
         switch (lr) {
-            case 1: stockham_pass<T, 2>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab, f3); break;
-            case 2: stockham_pass<T, 4>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab, f3); break;
-            case 3: stockham_pass<T, 8>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab, f3); break;
-            default: stockham_pass<T, 16>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab, f3); break;
+            case 1: stockham_pass<T, 2, PAD>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab, f3); break;
+            case 2: stockham_pass<T, 4, PAD>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab, f3); break;
+            case 3: stockham_pass<T, 8, PAD>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab, f3); break;
+            default: stockham_pass<T, 16, PAD>(lbuf, logN, logNs, nb, stride, gtw, logNmax, inverse, twtab, f3); break;
         }
         logNs += lr;
     }
@@ -279,7 +286,7 @@ __device__ void lds_fft(cx<T>* buf, int logN, int nb, int stride, const cx<T>* _
 // The last pass of a length N = 3 * 2^logN2 transform (after the power-of-two
 // passes): radix 3 with sub-transform length Ns = 2^logN2, twiddles W_N^{r t}
 // read from twd (the 2N-th roots e^{-2 pi i j/(2N)}: W_N^{r t} = twd[2 r t]).
-template <typename T>
+template <typename T, bool PAD = false>
 __device__ __noinline__ void stockham_pass3(PAT_LDS cx<T>* buf, int logN2, int nb, int stride,
                                                const PAT_GLOBAL cx<T>* __restrict__ twd, bool inv, int tsh)
 {
@@ -293,9 +300,9 @@ __device__ __noinline__ void stockham_pass3(PAT_LDS cx<T>* buf, int logN2, int n
         const int it = threadIdx.x + u * NT;
         if (it < total) {
             const int b = it >> logN2, t = it & (nbf - 1);
-            const PAT_LDS cx<T>* s = buf + b * stride;
+            const PAT_LDS cx<T>* s = buf + lds_phys<PAD>(b * stride);
 #pragma unroll
-            for (int r = 0; r < 3; ++r) v[u][r] = ld_lds(s + t + r * nbf);
+            for (int r = 0; r < 3; ++r) v[u][r] = ld_lds(s + lds_phys<PAD>(t + r * nbf));
         }
     }
     __syncthreads();
@@ -311,10 +318,10 @@ __device__ __noinline__ void stockham_pass3(PAT_LDS cx<T>* buf, int logN2, int n
             const cx<T> m = {a0.x - T(0.5) * sm.x, a0.y - T(0.5) * sm.y};
             // forward: y1 = m - i h3 df, y2 = m + i h3 df (inverse: signs swapped)
             const cx<T> jd = inv ? cx<T>{-h3 * df.y, h3 * df.x} : cx<T>{h3 * df.y, -h3 * df.x};
-            PAT_LDS cx<T>* s = buf + b * stride;
-            st_lds(s + t, a0 + sm);
-            st_lds(s + t + nbf, m + jd);
-            st_lds(s + t + 2 * nbf, m - jd);
+            PAT_LDS cx<T>* s = buf + lds_phys<PAD>(b * stride);
+            st_lds(s + lds_phys<PAD>(t), a0 + sm);
+            st_lds(s + lds_phys<PAD>(t + nbf), m + jd);
+            st_lds(s + lds_phys<PAD>(t + 2 * nbf), m - jd);
         }
     }
     __syncthreads();
@@ -324,12 +331,12 @@ __device__ __noinline__ void stockham_pass3(PAT_LDS cx<T>* buf, int logN2, int n
 // on the 2^logN2 factor, then the radix-3 pass.  The radix-3 pass keeps
 // FFT_REGS / 3 butterflies per thread, so nb * N <= (FFT_REGS / 3) * 3 * NT.
 // twd holds the 2N'-th roots of unity of a length N' = N 2^tsh.
-template <typename T>
+template <typename T, bool PAD = false>
 __device__ void lds_fft3(cx<T>* buf, int logN2, int nb, int stride, const cx<T>* __restrict__ tw, int logNmax,
                          const cx<T>* __restrict__ twd, bool inverse, int maxlr, bool twtab, int tsh = 0)
 {
-    lds_fft(buf, logN2, nb, stride, tw, logNmax, inverse, maxlr, twtab, 1);
-    stockham_pass3((PAT_LDS cx<T>*)buf, logN2, nb, stride, (const PAT_GLOBAL cx<T>*)twd, inverse, tsh);
+    lds_fft<T, PAD>(buf, logN2, nb, stride, tw, logNmax, inverse, maxlr, twtab, 1);
+    stockham_pass3<T, PAD>((PAT_LDS cx<T>*)buf, logN2, nb, stride, (const PAT_GLOBAL cx<T>*)twd, inverse, tsh);
 }
 
 // MI355X dispatches consecutive workgroups of a grid round-robin over its 8
@@ -658,18 +665,24 @@ __global__ __launch_bounds__(NT) void cols_fwd(Dev<T> d, const cx<T>* R, cx<T>* 
 
 // The ring transforms of nb images (ring l: N = 2^logN or 3 * 2^logN points),
 // as many sequences per lds_fft call as its register budget allows.
+// FP32 ring buffers are padded (lds_phys<true>): LDS of ring_lds bytes.
+template <typename T>
+constexpr bool RING_PAD = sizeof(T) == 4;
+
 template <typename T>
 __device__ __forceinline__ void ring_fft(const Dev<T>& d, int l, cx<T>* buf, int N, int logN, int nb, bool inverse)
 {
+    constexpr bool PAD = RING_PAD<T>;
     if (d.ringM3[l]) {
         const int per_call = max(1, min(nb, ((FFT_REGS / 3) * 3 * NT) / N));
         for (int i = 0; i < nb; i += per_call)
-            lds_fft3(buf + i * N, logN, min(per_call, nb - i), N, d.tw, d.logNmax, d.twr, inverse, d.fft_lr,
-                     d.tw_table, d.logNr3 - logN);
+            lds_fft3<T, PAD>(buf + lds_phys<PAD>(i * N), logN, min(per_call, nb - i), N, d.tw, d.logNmax, d.twr,
+                             inverse, d.fft_lr, d.tw_table, d.logNr3 - logN);
     } else {
         const int per_call = max(1, min(nb, FFT_BLOCK_POINTS >> logN));
         for (int i = 0; i < nb; i += per_call)
-            lds_fft(buf + i * N, logN, min(per_call, nb - i), N, d.tw, d.logNmax, inverse, d.fft_lr, d.tw_table);
+            lds_fft<T, PAD>(buf + lds_phys<PAD>(i * N), logN, min(per_call, nb - i), N, d.tw, d.logNmax, inverse,
+                            d.fft_lr, d.tw_table);
     }
 }
 
@@ -696,9 +709,9 @@ __device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<
             const int s = si - N / 4;
             for (int i = 0; i < nb; ++i) {
                 const cx<T> v = src[(size_t)si * nb + i];
-                cx<T>* bi = buf + i * N;
-                bi[s < 0 ? s + N : s] = v;
-                bi[s + N / 2] = conjg(v);
+                const int bo = i * N;
+                buf[lds_phys<RING_PAD<T>>(bo + (s < 0 ? s + N : s))] = v;
+                buf[lds_phys<RING_PAD<T>>(bo + (s + N / 2))] = conjg(v);
             }
         }
     } else
@@ -719,23 +732,23 @@ __device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<
                 acc = acc + racc * tp.wy[jy];
             }
             const cx<T> v = cmul(acc, tp.ph);
-            cx<T>* bi = buf + i * N;
-            bi[s < 0 ? s + N : s] = v;          // s in [-N/4, N/4)
-            bi[s + N / 2] = conjg(v);
+            const int bo = i * N;
+            buf[lds_phys<RING_PAD<T>>(bo + (s < 0 ? s + N : s))] = v;          // s in [-N/4, N/4)
+            buf[lds_phys<RING_PAD<T>>(bo + (s + N / 2))] = conjg(v);
         }
     }
     __syncthreads();
     ring_fft(d, l, buf, N, logN, nb, false);
     const T invN = T(1) / T(N);
     for (int i = 0; i < nb; ++i) {
-        const cx<T>* bi = buf + i * N;
+        const int bo = i * N;
         cx<T>* Vb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(V) + (size_t)(b0 + i) * ws_img);
         cx<T>* Ub = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(Ulow) + (size_t)(b0 + i) * ws_img);
         for (int k = threadIdx.x; k < d.Kp; k += blockDim.x) {
             cx<T> out = {T(0), T(0)};
-            if (k <= Kl) out = mul_ipow(bi[k] * d.Tb[(size_t)l * d.Kp + k], k);
+            if (k <= Kl) out = mul_ipow(buf[lds_phys<RING_PAD<T>>(bo + (k))] * d.Tb[(size_t)l * d.Kp + k], k);
             Vb[(size_t)l * d.Kp + k] = out;
-            if (l < d.lcorr && k <= d.klow) Ub[(size_t)l * (d.klow + 1) + k] = (k <= Kl ? bi[k] : cx<T>{T(0), T(0)}) * invN;
+            if (l < d.lcorr && k <= d.klow) Ub[(size_t)l * (d.klow + 1) + k] = (k <= Kl ? buf[lds_phys<RING_PAD<T>>(bo + (k))] : cx<T>{T(0), T(0)}) * invN;
         }
     }
 }
@@ -2044,14 +2057,14 @@ __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<
     for (int i = 0; i < nb; ++i) {
         const cx<T>* Vb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(V) + (size_t)(b0 + i) * ws_img);
         const cx<T>* Ub = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(Ulow) + (size_t)(b0 + i) * ws_img);
-        cx<T>* bi = buf + i * N;
+        const int bo = i * N;
         for (int k = threadIdx.x; k < N; k += blockDim.x) {
             cx<T> v = {T(0), T(0)};
             if (k <= Kl) {
                 v = mul_ipow(Vb[(size_t)l * d.Kp + k] * d.Tb[(size_t)l * d.Kp + k], (4 - (k & 3)) & 3);
                 if (l < d.lcorr && k <= d.klow) v = v + Ub[(size_t)l * (d.klow + 1) + k] * invN;
             }
-            bi[k] = v;
+            buf[lds_phys<RING_PAD<T>>(bo + (k))] = v;
         }
     }
     __syncthreads();
@@ -2065,8 +2078,10 @@ __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<
         cx<T>* dst = Pol + (size_t)(off + si) * B + b0;
         for (int i = 0; i < nb; ++i) {
             // transpose of the conjugate-symmetric fill, then of the point phase
-            const cx<T>* bi = buf + i * N;
-            dst[i] = cmul(bi[s < 0 ? s + N : s] + conjg(bi[s + N / 2]), ph);
+            const int bo = i * N;
+            const cx<T> a = buf[lds_phys<RING_PAD<T>>(bo + (s < 0 ? s + N : s))];
+            const cx<T> c = buf[lds_phys<RING_PAD<T>>(bo + s + N / 2)];
+            dst[i] = cmul(a + conjg(c), ph);
         }
     }
 }
@@ -2717,11 +2732,17 @@ int lds_cols(const pat::Params& P)
 }
 
 // largest number of images per ring_fwd block that fits 64 KiB of LDS (at most 4)
+// LDS bytes of a ring kernel block with G images (FP32 buffers padded)
+size_t ring_lds(const pat::Params& P, int G)
+{
+    if (P.dt == PAT_F64) return (size_t)16 * G * P.max_ring;
+    return (size_t)8 * lds_phys<true>(G * P.max_ring);
+}
+
 int ring_group_max(const pat::Params& P)
 {
-    size_t cs = (P.dt == PAT_F64) ? 16 : 8;
     int g = 4;
-    while (g > 1 && (size_t)g * P.max_ring * cs > 65536) g >>= 1;
+    while (g > 1 && ring_lds(P, g) > 65536) g >>= 1;
     return g;
 }
 
@@ -3118,7 +3139,7 @@ int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g
             if ((rc = check_launch("gather_bins"))) return rc;
         }
         StageTimer tm(p, st, 2);
-        ring_fwd<T, WMAX><<<dim3(d.L, (B + G - 1) / G), NT, cs * G * p->H.P.max_ring, st>>>(d, E, Pin, V, U, wi, B, G);
+        ring_fwd<T, WMAX><<<dim3(d.L, (B + G - 1) / G), NT, ring_lds(p->H.P, G), st>>>(d, E, Pin, V, U, wi, B, G);
     }
     if ((rc = check_launch("ring_fwd"))) return rc;
     {
@@ -3201,7 +3222,7 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
     {
         StageTimer tm(p, st, 9);
         const int Gr = std::max(1, std::min(p->ring_g, B));
-        ring_adj<T, WMAX><<<dim3((B + Gr - 1) / Gr, d.L), NT, cs * Gr * P.max_ring, st>>>(d, V, U, Pol, B, Gr, wi);
+        ring_adj<T, WMAX><<<dim3((B + Gr - 1) / Gr, d.L), NT, ring_lds(P, Gr), st>>>(d, V, U, Pol, B, Gr, wi);
     }
     if ((rc = check_launch("ring_adj"))) return rc;
     {
@@ -3444,12 +3465,12 @@ size_t stage_lds(const pat_plan_s* p, int S, int G)
         case PAT_STAGE_COLS_ADJ:
             if (p->df.wfRows) return wf_lds(p->df.wfRows);
             return cs * P.Ng * ((S == PAT_STAGE_COLS_FWD || S == PAT_STAGE_COLS_ADJ) ? p->cols_cw : 1);
-        case PAT_STAGE_RING_FWD: return cs * G * P.max_ring;
+        case PAT_STAGE_RING_FWD: return ring_lds(P, G);
         case PAT_STAGE_DCT_FWD:
         case PAT_STAGE_DCT_ADJ: return p->df.dct_wave ? dw_lds(p->df.dct_wave) : dct_lds(P, p->dct_cw);
         case PAT_STAGE_SYNTH_FWD: return p->df.wfSynth ? wf_lds(p->df.wfSynth) : cs * 2 * P.mf;
         case PAT_STAGE_SYNTH_ADJ: return p->df.wfSynth ? wf_lds(p->df.wfSynth) : cs * P.mf;
-        case PAT_STAGE_RING_ADJ: return cs * G * P.max_ring;
+        case PAT_STAGE_RING_ADJ: return ring_lds(P, G);
         case PAT_STAGE_SPREAD_ADJ: {
             const int bc = (P.dt == PAT_F64) ? 8 : 16;  // the grouped launch's image group
             if (P.dt == PAT_F32 && p->spread_staged == 2) return spread_bins_lds(bc);
@@ -3753,7 +3774,7 @@ int autotune(pat_plan_s* p, const char* path)
 int lds_ok(const pat::Params& P, std::string& err)
 {
     size_t cs = (P.dt == PAT_F64) ? 16 : 8;
-    size_t need = std::max({cs * P.Ng, cs * (size_t)P.max_ring, cs * (size_t)P.M, cs * 2 * (size_t)P.mf});
+    size_t need = std::max({cs * P.Ng, ring_lds(P, 1), cs * (size_t)P.M, cs * 2 * (size_t)P.mf});
     int longest = std::max({P.Ng, P.max_ring, P.mf3 ? 0 : P.mf});
     const int mf3_points = (FFT_REGS / 3) * 3 * NT;   // with a radix-3 pass
     if (need > 65536 || longest > FFT_BLOCK_POINTS || P.M > fft_points(P) || (P.mf3 && P.mf > mf3_points)) {
