@@ -844,55 +844,48 @@ __device__ __forceinline__ void gather_bins_body(const Dev<float>& d, Blk bk, co
         const int lx0 = gx0 + d.hw - ex0, ly0 = (gy0 - ty0) & mask;  // both in [0, TS)
         const size_t pr = (size_t)d.binRing[g];
         const float4* base = s_cell + (ly0 * NC + lx0) * (CR / 2);
-        // four images at a time (two float4 per cell) and one stencil row at a
-        // time (its y-weight evaluated there), so that the reads in flight fit
-        // the registers of 4 waves per SIMD
+        // one stencil row at a time (its y-weight evaluated once there), all
+        // BC images of the row's taps in registers
+        float4 acc[TPS];
+#pragma unroll
+        for (int m = 0; m < TPS; ++m) acc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll 1
-        for (int mc = 0; mc < TPS; mc += 2) {
-            float4 acc[2] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
-#pragma unroll 1
-            for (int jy = 0; jy < W; ++jy) {
-                const float wyj = es_w(pq.y - float(gy0 + jy), tw_, d.beta, d.beta_l2e);
-                const float4* rowp = base + jy * NC * (CR / 2) + mc;
-                float4 racc[2] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
+        for (int jy = 0; jy < W; ++jy) {
+            const float wyj = es_w(pq.y - float(gy0 + jy), tw_, d.beta, d.beta_l2e);
+            const float4* rowp = base + jy * NC * (CR / 2);
+#pragma unroll
+            for (int m = 0; m < TPS; ++m) {
+                float4 racc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                 for (int jx = 0; jx < W; ++jx) {
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const float4 c = rowp[jx * (CR / 2) + h];
-                        racc[h].x += c.x * wx[jx];
-                        racc[h].y += c.y * wx[jx];
-                        racc[h].z += c.z * wx[jx];
-                        racc[h].w += c.w * wx[jx];
-                    }
+                    const float4 c = rowp[jx * (CR / 2) + m];
+                    racc.x += c.x * wx[jx];
+                    racc.y += c.y * wx[jx];
+                    racc.z += c.z * wx[jx];
+                    racc.w += c.w * wx[jx];
                 }
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    acc[h].x += racc[h].x * wyj;
-                    acc[h].y += racc[h].y * wyj;
-                    acc[h].z += racc[h].z * wyj;
-                    acc[h].w += racc[h].w * wyj;
-                }
+                acc[m].x += racc.x * wyj;
+                acc[m].y += racc.y * wyj;
+                acc[m].z += racc.z * wyj;
+                acc[m].w += racc.w * wyj;
             }
+        }
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int k = 2 * (mc + h);
-                const cx<float> v0 = cmul(cx<float>{acc[h].x, acc[h].y}, ph);
-                const cx<float> v1 = cmul(cx<float>{acc[h].z, acc[h].w}, ph);
+        for (int m = 0; m < TPS; ++m) {
+            const cx<float> v0 = cmul(cx<float>{acc[m].x, acc[m].y}, ph);
+            const cx<float> v1 = cmul(cx<float>{acc[m].z, acc[m].w}, ph);
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int bi = b0 + k + u;
-                    if (k + u < nb) {
-                        const int c = bi / G, nc = min(G, B - c * G);
-                        Pout[(size_t)c * G * d.npts + pr * nc + (bi - c * G)] = u ? v1 : v0;
-                    }
+            for (int u = 0; u < 2; ++u) {
+                const int k = 2 * m + u, bi = b0 + k;
+                if (k < nb) {
+                    const int c = bi / G, nc = min(G, B - c * G);
+                    Pout[(size_t)c * G * d.npts + pr * nc + (bi - c * G)] = u ? v1 : v0;
                 }
             }
         }
     }
 }
 
-// at least 4 waves per SIMD: caps the registers the unrolled tap reads may take
 template <int BC>
 __global__ __launch_bounds__(NT, 4) void gather_bins(Dev<float> d, const cx<float>* E, cx<float>* Pout, int B, int G,
                                                      size_t ws_img)
