@@ -2440,15 +2440,57 @@ __device__ __forceinline__ void spread_bins_body(const Dev<float>& d, Blk bk, co
     }
 }
 
-// Heaviest tiles first, as spread_tiles: block rows 0, last, 1, last - 1, ...
-// in hardware order (contiguous bands of tile rows per XCD, for L2 reuse of
-// the shared bin rows, measured slower: the heavy rows then start on two XCDs)
+// Tile order.  Rows of tiles are taken heaviest first, as in spread_tiles
+// (rows 0, last, 1, last - 1, ...: the densest rings lie next to y = 0), and
+// inside a row every XCD takes its own chunk of nx / NUM_XCD adjacent tiles
+// (the leftover tiles of the rows go round-robin to the XCDs), so that the
+// bin rows and columns that neighbouring tiles both stage, in this row and
+// in the rows of the same half that follow soon after, are read through one
+// L2.  The rows of the lower half (odd order index) give chunk c to XCD
+// c + NUM_XCD / 2, so the heavy tiles at x = 0 of the two rows next to y = 0
+// run on different XCDs.  Hardware block lin runs on XCD lin mod NUM_XCD as
+// its (lin / NUM_XCD)-th block.
+__device__ __forceinline__ void spread_bins_tile(int lin, int nx, int ny, int& tx, int& ty)
+{
+    const int x = lin % NUM_XCD, j = lin / NUM_XCD;
+    const int cw = nx / NUM_XCD, extra = nx - cw * NUM_XCD;  // chunk width, leftover tiles per row
+    // blocks of XCD x in rows before ri: cw per row, plus the leftover tiles
+    // (ri' * extra + e) mod NUM_XCD == x, e < extra, that it was dealt
+    auto before = [&](int ri) {
+        int n = cw * ri;
+        if (extra) {
+            const int tot = ri * extra;              // leftover tiles dealt in rows < ri
+            n += tot / NUM_XCD + (x < tot % NUM_XCD ? 1 : 0);
+        }
+        return n;
+    };
+    int lo = 0, hi = ny;                             // largest ri with before(ri) <= j
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (before(mid) <= j) lo = mid;
+        else hi = mid;
+    }
+    const int ri = lo, r = j - before(ri);
+    if (r < cw) {
+        const int c = (ri & 1) ? (x + NUM_XCD / 2) % NUM_XCD : x;   // this XCD's chunk in row ri
+        tx = c * cw + r;
+    } else {
+        // the leftover tile e of row ri dealt to this XCD
+        const int first = (ri * extra) % NUM_XCD;   // XCD that takes leftover 0 of this row
+        const int e = (x - first + NUM_XCD) % NUM_XCD;
+        tx = NUM_XCD * cw + e;
+    }
+    ty = (ri & 1) ? ny - 1 - (ri >> 1) : (ri >> 1);
+}
+
 template <int BC>
 __global__ __launch_bounds__(NT) void spread_bins(Dev<float> d, const cx<float>* Pol, int B, cx<float>* E, size_t ws_img)
 {
     Blk bk = blk_plain();
-    const int k = bk.y;
-    bk.y = (k & 1) ? (int)gridDim.y - 1 - (k >> 1) : (k >> 1);
+    int tx, ty;
+    spread_bins_tile(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x, gridDim.y, tx, ty);
+    bk.x = tx;
+    bk.y = ty;
     spread_bins_body<BC>(d, bk, Pol, B, E, ws_img);
 }
 
