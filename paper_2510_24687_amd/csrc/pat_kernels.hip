@@ -438,7 +438,10 @@ struct Dev {
     // bin order of the FP32 spread (spread_bins): samples sorted by the cell of
     // their first tap, (gy0 mod Ng) * Ew + gx0 + hw, ring order within a bin
     const int* binRing;         // npts: ring-order index of the sample in each bin-order slot
+    const int* ringBin;         // npts: bin-order slot of each ring-order sample
     const int* binStart;        // Ng * Ew + 1: first slot of each bin
+    const int* spOrder;         // spCount: spread_bins dispatch table (spread_order)
+    int spCount;
     const cx<T>* binPos;        // npts: positions in bin order
     int binned;                 // 1: the adjoint spreads with spread_bins
     // approximate inverse (Sec. 3.3): its tables, and the per-call switches of
@@ -2033,9 +2036,11 @@ __global__ __launch_bounds__(NT) void lowk_adj(Dev<T> d, const cx<T>* G, cx<T>* 
     lowk_adj_body<T>(d, blk_plain(), G, Ulow, ws_img);
 }
 
-// Samples are written image-minor, Pol[(ringOff[l] + si) * B + b], already
-// multiplied by the conjugate point phase, for the batched spreads below
-// (whole rows of B values per sample: the spreads' staging reads them whole).
+// Samples are written image-minor, Pol[k * B + b], already multiplied by the
+// conjugate point phase, for the batched spreads below (whole rows of B values
+// per sample: the spreads' staging reads them whole); k is the ring-order
+// index ringOff[l] + si, or for the binned spread the sample's bin-order slot,
+// so that spread_bins stages the runs of a bin row as contiguous memory.
 template <typename T, int WMAX>
 __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<T>* V, const cx<T>* Ulow, cx<T>* Pol, int B,
                                               int G, size_t ws_img)
@@ -2068,14 +2073,26 @@ __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<
         T x, y;
         point_xy(d, off + si, x, y);
         const cx<T> ph = conjg(point_phase(d, x, y));
-        cx<T>* dst = Pol + (size_t)(off + si) * B + b0;
-        for (int i = 0; i < nb; ++i) {
-            // transpose of the conjugate-symmetric fill, then of the point phase
+        const size_t k = d.binned ? (size_t)d.ringBin[off + si] : (size_t)(off + si);
+        cx<T>* dst = Pol + k * B + b0;
+        // transpose of the conjugate-symmetric fill, then of the point phase
+        auto sample = [&](int i) {
             const int bo = i * N;
             const cx<T> a = buf[lds_phys<RING_PAD<T>>(bo + (s < 0 ? s + N : s))];
             const cx<T> c = buf[lds_phys<RING_PAD<T>>(bo + s + N / 2)];
-            dst[i] = cmul(a + conjg(c), ph);
+            return cmul(a + conjg(c), ph);
+        };
+        int i = 0;
+        if constexpr (sizeof(T) == 4) {
+            // FP32 pairs of images as one 16-byte store (the bin-order slots
+            // scatter the samples: one store instruction per pair, not two)
+            if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0)
+                for (; i + 1 < nb; i += 2) {
+                    const cx<T> u = sample(i), w = sample(i + 1);
+                    *reinterpret_cast<float4*>(dst + i) = make_float4(u.x, u.y, w.x, w.y);
+                }
         }
+        for (; i < nb; ++i) dst[i] = sample(i);
     }
 }
 
@@ -2304,60 +2321,81 @@ __host__ __device__ constexpr size_t spread_tiles_lds(bool staged, int bc, size_
 // ---------------------------------------------------------------------------
 // FP32 transpose of the gather over samples sorted by bin: the bin of a sample
 // is the cell of its first tap, gy0 = ceil(y - w/2) mod Ng and
-// gx0 = ceil(x - w/2) (ring order within a bin; binRing maps the bin order
-// back to the ring order of Pol).  Cell (gx, gy) receives exactly the samples
-// of the bins gx0 in [gx - w + 1, gx], gy0 in [gy - w + 1, gy]: in each of
-// those w bin rows, one contiguous run of slots.  A block owns a 16 x 16 tile
-// of cells (one per thread) and BC images.  It stages the runs of the tile's
-// 21 bin rows in LDS (positions, and each sample's BC values as one padded
-// row read with 16-byte loads), at most SB samples per pass, and then every
-// lane walks its own w runs: a lane visits only the ~31 samples that feed
-// its cell, where the lockstep walk of spread_tiles visits the union of the
-// tile's windows (~5x more).  Summation order per cell: bin row, then slot,
-// whatever the pass split; no atomics.
+// gx0 = ceil(x - w/2) (ring order within a bin).  Cell (gx, gy) receives
+// exactly the samples of the bins gx0 in [gx - w + 1, gx], gy0 in
+// [gy - w + 1, gy]: in each of those w bin rows, one contiguous run of slots.
+// A block owns a 16 x 16 tile of cells (one per thread) and BC images.  It
+// stages the runs of the tile's 21 bin rows in LDS, at most SB samples per
+// pass, one row of floats per sample: its BC values (contiguous in Pol, which
+// ring_adj writes in bin order for these plans) and its 2w kernel weights,
+// evaluated once per staged sample: the x weight of tap k at place
+// (gx0 + k) mod w, so that a cell finds its own by its column, and the y
+// weights by tap.  Every lane then walks its own w runs: a lane visits only
+// the ~31 samples that feed its cell, where the lockstep walk of spread_tiles
+// visits the union of the tile's windows (~5x more), and spends a product of
+// two staged weights and the BC multiply-adds per sample.  Summation order
+// per cell: bin row, then slot, whatever the pass split; no atomics.
+// The few tiles whose cells receive far more samples than the rest (the
+// densest small rings, next to the origin) are done as four blocks of 8 x 8
+// cells with four lanes per cell: lane k takes the slots k, k + 4, ... of
+// each run, and the four partial sums are added in a fixed order, (p0 + p1)
+// + (p2 + p3), so those cells differ from the one-lane order by rounding only
+// and every call gives the same bits.
 // ---------------------------------------------------------------------------
 constexpr int SB_TILE = 16;
-__host__ __device__ constexpr int spread_bins_cap(int bc) { return bc >= 16 ? 256 : 384; }
-// sample row of the staged values: BC values and 16 bytes of padding, so
-// that the 16-byte reads of lanes on neighbouring samples use other banks
-__host__ __device__ constexpr int spread_bins_row(int bc) { return bc + 2; }
+// samples per pass: the largest count whose rows fit four blocks in a CU's LDS
+__host__ __device__ constexpr int spread_bins_cap(int bc) { return bc >= 16 ? 224 : 352; }
+// floats per staged sample: 2 BC values, then w x weights and w y weights
+__host__ __device__ constexpr int spread_bins_row(int bc) { return 2 * bc + 12; }
 __host__ __device__ constexpr size_t spread_bins_lds(int bc)
 {
-    return 256 + (size_t)spread_bins_cap(bc) * (4 + 8 + 8 * (size_t)spread_bins_row(bc));
+    return 256 + 4 * (size_t)spread_bins_cap(bc) * (size_t)spread_bins_row(bc);
 }
 
-template <int BC>
-__device__ __forceinline__ void spread_bins_body(const Dev<float>& d, Blk bk, const cx<float>* Pol, int B, cx<float>* E,
-                                                 size_t ws_img)
+// TS = SB_TILE: the 16 x 16 tile (bk.x, bk.y), one lane per cell; TS = 8:
+// quadrant sub (x half sub & 1, y half sub >> 1) of that tile, four lanes per cell.
+template <int BC, int TS>
+__device__ __forceinline__ void spread_bins_body(const Dev<float>& d, Blk bk, int sub, const cx<float>* Pol, int B,
+                                                 cx<float>* E, size_t ws_img)
 {
-    constexpr int W = 6, TS = SB_TILE, NR = TS + W - 1;
-    constexpr int SB = spread_bins_cap(BC), SR = spread_bins_row(BC), TPS = BC / 2;
-    static_assert(NR <= 32 && TS * TS == NT && SB % 4 == 0 && SR % 2 == 0, "tile and LDS layout");
+    constexpr int W = 6, NR = TS + W - 1, LPC = NT / (TS * TS);  // lanes per cell
+    constexpr int SB = spread_bins_cap(BC), RW = spread_bins_row(BC), TPS = BC / 2;
+    constexpr int IT = (SB * TPS + NT - 1) / NT;  // staging tasks per thread and pass
+    static_assert(NR <= 32 && (LPC == 1 || LPC == 4) && LPC * TS * TS == NT && RW == 2 * BC + 2 * W && RW % 4 == 0 &&
+                      NT % TPS == 0,
+                  "tile and LDS layout");
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    unsigned char* lds = smem_raw;
-    int* s_vo = reinterpret_cast<int*>(lds);                  // NR + 1 run offsets (virtual index)
-    int* s_gs = s_vo + 32;                                    // NR first slots
-    int* s_map = reinterpret_cast<int*>(lds + 256);           // SB: slot of each staged sample
-    cx<float>* s_pos = reinterpret_cast<cx<float>*>(lds + 256 + 4 * SB);
-    float4* s_val = reinterpret_cast<float4*>(lds + 256 + 12 * SB);   // SB rows of SR / 2 float4
-    const int tid = threadIdx.x, cx_ = tid & (TS - 1), cy = tid / TS;
-    const int ex0 = bk.x * TS, ty0 = bk.y * TS;
+    int* s_vo = reinterpret_cast<int*>(smem_raw);            // NR + 1 run offsets (virtual index)
+    int* s_gs = s_vo + 32;                                   // NR first slots
+    float* s_row = reinterpret_cast<float*>(smem_raw + 256); // SB rows of RW floats
+    const int tid = threadIdx.x, cell = tid / LPC, part = tid % LPC;
+    const int cx_ = cell % TS, cy = cell / TS;
+    const int ex0 = bk.x * SB_TILE + (sub & 1) * TS, ty0 = bk.y * SB_TILE + (sub >> 1) * TS;
     const int e = ex0 + cx_, gy = ty0 + cy;
     const int Ng = d.Ng, mask = Ng - 1, Ew = d.Ew;
     const int b0 = bk.z * BC, nb = min(BC, B - b0);
     const bool valid = e < Ew;  // Ng is a multiple of the tile
     const int gx = e - d.hw;
     const int e_lo = max(ex0 - (W - 1), 0), e_hi = min(ex0 + TS - 1, Ew - 1);
-    if (tid < NR) {
-        const int row = (ty0 - (W - 1) + tid) & mask;
-        const int a = d.binStart[(size_t)row * Ew + e_lo], b = d.binStart[(size_t)row * Ew + e_hi + 1];
-        s_gs[tid] = a;
-        s_vo[tid + 1] = b - a;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        s_vo[0] = 0;
-        for (int q = 0; q < NR; ++q) s_vo[q + 1] += s_vo[q];
+    // the runs of the tile's bin rows: first slots, and offsets by a scan in the first wave
+    if (tid < 64) {
+        int a = 0, len = 0;
+        if (tid < NR && e_hi >= e_lo) {
+            const int row = (ty0 - (W - 1) + tid) & mask;
+            a = d.binStart[(size_t)row * Ew + e_lo];
+            len = d.binStart[(size_t)row * Ew + e_hi + 1] - a;
+        }
+        int inc = len;
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) {
+            const int t = __shfl_up(inc, o, 64);
+            if (tid >= o) inc += t;
+        }
+        if (tid < NR) {
+            s_gs[tid] = a;
+            s_vo[tid + 1] = inc;
+        }
+        if (tid == 0) s_vo[0] = 0;
     }
     __syncthreads();
     const int S = s_vo[NR];
@@ -2376,44 +2414,61 @@ __device__ __forceinline__ void spread_bins_body(const Dev<float>& d, Blk bk, co
         }
     }
     const float hwf = 0.5f * float(W), tw_ = 2.f / float(W);
+    const int rx = (gx + W) % W;          // place of this cell's x weight (gx >= -w/2)
+    const int mth = tid % TPS;            // image pair of this thread's staging tasks
     float4 acc[TPS];
 #pragma unroll
     for (int m = 0; m < TPS; ++m) acc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int pv = 0; pv < S; pv += SB) {
         const int cnt = min(SB, S - pv);
-        __syncthreads();  // the previous pass's walk is done with the slots
-        for (int q = 0; q < NR; ++q) {
-            const int a = max(s_vo[q], pv), b = min(s_vo[q + 1], pv + cnt);
-            for (int v = a + tid; v < b; v += NT) s_map[v - pv] = s_gs[q] + v - s_vo[q];
+        __syncthreads();  // the previous pass's walk is done with the rows
+        // staging: task (v, mth) loads image pair mth of staged sample v and
+        // evaluates weights mth, mth + TPS, ... of its 2w; the loads of all
+        // tasks are issued before any is used
+        float4 xv[IT];
+        cx<float> pp[IT];
+        int q = 0;
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int v = tid / TPS + it * (NT / TPS);
+            xv[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+            pp[it] = {0.f, 0.f};
+            if (v < cnt) {
+                const int vv = pv + v;
+                while (s_vo[q + 1] <= vv) ++q;
+                const size_t g = (size_t)(s_gs[q] + vv - s_vo[q]);
+                const cx<float>* src = Pol + g * B + b0 + 2 * mth;
+                if (2 * mth < nb) { xv[it].x = src[0].x; xv[it].y = src[0].y; }
+                if (2 * mth + 1 < nb) { xv[it].z = src[1].x; xv[it].w = src[1].y; }
+                pp[it] = d.binPos[g];
+            }
         }
-        __syncthreads();
-        // every load of this loop is independent of the others
-#pragma unroll 4
-        for (int t = tid; t < cnt * TPS; t += NT) {
-            const int v = t / TPS, m = t - v * TPS;
-            const int g = s_map[v];
-            const cx<float>* src = Pol + (size_t)d.binRing[g] * B + b0 + 2 * m;
-            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (2 * m < nb) { x.x = src[0].x; x.y = src[0].y; }
-            if (2 * m + 1 < nb) { x.z = src[1].x; x.w = src[1].y; }
-            s_val[v * (SR / 2) + m] = x;
-            if (m == 0) s_pos[v] = d.binPos[g];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int v = tid / TPS + it * (NT / TPS);
+            if (v < cnt) {
+                float* row = s_row + v * RW;
+                reinterpret_cast<float4*>(row)[mth] = xv[it];
+                const int gx0 = (int)ceil_t(pp[it].x - hwf), gy0 = (int)ceil_t(pp[it].y - hwf);
+#pragma unroll
+                for (int k = mth; k < 2 * W; k += TPS) {
+                    if (k < W) row[2 * BC + (gx0 + k + W) % W] = es_w(pp[it].x - float(gx0 + k), tw_, d.beta, d.beta_l2e);
+                    else row[2 * BC + k] = es_w(pp[it].y - float(gy0 + k - W), tw_, d.beta, d.beta_l2e);
+                }
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < W; ++r) {
+            // the binning puts every staged sample of this run inside the
+            // cell's stencil: x tap gx - gx0 and y tap w - 1 - r
             const int a = max(lo[r], pv) - pv, b = min(hi[r], pv + cnt) - pv;
-            for (int j = a; j < b; ++j) {
-                // the binning puts every staged sample of this run inside the
-                // cell's stencil: gx - gx0 and (gy - gy0) mod Ng lie in [0, W)
-                const cx<float> q = s_pos[j];
+            for (int j = a + part; j < b; j += LPC) {
+                const float* row = s_row + j * RW;
                 float4 val[TPS];
 #pragma unroll
-                for (int m = 0; m < TPS; ++m) val[m] = s_val[j * (SR / 2) + m];
-                const int gy0 = (int)ceil_t(q.y - hwf);
-                const int jy = (gy - gy0) & mask;
-                const float wgt = es_w(q.x - float(gx), tw_, d.beta, d.beta_l2e) *
-                                  es_w(q.y - float(gy0 + jy), tw_, d.beta, d.beta_l2e);
+                for (int m = 0; m < TPS; ++m) val[m] = reinterpret_cast<const float4*>(row)[m];
+                const float wgt = row[2 * BC + rx] * row[2 * BC + W + (W - 1 - r)];
 #pragma unroll
                 for (int m = 0; m < TPS; ++m) {
                     acc[m].x += val[m].x * wgt;
@@ -2424,9 +2479,22 @@ __device__ __forceinline__ void spread_bins_body(const Dev<float>& d, Blk bk, co
             }
         }
     }
+    if constexpr (LPC > 1) {
+        // the cell's LPC = 4 adjacent lanes: (p0 + p1) + (p2 + p3) on every lane
+#pragma unroll
+        for (int o = 1; o < LPC; o <<= 1)
+#pragma unroll
+            for (int m = 0; m < TPS; ++m) {
+                acc[m].x += __shfl_xor(acc[m].x, o, 64);
+                acc[m].y += __shfl_xor(acc[m].y, o, 64);
+                acc[m].z += __shfl_xor(acc[m].z, o, 64);
+                acc[m].w += __shfl_xor(acc[m].w, o, 64);
+            }
+    }
     if (valid) {
 #pragma unroll
         for (int m = 0; m < TPS; ++m) {
+            if (m % LPC != part) continue;  // one lane of the cell stores each image pair
             const cx<float> lo2[2] = {{acc[m].x, acc[m].y}, {acc[m].z, acc[m].w}};
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -2440,58 +2508,21 @@ __device__ __forceinline__ void spread_bins_body(const Dev<float>& d, Blk bk, co
     }
 }
 
-// Tile order.  Rows of tiles are taken heaviest first, as in spread_tiles
-// (rows 0, last, 1, last - 1, ...: the densest rings lie next to y = 0), and
-// inside a row every XCD takes its own chunk of nx / NUM_XCD adjacent tiles
-// (the leftover tiles of the rows go round-robin to the XCDs), so that the
-// bin rows and columns that neighbouring tiles both stage, in this row and
-// in the rows of the same half that follow soon after, are read through one
-// L2.  The rows of the lower half (odd order index) give chunk c to XCD
-// c + NUM_XCD / 2, so the heavy tiles at x = 0 of the two rows next to y = 0
-// run on different XCDs.  Hardware block lin runs on XCD lin mod NUM_XCD as
-// its (lin / NUM_XCD)-th block.
-__device__ __forceinline__ void spread_bins_tile(int lin, int nx, int ny, int& tx, int& ty)
-{
-    const int x = lin % NUM_XCD, j = lin / NUM_XCD;
-    const int cw = nx / NUM_XCD, extra = nx - cw * NUM_XCD;  // chunk width, leftover tiles per row
-    // blocks of XCD x in rows before ri: cw per row, plus the leftover tiles
-    // (ri' * extra + e) mod NUM_XCD == x, e < extra, that it was dealt
-    auto before = [&](int ri) {
-        int n = cw * ri;
-        if (extra) {
-            const int tot = ri * extra;              // leftover tiles dealt in rows < ri
-            n += tot / NUM_XCD + (x < tot % NUM_XCD ? 1 : 0);
-        }
-        return n;
-    };
-    int lo = 0, hi = ny;                             // largest ri with before(ri) <= j
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (before(mid) <= j) lo = mid;
-        else hi = mid;
-    }
-    const int ri = lo, r = j - before(ri);
-    if (r < cw) {
-        const int c = (ri & 1) ? (x + NUM_XCD / 2) % NUM_XCD : x;   // this XCD's chunk in row ri
-        tx = c * cw + r;
-    } else {
-        // the leftover tile e of row ri dealt to this XCD
-        const int first = (ri * extra) % NUM_XCD;   // XCD that takes leftover 0 of this row
-        const int e = (x - first + NUM_XCD) % NUM_XCD;
-        tx = NUM_XCD * cw + e;
-    }
-    ty = (ri & 1) ? ny - 1 - (ri >> 1) : (ri >> 1);
-}
-
+// Dispatch order: block lin does entry lin / nz of the plan's table spOrder
+// (tx | ty << 12 | quadrant << 24 | split << 26, see spread_order) for image
+// group lin mod nz.  The table lists the tiles longest first by a cost
+// estimate, so that the last blocks to start are short ones, and a tile whose
+// estimate alone would exceed the balanced share of a block slot appears as
+// its four split quadrants.
 template <int BC>
-__global__ __launch_bounds__(NT) void spread_bins(Dev<float> d, const cx<float>* Pol, int B, cx<float>* E, size_t ws_img)
+__global__ __launch_bounds__(NT) void spread_bins(Dev<float> d, const cx<float>* Pol, int B, cx<float>* E, size_t ws_img,
+                                                  int nz)
 {
-    Blk bk = blk_plain();
-    int tx, ty;
-    spread_bins_tile(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x, gridDim.y, tx, ty);
-    bk.x = tx;
-    bk.y = ty;
-    spread_bins_body<BC>(d, bk, Pol, B, E, ws_img);
+    const int lin = blockIdx.x;
+    const int t = d.spOrder[lin / nz];
+    const Blk bk = {t & 0xfff, (t >> 12) & 0xfff, lin % nz, 0};
+    if (t >> 26) spread_bins_body<BC, SB_TILE / 2>(d, bk, (t >> 24) & 3, Pol, B, E, ws_img);
+    else spread_bins_body<BC, SB_TILE>(d, bk, 0, Pol, B, E, ws_img);
 }
 
 template <typename T>
@@ -2949,6 +2980,68 @@ int lds_dct(const pat::Params& P)
     return cw;
 }
 
+// Dispatch table of spread_bins over the 16 x 16 cell tiles of the Ng x Ew
+// grid (bin table `start`).  A tile's cost is estimated as 53 + S + 2.9 wmax,
+// S the samples its bin rows stage and wmax the longest walk of its four
+// waves (per wave, the sum over the w bin rows of the longest run among its
+// 64 cells): the proportions of a least-squares fit of measured block
+// durations.  Tiles are listed by decreasing cost; one whose cost exceeds
+// 0.8 times the balanced share of a block slot, sum(cost) / slots, is listed
+// as its four quadrants instead (cost / 4 x 1.4 each).  Entries:
+// tx | ty << 12 | quadrant << 24 | split << 26.  Empty if a tile index does
+// not fit its field.
+std::vector<int> spread_order(const pat::Params& P, const std::vector<int>& start, int slots)
+{
+    const int W = P.w, Ng = P.Ng, Ew = P.Ew, mask = Ng - 1, TS = 16;
+    const int nx = (Ew + TS - 1) / TS, ny = Ng / TS;
+    if (nx >= 4096 || ny >= 4096 || ny * TS != Ng) return {};
+    auto run = [&](int row, int lo, int hi) {  // samples in bins lo..hi of a bin row
+        lo = std::max(lo, 0);
+        hi = std::min(hi, Ew - 1);
+        return hi < lo ? 0 : start[(size_t)row * Ew + hi + 1] - start[(size_t)row * Ew + lo];
+    };
+    std::vector<double> cost((size_t)nx * ny);
+    double total = 0;
+    for (int ty = 0; ty < ny; ++ty)
+        for (int tx = 0; tx < nx; ++tx) {
+            double S = 0, wmax = 0;
+            for (int q = 0; q < TS + W - 1; ++q)
+                S += run((ty * TS - (W - 1) + q) & mask, tx * TS - (W - 1), tx * TS + TS - 1);
+            for (int wv = 0; wv < NT / 64; ++wv) {
+                double steps = 0;
+                for (int r = 0; r < W; ++r) {
+                    int longest = 0;
+                    for (int cy = wv * (64 / TS); cy < (wv + 1) * (64 / TS); ++cy) {
+                        const int row = (ty * TS + cy - (W - 1) + r) & mask;
+                        for (int cx = 0; cx < TS && tx * TS + cx < Ew; ++cx)
+                            longest = std::max(longest, run(row, tx * TS + cx - (W - 1), tx * TS + cx));
+                    }
+                    steps += longest;
+                }
+                wmax = std::max(wmax, steps);
+            }
+            cost[(size_t)ty * nx + tx] = 53.0 + S + 2.9 * wmax;
+            total += cost[(size_t)ty * nx + tx];
+        }
+    const double split = 0.8 * total / std::max(slots, 1);
+    std::vector<std::pair<double, int>> items;
+    for (int ty = 0; ty < ny; ++ty)
+        for (int tx = 0; tx < nx; ++tx) {
+            const double c = cost[(size_t)ty * nx + tx];
+            const int enc = tx | ty << 12;
+            if (c > split)
+                for (int qd = 0; qd < 4; ++qd) items.push_back({c / 4 * 1.4, enc | qd << 24 | 1 << 26});
+            else
+                items.push_back({c, enc});
+        }
+    std::sort(items.begin(), items.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+        return a.first != b.first ? a.first > b.first : a.second < b.second;
+    });
+    std::vector<int> order(items.size());
+    for (size_t i = 0; i < items.size(); ++i) order[i] = items[i].second;
+    return order;
+}
+
 template <typename T>
 int upload(pat_plan_s* p, Dev<T>& d)
 {
@@ -3007,12 +3100,13 @@ int upload(pat_plan_s* p, Dev<T>& d)
     if ((rc = put(twm.data(), twm.size() * sizeof(T), (const void**)&d.twm))) return rc;
     std::vector<T> pos = conv(H.pos);
     if ((rc = put(pos.data(), pos.size() * sizeof(T), (const void**)&d.pos))) return rc;
-    d.binRing = nullptr; d.binStart = nullptr; d.binPos = nullptr; d.binned = 0;
+    d.binRing = nullptr; d.ringBin = nullptr; d.binStart = nullptr; d.binPos = nullptr; d.binned = 0;
+    d.spOrder = nullptr; d.spCount = 0;
     if constexpr (sizeof(T) == 4) {
         // counting sort of the samples by the cell of their first tap, computed
         // with the same FP32 operations as the kernels' tap rule
         const size_t nb = (size_t)P.Ng * P.Ew;
-        std::vector<int> key(P.npts), start(nb + 1, 0), ring(P.npts);
+        std::vector<int> key(P.npts), start(nb + 1, 0), ring(P.npts), rbin(P.npts);
         bool ok = true;
         const float hwf = 0.5f * (float)P.w;
         for (int q = 0; q < P.npts && ok; ++q) {
@@ -3030,13 +3124,24 @@ int upload(pat_plan_s* p, Dev<T>& d)
             for (int q = 0; q < P.npts; ++q) {
                 const int slot = fill[key[q]]++;
                 ring[slot] = q;
+                rbin[q] = slot;
                 bpos[2 * (size_t)slot] = pos[2 * (size_t)q];
                 bpos[2 * (size_t)slot + 1] = pos[2 * (size_t)q + 1];
             }
             if ((rc = put(ring.data(), ring.size() * sizeof(int), (const void**)&d.binRing))) return rc;
+            if ((rc = put(rbin.data(), rbin.size() * sizeof(int), (const void**)&d.ringBin))) return rc;
             if ((rc = put(start.data(), start.size() * sizeof(int), (const void**)&d.binStart))) return rc;
             if ((rc = put(bpos.data(), bpos.size() * sizeof(T), (const void**)&d.binPos))) return rc;
-            p->bin_ok = 1;
+            // four spread_bins blocks fit a CU's LDS at once
+            int ncu = 0;
+            if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || ncu < 1)
+                ncu = 256;
+            const std::vector<int> order = spread_order(P, start, 4 * ncu);
+            if (!order.empty()) {
+                if ((rc = put(order.data(), order.size() * sizeof(int), (const void**)&d.spOrder))) return rc;
+                d.spCount = (int)order.size();
+                p->bin_ok = 1;
+            }
         }
     }
     if (!p->bin_ok && p->spread_staged == 2) p->spread_staged = 1;
@@ -3269,8 +3374,11 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
         bool done = false;
         if constexpr (sizeof(T) == 4) {
             if (d.binned) {
-                if (p->spread_bc >= BCL) spread_bins<BCL><<<g1, NT, spread_bins_lds(BCL), st>>>(d, Pol, B, E, wi);
-                else spread_bins<BCL / 2><<<g2, NT, spread_bins_lds(BCL / 2), st>>>(d, Pol, B, E, wi);
+                const int nz1 = (int)g1.z, nz2 = (int)g2.z;
+                if (p->spread_bc >= BCL)
+                    spread_bins<BCL><<<d.spCount * nz1, NT, spread_bins_lds(BCL), st>>>(d, Pol, B, E, wi, nz1);
+                else
+                    spread_bins<BCL / 2><<<d.spCount * nz2, NT, spread_bins_lds(BCL / 2), st>>>(d, Pol, B, E, wi, nz2);
                 done = true;
             }
         }
@@ -3397,7 +3505,11 @@ __host__ __device__ inline void stage_grid(const Dev<T>& d, int S, int B, int G,
             if (d.binned) { nx = (d.Ew + GB_TILE - 1) / GB_TILE; ny = d.Ng / GB_TILE; nz = (B + GB_BC - 1) / GB_BC; }
             else { nx = 0; ny = 1; }
             break;
-        default: nx = (d.Ew + 15) / 16; ny = (d.Ng + 15) / 16; nz = (B + BC - 1) / BC; break;  // spread
+        default:  // spread: the binned form walks the plan's dispatch table
+            nz = (B + BC - 1) / BC;
+            if (d.binned) { nx = d.spCount; ny = 1; }
+            else { nx = (d.Ew + 15) / 16; ny = (d.Ng + 15) / 16; }
+            break;
     }
 }
 
@@ -3471,10 +3583,12 @@ __global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
     if constexpr (S == PAT_STAGE_SPREAD_ADJ) {
         if constexpr (sizeof(T) == 4) {
             if (q.d.binned) {
-                // heaviest tile rows first, as the single-plan launch
-                const int ny = (q.d.Ng + 15) / 16, k = bk.y;
-                bk.y = (k & 1) ? ny - 1 - (k >> 1) : (k >> 1);
-                spread_bins_body<BC>(q.d, bk, Pol, q.B, E, q.wi);
+                // entry local / nz of the plan's dispatch table for image group
+                // local mod nz, as the single-plan launch
+                const int t = q.d.spOrder[local / nz];
+                const Blk tb = {t & 0xfff, (t >> 12) & 0xfff, local % nz, 0};
+                if (t >> 26) spread_bins_body<BC, SB_TILE / 2>(q.d, tb, (t >> 24) & 3, Pol, q.B, E, q.wi);
+                else spread_bins_body<BC, SB_TILE>(q.d, tb, 0, Pol, q.B, E, q.wi);
                 return;
             }
         }
