@@ -442,6 +442,8 @@ struct Dev {
     const int* binStart;        // Ng * Ew + 1: first slot of each bin
     const int* spOrder;         // spCount: spread_bins dispatch table (spread_order)
     int spCount;
+    const int* gbOrder;         // gbCount: gather_bins dispatch table (gather_order)
+    int gbCount;
     const cx<T>* binPos;        // npts: positions in bin order
     int binned;                 // 1: the adjoint spreads with spread_bins
     // approximate inverse (Sec. 3.3): its tables, and the per-call switches of
@@ -804,26 +806,35 @@ __device__ __forceinline__ void gather_bins_body(const Dev<float>& d, Blk bk, co
         s_gs[tid] = a;
         s_vo[tid + 1] = b - a;
     }
-    // stage the cells: (row, column, image pair) tasks, coalesced along the row
-    for (int t = tid; t < NC * NC * TPS; t += NT) {
+    // stage the cells: (row, column, image pair) tasks, coalesced along the
+    // row; every load is issued before the first is stored
+    constexpr int ITG = (NC * NC * TPS + NT - 1) / NT;
+    float4 xs[ITG];
+#pragma unroll
+    for (int it = 0; it < ITG; ++it) {
+        const int t = tid + it * NT;
         const int m = t % TPS, c = t / TPS;
         const int lx = c % NC, ly = c / NC;
         const int ex = ex0 + lx, gy = (ty0 + ly) & mask;
-        float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (ex < Ew) {
+        xs[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (t < NC * NC * TPS && ex < Ew) {
             const int k = 2 * m;
             if (k < nb) {
                 const cx<float> v = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(E) +
                                                                      (size_t)(b0 + k) * ws_img)[(size_t)gy * Ew + ex];
-                x.x = v.x; x.y = v.y;
+                xs[it].x = v.x; xs[it].y = v.y;
             }
             if (k + 1 < nb) {
                 const cx<float> v = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(E) +
                                                                      (size_t)(b0 + k + 1) * ws_img)[(size_t)gy * Ew + ex];
-                x.z = v.x; x.w = v.y;
+                xs[it].z = v.x; xs[it].w = v.y;
             }
         }
-        s_cell[c * (CR / 2) + m] = x;
+    }
+#pragma unroll
+    for (int it = 0; it < ITG; ++it) {
+        const int t = tid + it * NT;
+        if (t < NC * NC * TPS) s_cell[(t / TPS) * (CR / 2) + t % TPS] = xs[it];
     }
     __syncthreads();
     if (tid == 0) {
@@ -889,11 +900,15 @@ __device__ __forceinline__ void gather_bins_body(const Dev<float>& d, Blk bk, co
     }
 }
 
+// Block lin does tile gbOrder[lin / nz] (tx | ty << 12; tiles longest first
+// by a cost estimate, see gather_order) for image group lin mod nz.
 template <int BC>
 __global__ __launch_bounds__(NT, 4) void gather_bins(Dev<float> d, const cx<float>* E, cx<float>* Pout, int B, int G,
-                                                     size_t ws_img)
+                                                     size_t ws_img, int nz)
 {
-    gather_bins_body<BC>(d, blk_xcd(), E, Pout, B, G, ws_img);
+    const int lin = blockIdx.x;
+    const int t = d.gbOrder[lin / nz];
+    gather_bins_body<BC>(d, Blk{t & 0xfff, t >> 12, lin % nz, 0}, E, Pout, B, G, ws_img);
 }
 
 // Sum over aligned groups of W consecutive lanes (W a power of two <= 64),
@@ -3042,6 +3057,33 @@ std::vector<int> spread_order(const pat::Params& P, const std::vector<int>& star
     return order;
 }
 
+// Dispatch table of gather_bins over its 16 x 16 bin tiles: a tile's cost is
+// estimated as 675 + S + 573 ceil(S / NT), S the samples of its bins (one
+// thread per sample, in rounds of NT), the proportions of a least-squares fit
+// of measured block durations; tiles longest first.  Entries tx | ty << 12;
+// empty if a tile index does not fit its field.
+std::vector<int> gather_order(const pat::Params& P, const std::vector<int>& start)
+{
+    const int Ng = P.Ng, Ew = P.Ew, TS = 16;
+    const int nx = (Ew + TS - 1) / TS, ny = Ng / TS;
+    if (nx >= 4096 || ny >= 4096 || ny * TS != Ng) return {};
+    std::vector<std::pair<double, int>> items;
+    for (int ty = 0; ty < ny; ++ty)
+        for (int tx = 0; tx < nx; ++tx) {
+            const int e1 = std::min(tx * TS + TS, Ew);
+            double S = 0;
+            for (int row = ty * TS; row < ty * TS + TS; ++row)
+                S += start[(size_t)row * Ew + e1] - start[(size_t)row * Ew + tx * TS];
+            items.push_back({675.0 + S + 573.0 * std::ceil(S / NT), tx | ty << 12});
+        }
+    std::sort(items.begin(), items.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+        return a.first != b.first ? a.first > b.first : a.second < b.second;
+    });
+    std::vector<int> order(items.size());
+    for (size_t i = 0; i < items.size(); ++i) order[i] = items[i].second;
+    return order;
+}
+
 template <typename T>
 int upload(pat_plan_s* p, Dev<T>& d)
 {
@@ -3101,7 +3143,7 @@ int upload(pat_plan_s* p, Dev<T>& d)
     std::vector<T> pos = conv(H.pos);
     if ((rc = put(pos.data(), pos.size() * sizeof(T), (const void**)&d.pos))) return rc;
     d.binRing = nullptr; d.ringBin = nullptr; d.binStart = nullptr; d.binPos = nullptr; d.binned = 0;
-    d.spOrder = nullptr; d.spCount = 0;
+    d.spOrder = nullptr; d.spCount = 0; d.gbOrder = nullptr; d.gbCount = 0;
     if constexpr (sizeof(T) == 4) {
         // counting sort of the samples by the cell of their first tap, computed
         // with the same FP32 operations as the kernels' tap rule
@@ -3136,10 +3178,12 @@ int upload(pat_plan_s* p, Dev<T>& d)
             int ncu = 0;
             if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || ncu < 1)
                 ncu = 256;
-            const std::vector<int> order = spread_order(P, start, 4 * ncu);
-            if (!order.empty()) {
+            const std::vector<int> order = spread_order(P, start, 4 * ncu), gorder = gather_order(P, start);
+            if (!order.empty() && !gorder.empty()) {
                 if ((rc = put(order.data(), order.size() * sizeof(int), (const void**)&d.spOrder))) return rc;
+                if ((rc = put(gorder.data(), gorder.size() * sizeof(int), (const void**)&d.gbOrder))) return rc;
                 d.spCount = (int)order.size();
+                d.gbCount = (int)gorder.size();
                 p->bin_ok = 1;
             }
         }
@@ -3272,8 +3316,8 @@ int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g
                 // the batch's sample array (the adjoint's Pol) holds the gathered samples
                 StageTimer tg(p, st, PAT_STAGE_GATHER_FWD);
                 cx<T>* Pg = reinterpret_cast<cx<T>*>(ws + (size_t)B * p->ws_stride);
-                const dim3 grid((d.Ew + GB_TILE - 1) / GB_TILE, d.Ng / GB_TILE, (B + GB_BC - 1) / GB_BC);
-                gather_bins<GB_BC><<<grid, NT, gather_bins_lds(GB_BC), st>>>(d, E, Pg, B, G, wi);
+                const int nz = (B + GB_BC - 1) / GB_BC;
+                gather_bins<GB_BC><<<d.gbCount * nz, NT, gather_bins_lds(GB_BC), st>>>(d, E, Pg, B, G, wi, nz);
                 Pin = Pg;
             }
             if ((rc = check_launch("gather_bins"))) return rc;
@@ -3502,7 +3546,7 @@ __host__ __device__ inline void stage_grid(const Dev<T>& d, int S, int B, int G,
         case PAT_STAGE_LOWK_ADJ: nx = d.lcorr; ny = B; break;
         case PAT_STAGE_RING_ADJ: nx = (B + G - 1) / G; ny = d.L; break;
         case STAGE_GATHER:
-            if (d.binned) { nx = (d.Ew + GB_TILE - 1) / GB_TILE; ny = d.Ng / GB_TILE; nz = (B + GB_BC - 1) / GB_BC; }
+            if (d.binned) { nx = d.gbCount; ny = 1; nz = (B + GB_BC - 1) / GB_BC; }
             else { nx = 0; ny = 1; }
             break;
         default:  // spread: the binned form walks the plan's dispatch table
@@ -3558,7 +3602,11 @@ __global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
     if constexpr (S == PAT_STAGE_ROWS_FWD) rows_fwd_body<T>(q.d, bk, q.fin, q.fs, R, q.wi);
     if constexpr (S == PAT_STAGE_COLS_FWD) cols_fwd_body<T>(q.d, bk, R, E, q.wi);
     if constexpr (S == STAGE_GATHER) {
-        if constexpr (sizeof(T) == 4) gather_bins_body<GB_BC>(q.d, bk, E, Pol, q.B, q.G, q.wi);
+        // entry local / nz of the plan's dispatch table, as the single-plan launch
+        if constexpr (sizeof(T) == 4) {
+            const int t = q.d.gbOrder[local / nz];
+            gather_bins_body<GB_BC>(q.d, Blk{t & 0xfff, t >> 12, local % nz, 0}, E, Pol, q.B, q.G, q.wi);
+        }
     }
     if constexpr (S == PAT_STAGE_RING_FWD) ring_fwd_body<T, WMAX>(q.d, bk, E, q.d.binned ? Pol : nullptr, V, U, q.wi, q.B, q.G);
     if constexpr (S == PAT_STAGE_DCT_FWD) {
