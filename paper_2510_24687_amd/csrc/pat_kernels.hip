@@ -691,6 +691,9 @@ __device__ __forceinline__ void ring_fft(const Dev<T>& d, int l, cx<T>* buf, int
     }
 }
 
+// loads per thread that the ring kernels' data loops issue together
+constexpr int RING_CH = 4;
+
 // One block per (ring, group of up to G images): the taps, weights and phase
 // of each half-ring sample are computed once and applied to every image of
 // the group (the transcendental work does not depend on the image).
@@ -710,13 +713,23 @@ __device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<
         // samples gathered by gather_bins, phase applied, grouped as this
         // kernel reads them: image group grp holds npts x nb values, sample-major
         const cx<T>* src = Pin + (size_t)b0 * d.npts + (size_t)d.ringOff[l] * nb;
-        for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
-            const int s = si - N / 4;
-            for (int i = 0; i < nb; ++i) {
-                const cx<T> v = src[(size_t)si * nb + i];
-                const int bo = i * N;
-                buf[lds_phys<RING_PAD<T>>(bo + (s < 0 ? s + N : s))] = v;
-                buf[lds_phys<RING_PAD<T>>(bo + (s + N / 2))] = conjg(v);
+        // value t = si nb + i, in chunks of RING_CH loads per thread issued together
+        const int nv = (N / 2) * nb;
+        for (int t0 = 0; t0 < nv; t0 += RING_CH * NT) {
+            cx<T> v[RING_CH];
+#pragma unroll
+            for (int u = 0; u < RING_CH; ++u) {
+                const int t = t0 + u * NT + threadIdx.x;
+                if (t < nv) v[u] = src[t];
+            }
+#pragma unroll
+            for (int u = 0; u < RING_CH; ++u) {
+                const int t = t0 + u * NT + threadIdx.x;
+                if (t < nv) {
+                    const int si = t / nb, i = t - si * nb, s = si - N / 4, bo = i * N;
+                    buf[lds_phys<RING_PAD<T>>(bo + (s < 0 ? s + N : s))] = v[u];
+                    buf[lds_phys<RING_PAD<T>>(bo + (s + N / 2))] = conjg(v[u]);
+                }
             }
         }
     } else
@@ -745,15 +758,28 @@ __device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<
     __syncthreads();
     ring_fft(d, l, buf, N, logN, nb, false);
     const T invN = T(1) / T(N);
-    for (int i = 0; i < nb; ++i) {
-        const int bo = i * N;
-        cx<T>* Vb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(V) + (size_t)(b0 + i) * ws_img);
-        cx<T>* Ub = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(Ulow) + (size_t)(b0 + i) * ws_img);
-        for (int k = threadIdx.x; k < d.Kp; k += blockDim.x) {
-            cx<T> out = {T(0), T(0)};
-            if (k <= Kl) out = mul_ipow(buf[lds_phys<RING_PAD<T>>(bo + (k))] * d.Tb[(size_t)l * d.Kp + k], k);
-            Vb[(size_t)l * d.Kp + k] = out;
-            if (l < d.lcorr && k <= d.klow) Ub[(size_t)l * (d.klow + 1) + k] = (k <= Kl ? buf[lds_phys<RING_PAD<T>>(bo + (k))] : cx<T>{T(0), T(0)}) * invN;
+    // chunks of RING_CH harmonics per thread: their table values are loaded
+    // together, before any store of the chunk
+    for (int k0 = 0; k0 < d.Kp; k0 += RING_CH * NT) {
+        T tb[RING_CH];
+#pragma unroll
+        for (int u = 0; u < RING_CH; ++u) {
+            const int k = k0 + u * NT + threadIdx.x;
+            tb[u] = (k <= Kl && k < d.Kp) ? d.Tb[(size_t)l * d.Kp + k] : T(0);
+        }
+        for (int i = 0; i < nb; ++i) {
+            const int bo = i * N;
+            cx<T>* Vb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(V) + (size_t)(b0 + i) * ws_img);
+            cx<T>* Ub = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(Ulow) + (size_t)(b0 + i) * ws_img);
+#pragma unroll
+            for (int u = 0; u < RING_CH; ++u) {
+                const int k = k0 + u * NT + threadIdx.x;
+                if (k >= d.Kp) continue;
+                cx<T> out = {T(0), T(0)};
+                if (k <= Kl) out = mul_ipow(buf[lds_phys<RING_PAD<T>>(bo + (k))] * tb[u], k);
+                Vb[(size_t)l * d.Kp + k] = out;
+                if (l < d.lcorr && k <= d.klow) Ub[(size_t)l * (d.klow + 1) + k] = (k <= Kl ? buf[lds_phys<RING_PAD<T>>(bo + (k))] : cx<T>{T(0), T(0)}) * invN;
+            }
         }
     }
 }
@@ -1214,6 +1240,28 @@ __device__ __forceinline__ void dw_pass(PAT_LDS cx<float>* buf, const PAT_GLOBAL
     constexpr int NBS = M / R;               // butterflies per sequence
     constexpr int NBT = NC * NBS;            // butterflies of the column group
     constexpr int PER = (NBT + L - 1) / L;   // butterflies per lane (the last round may be partial)
+    // twiddles W_{R NS}^{r k} = twd[r k STEP], conjugated (inverse direction).
+    // k = t mod NS: for NS <= L it is lane mod NS for every butterfly of the
+    // lane (loaded once); for the radix-3 pass (NS = 2^LOGP >= L) it is
+    // lane + L u' and W_M^k = W_M^lane W_M^{L u'} (the second factor uniform).
+    // They do not depend on the data: loaded first, so that their latency
+    // overlaps the LDS reads and the barrier.
+    constexpr int STEP = 2 * M / (R * NS);
+    constexpr int LR = R == 2 ? 1 : R == 4 ? 2 : 3;
+    cx<float> traw[LR];
+    if constexpr (NS > 1 && NS <= L && R != 3) {
+        const int k = lane & (NS - 1);
+#pragma unroll
+        for (int e = 0; e < LR; ++e) traw[e] = ld_glb(twd + ((k * STEP) << e));
+    }
+    cx<float> wlane = {1.f, 0.f}, wu3[PER];
+    if constexpr (R == 3) {
+        static_assert(NS >= L, "radix-3 pass after sub-transforms of at least L points");
+        wlane = ld_glb(twd + 2 * lane);
+        wlane.y = -wlane.y;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) wu3[u] = ld_glb(twd + 2 * L * ((u % (NS / L))));   // uniform: W_M^{L u'}
+    }
     cx<float> v[PER][R];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -1225,22 +1273,9 @@ __device__ __forceinline__ void dw_pass(PAT_LDS cx<float>* buf, const PAT_GLOBAL
         for (int r = 0; r < R; ++r) v[u][r] = ld_lds(s + dw_phys(tt + r * NBS));
     }
     __syncthreads();
-    // twiddles W_{R NS}^{r k} = twd[r k STEP], conjugated (inverse direction).
-    // k = t mod NS: for NS <= L it is lane mod NS for every butterfly of the
-    // lane (loaded once); for the radix-3 pass (NS = 2^LOGP >= L) it is
-    // lane + L u' and W_M^k = W_M^lane W_M^{L u'} (the second factor uniform).
-    constexpr int STEP = 2 * M / (R * NS);
     cx<float> wl[R];
-    if constexpr (NS > 1 && NS <= L && R != 3) {
-        const int k = lane & (NS - 1);
-        tw_powers<R>([&](int e) { cx<float> w = ld_glb(twd + ((k * STEP) << e)); w.y = -w.y; return w; }, wl);
-    }
-    cx<float> wlane = {1.f, 0.f};
-    if constexpr (R == 3) {
-        static_assert(NS >= L, "radix-3 pass after sub-transforms of at least L points");
-        wlane = ld_glb(twd + 2 * lane);
-        wlane.y = -wlane.y;
-    }
+    if constexpr (NS > 1 && NS <= L && R != 3)
+        tw_powers<R>([&](int e) { cx<float> w = traw[e]; w.y = -w.y; return w; }, wl);
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int t = lane + L * u;
@@ -1248,7 +1283,7 @@ __device__ __forceinline__ void dw_pass(PAT_LDS cx<float>* buf, const PAT_GLOBAL
         const int b = t / NBS, tt = t - b * NBS;
         const int k = tt % NS;
         if constexpr (R == 3) {
-            cx<float> wu = ld_glb(twd + 2 * L * ((u % (NS / L))));   // uniform: W_M^{L u'}
+            cx<float> wu = wu3[u];
             wu.y = -wu.y;
             const cx<float> w1 = cmul(wlane, wu), w2 = cmul(w1, w1);
             v[u][1] = cmul(v[u][1], w1);
@@ -1332,10 +1367,32 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
     const int nout = adjoint ? d.L : d.nt;
     const int y0 = adjoint ? 0 : 1, ymax = adjoint ? d.L - 1 : d.nt;
     const int Kp = d.Kp;
-    // (1) block: input rows of the CB columns -> column buffers, slots x = 0..M
-    for (int i = threadIdx.x; i < CB * nx; i += NT) {
-        const int row = i / CB, c = i - row * CB;
-        st_lds(lbuf + c * CP + dw_phys(row + x_lo), ld_glb((const PAT_GLOBAL cx<float>*)(ib + (size_t)row * Kp + k0 + c)));
+    constexpr int L = DW_LPC;
+    const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L, wv = lane >> 6;
+    // the twiddles of step (2), e^{-i pi j/M} for j = lane + L v: the lane's
+    // factor times a uniform one, loaded before the column data
+    constexpr int PJ = M / L;
+    static_assert(M % L == 0 && NC <= 4, "M must be a multiple of the column group");
+    const cx<float> wlane = ld_glb(twd + lane);
+    cx<float> wuni[PJ];
+#pragma unroll
+    for (int v = 0; v < PJ; ++v) wuni[v] = ld_glb(twd + L * v);
+    // (1) block: input rows of the CB columns -> column buffers, slots x = 0..M,
+    // in chunks of 8 loads per thread, all issued before the chunk's stores
+    for (int i0 = 0; i0 < CB * nx; i0 += 8 * NT) {
+        cx<float> v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * NT + threadIdx.x;
+            const int row = i / CB, c = i - row * CB;
+            if (i < CB * nx) v[u] = ld_glb((const PAT_GLOBAL cx<float>*)(ib + (size_t)row * Kp + k0 + c));
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * NT + threadIdx.x;
+            const int row = i / CB, c = i - row * CB;
+            if (i < CB * nx) st_lds(lbuf + c * CP + dw_phys(row + x_lo), v[u]);
+        }
     }
     const int nzero = x_lo + (M + 1 - x_hi);   // slots [0, x_lo) and [x_hi, M]
     for (int i = threadIdx.x; i < CB * nzero; i += NT) {
@@ -1344,19 +1401,13 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
         st_lds(lbuf + c * CP + dw_phys(x), cx<float>{0.f, 0.f});
     }
     __syncthreads();
-    constexpr int L = DW_LPC;
     // block-wide partial results of the two waves of each column group
     __shared__ cx<float> red[DW_GROUPS][4][2];
-    const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L, wv = lane >> 6;
     PAT_LDS cx<float>* wb = lbuf + grp * NC * CP;
     // (2) per column: F_1's interior sum and g_j = (f_j + f_{M-j})/2 - sin(pi j/M) (f_j - f_{M-j})
     cx<float> F1[NC], e0[NC], eM[NC];
     {
-        constexpr int PJ = M / L;
-        static_assert(M % L == 0 && NC <= 4, "M must be a multiple of the column group");
         cx<float> gv[NC][PJ];
-        // e^{-i pi j/M} for j = lane + L v: the lane's factor times a uniform one
-        const cx<float> wlane = ld_glb(twd + lane);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const PAT_LDS cx<float>* col = wb + c * CP;
@@ -1368,7 +1419,7 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
                 const int j = lane + L * v;
                 const cx<float> fj = ld_lds(col + dw_phys(j));
                 const cx<float> fm = ld_lds(col + dw_phys(M - j));
-                const cx<float> w = cmul(wlane, ld_glb(twd + L * v));   // (cos(pi j/M), -sin(pi j/M))
+                const cx<float> w = cmul(wlane, wuni[v]);   // (cos(pi j/M), -sin(pi j/M))
                 acc = acc + fj * w.x;
                 const float sj = -w.y;
                 gv[c][v] = {0.5f * (fj.x + fm.x) - sj * (fj.x - fm.x), 0.5f * (fj.y + fm.y) - sj * (fj.y - fm.y)};
@@ -2067,47 +2118,81 @@ __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<
     const int b0 = grp * G, nb = min(G, B - b0);
     const int N = d.ringN[l], logN = d.ringLog[l], Kl = d.ringK[l];
     const T invN = T(1) / T(N);
-    for (int i = 0; i < nb; ++i) {
-        const cx<T>* Vb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(V) + (size_t)(b0 + i) * ws_img);
-        const cx<T>* Ub = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(Ulow) + (size_t)(b0 + i) * ws_img);
-        const int bo = i * N;
-        for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    // entry t = i N + k, in chunks of RING_CH per thread whose loads are issued together
+    for (int t0 = 0; t0 < nb * N; t0 += RING_CH * NT) {
+        cx<T> vv[RING_CH], uu[RING_CH];
+        T tb[RING_CH];
+#pragma unroll
+        for (int u = 0; u < RING_CH; ++u) {
+            const int t = t0 + u * NT + threadIdx.x, i = t / N, k = t - i * N;
+            vv[u] = {T(0), T(0)};
+            uu[u] = {T(0), T(0)};
+            tb[u] = T(0);
+            if (t < nb * N && k <= Kl) {
+                const cx<T>* Vb = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(V) + (size_t)(b0 + i) * ws_img);
+                vv[u] = Vb[(size_t)l * d.Kp + k];
+                tb[u] = d.Tb[(size_t)l * d.Kp + k];
+                if (l < d.lcorr && k <= d.klow) {
+                    const cx<T>* Ub = reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(Ulow) + (size_t)(b0 + i) * ws_img);
+                    uu[u] = Ub[(size_t)l * (d.klow + 1) + k];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RING_CH; ++u) {
+            const int t = t0 + u * NT + threadIdx.x, i = t / N, k = t - i * N;
+            if (t >= nb * N) continue;
             cx<T> v = {T(0), T(0)};
             if (k <= Kl) {
-                v = mul_ipow(Vb[(size_t)l * d.Kp + k] * d.Tb[(size_t)l * d.Kp + k], (4 - (k & 3)) & 3);
-                if (l < d.lcorr && k <= d.klow) v = v + Ub[(size_t)l * (d.klow + 1) + k] * invN;
+                v = mul_ipow(vv[u] * tb[u], (4 - (k & 3)) & 3);
+                if (l < d.lcorr && k <= d.klow) v = v + uu[u] * invN;
             }
-            buf[lds_phys<RING_PAD<T>>(bo + (k))] = v;
+            buf[lds_phys<RING_PAD<T>>(i * N + k)] = v;
         }
     }
     __syncthreads();
     ring_fft(d, l, buf, N, logN, nb, true);
     const int off = d.ringOff[l];
-    for (int si = threadIdx.x; si < N / 2; si += blockDim.x) {
-        const int s = si - N / 4;
-        T x, y;
-        point_xy(d, off + si, x, y);
-        const cx<T> ph = conjg(point_phase(d, x, y));
-        const size_t k = d.binned ? (size_t)d.ringBin[off + si] : (size_t)(off + si);
-        cx<T>* dst = Pol + k * B + b0;
-        // transpose of the conjugate-symmetric fill, then of the point phase
-        auto sample = [&](int i) {
-            const int bo = i * N;
-            const cx<T> a = buf[lds_phys<RING_PAD<T>>(bo + (s < 0 ? s + N : s))];
-            const cx<T> c = buf[lds_phys<RING_PAD<T>>(bo + s + N / 2)];
-            return cmul(a + conjg(c), ph);
-        };
-        int i = 0;
-        if constexpr (sizeof(T) == 4) {
-            // FP32 pairs of images as one 16-byte store (the bin-order slots
-            // scatter the samples: one store instruction per pair, not two)
-            if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0)
-                for (; i + 1 < nb; i += 2) {
-                    const cx<T> u = sample(i), w = sample(i + 1);
-                    *reinterpret_cast<float4*>(dst + i) = make_float4(u.x, u.y, w.x, w.y);
-                }
+    for (int si0 = 0; si0 < N / 2; si0 += RING_CH * NT) {
+        // the chunk's positions and destination slots, loaded together before its stores
+        cx<T> pq[RING_CH];
+        size_t kq[RING_CH];
+#pragma unroll
+        for (int u = 0; u < RING_CH; ++u) {
+            const int si = si0 + u * NT + threadIdx.x;
+            pq[u] = {T(0), T(0)};
+            kq[u] = 0;
+            if (si < N / 2) {
+                pq[u] = d.pos[off + si];
+                kq[u] = d.binned ? (size_t)d.ringBin[off + si] : (size_t)(off + si);
+            }
         }
-        for (; i < nb; ++i) dst[i] = sample(i);
+#pragma unroll
+        for (int u = 0; u < RING_CH; ++u) {
+            const int si = si0 + u * NT + threadIdx.x;
+            if (si >= N / 2) continue;
+            const int s = si - N / 4;
+            const cx<T> ph = conjg(point_phase(d, pq[u].x, pq[u].y));
+            cx<T>* dst = Pol + kq[u] * B + b0;
+            // transpose of the conjugate-symmetric fill, then of the point phase
+            auto sample = [&](int i) {
+                const int bo = i * N;
+                const cx<T> a = buf[lds_phys<RING_PAD<T>>(bo + (s < 0 ? s + N : s))];
+                const cx<T> c = buf[lds_phys<RING_PAD<T>>(bo + s + N / 2)];
+                return cmul(a + conjg(c), ph);
+            };
+            int i = 0;
+            if constexpr (sizeof(T) == 4) {
+                // FP32 pairs of images as one 16-byte store (the bin-order slots
+                // scatter the samples: one store instruction per pair, not two)
+                if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0)
+                    for (; i + 1 < nb; i += 2) {
+                        const cx<T> v0 = sample(i), v1 = sample(i + 1);
+                        *reinterpret_cast<float4*>(dst + i) = make_float4(v0.x, v0.y, v1.x, v1.y);
+                    }
+            }
+            for (; i < nb; ++i) dst[i] = sample(i);
+        }
     }
 }
 
