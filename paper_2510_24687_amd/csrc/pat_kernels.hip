@@ -200,6 +200,23 @@ __device__ __noinline__ void stockham_pass(PAT_LDS cx<T>* buf, int logN, int log
     const int lnbf = logN - LR;
     const int nbf = f3 ? 3 << lnbf : 1 << lnbf;
     const int total = nb * nbf;
+    const int sh = logNmax - logNs - LR;
+    // without the full table: the entries W^1, W^2, W^4, W^8 of the thread's
+    // butterflies, loaded before the LDS reads (their latency overlaps those
+    // and the barrier)
+    cx<T> wp[BPT][LR];
+    if (logNs > 0 && !twtab) {
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) {
+            const int it = threadIdx.x + u * NT;
+            if (it < total) {
+                const int b = f3 ? (it >> lnbf) / 3 : it >> lnbf, t = it - b * nbf;
+                const int k = t & ((1 << logNs) - 1);
+#pragma unroll
+                for (int e = 0; e < LR; ++e) wp[u][e] = ld_glb(tw + ((k << e) << sh));
+            }
+        }
+    }
     cx<T> v[BPT][R];
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
@@ -219,7 +236,6 @@ __device__ __noinline__ void stockham_pass(PAT_LDS cx<T>* buf, int logN, int log
             const int b = f3 ? (it >> lnbf) / 3 : it >> lnbf, t = it - b * nbf;
             const int k = t & ((1 << logNs) - 1);
             if (logNs > 0) {
-                const int sh = logNmax - logNs - LR;
                 if (twtab) {
                     // W^r read from the table for every r
 #pragma unroll
@@ -231,12 +247,9 @@ __device__ __noinline__ void stockham_pass(PAT_LDS cx<T>* buf, int logN, int log
                 } else {
                     // W^r for r = 1..R-1 from the table entries W^1, W^2, W^4, W^8 (at
                     // most three products each): fewer table reads, more arithmetic
-                    cx<T> wp[LR];
 #pragma unroll
-                    for (int e = 0; e < LR; ++e) {
-                        wp[e] = ld_glb(tw + ((k << e) << sh));
-                        if (inv) wp[e].y = -wp[e].y;
-                    }
+                    for (int e = 0; e < LR; ++e)
+                        if (inv) wp[u][e].y = -wp[u][e].y;
 #pragma unroll
                     for (int r = 1; r < R; ++r) {
                         cx<T> w = {T(1), T(0)};
@@ -244,7 +257,7 @@ __device__ __noinline__ void stockham_pass(PAT_LDS cx<T>* buf, int logN, int log
 #pragma unroll
                         for (int e = 0; e < LR; ++e) {
                             if (r & (1 << e)) {
-                                w = first ? wp[e] : cmul(w, wp[e]);
+                                w = first ? wp[u][e] : cmul(w, wp[u][e]);
                                 first = false;
                             }
                         }
@@ -294,6 +307,17 @@ __device__ __noinline__ void stockham_pass3(PAT_LDS cx<T>* buf, int logN2, int n
     const int nbf = 1 << logN2;
     const int total = nb << logN2;
     const T h3 = T(0.86602540378443864676);  // sqrt(3)/2
+    // twiddles first (their latency overlaps the LDS reads and the barrier)
+    cx<T> w1s[BPT], w2s[BPT];
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int it = threadIdx.x + u * NT;
+        if (it < total) {
+            const int t = it & (nbf - 1);
+            w1s[u] = ld_glb(twd + ((2 * t) << tsh));
+            w2s[u] = ld_glb(twd + ((4 * t) << tsh));
+        }
+    }
     cx<T> v[BPT][3];
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
@@ -311,7 +335,7 @@ __device__ __noinline__ void stockham_pass3(PAT_LDS cx<T>* buf, int logN2, int n
         const int it = threadIdx.x + u * NT;
         if (it < total) {
             const int b = it >> logN2, t = it & (nbf - 1);
-            cx<T> w1 = ld_glb(twd + ((2 * t) << tsh)), w2 = ld_glb(twd + ((4 * t) << tsh));
+            cx<T> w1 = w1s[u], w2 = w2s[u];
             if (inv) { w1.y = -w1.y; w2.y = -w2.y; }
             const cx<T> a0 = v[u][0], a1 = cmul(v[u][1], w1), a2 = cmul(v[u][2], w2);
             const cx<T> sm = a1 + a2, df = a1 - a2;
