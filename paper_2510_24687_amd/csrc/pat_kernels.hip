@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <memory>
 #include <new>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -377,6 +378,15 @@ __device__ __forceinline__ void xcd_remap(int lin, int nx, int total, int& bx, i
     bx = logical % nx;
     by = logical / nx;
 }
+// Block lin of a table-driven launch over nz image groups: entry
+// (lin / (NUM_XCD nz)) NUM_XCD + lin mod NUM_XCD of the table (so that the
+// entry's XCD is the block's), image group (lin / NUM_XCD) mod nz.
+__host__ __device__ inline void table_block(int lin, int nz, int& entry, int& z)
+{
+    entry = (lin / (NUM_XCD * nz)) * NUM_XCD + lin % NUM_XCD;
+    z = (lin / NUM_XCD) % nz;
+}
+
 __device__ __forceinline__ void xcd_block(int& bx, int& by)
 {
     xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x, gridDim.x * gridDim.y, bx, by);
@@ -420,6 +430,7 @@ template <typename T>
 struct Dev {
     int n, m, nt, mf, logmf;
     int Ng, logNg, w, hw, Rw, Ew;
+    int Ep;                     // row pitch of E in cells: Ew rounded up to 16 (128-byte rows of tiles)
     int M, log2M, L, K, Kp, klow, lcorr, npts;
     int logNmax;
     int colsCW, dctCW;
@@ -679,10 +690,10 @@ __device__ __forceinline__ void cols_fwd_body(const Dev<T>& d, Blk bk, const cx<
         int gx = x0 + c;
         if (gx >= d.Rw) continue;
         cx<T> v = buf[c * Ng + gy];
-        Eb[(size_t)gy * d.Ew + gx + d.hw] = v;
+        Eb[(size_t)gy * d.Ep + gx + d.hw] = v;
         int gym = (Ng - gy) & (Ng - 1);
-        if (gx >= 1 && gx <= d.hw) Eb[(size_t)gym * d.Ew + d.hw - gx] = conjg(v);
-        if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) Eb[(size_t)gym * d.Ew + d.hw + Ng - gx] = conjg(v);
+        if (gx >= 1 && gx <= d.hw) Eb[(size_t)gym * d.Ep + d.hw - gx] = conjg(v);
+        if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) Eb[(size_t)gym * d.Ep + d.hw + Ng - gx] = conjg(v);
     }
 }
 
@@ -767,7 +778,7 @@ __device__ __forceinline__ void ring_fwd_body(const Dev<T>& d, Blk bk, const cx<
             cx<T> acc = {T(0), T(0)};
 #pragma unroll
             for (int jy = 0; jy < WMAX; ++jy) {
-                const cx<T>* row = Eb + (size_t)((tp.gy0 + jy) & mask) * d.Ew + tp.gx0 + d.hw;
+                const cx<T>* row = Eb + (size_t)((tp.gy0 + jy) & mask) * d.Ep + tp.gx0 + d.hw;
                 cx<T> racc = {T(0), T(0)};
 #pragma unroll
                 for (int jx = 0; jx < WMAX; ++jx) racc = racc + row[jx] * tp.wx[jx];
@@ -871,12 +882,12 @@ __device__ __forceinline__ void gather_bins_body(const Dev<float>& d, Blk bk, co
             const int k = 2 * m;
             if (k < nb) {
                 const cx<float> v = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(E) +
-                                                                     (size_t)(b0 + k) * ws_img)[(size_t)gy * Ew + ex];
+                                                                     (size_t)(b0 + k) * ws_img)[(size_t)gy * d.Ep + ex];
                 xs[it].x = v.x; xs[it].y = v.y;
             }
             if (k + 1 < nb) {
                 const cx<float> v = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(E) +
-                                                                     (size_t)(b0 + k + 1) * ws_img)[(size_t)gy * Ew + ex];
+                                                                     (size_t)(b0 + k + 1) * ws_img)[(size_t)gy * d.Ep + ex];
                 xs[it].z = v.x; xs[it].w = v.y;
             }
         }
@@ -950,15 +961,18 @@ __device__ __forceinline__ void gather_bins_body(const Dev<float>& d, Blk bk, co
     }
 }
 
-// Block lin does tile gbOrder[lin / nz] (tx | ty << 12; tiles longest first
-// by a cost estimate, see gather_order) for image group lin mod nz.
+// Block lin does the tile of table entry and image group table_block(lin)
+// (gbOrder: tx | ty << 12, per XCD a contiguous run of tiles taken longest
+// first by a cost estimate, see gather_order and xcd_table; -1: nothing).
 template <int BC>
 __global__ __launch_bounds__(NT, 4) void gather_bins(Dev<float> d, const cx<float>* E, cx<float>* Pout, int B, int G,
                                                      size_t ws_img, int nz)
 {
-    const int lin = blockIdx.x;
-    const int t = d.gbOrder[lin / nz];
-    gather_bins_body<BC>(d, Blk{t & 0xfff, t >> 12, lin % nz, 0}, E, Pout, B, G, ws_img);
+    int entry, z;
+    table_block(blockIdx.x, nz, entry, z);
+    const int t = d.gbOrder[entry];
+    if (t < 0) return;  // padding of a shorter XCD list
+    gather_bins_body<BC>(d, Blk{t & 0xfff, t >> 12, z, 0}, E, Pout, B, G, ws_img);
 }
 
 // Sum over aligned groups of W consecutive lanes (W a power of two <= 64),
@@ -1751,10 +1765,10 @@ __device__ __forceinline__ void cols_fwd_w_body(const Dev<float>& d, Blk bk, con
         const int gx = x0 + c;
         if (gx >= d.Rw) continue;
         const cx<float> v = ld_lds(lbuf + c * CP + dw_phys(gy));
-        Eb[(size_t)gy * d.Ew + gx + d.hw] = v;
+        Eb[(size_t)gy * d.Ep + gx + d.hw] = v;
         const int gym = (Ng - gy) & (Ng - 1);
-        if (gx >= 1 && gx <= d.hw) Eb[(size_t)gym * d.Ew + d.hw - gx] = conjg(v);
-        if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) Eb[(size_t)gym * d.Ew + d.hw + Ng - gx] = conjg(v);
+        if (gx >= 1 && gx <= d.hw) Eb[(size_t)gym * d.Ep + d.hw - gx] = conjg(v);
+        if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) Eb[(size_t)gym * d.Ep + d.hw + Ng - gx] = conjg(v);
     }
 }
 
@@ -1774,10 +1788,10 @@ __device__ __forceinline__ void cols_adj_w_body(const Dev<float>& d, Blk bk, con
         const int gx = x0 + c;
         cx<float> v = {0.f, 0.f};
         if (gx < d.Rw) {
-            v = Eb[(size_t)gy * d.Ew + gx + d.hw];
+            v = Eb[(size_t)gy * d.Ep + gx + d.hw];
             const int gym = (Ng - gy) & (Ng - 1);
-            if (gx >= 1 && gx <= d.hw) v = v + conjg(Eb[(size_t)gym * d.Ew + d.hw - gx]);
-            if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) v = v + conjg(Eb[(size_t)gym * d.Ew + d.hw + Ng - gx]);
+            if (gx >= 1 && gx <= d.hw) v = v + conjg(Eb[(size_t)gym * d.Ep + d.hw - gx]);
+            if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) v = v + conjg(Eb[(size_t)gym * d.Ep + d.hw + Ng - gx]);
         }
         st_lds(lbuf + c * CP + dw_phys(gy), v);
     }
@@ -2417,7 +2431,7 @@ __device__ __forceinline__ void spread_tiles_body(const Dev<T>& d, Blk bk, const
         for (int k = 0; k < BC; ++k)
             if (k < nb) {
                 cx<T>* Eb = reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(E) + (size_t)(b0 + k) * ws_img);
-                Eb[(size_t)gy * d.Ew + e] = acc[k];
+                Eb[(size_t)gy * d.Ep + e] = acc[k];
             }
     }
 }
@@ -2625,26 +2639,29 @@ __device__ __forceinline__ void spread_bins_body(const Dev<float>& d, Blk bk, in
                 const int k = 2 * m + h;
                 if (k < nb) {
                     cx<float>* Eb = reinterpret_cast<cx<float>*>(reinterpret_cast<char*>(E) + (size_t)(b0 + k) * ws_img);
-                    Eb[(size_t)gy * Ew + e] = lo2[h];
+                    Eb[(size_t)gy * d.Ep + e] = lo2[h];
                 }
             }
         }
     }
 }
 
-// Dispatch order: block lin does entry lin / nz of the plan's table spOrder
-// (tx | ty << 12 | quadrant << 24 | split << 26, see spread_order) for image
-// group lin mod nz.  The table lists the tiles longest first by a cost
-// estimate, so that the last blocks to start are short ones, and a tile whose
-// estimate alone would exceed the balanced share of a block slot appears as
-// its four split quadrants.
+// Dispatch order: block lin does the tile of table entry and image group
+// table_block(lin) of the plan's table spOrder (tx | ty << 12 | quadrant << 24
+// | split << 26; -1: nothing).  Per XCD the table holds a contiguous run of
+// tiles (their halos shared through its L2) taken longest first by a cost
+// estimate, so that the last blocks to start are short ones; a tile that
+// would end after the balanced share of a block slot appears as its four
+// split quadrants (spread_order, xcd_table).
 template <int BC>
 __global__ __launch_bounds__(NT) void spread_bins(Dev<float> d, const cx<float>* Pol, int B, cx<float>* E, size_t ws_img,
                                                   int nz)
 {
-    const int lin = blockIdx.x;
-    const int t = d.spOrder[lin / nz];
-    const Blk bk = {t & 0xfff, (t >> 12) & 0xfff, lin % nz, 0};
+    int entry, z;
+    table_block(blockIdx.x, nz, entry, z);
+    const int t = d.spOrder[entry];
+    if (t < 0) return;  // padding of a shorter XCD list
+    const Blk bk = {t & 0xfff, (t >> 12) & 0xfff, z, 0};
     if (t >> 26) spread_bins_body<BC, SB_TILE / 2>(d, bk, (t >> 24) & 3, Pol, B, E, ws_img);
     else spread_bins_body<BC, SB_TILE>(d, bk, 0, Pol, B, E, ws_img);
 }
@@ -2666,10 +2683,10 @@ __device__ __forceinline__ void cols_adj_body(const Dev<T>& d, Blk bk, const cx<
         int gx = x0 + c;
         cx<T> v = {T(0), T(0)};
         if (gx < d.Rw) {
-            v = Eb[(size_t)gy * d.Ew + gx + d.hw];
+            v = Eb[(size_t)gy * d.Ep + gx + d.hw];
             int gym = (Ng - gy) & (Ng - 1);
-            if (gx >= 1 && gx <= d.hw) v = v + conjg(Eb[(size_t)gym * d.Ew + d.hw - gx]);
-            if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) v = v + conjg(Eb[(size_t)gym * d.Ew + d.hw + Ng - gx]);
+            if (gx >= 1 && gx <= d.hw) v = v + conjg(Eb[(size_t)gym * d.Ep + d.hw - gx]);
+            if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) v = v + conjg(Eb[(size_t)gym * d.Ep + d.hw + Ng - gx]);
         }
         buf[c * Ng + gy] = v;
     }
@@ -2893,6 +2910,10 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Row pitch of E in cells: the extended width Ew rounded up to 16, so that a
+// tile's row of 16 cells is whole cache lines.
+int e_pitch(const pat::Params& P) { return (P.Ew + 15) / 16 * 16; }
+
 constexpr size_t SPREAD_PAD = 16;  // >= the spread's image group BC
 
 void layout(pat_plan_s* p)
@@ -2901,7 +2922,7 @@ void layout(pat_plan_s* p)
     size_t cs = (P.dt == PAT_F64) ? 16 : 8;
     size_t o = 0;
     p->offR = o; o = align256(o + cs * (size_t)P.n * P.Rw);
-    p->offE = o; o = align256(o + cs * (size_t)P.Ng * P.Ew);
+    p->offE = o; o = align256(o + cs * (size_t)P.Ng * e_pitch(P));
     p->offV = o; o = align256(o + cs * (size_t)P.L * P.Kp);
     p->offG = o; o = align256(o + cs * (size_t)P.nt * P.Kp);
     p->offU = o; o = align256(o + cs * (size_t)P.lcorr * (P.klow + 1));
@@ -3104,16 +3125,74 @@ int lds_dct(const pat::Params& P)
     return cw;
 }
 
-// Dispatch table of spread_bins over the 16 x 16 cell tiles of the Ng x Ew
-// grid (bin table `start`).  A tile's cost is estimated as 53 + S + 2.9 wmax,
-// S the samples its bin rows stage and wmax the longest walk of its four
-// waves (per wave, the sum over the w bin rows of the longest run among its
-// 64 cells): the proportions of a least-squares fit of measured block
-// durations.  Tiles are listed by decreasing cost; one whose cost exceeds
-// 0.8 times the balanced share of a block slot, sum(cost) / slots, is listed
-// as its four quadrants instead (cost / 4 x 1.4 each).  Entries:
-// tx | ty << 12 | quadrant << 24 | split << 26.  Empty if a tile index does
-// not fit its field.
+// Dispatch table of a tiled kernel from its tiles' estimated costs (in
+// row-major tile order).  The hardware deals consecutive workgroups to the
+// NUM_XCD XCDs in turn, so the table holds one list per XCD, interleaved:
+// entry j * NUM_XCD + x is the j-th tile of XCD x.  Each XCD receives one
+// contiguous run of the row-major order (runs of equal total cost), so that
+// neighbouring tiles, which stage the same halo, read it through one L2.
+// Within its list an XCD takes its tiles by decreasing cost, dispatched in a
+// simulation of its `slots` concurrent blocks to the slot that frees first;
+// with `split` set, a tile that would end after split_at times the balanced
+// share of a slot is listed as its four quadrants instead (cost / 4 x 1.2
+// each).  Lists are padded to equal length with -1 (an empty block).
+// Entries: tx | ty << 12 | quadrant << 24 | split << 26.
+std::vector<int> xcd_table(const std::vector<std::pair<double, int>>& tiles, int slots, bool split, double split_at)
+{
+    double total = 0;
+    for (const auto& t : tiles) total += t.first;
+    std::vector<std::vector<int>> lists(NUM_XCD);
+    size_t next = 0;
+    double done = 0;
+    for (int x = 0; x < NUM_XCD; ++x) {
+        // this XCD's run: tiles until the cumulative cost reaches (x + 1) / NUM_XCD of the total
+        std::vector<std::pair<double, int>> mine;
+        const double upto = total * (x + 1) / NUM_XCD;
+        while (next < tiles.size() && (x == NUM_XCD - 1 || done + 0.5 * tiles[next].first <= upto)) {
+            done += tiles[next].first;
+            mine.push_back(tiles[next++]);
+        }
+        std::sort(mine.begin(), mine.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+            return a.first != b.first ? a.first > b.first : a.second < b.second;
+        });
+        double part = 0;
+        for (const auto& t : mine) part += t.first;
+        const double limit = split_at * part / std::max(slots, 1);
+        std::priority_queue<double, std::vector<double>, std::greater<double>> slot_free;
+        for (int k = 0; k < std::max(slots, 1); ++k) slot_free.push(0.0);
+        auto dispatch = [&](double c) {
+            const double t = slot_free.top();
+            slot_free.pop();
+            slot_free.push(t + c);
+        };
+        for (const auto& t : mine) {
+            if (split && slot_free.top() + t.first > limit) {
+                for (int qd = 0; qd < 4; ++qd) {
+                    lists[x].push_back(t.second | qd << 24 | 1 << 26);
+                    dispatch(t.first / 4 * 1.2);
+                }
+            } else {
+                lists[x].push_back(t.second);
+                dispatch(t.first);
+            }
+        }
+    }
+    size_t len = 0;
+    for (const auto& l : lists) len = std::max(len, l.size());
+    std::vector<int> table(len * NUM_XCD, -1);
+    for (int x = 0; x < NUM_XCD; ++x)
+        for (size_t k = 0; k < lists[x].size(); ++k) table[k * NUM_XCD + x] = lists[x][k];
+    return table;
+}
+
+// spread_bins over the 16 x 16 cell tiles of the Ng x Ew grid (bin table
+// `start`): a tile's cost is estimated as 53 + S + 2.9 wmax, S the samples
+// its bin rows stage and wmax the longest walk of its four waves (per wave,
+// the sum over the w bin rows of the longest run among its 64 cells), the
+// proportions of a least-squares fit of measured block durations; heavy
+// tiles and the tiles of the last round are split (xcd_table).  Empty if a
+// tile index does not fit its field.
+constexpr double SPREAD_SPLIT = 1.1;
 std::vector<int> spread_order(const pat::Params& P, const std::vector<int>& start, int slots)
 {
     const int W = P.w, Ng = P.Ng, Ew = P.Ew, mask = Ng - 1, TS = 16;
@@ -3124,8 +3203,7 @@ std::vector<int> spread_order(const pat::Params& P, const std::vector<int>& star
         hi = std::min(hi, Ew - 1);
         return hi < lo ? 0 : start[(size_t)row * Ew + hi + 1] - start[(size_t)row * Ew + lo];
     };
-    std::vector<double> cost((size_t)nx * ny);
-    double total = 0;
+    std::vector<std::pair<double, int>> tiles;
     for (int ty = 0; ty < ny; ++ty)
         for (int tx = 0; tx < nx; ++tx) {
             double S = 0, wmax = 0;
@@ -3144,53 +3222,30 @@ std::vector<int> spread_order(const pat::Params& P, const std::vector<int>& star
                 }
                 wmax = std::max(wmax, steps);
             }
-            cost[(size_t)ty * nx + tx] = 53.0 + S + 2.9 * wmax;
-            total += cost[(size_t)ty * nx + tx];
+            tiles.push_back({53.0 + S + 2.9 * wmax, tx | ty << 12});
         }
-    const double split = 0.8 * total / std::max(slots, 1);
-    std::vector<std::pair<double, int>> items;
-    for (int ty = 0; ty < ny; ++ty)
-        for (int tx = 0; tx < nx; ++tx) {
-            const double c = cost[(size_t)ty * nx + tx];
-            const int enc = tx | ty << 12;
-            if (c > split)
-                for (int qd = 0; qd < 4; ++qd) items.push_back({c / 4 * 1.4, enc | qd << 24 | 1 << 26});
-            else
-                items.push_back({c, enc});
-        }
-    std::sort(items.begin(), items.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
-        return a.first != b.first ? a.first > b.first : a.second < b.second;
-    });
-    std::vector<int> order(items.size());
-    for (size_t i = 0; i < items.size(); ++i) order[i] = items[i].second;
-    return order;
+    return xcd_table(tiles, slots / NUM_XCD, true, SPREAD_SPLIT);
 }
 
-// Dispatch table of gather_bins over its 16 x 16 bin tiles: a tile's cost is
-// estimated as 675 + S + 573 ceil(S / NT), S the samples of its bins (one
-// thread per sample, in rounds of NT), the proportions of a least-squares fit
-// of measured block durations; tiles longest first.  Entries tx | ty << 12;
-// empty if a tile index does not fit its field.
-std::vector<int> gather_order(const pat::Params& P, const std::vector<int>& start)
+// gather_bins over its 16 x 16 bin tiles: a tile's cost is estimated as
+// 675 + S + 573 ceil(S / NT), S the samples of its bins (one thread per
+// sample, in rounds of NT), the proportions of a least-squares fit of
+// measured block durations.  Entries tx | ty << 12 (xcd_table, no splits).
+std::vector<int> gather_order(const pat::Params& P, const std::vector<int>& start, int slots)
 {
     const int Ng = P.Ng, Ew = P.Ew, TS = 16;
     const int nx = (Ew + TS - 1) / TS, ny = Ng / TS;
     if (nx >= 4096 || ny >= 4096 || ny * TS != Ng) return {};
-    std::vector<std::pair<double, int>> items;
+    std::vector<std::pair<double, int>> tiles;
     for (int ty = 0; ty < ny; ++ty)
         for (int tx = 0; tx < nx; ++tx) {
             const int e1 = std::min(tx * TS + TS, Ew);
             double S = 0;
             for (int row = ty * TS; row < ty * TS + TS; ++row)
                 S += start[(size_t)row * Ew + e1] - start[(size_t)row * Ew + tx * TS];
-            items.push_back({675.0 + S + 573.0 * std::ceil(S / NT), tx | ty << 12});
+            tiles.push_back({675.0 + S + 573.0 * std::ceil(S / NT), tx | ty << 12});
         }
-    std::sort(items.begin(), items.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
-        return a.first != b.first ? a.first > b.first : a.second < b.second;
-    });
-    std::vector<int> order(items.size());
-    for (size_t i = 0; i < items.size(); ++i) order[i] = items[i].second;
-    return order;
+    return xcd_table(tiles, slots / NUM_XCD, false, 0.0);
 }
 
 template <typename T>
@@ -3283,11 +3338,11 @@ int upload(pat_plan_s* p, Dev<T>& d)
             if ((rc = put(rbin.data(), rbin.size() * sizeof(int), (const void**)&d.ringBin))) return rc;
             if ((rc = put(start.data(), start.size() * sizeof(int), (const void**)&d.binStart))) return rc;
             if ((rc = put(bpos.data(), bpos.size() * sizeof(T), (const void**)&d.binPos))) return rc;
-            // four spread_bins blocks fit a CU's LDS at once
+            // four blocks of spread_bins (and of gather_bins) fit a CU's LDS at once
             int ncu = 0;
             if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || ncu < 1)
                 ncu = 256;
-            const std::vector<int> order = spread_order(P, start, 4 * ncu), gorder = gather_order(P, start);
+            const std::vector<int> order = spread_order(P, start, 4 * ncu), gorder = gather_order(P, start, 4 * ncu);
             if (!order.empty() && !gorder.empty()) {
                 if ((rc = put(order.data(), order.size() * sizeof(int), (const void**)&d.spOrder))) return rc;
                 if ((rc = put(gorder.data(), gorder.size() * sizeof(int), (const void**)&d.gbOrder))) return rc;
@@ -3303,7 +3358,7 @@ int upload(pat_plan_s* p, Dev<T>& d)
     if ((rc = put(Tbi.data(), Tbi.size() * sizeof(T), (const void**)&d.Tbi))) return rc;
     if ((rc = put(MkiT.data(), MkiT.size() * sizeof(T), (const void**)&d.MkiT))) return rc;
     d.n = P.n; d.m = P.m; d.nt = P.nt; d.mf = P.mf; d.mf3 = P.mf3; d.logmf = ilog2i(P.mf3 ? P.mf / 3 : P.mf);
-    d.Ng = P.Ng; d.logNg = ilog2i(P.Ng); d.w = P.w; d.hw = P.hw; d.Rw = P.Rw; d.Ew = P.Ew;
+    d.Ng = P.Ng; d.logNg = ilog2i(P.Ng); d.w = P.w; d.hw = P.hw; d.Rw = P.Rw; d.Ew = P.Ew; d.Ep = e_pitch(P);
     d.M = P.M; d.m3 = P.m3; d.log2M = ilog2i(P.m3 ? P.M / 3 : P.M); d.L = P.L; d.K = P.K; d.Kp = P.Kp; d.klow = P.klow; d.lcorr = P.lcorr;
     d.npts = P.npts; d.logNmax = ilog2i(P.Nmax);
     d.colsCW = p->cols_cw;
@@ -3713,8 +3768,11 @@ __global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
     if constexpr (S == STAGE_GATHER) {
         // entry local / nz of the plan's dispatch table, as the single-plan launch
         if constexpr (sizeof(T) == 4) {
-            const int t = q.d.gbOrder[local / nz];
-            gather_bins_body<GB_BC>(q.d, Blk{t & 0xfff, t >> 12, local % nz, 0}, E, Pol, q.B, q.G, q.wi);
+            int entry, z;
+            table_block(local, nz, entry, z);
+            const int t = q.d.gbOrder[entry];
+            if (t < 0) return;
+            gather_bins_body<GB_BC>(q.d, Blk{t & 0xfff, t >> 12, z, 0}, E, Pol, q.B, q.G, q.wi);
         }
     }
     if constexpr (S == PAT_STAGE_RING_FWD) ring_fwd_body<T, WMAX>(q.d, bk, E, q.d.binned ? Pol : nullptr, V, U, q.wi, q.B, q.G);
@@ -3742,8 +3800,11 @@ __global__ __launch_bounds__(NT) void grouped_stage(GroupArgs<T> ga)
             if (q.d.binned) {
                 // entry local / nz of the plan's dispatch table for image group
                 // local mod nz, as the single-plan launch
-                const int t = q.d.spOrder[local / nz];
-                const Blk tb = {t & 0xfff, (t >> 12) & 0xfff, local % nz, 0};
+                int entry, z;
+                table_block(local, nz, entry, z);
+                const int t = q.d.spOrder[entry];
+                if (t < 0) return;
+                const Blk tb = {t & 0xfff, (t >> 12) & 0xfff, z, 0};
                 if (t >> 26) spread_bins_body<BC, SB_TILE / 2>(q.d, tb, (t >> 24) & 3, Pol, q.B, E, q.wi);
                 else spread_bins_body<BC, SB_TILE>(q.d, tb, 0, Pol, q.B, E, q.wi);
                 return;
