@@ -107,6 +107,12 @@ def measured_traffic(kernel: str, B: int, shapes: dict = None):
                 "cols_adj": ("tune_cols_per_block", "tune_wave_fft"),
                 "rows_fwd": ("tune_wave_fft",), "rows_adj": ("tune_wave_fft",),
                 "synth_fwd": ("tune_wave_fft",), "synth_adj": ("tune_wave_fft",)}.get(kernel, ())
+    # the wave forms fix their own blocks: the wave cosine transform ignores the
+    # columns per block of dct_cols, the wave column FFTs those of cols_fwd / cols_adj
+    if shapes is not None and shapes.get("tune_dct_wave") == 1:
+        relevant = tuple(k for k in relevant if k != "tune_dct_cols_per_block")
+    if shapes is not None and shapes.get("tune_wave_fft") == 1:
+        relevant = tuple(k for k in relevant if k != "tune_cols_per_block")
     recorded = z.get("launch_shapes")
     if shapes is not None and recorded is not None and any(recorded.get(k) != shapes.get(k) for k in relevant):
         return None
