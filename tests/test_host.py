@@ -198,6 +198,9 @@ def test_bench_byte_model_and_traffic_record():
     t = bench.measured_traffic("dct_fwd", 16, shapes)
     assert 0.95 * per["dct_fwd"] <= t <= 1.05 * per["dct_fwd"]               # no re-reads
     shapes["tune_dct_cols_per_block"] += 1
+    # the wave cosine transform fixes its own columns per block
+    assert (bench.measured_traffic("dct_fwd", 16, shapes) is None) == (shapes["tune_dct_wave"] != 1)
+    shapes["tune_dct_wave"] = 1 - shapes["tune_dct_wave"]
     assert bench.measured_traffic("dct_fwd", 16, shapes) is None            # other launch shape
     assert bench.measured_traffic("rows_fwd", 16, shapes) is not None       # shape irrelevant to it
 
