@@ -139,8 +139,9 @@ typedef struct {
  * line wins); if absent it times the candidate launch shapes (FFT pass radix,
  * twiddle source, columns per transform block, images per ring-gather block
  * and per spread group, spread sample staging, the wave-per-column cosine
- * transform) one choice at a time with forward + adjoint at max_batch, keeps the
- * fastest, and appends a line.  A missing or unreadable file is treated as
+ * transform) one choice at a time with forward + adjoint at max_batch (after
+ * one discarded run, 8 timed pairs per candidate), keeps a candidate only if
+ * it is more than 1 % faster than the current choice, and appends a line.  A missing or unreadable file is treated as
  * empty; a line that fails validation is ignored.  The search allocates and
  * frees a temporary workspace.
  * Synchronises the current device.  Returns PAT_OK and *out, or an error
