@@ -447,7 +447,6 @@ struct Dev {
     int tw_table;               // 1: FFT passes read every twiddle from the table
     T beta, shift, half;        // half = Ng / (2 Lambda): grid cells per unit lambda
     T beta_l2e;                 // beta * log2(e)
-    T phase_k;                  // -shift * h / half: point phase per grid cell of x + y
     T lamh;                     // h: u = lambda h cos(phi)
     T dlam, pre_scale, adj_scale;
     double mask_r2, a, h;       // mask test in double (same decision as the oracle)
@@ -470,6 +469,9 @@ struct Dev {
     int mf3;                    // 1: mf = 3 * 2^logmf
     const cx<T>* twm;           // 2 mf: e^{-2 pi i j/(2 mf)} (angular-transform twiddles)
     const cx<T>* pos;           // npts: grid position (x, y) of each half-ring sample
+    const cx<T>* ph;            // npts: its point phase e^{-i shift h (x + y) / half}, evaluated in
+                                // FP64 (the adjoint's table; the gathers evaluate point_phase)
+    T phase_k;                  // -shift * h / half: point phase per grid cell of x + y
     // bin order of the FP32 spread (spread_bins): samples sorted by the cell of
     // their first tap, (gy0 mod Ng) * Ew + gx0 + hw, ring order within a bin
     const int* binRing;         // npts: ring-order index of the sample in each bin-order slot
@@ -2194,16 +2196,16 @@ __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<
     ring_fft(d, l, buf, N, logN, nb, true);
     const int off = d.ringOff[l];
     for (int si0 = 0; si0 < N / 2; si0 += RING_CH * NT) {
-        // the chunk's positions and destination slots, loaded together before its stores
-        cx<T> pq[RING_CH];
+        // the chunk's point phases and destination slots, loaded together before its stores
+        cx<T> phq[RING_CH];
         size_t kq[RING_CH];
 #pragma unroll
         for (int u = 0; u < RING_CH; ++u) {
             const int si = si0 + u * NT + threadIdx.x;
-            pq[u] = {T(0), T(0)};
+            phq[u] = {T(0), T(0)};
             kq[u] = 0;
             if (si < N / 2) {
-                pq[u] = d.pos[off + si];
+                phq[u] = d.ph[off + si];
                 kq[u] = d.binned ? (size_t)d.ringBin[off + si] : (size_t)(off + si);
             }
         }
@@ -2212,7 +2214,7 @@ __device__ __forceinline__ void ring_adj_body(const Dev<T>& d, Blk bk, const cx<
             const int si = si0 + u * NT + threadIdx.x;
             if (si >= N / 2) continue;
             const int s = si - N / 4;
-            const cx<T> ph = conjg(point_phase(d, pq[u].x, pq[u].y));
+            const cx<T> ph = conjg(phq[u]);
             cx<T>* dst = Pol + kq[u] * B + b0;
             // transpose of the conjugate-symmetric fill, then of the point phase
             auto sample = [&](int i) {
@@ -3308,6 +3310,18 @@ int upload(pat_plan_s* p, Dev<T>& d)
     if ((rc = put(twm.data(), twm.size() * sizeof(T), (const void**)&d.twm))) return rc;
     std::vector<T> pos = conv(H.pos);
     if ((rc = put(pos.data(), pos.size() * sizeof(T), (const void**)&d.pos))) return rc;
+    // point phase of every sample, e^{-i shift (u + v)} with u + v = h (x + y) / half,
+    // evaluated in FP64 from the FP64 positions
+    std::vector<T> pph(2 * (size_t)P.npts);
+    {
+        const double k = -P.shift * P.h / (0.5 * P.Ng / P.Lam);
+        for (int q = 0; q < P.npts; ++q) {
+            const double a = k * (H.pos[2 * (size_t)q] + H.pos[2 * (size_t)q + 1]);
+            pph[2 * (size_t)q] = (T)std::cos(a);
+            pph[2 * (size_t)q + 1] = (T)std::sin(a);
+        }
+    }
+    if ((rc = put(pph.data(), pph.size() * sizeof(T), (const void**)&d.ph))) return rc;
     d.binRing = nullptr; d.ringBin = nullptr; d.binStart = nullptr; d.binPos = nullptr; d.binned = 0;
     d.spOrder = nullptr; d.spCount = 0; d.gbOrder = nullptr; d.gbCount = 0;
     if constexpr (sizeof(T) == 4) {
