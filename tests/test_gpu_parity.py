@@ -155,6 +155,34 @@ def test_sampled_parity_at_full_size(name, B, shapes, tmp_path):
         assert rel(al, a[B - 1]) <= 1e-6
 
 
+@pytest.mark.parametrize("spread_images", [16, 8])
+def test_batch_of_several_image_groups(tmp_path, spread_images):
+    """B = 20 images: the binned spread runs 2 (16 images per group) or 3 (8)
+    image groups per tile and the binned gather 3 (8 per group), all blocks
+    dealt from the plans' dispatch tables; every image meets the FP32 bar
+    against the oracle and equals the same image computed alone."""
+    geom = P.full_circle(48, 96, 80)
+    B = 20
+    path = str(tmp_path / "t.txt")
+    pat.Plan(geom, torch.float32, max_batch=B, tuning_cache=path)
+    key = open(path).read().splitlines()[0].split(" | ")[0]
+    with open(path, "w") as fh:
+        fh.write(key + " | cols_cw=1 dct_cw=1 ring_group=2 spread_images=%d fft_radix_log2=4 ms=1.0 twiddle_table=0 "
+                 "spread_staged=2 dct_wave=1 wave_fft=1\n" % spread_images)
+    plan = pat.Plan(geom, torch.float32, max_batch=B, tuning_cache=path)
+    assert plan.info["tuned"] == 2 and plan.info["tune_spread_images"] == spread_images
+    f_np = np.stack([P.ellipse_phantom(48, 300 + s) for s in range(B)])
+    g_np = np.stack([P.randn((80, 96), 400 + s) for s in range(B)])
+    g = plan.forward(on_gpu(f_np, "f32")).double().cpu().numpy()
+    a = plan.adjoint(on_gpu(g_np, "f32")).double().cpu().numpy()
+    for b in range(B):
+        assert rel(g[b], O.forward(geom, f_np[b])) <= TOL["f32"], b
+        assert rel(a[b], O.adjoint(geom, g_np[b])) <= TOL["f32"], b
+    one = pat.Plan(geom, torch.float32, max_batch=1)
+    for b in (0, B - 1):
+        assert rel(one.adjoint(on_gpu(g_np[b], "f32")).double().cpu().numpy(), a[b]) <= 1e-6
+
+
 def test_forward_is_deterministic_and_linear():
     geom = P.full_circle(64, 128, 128)
     plan = pat.Plan(geom, torch.float32, max_batch=3)
