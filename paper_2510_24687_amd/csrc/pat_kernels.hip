@@ -1829,20 +1829,48 @@ __device__ __forceinline__ void synth_fwd_w_body(const Dev<float>& d, Blk bk, co
     const cx<float>* Gb = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(G) + (size_t)b * ws_img);
     const cx<float>* G1 = Gb + (size_t)j1 * d.Kp;
     const cx<float>* G2 = Gb + (size_t)j2 * d.Kp;
-    auto fold = [&](const cx<float>* row, int r) -> cx<float> {
+    // fold of harmonic row `row` onto residue r: the terms k = r, r + mf, ... <= K
+    // in that order; the first term's operands are passed in (loaded ahead)
+    auto fold = [&](const cx<float>* row, int r, cx<float> ph0, cx<float> v0) -> cx<float> {
         cx<float> z = {0.f, 0.f};
-        for (int k = r; k <= d.K; k += mf) z = z + cmul(d.phase[k] * (k == 0 ? 1.f : 2.f), row[k]);
+        if (r <= d.K) z = z + cmul(ph0 * (r == 0 ? 1.f : 2.f), v0);
+        for (int k = r + mf; k <= d.K; k += mf) z = z + cmul(d.phase[k] * 2.f, row[k]);
         return z;
     };
-    for (int r = lane; r <= mf / 2; r += 64) {
-        const int rm = r == 0 ? 0 : mf - r;
-        const cx<float> a = fold(G1, r), am = fold(G1, rm);
-        const cx<float> c = has2 ? fold(G2, r) : cx<float>{0.f, 0.f};
-        const cx<float> cm = has2 ? fold(G2, rm) : cx<float>{0.f, 0.f};
-        const cx<float> h1 = {0.5f * (a.x + am.x), 0.5f * (a.y - am.y)};
-        const cx<float> h2 = {0.5f * (c.x + cm.x), 0.5f * (c.y - cm.y)};
-        st_lds(buf + dw_phys(r), cx<float>{h1.x - h2.y, h1.y + h2.x});
-        if (rm != r) st_lds(buf + dw_phys(rm), cx<float>{h1.x + h2.y, h2.x - h1.y});
+    // chunks of SY_CH residues per lane: the first terms' phases and values of
+    // both rows are loaded together before any is used
+    constexpr int SY_CH = 4;
+    for (int r0 = 0; r0 <= mf / 2; r0 += SY_CH * 64) {
+        cx<float> p0[SY_CH], pm0[SY_CH], a0[SY_CH], am0[SY_CH], c0[SY_CH], cm0[SY_CH];
+#pragma unroll
+        for (int u = 0; u < SY_CH; ++u) {
+            const int r = r0 + u * 64 + lane, rm = r == 0 ? 0 : mf - r;
+            const cx<float> z = {0.f, 0.f};
+            p0[u] = pm0[u] = a0[u] = am0[u] = c0[u] = cm0[u] = z;
+            if (r > mf / 2) continue;
+            if (r <= d.K) {
+                p0[u] = d.phase[r];
+                a0[u] = G1[r];
+                if (has2) c0[u] = G2[r];
+            }
+            if (rm <= d.K) {
+                pm0[u] = d.phase[rm];
+                am0[u] = G1[rm];
+                if (has2) cm0[u] = G2[rm];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SY_CH; ++u) {
+            const int r = r0 + u * 64 + lane, rm = r == 0 ? 0 : mf - r;
+            if (r > mf / 2) continue;
+            const cx<float> a = fold(G1, r, p0[u], a0[u]), am = fold(G1, rm, pm0[u], am0[u]);
+            const cx<float> c = has2 ? fold(G2, r, p0[u], c0[u]) : cx<float>{0.f, 0.f};
+            const cx<float> cm = has2 ? fold(G2, rm, pm0[u], cm0[u]) : cx<float>{0.f, 0.f};
+            const cx<float> h1 = {0.5f * (a.x + am.x), 0.5f * (a.y - am.y)};
+            const cx<float> h2 = {0.5f * (c.x + cm.x), 0.5f * (c.y - cm.y)};
+            st_lds(buf + dw_phys(r), cx<float>{h1.x - h2.y, h1.y + h2.x});
+            if (rm != r) st_lds(buf + dw_phys(rm), cx<float>{h1.x + h2.y, h2.x - h1.y});
+        }
     }
     wave_sync();
     wf_fft<LOGM, true>(buf, (const PAT_GLOBAL cx<float>*)d.tw, d.logNmax, lane);
@@ -1868,26 +1896,48 @@ __device__ __forceinline__ void synth_adj_w_body(const Dev<float>& d, Blk bk, co
     const bool has2 = j2 < d.nt;
     const float* gb = g + (size_t)b * gstride;
     cx<float>* Gb = reinterpret_cast<cx<float>*>(reinterpret_cast<char*>(G) + (size_t)b * ws_img);
-    for (int i = lane; i < mf; i += 64) {
-        const float a = i < d.m ? gb[(size_t)j1 * d.m + i] : 0.f;
-        const float c = (i < d.m && has2) ? gb[(size_t)j2 * d.m + i] : 0.f;
-        st_lds(buf + dw_phys(i), cx<float>{a, c});
+    // chunks of 8 entries per lane, all loads issued before the chunk's stores
+    for (int i0 = 0; i0 < mf; i0 += 8 * 64) {
+        float a[8], c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * 64 + lane;
+            a[u] = (i < mf && i < d.m) ? gb[(size_t)j1 * d.m + i] : 0.f;
+            c[u] = (i < mf && i < d.m && has2) ? gb[(size_t)j2 * d.m + i] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * 64 + lane;
+            if (i < mf) st_lds(buf + dw_phys(i), cx<float>{a[u], c[u]});
+        }
     }
     wave_sync();
     wf_fft<LOGM, false>(buf, (const PAT_GLOBAL cx<float>*)d.tw, d.logNmax, lane);
-    for (int k = lane; k < d.Kp; k += 64) {
-        cx<float> y1 = {0.f, 0.f}, y2 = {0.f, 0.f};
-        if (k <= d.K) {
-            const int r = k & (mf - 1), rm = r == 0 ? 0 : mf - r;
-            const cx<float> zr = ld_lds(buf + dw_phys(r)), zm = ld_lds(buf + dw_phys(rm));
-            y1 = {0.5f * (zr.x + zm.x), 0.5f * (zr.y - zm.y)};
-            y2 = {0.5f * (zr.y + zm.y), 0.5f * (zm.x - zr.x)};
-            const cx<float> ph = conjg(d.phase[k]) * (k == 0 ? 1.f : 2.f);
-            y1 = cmul(ph, y1);
-            y2 = cmul(ph, y2);
+    for (int k0 = 0; k0 < d.Kp; k0 += 4 * 64) {
+        // the chunk's phases, loaded before its stores
+        cx<float> phk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * 64 + lane;
+            phk[u] = k <= d.K ? d.phase[k] : cx<float>{0.f, 0.f};
         }
-        Gb[(size_t)j1 * d.Kp + k] = y1;
-        if (has2) Gb[(size_t)j2 * d.Kp + k] = y2;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * 64 + lane;
+            if (k >= d.Kp) continue;
+            cx<float> y1 = {0.f, 0.f}, y2 = {0.f, 0.f};
+            if (k <= d.K) {
+                const int r = k & (mf - 1), rm = r == 0 ? 0 : mf - r;
+                const cx<float> zr = ld_lds(buf + dw_phys(r)), zm = ld_lds(buf + dw_phys(rm));
+                y1 = {0.5f * (zr.x + zm.x), 0.5f * (zr.y - zm.y)};
+                y2 = {0.5f * (zr.y + zm.y), 0.5f * (zm.x - zr.x)};
+                const cx<float> ph = conjg(phk[u]) * (k == 0 ? 1.f : 2.f);
+                y1 = cmul(ph, y1);
+                y2 = cmul(ph, y2);
+            }
+            Gb[(size_t)j1 * d.Kp + k] = y1;
+            if (has2) Gb[(size_t)j2 * d.Kp + k] = y2;
+        }
     }
 }
 
