@@ -1674,16 +1674,26 @@ __device__ __forceinline__ void rows_fwd_w_body(const Dev<float>& d, Blk bk, con
     const float s1 = d.Dq[p1] * d.pre_scale;
     const float s2 = p2 < n ? d.Dq[p2] * d.pre_scale : 0.f;
     const int h = n / 2;
-    for (int i = lane; i < Ng; i += 64) {
-        // position i holds column q = i + n/2 (i < n - n/2) or q = i - Ng + n/2 (i >= Ng - n/2)
-        const int q = i < n - h ? i + h : (i >= Ng - h ? i - Ng + h : -1);
-        cx<float> v = {0.f, 0.f};
-        if (q >= 0) {
-            const float dq = d.Dq[q];
-            v.x = in_mask(d, p1, q) ? fb[(size_t)p1 * n + q] * dq * s1 : 0.f;
-            v.y = (p2 < n && in_mask(d, p2, q)) ? fb[(size_t)p2 * n + q] * dq * s2 : 0.f;
+    // chunks of 8 positions per lane, loaded before the chunk's stores
+    for (int i0 = 0; i0 < Ng; i0 += 8 * 64) {
+        float dq[8], x1[8], x2[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            // position i holds column q = i + n/2 (i < n - n/2) or q = i - Ng + n/2 (i >= Ng - n/2)
+            const int i = i0 + u * 64 + lane;
+            const int q = i < n - h ? i + h : (i >= Ng - h ? i - Ng + h : -1);
+            dq[u] = x1[u] = x2[u] = 0.f;
+            if (i < Ng && q >= 0) {
+                dq[u] = d.Dq[q];
+                if (in_mask(d, p1, q)) x1[u] = fb[(size_t)p1 * n + q];
+                if (p2 < n && in_mask(d, p2, q)) x2[u] = fb[(size_t)p2 * n + q];
+            }
         }
-        st_lds(buf + dw_phys(i), v);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * 64 + lane;
+            if (i < Ng) st_lds(buf + dw_phys(i), cx<float>{x1[u] * dq[u] * s1, x2[u] * dq[u] * s2});
+        }
     }
     wave_sync();
     wf_fft<LOGN, false>(buf, (const PAT_GLOBAL cx<float>*)d.tw, d.logNmax, lane);
@@ -1711,28 +1721,57 @@ __device__ __forceinline__ void rows_adj_w_body(const Dev<float>& d, Blk bk, con
     const bool has2 = p2 < n;
     const cx<float>* Rb = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(R) + (size_t)b * ws_img);
     float* fb = f + (size_t)b * fstride;
-    for (int g = lane; g < Ng; g += 64) {
-        cx<float> xa, xb;
-        if (g == 0 || g == hN) {
-            xa = {Rb[(size_t)p1 * d.Rw + g].x, 0.f};
-            xb = {has2 ? Rb[(size_t)p2 * d.Rw + g].x : 0.f, 0.f};
-        } else if (g < hN) {
-            xa = Rb[(size_t)p1 * d.Rw + g] * 0.5f;
-            xb = has2 ? Rb[(size_t)p2 * d.Rw + g] * 0.5f : cx<float>{0.f, 0.f};
-        } else {
-            xa = conjg(Rb[(size_t)p1 * d.Rw + (Ng - g)]) * 0.5f;
-            xb = has2 ? conjg(Rb[(size_t)p2 * d.Rw + (Ng - g)]) * 0.5f : cx<float>{0.f, 0.f};
+    // chunks of 8 positions per lane: R entries g (g <= Ng/2) or Ng - g, loaded
+    // before the chunk's stores
+    for (int g0 = 0; g0 < Ng; g0 += 8 * 64) {
+        cx<float> ra[8], rb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int g = g0 + u * 64 + lane, gg = g <= hN ? g : Ng - g;
+            ra[u] = rb[u] = cx<float>{0.f, 0.f};
+            if (g < Ng) {
+                ra[u] = Rb[(size_t)p1 * d.Rw + gg];
+                if (has2) rb[u] = Rb[(size_t)p2 * d.Rw + gg];
+            }
         }
-        st_lds(buf + dw_phys(g), cx<float>{xa.x - xb.y, xa.y + xb.x});
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int g = g0 + u * 64 + lane;
+            if (g >= Ng) continue;
+            cx<float> xa, xb;
+            if (g == 0 || g == hN) {
+                xa = {ra[u].x, 0.f};
+                xb = {rb[u].x, 0.f};
+            } else if (g < hN) {
+                xa = ra[u] * 0.5f;
+                xb = rb[u] * 0.5f;
+            } else {
+                xa = conjg(ra[u]) * 0.5f;
+                xb = conjg(rb[u]) * 0.5f;
+            }
+            st_lds(buf + dw_phys(g), cx<float>{xa.x - xb.y, xa.y + xb.x});
+        }
     }
     wave_sync();
     wf_fft<LOGN, true>(buf, (const PAT_GLOBAL cx<float>*)d.tw, d.logNmax, lane);
     const float s1 = d.Dq[p1] * d.pre_scale * d.adj_scale;
     const float s2 = has2 ? d.Dq[p2] * d.pre_scale * d.adj_scale : 0.f;
-    for (int q = lane; q < n; q += 64) {
-        const cx<float> v = ld_lds(buf + dw_phys((q - n / 2 + Ng) & (Ng - 1)));
-        put_image(d, fb, b, p1, q, in_mask(d, p1, q) ? v.x * d.Dq[q] * s1 : 0.f);
-        if (has2) put_image(d, fb, b, p2, q, in_mask(d, p2, q) ? v.y * d.Dq[q] * s2 : 0.f);
+    for (int q0 = 0; q0 < n; q0 += 8 * 64) {
+        // the chunk's Dq, loaded before its stores
+        float dq[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * 64 + lane;
+            dq[u] = q < n ? d.Dq[q] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * 64 + lane;
+            if (q >= n) continue;
+            const cx<float> v = ld_lds(buf + dw_phys((q - n / 2 + Ng) & (Ng - 1)));
+            put_image(d, fb, b, p1, q, in_mask(d, p1, q) ? v.x * dq[u] * s1 : 0.f);
+            if (has2) put_image(d, fb, b, p2, q, in_mask(d, p2, q) ? v.y * dq[u] * s2 : 0.f);
+        }
     }
 }
 
@@ -1750,11 +1789,19 @@ __device__ __forceinline__ void cols_fwd_w_body(const Dev<float>& d, Blk bk, con
     cx<float>* Eb = reinterpret_cast<cx<float>*>(reinterpret_cast<char*>(E) + (size_t)b * ws_img);
     // rows p of R land at (p - n/2) mod Ng; positions [n - n/2, Ng - n/2) stay zero
     const int h = n / 2, nz = Ng - n;
-    for (int i = threadIdx.x; i < CB * n; i += NT) {
-        const int p = i / CB, c = i - p * CB;
-        const int gx = x0 + c;
-        const cx<float> v = gx < d.Rw ? Rb[(size_t)p * d.Rw + gx] : cx<float>{0.f, 0.f};
-        st_lds(lbuf + c * CP + dw_phys((p - h + Ng) & (Ng - 1)), v);
+    // chunks of 8 loads per thread, issued before the chunk's stores
+    for (int i0 = 0; i0 < CB * n; i0 += 8 * NT) {
+        cx<float> v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * NT + threadIdx.x, p = i / CB, gx = x0 + (i - p * CB);
+            v[u] = (i < CB * n && gx < d.Rw) ? Rb[(size_t)p * d.Rw + gx] : cx<float>{0.f, 0.f};
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * NT + threadIdx.x, p = i / CB, c = i - p * CB;
+            if (i < CB * n) st_lds(lbuf + c * CP + dw_phys((p - h + Ng) & (Ng - 1)), v[u]);
+        }
     }
     for (int i = threadIdx.x; i < CB * nz; i += NT) {
         const int z = i / CB, c = i - z * CB;
@@ -1787,17 +1834,26 @@ __device__ __forceinline__ void cols_adj_w_body(const Dev<float>& d, Blk bk, con
     const int x0 = bk.x * CB, b = bk.y, n = d.n;
     const cx<float>* Eb = reinterpret_cast<const cx<float>*>(reinterpret_cast<const char*>(E) + (size_t)b * ws_img);
     cx<float>* Rb = reinterpret_cast<cx<float>*>(reinterpret_cast<char*>(R) + (size_t)b * ws_img);
-    for (int i = threadIdx.x; i < CB * Ng; i += NT) {
-        const int gy = i / CB, c = i - gy * CB;
-        const int gx = x0 + c;
-        cx<float> v = {0.f, 0.f};
-        if (gx < d.Rw) {
-            v = Eb[(size_t)gy * d.Ep + gx + d.hw];
-            const int gym = (Ng - gy) & (Ng - 1);
-            if (gx >= 1 && gx <= d.hw) v = v + conjg(Eb[(size_t)gym * d.Ep + d.hw - gx]);
-            if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) v = v + conjg(Eb[(size_t)gym * d.Ep + d.hw + Ng - gx]);
+    // chunks of 8 cells per thread, loaded before the chunk's stores (the
+    // margin folds, rare, load their second operand in place)
+    for (int i0 = 0; i0 < CB * Ng; i0 += 8 * NT) {
+        cx<float> v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * NT + threadIdx.x, gy = i / CB, gx = x0 + (i - gy * CB);
+            v[u] = (i < CB * Ng && gx < d.Rw) ? Eb[(size_t)gy * d.Ep + gx + d.hw] : cx<float>{0.f, 0.f};
         }
-        st_lds(lbuf + c * CP + dw_phys(gy), v);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * NT + threadIdx.x, gy = i / CB, c = i - gy * CB, gx = x0 + c;
+            if (i >= CB * Ng) continue;
+            if (gx < d.Rw) {
+                const int gym = (Ng - gy) & (Ng - 1);
+                if (gx >= 1 && gx <= d.hw) v[u] = v[u] + conjg(Eb[(size_t)gym * d.Ep + d.hw - gx]);
+                if (gx >= Ng / 2 - d.hw && gx <= Ng / 2 - 1) v[u] = v[u] + conjg(Eb[(size_t)gym * d.Ep + d.hw + Ng - gx]);
+            }
+            st_lds(lbuf + c * CP + dw_phys(gy), v[u]);
+        }
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
