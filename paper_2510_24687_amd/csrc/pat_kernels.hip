@@ -909,11 +909,29 @@ __device__ __forceinline__ void gather_bins_body(const Dev<float>& d, Blk bk, co
     __syncthreads();
     const int S = s_vo[TS];
     const float hwf = 0.5f * float(W), tw_ = 2.f / float(W);
-    for (int v = tid; v < S; v += NT) {
-        int q = 0;
+    // slot of sample v (v increases along a thread's loop, so the bin row q only advances)
+    int q = 0;
+    auto slot = [&](int v) {
         while (q + 1 < TS && s_vo[q + 1] <= v) ++q;
-        const int g = s_gs[q] + v - s_vo[q];
-        const cx<float> pq = d.binPos[g];
+        return s_gs[q] + v - s_vo[q];
+    };
+    // software pipeline: the next sample's position and ring index are loaded
+    // while this one is interpolated
+    cx<float> pq_next = {0.f, 0.f};
+    int pr_next = 0;
+    if (tid < S) {
+        const int g = slot(tid);
+        pq_next = d.binPos[g];
+        pr_next = d.binRing[g];
+    }
+    for (int v = tid; v < S; v += NT) {
+        const cx<float> pq = pq_next;
+        const size_t pr = (size_t)pr_next;
+        if (v + NT < S) {
+            const int g = slot(v + NT);
+            pq_next = d.binPos[g];
+            pr_next = d.binRing[g];
+        }
         const int gx0 = (int)ceil_t(pq.x - hwf);
         const int gy0 = (int)ceil_t(pq.y - hwf);
         float wx[W];
@@ -921,7 +939,6 @@ __device__ __forceinline__ void gather_bins_body(const Dev<float>& d, Blk bk, co
         for (int j = 0; j < W; ++j) wx[j] = es_w(pq.x - float(gx0 + j), tw_, d.beta, d.beta_l2e);
         const cx<float> ph = point_phase(d, pq.x, pq.y);
         const int lx0 = gx0 + d.hw - ex0, ly0 = (gy0 - ty0) & mask;  // both in [0, TS)
-        const size_t pr = (size_t)d.binRing[g];
         const float4* base = s_cell + (ly0 * NC + lx0) * (CR / 2);
         // one stencil row at a time (its y-weight evaluated once there), all
         // BC images of the row's taps in registers
