@@ -1426,6 +1426,8 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
     const int nout = adjoint ? d.L : d.nt;
     const int y0 = adjoint ? 0 : 1, ymax = adjoint ? d.L - 1 : d.nt;
     const int Kp = d.Kp;
+    // d.sine: out(y) = sum_x f_x sin(pi x y / M) (the approximate inverse), else the cosine sum
+    const bool sine = d.sine != 0;
     constexpr int L = DW_LPC;
     const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L, wv = lane >> 6;
     // the twiddles of step (2), e^{-i pi j/M} for j = lane + L v: the lane's
@@ -1450,7 +1452,9 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
         for (int u = 0; u < 8; ++u) {
             const int i = i0 + u * NT + threadIdx.x;
             const int row = i / CB, c = i - row * CB;
-            if (i < CB * nx) st_lds(lbuf + c * CP + dw_phys(row + x_lo), v[u]);
+            // the sine sum has no x = 0 or x = M terms (their sines vanish)
+            const int x = row + x_lo;
+            if (i < CB * nx) st_lds(lbuf + c * CP + dw_phys(x), (sine && (x == 0 || x == M)) ? cx<float>{0.f, 0.f} : v[u]);
         }
     }
     const int nzero = x_lo + (M + 1 - x_hi);   // slots [0, x_lo) and [x_hi, M]
@@ -1463,7 +1467,8 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
     // block-wide partial results of the two waves of each column group
     __shared__ cx<float> red[DW_GROUPS][4][2];
     PAT_LDS cx<float>* wb = lbuf + grp * NC * CP;
-    // (2) per column: F_1's interior sum and g_j = (f_j + f_{M-j})/2 - sin(pi j/M) (f_j - f_{M-j})
+    // (2) per column: F_1's interior sum and g_j = (f_j + f_{M-j})/2 - sin(pi j/M) (f_j - f_{M-j});
+    // sine: g_j = sin(pi j/M) (f_j + f_{M-j}) + (f_j - f_{M-j})/2 (F_1 unused)
     cx<float> F1[NC], e0[NC], eM[NC];
     {
         cx<float> gv[NC][PJ];
@@ -1481,7 +1486,8 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
                 const cx<float> w = cmul(wlane, wuni[v]);   // (cos(pi j/M), -sin(pi j/M))
                 acc = acc + fj * w.x;
                 const float sj = -w.y;
-                gv[c][v] = {0.5f * (fj.x + fm.x) - sj * (fj.x - fm.x), 0.5f * (fj.y + fm.y) - sj * (fj.y - fm.y)};
+                gv[c][v] = sine ? cx<float>{sj * (fj.x + fm.x) + 0.5f * (fj.x - fm.x), sj * (fj.y + fm.y) + 0.5f * (fj.y - fm.y)}
+                                : cx<float>{0.5f * (fj.x + fm.x) - sj * (fj.x - fm.x), 0.5f * (fj.y + fm.y) - sj * (fj.y - fm.y)};
             }
             acc = wave_sum(acc);
             if ((lane & 63) == 0) red[grp][c][wv] = acc;
@@ -1505,7 +1511,13 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
     if constexpr (M3) dw_pass<M, NC, CP, 3, (1 << LOGP)>(wb, twd, lane);
     // (4) outputs: lane l owns q = CH l + 1 .. CH (l + 1): F_{2q} = (G_q + G_{M-q})/2,
     // F_{2q+1} = F_1 + S_q, S_q = sum_{p=1..q} -(i/2)(G_p - G_{M-p});
-    // out(y) = F_y + (f_0 + (-1)^y f_M)/2, written to slot y - y0
+    // out(y) = F_y + (f_0 + (-1)^y f_M)/2, written to slot y - y0.
+    // Sine (the real-data identities Re G_q = S_{2q+1} - S_{2q-1}, Im G_q = S_{2q},
+    // extended linearly to complex data): S_{2q} = -(i/2)(G_q - G_{M-q}),
+    // S_{2q+1} = S_1 + sum_{p=1..q} (G_p + G_{M-p})/2, S_1 = G_0/2, S_0 = 0.
+    cx<float> G0[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) G0[c] = ld_lds(wb + c * CP);
     const int Q = (ymax + 1) >> 1;             // q needed: even y = 2q <= ymax, odd y = 2q + 1 <= ymax
     constexpr int CHMAX = (M / 2 + L - 1) / L; // Q <= M/2
     const int CH = (Q + L - 1) / L;
@@ -1521,8 +1533,9 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
             cx<float> ev = {0.f, 0.f};
             if (i < CH && q <= M / 2) {
                 const cx<float> gq = ld_lds(col + dw_phys(q)), gm = ld_lds(col + dw_phys(M - q));
-                run = run + cx<float>{0.5f * (gq.y - gm.y), -0.5f * (gq.x - gm.x)};
-                ev = (gq + gm) * 0.5f;
+                const cx<float> anti = {0.5f * (gq.y - gm.y), -0.5f * (gq.x - gm.x)}, sym = (gq + gm) * 0.5f;
+                run = run + (sine ? sym : anti);
+                ev = sine ? anti : sym;
             }
             pre[i] = run;
             outv[c][i][0] = ev;
@@ -1536,17 +1549,19 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
         if (wv == 1) off = off + red[grp][c][0];
         __syncthreads();
         const float hx0 = 0.5f * e0[c].x, hy0 = 0.5f * e0[c].y, hxM = 0.5f * eM[c].x, hyM = 0.5f * eM[c].y;
+        const cx<float> S1 = G0[c] * 0.5f;
 #pragma unroll
         for (int i = 0; i < CHMAX; ++i) {
             const cx<float> S = off + pre[i];
             // y = 2q (even) and y = 2q + 1 (odd)
-            outv[c][i][0] = {outv[c][i][0].x + hx0 + hxM, outv[c][i][0].y + hy0 + hyM};
-            outv[c][i][1] = {F1[c].x + S.x + hx0 - hxM, F1[c].y + S.y + hy0 - hyM};
+            if (sine) {
+                outv[c][i][1] = S1 + S;
+            } else {
+                outv[c][i][0] = {outv[c][i][0].x + hx0 + hxM, outv[c][i][0].y + hy0 + hyM};
+                outv[c][i][1] = {F1[c].x + S.x + hx0 - hxM, F1[c].y + S.y + hy0 - hyM};
+            }
         }
     }
-    cx<float> G0[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) G0[c] = ld_lds(wb + c * CP);
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -1562,8 +1577,14 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
         }
         if (lane == 0) {
             // y = 1: F_1 + (f_0 - f_M)/2; y = 0 (adjoint only): G_0 + (f_0 + f_M)/2
-            st_lds(col + dw_phys(1 - y0), cx<float>{F1[c].x + 0.5f * (e0[c].x - eM[c].x), F1[c].y + 0.5f * (e0[c].y - eM[c].y)});
-            if (y0 == 0) st_lds(col, cx<float>{G0[c].x + 0.5f * (e0[c].x + eM[c].x), G0[c].y + 0.5f * (e0[c].y + eM[c].y)});
+            // (sine: S_1 = G_0/2 and S_0 = 0)
+            if (sine) {
+                st_lds(col + dw_phys(1 - y0), G0[c] * 0.5f);
+                if (y0 == 0) st_lds(col, cx<float>{0.f, 0.f});
+            } else {
+                st_lds(col + dw_phys(1 - y0), cx<float>{F1[c].x + 0.5f * (e0[c].x - eM[c].x), F1[c].y + 0.5f * (e0[c].y - eM[c].y)});
+                if (y0 == 0) st_lds(col, cx<float>{G0[c].x + 0.5f * (e0[c].x + eM[c].x), G0[c].y + 0.5f * (e0[c].y + eM[c].y)});
+            }
         }
     }
     __syncthreads();
@@ -3632,7 +3653,7 @@ int run_forward(pat_plan_s* p, const Dev<T>& d, int B, const T* f, long fs, T* g
     {
         StageTimer tm(p, st, 3);
         if constexpr (sizeof(T) == 4) {
-            if (d.dct_wave && !d.sine) {
+            if (d.dct_wave) {
                 if ((rc = launch_dct_wave(d, B, V, G, wi, 0, st))) return fail(rc, "dct_fwd: no dct_wave variant");
             } else {
                 dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, dct_lds(p->H.P, d.dctCW), st>>>(d, V, G, wi, 0);
@@ -3696,7 +3717,7 @@ int run_adjoint(pat_plan_s* p, const Dev<T>& d, int B, const T* g, long gs, T* f
     {
         StageTimer tm(p, st, 8);
         if constexpr (sizeof(T) == 4) {
-            if (d.dct_wave && !d.sine) {
+            if (d.dct_wave) {
                 if ((rc = launch_dct_wave(d, B, G, V, wi, 1, st))) return fail(rc, "dct_adj: no dct_wave variant");
             } else {
                 dct_cols<T><<<dim3((d.Kp + d.dctCW - 1) / d.dctCW, B), NT, dct_lds(p->H.P, d.dctCW), st>>>(d, G, V, wi, 1);
