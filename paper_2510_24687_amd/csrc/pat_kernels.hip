@@ -1409,7 +1409,7 @@ __device__ __forceinline__ cx<float> wave_excl_scan(cx<float> v, int lane)
 
 // Column block: forward (adjoint = 0) in = V [L][Kp] -> out = G [nt][Kp],
 // out row j holds y = j + 1; adjoint in = G (x = j + 1) -> out = V, row y.
-template <int M3, int LOGP>
+template <int M3, int LOGP, bool SINE>
 __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const cx<float>* in, cx<float>* out,
                                               size_t ws_img, int adjoint)
 {
@@ -1426,8 +1426,8 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
     const int nout = adjoint ? d.L : d.nt;
     const int y0 = adjoint ? 0 : 1, ymax = adjoint ? d.L - 1 : d.nt;
     const int Kp = d.Kp;
-    // d.sine: out(y) = sum_x f_x sin(pi x y / M) (the approximate inverse), else the cosine sum
-    const bool sine = d.sine != 0;
+    // SINE: out(y) = sum_x f_x sin(pi x y / M) (the approximate inverse), else the cosine sum
+    constexpr bool sine = SINE;
     constexpr int L = DW_LPC;
     const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L, wv = lane >> 6;
     // the twiddles of step (2), e^{-i pi j/M} for j = lane + L v: the lane's
@@ -1596,22 +1596,25 @@ __device__ __forceinline__ void dct_wave_body(const Dev<float>& d, Blk bk, const
     }
 }
 
-template <int M3, int LOGP>
+// SINE: the sine sum of the approximate inverse (its own kernel, so that the
+// cosine kernel keeps its register budget)
+template <int M3, int LOGP, bool SINE>
 __global__ __launch_bounds__(NT) void dct_wave(Dev<float> d, const cx<float>* in, cx<float>* out, size_t ws_img,
                                                int adjoint)
 {
-    dct_wave_body<M3, LOGP>(d, blk_xcd(), in, out, ws_img, adjoint);
+    dct_wave_body<M3, LOGP, SINE>(d, blk_xcd(), in, out, ws_img, adjoint);
 }
 
 // variant code of dct_wave: (M3 << 8) | LOGP, 0 = none
 #define PAT_DW_VARIANTS(X) X(1, 7) X(1, 8) X(1, 9) X(0, 8) X(0, 9) X(0, 10)
 
+// the grouped launches (A and A* only, never the inverse's sine sum) take the cosine form
 __device__ __forceinline__ void dct_wave_dispatch(const Dev<float>& d, Blk bk, const cx<float>* in, cx<float>* out,
                                                   size_t ws_img, int adjoint)
 {
     switch (d.dct_wave) {
 #define PAT_DW_CASE(a, b) \
-    case ((a) << 8) | (b): dct_wave_body<a, b>(d, bk, in, out, ws_img, adjoint); break;
+    case ((a) << 8) | (b): dct_wave_body<a, b, false>(d, bk, in, out, ws_img, adjoint); break;
         PAT_DW_VARIANTS(PAT_DW_CASE)
 #undef PAT_DW_CASE
         default: break;
@@ -3235,7 +3238,10 @@ int launch_dct_wave(const Dev<float>& d, int B, const cx<float>* in, cx<float>* 
     switch (d.dct_wave) {
 #define PAT_DW_LAUNCH(a, b) \
     case ((a) << 8) | (b): \
-        dct_wave<a, b><<<dim3(d.Kp / DwShape<a, b>::CB, B), NT, DwShape<a, b>::LDS, st>>>(d, in, out, wi, adjoint); \
+        if (d.sine)                                                                                                   \
+            dct_wave<a, b, true><<<dim3(d.Kp / DwShape<a, b>::CB, B), NT, DwShape<a, b>::LDS, st>>>(d, in, out, wi, adjoint); \
+        else                                                                                                          \
+            dct_wave<a, b, false><<<dim3(d.Kp / DwShape<a, b>::CB, B), NT, DwShape<a, b>::LDS, st>>>(d, in, out, wi, adjoint); \
         break;
         PAT_DW_VARIANTS(PAT_DW_LAUNCH)
 #undef PAT_DW_LAUNCH

@@ -156,3 +156,31 @@ def test_left_inverse_of_the_gpu_forward():
     e = rel(back[om0], f[om0])
     print("A^-1 A f: rel %.3e" % e)
     assert e < 1e-3
+
+
+@pytest.mark.parametrize("wave", [1, 0])
+def test_inverse_with_and_without_the_wave_sine_transform(tmp_path, wave):
+    """At n = 64 (M = 384 admits the one-wave transform) the approximate inverse
+    runs its sine transform on the wave kernel (dct_wave = 1) or on the
+    generic column kernel (dct_wave = 0), forced through the tuning cache:
+    both meet the FP32 bar against the oracle and agree with each other."""
+    geom = P.full_circle(64, 128, 128)
+    B = 2
+    path = str(tmp_path / "t.txt")
+    pat.Plan(geom, torch.float32, max_batch=B, tuning_cache=path)
+    key = open(path).read().splitlines()[0].split(" | ")[0]
+    outs = {}
+    g = np.stack([P.randn((128, 128), 900 + s) for s in range(B)])
+    for flag in (wave, 1 - wave):
+        cache = str(tmp_path / ("c%d.txt" % flag))
+        with open(cache, "w") as fh:
+            fh.write(key + " | cols_cw=1 dct_cw=1 ring_group=2 spread_images=16 fft_radix_log2=4 ms=1.0 "
+                     "twiddle_table=0 spread_staged=2 dct_wave=%d wave_fft=1\n" % flag)
+        plan = pat.Plan(geom, torch.float32, max_batch=B, tuning_cache=cache)
+        assert plan.info["tuned"] == 2 and plan.info["tune_dct_wave"] == flag
+        outs[flag] = plan.inverse(torch.tensor(g, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    ref = O.inverse(geom, g[0])
+    assert rel(outs[wave][0], ref) <= 1e-4
+    for b in range(B):
+        assert rel(outs[1][b], outs[0][b]) <= 1e-5
+
